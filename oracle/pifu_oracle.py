@@ -1,0 +1,535 @@
+"""Plain FP64 CPU oracle for hierarchical surface localization and mesh-free rendering.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this module.  It shares no code
+with the GPU library; the only common module is ``synth`` (seeded inputs).
+
+Paper: Li et al., "Monocular Real-Time Volumetric Performance Capture", ECCV 2020.
+  * Eq. 1 (Sec. 3.1): O(P) = f_O(Phi(P_xy, g_O(I)), P_z), surface = 0.5 level set.
+  * Sec. 3.2, "Octree-based Robust Surface Localization": binarize the coarser
+    level at 0.5, trilinearly interpolate to the current level, take the nodes
+    whose value is neither 0 nor 1, dilate by the 1-ring, evaluate, then
+    evaluate neighbours of conflict nodes until no conflict is left.
+  * Sec. 3.2, "Mesh-free Rendering" and Eq. 3: localize to level L-1 on the
+    target-view grid, upsample + argmax along z, shadow nodes, evaluate the
+    rest, argmax again, interpolate the surface point, colour it with Eq. 2.
+
+Readings of the paper where it is silent or ambiguous (kept identical on the GPU):
+  * a grid of "2^L" has 2^L cells, i.e. 2^L + 1 nodes per axis; node i sits at
+    NDC -1 + 2 i / 2^L; coarse nodes are the even fine nodes.
+  * pixel coordinates u = (x+1)/2 (W-1), v = (y+1)/2 (H-1); texels outside the
+    map contribute 0 to the bilinear sum.
+  * label = [logit > 0]; p = sigmoid(logit) is the occupancy value.
+  * dilation and "adjacent" use the 26-neighbourhood on the level's lattice.
+  * the conflict test compares [logit > 0] with [interp > 1/2]; conflict waves
+    are synchronous and stop when a wave adds no node.
+  * render rays run from the observer (z = +1, largest k) inwards; no conflict
+    loop at the last render level; points outside the input volume after the
+    view transform have logit -inf.
+  * the surface point is the 0.5 crossing of the linear interpolation of the
+    two nodes' occupancy values along z.
+
+Parity: every function here is pinned by the ``-m "not gpu"`` tests in
+``tests/test_oracle_*.py`` (closed forms, library routines, invariants, brute
+force on tiny grids).  The paper prints no worked example of the algorithm.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field as dc_field
+from typing import Callable, Dict, List, Optional, Tuple
+
+import numpy as np
+
+# ------------------------------------------------------------------ evaluate
+
+LRELU_SLOPE = 0.01
+
+
+def sigmoid(logit: np.ndarray) -> np.ndarray:
+    with np.errstate(over="ignore"):
+        return 1.0 / (1.0 + np.exp(-logit))
+
+
+def bilinear_sample(F: np.ndarray, x: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """Phi(P_xy, F): bilinear sampling of an HWC feature map at NDC (x, y) (Eq. 1).
+
+    Column u runs along x and row v along y.  Texels outside the map count as 0.
+    """
+    H, W, C = F.shape
+    F = np.asarray(F, np.float64)
+    u = (x + 1.0) * 0.5 * (W - 1)
+    v = (y + 1.0) * 0.5 * (H - 1)
+    u0 = np.floor(u)
+    v0 = np.floor(v)
+    fu = u - u0
+    fv = v - v0
+    out = np.zeros((x.shape[0], C))
+    for du, dv, w in ((0, 0, (1 - fu) * (1 - fv)), (1, 0, fu * (1 - fv)),
+                      (0, 1, (1 - fu) * fv), (1, 1, fu * fv)):
+        uu = (u0 + du).astype(np.int64)
+        vv = (v0 + dv).astype(np.int64)
+        inside = (uu >= 0) & (uu <= W - 1) & (vv >= 0) & (vv <= H - 1)
+        tex = F[np.clip(vv, 0, H - 1), np.clip(uu, 0, W - 1), :]
+        out += (w * inside)[:, None] * tex
+    return out
+
+
+def _act(h: np.ndarray, kind: str) -> np.ndarray:
+    if kind == "relu":
+        return np.maximum(h, 0.0)
+    if kind == "lrelu":
+        return np.where(h > 0, h, LRELU_SLOPE * h)
+    raise ValueError(kind)
+
+
+def mlp_preact(spec, f: np.ndarray, extras: np.ndarray) -> np.ndarray:
+    """Output pre-activation of the MLP f_O / f_T for point features f and extras.
+
+    Layer 0 reads [f; extras] (extras = z, or z and occ for the colour network,
+    Eq. 1 / Eq. 2); hidden layer l reads [h_{l-1}; f] where the spec has a skip.
+    """
+    f = np.asarray(f, np.float64)
+    x = np.concatenate([f, np.asarray(extras, np.float64).reshape(f.shape[0], -1)], axis=1)
+    n_layers = len(spec.widths)
+    h = x
+    for l in range(n_layers):
+        if l > 0 and spec.skip[l]:
+            h = np.concatenate([h, f], axis=1)
+        h = h @ np.asarray(spec.W[l], np.float64).T + np.asarray(spec.b[l], np.float64)
+        if l < n_layers - 1:
+            h = _act(h, spec.hidden_act)
+    return h
+
+
+@dataclass
+class Field:
+    """An occupancy field: an MLP over a feature map (Eq. 1) or an analytic stand-in."""
+    kind: str                              # "mlp" | "ellipsoids" | "plane"
+    feat: Optional[np.ndarray] = None      # H x W x C
+    mlp: object = None                     # synth.MLPSpec
+    ell: Optional[np.ndarray] = None       # n x 12
+    sharpness: float = 8.0
+    plane: Optional[np.ndarray] = None     # a, b, c, d
+
+
+def field_logit(fld: Field, P: np.ndarray, chunk: int = 32768) -> np.ndarray:
+    """logit of O(P) at input-view NDC points P (n x 3)."""
+    P = np.asarray(P, np.float64)
+    n = P.shape[0]
+    if fld.kind == "plane":
+        a = np.asarray(fld.plane, np.float64)
+        return P @ a[:3] + a[3]
+    if fld.kind == "ellipsoids":
+        E = np.asarray(fld.ell, np.float64)
+        qmin = np.full(n, np.inf)
+        for e in range(E.shape[0]):
+            c = E[e, :3]
+            M = E[e, 3:].reshape(3, 3)
+            d = (P - c) @ M.T
+            qmin = np.minimum(qmin, np.sum(d * d, axis=1))
+        return fld.sharpness * (1.0 - qmin)
+    if fld.kind == "mlp":
+        out = np.empty(n)
+        for s in range(0, n, chunk):
+            Pc = P[s:s + chunk]
+            f = bilinear_sample(fld.feat, Pc[:, 0], Pc[:, 1])
+            out[s:s + chunk] = mlp_preact(fld.mlp, f, Pc[:, 2:3])[:, 0]
+        return out
+    raise ValueError(fld.kind)
+
+
+def apply_view(view: np.ndarray, P: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
+    """P' = A P + t for a 3x4 row-major view; also the mask P' in [-1,1]^3."""
+    V = np.asarray(view, np.float64).reshape(3, 4)
+    Pp = P @ V[:, :3].T + V[:, 3]
+    inside = np.all((Pp >= -1.0) & (Pp <= 1.0), axis=1)
+    return Pp, inside
+
+
+def view_logit(fld: Field, view: Optional[np.ndarray], P: np.ndarray) -> np.ndarray:
+    """Evaluate a target-view point: transform into the input view; outside -> -inf."""
+    if view is None:
+        return field_logit(fld, P)
+    Pp, inside = apply_view(view, P)
+    out = np.full(P.shape[0], -np.inf)
+    if inside.any():
+        out[inside] = field_logit(fld, Pp[inside])
+    return out
+
+
+# ------------------------------------------------------------------ grids
+
+def lattice_coords(dims: Tuple[int, int, int], flat_idx: np.ndarray) -> np.ndarray:
+    """NDC coordinates of level-lattice nodes given by linear index (z fastest)."""
+    nx, ny, nz = dims
+    i = flat_idx // (ny * nz)
+    j = (flat_idx // nz) % ny
+    k = flat_idx % nz
+    return np.stack([-1.0 + 2.0 * i / (nx - 1), -1.0 + 2.0 * j / (ny - 1),
+                     -1.0 + 2.0 * k / (nz - 1)], axis=1)
+
+
+def upsample_x2(coarse: np.ndarray) -> np.ndarray:
+    """Trilinear interpolation of a node array onto the lattice with half the spacing.
+
+    Fine node 2a keeps coarse node a; fine node 2a+1 takes the mean of coarse nodes
+    a and a+1 -- along each axis in turn, which is trilinear interpolation
+    of the node values (Sec. 3.2, the interpolation step of the localization).
+    """
+    out = np.asarray(coarse, np.float64)
+    for ax in range(3):
+        n = out.shape[ax]
+        shape = list(out.shape)
+        shape[ax] = 2 * n - 1
+        fine = np.empty(shape)
+        even = [slice(None)] * 3
+        odd = [slice(None)] * 3
+        lo = [slice(None)] * 3
+        hi = [slice(None)] * 3
+        even[ax] = slice(0, None, 2)
+        odd[ax] = slice(1, None, 2)
+        lo[ax] = slice(0, n - 1)
+        hi[ax] = slice(1, n)
+        fine[tuple(even)] = out
+        fine[tuple(odd)] = 0.5 * (out[tuple(lo)] + out[tuple(hi)])
+        out = fine
+    return out
+
+
+def neighbourhood26(mask: np.ndarray) -> np.ndarray:
+    """Nodes whose index differs from a marked node by at most 1 along every axis.
+
+    This is the 1-ring (26-neighbourhood) dilation of Sec. 3.2, clipped at the
+    grid edge; the marked nodes themselves are included.
+    """
+    out = np.zeros_like(mask, dtype=bool)
+    pts = np.argwhere(mask)
+    if pts.size == 0:
+        return out
+    dims = np.array(mask.shape)
+    for di in (-1, 0, 1):
+        for dj in (-1, 0, 1):
+            for dk in (-1, 0, 1):
+                q = pts + np.array([di, dj, dk])
+                ok = np.all((q >= 0) & (q < dims), axis=1)
+                q = q[ok]
+                out[q[:, 0], q[:, 1], q[:, 2]] = True
+    return out
+
+
+@dataclass
+class LevelRecord:
+    level: int                 # log2 of the x cell count at this level
+    dims: Tuple[int, int, int]
+    evaluated: np.ndarray      # sorted linear indices (level lattice) evaluated at this level
+    stats: Dict[str, int]
+
+
+@dataclass
+class LocalizeResult:
+    dims: Tuple[int, int, int]          # lattice of the last level run
+    val: np.ndarray                     # occupancy value: p if evaluated, else interp (0/1)
+    label: np.ndarray                   # uint8 0/1
+    logit: np.ndarray                   # logit where evaluated, nan elsewhere
+    evaluated: np.ndarray               # bool, evaluated at any level
+    levels: List[LevelRecord] = dc_field(default_factory=list)
+
+
+def _eval_mask(evaluate, dims, mask):
+    idx = np.flatnonzero(mask.reshape(-1))
+    logit = evaluate(lattice_coords(dims, idx)) if idx.size else np.zeros(0)
+    return idx, logit
+
+
+def localize(evaluate: Callable[[np.ndarray], np.ndarray], log2_cells: Tuple[int, int, int],
+             n_refine: int, last_level: Optional[int] = None,
+             max_waves: int = 1 << 30) -> LocalizeResult:
+    """Coarse-to-fine surface localization (Sec. 3.2, "Octree-based Robust Surface
+    Localization").
+
+    ``log2_cells`` are the per-axis log2 cell counts of the finest lattice and
+    ``n_refine`` the number of x2 refinements above the coarsest level, which is
+    evaluated densely.  Runs levels 0..last_level (default n_refine).
+    """
+    T = n_refine
+    last = T if last_level is None else last_level
+    dims_at = lambda t: tuple((1 << (L - (T - t))) + 1 for L in log2_cells)
+    level_id = lambda t: log2_cells[0] - (T - t)
+
+    # coarsest level: every node is evaluated
+    dims = dims_at(0)
+    allmask = np.ones(dims, bool)
+    idx, logit_e = _eval_mask(evaluate, dims, allmask)
+    logit = logit_e.reshape(dims)
+    label = (logit > 0).astype(np.uint8)
+    val = sigmoid(logit)
+    evaluated = allmask.copy()
+    res_levels = [LevelRecord(level_id(0), dims, idx, dict(
+        nodes=int(np.prod(dims)), b0=0, dilated=int(idx.size), evaluated=int(idx.size),
+        waves=0, conflicts=0))]
+
+    for t in range(1, last + 1):
+        fdims = dims_at(t)
+        # binarize the coarser level at 0.5 and interpolate to this level
+        interp = upsample_x2(label.astype(np.float64))
+        assert interp.shape == fdims
+        coarse_pos = np.zeros(fdims, bool)
+        coarse_pos[::2, ::2, ::2] = True
+        f_eval = np.zeros(fdims, bool)
+        f_eval[::2, ::2, ::2] = evaluated
+        f_val = interp.copy()
+        f_val[::2, ::2, ::2] = val
+        f_logit = np.full(fdims, np.nan)
+        f_logit[::2, ::2, ::2] = logit
+        f_label = (interp > 0.5).astype(np.uint8)     # culled nodes: interp is 0 or 1
+        f_label[::2, ::2, ::2] = label
+        # boundary candidates: neither 0 nor 1; then the 1-ring dilation
+        b0 = (interp > 0.0) & (interp < 1.0)
+        cand = neighbourhood26(b0) & ~f_eval
+        now = np.zeros(fdims, bool)
+        interp_hi = interp > 0.5
+
+        def run(mask):
+            idx_, lg = _eval_mask(evaluate, fdims, mask)
+            flat_l = f_logit.reshape(-1)
+            flat_l[idx_] = lg
+            f_label.reshape(-1)[idx_] = (lg > 0).astype(np.uint8)
+            f_val.reshape(-1)[idx_] = sigmoid(lg)
+            f_eval.reshape(-1)[idx_] = True
+            now.reshape(-1)[idx_] = True
+            # conflict: network label differs from the binarized interpolation
+            return mask & ((f_label == 1) != interp_hi)
+
+        n_dilated = int(cand.sum())
+        conflict = run(cand)
+        n_conf = int(conflict.sum())
+        waves = 0
+        while conflict.any() and waves < max_waves:
+            nxt = neighbourhood26(conflict) & ~f_eval
+            if not nxt.any():
+                break
+            waves += 1
+            conflict = run(nxt)
+            n_conf += int(conflict.sum())
+        logit, label, val, evaluated = f_logit, f_label, f_val, f_eval
+        res_levels.append(LevelRecord(level_id(t), fdims, np.flatnonzero(now.reshape(-1)), dict(
+            nodes=int(np.prod(fdims)), b0=int(b0.sum()), dilated=n_dilated,
+            evaluated=int(now.sum()), waves=waves, conflicts=n_conf)))
+        dims = fdims
+    return LocalizeResult(dims, val, label, logit, evaluated, res_levels)
+
+
+def surface_cells(label: np.ndarray) -> np.ndarray:
+    """Sorted linear indices (i*Ry + j)*Rz + k of cells whose 8 corner labels differ."""
+    L = label.astype(bool)
+    corners = [L[di:L.shape[0] - 1 + di, dj:L.shape[1] - 1 + dj, dk:L.shape[2] - 1 + dk]
+               for di in (0, 1) for dj in (0, 1) for dk in (0, 1)]
+    anyv = np.zeros_like(corners[0])
+    allv = np.ones_like(corners[0])
+    for c in corners:
+        anyv |= c
+        allv &= c
+    return np.flatnonzero((anyv & ~allv).reshape(-1)).astype(np.uint32)
+
+
+def eval_level_map(res: LocalizeResult) -> np.ndarray:
+    """Per finest-lattice node: level id at which it was evaluated, 255 if never."""
+    out = np.full(res.dims, 255, np.uint8)
+    T = len(res.levels) - 1
+    for t, rec in enumerate(res.levels):
+        s = 1 << (T - t)
+        m = np.zeros(rec.dims, bool).reshape(-1)
+        m[rec.evaluated] = True
+        m = m.reshape(rec.dims)
+        sub = out[::s, ::s, ::s]
+        sub[m] = rec.level
+    return out
+
+
+def occupancy_grid(fld: Field, log2_final: int, log2_coarse: int,
+                   max_waves: int = 1 << 30) -> Dict[str, object]:
+    """Hierarchical occupancy grid of the input view, 2^L cells per axis."""
+    res = localize(lambda P: field_logit(fld, P), (log2_final,) * 3, log2_final - log2_coarse,
+                   max_waves=max_waves)
+    return dict(occ=res.val, labels=res.label, logit=res.logit, cells=surface_cells(res.label),
+                eval_level=eval_level_map(res), levels=res.levels, result=res)
+
+
+def dense_grid(fld: Field, log2_final: int) -> Dict[str, object]:
+    """Brute-force baseline: evaluate every node of the final grid."""
+    n = (1 << log2_final) + 1
+    dims = (n, n, n)
+    logit = field_logit(fld, lattice_coords(dims, np.arange(n ** 3))).reshape(dims)
+    label = (logit > 0).astype(np.uint8)
+    return dict(occ=sigmoid(logit), labels=label, logit=logit, cells=surface_cells(label))
+
+
+# ------------------------------------------------------------------ render
+
+def render_view(occ_fld: Field, color_fld: Field, view: np.ndarray, log2_w: int, log2_d: int,
+                log2_coarse_w: int, bg=(0.0, 0.0, 0.0)) -> Dict[str, object]:
+    """Mesh-free rendering (Sec. 3.2 and Eq. 3) on the target-view lattice.
+
+    The lattice has W+1 x H+1 x D+1 nodes (W = H = 2^log2_w, D = 2^log2_d); pixel
+    (v, u) of the W x H image is node column (u, v).  Rays run from k = D (nearest
+    the observer) to k = 0.
+    """
+    T = log2_w - log2_coarse_w
+    Wd = 1 << log2_w
+    D = 1 << log2_d
+    evaluate = lambda P: view_logit(occ_fld, view, P)
+    loc = localize(evaluate, (log2_w, log2_w, log2_d), T, last_level=T - 1)
+    lab_c = loc.label
+    # level L: upsample the binarized labels of level L-1
+    interp = upsample_x2(lab_c.astype(np.float64))[:Wd, :Wd, :]
+    cur = interp.copy()
+    lab = interp.copy()
+    evald = np.zeros(interp.shape, bool)
+    sub_v = loc.val[: Wd // 2, : Wd // 2, :]
+    cur[::2, ::2, ::2] = sub_v
+    lab[::2, ::2, ::2] = lab_c[: Wd // 2, : Wd // 2, :]
+    evald[::2, ::2, ::2] = loc.evaluated[: Wd // 2, : Wd // 2, :]
+    # argmax along z from the observer: first node with interpolated value 1
+    is_one = interp == 1.0
+    kk = np.arange(D + 1)
+    kstar = np.where(is_one.any(axis=2), np.max(np.where(is_one, kk, -1), axis=2), -1)
+    shadow = kk[None, None, :] < kstar[:, :, None]
+    todo = (~shadow) & (interp > 0.0) & (interp < 1.0) & ~evald
+    idx = np.flatnonzero(todo.reshape(-1))
+    dims_L = (Wd + 1, Wd + 1, D + 1)
+    # linear index in the full level-L lattice for coordinates
+    ii = idx // ((Wd) * (D + 1))
+    jj = (idx // (D + 1)) % Wd
+    k_ = idx % (D + 1)
+    full_idx = (ii * dims_L[1] + jj) * dims_L[2] + k_
+    lg = evaluate(lattice_coords(dims_L, full_idx)) if idx.size else np.zeros(0)
+    cur.reshape(-1)[idx] = sigmoid(lg)
+    lab.reshape(-1)[idx] = (lg > 0).astype(np.float64)
+    # binarize and argmax again
+    is_in = lab == 1.0
+    k1 = np.where(is_in.any(axis=2), np.max(np.where(is_in, kk, -1), axis=2), -1)
+    hit = k1 >= 0
+    zk = -1.0 + 2.0 * kk / D
+    depth = np.full((Wd, Wd), np.nan)      # indexed [u, v] here, transposed on return
+    occ_hit = np.zeros((Wd, Wd))
+    us, vs = np.nonzero(hit)
+    for u, v in zip(us, vs):
+        k = k1[u, v]
+        if k == D:
+            z = 1.0
+        else:
+            o_f = cur[u, v, k + 1]
+            o_b = cur[u, v, k]
+            t = (0.5 - o_f) / (o_b - o_f) if o_b - o_f > 0 else 0.0
+            z = zk[k + 1] + t * (zk[k] - zk[k + 1])
+        depth[u, v] = z
+        occ_hit[u, v] = cur[u, v, k]
+    rgb = np.empty((Wd, Wd, 3))
+    rgb[:] = np.asarray(bg, np.float64)
+    if us.size:
+        xs = -1.0 + 2.0 * us / Wd
+        ys = -1.0 + 2.0 * vs / Wd
+        P = np.stack([xs, ys, depth[us, vs]], axis=1)
+        Pp, _ = apply_view(view, P)
+        f = bilinear_sample(color_fld.feat, Pp[:, 0], Pp[:, 1])
+        pre = mlp_preact(color_fld.mlp, f, np.stack([Pp[:, 2], occ_hit[us, vs]], axis=1))
+        rgb[us, vs] = np.tanh(pre)
+    stats = dict(shadow=int(shadow.sum()), evaluated_last=int(idx.size), hits=int(hit.sum()))
+    return dict(rgb=np.transpose(rgb, (1, 0, 2)), depth=depth.T, hit=hit.T.astype(np.uint8),
+                kstar=kstar.T, k1=k1.T, levels=loc.levels, last_eval=idx, loc=loc, stats=stats,
+                eval_mask_last=todo)
+
+
+# ------------------------------------------------------------------ surrogate training
+
+def mlp_forward_cache(spec, f: np.ndarray, extras: np.ndarray):
+    """Forward pass keeping every layer input and pre-activation (for the backward pass)."""
+    f = np.asarray(f, np.float64)
+    x0 = np.concatenate([f, np.asarray(extras, np.float64).reshape(f.shape[0], -1)], axis=1)
+    ins, pres = [], []
+    h = x0
+    n = len(spec.widths)
+    for l in range(n):
+        if l > 0 and spec.skip[l]:
+            h = np.concatenate([h, f], axis=1)
+        ins.append(h)
+        z = h @ np.asarray(spec.W[l], np.float64).T + np.asarray(spec.b[l], np.float64)
+        pres.append(z)
+        h = _act(z, spec.hidden_act) if l < n - 1 else z
+    return ins, pres
+
+
+def bce_soft(s: np.ndarray, target: np.ndarray) -> Tuple[float, np.ndarray]:
+    """Binary cross entropy with soft targets on logits s (the loss the paper uses for
+    occupancy, Sec. 3.1), mean over the batch.  Returns (loss, dloss/ds)."""
+    s = np.asarray(s, np.float64)
+    t = np.asarray(target, np.float64)
+    loss_each = np.logaddexp(0.0, s) - t * s     # softplus(s) - t s
+    return float(loss_each.mean()), (sigmoid(s) - t) / s.shape[0]
+
+
+def mlp_backward(spec, ins, pres, dout: np.ndarray):
+    """Weight and bias gradients of the MLP given dloss/d(output pre-activation)."""
+    n = len(spec.widths)
+    dW = [None] * n
+    db = [None] * n
+    g = np.asarray(dout, np.float64).reshape(pres[-1].shape)
+    for l in range(n - 1, -1, -1):
+        dW[l] = g.T @ ins[l]
+        db[l] = g.sum(axis=0)
+        if l == 0:
+            break
+        dx = g @ np.asarray(spec.W[l], np.float64)
+        dh = dx[:, : spec.widths[l - 1]]
+        if spec.hidden_act == "relu":
+            g = dh * (pres[l - 1] > 0)
+        else:
+            g = dh * np.where(pres[l - 1] > 0, 1.0, LRELU_SLOPE)
+    return dW, db
+
+
+def rmsprop_step(w: np.ndarray, g: np.ndarray, v: np.ndarray, lr: float = 1e-3,
+                 alpha: float = 0.99, eps: float = 1e-8):
+    """RMSProp (the optimizer the paper uses for the shape network, appendix A1.2)."""
+    v = alpha * v + (1.0 - alpha) * g * g
+    w = w - lr * g / (np.sqrt(v) + eps)
+    return w, v
+
+
+# ------------------------------------------------------------------ number formats
+
+def to_bf16(x: np.ndarray) -> np.ndarray:
+    """Round float32 values to bfloat16 (round to nearest, ties to even); returns float32."""
+    u = np.asarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    nan = np.isnan(np.asarray(x, np.float32))
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    out = (r & 0xFFFFFFFF).astype(np.uint32).view(np.float32)
+    out = np.where(nan, np.float32(np.nan), out)
+    return out
+
+
+E4M3_MAX = 448.0
+
+
+def to_e4m3(x: np.ndarray) -> np.ndarray:
+    """Round to OCP FP8 E4M3FN (4 exponent bits, bias 7, 3 mantissa bits, no inf),
+    nearest-even, saturating at +-448.  Returns the decoded values as float64."""
+    x = np.asarray(x, np.float64)
+    a = np.abs(x)
+    out = np.zeros_like(a)
+    nz = a > 0
+    # exponent of the value, clamped to the smallest normal exponent (-6) so that
+    # subnormals share the 2^-9 quantum
+    e = np.floor(np.log2(np.where(nz, a, 1.0)))
+    e = np.maximum(e, -6.0)
+    q = np.ldexp(1.0, (e - 3).astype(np.int64))     # spacing of representable values
+    m = a / q
+    r = np.floor(m)
+    frac = m - r
+    up = (frac > 0.5) | ((frac == 0.5) & (np.mod(r, 2) == 1))
+    r = r + up
+    out = np.where(nz, r * q, 0.0)
+    out = np.minimum(out, E4M3_MAX)
+    out = np.where(np.isnan(x), np.nan, np.sign(x) * out)
+    return out

@@ -1,0 +1,178 @@
+"""Seeded synthetic inputs shared by the GPU path's tests/bench and the CPU oracle.
+
+This module holds no arithmetic of the method itself: it only draws the inputs
+(feature maps, MLP weights, analytic shapes, view matrices) that both sides read.
+All randomness comes from numpy's PCG64 bit generator seeded explicitly.
+
+Recipe (the paper's workloads stand in as synthetic arrays of the same shape):
+  * feature maps: per-channel white N(0,1), smoothed by a periodic Gaussian
+    filter of std ``sigma_px`` pixels, then standardised per channel; HWC fp32.
+    Shapes follow the encoder outputs of Sec. 3.1 / appendix A1.2
+    (256 ch x 128 x 128 for the shape encoder).
+  * MLP weights: W ~ N(0, 2 / fan_in) (fan_in includes skip inputs), zero biases
+    except an optional output bias; row-major [out][in].
+  * ellipsoid unions: centres U[-0.4,0.4]^3, semi-axes U[0.15,0.45], rotations
+    from normalised Gaussian quaternions.
+  * views: yaw rotation about the y axis, no translation (3x4 row-major).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(int(seed)))
+
+
+def feature_map(H: int, W: int, C: int, sigma_px: float, seed: int) -> np.ndarray:
+    """Smooth Gaussian random field, HWC float32, each channel zero-mean unit-std."""
+    g = rng(seed)
+    white = g.standard_normal((C, H, W))
+    fy = np.fft.fftfreq(H)[:, None]
+    fx = np.fft.fftfreq(W)[None, :]
+    # transfer function of a periodic Gaussian blur with std sigma_px pixels
+    tf = np.exp(-2.0 * (math.pi ** 2) * (sigma_px ** 2) * (fx ** 2 + fy ** 2))
+    sm = np.real(np.fft.ifft2(np.fft.fft2(white, axes=(1, 2)) * tf[None], axes=(1, 2)))
+    sm -= sm.mean(axis=(1, 2), keepdims=True)
+    sm /= sm.std(axis=(1, 2), keepdims=True)
+    return np.ascontiguousarray(np.transpose(sm, (1, 2, 0)).astype(np.float32))
+
+
+@dataclass
+class MLPSpec:
+    """Fully connected network description shared by both sides.
+
+    Layer 0 reads [f; extras]; layer l >= 1 reads [h_{l-1}; f] when skip[l] is
+    set, else h_{l-1}.  The last layer is the head (1 or 3 outputs).
+    """
+    feat_dim: int
+    n_extra: int                 # scalar inputs after f in layer 0: z (1) or z, occ (2)
+    widths: List[int]            # output width of each layer
+    skip: List[bool]             # skip[l]: layer l also reads f (skip[0] ignored)
+    hidden_act: str = "relu"     # relu | lrelu
+    out_act: str = "sigmoid"     # sigmoid | tanh
+    W: List[np.ndarray] = field(default_factory=list)   # float32 [out][in]
+    b: List[np.ndarray] = field(default_factory=list)   # float32 [out]
+
+    def in_width(self, l: int) -> int:
+        if l == 0:
+            return self.feat_dim + self.n_extra
+        return self.widths[l - 1] + (self.feat_dim if self.skip[l] else 0)
+
+    def flops_per_point(self) -> int:
+        return sum(2 * self.in_width(l) * self.widths[l] for l in range(len(self.widths)))
+
+    def n_params(self) -> int:
+        return sum(self.in_width(l) * self.widths[l] + self.widths[l] for l in range(len(self.widths)))
+
+
+def he_mlp(feat_dim: int, n_extra: int, widths: List[int], skip: List[bool], seed: int,
+           hidden_act: str = "relu", out_act: str = "sigmoid", out_bias: float = 0.0) -> MLPSpec:
+    spec = MLPSpec(feat_dim, n_extra, list(widths), list(skip), hidden_act, out_act)
+    g = rng(seed)
+    for l, n_out in enumerate(widths):
+        fan_in = spec.in_width(l)
+        Wl = g.standard_normal((n_out, fan_in)) * math.sqrt(2.0 / fan_in)
+        bl = np.zeros(n_out)
+        if l == len(widths) - 1:
+            bl[:] = out_bias
+        spec.W.append(np.ascontiguousarray(Wl.astype(np.float32)))
+        spec.b.append(np.ascontiguousarray(bl.astype(np.float32)))
+    return spec
+
+
+def ellipsoids(n: int, seed: int, scale: float = 1.0) -> np.ndarray:
+    """n x 12 float32: centre (3) then M = diag(1/a) R^T row-major (9).
+
+    q(P) = |M (P - c)|^2 is < 1 inside the ellipsoid.
+    """
+    g = rng(seed)
+    out = np.zeros((n, 12), np.float64)
+    for e in range(n):
+        c = g.uniform(-0.4, 0.4, 3)
+        a = g.uniform(0.15, 0.45, 3) * scale
+        q = g.standard_normal(4)
+        q /= np.linalg.norm(q)
+        w, x, y, z = q
+        R = np.array([
+            [1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+            [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+            [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)],
+        ])
+        M = np.diag(1.0 / a) @ R.T
+        out[e, :3] = c
+        out[e, 3:] = M.reshape(-1)
+    return out.astype(np.float32)
+
+
+def sphere_as_ellipsoid(r: float) -> np.ndarray:
+    out = np.zeros((1, 12), np.float32)
+    out[0, 3:] = (np.eye(3) / r).reshape(-1)
+    return out
+
+
+def yaw_view(theta_deg: float) -> np.ndarray:
+    """3x4 row-major [A | t] mapping target-view NDC to input-view NDC (rotation about y)."""
+    th = math.radians(theta_deg)
+    c, s = math.cos(th), math.sin(th)
+    if abs(c) < 1e-12:
+        c = 0.0
+    if abs(s) < 1e-12:
+        s = 0.0
+    A = np.array([[c, 0.0, s, 0.0], [0.0, 1.0, 0.0, 0.0], [-s, 0.0, c, 0.0]])
+    return A.reshape(-1).astype(np.float32)
+
+
+# ---------------------------------------------------------------- workloads
+PLANE_TINY = np.array([0.3, -0.5, 0.8, -0.1], np.float32)   # logit = a.P + d
+SHARPNESS = 8.0
+
+
+def tiny_features():
+    """64 ch x 32 x 32, 4-px correlation (the tiny plain-method workload)."""
+    return feature_map(32, 32, 64, 4.0, 101)
+
+
+def tiny_mlp():
+    """(64 feat + z) -> 128 -> 64 -> 1, ReLU hidden, sigmoid out."""
+    return he_mlp(64, 1, [128, 64, 1], [False, False, False], 201)
+
+
+def pifu_features(seed: int = 102):
+    """256 ch x 128 x 128 (the shape encoder's output size), 16-px correlation."""
+    return feature_map(128, 128, 256, 16.0, seed)
+
+
+def pifu_mlp(seed: int = 202, out_bias: float = 0.0):
+    """(256+z)->1024->512->256->128->1 with the feature concatenated into hidden layers 2-4."""
+    return he_mlp(256, 1, [1024, 512, 256, 128, 1], [False, True, True, True, False], seed,
+                  out_bias=out_bias)
+
+
+def surrogate_mlp(seed: int = 203):
+    """(256+z)->128->64->1, the distilled occupancy network."""
+    return he_mlp(256, 1, [128, 64, 1], [False, False, False], seed)
+
+
+def color_features(seed: int = 802):
+    return feature_map(128, 128, 256, 16.0, seed)
+
+
+def color_mlp(seed: int = 902):
+    """(256 + z + occ) -> 512 -> 256 -> 3, LeakyReLU hidden, tanh out."""
+    return he_mlp(256, 2, [512, 256, 3], [False, False, False], seed,
+                  hidden_act="lrelu", out_act="tanh")
+
+
+def precision_points(n: int, seed: int = 403) -> np.ndarray:
+    """n uniform points in [-1,1]^3 (float64 n x 3)."""
+    return rng(seed).uniform(-1.0, 1.0, (n, 3))
+
+
+def jitter_points(base: np.ndarray, spacing: float, seed: int) -> np.ndarray:
+    g = rng(seed)
+    return base + g.uniform(-0.5 * spacing, 0.5 * spacing, base.shape)
