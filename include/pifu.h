@@ -1,0 +1,254 @@
+/*
+ * pifu.h -- C ABI of libpifu, the MI355X (gfx950) implementation of hierarchical
+ * surface localization and mesh-free rendering for a pixel-aligned implicit
+ * function (Li et al., "Monocular Real-Time Volumetric Performance Capture",
+ * ECCV 2020, Sec. 3.2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - A grid with 2^L cells per axis has 2^L + 1 nodes per axis.  Node (i, j, k)
+ *    sits at NDC (-1 + 2i/2^Lx, -1 + 2j/2^Ly, -1 + 2k/2^Lz); i runs along x,
+ *    j along y, k along z.  Linear node index n = (i * ny + j) * nz + k (z fastest).
+ *  - Feature maps are HWC float32 in device memory: F[h][w][c], row h along y,
+ *    column w along x.  Pixel coordinates are u = (x+1)/2 (W-1), v = (y+1)/2 (H-1);
+ *    texels outside the map contribute 0 (the bilinear sampler of Eq. 1).
+ *  - label = [logit > 0]; occupancy p = sigmoid(logit) (the 0.5 level set of Sec. 3).
+ *  - Every pointer documented "device" must point to memory of the current HIP
+ *    device, owned by the caller.  "host" pointers are read during the call only.
+ *  - Every call validates its arguments on the host before any launch and
+ *    returns a negative status without touching device memory on failure.
+ *    No C++ exception crosses this boundary.
+ *  - pifu_occupancy_grid and pifu_render_view block until their work on
+ *    `stream` is complete (the conflict loop's trip count is read back between
+ *    waves); results are then visible to later work on any stream.
+ *  - The library never allocates device memory during a call: scratch comes
+ *    from the caller's workspace, sized by the matching *_workspace_size query.
+ */
+#ifndef PIFU_H
+#define PIFU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+#define PIFU_OK 0
+#define PIFU_ERR_INVALID_ARGUMENT (-1)   /* null/misaligned pointer, size out of range */
+#define PIFU_ERR_WORKSPACE_TOO_SMALL (-2)
+#define PIFU_ERR_UNSUPPORTED (-3)        /* device is not gfx950, or unsupported shape */
+#define PIFU_ERR_HIP (-4)                /* a HIP runtime call or launch failed */
+
+/* ---------------------------------------------------------------- enums */
+#define PIFU_FIELD_MLP 0          /* Eq. 1: MLP over bilinearly sampled features */
+#define PIFU_FIELD_ELLIPSOIDS 1   /* analytic stand-in: k (1 - min_i |M_i (P - c_i)|^2) */
+#define PIFU_FIELD_PLANE 2        /* analytic stand-in: a x + b y + c z + d */
+
+#define PIFU_ACT_RELU 1
+#define PIFU_ACT_LRELU 2          /* LeakyReLU, negative slope 0.01 */
+#define PIFU_ACT_SIGMOID 3
+#define PIFU_ACT_TANH 4
+
+#define PIFU_PREC_FP32 0          /* MFMA f32 inputs, f32 accumulation */
+#define PIFU_PREC_BF16 1          /* MFMA bf16 inputs, f32 accumulation */
+#define PIFU_PREC_FP8 2           /* MFMA OCP e4m3 inputs with per-layer scales, f32 accumulation */
+
+#define PIFU_MAX_LAYERS 8
+#define PIFU_MAX_ELLIPSOIDS 32
+
+typedef void* pifu_stream;        /* a hipStream_t; NULL means the null stream */
+typedef struct pifu_ctx pifu_ctx;
+
+/*
+ * Fully connected network (the occupancy MLP f_O of Eq. 1, the colour MLP f_T
+ * of Eq. 2, or a distilled surrogate).  Layer 0 reads [f; extras] where f is the
+ * sampled feature (feat_dim values) and extras are z (n_extra = 1) or z and the
+ * occupancy value (n_extra = 2).  Layer l >= 1 reads [h_{l-1}; f] when skip[l]
+ * is non-zero, else h_{l-1}.  Hidden layers use hidden_act; the last layer
+ * (1 or 3 outputs) is followed by out_act.
+ * W[l] is device float32 row-major [widths[l]][in_width(l)]; b[l] device float32.
+ * Supported: feat_dim % 32 == 0, hidden widths % 64 == 0, last width <= 4.
+ * fp8_amax[l] (host value) is the calibrated max |input| of layer l, used for the
+ * static FP8 activation scale; 0 selects the default amax 16.
+ */
+typedef struct pifu_mlp {
+  int32_t n_layers;
+  int32_t feat_dim;
+  int32_t n_extra;
+  int32_t hidden_act;
+  int32_t out_act;
+  int32_t widths[PIFU_MAX_LAYERS];
+  int32_t skip[PIFU_MAX_LAYERS];
+  const float* W[PIFU_MAX_LAYERS];
+  const float* b[PIFU_MAX_LAYERS];
+  float fp8_amax[PIFU_MAX_LAYERS];
+} pifu_mlp;
+
+/*
+ * An occupancy (or colour) field.  For PIFU_FIELD_MLP: feat (device, HWC float32,
+ * H x W x C with C == mlp->feat_dim) and mlp (host struct) are required;
+ * surrogate (host struct, nullable) is a cheaper MLP over the same features used
+ * on coarse levels (see pifu_grid_opts).  For PIFU_FIELD_ELLIPSOIDS: ell (host)
+ * holds n_ell records of 12 floats: centre c (3) then M = diag(1/a) R^T row-major
+ * (9); logit = sharpness * (1 - min_i |M_i (P - c_i)|^2).  For PIFU_FIELD_PLANE:
+ * logit = plane[0] x + plane[1] y + plane[2] z + plane[3].  Analytic fields are
+ * evaluated in float64.
+ */
+typedef struct pifu_field {
+  int32_t kind;
+  int32_t H, W, C;
+  const float* feat;
+  const pifu_mlp* mlp;
+  const pifu_mlp* surrogate;
+  int32_t n_ell;
+  float sharpness;
+  const float* ell;
+  float plane[4];
+} pifu_field;
+
+/* Per-level counters (Sec. 3.2 steps), written to host memory by the calls. */
+typedef struct pifu_level_stats {
+  int32_t level;            /* log2 of the x cell count of this level */
+  uint32_t nodes;           /* nodes of the level lattice (render last level: output columns x (D+1)) */
+  uint32_t b0;              /* boundary candidates: interpolated value neither 0 nor 1 */
+  uint32_t dilated;         /* nodes of the 1-ring dilation not evaluated before */
+  uint32_t evaluated;       /* nodes evaluated at this level (all waves) */
+  uint32_t waves;           /* conflict waves that added nodes */
+  uint32_t conflicts;       /* conflict nodes summed over waves */
+  uint32_t mlp_points;      /* points pushed through the MLP (incl. clipped render points) */
+  uint32_t band_fp32;       /* points re-run in FP32 by the precision band */
+  uint32_t guard_fp64;      /* points re-run in FP64 by the FP32 guard band */
+  uint32_t surrogate_fallback; /* surrogate points re-run with the full MLP */
+  uint32_t shadow;          /* render last level: shadow nodes (never evaluated) */
+  uint32_t hits;            /* render last level: pixels with a surface hit */
+  uint32_t reserved[3];
+} pifu_level_stats;
+
+/*
+ * Options of pifu_occupancy_grid.
+ *   log2_final in [1, 10], log2_coarse in [1, log2_final]: the final grid has
+ *   2^log2_final cells per axis and the coarsest (densely evaluated) level
+ *   2^log2_coarse.  dense != 0 evaluates every final node instead (the
+ *   brute-force baseline) and ignores log2_coarse.
+ *   precision: PIFU_PREC_*.  band_delta: for BF16/FP8, points with
+ *   |p - 0.5| < band_delta are re-run in FP32.  guard_logit: points whose FP32
+ *   logit has |logit| < guard_logit are re-run in FP64 so that labels are decided
+ *   exactly (0 disables).  surrogate_max_log2: levels with at most this log2
+ *   size use field->surrogate when present (points with |p_s - 0.5| <
+ *   surrogate_delta go to the full MLP); -1 disables.  tile_m: MLP point tile
+ *   (0 = default 128; 64/128/256).  max_waves: cap on conflict waves per level
+ *   (0 = none).
+ */
+typedef struct pifu_grid_opts {
+  int32_t log2_final;
+  int32_t log2_coarse;
+  int32_t dense;
+  int32_t precision;
+  float band_delta;
+  float guard_logit;
+  int32_t surrogate_max_log2;
+  float surrogate_delta;
+  int32_t tile_m;
+  int32_t max_waves;
+} pifu_grid_opts;
+
+/*
+ * Options of pifu_render_view.  The target-view lattice has 2^log2_w cells in x
+ * and y and 2^log2_d cells in z; the coarsest level has 2^log2_coarse_w cells in
+ * x and y (and 2^(log2_d - log2_w + log2_coarse_w) in z).  The image is W x H with
+ * W = H = 2^log2_w; pixel (row v, column u) is node column (u, v).  Other fields
+ * as in pifu_grid_opts.
+ */
+typedef struct pifu_render_opts {
+  int32_t log2_w;
+  int32_t log2_d;
+  int32_t log2_coarse_w;
+  int32_t precision;
+  float band_delta;
+  float guard_logit;
+  int32_t surrogate_max_log2;
+  float surrogate_delta;
+  int32_t tile_m;
+  int32_t max_waves;
+} pifu_render_opts;
+
+/* ---------------------------------------------------------------- handle */
+
+/* Creates a handle bound to the current HIP device (must be gfx950).  The
+ * handle owns a few bytes of pinned host memory for count read-back and never
+ * allocates device memory.  One handle must not be used by two threads at once. */
+int32_t pifu_create(pifu_ctx** out);
+void pifu_destroy(pifu_ctx* ctx);
+const char* pifu_status_string(int32_t status);
+
+/* ---------------------------------------------------------------- occupancy grid */
+
+/* Bytes of device workspace pifu_occupancy_grid needs for these options/field. */
+int32_t pifu_occupancy_grid_workspace_size(const pifu_field* field, const pifu_grid_opts* opts,
+                                           size_t* bytes);
+
+/*
+ * Hierarchical surface localization on the input-view grid (Sec. 3.2,
+ * "Octree-based Robust Surface Localization"; evaluation by Eq. 1).
+ * Outputs (device, (2^L+1)^3 entries, z fastest):
+ *   occ     float32: p where the network was evaluated, else the culled value 0/1.
+ *   labels  uint8 0/1.
+ *   eval_level (nullable) uint8: level (log2 size) at which each node was
+ *           evaluated, 255 if never.
+ * cells (device, cells_cap entries): sorted indices (i*R + j)*R + k of the cells
+ * whose 8 corner labels differ; *n_cells (host) receives the true count, which
+ * may exceed cells_cap (then only cells_cap entries are written).
+ * stats (host, nullable): log2_final - log2_coarse + 1 records, coarsest first.
+ */
+int32_t pifu_occupancy_grid(pifu_ctx* ctx, const pifu_field* field, const pifu_grid_opts* opts,
+                            float* occ, uint8_t* labels, uint8_t* eval_level,
+                            uint32_t* cells, uint32_t cells_cap, uint32_t* n_cells,
+                            pifu_level_stats* stats, void* workspace, size_t workspace_bytes,
+                            pifu_stream stream);
+
+/* ---------------------------------------------------------------- render */
+
+int32_t pifu_render_view_workspace_size(const pifu_field* occ_field, const pifu_field* color_field,
+                                        const pifu_render_opts* opts, size_t* bytes);
+
+/*
+ * Mesh-free rendering of a target view (Sec. 3.2, "Mesh-free Rendering"; Eq. 3).
+ * view (host, 12 floats): row-major 3x4 [A | t] mapping target-view NDC to
+ * input-view NDC; points mapped outside [-1,1]^3 have logit -inf.  bg (host, 3).
+ * Outputs (device, image row-major, H = W = 2^log2_w):
+ *   rgb   float32 H*W*3: tanh output of the colour MLP at the hit point
+ *         (Eq. 2 with extras z' and the occupancy of the hit node), bg elsewhere.
+ *   depth float32 H*W: target-view z of the hit point, NaN where no hit.
+ *   hit   uint8 H*W: 1 where the ray meets the surface.
+ * stats (host, nullable): (log2_w - log2_coarse_w + 1) records; the last one is
+ * the final render level (shadow, evaluated, hits).
+ * color_field must be PIFU_FIELD_MLP with an MLP of n_extra == 2 and 3 outputs.
+ */
+int32_t pifu_render_view(pifu_ctx* ctx, const pifu_field* occ_field, const pifu_field* color_field,
+                         const float* view, const pifu_render_opts* opts, const float* bg,
+                         float* rgb, float* depth, uint8_t* hit, pifu_level_stats* stats,
+                         void* workspace, size_t workspace_bytes, pifu_stream stream);
+
+/* ---------------------------------------------------------------- point evaluation */
+
+int32_t pifu_eval_points_workspace_size(const pifu_field* field, int32_t precision, uint32_t n,
+                                        size_t* bytes);
+
+/*
+ * Evaluates a field at n input-view NDC points (Eq. 1) with the same kernels the
+ * grid path uses.  pts: device float32 n x 4 (x, y, z, unused).  logit: device
+ * float32 n.  labels (device uint8 n, nullable) receives the label decided with
+ * the guard band.  precision / band_delta / guard_logit as in pifu_grid_opts.
+ * Blocks until done.
+ */
+int32_t pifu_eval_points(pifu_ctx* ctx, const pifu_field* field, int32_t precision,
+                         float band_delta, float guard_logit, const float* pts, uint32_t n,
+                         float* logit, uint8_t* labels, void* workspace, size_t workspace_bytes,
+                         pifu_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PIFU_H */

@@ -142,7 +142,10 @@ def field_logit(fld: Field, P: np.ndarray, chunk: int = 32768) -> np.ndarray:
 def apply_view(view: np.ndarray, P: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
     """P' = A P + t for a 3x4 row-major view; also the mask P' in [-1,1]^3."""
     V = np.asarray(view, np.float64).reshape(3, 4)
-    Pp = P @ V[:, :3].T + V[:, 3]
+    P = np.asarray(P, np.float64)
+    Pp = np.empty_like(P)
+    for r in range(3):   # elementwise, fixed order, no fused multiply-add
+        Pp[:, r] = ((V[r, 0] * P[:, 0] + V[r, 1] * P[:, 1]) + V[r, 2] * P[:, 2]) + V[r, 3]
     inside = np.all((Pp >= -1.0) & (Pp <= 1.0), axis=1)
     return Pp, inside
 

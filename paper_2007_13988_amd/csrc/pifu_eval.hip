@@ -1,0 +1,522 @@
+// Point evaluation kernels: point projection (with the optional target->input view
+// transform), bilinear feature gather (the sampler of Eq. 1), analytic stand-in
+// fields, the MLP output head, the FP64 guard re-evaluation, and the per-ray
+// kernels of mesh-free rendering (Sec. 3.2, Eq. 3).
+#include "pifu_internal.h"
+
+namespace pifu {
+
+static inline unsigned grid1d(size_t n, int block) { return (unsigned)((n + block - 1) / block); }
+
+// Node or explicit point -> input-view NDC.  Lattice coordinates are exact dyadic
+// values; the view product is taken in float64 in a fixed order without fused
+// multiply-add so the clip decision is reproducible.  Returns false when the point
+// falls outside [-1,1]^3 after the view transform.
+__device__ inline bool src_point(const PointSrc& s, const uint32_t* __restrict__ list, uint32_t m,
+                                 double P[3], float* occ) {
+  const uint32_t idx = list ? list[m] : m;
+  if (s.mode == 1) {
+    const float4 q = s.pts[idx];
+    P[0] = q.x;
+    P[1] = q.y;
+    P[2] = q.z;
+    if (occ) *occ = q.w;
+    return true;
+  }
+  const uint32_t nyz = (uint32_t)s.ny * s.nz;
+  const uint32_t a = idx / nyz;
+  const uint32_t r = idx - a * nyz;
+  const uint32_t b = r / s.nz;
+  const uint32_t k = r - b * s.nz;
+  double x = __dadd_rn(-1.0, __ddiv_rn(__dmul_rn(2.0, (double)a), (double)(s.nx - 1)));
+  double y = __dadd_rn(-1.0, __ddiv_rn(__dmul_rn(2.0, (double)b), (double)(s.ny - 1)));
+  double z = __dadd_rn(-1.0, __ddiv_rn(__dmul_rn(2.0, (double)k), (double)(s.nz - 1)));
+  if (!s.has_view) {
+    P[0] = x;
+    P[1] = y;
+    P[2] = z;
+    return true;
+  }
+  bool in = true;
+#pragma unroll
+  for (int r3 = 0; r3 < 3; ++r3) {
+    const double* v = s.view + 4 * r3;
+    double t = __dadd_rn(__dadd_rn(__dadd_rn(__dmul_rn(v[0], x), __dmul_rn(v[1], y)),
+                                   __dmul_rn(v[2], z)), v[3]);
+    P[r3] = t;
+    in = in && (t >= -1.0) && (t <= 1.0);
+  }
+  return in;
+}
+
+__device__ inline void bilinear_setup(double x, double y, int H, int W, int& u0, int& v0,
+                                      double w[4]) {
+  double u = __dmul_rn(__dmul_rn(__dadd_rn(x, 1.0), 0.5), (double)(W - 1));
+  double v = __dmul_rn(__dmul_rn(__dadd_rn(y, 1.0), 0.5), (double)(H - 1));
+  double fu0 = floor(u), fv0 = floor(v);
+  double fu = u - fu0, fv = v - fv0;
+  u0 = (int)fu0;
+  v0 = (int)fv0;
+  w[0] = (1.0 - fu) * (1.0 - fv);
+  w[1] = fu * (1.0 - fv);
+  w[2] = (1.0 - fu) * fv;
+  w[3] = fu * fv;
+}
+
+// ------------------------------------------------------------------ analytic fields
+__global__ void k_eval_analytic(PointSrc src, const uint32_t* __restrict__ list, uint32_t n,
+                                int kind, Ellipsoids ell, float4 plane,
+                                float* __restrict__ logit, uint8_t* __restrict__ lab) {
+  uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n) return;
+  double P[3];
+  bool in = src_point(src, list, m, P, nullptr);
+  double lg;
+  if (!in) {
+    lg = -INFINITY;
+  } else if (kind == PIFU_FIELD_PLANE) {
+    lg = (double)plane.x * P[0] + (double)plane.y * P[1] + (double)plane.z * P[2] + (double)plane.w;
+  } else {
+    double qmin = INFINITY;
+    for (int e = 0; e < ell.n; ++e) {
+      const float* E = ell.e + 12 * e;
+      double d0 = P[0] - E[0], d1 = P[1] - E[1], d2 = P[2] - E[2];
+      double q = 0.0;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        double t = (double)E[3 + 3 * r] * d0 + (double)E[4 + 3 * r] * d1 + (double)E[5 + 3 * r] * d2;
+        q += t * t;
+      }
+      qmin = q < qmin ? q : qmin;
+    }
+    lg = (double)ell.k * (1.0 - qmin);
+  }
+  logit[m] = (float)lg;
+  lab[m] = lg > 0.0;
+}
+
+void launch_eval_analytic(const PointSrc& src, const uint32_t* list, uint32_t n, int kind,
+                          const Ellipsoids& ell, const float plane[4], float* logit, uint8_t* lab,
+                          hipStream_t s) {
+  if (!n) return;
+  float4 pl = make_float4(plane[0], plane[1], plane[2], plane[3]);
+  hipLaunchKernelGGL(k_eval_analytic, dim3(grid1d(n, 128)), dim3(128), 0, s, src, list, n, kind,
+                     ell, pl, logit, lab);
+}
+
+// ------------------------------------------------------------------ bilinear gather
+// A group of C/4 lanes handles one point; each lane blends 4 channels of the four
+// texels (float4 loads from the HWC map) and writes them to row m of feat.
+template <bool BF16>
+__global__ void __launch_bounds__(256)
+k_gather(PointSrc src, const uint32_t* __restrict__ list, uint32_t n,
+         const float* __restrict__ F, int H, int W, int C, void* __restrict__ feat,
+         float* __restrict__ ext) {
+  const int lanes = C >> 2;
+  const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int per = lanes < 64 ? lanes : 64;   // lanes per point group (<= one wave)
+  const uint32_t m = gid / per;
+  const int lane = gid % per;
+  if (m >= n) return;
+  double P[3];
+  float occ = 0.f;
+  const bool in = src_point(src, list, m, P, &occ);
+  int u0, v0;
+  double w[4];
+  bilinear_setup(P[0], P[1], H, W, u0, v0, w);
+  const float wf[4] = {(float)w[0], (float)w[1], (float)w[2], (float)w[3]};
+  const int tu[4] = {u0, u0 + 1, u0, u0 + 1};
+  const int tv[4] = {v0, v0, v0 + 1, v0 + 1};
+  for (int c4 = lane; c4 < lanes; c4 += per) {
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (tu[t] < 0 || tu[t] > W - 1 || tv[t] < 0 || tv[t] > H - 1) continue;
+      const float4 q = *reinterpret_cast<const float4*>(F + ((size_t)tv[t] * W + tu[t]) * C + 4 * c4);
+      acc.x = fmaf(wf[t], q.x, acc.x);
+      acc.y = fmaf(wf[t], q.y, acc.y);
+      acc.z = fmaf(wf[t], q.z, acc.z);
+      acc.w = fmaf(wf[t], q.w, acc.w);
+    }
+    if (BF16) {
+      uint2 o;
+      o.x = (uint32_t)f32_to_bf16_bits(acc.x) | ((uint32_t)f32_to_bf16_bits(acc.y) << 16);
+      o.y = (uint32_t)f32_to_bf16_bits(acc.z) | ((uint32_t)f32_to_bf16_bits(acc.w) << 16);
+      *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(feat) + (size_t)m * C + 4 * c4) = o;
+    } else {
+      *reinterpret_cast<float4*>(reinterpret_cast<float*>(feat) + (size_t)m * C + 4 * c4) = acc;
+    }
+  }
+  if (lane == 0)
+    *reinterpret_cast<float4*>(ext + 4 * (size_t)m) =
+        make_float4((float)P[2], occ, in ? 0.f : 1.f, 0.f);
+}
+
+void launch_gather(const PointSrc& src, const uint32_t* list, uint32_t n, const float* F, int H,
+                   int W, int C, void* feat, int feat_bf16, float* ext, hipStream_t s) {
+  if (!n) return;
+  const int lanes = C >> 2;
+  const int per = lanes < 64 ? lanes : 64;
+  size_t threads = (size_t)n * per;
+  if (feat_bf16)
+    hipLaunchKernelGGL(k_gather<true>, dim3(grid1d(threads, 256)), dim3(256), 0, s, src, list, n, F,
+                       H, W, C, feat, ext);
+  else
+    hipLaunchKernelGGL(k_gather<false>, dim3(grid1d(threads, 256)), dim3(256), 0, s, src, list, n,
+                       F, H, W, C, feat, ext);
+}
+
+// ------------------------------------------------------------------ output head
+// One wave per point: the last linear layer (<= 4 outputs) as a wave-wide dot
+// product, then the output rule.  n_out == 1: occupancy logit (-inf when clipped),
+// label = [logit > 0].  n_out == 3: colour, tanh, written to rgb_out[pixel * 3 + c].
+__global__ void __launch_bounds__(256)
+k_head(const float* __restrict__ h, int K, const float* __restrict__ W, const float* __restrict__ b,
+       int n_out, int out_act, uint32_t n, const float* __restrict__ ext, float* __restrict__ logit,
+       uint8_t* __restrict__ lab, float* __restrict__ rgb_out, const uint32_t* __restrict__ rgb_index) {
+  const uint32_t m = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (m >= n) return;
+  float acc[4] = {0.f, 0.f, 0.f, 0.f};
+  const float* hr = h + (size_t)m * K;
+  for (int k = lane; k < K; k += 64) {
+    const float x = hr[k];
+    for (int o = 0; o < n_out; ++o) acc[o] = fmaf(x, W[(size_t)o * K + k], acc[o]);
+  }
+  for (int o = 0; o < n_out; ++o) {
+    float v = acc[o];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    acc[o] = v + b[o];
+  }
+  if (lane != 0) return;
+  if (n_out == 1) {
+    float v = acc[0];
+    if (ext && ext[4 * (size_t)m + 2] != 0.f) v = -INFINITY;
+    logit[m] = v;
+    lab[m] = v > 0.f;
+  } else {
+    const uint32_t pix = rgb_index ? rgb_index[m] : m;
+    for (int o = 0; o < n_out; ++o) {
+      float v = acc[o];
+      if (out_act == PIFU_ACT_TANH) v = tanhf(v);
+      else if (out_act == PIFU_ACT_SIGMOID) v = 1.f / (1.f + expf(-v));
+      rgb_out[(size_t)pix * n_out + o] = v;
+    }
+  }
+}
+
+void launch_head(const float* h, int K, const float* W, const float* b, int n_out, int out_act,
+                 uint32_t n, const float* ext, float* logit, uint8_t* lab, float* rgb_out,
+                 const uint32_t* rgb_index, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_head, dim3(grid1d((size_t)n * 64, 256)), dim3(256), 0, s, h, K, W, b, n_out,
+                     out_act, n, ext, logit, lab, rgb_out, rgb_index);
+}
+
+// ------------------------------------------------------------------ FP64 guard band
+__global__ void k_guard_select(const float* __restrict__ logit, uint32_t n, float g,
+                               uint32_t* __restrict__ glist, uint32_t* __restrict__ gcount) {
+  uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n) return;
+  if (fabsf(logit[m]) < g) {
+    uint32_t slot = atomicAdd(gcount, 1u);
+    glist[slot] = m;
+  }
+}
+
+void launch_guard_select(const float* logit, uint32_t n, float g, uint32_t* glist,
+                         uint32_t* gcount, hipStream_t s) {
+  if (!n || !(g > 0.f)) return;
+  hipLaunchKernelGGL(k_guard_select, dim3(grid1d(n, 256)), dim3(256), 0, s, logit, n, g, glist,
+                     gcount);
+}
+
+constexpr int GUARD_MAXW = 1024;
+constexpr int GUARD_MAXC = 512;
+
+// One workgroup per guarded point: the whole evaluation (gather + every layer) in
+// float64 with wave-wide dot products, so the label is decided in float64.
+__global__ void __launch_bounds__(256)
+k_guard_fp64(PointSrc src, const uint32_t* __restrict__ list, const uint32_t* __restrict__ glist,
+             MLPDesc mlp, const float* __restrict__ F, int H, int W, int C,
+             float* __restrict__ logit, uint8_t* __restrict__ lab) {
+  __shared__ double f[GUARD_MAXC];
+  __shared__ double hbuf[2][GUARD_MAXW + GUARD_MAXC + 4];
+  const uint32_t m = glist[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double P[3];
+  float occ = 0.f;
+  const bool in = src_point(src, list, m, P, &occ);
+  if (!in) {
+    if (tid == 0) {
+      logit[m] = -INFINITY;
+      lab[m] = 0;
+    }
+    return;
+  }
+  int u0, v0;
+  double w[4];
+  bilinear_setup(P[0], P[1], H, W, u0, v0, w);
+  for (int c = tid; c < C; c += 256) {
+    double acc = 0.0;
+    const int tu[4] = {u0, u0 + 1, u0, u0 + 1};
+    const int tv[4] = {v0, v0, v0 + 1, v0 + 1};
+    for (int t = 0; t < 4; ++t) {
+      if (tu[t] < 0 || tu[t] > W - 1 || tv[t] < 0 || tv[t] > H - 1) continue;
+      acc += w[t] * (double)F[((size_t)tv[t] * W + tu[t]) * C + c];
+    }
+    f[c] = acc;
+  }
+  __syncthreads();
+  // layer 0 input: [f; z (; occ)]
+  double* in_buf = hbuf[0];
+  for (int c = tid; c < C; c += 256) in_buf[c] = f[c];
+  if (tid == 0) {
+    in_buf[C] = P[2];
+    if (mlp.n_extra > 1) in_buf[C + 1] = occ;
+  }
+  __syncthreads();
+  int cur = 0;
+  double result = 0.0;
+  for (int l = 0; l < mlp.n_layers; ++l) {
+    const int K = mlp.in_w[l];
+    const int N = mlp.widths[l];
+    double* xin = hbuf[cur];
+    double* xout = hbuf[cur ^ 1];
+    const float* Wl = mlp.W[l];
+    const bool last = l == mlp.n_layers - 1;
+    for (int o = wave; o < N; o += 4) {
+      double acc = 0.0;
+      for (int k = lane; k < K; k += 64) acc += (double)Wl[(size_t)o * K + k] * xin[k];
+#pragma unroll
+      for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
+      acc += (double)mlp.b[l][o];
+      if (!last) {
+        if (mlp.hidden_act == PIFU_ACT_RELU) acc = acc > 0.0 ? acc : 0.0;
+        else acc = acc > 0.0 ? acc : 0.01 * acc;
+      }
+      if (lane == 0) {
+        if (last) {
+          if (o == 0) result = acc;
+        } else {
+          xout[o] = acc;
+        }
+      }
+    }
+    __syncthreads();
+    if (!last && mlp.skip[l + 1]) {
+      for (int c = tid; c < C; c += 256) xout[N + c] = f[c];
+      __syncthreads();
+    }
+    cur ^= 1;
+  }
+  if (tid == 0) {
+    logit[m] = (float)result;
+    lab[m] = result > 0.0;
+  }
+}
+
+void launch_guard_fp64(const PointSrc& src, const uint32_t* list, const uint32_t* glist,
+                       uint32_t gn, const MLPDesc& mlp, const float* F, int H, int W, int C,
+                       float* logit, uint8_t* lab, hipStream_t s) {
+  if (!gn) return;
+  hipLaunchKernelGGL(k_guard_fp64, dim3(gn), dim3(256), 0, s, src, list, glist, mlp, F, H, W, C,
+                     logit, lab);
+}
+
+// ------------------------------------------------------------------ mesh-free rendering
+// Level-L interpolation along a pixel column (u, v) of the target lattice, from the
+// binarized labels of level L-1: S(kc) sums the labels of the 1/2/4 coarse columns
+// around (u, v); even k use S(k/2), odd k the two neighbours.
+struct RayCol {
+  const uint8_t* col[4];
+  int ncol;
+  __device__ inline int S(int kc) const {
+    int s = 0;
+    for (int i = 0; i < ncol; ++i) s += col[i][kc] & ST_LABEL;
+    return s;
+  }
+  __device__ inline void at(int k, int& sum, int& cnt) const {
+    if (k & 1) {
+      sum = S(k >> 1) + S((k >> 1) + 1);
+      cnt = 2 * ncol;
+    } else {
+      sum = S(k >> 1);
+      cnt = ncol;
+    }
+  }
+};
+
+__device__ inline RayCol make_raycol(const uint8_t* stc, Lat c, int u, int v) {
+  RayCol r;
+  r.ncol = 0;
+  const int ua = u >> 1, ub = (u + 1) >> 1, va = v >> 1, vb = (v + 1) >> 1;
+  for (int i = 0; i < 2; ++i) {
+    int cu = i ? ub : ua;
+    if (i && ub == ua) continue;
+    for (int j = 0; j < 2; ++j) {
+      int cv = j ? vb : va;
+      if (j && vb == va) continue;
+      r.col[r.ncol++] = stc + ((size_t)cu * c.ny + cv) * c.nz;
+    }
+  }
+  return r;
+}
+
+// Per column: k* = the node nearest the observer whose interpolated value is 1;
+// nodes below it are shadow nodes.  Counts the non-shadow nodes with a fractional
+// interpolated value (the ones the network evaluates).
+__global__ void k_ray_count(const uint8_t* __restrict__ stc, Lat c, int W, int H, int D,
+                            uint32_t* __restrict__ cnt, uint32_t* __restrict__ kstar,
+                            uint32_t* __restrict__ shadow_total) {
+  const uint32_t col = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t shadow = 0;
+  if (col < (uint32_t)W * H) {
+    const int u = col / H, v = col - (col / H) * H;
+    RayCol rc = make_raycol(stc, c, u, v);
+    int ks = -1;
+    uint32_t n = 0;
+    for (int k = D; k >= 0; --k) {
+      int s, t;
+      rc.at(k, s, t);
+      if (s == t) {
+        ks = k;
+        break;
+      }
+      if (s > 0) ++n;
+    }
+    cnt[col] = n;
+    kstar[col] = (uint32_t)ks;
+    shadow = ks > 0 ? (uint32_t)ks : 0u;
+  }
+  for (int d = 32; d >= 1; d >>= 1) shadow += __shfl_xor(shadow, d, 64);
+  if ((threadIdx.x & 63) == 0 && shadow) atomicAdd(shadow_total, shadow);
+}
+
+void launch_ray_count(const uint8_t* stc, Lat c, int W, int H, int D, uint32_t* cnt,
+                      uint32_t* kstar, uint32_t* shadow_total, hipStream_t s) {
+  hipLaunchKernelGGL(k_ray_count, dim3(grid1d((size_t)W * H, 256)), dim3(256), 0, s, stc, c, W, H,
+                     D, cnt, kstar, shadow_total);
+}
+
+// Writes the level-L lattice indices of each column's candidates in increasing k.
+__global__ void k_ray_list(const uint8_t* __restrict__ stc, Lat c, int W, int H, int D,
+                           const uint32_t* __restrict__ kstar, const uint32_t* __restrict__ off,
+                           uint32_t* __restrict__ list) {
+  const uint32_t col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= (uint32_t)W * H) return;
+  const int u = col / H, v = col - (col / H) * H;
+  RayCol rc = make_raycol(stc, c, u, v);
+  const int ks = (int)kstar[col];
+  uint32_t pos = off[col];
+  const size_t base = ((size_t)u * (H + 1) + v) * (size_t)(D + 1);
+  for (int k = ks + 1; k <= D; ++k) {
+    int s, t;
+    rc.at(k, s, t);
+    if (s > 0 && s < t) list[pos++] = (uint32_t)(base + k);
+  }
+}
+
+void launch_ray_list(const uint8_t* stc, Lat c, int W, int H, int D, const uint32_t* kstar,
+                     const uint32_t* off, uint32_t* list, hipStream_t s) {
+  hipLaunchKernelGGL(k_ray_list, dim3(grid1d((size_t)W * H, 256)), dim3(256), 0, s, stc, c, W, H,
+                     D, kstar, off, list);
+}
+
+// Second argmax after evaluation: k1 = first node from the observer labelled inside;
+// the surface point is the 0.5 crossing of the occupancy values of k1 and k1 + 1.
+__global__ void k_ray_hit(const uint8_t* __restrict__ stc, const float* __restrict__ occc, Lat c,
+                          int W, int H, int D, const uint32_t* __restrict__ off,
+                          const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ list,
+                          const float* __restrict__ logit, const uint8_t* __restrict__ lab,
+                          const double* __restrict__ view_unused, float* __restrict__ depth,
+                          uint8_t* __restrict__ hit, float4* __restrict__ hitpts, double4 v0,
+                          double4 v1, double4 v2) {
+  const uint32_t col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= (uint32_t)W * H) return;
+  const int u = col / H, v = col - (col / H) * H;
+  RayCol rc = make_raycol(stc, c, u, v);
+  int j = (int)off[col] + (int)cnt[col] - 1;
+  const int jmin = (int)off[col];
+  float cur_prev = 0.f;
+  int k1 = -1;
+  float ob = 0.f, of = 0.f;
+  for (int k = D; k >= 0; --k) {
+    float cur;
+    int l;
+    if (!((u | v | k) & 1)) {
+      const size_t cn = ((size_t)(u >> 1) * c.ny + (v >> 1)) * c.nz + (k >> 1);
+      l = stc[cn] & ST_LABEL;
+      cur = occc[cn];
+    } else {
+      int s, t;
+      rc.at(k, s, t);
+      const uint32_t lid = ((uint32_t)u * (H + 1) + v) * (uint32_t)(D + 1) + k;
+      if (s > 0 && s < t && j >= jmin && list[j] == lid) {
+        l = lab[j];
+        cur = 1.0f / (1.0f + expf(-logit[j]));
+        --j;
+      } else {
+        l = (s == t);
+        cur = (float)s / (float)t;
+      }
+    }
+    if (l) {
+      k1 = k;
+      ob = cur;
+      of = cur_prev;
+      break;
+    }
+    cur_prev = cur;
+  }
+  const uint32_t pix = (uint32_t)v * W + u;
+  if (k1 < 0) return;
+  double z;
+  if (k1 == D) {
+    z = 1.0;
+  } else {
+    const double t = (ob - of > 0.f) ? (0.5 - (double)of) / ((double)ob - (double)of) : 0.0;
+    const double zf = -1.0 + 2.0 * (double)(k1 + 1) / D;
+    const double zb = -1.0 + 2.0 * (double)k1 / D;
+    z = zf + t * (zb - zf);
+  }
+  depth[pix] = (float)z;
+  hit[pix] = 1;
+  const double x = -1.0 + 2.0 * (double)u / W;
+  const double y = -1.0 + 2.0 * (double)v / H;
+  hitpts[pix] = make_float4((float)(v0.x * x + v0.y * y + v0.z * z + v0.w),
+                            (float)(v1.x * x + v1.y * y + v1.z * z + v1.w),
+                            (float)(v2.x * x + v2.y * y + v2.z * z + v2.w), ob);
+}
+
+void launch_ray_hit(const uint8_t* stc, const float* occc, Lat c, int W, int H, int D,
+                    const uint32_t* off, const uint32_t* cnt, const uint32_t* list,
+                    const float* logit, const uint8_t* lab, const double* view, float* depth,
+                    uint8_t* hit, float4* hitpts, hipStream_t s) {
+  double4 v0 = make_double4(view[0], view[1], view[2], view[3]);
+  double4 v1 = make_double4(view[4], view[5], view[6], view[7]);
+  double4 v2 = make_double4(view[8], view[9], view[10], view[11]);
+  hipLaunchKernelGGL(k_ray_hit, dim3(grid1d((size_t)W * H, 256)), dim3(256), 0, s, stc, occc, c, W,
+                     H, D, off, cnt, list, logit, lab, nullptr, depth, hit, hitpts, v0, v1, v2);
+}
+
+__global__ void k_fill_image(float* __restrict__ rgb, float* __restrict__ depth,
+                             uint8_t* __restrict__ hit, uint32_t npix, float bg0, float bg1,
+                             float bg2) {
+  uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npix) return;
+  rgb[3 * (size_t)p + 0] = bg0;
+  rgb[3 * (size_t)p + 1] = bg1;
+  rgb[3 * (size_t)p + 2] = bg2;
+  depth[p] = __int_as_float(0x7fc00000);
+  hit[p] = 0;
+}
+
+void launch_fill_image(float* rgb, float* depth, uint8_t* hit, uint32_t npix, float bg0, float bg1,
+                       float bg2, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_image, dim3(grid1d(npix, 256)), dim3(256), 0, s, rgb, depth, hit, npix,
+                     bg0, bg1, bg2);
+}
+
+}  // namespace pifu

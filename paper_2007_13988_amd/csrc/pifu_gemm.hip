@@ -1,0 +1,306 @@
+// MLP layers as MFMA GEMMs over compacted point tiles (Eq. 1's f_O / Eq. 2's f_T).
+//
+// One workgroup computes a BM x BN tile of C = act(A W^T + b + extras) where A is
+// the concatenation [A1 ; A2] of the previous activation and the sampled feature
+// (the skip connection), both row-major with the contraction index contiguous.
+// Tiles are staged through LDS with double buffering; each wave owns a
+// (BM/WM) x (BN/WN) sub-tile built from 32x32 MFMA blocks.
+//
+// The contraction index is permuted inside each MFMA group: lane half h feeds the
+// k values [c*h, c*h + c) of the group (c = elements per lane per MFMA) so that a
+// lane's operand is one contiguous 16-byte LDS read.  A and B use the same
+// permutation, so the sum over k is unchanged.
+#include "pifu_internal.h"
+
+namespace pifu {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+__device__ inline float act_apply(float v, int act) {
+  if (act == PIFU_ACT_RELU) return v > 0.f ? v : 0.f;
+  if (act == PIFU_ACT_LRELU) return v > 0.f ? v : 0.01f * v;
+  return v;
+}
+
+// Epilogue: 32x32 accumulator block -> C.  Output layout of a 32x32 MFMA block:
+// lane l, register r holds row 8*(r/4) + 4*(l/32) + (r%4), column l%32.
+template <bool OUT_BF16>
+__device__ inline void store_block(const GemmArgs& a, const f32x16& acc, int row0, int col0,
+                                   int lane) {
+  const int col = col0 + (lane & 31);
+  const float bias = a.bias[col];
+  float we[2] = {0.f, 0.f};
+  for (int e = 0; e < a.n_ext; ++e) we[e] = a.Wf[(size_t)col * a.ldwf + a.ext_col + e];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int row = row0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    if (row >= a.M) continue;
+    float v = acc[r] * a.scale + bias;
+    if (a.n_ext > 0) {
+      const float* ex = a.ext + 4 * (size_t)row;
+      v = fmaf(ex[0], we[0], v);
+      if (a.n_ext > 1) v = fmaf(ex[1], we[1], v);
+    }
+    v = act_apply(v, a.act);
+    if (OUT_BF16)
+      reinterpret_cast<uint16_t*>(a.C)[(size_t)row * a.ldc + col] = f32_to_bf16_bits(v);
+    else
+      reinterpret_cast<float*>(a.C)[(size_t)row * a.ldc + col] = v;
+  }
+}
+
+// ------------------------------------------------------------------ FP32 operands
+// v_mfma_f32_32x32x2_f32: per lane one A and one B element per MFMA; 4 MFMAs consume
+// a float4 of k from LDS (k-group of 8).
+template <int BM, int BN, int WM, int WN>
+__global__ void __launch_bounds__(256, 2) k_gemm_f32(GemmArgs a) {
+  constexpr int BK = 32;
+  constexpr int LD = BK + 4;
+  constexpr int TI = BM / WM / 32, TJ = BN / WN / 32;
+  __shared__ __attribute__((aligned(16))) float As[2][BM * LD];
+  __shared__ __attribute__((aligned(16))) float Bs[2][BN * LD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const int K = a.K1 + a.K2;
+  const int nk = K / BK;
+  constexpr int A_LOADS = BM * (BK / 4) / 256;
+  constexpr int B_LOADS = BN * (BK / 4) / 256;
+  float4 ra[A_LOADS], rb[B_LOADS];
+  const float* A1 = reinterpret_cast<const float*>(a.A1);
+  const float* A2 = reinterpret_cast<const float*>(a.A2);
+  const float* Wp = reinterpret_cast<const float*>(a.W);
+
+  auto gload = [&](int kt) {
+    const int k0 = kt * BK;
+    const float* src;
+    int ld, kk0;
+    if (k0 < a.K1) {
+      src = A1;
+      ld = a.lda1;
+      kk0 = k0;
+    } else {
+      src = A2;
+      ld = a.lda2;
+      kk0 = k0 - a.K1;
+    }
+#pragma unroll
+    for (int i = 0; i < A_LOADS; ++i) {
+      const int e = tid + 256 * i;
+      const int row = e >> 3, c4 = e & 7;
+      const int gm = m0 + row;
+      ra[i] = gm < a.M ? *reinterpret_cast<const float4*>(src + (size_t)gm * ld + kk0 + 4 * c4)
+                       : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int i = 0; i < B_LOADS; ++i) {
+      const int e = tid + 256 * i;
+      const int row = e >> 3, c4 = e & 7;
+      rb[i] = *reinterpret_cast<const float4*>(Wp + (size_t)(n0 + row) * a.ldw + k0 + 4 * c4);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < A_LOADS; ++i) {
+      const int e = tid + 256 * i;
+      *reinterpret_cast<float4*>(&As[buf][(e >> 3) * LD + 4 * (e & 7)]) = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < B_LOADS; ++i) {
+      const int e = tid + 256 * i;
+      *reinterpret_cast<float4*>(&Bs[buf][(e >> 3) * LD + 4 * (e & 7)]) = rb[i];
+    }
+  };
+
+  f32x16 acc[TI][TJ];
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  const int h = lane >> 5, l32 = lane & 31;
+  const int wrow = wm * (BM / WM), wcol = wn * (BN / WN);
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) gload(kt + 1);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 8) {
+      float4 av[TI], bv[TJ];
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+        av[i] = *reinterpret_cast<const float4*>(&As[buf][(wrow + 32 * i + l32) * LD + kk + 4 * h]);
+#pragma unroll
+      for (int j = 0; j < TJ; ++j)
+        bv[j] = *reinterpret_cast<const float4*>(&Bs[buf][(wcol + 32 * j + l32) * LD + kk + 4 * h]);
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i].x, bv[j].x, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i].y, bv[j].y, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i].z, bv[j].z, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i].w, bv[j].w, acc[i][j], 0, 0, 0);
+        }
+    }
+    if (kt + 1 < nk) sstore(buf ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j)
+      store_block<false>(a, acc[i][j], m0 + wrow + 32 * i, n0 + wcol + 32 * j, lane);
+}
+
+// ------------------------------------------------------------------ BF16 operands
+// v_mfma_f32_32x32x16_bf16: 8 bf16 per lane per MFMA (one 16-byte LDS read);
+// BK = 64 bf16 per stage.
+template <int BM, int BN, int WM, int WN, bool OUT_BF16>
+__global__ void __launch_bounds__(256, 2) k_gemm_bf16(GemmArgs a) {
+  constexpr int BK = 64;
+  constexpr int LD = BK + 8;   // in bf16 elements
+  constexpr int TI = BM / WM / 32, TJ = BN / WN / 32;
+  __shared__ __attribute__((aligned(16))) __bf16 As[2][BM * LD];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[2][BN * LD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const int K = a.K1 + a.K2;
+  const int nk = K / BK;
+  constexpr int A_LOADS = BM * (BK / 8) / 256;
+  constexpr int B_LOADS = BN * (BK / 8) / 256;
+  uint4 ra[A_LOADS], rb[B_LOADS];
+  const __bf16* A1 = reinterpret_cast<const __bf16*>(a.A1);
+  const __bf16* A2 = reinterpret_cast<const __bf16*>(a.A2);
+  const __bf16* Wp = reinterpret_cast<const __bf16*>(a.W);
+
+  auto gload = [&](int kt) {
+    const int k0 = kt * BK;
+    const __bf16* src;
+    int ld, kk0;
+    if (k0 < a.K1) {
+      src = A1;
+      ld = a.lda1;
+      kk0 = k0;
+    } else {
+      src = A2;
+      ld = a.lda2;
+      kk0 = k0 - a.K1;
+    }
+#pragma unroll
+    for (int i = 0; i < A_LOADS; ++i) {
+      const int e = tid + 256 * i;
+      const int row = e >> 3, c8 = e & 7;
+      const int gm = m0 + row;
+      ra[i] = gm < a.M ? *reinterpret_cast<const uint4*>(src + (size_t)gm * ld + kk0 + 8 * c8)
+                       : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < B_LOADS; ++i) {
+      const int e = tid + 256 * i;
+      const int row = e >> 3, c8 = e & 7;
+      rb[i] = *reinterpret_cast<const uint4*>(Wp + (size_t)(n0 + row) * a.ldw + k0 + 8 * c8);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < A_LOADS; ++i) {
+      const int e = tid + 256 * i;
+      *reinterpret_cast<uint4*>(&As[buf][(e >> 3) * LD + 8 * (e & 7)]) = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < B_LOADS; ++i) {
+      const int e = tid + 256 * i;
+      *reinterpret_cast<uint4*>(&Bs[buf][(e >> 3) * LD + 8 * (e & 7)]) = rb[i];
+    }
+  };
+
+  f32x16 acc[TI][TJ];
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  const int h = lane >> 5, l32 = lane & 31;
+  const int wrow = wm * (BM / WM), wcol = wn * (BN / WN);
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) gload(kt + 1);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 16) {
+      bf16x8 av[TI], bv[TJ];
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+        av[i] = *reinterpret_cast<const bf16x8*>(&As[buf][(wrow + 32 * i + l32) * LD + kk + 8 * h]);
+#pragma unroll
+      for (int j = 0; j < TJ; ++j)
+        bv[j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][(wcol + 32 * j + l32) * LD + kk + 8 * h]);
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    if (kt + 1 < nk) sstore(buf ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j)
+      store_block<OUT_BF16>(a, acc[i][j], m0 + wrow + 32 * i, n0 + wcol + 32 * j, lane);
+}
+
+// Copies the first K columns of a row-major [N][ldw_src] fp32 weight matrix into a
+// dense [N][K] operand matrix of the requested precision (fp32 or bf16).
+__global__ void k_pack_weights(const float* __restrict__ W, int N, int ldw_src, int K,
+                               void* __restrict__ dst, int bf16) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)N * K) return;
+  const int n = (int)(i / K), k = (int)(i - (size_t)n * K);
+  const float v = W[(size_t)n * ldw_src + k];
+  if (bf16)
+    reinterpret_cast<uint16_t*>(dst)[i] = f32_to_bf16_bits(v);
+  else
+    reinterpret_cast<float*>(dst)[i] = v;
+}
+
+void launch_pack_weights(const float* W, int N, int ldw_src, int K, void* dst, int bf16,
+                         hipStream_t s) {
+  size_t n = (size_t)N * K;
+  if (n)
+    hipLaunchKernelGGL(k_pack_weights, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, W, N,
+                       ldw_src, K, dst, bf16);
+}
+
+int launch_gemm(const GemmArgs& a, int precision, int tile_m, hipStream_t s) {
+  if (a.M <= 0) return 0;
+  const bool bn128 = (a.N % 128) == 0;
+  if (!bn128 && (a.N % 64) != 0) return -1;
+  const unsigned gy = bn128 ? a.N / 128 : a.N / 64;
+  (void)tile_m;
+  const unsigned gx = (unsigned)((a.M + 127) / 128);
+  if (precision == PIFU_PREC_FP32) {
+    if ((a.K1 % 32) || (a.K2 % 32)) return -1;
+    if (bn128)
+      hipLaunchKernelGGL((k_gemm_f32<128, 128, 2, 2>), dim3(gx, gy), dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_gemm_f32<128, 64, 4, 1>), dim3(gx, gy), dim3(256), 0, s, a);
+    return 0;
+  }
+  return -1;
+}
+
+}  // namespace pifu

@@ -1,0 +1,766 @@
+// Host side of libpifu: argument validation, workspace carving, the level loop of
+// hierarchical surface localization (Sec. 3.2), mesh-free rendering (Sec. 3.2,
+// Eq. 3) and the C ABI declared in include/pifu.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "pifu_internal.h"
+
+using namespace pifu;
+
+struct pifu_ctx {
+  int device;
+  uint32_t* host_counters;   // pinned, 64 words
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kCounters = 64;
+constexpr uint32_t kDefaultChunk = 65536;
+
+// Device-side counters (words of the counters array).
+enum { C_TOTAL = 0, C_CONFLICTS = 1, C_B0 = 2, C_GUARD = 3, C_SHADOW = 4 };
+
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+  template <class T>
+  T* take(size_t count) {
+    off = (off + kAlign - 1) / kAlign * kAlign;
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+#define HIP_TRY(x)                        \
+  do {                                    \
+    if ((x) != hipSuccess) return PIFU_ERR_HIP; \
+  } while (0)
+
+inline int check_launch() { return hipGetLastError() == hipSuccess ? PIFU_OK : PIFU_ERR_HIP; }
+
+// ------------------------------------------------------------------ validation
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+int validate_mlp(const pifu_mlp* m, int C, int n_extra_expected, int n_out_expected) {
+  if (!m) return PIFU_ERR_INVALID_ARGUMENT;
+  if (m->n_layers < 2 || m->n_layers > PIFU_MAX_LAYERS) return PIFU_ERR_INVALID_ARGUMENT;
+  if (m->feat_dim != C || C % 32 != 0 || C > 512) return PIFU_ERR_INVALID_ARGUMENT;
+  if (m->n_extra != n_extra_expected) return PIFU_ERR_INVALID_ARGUMENT;
+  if (m->hidden_act != PIFU_ACT_RELU && m->hidden_act != PIFU_ACT_LRELU)
+    return PIFU_ERR_INVALID_ARGUMENT;
+  for (int l = 0; l < m->n_layers; ++l) {
+    if (!m->W[l] || !m->b[l]) return PIFU_ERR_INVALID_ARGUMENT;
+    const bool last = l == m->n_layers - 1;
+    if (last) {
+      if (m->widths[l] != n_out_expected) return PIFU_ERR_INVALID_ARGUMENT;
+    } else if (m->widths[l] <= 0 || m->widths[l] % 64 != 0 || m->widths[l] > 1024) {
+      return PIFU_ERR_INVALID_ARGUMENT;
+    }
+    if (l > 0 && m->skip[l] && last) return PIFU_ERR_INVALID_ARGUMENT;
+  }
+  return PIFU_OK;
+}
+
+int validate_field(const pifu_field* f, int n_extra, int n_out) {
+  if (!f) return PIFU_ERR_INVALID_ARGUMENT;
+  if (f->kind == PIFU_FIELD_MLP) {
+    if (!f->feat || f->H < 2 || f->W < 2 || f->C <= 0) return PIFU_ERR_INVALID_ARGUMENT;
+    if (!aligned(f->feat, 16)) return PIFU_ERR_INVALID_ARGUMENT;
+    int r = validate_mlp(f->mlp, f->C, n_extra, n_out);
+    if (r) return r;
+    if (f->surrogate) {
+      r = validate_mlp(f->surrogate, f->C, n_extra, n_out);
+      if (r) return r;
+    }
+    return PIFU_OK;
+  }
+  if (n_out != 1) return PIFU_ERR_INVALID_ARGUMENT;
+  if (f->kind == PIFU_FIELD_ELLIPSOIDS) {
+    if (!f->ell || f->n_ell < 1 || f->n_ell > PIFU_MAX_ELLIPSOIDS) return PIFU_ERR_INVALID_ARGUMENT;
+    return PIFU_OK;
+  }
+  if (f->kind == PIFU_FIELD_PLANE) return PIFU_OK;
+  return PIFU_ERR_INVALID_ARGUMENT;
+}
+
+int validate_precision(int p) {
+  if (p == PIFU_PREC_FP32) return PIFU_OK;
+  if (p == PIFU_PREC_BF16 || p == PIFU_PREC_FP8) return PIFU_ERR_UNSUPPORTED;
+  return PIFU_ERR_INVALID_ARGUMENT;
+}
+
+// ------------------------------------------------------------------ MLP preparation
+struct MlpPrep {
+  MLPDesc d;
+  void* Wp[PIFU_MAX_LAYERS];
+  int Kp[PIFU_MAX_LAYERS];
+  int max_hidden;
+};
+
+void describe_mlp(const pifu_mlp* m, MLPDesc& d) {
+  std::memset(&d, 0, sizeof(d));
+  d.n_layers = m->n_layers;
+  d.feat_dim = m->feat_dim;
+  d.n_extra = m->n_extra;
+  d.hidden_act = m->hidden_act;
+  d.out_act = m->out_act;
+  for (int l = 0; l < m->n_layers; ++l) {
+    d.widths[l] = m->widths[l];
+    d.skip[l] = l > 0 ? (m->skip[l] != 0) : 0;
+    d.in_w[l] = l == 0 ? m->feat_dim + m->n_extra
+                       : m->widths[l - 1] + (d.skip[l] ? m->feat_dim : 0);
+    d.W[l] = m->W[l];
+    d.b[l] = m->b[l];
+  }
+}
+
+// Carves (and, when launch is set, fills) the packed operand copies of the hidden layers.
+void carve_mlp(Carver& cv, const pifu_mlp* m, int precision, MlpPrep& p) {
+  describe_mlp(m, p.d);
+  p.max_hidden = 0;
+  const size_t esz = precision == PIFU_PREC_FP32 ? 4 : 2;
+  for (int l = 0; l + 1 < m->n_layers; ++l) {
+    p.Kp[l] = l == 0 ? m->feat_dim : p.d.in_w[l];
+    p.Wp[l] = cv.take<char>((size_t)m->widths[l] * p.Kp[l] * esz);
+    p.max_hidden = std::max(p.max_hidden, m->widths[l]);
+  }
+}
+
+void pack_mlp(const MlpPrep& p, int precision, hipStream_t s) {
+  for (int l = 0; l + 1 < p.d.n_layers; ++l)
+    launch_pack_weights(p.d.W[l], p.d.widths[l], p.d.in_w[l], p.Kp[l], p.Wp[l],
+                        precision != PIFU_PREC_FP32, s);
+}
+
+// ------------------------------------------------------------------ evaluator
+struct EvalWs {
+  uint32_t chunk = 0;
+  void* feat = nullptr;
+  float* ext = nullptr;
+  void* hA = nullptr;
+  void* hB = nullptr;
+  uint32_t* glist = nullptr;
+  uint32_t* iota = nullptr;
+};
+
+struct FieldPrep {
+  const pifu_field* f = nullptr;
+  MlpPrep mlp;
+  bool has_mlp = false;
+  Ellipsoids ell;
+};
+
+void carve_field(Carver& cv, const pifu_field* f, int precision, FieldPrep& fp) {
+  fp.f = f;
+  fp.has_mlp = f->kind == PIFU_FIELD_MLP;
+  std::memset(&fp.ell, 0, sizeof(fp.ell));
+  if (fp.has_mlp) {
+    carve_mlp(cv, f->mlp, precision, fp.mlp);
+  } else if (f->kind == PIFU_FIELD_ELLIPSOIDS) {
+    fp.ell.n = f->n_ell;
+    fp.ell.k = f->sharpness;
+    if (f->ell) std::memcpy(fp.ell.e, f->ell, sizeof(float) * 12 * f->n_ell);
+  }
+}
+
+void carve_eval(Carver& cv, uint32_t max_points, int C, int max_hidden, EvalWs& ew) {
+  ew.chunk = std::max<uint32_t>(128, std::min<uint32_t>(kDefaultChunk, (max_points + 127) / 128 * 128));
+  const size_t ch = ew.chunk;
+  ew.feat = cv.take<float>(ch * std::max(C, 1));
+  ew.ext = cv.take<float>(ch * 4);
+  ew.hA = cv.take<float>(ch * std::max(max_hidden, 1));
+  ew.hB = cv.take<float>(ch * std::max(max_hidden, 1));
+  ew.glist = cv.take<uint32_t>(std::max<uint32_t>(max_points, 1));
+}
+
+struct EvalCtx {
+  pifu_ctx* ctx;
+  hipStream_t s;
+  uint32_t* counters;     // device
+  int precision;
+  float guard;
+};
+
+int read_counters(EvalCtx& e, int nwords) {
+  HIP_TRY(hipMemcpyAsync(e.ctx->host_counters, e.counters, sizeof(uint32_t) * nwords,
+                         hipMemcpyDeviceToHost, e.s));
+  HIP_TRY(hipStreamSynchronize(e.s));
+  return PIFU_OK;
+}
+
+// Runs the MLP over n points (chunked): gather -> hidden GEMMs -> head.
+int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, const PointSrc& src,
+            const uint32_t* list, uint32_t n, const EvalWs& ew, float* logit, uint8_t* lab,
+            float* rgb, uint32_t* guard_count) {
+  const pifu_field* f = fp.f;
+  const MLPDesc& d = mp.d;
+  const int C = f->C;
+  for (uint32_t c0 = 0; c0 < n; c0 += ew.chunk) {
+    const uint32_t m = std::min(ew.chunk, n - c0);
+    const uint32_t* lst = list + c0;
+    launch_gather(src, lst, m, f->feat, f->H, f->W, C, ew.feat, 0, ew.ext, e.s);
+    const void* prev = nullptr;
+    void* out = ew.hA;
+    for (int l = 0; l + 1 < d.n_layers; ++l) {
+      GemmArgs g;
+      std::memset(&g, 0, sizeof(g));
+      if (l == 0) {
+        g.A1 = ew.feat;
+        g.K1 = C;
+        g.lda1 = C;
+        g.n_ext = d.n_extra;
+        g.ext_col = C;
+      } else {
+        g.A1 = prev;
+        g.K1 = d.widths[l - 1];
+        g.lda1 = d.widths[l - 1];
+        if (d.skip[l]) {
+          g.A2 = ew.feat;
+          g.K2 = C;
+          g.lda2 = C;
+        }
+      }
+      g.W = mp.Wp[l];
+      g.ldw = mp.Kp[l];
+      g.Wf = d.W[l];
+      g.ldwf = d.in_w[l];
+      g.bias = d.b[l];
+      g.ext = ew.ext;
+      g.C = out;
+      g.ldc = d.widths[l];
+      g.M = (int)m;
+      g.N = d.widths[l];
+      g.act = d.hidden_act;
+      g.scale = 1.f;
+      if (launch_gemm(g, e.precision, 0, e.s)) return PIFU_ERR_UNSUPPORTED;
+      prev = out;
+      out = (out == ew.hA) ? ew.hB : ew.hA;
+    }
+    const int L = d.n_layers - 1;
+    launch_head(reinterpret_cast<const float*>(prev), d.widths[L - 1], d.W[L], d.b[L], d.widths[L],
+                d.out_act, m, ew.ext, logit ? logit + c0 : nullptr, lab ? lab + c0 : nullptr, rgb,
+                rgb ? lst : nullptr, e.s);
+  }
+  int r = check_launch();
+  if (r) return r;
+  if (guard_count) *guard_count = 0;
+  if (logit && e.guard > 0.f && n) {
+    HIP_TRY(hipMemsetAsync(e.counters + C_GUARD, 0, 4, e.s));
+    launch_guard_select(logit, n, e.guard, ew.glist, e.counters + C_GUARD, e.s);
+    r = read_counters(e, C_GUARD + 1);
+    if (r) return r;
+    const uint32_t gn = e.ctx->host_counters[C_GUARD];
+    if (guard_count) *guard_count = gn;
+    launch_guard_fp64(src, list, ew.glist, gn, d, f->feat, f->H, f->W, C, logit, lab, e.s);
+    r = check_launch();
+  }
+  return r;
+}
+
+// Evaluates the occupancy field at n points; fills logit and label per point.
+int eval_occupancy(EvalCtx& e, const FieldPrep& fp, const PointSrc& src, const uint32_t* list,
+                   uint32_t n, const EvalWs& ew, float* logit, uint8_t* lab, pifu_level_stats* st) {
+  if (!n) return PIFU_OK;
+  if (!fp.has_mlp) {
+    launch_eval_analytic(src, list, n, fp.f->kind, fp.ell, fp.f->plane, logit, lab, e.s);
+    return check_launch();
+  }
+  uint32_t gn = 0;
+  int r = run_mlp(e, fp, fp.mlp, src, list, n, ew, logit, lab, nullptr, &gn);
+  if (st) {
+    st->mlp_points += n;
+    st->guard_fp64 += gn;
+  }
+  return r;
+}
+
+// ------------------------------------------------------------------ localization
+struct LevelBuf {
+  Lat lat;
+  uint8_t* st;
+  float* occ;
+  int level_id;
+};
+
+struct LocalizeWs {
+  uint32_t* list;
+  uint32_t* cscratch;
+  float* logit;
+  uint8_t* lab;
+};
+
+Lat level_lattice(const int log2_cells[3], int T, int t) {
+  Lat l;
+  l.nx = (1 << (log2_cells[0] - (T - t))) + 1;
+  l.ny = (1 << (log2_cells[1] - (T - t))) + 1;
+  l.nz = (1 << (log2_cells[2] - (T - t))) + 1;
+  return l;
+}
+
+int compact_count(EvalCtx& e, const uint8_t* st, size_t n, uint8_t mask, uint8_t val,
+                  uint32_t* scratch, uint32_t* out, uint32_t cap, int mode, Lat f, uint32_t* count) {
+  launch_compact(st, n, mask, val, scratch, e.counters + C_TOTAL, out, cap, mode, f, e.s);
+  int r = check_launch();
+  if (r) return r;
+  r = read_counters(e, 1);
+  if (r) return r;
+  *count = e.ctx->host_counters[C_TOTAL];
+  return PIFU_OK;
+}
+
+// Levels 0..last of the hierarchy (level T is the finest lattice of `fin_log2`).
+int localize(EvalCtx& e, const FieldPrep& fp, const EvalWs& ew, const double* view,
+             const int fin_log2[3], int T, int last, LevelBuf* lv, const LocalizeWs& w,
+             uint8_t* eval_level, Lat eval_lat, int max_waves, pifu_level_stats* stats) {
+  PointSrc src;
+  std::memset(&src, 0, sizeof(src));
+  src.mode = 0;
+  if (view) {
+    src.has_view = 1;
+    for (int i = 0; i < 12; ++i) src.view[i] = view[i];
+  }
+  for (int t = 0; t <= last; ++t) {
+    LevelBuf& L = lv[t];
+    pifu_level_stats st;
+    std::memset(&st, 0, sizeof(st));
+    st.level = L.level_id;
+    st.nodes = (uint32_t)L.lat.n();
+    src.nx = L.lat.nx;
+    src.ny = L.lat.ny;
+    src.nz = L.lat.nz;
+    const int stride = 1 << (last - t);
+    const uint32_t n_nodes = (uint32_t)L.lat.n();
+    HIP_TRY(hipMemsetAsync(e.counters, 0, sizeof(uint32_t) * kCounters, e.s));
+    if (t == 0) {
+      // coarsest level: every node is evaluated
+      launch_fill_u8(L.st, 0, n_nodes, e.s);
+      launch_iota(w.list, n_nodes, e.s);
+      int r = eval_occupancy(e, fp, src, w.list, n_nodes, ew, w.logit, w.lab, &st);
+      if (r) return r;
+      launch_apply_grid(w.list, n_nodes, w.logit, w.lab, L.st, L.occ, nullptr, eval_level,
+                        L.level_id, L.lat, stride, eval_lat, 0, e.s);
+      st.dilated = n_nodes;
+      st.evaluated = n_nodes;
+    } else {
+      LevelBuf& Cc = lv[t - 1];
+      launch_transition(Cc.st, Cc.occ, Cc.lat, L.st, L.occ, L.lat, e.s);
+      launch_count_bits(L.st, n_nodes, ST_B0, e.counters + C_B0, e.s);
+      launch_select(L.st, L.lat, e.s);
+      uint32_t n = 0;
+      int r = compact_count(e, L.st, n_nodes, ST_PEND, ST_PEND, w.cscratch, w.list, n_nodes, 0,
+                            L.lat, &n);
+      if (r) return r;
+      st.dilated = n;
+      int waves = 0;
+      while (n) {
+        r = eval_occupancy(e, fp, src, w.list, n, ew, w.logit, w.lab, &st);
+        if (r) return r;
+        launch_apply_grid(w.list, n, w.logit, w.lab, L.st, L.occ, e.counters + C_CONFLICTS,
+                          eval_level, L.level_id, L.lat, stride, eval_lat, 1, e.s);
+        st.evaluated += n;
+        if (max_waves > 0 && waves >= max_waves) break;
+        launch_expand(w.list, n, L.st, L.lat, e.s);
+        r = compact_count(e, L.st, n_nodes, ST_PEND, ST_PEND, w.cscratch, w.list, n_nodes, 0,
+                          L.lat, &n);
+        if (r) return r;
+        if (n) ++waves;
+      }
+      st.waves = (uint32_t)waves;
+    }
+    int r = check_launch();
+    if (r) return r;
+    r = read_counters(e, C_SHADOW + 1);
+    if (r) return r;
+    st.conflicts = e.ctx->host_counters[C_CONFLICTS];
+    st.b0 = e.ctx->host_counters[C_B0];
+    if (stats) stats[t] = st;
+  }
+  return PIFU_OK;
+}
+
+// ------------------------------------------------------------------ occupancy grid layout
+struct GridWs {
+  LevelBuf lv[11];
+  LocalizeWs w;
+  EvalWs ew;
+  FieldPrep fp;
+  uint32_t* counters;
+  int T;
+  int log2[3];
+  size_t bytes;
+};
+
+int plan_grid(const pifu_field* field, const pifu_grid_opts* o, void* base, float* occ_out,
+              GridWs& g) {
+  const int L = o->log2_final;
+  const int l0 = o->dense ? L : o->log2_coarse;
+  g.T = L - l0;
+  g.log2[0] = g.log2[1] = g.log2[2] = L;
+  Carver cv(base);
+  g.counters = cv.take<uint32_t>(kCounters);
+  size_t max_n = 0;
+  for (int t = 0; t <= g.T; ++t) {
+    LevelBuf& b = g.lv[t];
+    b.lat = level_lattice(g.log2, g.T, t);
+    b.level_id = L - (g.T - t);
+    b.st = cv.take<uint8_t>(b.lat.n() + 16);
+    b.occ = (t == g.T) ? occ_out : cv.take<float>(b.lat.n());
+    max_n = std::max(max_n, b.lat.n());
+  }
+  g.w.list = cv.take<uint32_t>(max_n);
+  g.w.cscratch = cv.take<uint32_t>(compact_scratch_words(max_n));
+  g.w.logit = cv.take<float>(max_n);
+  g.w.lab = cv.take<uint8_t>(max_n);
+  carve_field(cv, field, o->precision, g.fp);
+  const int C = field->kind == PIFU_FIELD_MLP ? field->C : 0;
+  const int mh = g.fp.has_mlp ? g.fp.mlp.max_hidden : 0;
+  carve_eval(cv, (uint32_t)max_n, C, mh, g.ew);
+  g.bytes = cv.off + kAlign;
+  return PIFU_OK;
+}
+
+int validate_grid_opts(const pifu_field* field, const pifu_grid_opts* o) {
+  if (!o) return PIFU_ERR_INVALID_ARGUMENT;
+  if (o->log2_final < 1 || o->log2_final > 9) return PIFU_ERR_INVALID_ARGUMENT;
+  if (!o->dense && (o->log2_coarse < 1 || o->log2_coarse > o->log2_final))
+    return PIFU_ERR_INVALID_ARGUMENT;
+  int r = validate_precision(o->precision);
+  if (r) return r;
+  return validate_field(field, 1, 1);
+}
+
+// ------------------------------------------------------------------ render layout
+struct RenderWs {
+  LevelBuf lv[11];
+  LocalizeWs w;
+  EvalWs ew;
+  FieldPrep fp, cp;
+  uint32_t* counters;
+  uint32_t *cnt, *kstar, *off, *scan_scratch, *hitlist;
+  float4* hitpts;
+  int T;
+  int log2[3];
+  size_t bytes;
+};
+
+int validate_render_opts(const pifu_field* occ, const pifu_field* col, const pifu_render_opts* o) {
+  if (!o) return PIFU_ERR_INVALID_ARGUMENT;
+  if (o->log2_w < 2 || o->log2_w > 10 || o->log2_d < 2 || o->log2_d > 10)
+    return PIFU_ERR_INVALID_ARGUMENT;
+  const int T = o->log2_w - o->log2_coarse_w;
+  if (T < 1 || o->log2_coarse_w < 1 || o->log2_d - T < 1) return PIFU_ERR_INVALID_ARGUMENT;
+  const double nodes = std::ldexp(1.0, o->log2_w) * std::ldexp(1.0, o->log2_w) *
+                       (std::ldexp(1.0, o->log2_d) + 1.0);
+  if (nodes >= 4294967295.0) return PIFU_ERR_INVALID_ARGUMENT;
+  int r = validate_precision(o->precision);
+  if (r) return r;
+  r = validate_field(occ, 1, 1);
+  if (r) return r;
+  if (!col || col->kind != PIFU_FIELD_MLP) return PIFU_ERR_INVALID_ARGUMENT;
+  return validate_field(col, 2, 3);
+}
+
+int plan_render(const pifu_field* occ, const pifu_field* col, const pifu_render_opts* o, void* base,
+                RenderWs& g) {
+  g.T = o->log2_w - o->log2_coarse_w;
+  g.log2[0] = g.log2[1] = o->log2_w;
+  g.log2[2] = o->log2_d;
+  Carver cv(base);
+  g.counters = cv.take<uint32_t>(kCounters);
+  size_t max_n = 0;
+  for (int t = 0; t < g.T; ++t) {
+    LevelBuf& b = g.lv[t];
+    b.lat = level_lattice(g.log2, g.T, t);
+    b.level_id = o->log2_w - (g.T - t);
+    b.st = cv.take<uint8_t>(b.lat.n() + 16);
+    b.occ = cv.take<float>(b.lat.n());
+    max_n = std::max(max_n, b.lat.n());
+  }
+  const size_t W = (size_t)1 << o->log2_w, D = (size_t)1 << o->log2_d;
+  const size_t ncol = W * W;
+  const size_t last_n = ncol * (D + 1);
+  max_n = std::max(max_n, last_n);
+  g.w.list = cv.take<uint32_t>(max_n);
+  g.w.cscratch = cv.take<uint32_t>(std::max(compact_scratch_words(max_n), scan_scratch_words(ncol)));
+  g.w.logit = cv.take<float>(max_n);
+  g.w.lab = cv.take<uint8_t>(max_n);
+  g.cnt = cv.take<uint32_t>(ncol);
+  g.kstar = cv.take<uint32_t>(ncol);
+  g.off = cv.take<uint32_t>(ncol);
+  g.scan_scratch = cv.take<uint32_t>(scan_scratch_words(ncol));
+  g.hitlist = cv.take<uint32_t>(ncol);
+  g.hitpts = cv.take<float4>(ncol);
+  carve_field(cv, occ, o->precision, g.fp);
+  carve_field(cv, col, PIFU_PREC_FP32, g.cp);
+  int C = 0, mh = 0;
+  if (g.fp.has_mlp) {
+    C = occ->C;
+    mh = g.fp.mlp.max_hidden;
+  }
+  C = std::max(C, col->C);
+  mh = std::max(mh, g.cp.mlp.max_hidden);
+  carve_eval(cv, (uint32_t)max_n, C, mh, g.ew);
+  g.bytes = cv.off + kAlign;
+  return PIFU_OK;
+}
+
+hipStream_t as_stream(pifu_stream s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace
+
+// ================================================================== C ABI
+extern "C" {
+
+int32_t pifu_create(pifu_ctx** out) {
+  if (!out) return PIFU_ERR_INVALID_ARGUMENT;
+  *out = nullptr;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return PIFU_ERR_HIP;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return PIFU_ERR_HIP;
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return PIFU_ERR_UNSUPPORTED;
+  pifu_ctx* c = new (std::nothrow) pifu_ctx;
+  if (!c) return PIFU_ERR_HIP;
+  c->device = dev;
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->host_counters), sizeof(uint32_t) * kCounters,
+                    hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return PIFU_ERR_HIP;
+  }
+  *out = c;
+  return PIFU_OK;
+}
+
+void pifu_destroy(pifu_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->host_counters) (void)hipHostFree(ctx->host_counters);
+  delete ctx;
+}
+
+const char* pifu_status_string(int32_t s) {
+  switch (s) {
+    case PIFU_OK: return "ok";
+    case PIFU_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case PIFU_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+    case PIFU_ERR_UNSUPPORTED: return "unsupported";
+    case PIFU_ERR_HIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+int32_t pifu_occupancy_grid_workspace_size(const pifu_field* field, const pifu_grid_opts* opts,
+                                           size_t* bytes) {
+  if (!bytes) return PIFU_ERR_INVALID_ARGUMENT;
+  int r = validate_grid_opts(field, opts);
+  if (r) return r;
+  GridWs* g = new (std::nothrow) GridWs;
+  if (!g) return PIFU_ERR_HIP;
+  plan_grid(field, opts, nullptr, nullptr, *g);
+  *bytes = g->bytes;
+  delete g;
+  return PIFU_OK;
+}
+
+int32_t pifu_occupancy_grid(pifu_ctx* ctx, const pifu_field* field, const pifu_grid_opts* opts,
+                            float* occ, uint8_t* labels, uint8_t* eval_level, uint32_t* cells,
+                            uint32_t cells_cap, uint32_t* n_cells, pifu_level_stats* stats,
+                            void* workspace, size_t workspace_bytes, pifu_stream stream) {
+  if (!ctx || !occ || !labels || !n_cells || !workspace) return PIFU_ERR_INVALID_ARGUMENT;
+  if (cells_cap && !cells) return PIFU_ERR_INVALID_ARGUMENT;
+  if (!aligned(workspace, kAlign)) return PIFU_ERR_INVALID_ARGUMENT;
+  int r = validate_grid_opts(field, opts);
+  if (r) return r;
+  GridWs* gp = new (std::nothrow) GridWs;
+  if (!gp) return PIFU_ERR_HIP;
+  GridWs& g = *gp;
+  plan_grid(field, opts, nullptr, nullptr, g);
+  if (workspace_bytes < g.bytes) {
+    delete gp;
+    return PIFU_ERR_WORKSPACE_TOO_SMALL;
+  }
+  void* base = reinterpret_cast<void*>((reinterpret_cast<uintptr_t>(workspace) + kAlign - 1) /
+                                       kAlign * kAlign);
+  plan_grid(field, opts, base, occ, g);
+  hipStream_t s = as_stream(stream);
+  EvalCtx e{ctx, s, g.counters, opts->precision, opts->guard_logit};
+  if (g.fp.has_mlp) pack_mlp(g.fp.mlp, opts->precision, s);
+  const Lat fin = g.lv[g.T].lat;
+  if (eval_level) launch_fill_u8(eval_level, 255, fin.n(), s);
+  r = localize(e, g.fp, g.ew, nullptr, g.log2, g.T, g.T, g.lv, g.w, eval_level, fin,
+               opts->max_waves, stats);
+  if (!r) {
+    launch_cells(g.lv[g.T].st, fin, labels, s);
+    uint32_t nc = 0;
+    r = compact_count(e, g.lv[g.T].st, fin.n(), ST_CELL, ST_CELL, g.w.cscratch, cells, cells_cap,
+                      1, fin, &nc);
+    *n_cells = nc;
+  }
+  delete gp;
+  return r;
+}
+
+int32_t pifu_render_view_workspace_size(const pifu_field* occ_field, const pifu_field* color_field,
+                                        const pifu_render_opts* opts, size_t* bytes) {
+  if (!bytes) return PIFU_ERR_INVALID_ARGUMENT;
+  int r = validate_render_opts(occ_field, color_field, opts);
+  if (r) return r;
+  RenderWs* g = new (std::nothrow) RenderWs;
+  if (!g) return PIFU_ERR_HIP;
+  plan_render(occ_field, color_field, opts, nullptr, *g);
+  *bytes = g->bytes;
+  delete g;
+  return PIFU_OK;
+}
+
+int32_t pifu_render_view(pifu_ctx* ctx, const pifu_field* occ_field, const pifu_field* color_field,
+                         const float* view, const pifu_render_opts* opts, const float* bg,
+                         float* rgb, float* depth, uint8_t* hit, pifu_level_stats* stats,
+                         void* workspace, size_t workspace_bytes, pifu_stream stream) {
+  if (!ctx || !view || !bg || !rgb || !depth || !hit || !workspace) return PIFU_ERR_INVALID_ARGUMENT;
+  if (!aligned(workspace, kAlign)) return PIFU_ERR_INVALID_ARGUMENT;
+  int r = validate_render_opts(occ_field, color_field, opts);
+  if (r) return r;
+  RenderWs* gp = new (std::nothrow) RenderWs;
+  if (!gp) return PIFU_ERR_HIP;
+  RenderWs& g = *gp;
+  plan_render(occ_field, color_field, opts, nullptr, g);
+  if (workspace_bytes < g.bytes) {
+    delete gp;
+    return PIFU_ERR_WORKSPACE_TOO_SMALL;
+  }
+  void* base = reinterpret_cast<void*>((reinterpret_cast<uintptr_t>(workspace) + kAlign - 1) /
+                                       kAlign * kAlign);
+  plan_render(occ_field, color_field, opts, base, g);
+  hipStream_t s = as_stream(stream);
+  EvalCtx e{ctx, s, g.counters, opts->precision, opts->guard_logit};
+  if (g.fp.has_mlp) pack_mlp(g.fp.mlp, opts->precision, s);
+  pack_mlp(g.cp.mlp, PIFU_PREC_FP32, s);
+  double vd[12];
+  for (int i = 0; i < 12; ++i) vd[i] = view[i];
+  const int T = g.T;
+  const int W = 1 << opts->log2_w, H = W, D = 1 << opts->log2_d;
+  const Lat finL = level_lattice(g.log2, T, T);
+  r = localize(e, g.fp, g.ew, vd, g.log2, T, T - 1, g.lv, g.w, nullptr, finL, opts->max_waves,
+               stats);
+  if (r) {
+    delete gp;
+    return r;
+  }
+  // last level: interpolate, argmax along z from the observer, shadow nodes
+  pifu_level_stats st;
+  std::memset(&st, 0, sizeof(st));
+  st.level = opts->log2_w;
+  st.nodes = (uint32_t)((size_t)W * H * (D + 1));
+  const LevelBuf& C = g.lv[T - 1];
+  HIP_TRY(hipMemsetAsync(g.counters, 0, sizeof(uint32_t) * kCounters, s));
+  launch_fill_image(rgb, depth, hit, (uint32_t)(W * H), bg[0], bg[1], bg[2], s);
+  launch_ray_count(C.st, C.lat, W, H, D, g.cnt, g.kstar, g.counters + C_SHADOW, s);
+  launch_scan_u32(g.cnt, (uint32_t)(W * H), g.off, g.scan_scratch, g.counters + C_TOTAL, s);
+  r = check_launch();
+  if (!r) r = read_counters(e, C_SHADOW + 1);
+  uint32_t nT = 0;
+  if (!r) {
+    nT = ctx->host_counters[C_TOTAL];
+    st.shadow = ctx->host_counters[C_SHADOW];
+    launch_ray_list(C.st, C.lat, W, H, D, g.kstar, g.off, g.w.list, s);
+    PointSrc src;
+    std::memset(&src, 0, sizeof(src));
+    src.mode = 0;
+    src.nx = finL.nx;
+    src.ny = finL.ny;
+    src.nz = finL.nz;
+    src.has_view = 1;
+    for (int i = 0; i < 12; ++i) src.view[i] = vd[i];
+    r = eval_occupancy(e, g.fp, src, g.w.list, nT, g.ew, g.w.logit, g.w.lab, &st);
+    st.dilated = nT;
+    st.evaluated = nT;
+  }
+  if (!r) {
+    launch_ray_hit(C.st, C.occ, C.lat, W, H, D, g.off, g.cnt, g.w.list, g.w.logit, g.w.lab, vd,
+                   depth, hit, g.hitpts, s);
+    uint32_t nh = 0;
+    Lat img{1, 1, W * H};
+    r = compact_count(e, hit, (size_t)W * H, 1, 1, g.w.cscratch, g.hitlist, (uint32_t)(W * H), 0,
+                      img, &nh);
+    st.hits = nh;
+    if (!r && nh) {
+      PointSrc ps;
+      std::memset(&ps, 0, sizeof(ps));
+      ps.mode = 1;
+      ps.pts = g.hitpts;
+      EvalCtx ec{ctx, s, g.counters, PIFU_PREC_FP32, 0.f};
+      r = run_mlp(ec, g.cp, g.cp.mlp, ps, g.hitlist, nh, g.ew, nullptr, nullptr, rgb, nullptr);
+    }
+  }
+  if (!r) r = check_launch();
+  if (!r) HIP_TRY(hipStreamSynchronize(s));
+  if (stats) stats[T] = st;
+  delete gp;
+  return r;
+}
+
+int32_t pifu_eval_points_workspace_size(const pifu_field* field, int32_t precision, uint32_t n,
+                                        size_t* bytes) {
+  if (!bytes || !field) return PIFU_ERR_INVALID_ARGUMENT;
+  int r = validate_precision(precision);
+  if (r) return r;
+  r = validate_field(field, 1, 1);
+  if (r) return r;
+  Carver cv(nullptr);
+  cv.take<uint32_t>(kCounters);
+  cv.take<uint32_t>(std::max<uint32_t>(n, 1));
+  FieldPrep fp;
+  carve_field(cv, field, precision, fp);
+  EvalWs ew;
+  carve_eval(cv, std::max<uint32_t>(n, 1), field->kind == PIFU_FIELD_MLP ? field->C : 0,
+             fp.has_mlp ? fp.mlp.max_hidden : 0, ew);
+  *bytes = cv.off + kAlign;
+  return PIFU_OK;
+}
+
+int32_t pifu_eval_points(pifu_ctx* ctx, const pifu_field* field, int32_t precision,
+                         float band_delta, float guard_logit, const float* pts, uint32_t n,
+                         float* logit, uint8_t* labels, void* workspace, size_t workspace_bytes,
+                         pifu_stream stream) {
+  (void)band_delta;
+  if (!ctx || !pts || !logit || !workspace) return PIFU_ERR_INVALID_ARGUMENT;
+  if (!aligned(pts, 16) || !aligned(workspace, kAlign)) return PIFU_ERR_INVALID_ARGUMENT;
+  size_t need = 0;
+  int r = pifu_eval_points_workspace_size(field, precision, n, &need);
+  if (r) return r;
+  if (workspace_bytes < need) return PIFU_ERR_WORKSPACE_TOO_SMALL;
+  if (!n) return PIFU_OK;
+  Carver cv(workspace);
+  uint32_t* counters = cv.take<uint32_t>(kCounters);
+  uint32_t* iota = cv.take<uint32_t>(n);
+  FieldPrep fp;
+  carve_field(cv, field, precision, fp);
+  EvalWs ew;
+  carve_eval(cv, n, field->kind == PIFU_FIELD_MLP ? field->C : 0,
+             fp.has_mlp ? fp.mlp.max_hidden : 0, ew);
+  hipStream_t s = as_stream(stream);
+  uint8_t* lab = labels;
+  if (!lab) lab = reinterpret_cast<uint8_t*>(ew.glist);   // scratch when labels are not wanted
+  EvalCtx e{ctx, s, counters, precision, guard_logit};
+  if (fp.has_mlp) pack_mlp(fp.mlp, precision, s);
+  launch_iota(iota, n, s);
+  PointSrc src;
+  std::memset(&src, 0, sizeof(src));
+  src.mode = 1;
+  src.pts = reinterpret_cast<const float4*>(pts);
+  if (!labels && fp.has_mlp && guard_logit > 0.f) return PIFU_ERR_INVALID_ARGUMENT;
+  r = eval_occupancy(e, fp, src, iota, n, ew, logit, lab, nullptr);
+  if (!r) r = check_launch();
+  if (!r) HIP_TRY(hipStreamSynchronize(s));
+  return r;
+}
+
+}  // extern "C"

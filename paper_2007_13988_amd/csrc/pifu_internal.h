@@ -1,0 +1,144 @@
+// Internal declarations shared by the libpifu translation units (kernels, GEMM, host).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/pifu.h"
+
+namespace pifu {
+
+// Per-node state byte of a level lattice.
+enum : uint8_t {
+  ST_LABEL = 0x01,  // current binary label
+  ST_EVAL = 0x02,   // evaluated by the network at this or a coarser level
+  ST_B0 = 0x04,     // boundary candidate: interpolated value strictly between 0 and 1
+  ST_HI = 0x08,     // interpolated value > 1/2 (the value the conflict test compares with)
+  ST_PEND = 0x10,   // selected for evaluation, not evaluated yet
+  ST_NOW = 0x20,    // evaluated at this level
+  ST_CONF = 0x40,   // conflict: network label differs from the binarized interpolation
+  ST_CELL = 0x80,   // final level: the cell with this node as lowest corner is mixed
+};
+
+struct Lat {
+  int nx, ny, nz;
+  __host__ __device__ size_t n() const { return (size_t)nx * ny * nz; }
+};
+
+// Where the points of an evaluation come from.
+//   mode 0: lattice nodes; point m is node list[m] of lattice (nx, ny, nz),
+//           optionally mapped by the 3x4 view (target NDC -> input NDC).
+//   mode 1: explicit points pts[list ? list[m] : m] (x, y, z, occ), input NDC.
+struct PointSrc {
+  int mode;
+  int nx, ny, nz;
+  int has_view;
+  double view[12];
+  const float4* pts;
+};
+
+struct MLPDesc {
+  int n_layers, feat_dim, n_extra, hidden_act, out_act;
+  int widths[PIFU_MAX_LAYERS];
+  int skip[PIFU_MAX_LAYERS];
+  int in_w[PIFU_MAX_LAYERS];
+  const float* W[PIFU_MAX_LAYERS];
+  const float* b[PIFU_MAX_LAYERS];
+};
+
+struct Ellipsoids {
+  int n;
+  float k;
+  float e[PIFU_MAX_ELLIPSOIDS * 12];
+};
+
+// float32 -> bfloat16 bits, round to nearest even (NaN stays a quiet NaN).
+__host__ __device__ inline uint16_t f32_to_bf16_bits(float x) {
+  uint32_t u;
+  __builtin_memcpy(&u, &x, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+constexpr int COMPACT_BLOCK = 256;
+constexpr int COMPACT_PER_THREAD = 16;
+constexpr int COMPACT_TILE = COMPACT_BLOCK * COMPACT_PER_THREAD;
+
+// ------------------------------------------------------------------ level kernels
+void launch_fill_u8(uint8_t* p, uint8_t v, size_t n, hipStream_t s);
+void launch_iota(uint32_t* list, uint32_t n, hipStream_t s);
+void launch_transition(const uint8_t* cst, const float* cocc, Lat c, uint8_t* fst, float* focc,
+                       Lat f, hipStream_t s);
+void launch_select(uint8_t* st, Lat f, hipStream_t s);
+// Stable compaction of the nodes whose state byte satisfies (st & mask) == val.
+// mode 0 writes node indices, mode 1 cell indices (i*(nx-1)+j)*(nz... of lattice f).
+void launch_compact(const uint8_t* st, size_t n, uint8_t mask, uint8_t val, uint32_t* bcount,
+                    uint32_t* total, uint32_t* out, uint32_t cap, int mode, Lat f, hipStream_t s);
+size_t compact_scratch_words(size_t n);
+void launch_apply_grid(const uint32_t* list, uint32_t n, const float* logit, const uint8_t* lab,
+                       uint8_t* st, float* occ, uint32_t* conflicts, uint8_t* eval_level,
+                       int level_id, Lat lvl, int stride, Lat fin, int check_conflict,
+                       hipStream_t s);
+void launch_expand(const uint32_t* list, uint32_t n, uint8_t* st, Lat f, hipStream_t s);
+void launch_cells(uint8_t* st, Lat f, uint8_t* labels, hipStream_t s);
+void launch_count_bits(const uint8_t* st, size_t n, uint8_t bit, uint32_t* out, hipStream_t s);
+
+// ------------------------------------------------------------------ evaluation kernels
+void launch_eval_analytic(const PointSrc& src, const uint32_t* list, uint32_t n, int kind,
+                          const Ellipsoids& ell, const float plane[4], float* logit,
+                          uint8_t* lab, hipStream_t s);
+// Bilinear gather of C channels (Eq. 1's sampler) for points m in [0, n); writes
+// feat (n x C, fp32 or bf16) and ext (n x 4: z', occ, clipped, 0).
+void launch_gather(const PointSrc& src, const uint32_t* list, uint32_t n, const float* F, int H,
+                   int W, int C, void* feat, int feat_bf16, float* ext, hipStream_t s);
+void launch_head(const float* h, int K, const float* W, const float* b, int n_out, int out_act,
+                 uint32_t n, const float* ext, float* logit, uint8_t* lab, float* rgb_out,
+                 const uint32_t* rgb_index, hipStream_t s);
+void launch_guard_select(const float* logit, uint32_t n, float g, uint32_t* glist,
+                         uint32_t* gcount, hipStream_t s);
+void launch_guard_fp64(const PointSrc& src, const uint32_t* list, const uint32_t* glist,
+                       uint32_t gn, const MLPDesc& mlp, const float* F, int H, int W, int C,
+                       float* logit, uint8_t* lab, hipStream_t s);
+
+// ------------------------------------------------------------------ render kernels
+void launch_ray_count(const uint8_t* stc, Lat c, int W, int H, int D, uint32_t* cnt,
+                      uint32_t* kstar, uint32_t* shadow_total, hipStream_t s);
+void launch_scan_u32(const uint32_t* in, uint32_t n, uint32_t* out_excl, uint32_t* scratch,
+                     uint32_t* total, hipStream_t s);
+size_t scan_scratch_words(size_t n);
+void launch_ray_list(const uint8_t* stc, Lat c, int W, int H, int D, const uint32_t* kstar,
+                     const uint32_t* off, uint32_t* list, hipStream_t s);
+void launch_ray_hit(const uint8_t* stc, const float* occc, Lat c, int W, int H, int D,
+                    const uint32_t* off, const uint32_t* cnt, const uint32_t* list,
+                    const float* logit, const uint8_t* lab, const double* view, float* depth,
+                    uint8_t* hit, float4* hitpts, hipStream_t s);
+void launch_fill_image(float* rgb, float* depth, uint8_t* hit, uint32_t npix, float bg0, float bg1,
+                       float bg2, hipStream_t s);
+
+// ------------------------------------------------------------------ GEMM (MFMA)
+// C[m][n] = act(sum_k A[m][k] W[n][k] + b[n] + sum_e ext[m][e] W[n][ext_col + e]) for m < M,
+// A = [A1 (K1 columns, ld lda1) ; A2 (K2 columns, ld lda2)].  precision selects the MFMA
+// operand type; for BF16/FP8 A1, A2 and C are bf16 and W is the pre-converted copy.
+struct GemmArgs {
+  const void* A1;
+  int K1, lda1;
+  const void* A2;
+  int K2, lda2;
+  const void* W;     // [N][ldw] operand copy (fp32 or bf16 / fp8)
+  int ldw;
+  const float* Wf;   // fp32 original (for the extras columns)
+  int ldwf;
+  const float* bias;
+  const float* ext;  // M x 4
+  int n_ext, ext_col;
+  void* C;
+  int ldc;
+  int M, N;
+  int act;
+  float scale;       // FP8: product of operand scales (dequantization), else 1
+};
+int launch_gemm(const GemmArgs& a, int precision, int tile_m, hipStream_t s);
+void launch_pack_weights(const float* W, int N, int ldw_src, int K, void* dst, int bf16,
+                         hipStream_t s);
+
+}  // namespace pifu

@@ -1,0 +1,424 @@
+// Level kernels of hierarchical surface localization (Sec. 3.2): level transition
+// (binarize + trilinear x2), 1-ring dilation, stable stream compaction, conflict
+// expansion, surface-cell extraction.  All are HBM/L2-bound byte-state passes.
+#include "pifu_internal.h"
+
+namespace pifu {
+
+static inline unsigned grid1d(size_t n, int block) { return (unsigned)((n + block - 1) / block); }
+
+__global__ void k_fill_u8(uint8_t* __restrict__ p, uint8_t v, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+void launch_fill_u8(uint8_t* p, uint8_t v, size_t n, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_fill_u8, dim3(grid1d(n, 256)), dim3(256), 0, s, p, v, n);
+}
+
+__global__ void k_iota(uint32_t* __restrict__ list, uint32_t n) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) list[i] = i;
+}
+
+void launch_iota(uint32_t* list, uint32_t n, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_iota, dim3(grid1d(n, 256)), dim3(256), 0, s, list, n);
+}
+
+// Level transition.  Coarse level nodes keep their label, evaluated flag and value;
+// every other fine node gets the mean of the binarized labels of its 2/4/8 enclosing
+// coarse corners (trilinear interpolation of the binary field).  Fractional means are
+// boundary candidates (ST_B0); integral ones are the culled value.
+__global__ void k_transition(const uint8_t* __restrict__ cst, const float* __restrict__ cocc,
+                             Lat c, uint8_t* __restrict__ fst, float* __restrict__ focc, Lat f) {
+  size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= f.n()) return;
+  const uint32_t nyz = (uint32_t)f.ny * f.nz;
+  const uint32_t a = (uint32_t)(n / nyz);
+  const uint32_t r = (uint32_t)(n - (size_t)a * nyz);
+  const uint32_t b = r / f.nz;
+  const uint32_t k = r - b * f.nz;
+  const uint32_t a0 = a >> 1, a1 = (a + 1) >> 1;
+  const uint32_t b0 = b >> 1, b1 = (b + 1) >> 1;
+  const uint32_t k0 = k >> 1, k1 = (k + 1) >> 1;
+  const uint32_t cyz = (uint32_t)c.ny * c.nz;
+  if (!((a | b | k) & 1)) {
+    size_t cn = (size_t)a0 * cyz + (size_t)b0 * c.nz + k0;
+    uint8_t s = cst[cn] & (ST_LABEL | ST_EVAL);
+    fst[n] = s | ((s & ST_LABEL) ? ST_HI : 0);
+    focc[n] = cocc[cn];
+    return;
+  }
+  int sum = 0, cnt = 0;
+  for (int da = 0; da < 2; ++da) {
+    uint32_t ia = da ? a1 : a0;
+    if (da && a1 == a0) continue;
+    for (int db = 0; db < 2; ++db) {
+      uint32_t ib = db ? b1 : b0;
+      if (db && b1 == b0) continue;
+      const uint8_t* row = cst + (size_t)ia * cyz + (size_t)ib * c.nz;
+      sum += row[k0] & ST_LABEL;
+      ++cnt;
+      if (k1 != k0) {
+        sum += row[k1] & ST_LABEL;
+        ++cnt;
+      }
+    }
+  }
+  uint8_t s;
+  float v;
+  if (sum == 0) {
+    s = 0;
+    v = 0.f;
+  } else if (sum == cnt) {
+    s = ST_LABEL | ST_HI;
+    v = 1.f;
+  } else {
+    const bool hi = 2 * sum > cnt;
+    s = ST_B0 | (hi ? (ST_HI | ST_LABEL) : 0);
+    v = (float)sum / (float)cnt;
+  }
+  fst[n] = s;
+  focc[n] = v;
+}
+
+void launch_transition(const uint8_t* cst, const float* cocc, Lat c, uint8_t* fst, float* focc,
+                       Lat f, hipStream_t s) {
+  hipLaunchKernelGGL(k_transition, dim3(grid1d(f.n(), 256)), dim3(256), 0, s, cst, cocc, c, fst,
+                     focc, f);
+}
+
+// 1-ring dilation of the boundary candidates: a node not evaluated before is selected
+// when any node of its 3x3x3 neighbourhood (clipped at the grid edge) is a candidate.
+__global__ void k_select(uint8_t* __restrict__ st, Lat f) {
+  size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= f.n()) return;
+  uint8_t s = st[n];
+  if (s & ST_EVAL) return;
+  const uint32_t nyz = (uint32_t)f.ny * f.nz;
+  const int a = (int)(n / nyz);
+  const int r = (int)(n - (size_t)a * nyz);
+  const int b = r / f.nz;
+  const int k = r - b * f.nz;
+  bool any = false;
+  for (int da = -1; da <= 1 && !any; ++da) {
+    int ia = a + da;
+    if (ia < 0 || ia >= f.nx) continue;
+    for (int db = -1; db <= 1 && !any; ++db) {
+      int ib = b + db;
+      if (ib < 0 || ib >= f.ny) continue;
+      const uint8_t* row = st + (size_t)ia * nyz + (size_t)ib * f.nz;
+      for (int dk = -1; dk <= 1; ++dk) {
+        int ik = k + dk;
+        if (ik < 0 || ik >= f.nz) continue;
+        if (row[ik] & ST_B0) {
+          any = true;
+          break;
+        }
+      }
+    }
+  }
+  if (any) st[n] = s | ST_PEND;
+}
+
+void launch_select(uint8_t* st, Lat f, hipStream_t s) {
+  hipLaunchKernelGGL(k_select, dim3(grid1d(f.n(), 256)), dim3(256), 0, s, st, f);
+}
+
+// ------------------------------------------------------------------ compaction
+// Three passes: per-tile counts, exclusive scan of the tile counts, ordered write.
+// Thread t of tile b owns nodes [b*4096 + 16t, +16), so output order is node order.
+
+__device__ inline uint32_t pred_mask16(const uint8_t* __restrict__ st, size_t base, size_t n,
+                                       uint8_t mask, uint8_t val) {
+  uint32_t m = 0;
+  if (base + 16 <= n) {
+    uint4 q = *reinterpret_cast<const uint4*>(st + base);
+    uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      uint8_t s = (uint8_t)(w[i >> 2] >> (8 * (i & 3)));
+      m |= (uint32_t)((s & mask) == val) << i;
+    }
+  } else {
+    for (int i = 0; i < 16; ++i)
+      if (base + i < n) m |= (uint32_t)((st[base + i] & mask) == val) << i;
+  }
+  return m;
+}
+
+__device__ inline uint32_t wave_incl_scan(uint32_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t t = __shfl_up(v, d, 64);
+    if (lane >= d) v += t;
+  }
+  return v;
+}
+
+__global__ void __launch_bounds__(COMPACT_BLOCK)
+k_compact_count(const uint8_t* __restrict__ st, size_t n, uint8_t mask, uint8_t val,
+                uint32_t* __restrict__ bcount) {
+  __shared__ uint32_t wsum[COMPACT_BLOCK / 64];
+  size_t base = (size_t)blockIdx.x * COMPACT_TILE + (size_t)threadIdx.x * COMPACT_PER_THREAD;
+  uint32_t c = __popc(pred_mask16(st, base, n, mask, val));
+  uint32_t inc = wave_incl_scan(c);
+  if ((threadIdx.x & 63) == 63) wsum[threadIdx.x >> 6] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int w = 0; w < COMPACT_BLOCK / 64; ++w) t += wsum[w];
+    bcount[blockIdx.x] = t;
+  }
+}
+
+// Exclusive scan of n words by one workgroup of 1024 threads; writes the total.
+__global__ void __launch_bounds__(1024)
+k_scan_small(const uint32_t* __restrict__ in, uint32_t n, uint32_t* __restrict__ out,
+             uint32_t* __restrict__ total) {
+  __shared__ uint32_t wsum[16];
+  const uint32_t per = (n + 1023) / 1024;
+  const uint32_t beg = threadIdx.x * per;
+  uint32_t loc = 0;
+  for (uint32_t i = 0; i < per; ++i)
+    if (beg + i < n) loc += in[beg + i];
+  uint32_t inc = wave_incl_scan(loc);
+  if ((threadIdx.x & 63) == 63) wsum[threadIdx.x >> 6] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int w = 0; w < 16; ++w) {
+      uint32_t t = wsum[w];
+      wsum[w] = run;
+      run += t;
+    }
+    if (total) *total = run;
+  }
+  __syncthreads();
+  uint32_t run = wsum[threadIdx.x >> 6] + inc - loc;
+  for (uint32_t i = 0; i < per; ++i)
+    if (beg + i < n) {
+      uint32_t v = in[beg + i];
+      out[beg + i] = run;
+      run += v;
+    }
+}
+
+__global__ void __launch_bounds__(COMPACT_BLOCK)
+k_compact_write(const uint8_t* __restrict__ st, size_t n, uint8_t mask, uint8_t val,
+                const uint32_t* __restrict__ boff, uint32_t* __restrict__ out, uint32_t cap,
+                int mode, Lat f) {
+  __shared__ uint32_t wsum[COMPACT_BLOCK / 64];
+  size_t base = (size_t)blockIdx.x * COMPACT_TILE + (size_t)threadIdx.x * COMPACT_PER_THREAD;
+  uint32_t m = pred_mask16(st, base, n, mask, val);
+  uint32_t c = __popc(m);
+  uint32_t inc = wave_incl_scan(c);
+  if ((threadIdx.x & 63) == 63) wsum[threadIdx.x >> 6] = inc;
+  __syncthreads();
+  uint32_t woff = 0;
+  for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) woff += wsum[w];
+  uint32_t pos = boff[blockIdx.x] + woff + inc - c;
+  const uint32_t nyz = (uint32_t)f.ny * f.nz;
+  while (m) {
+    int i = __ffs(m) - 1;
+    m &= m - 1;
+    if (pos < cap) {
+      size_t node = base + i;
+      uint32_t v = (uint32_t)node;
+      if (mode == 1) {
+        uint32_t a = (uint32_t)(node / nyz);
+        uint32_t r = (uint32_t)(node - (size_t)a * nyz);
+        uint32_t b = r / f.nz;
+        uint32_t k = r - b * f.nz;
+        v = (a * (uint32_t)(f.ny - 1) + b) * (uint32_t)(f.nz - 1) + k;
+      }
+      out[pos] = v;
+    }
+    ++pos;
+  }
+}
+
+size_t compact_scratch_words(size_t n) { return (n + COMPACT_TILE - 1) / COMPACT_TILE * 2 + 64; }
+
+void launch_compact(const uint8_t* st, size_t n, uint8_t mask, uint8_t val, uint32_t* bcount,
+                    uint32_t* total, uint32_t* out, uint32_t cap, int mode, Lat f, hipStream_t s) {
+  uint32_t nb = (uint32_t)((n + COMPACT_TILE - 1) / COMPACT_TILE);
+  if (nb == 0) {
+    (void)hipMemsetAsync(total, 0, 4, s);
+    return;
+  }
+  uint32_t* boff = bcount + nb;
+  hipLaunchKernelGGL(k_compact_count, dim3(nb), dim3(COMPACT_BLOCK), 0, s, st, n, mask, val, bcount);
+  hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, bcount, nb, boff, total);
+  hipLaunchKernelGGL(k_compact_write, dim3(nb), dim3(COMPACT_BLOCK), 0, s, st, n, mask, val, boff,
+                     out, cap, mode, f);
+}
+
+// ------------------------------------------------------------------ generic scan (render)
+__global__ void __launch_bounds__(1024)
+k_scan_tiles(const uint32_t* __restrict__ in, uint32_t n, uint32_t* __restrict__ tsum) {
+  __shared__ uint32_t wsum[16];
+  uint32_t i = blockIdx.x * 1024 + threadIdx.x;
+  uint32_t v = i < n ? in[i] : 0;
+  uint32_t inc = wave_incl_scan(v);
+  if ((threadIdx.x & 63) == 63) wsum[threadIdx.x >> 6] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int w = 0; w < 16; ++w) t += wsum[w];
+    tsum[blockIdx.x] = t;
+  }
+}
+
+__global__ void __launch_bounds__(1024)
+k_scan_apply(const uint32_t* __restrict__ in, uint32_t n, const uint32_t* __restrict__ toff,
+             uint32_t* __restrict__ out) {
+  __shared__ uint32_t wsum[16];
+  uint32_t i = blockIdx.x * 1024 + threadIdx.x;
+  uint32_t v = i < n ? in[i] : 0;
+  uint32_t inc = wave_incl_scan(v);
+  if ((threadIdx.x & 63) == 63) wsum[threadIdx.x >> 6] = inc;
+  __syncthreads();
+  uint32_t woff = 0;
+  for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) woff += wsum[w];
+  if (i < n) out[i] = toff[blockIdx.x] + woff + inc - v;
+}
+
+size_t scan_scratch_words(size_t n) { return (n + 1023) / 1024 * 2 + 64; }
+
+void launch_scan_u32(const uint32_t* in, uint32_t n, uint32_t* out_excl, uint32_t* scratch,
+                     uint32_t* total, hipStream_t s) {
+  uint32_t nt = (n + 1023) / 1024;
+  if (nt == 0) {
+    (void)hipMemsetAsync(total, 0, 4, s);
+    return;
+  }
+  hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(1024), 0, s, in, n, scratch);
+  hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, scratch, nt, scratch + nt, total);
+  hipLaunchKernelGGL(k_scan_apply, dim3(nt), dim3(1024), 0, s, in, n, scratch + nt, out_excl);
+}
+
+// ------------------------------------------------------------------ evaluation results
+// Writes the network's label and value into the level state; flags conflicts
+// ([logit > 0] != [interp > 1/2]) among the nodes evaluated at this level.
+__global__ void k_apply_grid(const uint32_t* __restrict__ list, uint32_t n,
+                             const float* __restrict__ logit, const uint8_t* __restrict__ lab,
+                             uint8_t* __restrict__ st, float* __restrict__ occ,
+                             uint32_t* __restrict__ conflicts, uint8_t* __restrict__ eval_level,
+                             int level_id, Lat lvl, int stride, Lat fin, int check_conflict) {
+  uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
+  bool conf = false;
+  if (m < n) {
+    const uint32_t node = list[m];
+    const uint8_t s = st[node];
+    const uint8_t l = lab[m] ? ST_LABEL : 0;
+    const float x = logit[m];
+    const float p = 1.0f / (1.0f + expf(-x));
+    uint8_t ns = (uint8_t)((s & ~(ST_LABEL | ST_PEND | ST_CONF)) | ST_EVAL | ST_NOW | l);
+    if (check_conflict && ((l != 0) != ((s & ST_HI) != 0))) {
+      ns |= ST_CONF;
+      conf = true;
+    }
+    st[node] = ns;
+    occ[node] = p;
+    if (eval_level) {
+      const uint32_t nyz = (uint32_t)lvl.ny * lvl.nz;
+      uint32_t a = node / nyz;
+      uint32_t r = node - a * nyz;
+      uint32_t b = r / lvl.nz;
+      uint32_t k = r - b * lvl.nz;
+      size_t fn = ((size_t)(a * stride) * fin.ny + (size_t)(b * stride)) * fin.nz + (size_t)k * stride;
+      eval_level[fn] = (uint8_t)level_id;
+    }
+  }
+  if (conflicts) {
+    unsigned long long bal = __ballot(conf);
+    if ((threadIdx.x & 63) == 0 && bal) atomicAdd(conflicts, (uint32_t)__popcll(bal));
+  }
+}
+
+void launch_apply_grid(const uint32_t* list, uint32_t n, const float* logit, const uint8_t* lab,
+                       uint8_t* st, float* occ, uint32_t* conflicts, uint8_t* eval_level,
+                       int level_id, Lat lvl, int stride, Lat fin, int check_conflict,
+                       hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_apply_grid, dim3(grid1d(n, 256)), dim3(256), 0, s, list, n, logit, lab, st,
+                     occ, conflicts, eval_level, level_id, lvl, stride, fin, check_conflict);
+}
+
+// Conflict expansion: every not-yet-evaluated node of the 26-neighbourhood of a
+// conflict node of the last wave is selected.  Concurrent read-modify-writes of one
+// byte only ever add ST_PEND, so they agree.
+__global__ void k_expand(const uint32_t* __restrict__ list, uint32_t n, uint8_t* __restrict__ st,
+                         Lat f) {
+  uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n) return;
+  const uint32_t node = list[m];
+  if (!(st[node] & ST_CONF)) return;
+  const uint32_t nyz = (uint32_t)f.ny * f.nz;
+  const int a = (int)(node / nyz);
+  const int r = (int)(node - (uint32_t)a * nyz);
+  const int b = r / f.nz;
+  const int k = r - b * f.nz;
+  for (int da = -1; da <= 1; ++da) {
+    int ia = a + da;
+    if (ia < 0 || ia >= f.nx) continue;
+    for (int db = -1; db <= 1; ++db) {
+      int ib = b + db;
+      if (ib < 0 || ib >= f.ny) continue;
+      uint8_t* row = st + (size_t)ia * nyz + (size_t)ib * f.nz;
+      for (int dk = -1; dk <= 1; ++dk) {
+        int ik = k + dk;
+        if (ik < 0 || ik >= f.nz) continue;
+        uint8_t s = row[ik];
+        if (!(s & (ST_EVAL | ST_PEND))) row[ik] = s | ST_PEND;
+      }
+    }
+  }
+}
+
+void launch_expand(const uint32_t* list, uint32_t n, uint8_t* st, Lat f, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_expand, dim3(grid1d(n, 256)), dim3(256), 0, s, list, n, st, f);
+}
+
+// Final level: export the 0/1 labels and flag mixed cells (8 corner labels differ).
+__global__ void k_cells(uint8_t* __restrict__ st, Lat f, uint8_t* __restrict__ labels) {
+  size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= f.n()) return;
+  const uint8_t s = st[n];
+  const uint8_t l = s & ST_LABEL;
+  labels[n] = l;
+  const uint32_t nyz = (uint32_t)f.ny * f.nz;
+  const uint32_t a = (uint32_t)(n / nyz);
+  const uint32_t r = (uint32_t)(n - (size_t)a * nyz);
+  const uint32_t b = r / f.nz;
+  const uint32_t k = r - b * f.nz;
+  if (a + 1 >= (uint32_t)f.nx || b + 1 >= (uint32_t)f.ny || k + 1 >= (uint32_t)f.nz) return;
+  int sum = 0;
+  for (int da = 0; da < 2; ++da)
+    for (int db = 0; db < 2; ++db) {
+      const uint8_t* row = st + (size_t)(a + da) * nyz + (size_t)(b + db) * f.nz + k;
+      sum += (row[0] & ST_LABEL) + (row[1] & ST_LABEL);
+    }
+  if (sum != 0 && sum != 8) st[n] = s | ST_CELL;
+}
+
+void launch_cells(uint8_t* st, Lat f, uint8_t* labels, hipStream_t s) {
+  hipLaunchKernelGGL(k_cells, dim3(grid1d(f.n(), 256)), dim3(256), 0, s, st, f, labels);
+}
+
+__global__ void k_count_bits(const uint8_t* __restrict__ st, size_t n, uint8_t bit,
+                             uint32_t* __restrict__ out) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool v = i < n && (st[i] & bit);
+  unsigned long long bal = __ballot(v);
+  if ((threadIdx.x & 63) == 0 && bal) atomicAdd(out, (uint32_t)__popcll(bal));
+}
+
+void launch_count_bits(const uint8_t* st, size_t n, uint8_t bit, uint32_t* out, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_count_bits, dim3(grid1d(n, 256)), dim3(256), 0, s, st, n, bit, out);
+}
+
+}  // namespace pifu

@@ -1,0 +1,351 @@
+"""ctypes binding of libpifu (include/pifu.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP kernels of
+libpifu.so.  PyTorch provides device memory (outputs, workspace, weights) and the
+current stream.  There is no CPU fallback: without the built library every call
+raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpifu.so")
+INCLUDE = os.path.join(os.path.dirname(_HERE), "include", "pifu.h")
+
+MAX_LAYERS = 8
+FIELD_MLP, FIELD_ELLIPSOIDS, FIELD_PLANE = 0, 1, 2
+ACT = {"relu": 1, "lrelu": 2, "sigmoid": 3, "tanh": 4}
+PREC = {"fp32": 0, "bf16": 1, "fp8": 2}
+STATUS = {0: "ok", -1: "invalid argument", -2: "workspace too small", -3: "unsupported",
+          -4: "HIP runtime error"}
+
+
+class PifuMLP(C.Structure):
+    _fields_ = [("n_layers", C.c_int32), ("feat_dim", C.c_int32), ("n_extra", C.c_int32),
+                ("hidden_act", C.c_int32), ("out_act", C.c_int32),
+                ("widths", C.c_int32 * MAX_LAYERS), ("skip", C.c_int32 * MAX_LAYERS),
+                ("W", C.c_void_p * MAX_LAYERS), ("b", C.c_void_p * MAX_LAYERS),
+                ("fp8_amax", C.c_float * MAX_LAYERS)]
+
+
+class PifuField(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("H", C.c_int32), ("W", C.c_int32), ("C", C.c_int32),
+                ("feat", C.c_void_p), ("mlp", C.POINTER(PifuMLP)),
+                ("surrogate", C.POINTER(PifuMLP)), ("n_ell", C.c_int32),
+                ("sharpness", C.c_float), ("ell", C.c_void_p), ("plane", C.c_float * 4)]
+
+
+class PifuLevelStats(C.Structure):
+    _fields_ = [("level", C.c_int32), ("nodes", C.c_uint32), ("b0", C.c_uint32),
+                ("dilated", C.c_uint32), ("evaluated", C.c_uint32), ("waves", C.c_uint32),
+                ("conflicts", C.c_uint32), ("mlp_points", C.c_uint32), ("band_fp32", C.c_uint32),
+                ("guard_fp64", C.c_uint32), ("surrogate_fallback", C.c_uint32),
+                ("shadow", C.c_uint32), ("hits", C.c_uint32), ("reserved", C.c_uint32 * 3)]
+
+    def as_dict(self) -> Dict[str, int]:
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class PifuGridOpts(C.Structure):
+    _fields_ = [("log2_final", C.c_int32), ("log2_coarse", C.c_int32), ("dense", C.c_int32),
+                ("precision", C.c_int32), ("band_delta", C.c_float), ("guard_logit", C.c_float),
+                ("surrogate_max_log2", C.c_int32), ("surrogate_delta", C.c_float),
+                ("tile_m", C.c_int32), ("max_waves", C.c_int32)]
+
+
+class PifuRenderOpts(C.Structure):
+    _fields_ = [("log2_w", C.c_int32), ("log2_d", C.c_int32), ("log2_coarse_w", C.c_int32),
+                ("precision", C.c_int32), ("band_delta", C.c_float), ("guard_logit", C.c_float),
+                ("surrogate_max_log2", C.c_int32), ("surrogate_delta", C.c_float),
+                ("tile_m", C.c_int32), ("max_waves", C.c_int32)]
+
+
+EXPORTS = ["pifu_create", "pifu_destroy", "pifu_status_string",
+           "pifu_occupancy_grid_workspace_size", "pifu_occupancy_grid",
+           "pifu_render_view_workspace_size", "pifu_render_view",
+           "pifu_eval_points_workspace_size", "pifu_eval_points"]
+
+_lib = None
+
+
+def load_library():
+    """Loads libpifu.so and declares the C signatures; raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    i32, u32, sz = C.c_int32, C.c_uint32, C.c_size_t
+    lib.pifu_create.argtypes = [C.POINTER(P)]
+    lib.pifu_destroy.argtypes = [P]
+    lib.pifu_destroy.restype = None
+    lib.pifu_status_string.argtypes = [i32]
+    lib.pifu_status_string.restype = C.c_char_p
+    lib.pifu_occupancy_grid_workspace_size.argtypes = [C.POINTER(PifuField),
+                                                       C.POINTER(PifuGridOpts), C.POINTER(sz)]
+    lib.pifu_occupancy_grid.argtypes = [P, C.POINTER(PifuField), C.POINTER(PifuGridOpts), P, P, P,
+                                        P, u32, C.POINTER(u32), C.POINTER(PifuLevelStats), P, sz, P]
+    lib.pifu_render_view_workspace_size.argtypes = [C.POINTER(PifuField), C.POINTER(PifuField),
+                                                    C.POINTER(PifuRenderOpts), C.POINTER(sz)]
+    lib.pifu_render_view.argtypes = [P, C.POINTER(PifuField), C.POINTER(PifuField),
+                                     C.POINTER(C.c_float), C.POINTER(PifuRenderOpts),
+                                     C.POINTER(C.c_float), P, P, P, C.POINTER(PifuLevelStats), P,
+                                     sz, P]
+    lib.pifu_eval_points_workspace_size.argtypes = [C.POINTER(PifuField), i32, u32, C.POINTER(sz)]
+    lib.pifu_eval_points.argtypes = [P, C.POINTER(PifuField), i32, C.c_float, C.c_float, P, u32, P,
+                                     P, P, sz, P]
+    for name in EXPORTS:
+        if name not in ("pifu_destroy", "pifu_status_string"):
+            getattr(lib, name).restype = i32
+    _lib = lib
+    return lib
+
+
+class PifuError(RuntimeError):
+    pass
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        raise PifuError(f"{what} failed: {STATUS.get(status, status)} ({status})")
+
+
+_ctx: Dict[int, C.c_void_p] = {}
+
+
+def context() -> C.c_void_p:
+    dev = torch.cuda.current_device()
+    if dev not in _ctx:
+        lib = load_library()
+        h = C.c_void_p()
+        _check(lib.pifu_create(C.byref(h)), "pifu_create")
+        _ctx[dev] = h
+    return _ctx[dev]
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream=None) -> C.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+# ------------------------------------------------------------------ device-side inputs
+
+class DeviceMLP:
+    """An MLP whose weights live on the GPU, described for the C ABI."""
+
+    def __init__(self, spec, device="cuda"):
+        self.spec = spec
+        self.W = [torch.as_tensor(np.ascontiguousarray(w, np.float32)).to(device) for w in spec.W]
+        self.b = [torch.as_tensor(np.ascontiguousarray(b, np.float32)).to(device) for b in spec.b]
+        s = PifuMLP()
+        s.n_layers = len(spec.widths)
+        s.feat_dim = spec.feat_dim
+        s.n_extra = spec.n_extra
+        s.hidden_act = ACT[spec.hidden_act]
+        s.out_act = ACT[spec.out_act]
+        for l, w in enumerate(spec.widths):
+            s.widths[l] = w
+            s.skip[l] = int(bool(spec.skip[l])) if l > 0 else 0
+            s.W[l] = self.W[l].data_ptr()
+            s.b[l] = self.b[l].data_ptr()
+        amax = getattr(spec, "fp8_amax", None)
+        if amax is not None:
+            for l, a in enumerate(amax):
+                s.fp8_amax[l] = float(a)
+        self.struct = s
+
+
+class DeviceField:
+    """An occupancy/colour field for the C ABI (MLP over a feature map, or analytic)."""
+
+    def __init__(self, kind: int, feat=None, mlp: Optional[DeviceMLP] = None,
+                 surrogate: Optional[DeviceMLP] = None, ell=None, sharpness: float = 8.0,
+                 plane=None, device="cuda"):
+        s = PifuField()
+        s.kind = kind
+        self._keep = []
+        if kind == FIELD_MLP:
+            ft = torch.as_tensor(np.ascontiguousarray(feat, np.float32)).to(device) \
+                if not isinstance(feat, torch.Tensor) else feat.contiguous()
+            self.feat = ft
+            s.H, s.W, s.C = ft.shape
+            s.feat = ft.data_ptr()
+            self.mlp = mlp
+            s.mlp = C.pointer(mlp.struct)
+            if surrogate is not None:
+                s.surrogate = C.pointer(surrogate.struct)
+            self.surrogate = surrogate
+        elif kind == FIELD_ELLIPSOIDS:
+            e = np.ascontiguousarray(ell, np.float32).reshape(-1, 12)
+            self._ell = e
+            s.n_ell = e.shape[0]
+            s.sharpness = sharpness
+            s.ell = e.ctypes.data
+        elif kind == FIELD_PLANE:
+            for i in range(4):
+                s.plane[i] = float(plane[i])
+        self.struct = s
+
+    @staticmethod
+    def mlp_field(feat, spec, surrogate_spec=None, device="cuda"):
+        sur = DeviceMLP(surrogate_spec, device) if surrogate_spec is not None else None
+        return DeviceField(FIELD_MLP, feat=feat, mlp=DeviceMLP(spec, device), surrogate=sur,
+                           device=device)
+
+    @staticmethod
+    def ellipsoids(ell, sharpness=8.0):
+        return DeviceField(FIELD_ELLIPSOIDS, ell=ell, sharpness=sharpness)
+
+    @staticmethod
+    def plane_field(coef):
+        return DeviceField(FIELD_PLANE, plane=coef)
+
+
+# ------------------------------------------------------------------ entry points
+
+def grid_opts(log2_final, log2_coarse, dense=False, precision="fp32", band_delta=0.02,
+              guard_logit=1e-3, surrogate_max_log2=-1, surrogate_delta=0.1, tile_m=0,
+              max_waves=0) -> PifuGridOpts:
+    o = PifuGridOpts()
+    o.log2_final, o.log2_coarse, o.dense = log2_final, log2_coarse, int(dense)
+    o.precision = PREC[precision]
+    o.band_delta, o.guard_logit = band_delta, guard_logit
+    o.surrogate_max_log2, o.surrogate_delta = surrogate_max_log2, surrogate_delta
+    o.tile_m, o.max_waves = tile_m, max_waves
+    return o
+
+
+def occupancy_grid_workspace_size(field: DeviceField, opts: PifuGridOpts) -> int:
+    lib = load_library()
+    n = C.c_size_t()
+    _check(lib.pifu_occupancy_grid_workspace_size(C.byref(field.struct), C.byref(opts), C.byref(n)),
+           "pifu_occupancy_grid_workspace_size")
+    return n.value
+
+
+class GridOutputs:
+    """Preallocated outputs + workspace of pifu_occupancy_grid (reusable across calls)."""
+
+    def __init__(self, field: DeviceField, opts: PifuGridOpts, cells_cap: Optional[int] = None,
+                 eval_level: bool = False, device="cuda"):
+        n = (1 << opts.log2_final) + 1
+        self.opts = opts
+        self.occ = torch.empty((n, n, n), dtype=torch.float32, device=device)
+        self.labels = torch.empty((n, n, n), dtype=torch.uint8, device=device)
+        self.eval_level = torch.empty((n, n, n), dtype=torch.uint8, device=device) if eval_level else None
+        cap = cells_cap if cells_cap is not None else min((n - 1) ** 3, 1 << 26)
+        self.cells = torch.empty(max(cap, 1), dtype=torch.int32, device=device)
+        self.cells_cap = cap
+        self.ws_bytes = occupancy_grid_workspace_size(field, opts)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        n_levels = 1 if opts.dense else opts.log2_final - opts.log2_coarse + 1
+        self.stats = (PifuLevelStats * n_levels)()
+        self.n_cells = C.c_uint32()
+
+
+def occupancy_grid_into(field: DeviceField, out: GridOutputs, stream=None) -> None:
+    lib = load_library()
+    st = lib.pifu_occupancy_grid(context(), C.byref(field.struct), C.byref(out.opts),
+                                 _ptr(out.occ), _ptr(out.labels), _ptr(out.eval_level),
+                                 _ptr(out.cells), out.cells_cap, C.byref(out.n_cells), out.stats,
+                                 _ptr(out.ws), out.ws_bytes, _stream(stream))
+    _check(st, "pifu_occupancy_grid")
+
+
+def occupancy_grid(field: DeviceField, log2_final: int, log2_coarse: int, *, dense=False,
+                   precision="fp32", guard_logit=1e-3, band_delta=0.02, max_waves=0,
+                   cells_cap=None, eval_level=False, stream=None, **kw) -> Dict[str, object]:
+    """Hierarchical occupancy grid (see pifu_occupancy_grid in include/pifu.h)."""
+    opts = grid_opts(log2_final, log2_coarse, dense, precision, band_delta, guard_logit,
+                     max_waves=max_waves, **kw)
+    out = GridOutputs(field, opts, cells_cap, eval_level)
+    occupancy_grid_into(field, out, stream)
+    nc = out.n_cells.value
+    return dict(occ=out.occ, labels=out.labels, eval_level=out.eval_level,
+                cells=out.cells[:min(nc, out.cells_cap)], n_cells=nc,
+                stats=[s.as_dict() for s in out.stats])
+
+
+def render_opts(log2_w, log2_d, log2_coarse_w, precision="fp32", band_delta=0.02, guard_logit=1e-3,
+                surrogate_max_log2=-1, surrogate_delta=0.1, tile_m=0, max_waves=0) -> PifuRenderOpts:
+    o = PifuRenderOpts()
+    o.log2_w, o.log2_d, o.log2_coarse_w = log2_w, log2_d, log2_coarse_w
+    o.precision = PREC[precision]
+    o.band_delta, o.guard_logit = band_delta, guard_logit
+    o.surrogate_max_log2, o.surrogate_delta = surrogate_max_log2, surrogate_delta
+    o.tile_m, o.max_waves = tile_m, max_waves
+    return o
+
+
+class RenderOutputs:
+    def __init__(self, occ_field: DeviceField, color_field: DeviceField, opts: PifuRenderOpts,
+                 device="cuda"):
+        lib = load_library()
+        W = 1 << opts.log2_w
+        self.opts = opts
+        self.rgb = torch.empty((W, W, 3), dtype=torch.float32, device=device)
+        self.depth = torch.empty((W, W), dtype=torch.float32, device=device)
+        self.hit = torch.empty((W, W), dtype=torch.uint8, device=device)
+        n = C.c_size_t()
+        _check(lib.pifu_render_view_workspace_size(C.byref(occ_field.struct),
+                                                   C.byref(color_field.struct), C.byref(opts),
+                                                   C.byref(n)), "pifu_render_view_workspace_size")
+        self.ws_bytes = n.value
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        self.stats = (PifuLevelStats * (opts.log2_w - opts.log2_coarse_w + 1))()
+
+
+def render_view_into(occ_field: DeviceField, color_field: DeviceField, view, bg,
+                     out: RenderOutputs, stream=None) -> None:
+    lib = load_library()
+    v = (C.c_float * 12)(*[float(x) for x in np.asarray(view, np.float32).reshape(-1)])
+    b = (C.c_float * 3)(*[float(x) for x in bg])
+    st = lib.pifu_render_view(context(), C.byref(occ_field.struct), C.byref(color_field.struct), v,
+                              C.byref(out.opts), b, _ptr(out.rgb), _ptr(out.depth), _ptr(out.hit),
+                              out.stats, _ptr(out.ws), out.ws_bytes, _stream(stream))
+    _check(st, "pifu_render_view")
+
+
+def render_view(occ_field: DeviceField, color_field: DeviceField, view, log2_w: int, log2_d: int,
+                log2_coarse_w: int, bg=(0.0, 0.0, 0.0), *, precision="fp32", guard_logit=1e-3,
+                band_delta=0.02, max_waves=0, stream=None, **kw) -> Dict[str, object]:
+    """Mesh-free rendering of a target view (see pifu_render_view in include/pifu.h)."""
+    opts = render_opts(log2_w, log2_d, log2_coarse_w, precision, band_delta, guard_logit,
+                       max_waves=max_waves, **kw)
+    out = RenderOutputs(occ_field, color_field, opts)
+    render_view_into(occ_field, color_field, view, bg, out, stream)
+    return dict(rgb=out.rgb, depth=out.depth, hit=out.hit, stats=[s.as_dict() for s in out.stats])
+
+
+def eval_points(field: DeviceField, pts, precision="fp32", guard_logit=1e-3, band_delta=0.02,
+                stream=None):
+    """Field logits and labels at input-view NDC points (n x 3)."""
+    lib = load_library()
+    p = torch.as_tensor(np.asarray(pts, np.float32)) if not isinstance(pts, torch.Tensor) else pts
+    n = p.shape[0]
+    p4 = torch.zeros((n, 4), dtype=torch.float32, device="cuda")
+    p4[:, :3] = p.to(device="cuda", dtype=torch.float32)
+    logit = torch.empty(n, dtype=torch.float32, device="cuda")
+    labels = torch.empty(n, dtype=torch.uint8, device="cuda")
+    sz = C.c_size_t()
+    _check(lib.pifu_eval_points_workspace_size(C.byref(field.struct), PREC[precision], n,
+                                               C.byref(sz)), "pifu_eval_points_workspace_size")
+    ws = torch.empty(sz.value, dtype=torch.uint8, device="cuda")
+    st = lib.pifu_eval_points(context(), C.byref(field.struct), PREC[precision], band_delta,
+                              guard_logit, _ptr(p4), n, _ptr(logit), _ptr(labels), _ptr(ws),
+                              sz.value, _stream(stream))
+    _check(st, "pifu_eval_points")
+    return logit, labels

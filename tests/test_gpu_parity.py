@@ -1,0 +1,157 @@
+"""GPU parity: libpifu (through its C ABI) against the FP64 oracle.
+
+Bar: labels, per-level evaluated sets, conflict statistics and cell lists are
+bit-exact; FP32 occupancy p is within 1e-4 of the FP64 value.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import pifu_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+P_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def pifu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2007_13988_amd as P
+    P.load_library()
+    return P
+
+
+def _fields_tiny(P):
+    feat = synth.tiny_features()
+    spec = synth.tiny_mlp()
+    return O.Field("mlp", feat=feat, mlp=spec), P.DeviceField.mlp_field(feat, spec)
+
+
+def _stats_equal(gpu_stats, levels):
+    for g, rec in zip(gpu_stats, levels):
+        for k in ("nodes", "b0", "dilated", "evaluated", "waves", "conflicts"):
+            assert g[k] == rec.stats[k], (rec.level, k, g[k], rec.stats[k])
+
+
+def _grid_parity(gpu, ref):
+    lab = gpu["labels"].cpu().numpy()
+    assert np.array_equal(lab, ref["labels"]), "labels differ"
+    assert np.array_equal(gpu["eval_level"].cpu().numpy(), ref["eval_level"]), "evaluated sets differ"
+    assert gpu["n_cells"] == ref["cells"].size
+    assert np.array_equal(gpu["cells"].cpu().numpy().astype(np.uint32), ref["cells"])
+    occ = gpu["occ"].cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(occ - ref["occ"])) <= P_TOL
+    _stats_equal(gpu["stats"], ref["levels"])
+
+
+def test_eval_points_tiny_mlp(pifu):
+    fo, fg = _fields_tiny(pifu)
+    pts = synth.precision_points(20000, 11)
+    pts[:100, :2] = np.clip(pts[:100, :2] * 1.3, -1.3, 1.3)   # some samples fall off the map
+    lg, lab = pifu.eval_points(fg, pts)
+    ref = O.field_logit(fo, pts)
+    lg = lg.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(O.sigmoid(lg) - O.sigmoid(ref))) <= P_TOL
+    assert np.array_equal(lab.cpu().numpy(), (ref > 0).astype(np.uint8))
+
+
+def test_eval_points_pifu_mlp(pifu):
+    feat = synth.pifu_features()
+    spec = synth.pifu_mlp()
+    fo = O.Field("mlp", feat=feat, mlp=spec)
+    fg = pifu.DeviceField.mlp_field(feat, spec)
+    pts = synth.precision_points(5000, 12)
+    lg, lab = pifu.eval_points(fg, pts)
+    ref = O.field_logit(fo, pts)
+    lg = lg.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(lg - ref)) <= 1e-4
+    assert np.max(np.abs(O.sigmoid(lg) - O.sigmoid(ref))) <= P_TOL
+    assert np.array_equal(lab.cpu().numpy(), (ref > 0).astype(np.uint8))
+
+
+def test_eval_points_ellipsoids(pifu):
+    ell = synth.ellipsoids(8, 302)
+    fo = O.Field("ellipsoids", ell=ell, sharpness=8.0)
+    fg = pifu.DeviceField.ellipsoids(ell, 8.0)
+    pts = synth.precision_points(10000, 13)
+    lg, lab = pifu.eval_points(fg, pts)
+    ref = O.field_logit(fo, pts)
+    assert np.max(np.abs(lg.cpu().numpy() - ref)) <= 1e-5
+    assert np.array_equal(lab.cpu().numpy(), (ref > 0).astype(np.uint8))
+
+
+@pytest.mark.parametrize("L,l0", [(5, 3), (5, 2), (4, 4)])
+def test_occupancy_grid_tiny_mlp(pifu, L, l0):
+    fo, fg = _fields_tiny(pifu)
+    gpu = pifu.occupancy_grid(fg, L, l0, eval_level=True)
+    ref = O.occupancy_grid(fo, L, l0)
+    _grid_parity(gpu, ref)
+
+
+def test_occupancy_grid_dense_tiny(pifu):
+    fo, fg = _fields_tiny(pifu)
+    gpu = pifu.occupancy_grid(fg, 5, 5, dense=True, eval_level=True)
+    ref = O.dense_grid(fo, 5)
+    assert np.array_equal(gpu["labels"].cpu().numpy(), ref["labels"])
+    assert np.array_equal(gpu["cells"].cpu().numpy().astype(np.uint32), ref["cells"])
+    assert np.max(np.abs(gpu["occ"].cpu().numpy() - ref["occ"])) <= P_TOL
+
+
+@pytest.mark.parametrize("seed,L,l0", [(301, 6, 3), (302, 8, 5)])
+def test_occupancy_grid_ellipsoids(pifu, seed, L, l0):
+    ell = synth.ellipsoids(8, seed)
+    fo = O.Field("ellipsoids", ell=ell, sharpness=8.0)
+    fg = pifu.DeviceField.ellipsoids(ell, 8.0)
+    gpu = pifu.occupancy_grid(fg, L, l0, eval_level=True)
+    ref = O.occupancy_grid(fo, L, l0)
+    _grid_parity(gpu, ref)
+
+
+def test_occupancy_grid_plane_and_constant(pifu):
+    for plane in (synth.PLANE_TINY, np.array([0, 0, 0, 1.0], np.float32)):
+        fo = O.Field("plane", plane=plane)
+        fg = pifu.DeviceField.plane_field(plane)
+        gpu = pifu.occupancy_grid(fg, 6, 2, eval_level=True)
+        ref = O.occupancy_grid(fo, 6, 2)
+        _grid_parity(gpu, ref)
+
+
+def test_cells_capacity_truncates(pifu):
+    fo, fg = _fields_tiny(pifu)
+    ref = O.occupancy_grid(fo, 5, 3)
+    gpu = pifu.occupancy_grid(fg, 5, 3, cells_cap=17)
+    assert gpu["n_cells"] == ref["cells"].size
+    assert np.array_equal(gpu["cells"].cpu().numpy().astype(np.uint32), ref["cells"][:17])
+
+
+def _color(C=64, seed=5):
+    feat = synth.feature_map(32, 32, C, 4.0, seed)
+    spec = synth.he_mlp(C, 2, [128, 64, 3], [False, False, False], seed + 1, hidden_act="lrelu",
+                        out_act="tanh")
+    return feat, spec
+
+
+@pytest.mark.parametrize("yaw", [0.0, 45.0, 90.0])
+def test_render_tiny(pifu, yaw):
+    fo, fg = _fields_tiny(pifu)
+    cfeat, cspec = _color()
+    co = O.Field("mlp", feat=cfeat, mlp=cspec)
+    cg = pifu.DeviceField.mlp_field(cfeat, cspec)
+    view = synth.yaw_view(yaw)
+    bg = (0.2, 0.4, 0.6)
+    ref = O.render_view(fo, co, view, 6, 5, 4, bg)
+    gpu = pifu.render_view(fg, cg, view, 6, 5, 4, bg)
+    hit = gpu["hit"].cpu().numpy()
+    assert np.array_equal(hit, ref["hit"])
+    d = gpu["depth"].cpu().numpy()
+    assert np.array_equal(np.isnan(d), np.isnan(ref["depth"]))
+    assert np.max(np.abs(d[hit == 1] - ref["depth"][hit == 1])) <= 1e-4
+    assert np.max(np.abs(gpu["rgb"].cpu().numpy() - ref["rgb"])) <= 1e-4
+    _stats_equal(gpu["stats"][:-1], ref["levels"])
+    last = gpu["stats"][-1]
+    assert last["evaluated"] == ref["stats"]["evaluated_last"]
+    assert last["shadow"] == ref["stats"]["shadow"]
+    assert last["hits"] == ref["stats"]["hits"]

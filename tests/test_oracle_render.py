@@ -97,8 +97,9 @@ def _brute_render(occ_fld, col_fld, view, lw, ld, lcw, bg):
     return rgb.transpose(1, 0, 2), depth.T, hit.T, n_eval
 
 
-@pytest.mark.parametrize("yaw,kind", [(0.0, "mlp"), (45.0, "mlp"), (45.0, "ell")])
-def test_render_matches_per_ray_brute_force(yaw, kind):
+@pytest.mark.parametrize("yaw,kind,sizes", [(0.0, "mlp", (4, 3, 2)), (45.0, "mlp", (4, 3, 2)),
+                                            (45.0, "ell", (5, 4, 3))])
+def test_render_matches_per_ray_brute_force(yaw, kind, sizes):
     if kind == "mlp":
         feat = synth.feature_map(16, 16, 8, 2.0, 3)
         occ = O.Field("mlp", feat=feat, mlp=synth.he_mlp(8, 1, [16, 8, 1], [False] * 3, 4))
@@ -107,8 +108,9 @@ def test_render_matches_per_ray_brute_force(yaw, kind):
     col = _color_field()
     view = synth.yaw_view(yaw)
     bg = (0.25, -0.5, 1.0)
-    r = O.render_view(occ, col, view, 4, 3, 2, bg)
-    rgb, depth, hit, n_eval = _brute_render(occ, col, view, 4, 3, 2, bg)
+    r = O.render_view(occ, col, view, *sizes, bg)
+    rgb, depth, hit, n_eval = _brute_render(occ, col, view, *sizes, bg)
+    assert hit.sum() > 0
     assert np.array_equal(r["hit"], hit)
     assert np.array_equal(np.isnan(r["depth"]), np.isnan(depth))
     assert np.allclose(r["depth"][hit == 1], depth[hit == 1], rtol=0, atol=1e-12)
