@@ -248,6 +248,33 @@ int32_t pifu_eval_points(pifu_ctx* ctx, const pifu_field* field, int32_t precisi
                          float* logit, uint8_t* labels, void* workspace, size_t workspace_bytes,
                          pifu_stream stream);
 
+/* ---------------------------------------------------------------- kernel profiling */
+
+/* Kernel families timed by the built-in profiler (index into pifu_profile_read's array). */
+#define PIFU_KERN_GEMM_F32 0      /* MLP hidden layer, FP32 MFMA */
+#define PIFU_KERN_GEMM_BF16 1     /* MLP hidden layer, BF16 MFMA */
+#define PIFU_KERN_GEMM_FP8 2      /* MLP hidden layer, FP8 MFMA */
+#define PIFU_KERN_GATHER 3        /* point projection + bilinear feature gather */
+#define PIFU_KERN_HEAD 4          /* last MLP layer + output rule */
+#define PIFU_KERN_COUNT 8
+
+/* Accumulated over the launches of one kernel family since the last enable. flops
+ * and bytes are algorithmic counts (2*M*N*K for a GEMM; texels read + features
+ * written for the gather), not hardware counters. */
+typedef struct pifu_kernel_profile {
+  uint64_t launches;
+  double total_ms;
+  double flops;
+  double bytes;
+} pifu_kernel_profile;
+
+/* on != 0: every later call records HIP events around each launch of the families
+ * above, on the stream the launch uses, and accumulates durations when the call
+ * completes.  Enabling (or disabling) resets the accumulators. */
+int32_t pifu_profile_enable(pifu_ctx* ctx, int32_t on);
+/* Copies PIFU_KERN_COUNT records into out (host). */
+int32_t pifu_profile_read(pifu_ctx* ctx, pifu_kernel_profile* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -7,17 +7,65 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "pifu_internal.h"
 
 using namespace pifu;
 
+struct ProfRecord {
+  int kind;
+  int ev;            // index of the start event; stop is ev + 1
+  double flops, bytes;
+};
+
 struct pifu_ctx {
   int device;
   uint32_t* host_counters;   // pinned, 64 words
+  bool prof_on = false;
+  std::vector<hipEvent_t> events;
+  std::vector<ProfRecord> pending;
+  pifu_kernel_profile prof[PIFU_KERN_COUNT];
 };
 
 namespace {
+
+// Event pair around one launch when profiling is on.
+struct ProfScope {
+  pifu_ctx* c;
+  hipStream_t s;
+  int idx = -1;
+  ProfScope(pifu_ctx* ctx, hipStream_t st, int kind, double flops, double bytes) : c(ctx), s(st) {
+    if (!c || !c->prof_on) return;
+    const size_t need = 2 * (c->pending.size() + 1);
+    while (c->events.size() < need) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return;
+      c->events.push_back(e);
+    }
+    idx = (int)(2 * c->pending.size());
+    c->pending.push_back(ProfRecord{kind, idx, flops, bytes});
+    (void)hipEventRecord(c->events[idx], s);
+  }
+  ~ProfScope() {
+    if (idx >= 0) (void)hipEventRecord(c->events[idx + 1], s);
+  }
+};
+
+// Folds the recorded launches into the accumulators; the stream must be idle.
+void prof_resolve(pifu_ctx* c) {
+  if (!c) return;
+  for (const ProfRecord& r : c->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->events[r.ev], c->events[r.ev + 1]) != hipSuccess) continue;
+    pifu_kernel_profile& p = c->prof[r.kind];
+    p.launches += 1;
+    p.total_ms += ms;
+    p.flops += r.flops;
+    p.bytes += r.bytes;
+  }
+  c->pending.clear();
+}
 
 constexpr size_t kAlign = 256;
 constexpr int kCounters = 64;
@@ -206,7 +254,10 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, const PointSrc& 
   for (uint32_t c0 = 0; c0 < n; c0 += ew.chunk) {
     const uint32_t m = std::min(ew.chunk, n - c0);
     const uint32_t* lst = list + c0;
-    launch_gather(src, lst, m, f->feat, f->H, f->W, C, ew.feat, 0, ew.ext, e.s);
+    {
+      ProfScope ps(e.ctx, e.s, PIFU_KERN_GATHER, 0.0, (double)m * (20.0 * C + 20.0));
+      launch_gather(src, lst, m, f->feat, f->H, f->W, C, ew.feat, 0, ew.ext, e.s);
+    }
     const void* prev = nullptr;
     void* out = ew.hA;
     for (int l = 0; l + 1 < d.n_layers; ++l) {
@@ -240,11 +291,18 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, const PointSrc& 
       g.N = d.widths[l];
       g.act = d.hidden_act;
       g.scale = 1.f;
-      if (launch_gemm(g, e.precision, 0, e.s)) return PIFU_ERR_UNSUPPORTED;
+      {
+        const int kind = e.precision == PIFU_PREC_FP32   ? PIFU_KERN_GEMM_F32
+                         : e.precision == PIFU_PREC_BF16 ? PIFU_KERN_GEMM_BF16
+                                                         : PIFU_KERN_GEMM_FP8;
+        ProfScope ps(e.ctx, e.s, kind, 2.0 * m * g.N * (g.K1 + g.K2 + g.n_ext), 0.0);
+        if (launch_gemm(g, e.precision, 0, e.s)) return PIFU_ERR_UNSUPPORTED;
+      }
       prev = out;
       out = (out == ew.hA) ? ew.hB : ew.hA;
     }
     const int L = d.n_layers - 1;
+    ProfScope ps(e.ctx, e.s, PIFU_KERN_HEAD, 2.0 * m * d.widths[L - 1] * d.widths[L], 0.0);
     launch_head(reinterpret_cast<const float*>(prev), d.widths[L - 1], d.W[L], d.b[L], d.widths[L],
                 d.out_act, m, ew.ext, logit ? logit + c0 : nullptr, lab ? lab + c0 : nullptr, rgb,
                 rgb ? lst : nullptr, e.s);
@@ -542,6 +600,7 @@ int32_t pifu_create(pifu_ctx** out) {
 void pifu_destroy(pifu_ctx* ctx) {
   if (!ctx) return;
   if (ctx->host_counters) (void)hipHostFree(ctx->host_counters);
+  for (hipEvent_t ev : ctx->events) (void)hipEventDestroy(ev);
   delete ctx;
 }
 
@@ -603,6 +662,7 @@ int32_t pifu_occupancy_grid(pifu_ctx* ctx, const pifu_field* field, const pifu_g
                       1, fin, &nc);
     *n_cells = nc;
   }
+  prof_resolve(ctx);
   delete gp;
   return r;
 }
@@ -701,8 +761,9 @@ int32_t pifu_render_view(pifu_ctx* ctx, const pifu_field* occ_field, const pifu_
     }
   }
   if (!r) r = check_launch();
-  if (!r) HIP_TRY(hipStreamSynchronize(s));
+  if (!r) r = hipStreamSynchronize(s) == hipSuccess ? PIFU_OK : PIFU_ERR_HIP;
   if (stats) stats[T] = st;
+  prof_resolve(ctx);
   delete gp;
   return r;
 }
@@ -759,8 +820,23 @@ int32_t pifu_eval_points(pifu_ctx* ctx, const pifu_field* field, int32_t precisi
   if (!labels && fp.has_mlp && guard_logit > 0.f) return PIFU_ERR_INVALID_ARGUMENT;
   r = eval_occupancy(e, fp, src, iota, n, ew, logit, lab, nullptr);
   if (!r) r = check_launch();
-  if (!r) HIP_TRY(hipStreamSynchronize(s));
+  if (!r) r = hipStreamSynchronize(s) == hipSuccess ? PIFU_OK : PIFU_ERR_HIP;
+  prof_resolve(ctx);
   return r;
+}
+
+int32_t pifu_profile_enable(pifu_ctx* ctx, int32_t on) {
+  if (!ctx) return PIFU_ERR_INVALID_ARGUMENT;
+  ctx->prof_on = on != 0;
+  ctx->pending.clear();
+  std::memset(ctx->prof, 0, sizeof(ctx->prof));
+  return PIFU_OK;
+}
+
+int32_t pifu_profile_read(pifu_ctx* ctx, pifu_kernel_profile* out) {
+  if (!ctx || !out) return PIFU_ERR_INVALID_ARGUMENT;
+  std::memcpy(out, ctx->prof, sizeof(ctx->prof));
+  return PIFU_OK;
 }
 
 }  // extern "C"

@@ -66,10 +66,19 @@ class PifuRenderOpts(C.Structure):
                 ("tile_m", C.c_int32), ("max_waves", C.c_int32)]
 
 
+class PifuKernelProfile(C.Structure):
+    _fields_ = [("launches", C.c_uint64), ("total_ms", C.c_double), ("flops", C.c_double),
+                ("bytes", C.c_double)]
+
+
+KERN = {"gemm_f32": 0, "gemm_bf16": 1, "gemm_fp8": 2, "gather": 3, "head": 4}
+KERN_COUNT = 8
+
 EXPORTS = ["pifu_create", "pifu_destroy", "pifu_status_string",
            "pifu_occupancy_grid_workspace_size", "pifu_occupancy_grid",
            "pifu_render_view_workspace_size", "pifu_render_view",
-           "pifu_eval_points_workspace_size", "pifu_eval_points"]
+           "pifu_eval_points_workspace_size", "pifu_eval_points",
+           "pifu_profile_enable", "pifu_profile_read"]
 
 _lib = None
 
@@ -103,6 +112,8 @@ def load_library():
     lib.pifu_eval_points_workspace_size.argtypes = [C.POINTER(PifuField), i32, u32, C.POINTER(sz)]
     lib.pifu_eval_points.argtypes = [P, C.POINTER(PifuField), i32, C.c_float, C.c_float, P, u32, P,
                                      P, P, sz, P]
+    lib.pifu_profile_enable.argtypes = [P, i32]
+    lib.pifu_profile_read.argtypes = [P, C.POINTER(PifuKernelProfile)]
     for name in EXPORTS:
         if name not in ("pifu_destroy", "pifu_status_string"):
             getattr(lib, name).restype = i32
@@ -130,6 +141,18 @@ def context() -> C.c_void_p:
         _check(lib.pifu_create(C.byref(h)), "pifu_create")
         _ctx[dev] = h
     return _ctx[dev]
+
+
+def profile_enable(on: bool = True) -> None:
+    """Turns the library's per-launch event timing on/off (resets the accumulators)."""
+    _check(load_library().pifu_profile_enable(context(), int(on)), "pifu_profile_enable")
+
+
+def profile_read() -> Dict[str, Dict[str, float]]:
+    recs = (PifuKernelProfile * KERN_COUNT)()
+    _check(load_library().pifu_profile_read(context(), recs), "pifu_profile_read")
+    return {name: dict(launches=recs[i].launches, total_ms=recs[i].total_ms,
+                       flops=recs[i].flops, bytes=recs[i].bytes) for name, i in KERN.items()}
 
 
 def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
