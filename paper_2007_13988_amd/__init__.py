@@ -2,5 +2,5 @@
 pixel-aligned implicit function.  The compute path is libpifu.so (HIP); this package
 holds its build script and the ctypes binding."""
 from .pifu import (DeviceField, DeviceMLP, GridOutputs, RenderOutputs, eval_points,  # noqa: F401
-                   grid_opts, load_library, occupancy_grid, occupancy_grid_into, render_opts,
-                   render_view, render_view_into)
+                   grid_opts, load_library, occupancy_grid, occupancy_grid_into, profile_enable,
+                   profile_read, render_opts, render_view, render_view_into)

@@ -1,0 +1,301 @@
+// Float64 re-evaluation of the points whose FP32 logit lies in the guard band
+// |logit| < g, so that the binary label [logit > 0] is decided in float64.  The
+// guarded points are batched: float64 gather, float64 MFMA GEMMs per hidden layer,
+// float64 head -- the same network as the FP32 path, evaluated in double precision.
+#include "pifu_internal.h"
+
+namespace pifu {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+static inline unsigned grid1d(size_t n, int block) { return (unsigned)((n + block - 1) / block); }
+
+__device__ inline bool src_point64(const PointSrc& s, uint32_t idx, double P[3], double* occ) {
+  if (s.mode == 1) {
+    const float4 q = s.pts[idx];
+    P[0] = q.x;
+    P[1] = q.y;
+    P[2] = q.z;
+    *occ = q.w;
+    return true;
+  }
+  *occ = 0.0;
+  const uint32_t nyz = (uint32_t)s.ny * s.nz;
+  const uint32_t a = idx / nyz;
+  const uint32_t r = idx - a * nyz;
+  const uint32_t b = r / s.nz;
+  const uint32_t k = r - b * s.nz;
+  double x = __dadd_rn(-1.0, __ddiv_rn(__dmul_rn(2.0, (double)a), (double)(s.nx - 1)));
+  double y = __dadd_rn(-1.0, __ddiv_rn(__dmul_rn(2.0, (double)b), (double)(s.ny - 1)));
+  double z = __dadd_rn(-1.0, __ddiv_rn(__dmul_rn(2.0, (double)k), (double)(s.nz - 1)));
+  if (!s.has_view) {
+    P[0] = x;
+    P[1] = y;
+    P[2] = z;
+    return true;
+  }
+  bool in = true;
+#pragma unroll
+  for (int r3 = 0; r3 < 3; ++r3) {
+    const double* v = s.view + 4 * r3;
+    double t = __dadd_rn(__dadd_rn(__dadd_rn(__dmul_rn(v[0], x), __dmul_rn(v[1], y)),
+                                   __dmul_rn(v[2], z)), v[3]);
+    P[r3] = t;
+    in = in && (t >= -1.0) && (t <= 1.0);
+  }
+  return in;
+}
+
+// Node list of the guarded points: gnode[i] = list[glist[i]].
+__global__ void k_guard_nodes(const uint32_t* __restrict__ list, const uint32_t* __restrict__ glist,
+                              uint32_t gn, uint32_t* __restrict__ gnode) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < gn) gnode[i] = list ? list[glist[i]] : glist[i];
+}
+
+// One wave per point: float64 bilinear blend of C channels; ext64 = (z', occ, clipped, 0).
+__global__ void __launch_bounds__(256)
+k_gather64(PointSrc src, const uint32_t* __restrict__ nodes, uint32_t n,
+           const float* __restrict__ F, int H, int W, int C, double* __restrict__ feat,
+           double* __restrict__ ext) {
+  const uint32_t m = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (m >= n) return;
+  double P[3], occ;
+  const bool in = src_point64(src, nodes[m], P, &occ);
+  double u = __dmul_rn(__dmul_rn(__dadd_rn(P[0], 1.0), 0.5), (double)(W - 1));
+  double v = __dmul_rn(__dmul_rn(__dadd_rn(P[1], 1.0), 0.5), (double)(H - 1));
+  const double fu0 = floor(u), fv0 = floor(v);
+  const double fu = u - fu0, fv = v - fv0;
+  const int u0 = (int)fu0, v0 = (int)fv0;
+  const double w[4] = {(1.0 - fu) * (1.0 - fv), fu * (1.0 - fv), (1.0 - fu) * fv, fu * fv};
+  const int tu[4] = {u0, u0 + 1, u0, u0 + 1};
+  const int tv[4] = {v0, v0, v0 + 1, v0 + 1};
+  for (int c = lane; c < C; c += 64) {
+    double acc = 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (tu[t] < 0 || tu[t] > W - 1 || tv[t] < 0 || tv[t] > H - 1) continue;
+      acc += w[t] * (double)F[((size_t)tv[t] * W + tu[t]) * C + c];
+    }
+    feat[(size_t)m * C + c] = acc;
+  }
+  if (lane == 0) {
+    double* e = ext + 4 * (size_t)m;
+    e[0] = P[2];
+    e[1] = occ;
+    e[2] = in ? 0.0 : 1.0;
+    e[3] = 0.0;
+  }
+}
+
+// Dense float64 operand copy of the first K columns of a [N][ldw_src] fp32 matrix.
+__global__ void k_pack64(const float* __restrict__ W, int N, int ldw_src, int K,
+                         double* __restrict__ dst) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)N * K) return;
+  const int n = (int)(i / K), k = (int)(i - (size_t)n * K);
+  dst[i] = (double)W[(size_t)n * ldw_src + k];
+}
+
+struct Gemm64Args {
+  const double* A1;
+  int K1, lda1;
+  const double* A2;
+  int K2, lda2;
+  const double* W;   // [N][K1 + K2]
+  const float* Wf;   // original fp32 weights (extras columns)
+  int ldwf;
+  const float* bias;
+  const double* ext;
+  int n_ext, ext_col;
+  double* C;
+  int M, N, act;
+};
+
+// 64 x 64 output tile, 4 waves of 32 x 32 (2 x 2 blocks of v_mfma_f64_16x16x4f64).
+// Lane group g = lane/16 feeds the k values [4g, 4g+4) of each 16-wide k step
+// (same permutation for A and B).  Output block layout: lane l, register r holds
+// row 4*(l/16) + r, column l%16.
+__global__ void __launch_bounds__(256) k_gemm64(Gemm64Args a) {
+  constexpr int BM = 64, BN = 64, BK = 16, LD = BK + 2;
+  __shared__ __attribute__((aligned(16))) double As[BM * LD];
+  __shared__ __attribute__((aligned(16))) double Bs[BN * LD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const int K = a.K1 + a.K2;
+  const int g = lane >> 4, r16 = lane & 15;
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    const double* src;
+    int ld, kk0;
+    if (k0 < a.K1) {
+      src = a.A1;
+      ld = a.lda1;
+      kk0 = k0;
+    } else {
+      src = a.A2;
+      ld = a.lda2;
+      kk0 = k0 - a.K1;
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int e = tid + 256 * i;          // 512 double2 per 64 x 16 tile
+      const int row = e >> 3, c2 = e & 7;
+      const int gm = m0 + row;
+      double2 va = gm < a.M ? *reinterpret_cast<const double2*>(src + (size_t)gm * ld + kk0 + 2 * c2)
+                            : make_double2(0.0, 0.0);
+      *reinterpret_cast<double2*>(&As[row * LD + 2 * c2]) = va;
+      double2 vb = *reinterpret_cast<const double2*>(a.W + (size_t)(n0 + row) * K + k0 + 2 * c2);
+      *reinterpret_cast<double2*>(&Bs[row * LD + 2 * c2]) = vb;
+    }
+    __syncthreads();
+    double av[2][4], bv[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        av[i][s] = As[(wm * 32 + 16 * i + r16) * LD + 4 * g + s];
+        bv[i][s] = Bs[(wn * 32 + 16 * i + r16) * LD + 4 * g + s];
+      }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][s], bv[j][s], acc[i][j], 0, 0, 0);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = n0 + wn * 32 + 16 * j + r16;
+      const double bias = a.bias[col];
+      double we0 = 0.0, we1 = 0.0;
+      if (a.n_ext > 0) we0 = a.Wf[(size_t)col * a.ldwf + a.ext_col];
+      if (a.n_ext > 1) we1 = a.Wf[(size_t)col * a.ldwf + a.ext_col + 1];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * 32 + 16 * i + 4 * g + r;
+        if (row >= a.M) continue;
+        double v = acc[i][j][r] + bias;
+        if (a.n_ext > 0) v += a.ext[4 * (size_t)row] * we0;
+        if (a.n_ext > 1) v += a.ext[4 * (size_t)row + 1] * we1;
+        if (a.act == PIFU_ACT_RELU) v = v > 0.0 ? v : 0.0;
+        else if (a.act == PIFU_ACT_LRELU) v = v > 0.0 ? v : 0.01 * v;
+        a.C[(size_t)row * a.N + col] = v;
+      }
+    }
+}
+
+// One wave per point: last layer in float64, then scatter to the guarded positions.
+__global__ void __launch_bounds__(256)
+k_head64(const double* __restrict__ h, int K, const float* __restrict__ W,
+         const float* __restrict__ b, uint32_t n, const double* __restrict__ ext,
+         const uint32_t* __restrict__ glist, float* __restrict__ logit, uint8_t* __restrict__ lab) {
+  const uint32_t m = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (m >= n) return;
+  double acc = 0.0;
+  for (int k = lane; k < K; k += 64) acc += h[(size_t)m * K + k] * (double)W[k];
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
+  if (lane) return;
+  double v = acc + (double)b[0];
+  if (ext[4 * (size_t)m + 2] != 0.0) v = -INFINITY;
+  const uint32_t pos = glist[m];
+  logit[pos] = (float)v;
+  lab[pos] = v > 0.0;
+}
+
+size_t guard64_ws_bytes(const MLPDesc& d, uint32_t chunk) {
+  size_t w = 0;
+  int maxw = 1;
+  for (int l = 0; l + 1 < d.n_layers; ++l) {
+    const int Kp = l == 0 ? d.feat_dim : d.in_w[l];
+    w += (size_t)d.widths[l] * Kp;
+    maxw = d.widths[l] > maxw ? d.widths[l] : maxw;
+  }
+  const size_t elems = w + (size_t)chunk * (d.feat_dim + 4 + 2 * maxw) + 64;
+  return elems * sizeof(double) + (size_t)chunk * 4 + 4096;
+}
+
+// Re-evaluates the gn guarded points (positions glist into the evaluated list) in
+// float64 and overwrites their logit and label.  ws holds guard64_ws_bytes(d, chunk).
+void run_guard64(const PointSrc& src, const uint32_t* list, const uint32_t* glist, uint32_t gn,
+                 const MLPDesc& d, const float* F, int H, int W, int C, float* logit, uint8_t* lab,
+                 void* ws, uint32_t chunk, hipStream_t s) {
+  if (!gn) return;
+  double* base = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(ws) + 255) & ~uintptr_t(255));
+  double* Wp[PIFU_MAX_LAYERS];
+  int maxw = 1;
+  for (int l = 0; l + 1 < d.n_layers; ++l) {
+    const int Kp = l == 0 ? d.feat_dim : d.in_w[l];
+    Wp[l] = base;
+    base += (size_t)d.widths[l] * Kp;
+    hipLaunchKernelGGL(k_pack64, dim3(grid1d((size_t)d.widths[l] * Kp, 256)), dim3(256), 0, s,
+                       d.W[l], d.widths[l], d.in_w[l], Kp, Wp[l]);
+    maxw = d.widths[l] > maxw ? d.widths[l] : maxw;
+  }
+  double* feat = base;
+  base += (size_t)chunk * C;
+  double* ext = base;
+  base += (size_t)chunk * 4;
+  double* hA = base;
+  base += (size_t)chunk * maxw;
+  double* hB = base;
+  base += (size_t)chunk * maxw;
+  uint32_t* gnode = reinterpret_cast<uint32_t*>(base);
+  for (uint32_t c0 = 0; c0 < gn; c0 += chunk) {
+    const uint32_t m = gn - c0 < chunk ? gn - c0 : chunk;
+    hipLaunchKernelGGL(k_guard_nodes, dim3(grid1d(m, 256)), dim3(256), 0, s, list, glist + c0, m,
+                       gnode);
+    hipLaunchKernelGGL(k_gather64, dim3(grid1d((size_t)m * 64, 256)), dim3(256), 0, s, src, gnode,
+                       m, F, H, W, C, feat, ext);
+    const double* prev = nullptr;
+    double* out = hA;
+    for (int l = 0; l + 1 < d.n_layers; ++l) {
+      Gemm64Args g = {};
+      if (l == 0) {
+        g.A1 = feat;
+        g.K1 = C;
+        g.lda1 = C;
+        g.n_ext = d.n_extra;
+        g.ext_col = C;
+      } else {
+        g.A1 = prev;
+        g.K1 = d.widths[l - 1];
+        g.lda1 = d.widths[l - 1];
+        if (d.skip[l]) {
+          g.A2 = feat;
+          g.K2 = C;
+          g.lda2 = C;
+        }
+      }
+      g.W = Wp[l];
+      g.Wf = d.W[l];
+      g.ldwf = d.in_w[l];
+      g.bias = d.b[l];
+      g.ext = ext;
+      g.C = out;
+      g.M = (int)m;
+      g.N = d.widths[l];
+      g.act = d.hidden_act;
+      hipLaunchKernelGGL(k_gemm64, dim3((m + 63) / 64, d.widths[l] / 64), dim3(256), 0, s, g);
+      prev = out;
+      out = out == hA ? hB : hA;
+    }
+    const int L = d.n_layers - 1;
+    hipLaunchKernelGGL(k_head64, dim3(grid1d((size_t)m * 64, 256)), dim3(256), 0, s, prev,
+                       d.widths[L - 1], d.W[L], d.b[L], m, ext, glist + c0, logit, lab);
+  }
+}
+
+}  // namespace pifu

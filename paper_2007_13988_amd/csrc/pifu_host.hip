@@ -197,6 +197,8 @@ struct EvalWs {
   void* hB = nullptr;
   uint32_t* glist = nullptr;
   uint32_t* iota = nullptr;
+  void* g64 = nullptr;       // float64 guard-band evaluation scratch
+  uint32_t chunk64 = 0;
 };
 
 struct FieldPrep {
@@ -217,6 +219,12 @@ void carve_field(Carver& cv, const pifu_field* f, int precision, FieldPrep& fp) 
     fp.ell.k = f->sharpness;
     if (f->ell) std::memcpy(fp.ell.e, f->ell, sizeof(float) * 12 * f->n_ell);
   }
+}
+
+void carve_guard(Carver& cv, const FieldPrep& fp, uint32_t max_points, EvalWs& ew) {
+  if (!fp.has_mlp) return;
+  ew.chunk64 = std::max<uint32_t>(64, std::min<uint32_t>(16384, max_points));
+  ew.g64 = cv.take<char>(guard64_ws_bytes(fp.mlp.d, ew.chunk64));
 }
 
 void carve_eval(Carver& cv, uint32_t max_points, int C, int max_hidden, EvalWs& ew) {
@@ -317,7 +325,8 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, const PointSrc& 
     if (r) return r;
     const uint32_t gn = e.ctx->host_counters[C_GUARD];
     if (guard_count) *guard_count = gn;
-    launch_guard_fp64(src, list, ew.glist, gn, d, f->feat, f->H, f->W, C, logit, lab, e.s);
+    run_guard64(src, list, ew.glist, gn, d, f->feat, f->H, f->W, C, logit, lab, ew.g64, ew.chunk64,
+                e.s);
     r = check_launch();
   }
   return r;
@@ -481,6 +490,7 @@ int plan_grid(const pifu_field* field, const pifu_grid_opts* o, void* base, floa
   const int C = field->kind == PIFU_FIELD_MLP ? field->C : 0;
   const int mh = g.fp.has_mlp ? g.fp.mlp.max_hidden : 0;
   carve_eval(cv, (uint32_t)max_n, C, mh, g.ew);
+  carve_guard(cv, g.fp, (uint32_t)max_n, g.ew);
   g.bytes = cv.off + kAlign;
   return PIFU_OK;
 }
@@ -566,6 +576,7 @@ int plan_render(const pifu_field* occ, const pifu_field* col, const pifu_render_
   C = std::max(C, col->C);
   mh = std::max(mh, g.cp.mlp.max_hidden);
   carve_eval(cv, (uint32_t)max_n, C, mh, g.ew);
+  carve_guard(cv, g.fp, (uint32_t)max_n, g.ew);
   g.bytes = cv.off + kAlign;
   return PIFU_OK;
 }
@@ -783,6 +794,7 @@ int32_t pifu_eval_points_workspace_size(const pifu_field* field, int32_t precisi
   EvalWs ew;
   carve_eval(cv, std::max<uint32_t>(n, 1), field->kind == PIFU_FIELD_MLP ? field->C : 0,
              fp.has_mlp ? fp.mlp.max_hidden : 0, ew);
+  carve_guard(cv, fp, std::max<uint32_t>(n, 1), ew);
   *bytes = cv.off + kAlign;
   return PIFU_OK;
 }
@@ -807,6 +819,7 @@ int32_t pifu_eval_points(pifu_ctx* ctx, const pifu_field* field, int32_t precisi
   EvalWs ew;
   carve_eval(cv, n, field->kind == PIFU_FIELD_MLP ? field->C : 0,
              fp.has_mlp ? fp.mlp.max_hidden : 0, ew);
+  carve_guard(cv, fp, n, ew);
   hipStream_t s = as_stream(stream);
   uint8_t* lab = labels;
   if (!lab) lab = reinterpret_cast<uint8_t*>(ew.glist);   // scratch when labels are not wanted

@@ -99,6 +99,10 @@ void launch_guard_select(const float* logit, uint32_t n, float g, uint32_t* glis
 void launch_guard_fp64(const PointSrc& src, const uint32_t* list, const uint32_t* glist,
                        uint32_t gn, const MLPDesc& mlp, const float* F, int H, int W, int C,
                        float* logit, uint8_t* lab, hipStream_t s);
+size_t guard64_ws_bytes(const MLPDesc& d, uint32_t chunk);
+void run_guard64(const PointSrc& src, const uint32_t* list, const uint32_t* glist, uint32_t gn,
+                 const MLPDesc& d, const float* F, int H, int W, int C, float* logit, uint8_t* lab,
+                 void* ws, uint32_t chunk, hipStream_t s);
 
 // ------------------------------------------------------------------ render kernels
 void launch_ray_count(const uint8_t* stc, Lat c, int W, int H, int D, uint32_t* cnt,

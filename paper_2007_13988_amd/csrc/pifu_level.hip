@@ -411,14 +411,25 @@ void launch_cells(uint8_t* st, Lat f, uint8_t* labels, hipStream_t s) {
 
 __global__ void k_count_bits(const uint8_t* __restrict__ st, size_t n, uint8_t bit,
                              uint32_t* __restrict__ out) {
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool v = i < n && (st[i] & bit);
-  unsigned long long bal = __ballot(v);
-  if ((threadIdx.x & 63) == 0 && bal) atomicAdd(out, (uint32_t)__popcll(bal));
+  // 16 nodes per thread, one atomic per workgroup
+  __shared__ uint32_t wsum[COMPACT_BLOCK / 64];
+  size_t base = (size_t)blockIdx.x * COMPACT_TILE + (size_t)threadIdx.x * COMPACT_PER_THREAD;
+  uint32_t c = __popc(pred_mask16(st, base, n, bit, bit));
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d, 64);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int w = 0; w < COMPACT_BLOCK / 64; ++w) t += wsum[w];
+    if (t) atomicAdd(out, t);
+  }
 }
 
 void launch_count_bits(const uint8_t* st, size_t n, uint8_t bit, uint32_t* out, hipStream_t s) {
-  if (n) hipLaunchKernelGGL(k_count_bits, dim3(grid1d(n, 256)), dim3(256), 0, s, st, n, bit, out);
+  if (n)
+    hipLaunchKernelGGL(k_count_bits, dim3((unsigned)((n + COMPACT_TILE - 1) / COMPACT_TILE)),
+                       dim3(COMPACT_BLOCK), 0, s, st, n, bit, out);
 }
 
 }  // namespace pifu

@@ -73,6 +73,44 @@ def test_eval_points_pifu_mlp(pifu):
     assert np.array_equal(lab.cpu().numpy(), (ref > 0).astype(np.uint8))
 
 
+def test_fp64_guard_path_matches_oracle(pifu):
+    """A guard band wider than every logit sends all points through the float64
+    re-evaluation (float64 gather, float64 MFMA GEMMs, float64 head)."""
+    feat = synth.pifu_features()
+    spec = synth.pifu_mlp()
+    fo = O.Field("mlp", feat=feat, mlp=spec)
+    fg = pifu.DeviceField.mlp_field(feat, spec)
+    pts = synth.precision_points(3000, 14).astype(np.float32).astype(np.float64)
+    pts[:50, :2] *= 1.2                     # off-map samples (zero padding)
+    pts = pts.astype(np.float32).astype(np.float64)
+    lg, lab = pifu.eval_points(fg, pts, guard_logit=1e30)
+    ref = O.field_logit(fo, pts)
+    # float64 result stored as float32
+    assert np.all(np.abs(lg.cpu().numpy() - ref) <= 1e-6 * np.maximum(1.0, np.abs(ref)))
+    assert np.array_equal(lab.cpu().numpy(), (ref > 0).astype(np.uint8))
+
+
+def test_fp32_logit_error_is_well_inside_the_guard_band(pifu):
+    """The guard band must exceed the FP32 path's logit error: assert the error
+    over many points near evaluated surface nodes stays below a tenth of it."""
+    feat = synth.pifu_features()
+    spec = synth.pifu_mlp()
+    fo = O.Field("mlp", feat=feat, mlp=spec)
+    fg = pifu.DeviceField.mlp_field(feat, spec)
+    g = O.occupancy_grid(O.Field("mlp", feat=feat, mlp=spec), 5, 5)   # 33^3 coarse grid
+    n = 33
+    near = np.argwhere(np.abs(g["logit"]) < 2.0)
+    base = -1.0 + 2.0 * near / (n - 1)
+    pts = np.concatenate([synth.jitter_points(base, 2.0 / (n - 1), 15),
+                          synth.precision_points(20000, 16)])[:60000]
+    pts = pts.astype(np.float32).astype(np.float64)
+    lg, _ = pifu.eval_points(fg, pts, guard_logit=0.0)
+    ref = O.field_logit(fo, pts)
+    err = np.max(np.abs(lg.cpu().numpy() - ref))
+    print(f"max |logit32 - logit64| = {err:.3e} over {pts.shape[0]} points")
+    assert err <= 1e-3 / 10, err
+
+
 def test_eval_points_ellipsoids(pifu):
     ell = synth.ellipsoids(8, 302)
     fo = O.Field("ellipsoids", ell=ell, sharpness=8.0)
