@@ -520,3 +520,35 @@ void launch_fill_image(float* rgb, float* depth, uint8_t* hit, uint32_t npix, fl
 }
 
 }  // namespace pifu
+
+namespace pifu {
+
+__global__ void k_gather_u32(const uint32_t* __restrict__ src, const uint32_t* __restrict__ pos,
+                             uint32_t n, uint32_t* __restrict__ out) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = src[pos[i]];
+}
+
+void launch_gather_u32(const uint32_t* src, const uint32_t* pos, uint32_t n, uint32_t* out,
+                       hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_gather_u32, dim3(grid1d(n, 256)), dim3(256), 0, s, src, pos, n, out);
+}
+
+__global__ void k_scatter_results(const uint32_t* __restrict__ pos, uint32_t n,
+                                  const float* __restrict__ tl, const uint8_t* __restrict__ tb,
+                                  float* __restrict__ logit, uint8_t* __restrict__ lab) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t p = pos[i];
+  logit[p] = tl[i];
+  lab[p] = tb[i];
+}
+
+void launch_scatter_results(const uint32_t* pos, uint32_t n, const float* tl, const uint8_t* tb,
+                            float* logit, uint8_t* lab, hipStream_t s) {
+  if (n)
+    hipLaunchKernelGGL(k_scatter_results, dim3(grid1d(n, 256)), dim3(256), 0, s, pos, n, tl, tb,
+                       logit, lab);
+}
+
+}  // namespace pifu

@@ -115,8 +115,8 @@ struct Gemm64Args {
 
 // 64 x 64 output tile, 4 waves of 32 x 32 (2 x 2 blocks of v_mfma_f64_16x16x4f64).
 // Lane group g = lane/16 feeds the k values [4g, 4g+4) of each 16-wide k step
-// (same permutation for A and B).  Output block layout: lane l, register r holds
-// row 4*(l/16) + r, column l%16.
+// (same permutation for A and B).  Output block layout (checked on gfx950 with a
+// lane probe): lane l, register r holds row 4*r + l/16, column l%16.
 __global__ void __launch_bounds__(256) k_gemm64(Gemm64Args a) {
   constexpr int BM = 64, BN = 64, BK = 16, LD = BK + 2;
   __shared__ __attribute__((aligned(16))) double As[BM * LD];
@@ -183,7 +183,7 @@ __global__ void __launch_bounds__(256) k_gemm64(Gemm64Args a) {
       if (a.n_ext > 1) we1 = a.Wf[(size_t)col * a.ldwf + a.ext_col + 1];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm * 32 + 16 * i + 4 * g + r;
+        const int row = m0 + wm * 32 + 16 * i + 4 * r + g;
         if (row >= a.M) continue;
         double v = acc[i][j][r] + bias;
         if (a.n_ext > 0) v += a.ext[4 * (size_t)row] * we0;

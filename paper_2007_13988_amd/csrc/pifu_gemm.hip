@@ -300,6 +300,21 @@ int launch_gemm(const GemmArgs& a, int precision, int tile_m, hipStream_t s) {
       hipLaunchKernelGGL((k_gemm_f32<128, 64, 4, 1>), dim3(gx, gy), dim3(256), 0, s, a);
     return 0;
   }
+  if (precision == PIFU_PREC_BF16) {
+    if ((a.K1 % 64) || (a.K2 % 64)) return -1;
+    if (bn128) {
+      if (a.c_bf16)
+        hipLaunchKernelGGL((k_gemm_bf16<128, 128, 2, 2, true>), dim3(gx, gy), dim3(256), 0, s, a);
+      else
+        hipLaunchKernelGGL((k_gemm_bf16<128, 128, 2, 2, false>), dim3(gx, gy), dim3(256), 0, s, a);
+    } else {
+      if (a.c_bf16)
+        hipLaunchKernelGGL((k_gemm_bf16<128, 64, 4, 1, true>), dim3(gx, gy), dim3(256), 0, s, a);
+      else
+        hipLaunchKernelGGL((k_gemm_bf16<128, 64, 4, 1, false>), dim3(gx, gy), dim3(256), 0, s, a);
+    }
+    return 0;
+  }
   return -1;
 }
 

@@ -140,17 +140,19 @@ int validate_field(const pifu_field* f, int n_extra, int n_out) {
 }
 
 int validate_precision(int p) {
-  if (p == PIFU_PREC_FP32) return PIFU_OK;
-  if (p == PIFU_PREC_BF16 || p == PIFU_PREC_FP8) return PIFU_ERR_UNSUPPORTED;
+  if (p == PIFU_PREC_FP32 || p == PIFU_PREC_BF16) return PIFU_OK;
+  if (p == PIFU_PREC_FP8) return PIFU_ERR_UNSUPPORTED;
   return PIFU_ERR_INVALID_ARGUMENT;
 }
 
 // ------------------------------------------------------------------ MLP preparation
 struct MlpPrep {
   MLPDesc d;
-  void* Wp[PIFU_MAX_LAYERS];
+  float* Wp32[PIFU_MAX_LAYERS];      // FP32 operand copies [N][Kp]
+  uint16_t* Wp16[PIFU_MAX_LAYERS];   // BF16 operand copies (BF16/FP8 runs)
   int Kp[PIFU_MAX_LAYERS];
   int max_hidden;
+  int prec;
 };
 
 void describe_mlp(const pifu_mlp* m, MLPDesc& d) {
@@ -170,22 +172,27 @@ void describe_mlp(const pifu_mlp* m, MLPDesc& d) {
   }
 }
 
-// Carves (and, when launch is set, fills) the packed operand copies of the hidden layers.
+// Carves the packed operand copies of the hidden layers: one in the run precision
+// and, for BF16/FP8 runs, an FP32 copy for the threshold-band re-evaluation.
 void carve_mlp(Carver& cv, const pifu_mlp* m, int precision, MlpPrep& p) {
   describe_mlp(m, p.d);
   p.max_hidden = 0;
-  const size_t esz = precision == PIFU_PREC_FP32 ? 4 : 2;
+  p.prec = precision;
   for (int l = 0; l + 1 < m->n_layers; ++l) {
     p.Kp[l] = l == 0 ? m->feat_dim : p.d.in_w[l];
-    p.Wp[l] = cv.take<char>((size_t)m->widths[l] * p.Kp[l] * esz);
+    const size_t n = (size_t)m->widths[l] * p.Kp[l];
+    p.Wp32[l] = cv.take<float>(n);
+    p.Wp16[l] = precision != PIFU_PREC_FP32 ? cv.take<uint16_t>(n) : nullptr;
     p.max_hidden = std::max(p.max_hidden, m->widths[l]);
   }
 }
 
-void pack_mlp(const MlpPrep& p, int precision, hipStream_t s) {
-  for (int l = 0; l + 1 < p.d.n_layers; ++l)
-    launch_pack_weights(p.d.W[l], p.d.widths[l], p.d.in_w[l], p.Kp[l], p.Wp[l],
-                        precision != PIFU_PREC_FP32, s);
+void pack_mlp(const MlpPrep& p, hipStream_t s) {
+  for (int l = 0; l + 1 < p.d.n_layers; ++l) {
+    launch_pack_weights(p.d.W[l], p.d.widths[l], p.d.in_w[l], p.Kp[l], p.Wp32[l], 0, s);
+    if (p.Wp16[l])
+      launch_pack_weights(p.d.W[l], p.d.widths[l], p.d.in_w[l], p.Kp[l], p.Wp16[l], 1, s);
+  }
 }
 
 // ------------------------------------------------------------------ evaluator
@@ -196,24 +203,32 @@ struct EvalWs {
   void* hA = nullptr;
   void* hB = nullptr;
   uint32_t* glist = nullptr;
-  uint32_t* iota = nullptr;
   void* g64 = nullptr;       // float64 guard-band evaluation scratch
   uint32_t chunk64 = 0;
+  // re-evaluation of a subset (band: FP32 re-run; sur: surrogate fallback)
+  uint32_t *band_pos = nullptr, *band_nodes = nullptr;
+  float* band_logit = nullptr;
+  uint8_t* band_lab = nullptr;
+  uint32_t *sur_pos = nullptr, *sur_nodes = nullptr;
+  float* sur_logit = nullptr;
+  uint8_t* sur_lab = nullptr;
 };
 
 struct FieldPrep {
   const pifu_field* f = nullptr;
-  MlpPrep mlp;
-  bool has_mlp = false;
+  MlpPrep mlp, sur;
+  bool has_mlp = false, has_sur = false;
   Ellipsoids ell;
 };
 
 void carve_field(Carver& cv, const pifu_field* f, int precision, FieldPrep& fp) {
   fp.f = f;
   fp.has_mlp = f->kind == PIFU_FIELD_MLP;
+  fp.has_sur = fp.has_mlp && f->surrogate != nullptr;
   std::memset(&fp.ell, 0, sizeof(fp.ell));
   if (fp.has_mlp) {
     carve_mlp(cv, f->mlp, precision, fp.mlp);
+    if (fp.has_sur) carve_mlp(cv, f->surrogate, PIFU_PREC_BF16, fp.sur);
   } else if (f->kind == PIFU_FIELD_ELLIPSOIDS) {
     fp.ell.n = f->n_ell;
     fp.ell.k = f->sharpness;
@@ -221,10 +236,26 @@ void carve_field(Carver& cv, const pifu_field* f, int precision, FieldPrep& fp) 
   }
 }
 
+void pack_field(const FieldPrep& fp, hipStream_t s) {
+  if (fp.has_mlp) pack_mlp(fp.mlp, s);
+  if (fp.has_sur) pack_mlp(fp.sur, s);
+}
+
 void carve_guard(Carver& cv, const FieldPrep& fp, uint32_t max_points, EvalWs& ew) {
   if (!fp.has_mlp) return;
   ew.chunk64 = std::max<uint32_t>(64, std::min<uint32_t>(16384, max_points));
   ew.g64 = cv.take<char>(guard64_ws_bytes(fp.mlp.d, ew.chunk64));
+  const size_t n = std::max<uint32_t>(max_points, 1);
+  ew.band_pos = cv.take<uint32_t>(n);
+  ew.band_nodes = cv.take<uint32_t>(n);
+  ew.band_logit = cv.take<float>(n);
+  ew.band_lab = cv.take<uint8_t>(n);
+  if (fp.has_sur) {
+    ew.sur_pos = cv.take<uint32_t>(n);
+    ew.sur_nodes = cv.take<uint32_t>(n);
+    ew.sur_logit = cv.take<float>(n);
+    ew.sur_lab = cv.take<uint8_t>(n);
+  }
 }
 
 void carve_eval(Carver& cv, uint32_t max_points, int C, int max_hidden, EvalWs& ew) {
@@ -242,7 +273,9 @@ struct EvalCtx {
   hipStream_t s;
   uint32_t* counters;     // device
   int precision;
-  float guard;
+  float guard;            // |logit| below which FP32 results are re-run in FP64
+  float band = 0.f;       // |logit| below which BF16/FP8 results are re-run in FP32
+  float sur_band = 0.f;   // |logit| below which surrogate results go to the full MLP
 };
 
 int read_counters(EvalCtx& e, int nwords) {
@@ -252,19 +285,28 @@ int read_counters(EvalCtx& e, int nwords) {
   return PIFU_OK;
 }
 
-// Runs the MLP over n points (chunked): gather -> hidden GEMMs -> head.
-int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, const PointSrc& src,
+// |p - 0.5| < delta  <=>  |logit| < log((0.5 + delta) / (0.5 - delta)).
+float logit_band(float delta) {
+  if (!(delta > 0.f)) return 0.f;
+  if (delta >= 0.5f) return INFINITY;
+  return (float)std::log((0.5 + (double)delta) / (0.5 - (double)delta));
+}
+
+// Runs an MLP over n points (chunked): gather -> hidden GEMMs -> head.  prec selects
+// the MFMA operand type of the hidden layers.
+int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const PointSrc& src,
             const uint32_t* list, uint32_t n, const EvalWs& ew, float* logit, uint8_t* lab,
-            float* rgb, uint32_t* guard_count) {
+            float* rgb) {
   const pifu_field* f = fp.f;
   const MLPDesc& d = mp.d;
   const int C = f->C;
+  const bool b16 = prec != PIFU_PREC_FP32;
   for (uint32_t c0 = 0; c0 < n; c0 += ew.chunk) {
     const uint32_t m = std::min(ew.chunk, n - c0);
     const uint32_t* lst = list + c0;
     {
-      ProfScope ps(e.ctx, e.s, PIFU_KERN_GATHER, 0.0, (double)m * (20.0 * C + 20.0));
-      launch_gather(src, lst, m, f->feat, f->H, f->W, C, ew.feat, 0, ew.ext, e.s);
+      ProfScope ps(e.ctx, e.s, PIFU_KERN_GATHER, 0.0, (double)m * (16.0 * C + (b16 ? 2 : 4) * C + 20.0));
+      launch_gather(src, lst, m, f->feat, f->H, f->W, C, ew.feat, b16, ew.ext, e.s);
     }
     const void* prev = nullptr;
     void* out = ew.hA;
@@ -287,7 +329,7 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, const PointSrc& 
           g.lda2 = C;
         }
       }
-      g.W = mp.Wp[l];
+      g.W = b16 ? (const void*)mp.Wp16[l] : (const void*)mp.Wp32[l];
       g.ldw = mp.Kp[l];
       g.Wf = d.W[l];
       g.ldwf = d.in_w[l];
@@ -299,12 +341,13 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, const PointSrc& 
       g.N = d.widths[l];
       g.act = d.hidden_act;
       g.scale = 1.f;
+      g.c_bf16 = b16 && (l + 2 < d.n_layers);   // the head reads FP32
       {
-        const int kind = e.precision == PIFU_PREC_FP32   ? PIFU_KERN_GEMM_F32
-                         : e.precision == PIFU_PREC_BF16 ? PIFU_KERN_GEMM_BF16
-                                                         : PIFU_KERN_GEMM_FP8;
+        const int kind = prec == PIFU_PREC_FP32   ? PIFU_KERN_GEMM_F32
+                         : prec == PIFU_PREC_BF16 ? PIFU_KERN_GEMM_BF16
+                                                  : PIFU_KERN_GEMM_FP8;
         ProfScope ps(e.ctx, e.s, kind, 2.0 * m * g.N * (g.K1 + g.K2 + g.n_ext), 0.0);
-        if (launch_gemm(g, e.precision, 0, e.s)) return PIFU_ERR_UNSUPPORTED;
+        if (launch_gemm(g, prec, 0, e.s)) return PIFU_ERR_UNSUPPORTED;
       }
       prev = out;
       out = (out == ew.hA) ? ew.hB : ew.hA;
@@ -315,38 +358,81 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, const PointSrc& 
                 d.out_act, m, ew.ext, logit ? logit + c0 : nullptr, lab ? lab + c0 : nullptr, rgb,
                 rgb ? lst : nullptr, e.s);
   }
+  return check_launch();
+}
+
+// Positions m < n with |logit[m]| < bound (any order) and their count.
+int select_near(EvalCtx& e, const float* logit, uint32_t n, float bound, uint32_t* pos,
+                uint32_t* count) {
+  *count = 0;
+  if (!(bound > 0.f) || !n) return PIFU_OK;
+  HIP_TRY(hipMemsetAsync(e.counters + C_GUARD, 0, 4, e.s));
+  launch_guard_select(logit, n, bound, pos, e.counters + C_GUARD, e.s);
   int r = check_launch();
   if (r) return r;
-  if (guard_count) *guard_count = 0;
-  if (logit && e.guard > 0.f && n) {
-    HIP_TRY(hipMemsetAsync(e.counters + C_GUARD, 0, 4, e.s));
-    launch_guard_select(logit, n, e.guard, ew.glist, e.counters + C_GUARD, e.s);
-    r = read_counters(e, C_GUARD + 1);
+  r = read_counters(e, C_GUARD + 1);
+  if (r) return r;
+  *count = e.ctx->host_counters[C_GUARD];
+  return PIFU_OK;
+}
+
+// Full-network evaluation: run precision, then the FP32 band, then the FP64 guard.
+int eval_full(EvalCtx& e, const FieldPrep& fp, const PointSrc& src, const uint32_t* list,
+              uint32_t n, const EvalWs& ew, float* logit, uint8_t* lab, pifu_level_stats* st) {
+  const pifu_field* f = fp.f;
+  int r = run_mlp(e, fp, fp.mlp, e.precision, src, list, n, ew, logit, lab, nullptr);
+  if (r) return r;
+  if (st) st->mlp_points += n;
+  if (e.precision != PIFU_PREC_FP32 && e.band > 0.f) {
+    uint32_t nb = 0;
+    r = select_near(e, logit, n, e.band, ew.band_pos, &nb);
     if (r) return r;
-    const uint32_t gn = e.ctx->host_counters[C_GUARD];
-    if (guard_count) *guard_count = gn;
-    run_guard64(src, list, ew.glist, gn, d, f->feat, f->H, f->W, C, logit, lab, ew.g64, ew.chunk64,
-                e.s);
+    if (nb) {
+      launch_gather_u32(list, ew.band_pos, nb, ew.band_nodes, e.s);
+      r = run_mlp(e, fp, fp.mlp, PIFU_PREC_FP32, src, ew.band_nodes, nb, ew, ew.band_logit,
+                  ew.band_lab, nullptr);
+      if (r) return r;
+      launch_scatter_results(ew.band_pos, nb, ew.band_logit, ew.band_lab, logit, lab, e.s);
+      if (st) st->band_fp32 += nb;
+    }
+  }
+  if (e.guard > 0.f) {
+    uint32_t gn = 0;
+    r = select_near(e, logit, n, e.guard, ew.glist, &gn);
+    if (r) return r;
+    run_guard64(src, list, ew.glist, gn, fp.mlp.d, f->feat, f->H, f->W, f->C, logit, lab, ew.g64,
+                ew.chunk64, e.s);
+    if (st) st->guard_fp64 += gn;
     r = check_launch();
   }
   return r;
 }
 
-// Evaluates the occupancy field at n points; fills logit and label per point.
+// Evaluates the occupancy field at n points; fills logit and label per point.  With
+// use_surrogate, the surrogate network (BF16) runs first and the points whose
+// surrogate occupancy lies within the fallback band of 0.5 go to the full network.
 int eval_occupancy(EvalCtx& e, const FieldPrep& fp, const PointSrc& src, const uint32_t* list,
-                   uint32_t n, const EvalWs& ew, float* logit, uint8_t* lab, pifu_level_stats* st) {
+                   uint32_t n, const EvalWs& ew, float* logit, uint8_t* lab, pifu_level_stats* st,
+                   bool use_surrogate = false) {
   if (!n) return PIFU_OK;
   if (!fp.has_mlp) {
     launch_eval_analytic(src, list, n, fp.f->kind, fp.ell, fp.f->plane, logit, lab, e.s);
     return check_launch();
   }
-  uint32_t gn = 0;
-  int r = run_mlp(e, fp, fp.mlp, src, list, n, ew, logit, lab, nullptr, &gn);
-  if (st) {
-    st->mlp_points += n;
-    st->guard_fp64 += gn;
+  if (!(use_surrogate && fp.has_sur)) return eval_full(e, fp, src, list, n, ew, logit, lab, st);
+  int r = run_mlp(e, fp, fp.sur, PIFU_PREC_BF16, src, list, n, ew, logit, lab, nullptr);
+  if (r) return r;
+  uint32_t ns = 0;
+  r = select_near(e, logit, n, e.sur_band, ew.sur_pos, &ns);
+  if (r) return r;
+  if (ns) {
+    launch_gather_u32(list, ew.sur_pos, ns, ew.sur_nodes, e.s);
+    r = eval_full(e, fp, src, ew.sur_nodes, ns, ew, ew.sur_logit, ew.sur_lab, st);
+    if (r) return r;
+    launch_scatter_results(ew.sur_pos, ns, ew.sur_logit, ew.sur_lab, logit, lab, e.s);
   }
-  return r;
+  if (st) st->surrogate_fallback += ns;
+  return check_launch();
 }
 
 // ------------------------------------------------------------------ localization
@@ -386,7 +472,8 @@ int compact_count(EvalCtx& e, const uint8_t* st, size_t n, uint8_t mask, uint8_t
 // Levels 0..last of the hierarchy (level T is the finest lattice of `fin_log2`).
 int localize(EvalCtx& e, const FieldPrep& fp, const EvalWs& ew, const double* view,
              const int fin_log2[3], int T, int last, LevelBuf* lv, const LocalizeWs& w,
-             uint8_t* eval_level, Lat eval_lat, int max_waves, pifu_level_stats* stats) {
+             uint8_t* eval_level, Lat eval_lat, int max_waves, int sur_max_log2,
+             pifu_level_stats* stats) {
   PointSrc src;
   std::memset(&src, 0, sizeof(src));
   src.mode = 0;
@@ -410,7 +497,8 @@ int localize(EvalCtx& e, const FieldPrep& fp, const EvalWs& ew, const double* vi
       // coarsest level: every node is evaluated
       launch_fill_u8(L.st, 0, n_nodes, e.s);
       launch_iota(w.list, n_nodes, e.s);
-      int r = eval_occupancy(e, fp, src, w.list, n_nodes, ew, w.logit, w.lab, &st);
+      int r = eval_occupancy(e, fp, src, w.list, n_nodes, ew, w.logit, w.lab, &st,
+                             L.level_id <= sur_max_log2);
       if (r) return r;
       launch_apply_grid(w.list, n_nodes, w.logit, w.lab, L.st, L.occ, nullptr, eval_level,
                         L.level_id, L.lat, stride, eval_lat, 0, e.s);
@@ -428,7 +516,8 @@ int localize(EvalCtx& e, const FieldPrep& fp, const EvalWs& ew, const double* vi
       st.dilated = n;
       int waves = 0;
       while (n) {
-        r = eval_occupancy(e, fp, src, w.list, n, ew, w.logit, w.lab, &st);
+        r = eval_occupancy(e, fp, src, w.list, n, ew, w.logit, w.lab, &st,
+                           L.level_id <= sur_max_log2);
         if (r) return r;
         launch_apply_grid(w.list, n, w.logit, w.lab, L.st, L.occ, e.counters + C_CONFLICTS,
                           eval_level, L.level_id, L.lat, stride, eval_lat, 1, e.s);
@@ -661,11 +750,13 @@ int32_t pifu_occupancy_grid(pifu_ctx* ctx, const pifu_field* field, const pifu_g
   plan_grid(field, opts, base, occ, g);
   hipStream_t s = as_stream(stream);
   EvalCtx e{ctx, s, g.counters, opts->precision, opts->guard_logit};
-  if (g.fp.has_mlp) pack_mlp(g.fp.mlp, opts->precision, s);
+  e.band = logit_band(opts->band_delta);
+  e.sur_band = logit_band(opts->surrogate_delta);
+  pack_field(g.fp, s);
   const Lat fin = g.lv[g.T].lat;
   if (eval_level) launch_fill_u8(eval_level, 255, fin.n(), s);
   r = localize(e, g.fp, g.ew, nullptr, g.log2, g.T, g.T, g.lv, g.w, eval_level, fin,
-               opts->max_waves, stats);
+               opts->max_waves, opts->surrogate_max_log2, stats);
   if (!r) {
     launch_cells(g.lv[g.T].st, fin, labels, s);
     uint32_t nc = 0;
@@ -712,15 +803,17 @@ int32_t pifu_render_view(pifu_ctx* ctx, const pifu_field* occ_field, const pifu_
   plan_render(occ_field, color_field, opts, base, g);
   hipStream_t s = as_stream(stream);
   EvalCtx e{ctx, s, g.counters, opts->precision, opts->guard_logit};
-  if (g.fp.has_mlp) pack_mlp(g.fp.mlp, opts->precision, s);
-  pack_mlp(g.cp.mlp, PIFU_PREC_FP32, s);
+  e.band = logit_band(opts->band_delta);
+  e.sur_band = logit_band(opts->surrogate_delta);
+  pack_field(g.fp, s);
+  pack_field(g.cp, s);
   double vd[12];
   for (int i = 0; i < 12; ++i) vd[i] = view[i];
   const int T = g.T;
   const int W = 1 << opts->log2_w, H = W, D = 1 << opts->log2_d;
   const Lat finL = level_lattice(g.log2, T, T);
   r = localize(e, g.fp, g.ew, vd, g.log2, T, T - 1, g.lv, g.w, nullptr, finL, opts->max_waves,
-               stats);
+               opts->surrogate_max_log2, stats);
   if (r) {
     delete gp;
     return r;
@@ -750,7 +843,8 @@ int32_t pifu_render_view(pifu_ctx* ctx, const pifu_field* occ_field, const pifu_
     src.nz = finL.nz;
     src.has_view = 1;
     for (int i = 0; i < 12; ++i) src.view[i] = vd[i];
-    r = eval_occupancy(e, g.fp, src, g.w.list, nT, g.ew, g.w.logit, g.w.lab, &st);
+    r = eval_occupancy(e, g.fp, src, g.w.list, nT, g.ew, g.w.logit, g.w.lab, &st,
+                       opts->log2_w <= opts->surrogate_max_log2);
     st.dilated = nT;
     st.evaluated = nT;
   }
@@ -768,7 +862,8 @@ int32_t pifu_render_view(pifu_ctx* ctx, const pifu_field* occ_field, const pifu_
       ps.mode = 1;
       ps.pts = g.hitpts;
       EvalCtx ec{ctx, s, g.counters, PIFU_PREC_FP32, 0.f};
-      r = run_mlp(ec, g.cp, g.cp.mlp, ps, g.hitlist, nh, g.ew, nullptr, nullptr, rgb, nullptr);
+      r = run_mlp(ec, g.cp, g.cp.mlp, PIFU_PREC_FP32, ps, g.hitlist, nh, g.ew, nullptr, nullptr,
+                  rgb);
     }
   }
   if (!r) r = check_launch();
@@ -803,7 +898,6 @@ int32_t pifu_eval_points(pifu_ctx* ctx, const pifu_field* field, int32_t precisi
                          float band_delta, float guard_logit, const float* pts, uint32_t n,
                          float* logit, uint8_t* labels, void* workspace, size_t workspace_bytes,
                          pifu_stream stream) {
-  (void)band_delta;
   if (!ctx || !pts || !logit || !workspace) return PIFU_ERR_INVALID_ARGUMENT;
   if (!aligned(pts, 16) || !aligned(workspace, kAlign)) return PIFU_ERR_INVALID_ARGUMENT;
   size_t need = 0;
@@ -824,7 +918,8 @@ int32_t pifu_eval_points(pifu_ctx* ctx, const pifu_field* field, int32_t precisi
   uint8_t* lab = labels;
   if (!lab) lab = reinterpret_cast<uint8_t*>(ew.glist);   // scratch when labels are not wanted
   EvalCtx e{ctx, s, counters, precision, guard_logit};
-  if (fp.has_mlp) pack_mlp(fp.mlp, precision, s);
+  e.band = logit_band(band_delta);
+  pack_field(fp, s);
   launch_iota(iota, n, s);
   PointSrc src;
   std::memset(&src, 0, sizeof(src));

@@ -99,6 +99,12 @@ void launch_guard_select(const float* logit, uint32_t n, float g, uint32_t* glis
 void launch_guard_fp64(const PointSrc& src, const uint32_t* list, const uint32_t* glist,
                        uint32_t gn, const MLPDesc& mlp, const float* F, int H, int W, int C,
                        float* logit, uint8_t* lab, hipStream_t s);
+// out[i] = src[pos[i]]
+void launch_gather_u32(const uint32_t* src, const uint32_t* pos, uint32_t n, uint32_t* out,
+                       hipStream_t s);
+// logit[pos[i]] = tl[i], lab[pos[i]] = tb[i]
+void launch_scatter_results(const uint32_t* pos, uint32_t n, const float* tl, const uint8_t* tb,
+                            float* logit, uint8_t* lab, hipStream_t s);
 size_t guard64_ws_bytes(const MLPDesc& d, uint32_t chunk);
 void run_guard64(const PointSrc& src, const uint32_t* list, const uint32_t* glist, uint32_t gn,
                  const MLPDesc& d, const float* F, int H, int W, int C, float* logit, uint8_t* lab,
@@ -140,6 +146,7 @@ struct GemmArgs {
   int M, N;
   int act;
   float scale;       // FP8: product of operand scales (dequantization), else 1
+  int c_bf16;        // BF16/FP8 paths: write C as bf16 (next layer's input), else fp32
 };
 int launch_gemm(const GemmArgs& a, int precision, int tile_m, hipStream_t s);
 void launch_pack_weights(const float* W, int N, int ldw_src, int K, void* dst, int bf16,
