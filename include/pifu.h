@@ -248,6 +248,35 @@ int32_t pifu_eval_points(pifu_ctx* ctx, const pifu_field* field, int32_t precisi
                          float* logit, uint8_t* labels, void* workspace, size_t workspace_bytes,
                          pifu_stream stream);
 
+/* ---------------------------------------------------------------- surrogate training */
+
+/* Bytes of workspace pifu_mlp_grad needs for batches of up to max_batch points. */
+int32_t pifu_mlp_train_workspace_size(const pifu_field* field, uint32_t max_batch, size_t* bytes);
+
+/*
+ * Gradient of the mean soft-target binary cross entropy (the occupancy loss of
+ * Sec. 3.1, with soft teacher targets) of field->mlp over a batch:
+ *   loss = mean_m [softplus(s_m) - t_m s_m],  s_m = logit of point m.
+ * field: PIFU_FIELD_MLP (feat = the frame's feature map, mlp = the network being
+ * trained, float32 weights).  pts: device float32 n x 4 (x, y, z in input NDC,
+ * teacher occupancy t in [0,1]).  dW[l], db[l]: device float32 outputs shaped like
+ * mlp->W[l], mlp->b[l].  loss: device float (nullable).  Reductions over the batch
+ * run in a fixed order, so results are bit-reproducible.  Asynchronous on stream.
+ */
+int32_t pifu_mlp_grad(pifu_ctx* ctx, const pifu_field* field, const float* pts, uint32_t n,
+                      float* const* dW, float* const* db, float* loss, void* workspace,
+                      size_t workspace_bytes, pifu_stream stream);
+
+/*
+ * One RMSProp step on every parameter of net (the optimizer the paper trains the
+ * shape network with, appendix A1.2):  v = alpha v + (1 - alpha) g^2,
+ * w -= lr g / (sqrt(v) + eps).  net->W / net->b are updated in place (device);
+ * vW / vb hold the running averages (device, zero-initialised by the caller).
+ */
+int32_t pifu_rmsprop_step(pifu_ctx* ctx, const pifu_mlp* net, const float* const* dW,
+                          const float* const* db, float* const* vW, float* const* vb, float lr,
+                          float alpha, float eps, pifu_stream stream);
+
 /* ---------------------------------------------------------------- kernel profiling */
 
 /* Kernel families timed by the built-in profiler (index into pifu_profile_read's array). */

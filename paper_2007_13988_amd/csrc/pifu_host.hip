@@ -948,3 +948,175 @@ int32_t pifu_profile_read(pifu_ctx* ctx, pifu_kernel_profile* out) {
 }
 
 }  // extern "C"
+
+// ================================================================== surrogate training
+namespace {
+
+struct TrainWs {
+  MlpPrep mp;
+  float* feat;
+  float* ext;
+  float* H[PIFU_MAX_LAYERS];
+  float* s;
+  uint8_t* lab;
+  float* g;
+  float* dA;
+  float* dB;
+  float* part;
+  float* loss_part;
+  size_t bytes;
+};
+
+void plan_train(const pifu_field* f, uint32_t n, void* base, TrainWs& t) {
+  Carver cv(base);
+  carve_mlp(cv, f->mlp, PIFU_PREC_FP32, t.mp);
+  const MLPDesc& d = t.mp.d;
+  const size_t N = std::max<uint32_t>(n, 1);
+  t.feat = cv.take<float>(N * f->C);
+  t.ext = cv.take<float>(N * 4);
+  size_t maxpart = 0;
+  int maxw = 1;
+  for (int l = 0; l < d.n_layers; ++l) {
+    t.H[l] = l + 1 < d.n_layers ? cv.take<float>(N * d.widths[l]) : nullptr;
+    maxpart = std::max(maxpart, weight_grad_part_floats(d.widths[l], d.in_w[l], (uint32_t)N));
+    if (l + 1 < d.n_layers) maxw = std::max(maxw, d.widths[l]);
+  }
+  t.s = cv.take<float>(N);
+  t.lab = cv.take<uint8_t>(N);
+  t.g = cv.take<float>(N);
+  t.dA = cv.take<float>(N * maxw);
+  t.dB = cv.take<float>(N * maxw);
+  t.part = cv.take<float>(maxpart);
+  t.loss_part = cv.take<float>(bce_partials((uint32_t)N) + 1);
+  t.bytes = cv.off + kAlign;
+}
+
+int validate_train_field(const pifu_field* f) {
+  if (!f || f->kind != PIFU_FIELD_MLP) return PIFU_ERR_INVALID_ARGUMENT;
+  int r = validate_field(f, 1, 1);
+  if (r) return r;
+  const pifu_mlp* m = f->mlp;
+  for (int l = 0; l + 1 < m->n_layers; ++l)
+    if (m->hidden_act != PIFU_ACT_RELU && m->hidden_act != PIFU_ACT_LRELU) return PIFU_ERR_INVALID_ARGUMENT;
+  return PIFU_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t pifu_mlp_train_workspace_size(const pifu_field* field, uint32_t max_batch, size_t* bytes) {
+  if (!bytes) return PIFU_ERR_INVALID_ARGUMENT;
+  int r = validate_train_field(field);
+  if (r) return r;
+  TrainWs t;
+  plan_train(field, max_batch, nullptr, t);
+  *bytes = t.bytes;
+  return PIFU_OK;
+}
+
+int32_t pifu_mlp_grad(pifu_ctx* ctx, const pifu_field* field, const float* pts, uint32_t n,
+                      float* const* dW, float* const* db, float* loss, void* workspace,
+                      size_t workspace_bytes, pifu_stream stream) {
+  if (!ctx || !pts || !dW || !db || !workspace || n == 0) return PIFU_ERR_INVALID_ARGUMENT;
+  if (!aligned(pts, 16) || !aligned(workspace, kAlign)) return PIFU_ERR_INVALID_ARGUMENT;
+  int r = validate_train_field(field);
+  if (r) return r;
+  TrainWs t;
+  plan_train(field, n, nullptr, t);
+  if (workspace_bytes < t.bytes) return PIFU_ERR_WORKSPACE_TOO_SMALL;
+  plan_train(field, n, workspace, t);
+  const MLPDesc& d = t.mp.d;
+  for (int l = 0; l < d.n_layers; ++l)
+    if (!dW[l] || !db[l]) return PIFU_ERR_INVALID_ARGUMENT;
+  hipStream_t s = as_stream(stream);
+  pack_mlp(t.mp, s);
+  const int C = field->C;
+  PointSrc src;
+  std::memset(&src, 0, sizeof(src));
+  src.mode = 1;
+  src.pts = reinterpret_cast<const float4*>(pts);
+  // forward, keeping every hidden activation
+  launch_gather(src, nullptr, n, field->feat, field->H, field->W, C, t.feat, 0, t.ext, s);
+  for (int l = 0; l + 1 < d.n_layers; ++l) {
+    GemmArgs g;
+    std::memset(&g, 0, sizeof(g));
+    if (l == 0) {
+      g.A1 = t.feat;
+      g.K1 = C;
+      g.lda1 = C;
+      g.n_ext = d.n_extra;
+      g.ext_col = C;
+    } else {
+      g.A1 = t.H[l - 1];
+      g.K1 = d.widths[l - 1];
+      g.lda1 = d.widths[l - 1];
+      if (d.skip[l]) {
+        g.A2 = t.feat;
+        g.K2 = C;
+        g.lda2 = C;
+      }
+    }
+    g.W = t.mp.Wp32[l];
+    g.ldw = t.mp.Kp[l];
+    g.Wf = d.W[l];
+    g.ldwf = d.in_w[l];
+    g.bias = d.b[l];
+    g.ext = t.ext;
+    g.C = t.H[l];
+    g.ldc = d.widths[l];
+    g.M = (int)n;
+    g.N = d.widths[l];
+    g.act = d.hidden_act;
+    g.scale = 1.f;
+    if (launch_gemm(g, PIFU_PREC_FP32, 0, s)) return PIFU_ERR_UNSUPPORTED;
+  }
+  const int L = d.n_layers - 1;
+  launch_head(t.H[L - 1], d.widths[L - 1], d.W[L], d.b[L], 1, d.out_act, n, t.ext, t.s, t.lab,
+              nullptr, nullptr, s);
+  // loss and dloss/dlogit
+  launch_bce_grad(t.s, src.pts, n, t.g, t.loss_part, loss, s);
+  // backward
+  const float* G = t.g;
+  int Ng = 1;
+  float* bufs[2] = {t.dA, t.dB};
+  int which = 0;
+  for (int l = L; l >= 0; --l) {
+    if (l == 0) {
+      launch_weight_grad(G, Ng, t.feat, C, C, nullptr, 0, 0, t.ext, d.n_extra, n, t.part, dW[l],
+                         db[l], s);
+    } else {
+      launch_weight_grad(G, Ng, t.H[l - 1], d.widths[l - 1], d.widths[l - 1],
+                         d.skip[l] ? t.feat : nullptr, d.skip[l] ? C : 0, C, nullptr, 0, n,
+                         t.part, dW[l], db[l], s);
+      float* dH = bufs[which];
+      which ^= 1;
+      launch_backprop_input(G, Ng, d.W[l], d.in_w[l], t.H[l - 1], d.widths[l - 1], n,
+                            d.hidden_act, dH, s);
+      G = dH;
+      Ng = d.widths[l - 1];
+    }
+  }
+  r = check_launch();
+  return r;
+}
+
+int32_t pifu_rmsprop_step(pifu_ctx* ctx, const pifu_mlp* net, const float* const* dW,
+                          const float* const* db, float* const* vW, float* const* vb, float lr,
+                          float alpha, float eps, pifu_stream stream) {
+  if (!ctx || !net || !dW || !db || !vW || !vb) return PIFU_ERR_INVALID_ARGUMENT;
+  if (net->n_layers < 1 || net->n_layers > PIFU_MAX_LAYERS) return PIFU_ERR_INVALID_ARGUMENT;
+  MLPDesc d;
+  describe_mlp(net, d);
+  hipStream_t s = as_stream(stream);
+  for (int l = 0; l < d.n_layers; ++l) {
+    if (!dW[l] || !db[l] || !vW[l] || !vb[l] || !d.W[l] || !d.b[l]) return PIFU_ERR_INVALID_ARGUMENT;
+    // the network's parameters are updated in place
+    launch_rmsprop(const_cast<float*>(d.W[l]), dW[l], vW[l], (size_t)d.widths[l] * d.in_w[l], lr,
+                   alpha, eps, s);
+    launch_rmsprop(const_cast<float*>(d.b[l]), db[l], vb[l], (size_t)d.widths[l], lr, alpha, eps, s);
+  }
+  return check_launch();
+}
+
+}  // extern "C"

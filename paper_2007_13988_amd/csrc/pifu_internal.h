@@ -153,3 +153,18 @@ void launch_pack_weights(const float* W, int N, int ldw_src, int K, void* dst, i
                          hipStream_t s);
 
 }  // namespace pifu
+
+namespace pifu {
+// ------------------------------------------------------------------ training kernels
+uint32_t bce_partials(uint32_t n);
+void launch_bce_grad(const float* s, const float4* pts, uint32_t n, float* g, float* loss_part,
+                     float* loss, hipStream_t st);
+void launch_weight_grad(const float* G, int N, const float* A1, int K1, int lda1, const float* A2,
+                        int K2, int lda2, const float* ext, int n_ext, uint32_t M, float* part,
+                        float* dW, float* db, hipStream_t st);
+size_t weight_grad_part_floats(int N, int K, uint32_t M);
+void launch_backprop_input(const float* G, int N, const float* W, int ldw, const float* H, int Kh,
+                           uint32_t M, int act, float* dH, hipStream_t st);
+void launch_rmsprop(float* w, const float* g, float* v, size_t n, float lr, float alpha, float eps,
+                    hipStream_t st);
+}  // namespace pifu

@@ -78,7 +78,8 @@ EXPORTS = ["pifu_create", "pifu_destroy", "pifu_status_string",
            "pifu_occupancy_grid_workspace_size", "pifu_occupancy_grid",
            "pifu_render_view_workspace_size", "pifu_render_view",
            "pifu_eval_points_workspace_size", "pifu_eval_points",
-           "pifu_profile_enable", "pifu_profile_read"]
+           "pifu_profile_enable", "pifu_profile_read", "pifu_mlp_train_workspace_size",
+           "pifu_mlp_grad", "pifu_rmsprop_step"]
 
 _lib = None
 
@@ -112,6 +113,11 @@ def load_library():
     lib.pifu_eval_points_workspace_size.argtypes = [C.POINTER(PifuField), i32, u32, C.POINTER(sz)]
     lib.pifu_eval_points.argtypes = [P, C.POINTER(PifuField), i32, C.c_float, C.c_float, P, u32, P,
                                      P, P, sz, P]
+    PP = C.POINTER(C.c_void_p)
+    lib.pifu_mlp_train_workspace_size.argtypes = [C.POINTER(PifuField), u32, C.POINTER(sz)]
+    lib.pifu_mlp_grad.argtypes = [P, C.POINTER(PifuField), P, u32, PP, PP, P, P, sz, P]
+    lib.pifu_rmsprop_step.argtypes = [P, C.POINTER(PifuMLP), PP, PP, PP, PP, C.c_float, C.c_float,
+                                      C.c_float, P]
     lib.pifu_profile_enable.argtypes = [P, i32]
     lib.pifu_profile_read.argtypes = [P, C.POINTER(PifuKernelProfile)]
     for name in EXPORTS:
