@@ -1,0 +1,113 @@
+"""The C ABI without a GPU: the library loads, exports every function include/pifu.h
+declares, its structs match the ctypes mirrors, and host-side validation rejects bad
+arguments before any launch."""
+import ctypes as C
+import os
+import re
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pifu.h")
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2007_13988_amd.pifu as P
+    P.load_library()
+    return P
+
+
+def _declared():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\*?(pifu_\w+)\(", src, re.M)))
+
+
+def test_library_exports_every_declared_function(P):
+    lib = P.load_library()
+    names = _declared()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", P.LIB_PATH], capture_output=True, text=True)
+    for n in names:
+        assert re.search(rf"\bT {n}\b", out.stdout), n
+
+
+def test_struct_layouts_match_header(P):
+    prog = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "pifu.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(pifu_mlp), sizeof(pifu_field), sizeof(pifu_level_stats),
+         sizeof(pifu_grid_opts), sizeof(pifu_render_opts), sizeof(pifu_kernel_profile));
+  printf("%zu %zu %zu\n", offsetof(pifu_field, feat), offsetof(pifu_field, ell),
+         offsetof(pifu_mlp, fp8_amax));
+  return 0;
+}
+"""
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "s.c")
+        open(c, "w").write(prog)
+        exe = os.path.join(d, "s")
+        subprocess.run(["gcc", "-I", os.path.dirname(HEADER), c, "-o", exe], check=True)
+        lines = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split("\n")
+    sizes = [int(x) for x in lines[0].split()]
+    assert sizes == [C.sizeof(P.PifuMLP), C.sizeof(P.PifuField), C.sizeof(P.PifuLevelStats),
+                     C.sizeof(P.PifuGridOpts), C.sizeof(P.PifuRenderOpts),
+                     C.sizeof(P.PifuKernelProfile)]
+    offs = [int(x) for x in lines[1].split()]
+    assert offs == [P.PifuField.feat.offset, P.PifuField.ell.offset, P.PifuMLP.fp8_amax.offset]
+
+
+def _ell_field(P):
+    return P.DeviceField.ellipsoids(synth.ellipsoids(8, 302), 8.0)
+
+
+def _ws(P, field, opts):
+    lib = P.load_library()
+    n = C.c_size_t()
+    st = lib.pifu_occupancy_grid_workspace_size(C.byref(field.struct) if field else None,
+                                                C.byref(opts) if opts else None, C.byref(n))
+    return st, n.value
+
+
+def test_workspace_query_and_validation(P):
+    f = _ell_field(P)
+    st, n = _ws(P, f, P.grid_opts(8, 5))
+    assert st == 0 and n > 257 ** 3
+    assert _ws(P, f, P.grid_opts(10, 5))[0] == -1          # final grid too large
+    assert _ws(P, f, P.grid_opts(5, 6))[0] == -1           # coarse finer than final
+    assert _ws(P, f, P.grid_opts(5, 0))[0] == -1
+    assert _ws(P, None, P.grid_opts(5, 3))[0] == -1        # null field
+    assert _ws(P, f, None)[0] == -1                        # null options
+    o = P.grid_opts(5, 3)
+    o.precision = 7
+    assert _ws(P, f, o)[0] == -1                           # unknown precision
+    bad = P.DeviceField(P.FIELD_ELLIPSOIDS, ell=np.zeros((0, 12), np.float32))
+    assert _ws(P, bad, P.grid_opts(5, 3))[0] == -1         # no ellipsoid
+
+
+def test_render_workspace_validation(P):
+    lib = P.load_library()
+    f = _ell_field(P)
+    n = C.c_size_t()
+    o = P.render_opts(9, 8, 6)
+    # the colour field must be an MLP field
+    assert lib.pifu_render_view_workspace_size(C.byref(f.struct), C.byref(f.struct), C.byref(o),
+                                               C.byref(n)) == -1
+    o2 = P.render_opts(6, 2, 2)                            # z would have no coarse cells
+    assert lib.pifu_render_view_workspace_size(C.byref(f.struct), C.byref(f.struct), C.byref(o2),
+                                               C.byref(n)) == -1
+
+
+def test_status_strings(P):
+    lib = P.load_library()
+    assert lib.pifu_status_string(0) == b"ok"
+    assert lib.pifu_status_string(-2) == b"workspace too small"
