@@ -54,8 +54,8 @@ __device__ inline void store_block(const GemmArgs& a, const f32x16& acc, int row
 // ------------------------------------------------------------------ FP32 operands
 // v_mfma_f32_32x32x2_f32: per lane one A and one B element per MFMA; 4 MFMAs consume
 // a float4 of k from LDS (k-group of 8).
-template <int BM, int BN, int WM, int WN>
-__global__ void __launch_bounds__(256, 2) k_gemm_f32(GemmArgs a) {
+template <int BM, int BN, int WM, int WN, int MINB>
+__global__ void __launch_bounds__(256, MINB) k_gemm_f32(GemmArgs a) {
   constexpr int BK = 32;
   constexpr int LD = BK + 4;
   constexpr int TI = BM / WM / 32, TJ = BN / WN / 32;
@@ -162,8 +162,8 @@ __global__ void __launch_bounds__(256, 2) k_gemm_f32(GemmArgs a) {
 // ------------------------------------------------------------------ BF16 operands
 // v_mfma_f32_32x32x16_bf16: 8 bf16 per lane per MFMA (one 16-byte LDS read);
 // BK = 64 bf16 per stage.
-template <int BM, int BN, int WM, int WN, bool OUT_BF16>
-__global__ void __launch_bounds__(256, 2) k_gemm_bf16(GemmArgs a) {
+template <int BM, int BN, int WM, int WN, int MINB, bool OUT_BF16>
+__global__ void __launch_bounds__(256, MINB) k_gemm_bf16(GemmArgs a) {
   constexpr int BK = 64;
   constexpr int LD = BK + 8;   // in bf16 elements
   constexpr int TI = BM / WM / 32, TJ = BN / WN / 32;
@@ -285,33 +285,50 @@ void launch_pack_weights(const float* W, int N, int ldw_src, int K, void* dst, i
                        ldw_src, K, dst, bf16);
 }
 
+// Tile shapes per point tile BM (the autotuned parameter) and output tile BN:
+//   BM 64: waves 1x4 (BN 128) / 2x2 (BN 64); BM 128: 2x2 / 4x1; BM 256: 2x2 / 4x1.
+// Every variant walks k in the same order, so results do not depend on BM.
+#define PIFU_F32(BM_, BN_, WM_, WN_, MB_) \
+  hipLaunchKernelGGL((k_gemm_f32<BM_, BN_, WM_, WN_, MB_>), dim3((a.M + BM_ - 1) / BM_, a.N / BN_), \
+                     dim3(256), 0, s, a)
+#define PIFU_B16(BM_, BN_, WM_, WN_, MB_)                                                        \
+  do {                                                                                           \
+    if (a.c_bf16)                                                                                \
+      hipLaunchKernelGGL((k_gemm_bf16<BM_, BN_, WM_, WN_, MB_, true>),                           \
+                         dim3((a.M + BM_ - 1) / BM_, a.N / BN_), dim3(256), 0, s, a);             \
+    else                                                                                         \
+      hipLaunchKernelGGL((k_gemm_bf16<BM_, BN_, WM_, WN_, MB_, false>),                          \
+                         dim3((a.M + BM_ - 1) / BM_, a.N / BN_), dim3(256), 0, s, a);             \
+  } while (0)
+
 int launch_gemm(const GemmArgs& a, int precision, int tile_m, hipStream_t s) {
   if (a.M <= 0) return 0;
   const bool bn128 = (a.N % 128) == 0;
   if (!bn128 && (a.N % 64) != 0) return -1;
-  const unsigned gy = bn128 ? a.N / 128 : a.N / 64;
-  (void)tile_m;
-  const unsigned gx = (unsigned)((a.M + 127) / 128);
+  const int bm = tile_m == 64 ? 64 : (tile_m == 256 ? 256 : 128);
   if (precision == PIFU_PREC_FP32) {
     if ((a.K1 % 32) || (a.K2 % 32)) return -1;
-    if (bn128)
-      hipLaunchKernelGGL((k_gemm_f32<128, 128, 2, 2>), dim3(gx, gy), dim3(256), 0, s, a);
-    else
-      hipLaunchKernelGGL((k_gemm_f32<128, 64, 4, 1>), dim3(gx, gy), dim3(256), 0, s, a);
+    if (bn128) {
+      if (bm == 64) PIFU_F32(64, 128, 1, 4, 2);
+      else if (bm == 128) PIFU_F32(128, 128, 2, 2, 2);
+      else PIFU_F32(256, 128, 2, 2, 1);
+    } else {
+      if (bm == 64) PIFU_F32(64, 64, 2, 2, 2);
+      else if (bm == 128) PIFU_F32(128, 64, 4, 1, 2);
+      else PIFU_F32(256, 64, 4, 1, 1);
+    }
     return 0;
   }
   if (precision == PIFU_PREC_BF16) {
     if ((a.K1 % 64) || (a.K2 % 64)) return -1;
     if (bn128) {
-      if (a.c_bf16)
-        hipLaunchKernelGGL((k_gemm_bf16<128, 128, 2, 2, true>), dim3(gx, gy), dim3(256), 0, s, a);
-      else
-        hipLaunchKernelGGL((k_gemm_bf16<128, 128, 2, 2, false>), dim3(gx, gy), dim3(256), 0, s, a);
+      if (bm == 64) PIFU_B16(64, 128, 1, 4, 2);
+      else if (bm == 128) PIFU_B16(128, 128, 2, 2, 2);
+      else PIFU_B16(256, 128, 2, 2, 1);
     } else {
-      if (a.c_bf16)
-        hipLaunchKernelGGL((k_gemm_bf16<128, 64, 4, 1, true>), dim3(gx, gy), dim3(256), 0, s, a);
-      else
-        hipLaunchKernelGGL((k_gemm_bf16<128, 64, 4, 1, false>), dim3(gx, gy), dim3(256), 0, s, a);
+      if (bm == 64) PIFU_B16(64, 64, 2, 2, 2);
+      else if (bm == 128) PIFU_B16(128, 64, 4, 1, 2);
+      else PIFU_B16(256, 64, 4, 1, 1);
     }
     return 0;
   }
