@@ -208,6 +208,38 @@ int32_t pifu_occupancy_grid(pifu_ctx* ctx, const pifu_field* field, const pifu_g
                             pifu_level_stats* stats, void* workspace, size_t workspace_bytes,
                             pifu_stream stream);
 
+/* ---------------------------------------------------------------- several frames */
+
+/* Outputs of one frame of pifu_occupancy_grid_batched (device buffers as in
+ * pifu_occupancy_grid; n_cells is written by the call; stats host, nullable,
+ * log2_final - log2_coarse + 1 records). */
+typedef struct pifu_grid_out {
+  float* occ;
+  uint8_t* labels;
+  uint32_t* cells;
+  uint32_t cells_cap;
+  uint32_t n_cells;
+  pifu_level_stats* stats;
+} pifu_grid_out;
+
+int32_t pifu_occupancy_grid_batched_workspace_size(int32_t n, const pifu_field* const* fields,
+                                                   const pifu_grid_opts* const* opts,
+                                                   size_t* bytes);
+
+/*
+ * Hierarchical localization of n <= 16 independent frames in one pass: frames are
+ * processed independently in the paper (Sec. 3), so their levels run in lockstep
+ * and every conflict wave evaluates all frames' points with one set of MLP GEMMs
+ * (the network is shared; feature maps and analytic shapes differ per frame).
+ * Frames may differ in log2_final; every other option, the field kind and the
+ * network must be equal (else PIFU_ERR_INVALID_ARGUMENT).  Results are identical
+ * to n calls of pifu_occupancy_grid.  The combined point list holds at most 2^28
+ * points per wave (PIFU_ERR_WORKSPACE_TOO_SMALL beyond).  Blocks until done.
+ */
+int32_t pifu_occupancy_grid_batched(pifu_ctx* ctx, int32_t n, const pifu_field* const* fields,
+                                    const pifu_grid_opts* const* opts, pifu_grid_out* outs,
+                                    void* workspace, size_t workspace_bytes, pifu_stream stream);
+
 /* ---------------------------------------------------------------- render */
 
 int32_t pifu_render_view_workspace_size(const pifu_field* occ_field, const pifu_field* color_field,

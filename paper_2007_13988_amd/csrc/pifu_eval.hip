@@ -14,7 +14,7 @@ static inline unsigned grid1d(size_t n, int block) { return (unsigned)((n + bloc
 // falls outside [-1,1]^3 after the view transform.
 __device__ inline bool src_point(const PointSrc& s, const uint32_t* __restrict__ list, uint32_t m,
                                  double P[3], float* occ) {
-  const uint32_t idx = list ? list[m] : m;
+  const uint32_t idx = (list ? list[m] : m) - s.base_sub;
   if (s.mode == 1) {
     const float4 q = s.pts[idx];
     P[0] = q.x;

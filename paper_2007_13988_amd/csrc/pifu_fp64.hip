@@ -11,6 +11,7 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 static inline unsigned grid1d(size_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
 __device__ inline bool src_point64(const PointSrc& s, uint32_t idx, double P[3], double* occ) {
+  idx -= s.base_sub;
   if (s.mode == 1) {
     const float4 q = s.pts[idx];
     P[0] = q.x;

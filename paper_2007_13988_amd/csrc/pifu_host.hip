@@ -292,21 +292,43 @@ float logit_band(float delta) {
   return (float)std::log((0.5 + (double)delta) / (0.5 - (double)delta));
 }
 
+// A run of list entries whose points sample one frame's feature map.
+struct Seg {
+  uint32_t begin, count;
+  const float* F;
+  uint32_t base_sub;
+};
+
 // Runs an MLP over n points (chunked): gather -> hidden GEMMs -> head.  prec selects
-// the MFMA operand type of the hidden layers.
+// the MFMA operand type of the hidden layers.  segs (nullable) splits the list into
+// frames that share the network but not the feature map; the GEMMs span all frames.
 int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const PointSrc& src,
             const uint32_t* list, uint32_t n, const EvalWs& ew, float* logit, uint8_t* lab,
-            float* rgb) {
+            float* rgb, const Seg* segs = nullptr, int nseg = 0) {
   const pifu_field* f = fp.f;
   const MLPDesc& d = mp.d;
   const int C = f->C;
   const bool b16 = prec != PIFU_PREC_FP32;
+  Seg one{0, n, f->feat, src.base_sub};
+  if (!segs) {
+    segs = &one;
+    nseg = 1;
+  }
   for (uint32_t c0 = 0; c0 < n; c0 += ew.chunk) {
     const uint32_t m = std::min(ew.chunk, n - c0);
     const uint32_t* lst = list + c0;
     {
       ProfScope ps(e.ctx, e.s, PIFU_KERN_GATHER, 0.0, (double)m * (16.0 * C + (b16 ? 2 : 4) * C + 20.0));
-      launch_gather(src, lst, m, f->feat, f->H, f->W, C, ew.feat, b16, ew.ext, e.s);
+      for (int q = 0; q < nseg; ++q) {
+        const uint32_t lo = std::max(c0, segs[q].begin);
+        const uint32_t hi = std::min(c0 + m, segs[q].begin + segs[q].count);
+        if (lo >= hi) continue;
+        PointSrc sq = src;
+        sq.base_sub = segs[q].base_sub;
+        char* fb = reinterpret_cast<char*>(ew.feat) + (size_t)(lo - c0) * C * (b16 ? 2 : 4);
+        launch_gather(sq, list + lo, hi - lo, segs[q].F, f->H, f->W, C, fb, b16,
+                      ew.ext + 4 * (size_t)(lo - c0), e.s);
+      }
     }
     const void* prev = nullptr;
     void* out = ew.hA;
@@ -376,36 +398,51 @@ int select_near(EvalCtx& e, const float* logit, uint32_t n, float bound, uint32_
   return PIFU_OK;
 }
 
-// Full-network evaluation: run precision, then the FP32 band, then the FP64 guard.
-int eval_full(EvalCtx& e, const FieldPrep& fp, const PointSrc& src, const uint32_t* list,
-              uint32_t n, const EvalWs& ew, float* logit, uint8_t* lab, pifu_level_stats* st) {
+// After the run-precision pass: the FP32 band (BF16/FP8 runs), then the FP64 guard.
+// F is the feature map of the points' frame.
+int post_full(EvalCtx& e, const FieldPrep& fp, const PointSrc& src, const float* F,
+              const uint32_t* list, uint32_t n, const EvalWs& ew, float* logit, uint8_t* lab,
+              pifu_level_stats* st) {
   const pifu_field* f = fp.f;
-  int r = run_mlp(e, fp, fp.mlp, e.precision, src, list, n, ew, logit, lab, nullptr);
-  if (r) return r;
-  if (st) st->mlp_points += n;
+  int r = PIFU_OK;
+  const Seg one{0, n, F, src.base_sub};
   if (e.precision != PIFU_PREC_FP32 && e.band > 0.f) {
     uint32_t nb = 0;
     r = select_near(e, logit, n, e.band, ew.band_pos, &nb);
     if (r) return r;
     if (nb) {
       launch_gather_u32(list, ew.band_pos, nb, ew.band_nodes, e.s);
+      const Seg bseg{0, nb, F, src.base_sub};
       r = run_mlp(e, fp, fp.mlp, PIFU_PREC_FP32, src, ew.band_nodes, nb, ew, ew.band_logit,
-                  ew.band_lab, nullptr);
+                  ew.band_lab, nullptr, &bseg, 1);
       if (r) return r;
       launch_scatter_results(ew.band_pos, nb, ew.band_logit, ew.band_lab, logit, lab, e.s);
       if (st) st->band_fp32 += nb;
     }
   }
+  (void)one;
   if (e.guard > 0.f) {
     uint32_t gn = 0;
     r = select_near(e, logit, n, e.guard, ew.glist, &gn);
     if (r) return r;
-    run_guard64(src, list, ew.glist, gn, fp.mlp.d, f->feat, f->H, f->W, f->C, logit, lab, ew.g64,
+    run_guard64(src, list, ew.glist, gn, fp.mlp.d, F, f->H, f->W, f->C, logit, lab, ew.g64,
                 ew.chunk64, e.s);
     if (st) st->guard_fp64 += gn;
     r = check_launch();
   }
   return r;
+}
+
+// Full-network evaluation: run precision, then the FP32 band, then the FP64 guard.
+int eval_full(EvalCtx& e, const FieldPrep& fp, const PointSrc& src, const uint32_t* list,
+              uint32_t n, const EvalWs& ew, float* logit, uint8_t* lab, pifu_level_stats* st,
+              const float* F = nullptr) {
+  if (!F) F = fp.f->feat;
+  const Seg one{0, n, F, src.base_sub};
+  int r = run_mlp(e, fp, fp.mlp, e.precision, src, list, n, ew, logit, lab, nullptr, &one, 1);
+  if (r) return r;
+  if (st) st->mlp_points += n;
+  return post_full(e, fp, src, F, list, n, ew, logit, lab, st);
 }
 
 // Evaluates the occupancy field at n points; fills logit and label per point.  With
@@ -1117,6 +1154,330 @@ int32_t pifu_rmsprop_step(pifu_ctx* ctx, const pifu_mlp* net, const float* const
     launch_rmsprop(const_cast<float*>(d.b[l]), db[l], vb[l], (size_t)d.widths[l], lr, alpha, eps, s);
   }
   return check_launch();
+}
+
+}  // extern "C"
+
+// ================================================================== multi-frame batching
+namespace {
+
+constexpr int kMaxFrames = 16;
+constexpr uint32_t kBatchListCap = 1u << 28;
+enum { C_SEG = 16, C_CONF_F = 40, C_B0_F = 56 };   // counter words (per frame blocks of 16)
+
+struct BatchPlan {
+  int n = 0;
+  int order[kMaxFrames];       // frames sorted by number of refinements, descending
+  int pos[kMaxFrames];         // position of frame f in the combined arrays
+  int T[kMaxFrames];
+  int Tmax = 0, l0 = 0;
+  Lat lat[11];
+  int active[11];
+  uint8_t* st[11];
+  float* occ[11];
+  uint32_t* counters = nullptr;
+  LocalizeWs w;
+  uint32_t list_cap = 0;
+  FieldPrep fps[kMaxFrames];
+  EvalWs ew;
+  size_t bytes = 0;
+};
+
+int validate_batch(int n, const pifu_field* const* fields, const pifu_grid_opts* const* opts) {
+  if (n < 1 || n > kMaxFrames || !fields || !opts) return PIFU_ERR_INVALID_ARGUMENT;
+  for (int f = 0; f < n; ++f) {
+    int r = validate_grid_opts(fields[f], opts[f]);
+    if (r) return r;
+    const pifu_grid_opts& a = *opts[0];
+    const pifu_grid_opts& b = *opts[f];
+    if (b.dense || b.log2_coarse != a.log2_coarse || b.precision != a.precision ||
+        b.band_delta != a.band_delta || b.guard_logit != a.guard_logit ||
+        b.surrogate_max_log2 != a.surrogate_max_log2 || b.surrogate_delta != a.surrogate_delta ||
+        b.max_waves != a.max_waves || b.tile_m != a.tile_m)
+      return PIFU_ERR_INVALID_ARGUMENT;
+    const pifu_field* A = fields[0];
+    const pifu_field* B = fields[f];
+    if (A->kind != B->kind) return PIFU_ERR_INVALID_ARGUMENT;
+    if (A->kind == PIFU_FIELD_MLP) {
+      // frames share one network; only the feature maps differ
+      if (B->H != A->H || B->W != A->W || B->C != A->C) return PIFU_ERR_INVALID_ARGUMENT;
+      if (std::memcmp(A->mlp, B->mlp, sizeof(pifu_mlp)) != 0) return PIFU_ERR_INVALID_ARGUMENT;
+      if ((A->surrogate == nullptr) != (B->surrogate == nullptr)) return PIFU_ERR_INVALID_ARGUMENT;
+      if (A->surrogate && std::memcmp(A->surrogate, B->surrogate, sizeof(pifu_mlp)) != 0)
+        return PIFU_ERR_INVALID_ARGUMENT;
+    }
+  }
+  return PIFU_OK;
+}
+
+void plan_batch(int n, const pifu_field* const* fields, const pifu_grid_opts* const* opts, void* base,
+                BatchPlan& b) {
+  b.n = n;
+  b.l0 = opts[0]->log2_coarse;
+  b.Tmax = 0;
+  for (int f = 0; f < n; ++f) {
+    b.T[f] = opts[f]->log2_final - b.l0;
+    b.order[f] = f;
+    b.Tmax = std::max(b.Tmax, b.T[f]);
+  }
+  std::stable_sort(b.order, b.order + n, [&](int x, int y) { return b.T[x] > b.T[y]; });
+  for (int p = 0; p < n; ++p) b.pos[b.order[p]] = p;
+  Carver cv(base);
+  b.counters = cv.take<uint32_t>(kCounters + 2 * kMaxFrames + 64);
+  size_t max_n = 0;
+  for (int r = 0; r <= b.Tmax; ++r) {
+    const int lg = b.l0 + r;
+    b.lat[r] = Lat{(1 << lg) + 1, (1 << lg) + 1, (1 << lg) + 1};
+    int a = 0;
+    for (int f = 0; f < n; ++f) a += b.T[f] >= r;
+    b.active[r] = a;
+    const size_t tot = b.lat[r].n() * a;
+    b.st[r] = cv.take<uint8_t>(tot + 16);
+    b.occ[r] = cv.take<float>(tot);
+    max_n = std::max(max_n, tot);
+  }
+  b.list_cap = (uint32_t)std::min<size_t>(max_n, kBatchListCap);
+  b.w.list = cv.take<uint32_t>(b.list_cap);
+  b.w.cscratch = cv.take<uint32_t>(compact_scratch_words(max_n));
+  b.w.logit = cv.take<float>(b.list_cap);
+  b.w.lab = cv.take<uint8_t>(b.list_cap);
+  // one network for every frame: carve its operand copies once
+  carve_field(cv, fields[0], opts[0]->precision, b.fps[0]);
+  for (int f = 1; f < n; ++f) {
+    b.fps[f] = b.fps[0];
+    b.fps[f].f = fields[f];
+    if (fields[f]->kind == PIFU_FIELD_ELLIPSOIDS) {
+      std::memset(&b.fps[f].ell, 0, sizeof(b.fps[f].ell));
+      b.fps[f].ell.n = fields[f]->n_ell;
+      b.fps[f].ell.k = fields[f]->sharpness;
+      if (fields[f]->ell) std::memcpy(b.fps[f].ell.e, fields[f]->ell, sizeof(float) * 12 * fields[f]->n_ell);
+    }
+  }
+  const int C = fields[0]->kind == PIFU_FIELD_MLP ? fields[0]->C : 0;
+  int mh = b.fps[0].has_mlp ? b.fps[0].mlp.max_hidden : 0;
+  if (b.fps[0].has_sur) mh = std::max(mh, b.fps[0].sur.max_hidden);
+  carve_eval(cv, b.list_cap, C, mh, b.ew);
+  carve_guard(cv, b.fps[0], b.list_cap, b.ew);
+  b.bytes = cv.off + kAlign;
+}
+
+// Stable compaction over the combined array, then the per-frame bounds of the list;
+// one read-back carries the total and the bounds.
+int compact_frames(EvalCtx& e, BatchPlan& b, int r, uint32_t* n_out, uint32_t* bounds) {
+  const Lat L = b.lat[r];
+  const int A = b.active[r];
+  const size_t tot = L.n() * A;
+  launch_compact(b.st[r], tot, ST_PEND, ST_PEND, b.w.cscratch, e.counters + C_TOTAL, b.w.list,
+                 b.list_cap, 0, L, e.s);
+  int rc = check_launch();
+  if (rc) return rc;
+  rc = read_counters(e, 1);
+  if (rc) return rc;
+  const uint32_t n = e.ctx->host_counters[C_TOTAL];
+  if (n > b.list_cap) return PIFU_ERR_WORKSPACE_TOO_SMALL;
+  launch_segment_bounds(b.w.list, n, (uint32_t)L.n(), A, e.counters + C_SEG, e.s);
+  rc = read_counters(e, C_SEG + A + 1);
+  if (rc) return rc;
+  for (int p = 0; p <= A; ++p) bounds[p] = e.ctx->host_counters[C_SEG + p];
+  *n_out = n;
+  return PIFU_OK;
+}
+
+// Evaluates the combined list: the network's GEMMs span every frame, the gathers and
+// the band / guard / surrogate-fallback re-runs stay per frame.
+int eval_frames(EvalCtx& e, BatchPlan& b, int r, const uint32_t* bounds, uint32_t n,
+                pifu_level_stats* st, bool use_sur) {
+  const int A = b.active[r];
+  const Lat L = b.lat[r];
+  PointSrc src;
+  std::memset(&src, 0, sizeof(src));
+  src.mode = 0;
+  src.nx = L.nx;
+  src.ny = L.ny;
+  src.nz = L.nz;
+  Seg segs[kMaxFrames];
+  int ns = 0;
+  for (int p = 0; p < A; ++p) {
+    const int f = b.order[p];
+    segs[ns++] = Seg{bounds[p], bounds[p + 1] - bounds[p], b.fps[f].f->feat,
+                     (uint32_t)(L.n() * p)};
+  }
+  const FieldPrep& fp0 = b.fps[0];
+  if (!fp0.has_mlp) {
+    for (int q = 0; q < ns; ++q) {
+      const int f = b.order[q];
+      if (!segs[q].count) continue;
+      PointSrc sq = src;
+      sq.base_sub = segs[q].base_sub;
+      launch_eval_analytic(sq, b.w.list + segs[q].begin, segs[q].count, b.fps[f].f->kind,
+                           b.fps[f].ell, b.fps[f].f->plane, b.w.logit + segs[q].begin,
+                           b.w.lab + segs[q].begin, e.s);
+    }
+    return check_launch();
+  }
+  const bool sur = use_sur && fp0.has_sur;
+  int rc = run_mlp(e, fp0, sur ? fp0.sur : fp0.mlp, sur ? PIFU_PREC_BF16 : e.precision, src,
+                   b.w.list, n, b.ew, b.w.logit, b.w.lab, nullptr, segs, ns);
+  if (rc) return rc;
+  for (int q = 0; q < ns; ++q) {
+    const int f = b.order[q];
+    if (!segs[q].count) continue;
+    PointSrc sq = src;
+    sq.base_sub = segs[q].base_sub;
+    const uint32_t* lst = b.w.list + segs[q].begin;
+    float* lg = b.w.logit + segs[q].begin;
+    uint8_t* lb = b.w.lab + segs[q].begin;
+    pifu_level_stats* sf = st ? &st[f] : nullptr;
+    if (!sur) {
+      if (sf) sf->mlp_points += segs[q].count;
+      rc = post_full(e, b.fps[f], sq, segs[q].F, lst, segs[q].count, b.ew, lg, lb, sf);
+      if (rc) return rc;
+      continue;
+    }
+    uint32_t nsur = 0;
+    rc = select_near(e, lg, segs[q].count, e.sur_band, b.ew.sur_pos, &nsur);
+    if (rc) return rc;
+    if (nsur) {
+      launch_gather_u32(lst, b.ew.sur_pos, nsur, b.ew.sur_nodes, e.s);
+      rc = eval_full(e, b.fps[f], sq, b.ew.sur_nodes, nsur, b.ew, b.ew.sur_logit, b.ew.sur_lab, sf,
+                     segs[q].F);
+      if (rc) return rc;
+      launch_scatter_results(b.ew.sur_pos, nsur, b.ew.sur_logit, b.ew.sur_lab, lg, lb, e.s);
+    }
+    if (sf) sf->surrogate_fallback += nsur;
+  }
+  return check_launch();
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t pifu_occupancy_grid_batched_workspace_size(int32_t n, const pifu_field* const* fields,
+                                                   const pifu_grid_opts* const* opts,
+                                                   size_t* bytes) {
+  if (!bytes) return PIFU_ERR_INVALID_ARGUMENT;
+  int r = validate_batch(n, fields, opts);
+  if (r) return r;
+  BatchPlan* b = new (std::nothrow) BatchPlan;
+  if (!b) return PIFU_ERR_HIP;
+  plan_batch(n, fields, opts, nullptr, *b);
+  *bytes = b->bytes;
+  delete b;
+  return PIFU_OK;
+}
+
+int32_t pifu_occupancy_grid_batched(pifu_ctx* ctx, int32_t n, const pifu_field* const* fields,
+                                    const pifu_grid_opts* const* opts, pifu_grid_out* outs,
+                                    void* workspace, size_t workspace_bytes, pifu_stream stream) {
+  if (!ctx || !outs || !workspace || !aligned(workspace, kAlign)) return PIFU_ERR_INVALID_ARGUMENT;
+  int rc = validate_batch(n, fields, opts);
+  if (rc) return rc;
+  for (int f = 0; f < n; ++f)
+    if (!outs[f].occ || !outs[f].labels || (outs[f].cells_cap && !outs[f].cells))
+      return PIFU_ERR_INVALID_ARGUMENT;
+  BatchPlan* bp = new (std::nothrow) BatchPlan;
+  if (!bp) return PIFU_ERR_HIP;
+  BatchPlan& b = *bp;
+  plan_batch(n, fields, opts, nullptr, b);
+  if (workspace_bytes < b.bytes) {
+    delete bp;
+    return PIFU_ERR_WORKSPACE_TOO_SMALL;
+  }
+  plan_batch(n, fields, opts, workspace, b);
+  hipStream_t s = as_stream(stream);
+  const pifu_grid_opts& o = *opts[0];
+  EvalCtx e{ctx, s, b.counters, o.precision, o.guard_logit};
+  e.band = logit_band(o.band_delta);
+  e.sur_band = logit_band(o.surrogate_delta);
+  pack_field(b.fps[0], s);
+  pifu_level_stats st[kMaxFrames];
+  uint32_t bounds[kMaxFrames + 1];
+  for (int r = 0; r <= b.Tmax && !rc; ++r) {
+    const Lat L = b.lat[r];
+    const int A = b.active[r];
+    const uint32_t nl = (uint32_t)L.n();
+    const int level_id = b.l0 + r;
+    std::memset(st, 0, sizeof(st));
+    for (int f = 0; f < n; ++f) {
+      st[f].level = level_id;
+      st[f].nodes = nl;
+    }
+    if (hipMemsetAsync(b.counters, 0, sizeof(uint32_t) * (kCounters + 2 * kMaxFrames + 64), s) !=
+        hipSuccess) {
+      rc = PIFU_ERR_HIP;
+      break;
+    }
+    const bool use_sur = level_id <= o.surrogate_max_log2;
+    uint32_t cnt = 0;
+    if (r == 0) {
+      const uint32_t tot = nl * (uint32_t)A;
+      launch_fill_u8(b.st[0], 0, tot, s);
+      launch_iota(b.w.list, tot, s);
+      for (int p = 0; p <= A; ++p) bounds[p] = nl * (uint32_t)p;
+      rc = eval_frames(e, b, 0, bounds, tot, st, use_sur);
+      if (rc) break;
+      launch_apply_grid(b.w.list, tot, b.w.logit, b.w.lab, b.st[0], b.occ[0], nullptr, nullptr,
+                        level_id, L, 1, L, 0, s, nl);
+      for (int p = 0; p < A; ++p) {
+        st[b.order[p]].dilated = nl;
+        st[b.order[p]].evaluated = nl;
+      }
+    } else {
+      launch_transition(b.st[r - 1], b.occ[r - 1], b.lat[r - 1], b.st[r], b.occ[r], L, s, A);
+      for (int p = 0; p < A; ++p)
+        launch_count_bits(b.st[r] + (size_t)p * nl, nl, ST_B0, b.counters + C_B0_F + p, s);
+      launch_select(b.st[r], L, s, A);
+      rc = compact_frames(e, b, r, &cnt, bounds);
+      if (rc) break;
+      for (int p = 0; p < A; ++p) st[b.order[p]].dilated = bounds[p + 1] - bounds[p];
+      int waves = 0;
+      while (cnt) {
+        rc = eval_frames(e, b, r, bounds, cnt, st, use_sur);
+        if (rc) break;
+        launch_apply_grid(b.w.list, cnt, b.w.logit, b.w.lab, b.st[r], b.occ[r],
+                          b.counters + C_CONF_F, nullptr, level_id, L, 1, L, 1, s, nl);
+        for (int p = 0; p < A; ++p) {
+          const uint32_t c = bounds[p + 1] - bounds[p];
+          st[b.order[p]].evaluated += c;
+          if (waves > 0 && c) st[b.order[p]].waves += 1;
+        }
+        if (o.max_waves > 0 && waves >= o.max_waves) break;
+        launch_expand(b.w.list, cnt, b.st[r], L, s, nl);
+        rc = compact_frames(e, b, r, &cnt, bounds);
+        if (rc) break;
+        if (cnt) ++waves;
+      }
+      if (rc) break;
+    }
+    rc = check_launch();
+    if (!rc) rc = read_counters(e, C_B0_F + kMaxFrames);
+    if (rc) break;
+    for (int p = 0; p < A; ++p) {
+      const int f = b.order[p];
+      st[f].conflicts = ctx->host_counters[C_CONF_F + p];
+      st[f].b0 = r ? ctx->host_counters[C_B0_F + p] : 0;
+      if (outs[f].stats) outs[f].stats[r] = st[f];
+    }
+    // frames whose final level this is: labels, cells and occupancy out
+    for (int p = 0; p < A && !rc; ++p) {
+      const int f = b.order[p];
+      if (b.T[f] != r) continue;
+      uint8_t* sf = b.st[r] + (size_t)p * nl;
+      launch_cells(sf, L, outs[f].labels, s);
+      uint32_t nc = 0;
+      rc = compact_count(e, sf, nl, ST_CELL, ST_CELL, b.w.cscratch, outs[f].cells, outs[f].cells_cap,
+                         1, L, &nc);
+      outs[f].n_cells = nc;
+      if (!rc && hipMemcpyAsync(outs[f].occ, b.occ[r] + (size_t)p * nl, sizeof(float) * nl,
+                                hipMemcpyDeviceToDevice, s) != hipSuccess)
+        rc = PIFU_ERR_HIP;
+    }
+  }
+  if (!rc) rc = hipStreamSynchronize(s) == hipSuccess ? PIFU_OK : PIFU_ERR_HIP;
+  prof_resolve(ctx);
+  delete bp;
+  return rc;
 }
 
 }  // extern "C"

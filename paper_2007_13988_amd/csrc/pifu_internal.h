@@ -28,12 +28,15 @@ struct Lat {
 //   mode 0: lattice nodes; point m is node list[m] of lattice (nx, ny, nz),
 //           optionally mapped by the 3x4 view (target NDC -> input NDC).
 //   mode 1: explicit points pts[list ? list[m] : m] (x, y, z, occ), input NDC.
+//   base_sub is subtracted from every list entry first (a frame's offset inside a
+//   multi-frame state array).
 struct PointSrc {
   int mode;
   int nx, ny, nz;
   int has_view;
   double view[12];
   const float4* pts;
+  uint32_t base_sub;
 };
 
 struct MLPDesc {
@@ -67,9 +70,13 @@ constexpr int COMPACT_TILE = COMPACT_BLOCK * COMPACT_PER_THREAD;
 // ------------------------------------------------------------------ level kernels
 void launch_fill_u8(uint8_t* p, uint8_t v, size_t n, hipStream_t s);
 void launch_iota(uint32_t* list, uint32_t n, hipStream_t s);
+// frames > 1: `frames` lattices stored back to back (coarse and fine), one grid row each.
 void launch_transition(const uint8_t* cst, const float* cocc, Lat c, uint8_t* fst, float* focc,
-                       Lat f, hipStream_t s);
-void launch_select(uint8_t* st, Lat f, hipStream_t s);
+                       Lat f, hipStream_t s, int frames = 1);
+void launch_select(uint8_t* st, Lat f, hipStream_t s, int frames = 1);
+// bounds[f] (f = 0..frames) = first list position with entry >= f * frame_nodes.
+void launch_segment_bounds(const uint32_t* list, uint32_t n, uint32_t frame_nodes, int frames,
+                           uint32_t* bounds, hipStream_t s);
 // Stable compaction of the nodes whose state byte satisfies (st & mask) == val.
 // mode 0 writes node indices, mode 1 cell indices (i*(nx-1)+j)*(nz... of lattice f).
 void launch_compact(const uint8_t* st, size_t n, uint8_t mask, uint8_t val, uint32_t* bcount,
@@ -78,8 +85,10 @@ size_t compact_scratch_words(size_t n);
 void launch_apply_grid(const uint32_t* list, uint32_t n, const float* logit, const uint8_t* lab,
                        uint8_t* st, float* occ, uint32_t* conflicts, uint8_t* eval_level,
                        int level_id, Lat lvl, int stride, Lat fin, int check_conflict,
-                       hipStream_t s);
-void launch_expand(const uint32_t* list, uint32_t n, uint8_t* st, Lat f, hipStream_t s);
+                       hipStream_t s, uint32_t frame_nodes = 0);
+// frame_nodes > 0: list entries index a multi-frame state array of frames of that size.
+void launch_expand(const uint32_t* list, uint32_t n, uint8_t* st, Lat f, hipStream_t s,
+                   uint32_t frame_nodes = 0);
 void launch_cells(uint8_t* st, Lat f, uint8_t* labels, hipStream_t s);
 void launch_count_bits(const uint8_t* st, size_t n, uint8_t bit, uint32_t* out, hipStream_t s);
 

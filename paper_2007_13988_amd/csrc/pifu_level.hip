@@ -33,6 +33,11 @@ __global__ void k_transition(const uint8_t* __restrict__ cst, const float* __res
                              Lat c, uint8_t* __restrict__ fst, float* __restrict__ focc, Lat f) {
   size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= f.n()) return;
+  // frame blockIdx.y of a multi-frame state array
+  cst += (size_t)blockIdx.y * c.n();
+  cocc += (size_t)blockIdx.y * c.n();
+  fst += (size_t)blockIdx.y * f.n();
+  focc += (size_t)blockIdx.y * f.n();
   const uint32_t nyz = (uint32_t)f.ny * f.nz;
   const uint32_t a = (uint32_t)(n / nyz);
   const uint32_t r = (uint32_t)(n - (size_t)a * nyz);
@@ -83,9 +88,9 @@ __global__ void k_transition(const uint8_t* __restrict__ cst, const float* __res
 }
 
 void launch_transition(const uint8_t* cst, const float* cocc, Lat c, uint8_t* fst, float* focc,
-                       Lat f, hipStream_t s) {
-  hipLaunchKernelGGL(k_transition, dim3(grid1d(f.n(), 256)), dim3(256), 0, s, cst, cocc, c, fst,
-                     focc, f);
+                       Lat f, hipStream_t s, int frames) {
+  hipLaunchKernelGGL(k_transition, dim3(grid1d(f.n(), 256), frames), dim3(256), 0, s, cst, cocc, c,
+                     fst, focc, f);
 }
 
 // 1-ring dilation of the boundary candidates: a node not evaluated before is selected
@@ -93,6 +98,7 @@ void launch_transition(const uint8_t* cst, const float* cocc, Lat c, uint8_t* fs
 __global__ void k_select(uint8_t* __restrict__ st, Lat f) {
   size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= f.n()) return;
+  st += (size_t)blockIdx.y * f.n();   // frame of a multi-frame state array
   uint8_t s = st[n];
   if (s & ST_EVAL) return;
   const uint32_t nyz = (uint32_t)f.ny * f.nz;
@@ -121,8 +127,8 @@ __global__ void k_select(uint8_t* __restrict__ st, Lat f) {
   if (any) st[n] = s | ST_PEND;
 }
 
-void launch_select(uint8_t* st, Lat f, hipStream_t s) {
-  hipLaunchKernelGGL(k_select, dim3(grid1d(f.n(), 256)), dim3(256), 0, s, st, f);
+void launch_select(uint8_t* st, Lat f, hipStream_t s, int frames) {
+  hipLaunchKernelGGL(k_select, dim3(grid1d(f.n(), 256), frames), dim3(256), 0, s, st, f);
 }
 
 // ------------------------------------------------------------------ compaction
@@ -306,9 +312,24 @@ __global__ void k_apply_grid(const uint32_t* __restrict__ list, uint32_t n,
                              const float* __restrict__ logit, const uint8_t* __restrict__ lab,
                              uint8_t* __restrict__ st, float* __restrict__ occ,
                              uint32_t* __restrict__ conflicts, uint8_t* __restrict__ eval_level,
-                             int level_id, Lat lvl, int stride, Lat fin, int check_conflict) {
+                             int level_id, Lat lvl, int stride, Lat fin, int check_conflict,
+                             uint32_t frame_nodes) {
   uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
   bool conf = false;
+  if (m < n && frame_nodes) {
+    // multi-frame: one conflict counter per frame (no evaluation-level map)
+    const uint32_t node = list[m];
+    const uint8_t s = st[node];
+    const uint8_t l = lab[m] ? ST_LABEL : 0;
+    occ[node] = 1.0f / (1.0f + expf(-logit[m]));
+    uint8_t ns = (uint8_t)((s & ~(ST_LABEL | ST_PEND | ST_CONF)) | ST_EVAL | ST_NOW | l);
+    if (check_conflict && ((l != 0) != ((s & ST_HI) != 0))) {
+      ns |= ST_CONF;
+      if (conflicts) atomicAdd(conflicts + node / frame_nodes, 1u);
+    }
+    st[node] = ns;
+    return;
+  }
   if (m < n) {
     const uint32_t node = list[m];
     const uint8_t s = st[node];
@@ -341,21 +362,27 @@ __global__ void k_apply_grid(const uint32_t* __restrict__ list, uint32_t n,
 void launch_apply_grid(const uint32_t* list, uint32_t n, const float* logit, const uint8_t* lab,
                        uint8_t* st, float* occ, uint32_t* conflicts, uint8_t* eval_level,
                        int level_id, Lat lvl, int stride, Lat fin, int check_conflict,
-                       hipStream_t s) {
+                       hipStream_t s, uint32_t frame_nodes) {
   if (!n) return;
   hipLaunchKernelGGL(k_apply_grid, dim3(grid1d(n, 256)), dim3(256), 0, s, list, n, logit, lab, st,
-                     occ, conflicts, eval_level, level_id, lvl, stride, fin, check_conflict);
+                     occ, conflicts, eval_level, level_id, lvl, stride, fin, check_conflict,
+                     frame_nodes);
 }
 
 // Conflict expansion: every not-yet-evaluated node of the 26-neighbourhood of a
 // conflict node of the last wave is selected.  Concurrent read-modify-writes of one
 // byte only ever add ST_PEND, so they agree.
 __global__ void k_expand(const uint32_t* __restrict__ list, uint32_t n, uint8_t* __restrict__ st,
-                         Lat f) {
+                         Lat f, uint32_t frame_nodes) {
   uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= n) return;
-  const uint32_t node = list[m];
+  uint32_t node = list[m];
   if (!(st[node] & ST_CONF)) return;
+  if (frame_nodes) {   // neighbours stay inside the node's frame
+    const uint32_t local = node % frame_nodes;
+    st += (size_t)(node - local);
+    node = local;
+  }
   const uint32_t nyz = (uint32_t)f.ny * f.nz;
   const int a = (int)(node / nyz);
   const int r = (int)(node - (uint32_t)a * nyz);
@@ -378,9 +405,30 @@ __global__ void k_expand(const uint32_t* __restrict__ list, uint32_t n, uint8_t*
   }
 }
 
-void launch_expand(const uint32_t* list, uint32_t n, uint8_t* st, Lat f, hipStream_t s) {
+void launch_expand(const uint32_t* list, uint32_t n, uint8_t* st, Lat f, hipStream_t s,
+                   uint32_t frame_nodes) {
   if (!n) return;
-  hipLaunchKernelGGL(k_expand, dim3(grid1d(n, 256)), dim3(256), 0, s, list, n, st, f);
+  hipLaunchKernelGGL(k_expand, dim3(grid1d(n, 256)), dim3(256), 0, s, list, n, st, f, frame_nodes);
+}
+
+// bounds[f] = first position of the sorted list whose entry is >= f * frame_nodes.
+__global__ void k_segment_bounds(const uint32_t* __restrict__ list, uint32_t n,
+                                 uint32_t frame_nodes, int frames, uint32_t* __restrict__ bounds) {
+  const int f = threadIdx.x;
+  if (f > frames) return;
+  const uint64_t key = (uint64_t)f * frame_nodes;
+  uint32_t lo = 0, hi = n;
+  while (lo < hi) {
+    const uint32_t mid = lo + (hi - lo) / 2;
+    if ((uint64_t)list[mid] < key) lo = mid + 1;
+    else hi = mid;
+  }
+  bounds[f] = lo;
+}
+
+void launch_segment_bounds(const uint32_t* list, uint32_t n, uint32_t frame_nodes, int frames,
+                           uint32_t* bounds, hipStream_t s) {
+  hipLaunchKernelGGL(k_segment_bounds, dim3(1), dim3(64), 0, s, list, n, frame_nodes, frames, bounds);
 }
 
 // Final level: export the 0/1 labels and flag mixed cells (8 corner labels differ).

@@ -66,6 +66,12 @@ class PifuRenderOpts(C.Structure):
                 ("tile_m", C.c_int32), ("max_waves", C.c_int32)]
 
 
+class PifuGridOut(C.Structure):
+    _fields_ = [("occ", C.c_void_p), ("labels", C.c_void_p), ("cells", C.c_void_p),
+                ("cells_cap", C.c_uint32), ("n_cells", C.c_uint32),
+                ("stats", C.POINTER(PifuLevelStats))]
+
+
 class PifuKernelProfile(C.Structure):
     _fields_ = [("launches", C.c_uint64), ("total_ms", C.c_double), ("flops", C.c_double),
                 ("bytes", C.c_double)]
@@ -79,7 +85,8 @@ EXPORTS = ["pifu_create", "pifu_destroy", "pifu_status_string",
            "pifu_render_view_workspace_size", "pifu_render_view",
            "pifu_eval_points_workspace_size", "pifu_eval_points",
            "pifu_profile_enable", "pifu_profile_read", "pifu_mlp_train_workspace_size",
-           "pifu_mlp_grad", "pifu_rmsprop_step"]
+           "pifu_mlp_grad", "pifu_rmsprop_step", "pifu_occupancy_grid_batched_workspace_size",
+           "pifu_occupancy_grid_batched"]
 
 _lib = None
 
@@ -118,6 +125,8 @@ def load_library():
     lib.pifu_mlp_grad.argtypes = [P, C.POINTER(PifuField), P, u32, PP, PP, P, P, sz, P]
     lib.pifu_rmsprop_step.argtypes = [P, C.POINTER(PifuMLP), PP, PP, PP, PP, C.c_float, C.c_float,
                                       C.c_float, P]
+    lib.pifu_occupancy_grid_batched_workspace_size.argtypes = [i32, PP, PP, C.POINTER(sz)]
+    lib.pifu_occupancy_grid_batched.argtypes = [P, i32, PP, PP, C.POINTER(PifuGridOut), P, sz, P]
     lib.pifu_profile_enable.argtypes = [P, i32]
     lib.pifu_profile_read.argtypes = [P, C.POINTER(PifuKernelProfile)]
     for name in EXPORTS:
@@ -378,3 +387,50 @@ def eval_points(field: DeviceField, pts, precision="fp32", guard_logit=1e-3, ban
                               sz.value, _stream(stream))
     _check(st, "pifu_eval_points")
     return logit, labels
+
+
+class BatchedGrid:
+    """Preallocated outputs + workspace for pifu_occupancy_grid_batched."""
+
+    def __init__(self, fields: Sequence[DeviceField], opts: Sequence[PifuGridOpts], device="cuda"):
+        lib = load_library()
+        self.fields = list(fields)
+        self.opts = list(opts)
+        n = len(fields)
+        self._f = (C.c_void_p * n)(*[C.addressof(f.struct) for f in self.fields])
+        self._o = (C.c_void_p * n)(*[C.addressof(o) for o in self.opts])
+        sz = C.c_size_t()
+        _check(lib.pifu_occupancy_grid_batched_workspace_size(n, self._f, self._o, C.byref(sz)),
+               "pifu_occupancy_grid_batched_workspace_size")
+        self.ws = torch.empty(sz.value, dtype=torch.uint8, device=device)
+        self.outs = (PifuGridOut * n)()
+        self.occ, self.labels, self.cells, self.stats = [], [], [], []
+        for i, o in enumerate(self.opts):
+            m = (1 << o.log2_final) + 1
+            occ = torch.empty((m, m, m), dtype=torch.float32, device=device)
+            lab = torch.empty((m, m, m), dtype=torch.uint8, device=device)
+            cap = min((m - 1) ** 3, 1 << 26)
+            cells = torch.empty(cap, dtype=torch.int32, device=device)
+            st = (PifuLevelStats * (o.log2_final - o.log2_coarse + 1))()
+            self.occ.append(occ)
+            self.labels.append(lab)
+            self.cells.append(cells)
+            self.stats.append(st)
+            self.outs[i].occ = occ.data_ptr()
+            self.outs[i].labels = lab.data_ptr()
+            self.outs[i].cells = cells.data_ptr()
+            self.outs[i].cells_cap = cap
+            self.outs[i].stats = C.cast(st, C.POINTER(PifuLevelStats))
+
+    def run(self, stream=None):
+        lib = load_library()
+        st = lib.pifu_occupancy_grid_batched(context(), len(self.fields), self._f, self._o,
+                                             self.outs, self.ws.data_ptr(), self.ws.numel(),
+                                             _stream(stream))
+        _check(st, "pifu_occupancy_grid_batched")
+
+    def result(self, i):
+        nc = self.outs[i].n_cells
+        return dict(occ=self.occ[i], labels=self.labels[i],
+                    cells=self.cells[i][:min(nc, self.outs[i].cells_cap)], n_cells=nc,
+                    stats=[s.as_dict() for s in self.stats[i]])
