@@ -309,6 +309,23 @@ int32_t pifu_rmsprop_step(pifu_ctx* ctx, const pifu_mlp* net, const float* const
                           const float* const* db, float* const* vW, float* const* vb, float lr,
                           float alpha, float eps, pifu_stream stream);
 
+/* ---------------------------------------------------------------- tile autotuner */
+
+/*
+ * Times every hidden layer of field->mlp (and field->surrogate, in BF16) with point
+ * tiles 64, 128 and 256 on m lattice points, and records the fastest tile per
+ * (precision, layer shape, batch-size bucket <= 8192 / <= 32768 / larger) in ctx;
+ * later calls with tile_m == 0 use it.  A tile within 3% of the fastest loses to
+ * 128, then to 64 (deterministic ties).  All tiles produce bit-identical results.
+ * chosen (host, nullable) receives one tile per timed layer.  Workspace as
+ * pifu_eval_points_workspace_size(field, precision, m).  Blocks until done.
+ */
+int32_t pifu_autotune_mlp(pifu_ctx* ctx, const pifu_field* field, int32_t precision, uint32_t m,
+                          int32_t* chosen, void* workspace, size_t workspace_bytes,
+                          pifu_stream stream);
+/* Forgets every autotuned tile of ctx. */
+int32_t pifu_autotune_clear(pifu_ctx* ctx);
+
 /* ---------------------------------------------------------------- kernel profiling */
 
 /* Kernel families timed by the built-in profiler (index into pifu_profile_read's array). */

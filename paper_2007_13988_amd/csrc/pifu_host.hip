@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <new>
 #include <vector>
 
@@ -22,6 +23,8 @@ struct ProfRecord {
 struct pifu_ctx {
   int device;
   uint32_t* host_counters;   // pinned, 64 words
+  // autotuned point tile per (precision, N, K, batch bucket); filled by pifu_autotune_mlp
+  std::map<uint64_t, int> tile_cache;
   bool prof_on = false;
   std::vector<hipEvent_t> events;
   std::vector<ProfRecord> pending;
@@ -276,7 +279,20 @@ struct EvalCtx {
   float guard;            // |logit| below which FP32 results are re-run in FP64
   float band = 0.f;       // |logit| below which BF16/FP8 results are re-run in FP32
   float sur_band = 0.f;   // |logit| below which surrogate results go to the full MLP
+  int tile_m = 0;         // forced point tile (64/128/256), 0 = autotuned or 128
 };
+
+int batch_bucket(uint32_t m) { return m <= 8192 ? 0 : (m <= 32768 ? 1 : 2); }
+
+uint64_t tile_key(int prec, int N, int K, uint32_t m) {
+  return ((uint64_t)prec << 48) | ((uint64_t)N << 32) | ((uint64_t)K << 8) | (uint64_t)batch_bucket(m);
+}
+
+int pick_tile(const EvalCtx& e, int prec, int N, int K, uint32_t m) {
+  if (e.tile_m) return e.tile_m;
+  auto it = e.ctx->tile_cache.find(tile_key(prec, N, K, m));
+  return it == e.ctx->tile_cache.end() ? 128 : it->second;
+}
 
 int read_counters(EvalCtx& e, int nwords) {
   HIP_TRY(hipMemcpyAsync(e.ctx->host_counters, e.counters, sizeof(uint32_t) * nwords,
@@ -369,7 +385,8 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
                          : prec == PIFU_PREC_BF16 ? PIFU_KERN_GEMM_BF16
                                                   : PIFU_KERN_GEMM_FP8;
         ProfScope ps(e.ctx, e.s, kind, 2.0 * m * g.N * (g.K1 + g.K2 + g.n_ext), 0.0);
-        if (launch_gemm(g, prec, 0, e.s)) return PIFU_ERR_UNSUPPORTED;
+        if (launch_gemm(g, prec, pick_tile(e, prec, g.N, g.K1 + g.K2, m), e.s))
+          return PIFU_ERR_UNSUPPORTED;
       }
       prev = out;
       out = (out == ew.hA) ? ew.hB : ew.hA;
@@ -789,6 +806,7 @@ int32_t pifu_occupancy_grid(pifu_ctx* ctx, const pifu_field* field, const pifu_g
   EvalCtx e{ctx, s, g.counters, opts->precision, opts->guard_logit};
   e.band = logit_band(opts->band_delta);
   e.sur_band = logit_band(opts->surrogate_delta);
+  e.tile_m = opts->tile_m;
   pack_field(g.fp, s);
   const Lat fin = g.lv[g.T].lat;
   if (eval_level) launch_fill_u8(eval_level, 255, fin.n(), s);
@@ -842,6 +860,7 @@ int32_t pifu_render_view(pifu_ctx* ctx, const pifu_field* occ_field, const pifu_
   EvalCtx e{ctx, s, g.counters, opts->precision, opts->guard_logit};
   e.band = logit_band(opts->band_delta);
   e.sur_band = logit_band(opts->surrogate_delta);
+  e.tile_m = opts->tile_m;
   pack_field(g.fp, s);
   pack_field(g.cp, s);
   double vd[12];
@@ -975,6 +994,120 @@ int32_t pifu_profile_enable(pifu_ctx* ctx, int32_t on) {
   ctx->prof_on = on != 0;
   ctx->pending.clear();
   std::memset(ctx->prof, 0, sizeof(ctx->prof));
+  return PIFU_OK;
+}
+
+// Autotuner: times every hidden layer of the field's network (and of its surrogate)
+// with point tiles 64, 128 and 256 on m gathered lattice points, and caches the
+// fastest per (precision, layer shape, batch bucket).  A tile within 3% of the
+// fastest loses to 128 (then to the smaller tile), so ties break deterministically.
+// All tiles give bit-identical results (same k order), so tuning never changes output.
+int32_t pifu_autotune_mlp(pifu_ctx* ctx, const pifu_field* field, int32_t precision, uint32_t m,
+                          int32_t* chosen, void* workspace, size_t workspace_bytes,
+                          pifu_stream stream) {
+  if (!ctx || !workspace || m == 0 || !field || field->kind != PIFU_FIELD_MLP)
+    return PIFU_ERR_INVALID_ARGUMENT;
+  size_t need = 0;
+  int r = pifu_eval_points_workspace_size(field, precision, m, &need);
+  if (r) return r;
+  if (workspace_bytes < need) return PIFU_ERR_WORKSPACE_TOO_SMALL;
+  Carver cv(workspace);
+  uint32_t* counters = cv.take<uint32_t>(kCounters);
+  uint32_t* iota = cv.take<uint32_t>(m);
+  FieldPrep fp;
+  carve_field(cv, field, precision, fp);
+  EvalWs ew;
+  carve_eval(cv, m, field->C, fp.mlp.max_hidden, ew);
+  (void)counters;
+  hipStream_t s = as_stream(stream);
+  pack_field(fp, s);
+  launch_iota(iota, m, s);
+  // points: the first m nodes of a 129^3 lattice (z fastest), i.e. whole columns
+  PointSrc src;
+  std::memset(&src, 0, sizeof(src));
+  src.mode = 0;
+  src.nx = src.ny = src.nz = 129;
+  const uint32_t mm = std::min<uint32_t>(m, ew.chunk);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return PIFU_ERR_HIP;
+  int out_i = 0;
+  for (int net = 0; net < 2; ++net) {
+    if (net == 1 && !fp.has_sur) break;
+    const MlpPrep& mp = net ? fp.sur : fp.mlp;
+    const int prec = net ? PIFU_PREC_BF16 : precision;
+    const bool b16 = prec != PIFU_PREC_FP32;
+    launch_gather(src, iota, mm, field->feat, field->H, field->W, field->C, ew.feat, b16, ew.ext, s);
+    const MLPDesc& d = mp.d;
+    const void* prev = nullptr;
+    void* out = ew.hA;
+    for (int l = 0; l + 1 < d.n_layers; ++l) {
+      GemmArgs g;
+      std::memset(&g, 0, sizeof(g));
+      if (l == 0) {
+        g.A1 = ew.feat;
+        g.K1 = field->C;
+        g.lda1 = field->C;
+        g.n_ext = d.n_extra;
+        g.ext_col = field->C;
+      } else {
+        g.A1 = prev;
+        g.K1 = g.lda1 = d.widths[l - 1];
+        if (d.skip[l]) {
+          g.A2 = ew.feat;
+          g.K2 = g.lda2 = field->C;
+        }
+      }
+      g.W = b16 ? (const void*)mp.Wp16[l] : (const void*)mp.Wp32[l];
+      g.ldw = mp.Kp[l];
+      g.Wf = d.W[l];
+      g.ldwf = d.in_w[l];
+      g.bias = d.b[l];
+      g.ext = ew.ext;
+      g.C = out;
+      g.ldc = g.N = d.widths[l];
+      g.M = (int)mm;
+      g.act = d.hidden_act;
+      g.scale = 1.f;
+      g.c_bf16 = b16 && (l + 2 < d.n_layers);
+      const int tiles[3] = {64, 128, 256};
+      float best[3];
+      for (int t = 0; t < 3; ++t) {
+        launch_gemm(g, prec, tiles[t], s);   // warm-up
+        float tot = 0.f;
+        for (int rep = 0; rep < 3; ++rep) {
+          (void)hipEventRecord(e0, s);
+          launch_gemm(g, prec, tiles[t], s);
+          (void)hipEventRecord(e1, s);
+          if (hipEventSynchronize(e1) != hipSuccess) return PIFU_ERR_HIP;
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          tot += ms;
+        }
+        best[t] = tot;
+      }
+      const float fastest = std::min(best[0], std::min(best[1], best[2]));
+      const int pref[3] = {1, 0, 2};   // 128, then 64, then 256
+      int pick = 128;
+      for (int q = 0; q < 3; ++q)
+        if (best[pref[q]] <= 1.03f * fastest) {
+          pick = tiles[pref[q]];
+          break;
+        }
+      ctx->tile_cache[tile_key(prec, g.N, g.K1 + g.K2, m)] = pick;
+      if (chosen && out_i < 2 * PIFU_MAX_LAYERS) chosen[out_i] = pick;
+      ++out_i;
+      prev = out;
+      out = out == ew.hA ? ew.hB : ew.hA;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return check_launch();
+}
+
+int32_t pifu_autotune_clear(pifu_ctx* ctx) {
+  if (!ctx) return PIFU_ERR_INVALID_ARGUMENT;
+  ctx->tile_cache.clear();
   return PIFU_OK;
 }
 
@@ -1390,6 +1523,7 @@ int32_t pifu_occupancy_grid_batched(pifu_ctx* ctx, int32_t n, const pifu_field* 
   EvalCtx e{ctx, s, b.counters, o.precision, o.guard_logit};
   e.band = logit_band(o.band_delta);
   e.sur_band = logit_band(o.surrogate_delta);
+  e.tile_m = o.tile_m;
   pack_field(b.fps[0], s);
   pifu_level_stats st[kMaxFrames];
   uint32_t bounds[kMaxFrames + 1];

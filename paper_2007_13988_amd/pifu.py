@@ -86,7 +86,7 @@ EXPORTS = ["pifu_create", "pifu_destroy", "pifu_status_string",
            "pifu_eval_points_workspace_size", "pifu_eval_points",
            "pifu_profile_enable", "pifu_profile_read", "pifu_mlp_train_workspace_size",
            "pifu_mlp_grad", "pifu_rmsprop_step", "pifu_occupancy_grid_batched_workspace_size",
-           "pifu_occupancy_grid_batched"]
+           "pifu_occupancy_grid_batched", "pifu_autotune_mlp", "pifu_autotune_clear"]
 
 _lib = None
 
@@ -127,6 +127,8 @@ def load_library():
                                       C.c_float, P]
     lib.pifu_occupancy_grid_batched_workspace_size.argtypes = [i32, PP, PP, C.POINTER(sz)]
     lib.pifu_occupancy_grid_batched.argtypes = [P, i32, PP, PP, C.POINTER(PifuGridOut), P, sz, P]
+    lib.pifu_autotune_mlp.argtypes = [P, C.POINTER(PifuField), i32, u32, C.POINTER(i32), P, sz, P]
+    lib.pifu_autotune_clear.argtypes = [P]
     lib.pifu_profile_enable.argtypes = [P, i32]
     lib.pifu_profile_read.argtypes = [P, C.POINTER(PifuKernelProfile)]
     for name in EXPORTS:
@@ -156,6 +158,28 @@ def context() -> C.c_void_p:
         _check(lib.pifu_create(C.byref(h)), "pifu_create")
         _ctx[dev] = h
     return _ctx[dev]
+
+
+def autotune(field: "DeviceField", precision="fp32", batch_sizes=(4096, 16384, 65536),
+             stream=None) -> Dict[int, List[int]]:
+    """Runs the library's tile autotuner for each batch-size bucket; returns the
+    chosen point tile per timed layer for each batch size."""
+    lib = load_library()
+    out = {}
+    for m in batch_sizes:
+        sz = C.c_size_t()
+        _check(lib.pifu_eval_points_workspace_size(C.byref(field.struct), PREC[precision], m,
+                                                   C.byref(sz)), "autotune workspace")
+        ws = torch.empty(sz.value, dtype=torch.uint8, device="cuda")
+        chosen = (C.c_int32 * 16)(*([0] * 16))
+        _check(lib.pifu_autotune_mlp(context(), C.byref(field.struct), PREC[precision], m, chosen,
+                                     ws.data_ptr(), sz.value, _stream(stream)), "pifu_autotune_mlp")
+        out[m] = [c for c in chosen if c]
+    return out
+
+
+def autotune_clear() -> None:
+    _check(load_library().pifu_autotune_clear(context()), "pifu_autotune_clear")
 
 
 def profile_enable(on: bool = True) -> None:

@@ -50,6 +50,24 @@ def test_batched_ellipsoid_frames_match_single_calls(pifu):
     _same(pifu, fields, [6, 7, 6, 7, 6, 7], 4)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_tile_choice_never_changes_results(pifu, prec):
+    """Forced point tiles 64/128/256 and the autotuned choice give identical grids."""
+    from paper_2007_13988_amd import pifu as PP
+    feat = synth.pifu_features(513)
+    spec = synth.pifu_mlp()
+    fld = pifu.DeviceField.mlp_field(feat, spec)
+    ref = pifu.occupancy_grid(fld, 6, 4, precision=prec, tile_m=128)
+    for t in (64, 256):
+        o = pifu.occupancy_grid(fld, 6, 4, precision=prec, tile_m=t)
+        assert torch.equal(o["labels"], ref["labels"]) and torch.equal(o["occ"], ref["occ"]), t
+    chosen = PP.autotune(fld, prec, batch_sizes=(4096, 16384))
+    assert all(c in (64, 128, 256) for v in chosen.values() for c in v) and chosen[4096]
+    o = pifu.occupancy_grid(fld, 6, 4, precision=prec)
+    assert torch.equal(o["labels"], ref["labels"]) and torch.equal(o["occ"], ref["occ"])
+    PP.autotune_clear()
+
+
 def test_batched_pifu_frames_bf16_match_single_calls(pifu):
     spec = synth.pifu_mlp()
     net = pifu.DeviceMLP(spec)
