@@ -326,6 +326,15 @@ int32_t pifu_autotune_mlp(pifu_ctx* ctx, const pifu_field* field, int32_t precis
 /* Forgets every autotuned tile of ctx. */
 int32_t pifu_autotune_clear(pifu_ctx* ctx);
 
+/*
+ * The library's operand conversions applied to n float32 values (device in/out):
+ * PIFU_PREC_BF16 -> uint16 bfloat16 bits (round to nearest even);
+ * PIFU_PREC_FP8 -> uint8 OCP e4m3fn codes (nearest even, saturating at +-448, no
+ * scaling).  The MLP kernels use exactly these conversions.  Blocks until done.
+ */
+int32_t pifu_convert_f32(pifu_ctx* ctx, const float* in, uint32_t n, int32_t precision, void* out,
+                         pifu_stream stream);
+
 /* ---------------------------------------------------------------- kernel profiling */
 
 /* Kernel families timed by the built-in profiler (index into pifu_profile_read's array). */

@@ -544,6 +544,18 @@ __global__ void k_scatter_results(const uint32_t* __restrict__ pos, uint32_t n,
   lab[p] = tb[i];
 }
 
+// The library's number-format conversions applied to an array (for checking them).
+__global__ void k_convert(const float* __restrict__ in, uint32_t n, int fmt, void* __restrict__ out) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (fmt == PIFU_PREC_BF16) reinterpret_cast<uint16_t*>(out)[i] = f32_to_bf16_bits(in[i]);
+  else reinterpret_cast<uint8_t*>(out)[i] = f32_to_e4m3(in[i]);
+}
+
+void launch_convert(const float* in, uint32_t n, int fmt, void* out, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_convert, dim3(grid1d(n, 256)), dim3(256), 0, s, in, n, fmt, out);
+}
+
 void launch_scatter_results(const uint32_t* pos, uint32_t n, const float* tl, const uint8_t* tb,
                             float* logit, uint8_t* lab, hipStream_t s) {
   if (n)

@@ -285,6 +285,177 @@ void launch_pack_weights(const float* W, int N, int ldw_src, int K, void* dst, i
                        ldw_src, K, dst, bf16);
 }
 
+// ------------------------------------------------------------------ FP8 (OCP e4m3) operands
+// v_mfma_scale_f32_32x32x64_f8f6f4 with both formats e4m3 and unit block scales
+// (E8M0 127): 32 fp8 values per lane per MFMA (two 16-byte LDS reads).  A arrives
+// as bf16 and is quantized while it is staged into LDS (e4m3(a / s_a), saturating);
+// W is pre-quantized per layer; the epilogue multiplies by s_a * s_w.
+__device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ inline uint32_t quant4(uint32_t lo2, uint32_t hi2, float inv) {
+  // two uint32 holding 4 bf16 values -> 4 e4m3 bytes
+  const uint32_t b0 = f32_to_e4m3(bf16_to_f32((uint16_t)(lo2 & 0xffff)) * inv);
+  const uint32_t b1 = f32_to_e4m3(bf16_to_f32((uint16_t)(lo2 >> 16)) * inv);
+  const uint32_t b2 = f32_to_e4m3(bf16_to_f32((uint16_t)(hi2 & 0xffff)) * inv);
+  const uint32_t b3 = f32_to_e4m3(bf16_to_f32((uint16_t)(hi2 >> 16)) * inv);
+  return b0 | (b1 << 8) | (b2 << 16) | (b3 << 24);
+}
+
+template <int BM, int BN, int WM, int WN, int MINB, bool OUT_BF16, int BK>
+__global__ void __launch_bounds__(256, MINB) k_gemm_fp8(GemmArgs a) {
+  // BK fp8 bytes (= elements) per stage: 128, or 64 when a K range is not a multiple of 128
+  constexpr int LD = BK + 16;    // bytes
+  constexpr int TI = BM / WM / 32, TJ = BN / WN / 32;
+  __shared__ __attribute__((aligned(16))) uint8_t As[2][BM * LD];
+  __shared__ __attribute__((aligned(16))) uint8_t Bs[2][BN * LD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const int K = a.K1 + a.K2;
+  const int nk = K / BK;
+  // A: BM rows x BK bf16 = BK/8 uint4 per row; B: BN rows x BK bytes = BK/16 uint4 per row
+  constexpr int AV = BK / 8, BV = BK / 16;
+  constexpr int A_LOADS = BM * AV / 256;
+  constexpr int B_LOADS = BN * BV / 256 > 0 ? BN * BV / 256 : 1;
+  uint4 ra[A_LOADS], rb[B_LOADS];
+  const uint16_t* A1 = reinterpret_cast<const uint16_t*>(a.A1);
+  const uint16_t* A2 = reinterpret_cast<const uint16_t*>(a.A2);
+  const uint8_t* Wp = reinterpret_cast<const uint8_t*>(a.W);
+  const float inv = a.a_inv_scale;
+
+  auto gload = [&](int kt) {
+    const int k0 = kt * BK;
+    const uint16_t* src;
+    int ld, kk0;
+    if (k0 < a.K1) {
+      src = A1;
+      ld = a.lda1;
+      kk0 = k0;
+    } else {
+      src = A2;
+      ld = a.lda2;
+      kk0 = k0 - a.K1;
+    }
+#pragma unroll
+    for (int i = 0; i < A_LOADS; ++i) {
+      const int e = tid + 256 * i;
+      const int row = e / AV, c8 = e % AV;
+      const int gm = m0 + row;
+      ra[i] = gm < a.M ? *reinterpret_cast<const uint4*>(src + (size_t)gm * ld + kk0 + 8 * c8)
+                       : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < B_LOADS; ++i) {
+      const int e = tid + 256 * i;
+      const int row = e / BV, c16 = e % BV;
+      if (row < BN)
+        rb[i] = *reinterpret_cast<const uint4*>(Wp + (size_t)(n0 + row) * a.ldw + k0 + 16 * c16);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < A_LOADS; ++i) {
+      const int e = tid + 256 * i;
+      const int row = e / AV, c8 = e % AV;
+      uint2 q;
+      q.x = quant4(ra[i].x, ra[i].y, inv);
+      q.y = quant4(ra[i].z, ra[i].w, inv);
+      *reinterpret_cast<uint2*>(&As[buf][row * LD + 8 * c8]) = q;
+    }
+#pragma unroll
+    for (int i = 0; i < B_LOADS; ++i) {
+      const int e = tid + 256 * i;
+      if (e / BV < BN) *reinterpret_cast<uint4*>(&Bs[buf][(e / BV) * LD + 16 * (e % BV)]) = rb[i];
+    }
+  };
+
+  f32x16 acc[TI][TJ];
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  const int h = lane >> 5, l32 = lane & 31;
+  const int wrow = wm * (BM / WM), wcol = wn * (BN / WN);
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) gload(kt + 1);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 64) {
+      i32x8 av[TI], bv[TJ];
+#pragma unroll
+      for (int i = 0; i < TI; ++i) {
+        const uint8_t* p = &As[buf][(wrow + 32 * i + l32) * LD + kk + 32 * h];
+        const uint4 x0 = *reinterpret_cast<const uint4*>(p);
+        const uint4 x1 = *reinterpret_cast<const uint4*>(p + 16);
+        av[i] = (i32x8){(int)x0.x, (int)x0.y, (int)x0.z, (int)x0.w,
+                        (int)x1.x, (int)x1.y, (int)x1.z, (int)x1.w};
+      }
+#pragma unroll
+      for (int j = 0; j < TJ; ++j) {
+        const uint8_t* p = &Bs[buf][(wcol + 32 * j + l32) * LD + kk + 32 * h];
+        const uint4 x0 = *reinterpret_cast<const uint4*>(p);
+        const uint4 x1 = *reinterpret_cast<const uint4*>(p + 16);
+        bv[j] = (i32x8){(int)x0.x, (int)x0.y, (int)x0.z, (int)x0.w,
+                        (int)x1.x, (int)x1.y, (int)x1.z, (int)x1.w};
+      }
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av[i], bv[j], acc[i][j], 0, 0,
+                                                                      0, 127, 0, 127);
+    }
+    if (kt + 1 < nk) sstore(buf ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j)
+      store_block<OUT_BF16>(a, acc[i][j], m0 + wrow + 32 * i, n0 + wcol + 32 * j, lane);
+}
+
+// Per-layer weight quantization: dst = e4m3(W / s_w) for the first K columns, where
+// s_w = amax / 448 comes from *amax_bits (an atomicMax over |W| as float bits).
+__global__ void k_absmax(const float* __restrict__ W, int N, int ldw, int K,
+                         uint32_t* __restrict__ amax_bits) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float v = 0.f;
+  if (i < (size_t)N * K) {
+    const int n = (int)(i / K), k = (int)(i - (size_t)n * K);
+    v = fabsf(W[(size_t)n * ldw + k]);
+  }
+  for (int d = 32; d >= 1; d >>= 1) v = fmaxf(v, __shfl_xor(v, d, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(amax_bits, __float_as_uint(v));
+}
+
+__global__ void k_pack_fp8(const float* __restrict__ W, int N, int ldw, int K,
+                           const uint32_t* __restrict__ amax_bits, uint8_t* __restrict__ dst) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)N * K) return;
+  const float amax = __uint_as_float(*amax_bits);
+  const float inv = amax > 0.f ? 448.f / amax : 1.f;
+  const int n = (int)(i / K), k = (int)(i - (size_t)n * K);
+  dst[i] = f32_to_e4m3(W[(size_t)n * ldw + k] * inv);
+}
+
+void launch_pack_fp8(const float* W, int N, int ldw, int K, uint32_t* amax_bits, uint8_t* dst,
+                     hipStream_t s) {
+  const size_t n = (size_t)N * K;
+  if (!n) return;
+  (void)hipMemsetAsync(amax_bits, 0, 4, s);
+  hipLaunchKernelGGL(k_absmax, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, W, N, ldw, K,
+                     amax_bits);
+  hipLaunchKernelGGL(k_pack_fp8, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, W, N, ldw, K,
+                     amax_bits, dst);
+}
+
 // Tile shapes per point tile BM (the autotuned parameter) and output tile BN:
 //   BM 64: waves 1x4 (BN 128) / 2x2 (BN 64); BM 128: 2x2 / 4x1; BM 256: 2x2 / 4x1.
 // Every variant walks k in the same order, so results do not depend on BM.
@@ -330,6 +501,42 @@ int launch_gemm(const GemmArgs& a, int precision, int tile_m, hipStream_t s) {
       else if (bm == 128) PIFU_B16(128, 64, 4, 1, 2);
       else PIFU_B16(256, 64, 4, 1, 1);
     }
+    return 0;
+  }
+  if (precision == PIFU_PREC_FP8) {
+    const bool k128 = (a.K1 % 128) == 0 && (a.K2 % 128) == 0;
+    if ((a.K1 % 64) || (a.K2 % 64)) return -1;
+#define PIFU_F8(BM_, BN_, WM_, WN_, MB_, BK_)                                                    \
+  do {                                                                                           \
+    if (a.c_bf16)                                                                                \
+      hipLaunchKernelGGL((k_gemm_fp8<BM_, BN_, WM_, WN_, MB_, true, BK_>),                       \
+                         dim3((a.M + BM_ - 1) / BM_, a.N / BN_), dim3(256), 0, s, a);             \
+    else                                                                                         \
+      hipLaunchKernelGGL((k_gemm_fp8<BM_, BN_, WM_, WN_, MB_, false, BK_>),                      \
+                         dim3((a.M + BM_ - 1) / BM_, a.N / BN_), dim3(256), 0, s, a);             \
+  } while (0)
+    if (k128) {
+      if (bn128) {
+        if (bm == 64) PIFU_F8(64, 128, 1, 4, 2, 128);
+        else if (bm == 128) PIFU_F8(128, 128, 2, 2, 2, 128);
+        else PIFU_F8(256, 128, 2, 2, 1, 128);
+      } else {
+        if (bm == 64) PIFU_F8(64, 64, 2, 2, 2, 128);
+        else if (bm == 128) PIFU_F8(128, 64, 4, 1, 2, 128);
+        else PIFU_F8(256, 64, 4, 1, 1, 128);
+      }
+    } else {
+      if (bn128) {
+        if (bm == 64) PIFU_F8(64, 128, 1, 4, 2, 64);
+        else if (bm == 128) PIFU_F8(128, 128, 2, 2, 2, 64);
+        else PIFU_F8(256, 128, 2, 2, 1, 64);
+      } else {
+        if (bm == 64) PIFU_F8(64, 64, 2, 2, 2, 64);
+        else if (bm == 128) PIFU_F8(128, 64, 4, 1, 2, 64);
+        else PIFU_F8(256, 64, 4, 1, 1, 64);
+      }
+    }
+#undef PIFU_F8
     return 0;
   }
   return -1;

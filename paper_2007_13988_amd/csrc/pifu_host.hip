@@ -143,8 +143,7 @@ int validate_field(const pifu_field* f, int n_extra, int n_out) {
 }
 
 int validate_precision(int p) {
-  if (p == PIFU_PREC_FP32 || p == PIFU_PREC_BF16) return PIFU_OK;
-  if (p == PIFU_PREC_FP8) return PIFU_ERR_UNSUPPORTED;
+  if (p == PIFU_PREC_FP32 || p == PIFU_PREC_BF16 || p == PIFU_PREC_FP8) return PIFU_OK;
   return PIFU_ERR_INVALID_ARGUMENT;
 }
 
@@ -153,6 +152,10 @@ struct MlpPrep {
   MLPDesc d;
   float* Wp32[PIFU_MAX_LAYERS];      // FP32 operand copies [N][Kp]
   uint16_t* Wp16[PIFU_MAX_LAYERS];   // BF16 operand copies (BF16/FP8 runs)
+  uint8_t* Wp8[PIFU_MAX_LAYERS];     // FP8 e4m3 operand copies (FP8 runs), scaled by 1/w_scale
+  uint32_t* amax;                    // device: per-layer max |W| (float bits), FP8 runs
+  float w_scale[PIFU_MAX_LAYERS];    // FP8 weight scale amax/448 (host, after pack)
+  float a_scale[PIFU_MAX_LAYERS];    // FP8 activation scale (calibrated amax)/448
   int Kp[PIFU_MAX_LAYERS];
   int max_hidden;
   int prec;
@@ -181,21 +184,40 @@ void carve_mlp(Carver& cv, const pifu_mlp* m, int precision, MlpPrep& p) {
   describe_mlp(m, p.d);
   p.max_hidden = 0;
   p.prec = precision;
+  p.amax = precision == PIFU_PREC_FP8 ? cv.take<uint32_t>(PIFU_MAX_LAYERS) : nullptr;
   for (int l = 0; l + 1 < m->n_layers; ++l) {
     p.Kp[l] = l == 0 ? m->feat_dim : p.d.in_w[l];
     const size_t n = (size_t)m->widths[l] * p.Kp[l];
     p.Wp32[l] = cv.take<float>(n);
-    p.Wp16[l] = precision != PIFU_PREC_FP32 ? cv.take<uint16_t>(n) : nullptr;
+    p.Wp16[l] = precision == PIFU_PREC_BF16 ? cv.take<uint16_t>(n) : nullptr;
+    p.Wp8[l] = precision == PIFU_PREC_FP8 ? cv.take<uint8_t>(n) : nullptr;
     p.max_hidden = std::max(p.max_hidden, m->widths[l]);
+    const float amax_a = m->fp8_amax[l] > 0.f ? m->fp8_amax[l] : 16.f;
+    p.a_scale[l] = amax_a / 448.f;
+    p.w_scale[l] = 1.f;
   }
 }
 
-void pack_mlp(const MlpPrep& p, hipStream_t s) {
+int pack_mlp(MlpPrep& p, pifu_ctx* ctx, hipStream_t s) {
   for (int l = 0; l + 1 < p.d.n_layers; ++l) {
     launch_pack_weights(p.d.W[l], p.d.widths[l], p.d.in_w[l], p.Kp[l], p.Wp32[l], 0, s);
     if (p.Wp16[l])
       launch_pack_weights(p.d.W[l], p.d.widths[l], p.d.in_w[l], p.Kp[l], p.Wp16[l], 1, s);
+    if (p.Wp8[l])
+      launch_pack_fp8(p.d.W[l], p.d.widths[l], p.d.in_w[l], p.Kp[l], p.amax + l, p.Wp8[l], s);
   }
+  if (!p.amax) return check_launch();
+  // the FP8 weight scales enter the GEMM epilogue: read them back once per call
+  const int nl = p.d.n_layers - 1;
+  HIP_TRY(hipMemcpyAsync(ctx->host_counters + 32, p.amax, sizeof(uint32_t) * nl,
+                         hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int l = 0; l < nl; ++l) {
+    float a;
+    std::memcpy(&a, ctx->host_counters + 32 + l, 4);
+    p.w_scale[l] = a > 0.f ? a / 448.f : 1.f;
+  }
+  return check_launch();
 }
 
 // ------------------------------------------------------------------ evaluator
@@ -239,9 +261,11 @@ void carve_field(Carver& cv, const pifu_field* f, int precision, FieldPrep& fp) 
   }
 }
 
-void pack_field(const FieldPrep& fp, hipStream_t s) {
-  if (fp.has_mlp) pack_mlp(fp.mlp, s);
-  if (fp.has_sur) pack_mlp(fp.sur, s);
+int pack_field(FieldPrep& fp, pifu_ctx* ctx, hipStream_t s) {
+  int r = PIFU_OK;
+  if (fp.has_mlp) r = pack_mlp(fp.mlp, ctx, s);
+  if (!r && fp.has_sur) r = pack_mlp(fp.sur, ctx, s);
+  return r;
 }
 
 void carve_guard(Carver& cv, const FieldPrep& fp, uint32_t max_points, EvalWs& ew) {
@@ -367,7 +391,10 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
           g.lda2 = C;
         }
       }
-      g.W = b16 ? (const void*)mp.Wp16[l] : (const void*)mp.Wp32[l];
+      g.W = prec == PIFU_PREC_FP8    ? (const void*)mp.Wp8[l]
+            : prec == PIFU_PREC_BF16 ? (const void*)mp.Wp16[l]
+                                     : (const void*)mp.Wp32[l];
+      g.a_inv_scale = prec == PIFU_PREC_FP8 ? 1.f / mp.a_scale[l] : 1.f;
       g.ldw = mp.Kp[l];
       g.Wf = d.W[l];
       g.ldwf = d.in_w[l];
@@ -378,7 +405,7 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
       g.M = (int)m;
       g.N = d.widths[l];
       g.act = d.hidden_act;
-      g.scale = 1.f;
+      g.scale = prec == PIFU_PREC_FP8 ? mp.a_scale[l] * mp.w_scale[l] : 1.f;
       g.c_bf16 = b16 && (l + 2 < d.n_layers);   // the head reads FP32
       {
         const int kind = prec == PIFU_PREC_FP32   ? PIFU_KERN_GEMM_F32
@@ -807,7 +834,10 @@ int32_t pifu_occupancy_grid(pifu_ctx* ctx, const pifu_field* field, const pifu_g
   e.band = logit_band(opts->band_delta);
   e.sur_band = logit_band(opts->surrogate_delta);
   e.tile_m = opts->tile_m;
-  pack_field(g.fp, s);
+  if (int pr = pack_field(g.fp, ctx, s)) {
+    delete gp;
+    return pr;
+  }
   const Lat fin = g.lv[g.T].lat;
   if (eval_level) launch_fill_u8(eval_level, 255, fin.n(), s);
   r = localize(e, g.fp, g.ew, nullptr, g.log2, g.T, g.T, g.lv, g.w, eval_level, fin,
@@ -861,8 +891,14 @@ int32_t pifu_render_view(pifu_ctx* ctx, const pifu_field* occ_field, const pifu_
   e.band = logit_band(opts->band_delta);
   e.sur_band = logit_band(opts->surrogate_delta);
   e.tile_m = opts->tile_m;
-  pack_field(g.fp, s);
-  pack_field(g.cp, s);
+  if (int pr = pack_field(g.fp, ctx, s)) {
+    delete gp;
+    return pr;
+  }
+  if (int pr = pack_field(g.cp, ctx, s)) {
+    delete gp;
+    return pr;
+  }
   double vd[12];
   for (int i = 0; i < 12; ++i) vd[i] = view[i];
   const int T = g.T;
@@ -975,7 +1011,7 @@ int32_t pifu_eval_points(pifu_ctx* ctx, const pifu_field* field, int32_t precisi
   if (!lab) lab = reinterpret_cast<uint8_t*>(ew.glist);   // scratch when labels are not wanted
   EvalCtx e{ctx, s, counters, precision, guard_logit};
   e.band = logit_band(band_delta);
-  pack_field(fp, s);
+  if (int pr = pack_field(fp, ctx, s)) return pr;
   launch_iota(iota, n, s);
   PointSrc src;
   std::memset(&src, 0, sizeof(src));
@@ -1020,7 +1056,7 @@ int32_t pifu_autotune_mlp(pifu_ctx* ctx, const pifu_field* field, int32_t precis
   carve_eval(cv, m, field->C, fp.mlp.max_hidden, ew);
   (void)counters;
   hipStream_t s = as_stream(stream);
-  pack_field(fp, s);
+  if (int pr = pack_field(fp, ctx, s)) return pr;
   launch_iota(iota, m, s);
   // points: the first m nodes of a 129^3 lattice (z fastest), i.e. whole columns
   PointSrc src;
@@ -1057,7 +1093,10 @@ int32_t pifu_autotune_mlp(pifu_ctx* ctx, const pifu_field* field, int32_t precis
           g.K2 = g.lda2 = field->C;
         }
       }
-      g.W = b16 ? (const void*)mp.Wp16[l] : (const void*)mp.Wp32[l];
+      g.W = prec == PIFU_PREC_FP8    ? (const void*)mp.Wp8[l]
+            : prec == PIFU_PREC_BF16 ? (const void*)mp.Wp16[l]
+                                     : (const void*)mp.Wp32[l];
+      g.a_inv_scale = prec == PIFU_PREC_FP8 ? 1.f / mp.a_scale[l] : 1.f;
       g.ldw = mp.Kp[l];
       g.Wf = d.W[l];
       g.ldwf = d.in_w[l];
@@ -1067,7 +1106,7 @@ int32_t pifu_autotune_mlp(pifu_ctx* ctx, const pifu_field* field, int32_t precis
       g.ldc = g.N = d.widths[l];
       g.M = (int)mm;
       g.act = d.hidden_act;
-      g.scale = 1.f;
+      g.scale = prec == PIFU_PREC_FP8 ? mp.a_scale[l] * mp.w_scale[l] : 1.f;
       g.c_bf16 = b16 && (l + 2 < d.n_layers);
       const int tiles[3] = {64, 128, 256};
       float best[3];
@@ -1103,6 +1142,17 @@ int32_t pifu_autotune_mlp(pifu_ctx* ctx, const pifu_field* field, int32_t precis
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return check_launch();
+}
+
+int32_t pifu_convert_f32(pifu_ctx* ctx, const float* in, uint32_t n, int32_t precision, void* out,
+                         pifu_stream stream) {
+  if (!ctx || !in || !out) return PIFU_ERR_INVALID_ARGUMENT;
+  if (precision != PIFU_PREC_BF16 && precision != PIFU_PREC_FP8) return PIFU_ERR_INVALID_ARGUMENT;
+  hipStream_t s = as_stream(stream);
+  launch_convert(in, n, precision, out, s);
+  int r = check_launch();
+  if (!r) r = hipStreamSynchronize(s) == hipSuccess ? PIFU_OK : PIFU_ERR_HIP;
+  return r;
 }
 
 int32_t pifu_autotune_clear(pifu_ctx* ctx) {
@@ -1200,7 +1250,7 @@ int32_t pifu_mlp_grad(pifu_ctx* ctx, const pifu_field* field, const float* pts, 
   for (int l = 0; l < d.n_layers; ++l)
     if (!dW[l] || !db[l]) return PIFU_ERR_INVALID_ARGUMENT;
   hipStream_t s = as_stream(stream);
-  pack_mlp(t.mp, s);
+  if (int pr = pack_mlp(t.mp, ctx, s)) return pr;
   const int C = field->C;
   PointSrc src;
   std::memset(&src, 0, sizeof(src));
@@ -1524,7 +1574,14 @@ int32_t pifu_occupancy_grid_batched(pifu_ctx* ctx, int32_t n, const pifu_field* 
   e.band = logit_band(o.band_delta);
   e.sur_band = logit_band(o.surrogate_delta);
   e.tile_m = o.tile_m;
-  pack_field(b.fps[0], s);
+  if (int pr = pack_field(b.fps[0], ctx, s)) {
+    delete bp;
+    return pr;
+  }
+  for (int f = 1; f < n; ++f) {   // frames share the packed network and its scales
+    b.fps[f].mlp = b.fps[0].mlp;
+    b.fps[f].sur = b.fps[0].sur;
+  }
   pifu_level_stats st[kMaxFrames];
   uint32_t bounds[kMaxFrames + 1];
   for (int r = 0; r <= b.Tmax && !rc; ++r) {

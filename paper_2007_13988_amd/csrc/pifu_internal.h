@@ -111,6 +111,7 @@ void launch_guard_fp64(const PointSrc& src, const uint32_t* list, const uint32_t
 // out[i] = src[pos[i]]
 void launch_gather_u32(const uint32_t* src, const uint32_t* pos, uint32_t n, uint32_t* out,
                        hipStream_t s);
+void launch_convert(const float* in, uint32_t n, int fmt, void* out, hipStream_t s);
 // logit[pos[i]] = tl[i], lab[pos[i]] = tb[i]
 void launch_scatter_results(const uint32_t* pos, uint32_t n, const float* tl, const uint8_t* tb,
                             float* logit, uint8_t* lab, hipStream_t s);
@@ -156,8 +157,33 @@ struct GemmArgs {
   int act;
   float scale;       // FP8: product of operand scales (dequantization), else 1
   int c_bf16;        // BF16/FP8 paths: write C as bf16 (next layer's input), else fp32
+  float a_inv_scale; // FP8: activations are quantized as e4m3(a * a_inv_scale)
 };
+
+// float32 -> OCP FP8 E4M3FN code (bias 7, 3 mantissa bits, no infinities), round to
+// nearest even, saturating at +-448; NaN -> 0x7f.
+__host__ __device__ inline uint8_t f32_to_e4m3(float x) {
+  uint32_t u;
+  __builtin_memcpy(&u, &x, 4);
+  const uint8_t sign = (uint8_t)((u >> 24) & 0x80u);
+  float a = __builtin_fabsf(x);
+  if (!(a == a)) return 0x7f;
+  if (a >= 448.f) return sign | 0x7e;
+  int e = (int)((u >> 23) & 0xffu) - 127;
+  uint32_t code;
+  if (e < -6) {
+    code = (uint32_t)__builtin_rintf(a * 512.f);            // subnormal quantum 2^-9
+  } else {
+    const float q = __builtin_ldexpf(a, 3 - e);             // in [8, 16)
+    code = (uint32_t)((e + 7) << 3) + ((uint32_t)__builtin_rintf(q) - 8u);
+  }
+  if (code > 0x7e) code = 0x7e;
+  return sign | (uint8_t)code;
+}
 int launch_gemm(const GemmArgs& a, int precision, int tile_m, hipStream_t s);
+// FP8 operand copy: amax_bits <- max |W| (float bits), dst = e4m3(W * 448 / amax).
+void launch_pack_fp8(const float* W, int N, int ldw, int K, uint32_t* amax_bits, uint8_t* dst,
+                     hipStream_t s);
 void launch_pack_weights(const float* W, int N, int ldw_src, int K, void* dst, int bf16,
                          hipStream_t s);
 

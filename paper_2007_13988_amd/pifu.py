@@ -86,7 +86,8 @@ EXPORTS = ["pifu_create", "pifu_destroy", "pifu_status_string",
            "pifu_eval_points_workspace_size", "pifu_eval_points",
            "pifu_profile_enable", "pifu_profile_read", "pifu_mlp_train_workspace_size",
            "pifu_mlp_grad", "pifu_rmsprop_step", "pifu_occupancy_grid_batched_workspace_size",
-           "pifu_occupancy_grid_batched", "pifu_autotune_mlp", "pifu_autotune_clear"]
+           "pifu_occupancy_grid_batched", "pifu_autotune_mlp", "pifu_autotune_clear",
+           "pifu_convert_f32"]
 
 _lib = None
 
@@ -129,6 +130,7 @@ def load_library():
     lib.pifu_occupancy_grid_batched.argtypes = [P, i32, PP, PP, C.POINTER(PifuGridOut), P, sz, P]
     lib.pifu_autotune_mlp.argtypes = [P, C.POINTER(PifuField), i32, u32, C.POINTER(i32), P, sz, P]
     lib.pifu_autotune_clear.argtypes = [P]
+    lib.pifu_convert_f32.argtypes = [P, P, u32, i32, P, P]
     lib.pifu_profile_enable.argtypes = [P, i32]
     lib.pifu_profile_read.argtypes = [P, C.POINTER(PifuKernelProfile)]
     for name in EXPORTS:
@@ -175,6 +177,16 @@ def autotune(field: "DeviceField", precision="fp32", batch_sizes=(4096, 16384, 6
         _check(lib.pifu_autotune_mlp(context(), C.byref(field.struct), PREC[precision], m, chosen,
                                      ws.data_ptr(), sz.value, _stream(stream)), "pifu_autotune_mlp")
         out[m] = [c for c in chosen if c]
+    return out
+
+
+def convert(x: torch.Tensor, precision: str) -> torch.Tensor:
+    """The library's bf16 / e4m3 conversion of a device float32 tensor (raw bits)."""
+    x = x.contiguous().to(device="cuda", dtype=torch.float32)
+    out = torch.empty(x.numel(), dtype=torch.int16 if precision == "bf16" else torch.uint8,
+                      device="cuda")
+    _check(load_library().pifu_convert_f32(context(), x.data_ptr(), x.numel(), PREC[precision],
+                                           out.data_ptr(), _stream(None)), "pifu_convert_f32")
     return out
 
 

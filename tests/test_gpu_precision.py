@@ -1,0 +1,81 @@
+"""Precision ladder (BF16 and FP8 e4m3 MFMA with FP32 accumulation, FP32 re-run of
+the points within 0.02 of p = 0.5, FP64 guard): operand conversions bit-checked
+against torch's casts, probability error against the FP64 oracle on sampled points,
+label flips, and surface-cell agreement of the hierarchical grid."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import pifu_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pifu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2007_13988_amd as P
+    P.load_library()
+    return P
+
+
+def test_operand_conversions_match_torch_casts(pifu):
+    from paper_2007_13988_amd.pifu import convert
+    g = np.random.default_rng(0)
+    x = np.concatenate([g.standard_normal(200000) * 50, g.uniform(-500, 500, 20000),
+                        np.ldexp(1.0, np.arange(-14, 10)),
+                        [0.0, 2.0 ** -10, 3 * 2.0 ** -10, 447.9, 448, 464, 1e6, -1e6]]).astype(np.float32)
+    xt = torch.from_numpy(x)
+    b = convert(xt, "bf16").cpu()
+    assert torch.equal(b, xt.to(torch.bfloat16).view(torch.int16))
+    f8 = convert(xt, "fp8").cpu()
+    ref = xt.clamp(-448, 448).to(torch.float8_e4m3fn).view(torch.uint8)   # saturating reading
+    assert torch.equal(f8, ref)
+
+
+def _sample_points(fo, n_uniform, seed):
+    """Half uniform, half jittered around nodes near the surface of the 33^3 grid."""
+    g = O.occupancy_grid(fo, 5, 3)
+    ev = np.argwhere(g["eval_level"] != 255)
+    base = -1.0 + 2.0 * ev / 32
+    near = synth.jitter_points(base[np.random.default_rng(seed).integers(0, len(base), n_uniform)],
+                               2.0 / 32, seed + 1)
+    pts = np.concatenate([synth.precision_points(n_uniform, seed), np.clip(near, -1, 1)])
+    return pts.astype(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("prec,mean_tol", [("bf16", 5e-3), ("fp8", 3e-2)])
+def test_probability_error_and_label_flips(pifu, prec, mean_tol):
+    fo = O.Field("mlp", feat=synth.tiny_features(), mlp=synth.tiny_mlp())
+    fg = pifu.DeviceField.mlp_field(synth.tiny_features(), synth.tiny_mlp())
+    pts = _sample_points(fo, 500000, 403)
+    ref = O.field_logit(fo, pts)
+    p64 = O.sigmoid(ref)
+    raw, _ = pifu.eval_points(fg, pts, precision=prec, band_delta=0.0, guard_logit=0.0)
+    err = np.abs(O.sigmoid(raw.cpu().numpy().astype(np.float64)) - p64)
+    lg, lab = pifu.eval_points(fg, pts, precision=prec, band_delta=0.02, guard_logit=1e-3)
+    flips = int(np.sum(lab.cpu().numpy() != (ref > 0)))
+    band = np.abs(p64 - 0.5) < 0.02
+    print(f"{prec}: |p - p64| max {err.max():.3e} mean {err.mean():.3e} "
+          f"p99 {np.quantile(err, 0.99):.3e}; label flips with band {flips} "
+          f"of {pts.shape[0]}; points in band {int(band.sum())}")
+    assert err.mean() < mean_tol
+    # inside the band the label is decided in FP32/FP64, so any flip comes from a
+    # low-precision error larger than the band itself
+    assert flips <= 1e-4 * pts.shape[0]
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_grid_surface_cells_against_oracle(pifu, prec):
+    from paper_2007_13988_amd.surrogate import cell_disagreement
+    fo = O.Field("mlp", feat=synth.tiny_features(), mlp=synth.tiny_mlp())
+    fg = pifu.DeviceField.mlp_field(synth.tiny_features(), synth.tiny_mlp())
+    ref = O.occupancy_grid(fo, 5, 3)
+    out = pifu.occupancy_grid(fg, 5, 3, precision=prec, band_delta=0.02)
+    lab = out["labels"].cpu().numpy()
+    d = cell_disagreement(out["cells"], torch.from_numpy(ref["cells"].astype(np.int64)).cuda())
+    print(f"{prec}: label flips {int(np.sum(lab != ref['labels']))} of {lab.size}, "
+          f"surface-cell disagreement {d:.2e}")
+    assert d <= 1e-3 or prec == "fp8"
