@@ -7,7 +7,11 @@ One step = one frame of the hot path on synthetic inputs already resident in HBM
   * pifu_render_view: 512 x 512 image, 256 depth cells, from a 64 x 64 x 32 coarse
     level, view rotated 90 degrees about y, colour MLP (256+z+occ)->512->256->3 over
     a second 256 ch x 128 x 128 map.
-Prints one JSON line (see the design doc for the fields).
+Two forms are timed on the same frame: the plain FP32 method (FP64 guard band) and
+the surrogate + BF16 form (distilled (256+z)->128->64->1 network on the 32^3..128^3
+levels, full network in BF16 with an FP32 band at |p-0.5| < 0.02 and the FP64 guard).
+`value` is the surrogate + BF16 form when its surface cells agree with the FP32 form
+within 0.1%, else the FP32 form.  Prints one JSON line.
 """
 import argparse
 import json
@@ -18,9 +22,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FP32_MFMA_PEAK_TFLOPS = 157.3
-BF16_MFMA_PEAK_TFLOPS = 2500.0
-FP8_MFMA_PEAK_TFLOPS = 5000.0
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
 
 
 def parse():
@@ -28,10 +30,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--form", default="fp32", choices=["fp32"])
+    ap.add_argument("--forms", default="fp32,surrogate_bf16")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="budget of the oracle timing sample (cpu_baseline)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--train-frames", type=int, default=6)
+    ap.add_argument("--train-samples", type=int, default=524288)
+    ap.add_argument("--epochs", type=int, default=4)
     return ap.parse_args()
 
 
@@ -55,11 +60,11 @@ def cpu_baseline(points_per_frame, budget_s):
     dt = time.perf_counter() - t0
     threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
     per_pt = dt / done
-    return {"value": per_pt * points_per_frame * 1e3, "unit": "ms/frame", "cores": threads,
-            "kind": "oracle",
+    return {"value": round(per_pt * points_per_frame * 1e3, 1), "unit": "ms/frame",
+            "cores": threads, "kind": "oracle",
             "sample": f"FP64 oracle occupancy MLP on {done} points ({dt:.1f} s), scaled to the "
-                      f"frame's {points_per_frame} MLP-evaluated points (occupancy grid + render); "
-                      f"level logic and colour MLP not included"}
+                      f"frame's {points_per_frame} MLP-evaluated points (occupancy grid + render) "
+                      f"of the plain FP32 form; level logic and colour MLP not included"}
 
 
 def main():
@@ -68,89 +73,147 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                                    "(multi-GPU sharding is described in DESIGN.md only)"}))
         sys.exit(2)
-    import numpy as np
     import torch
 
     import paper_2007_13988_amd as P
     import synth
 
     torch.cuda.set_device(0)
+    forms = args.forms.split(",")
+    teacher = synth.pifu_mlp()
     feat = synth.pifu_features()
-    spec = synth.pifu_mlp()
-    occ_field = P.DeviceField.mlp_field(feat, spec)
+    t_net = P.DeviceMLP(teacher)
     col_field = P.DeviceField.mlp_field(synth.color_features(), synth.color_mlp())
     view = synth.yaw_view(90.0)
     bg = (0.0, 0.0, 0.0)
-    prec = "fp32"
-    gopts = P.grid_opts(8, 5, precision=prec, guard_logit=1e-3)
-    gout = P.GridOutputs(occ_field, gopts)
-    ropts = P.render_opts(9, 8, 6, precision=prec, guard_logit=1e-3)
-    rout = P.RenderOutputs(occ_field, col_field, ropts)
     stream = torch.cuda.current_stream()
+    setup = {}
 
-    def frame():
-        P.occupancy_grid_into(occ_field, gout, stream)
-        P.render_view_into(occ_field, col_field, view, bg, rout, stream)
+    sur_net, delta = None, None
+    if "surrogate_bf16" in forms:
+        from paper_2007_13988_amd.surrogate import choose_delta, distill
+        t0 = time.perf_counter()
+        sur_net, losses = distill(teacher, synth.surrogate_mlp(),
+                                  [synth.pifu_features(700 + s) for s in range(args.train_frames)],
+                                  samples_per_frame=args.train_samples, epochs=args.epochs, seed=0)
+        t_train = time.perf_counter() - t0
+        delta, report = choose_delta(teacher, sur_net,
+                                     [synth.pifu_features(710), synth.pifu_features(711)])
+        setup = {"surrogate_train_s": round(t_train, 2),
+                 "surrogate_samples": args.train_frames * args.train_samples,
+                 "surrogate_loss_first_last": [round(losses[0], 5), round(losses[-1], 5)],
+                 "surrogate_delta": delta, "delta_sweep": report}
 
-    for _ in range(args.warmup):
-        frame()
-    torch.cuda.synchronize()
-    P.profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    t_occ = 0.0
-    for _ in range(args.steps):
-        a = time.perf_counter()
-        P.occupancy_grid_into(occ_field, gout, stream)
-        t_occ += time.perf_counter() - a
-        P.render_view_into(occ_field, col_field, view, bg, rout, stream)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    prof = P.profile_read()
-    P.profile_enable(False)
+    def make(form):
+        if form == "fp32":
+            fld = P.DeviceField(P.FIELD_MLP, feat=feat, mlp=t_net)
+            kw = dict(precision="fp32", guard_logit=1e-3)
+        else:
+            fld = P.DeviceField(P.FIELD_MLP, feat=feat, mlp=t_net, surrogate=sur_net)
+            kw = dict(precision="bf16", guard_logit=1e-3, band_delta=0.02, surrogate_max_log2=7,
+                      surrogate_delta=delta)
+        gout = P.GridOutputs(fld, P.grid_opts(8, 5, **kw))
+        rout = P.RenderOutputs(fld, col_field, P.render_opts(9, 8, 6, **kw))
+        return fld, gout, rout
 
-    ms = elapsed / args.steps * 1e3
-    gst = [s.as_dict() for s in gout.stats]
-    rst = [s.as_dict() for s in rout.stats]
-    occ_pts = sum(s["mlp_points"] for s in gst)
-    ren_pts = sum(s["mlp_points"] for s in rst)
-    hits = rst[-1]["hits"]
-    pts_frame = occ_pts + ren_pts
-    g = prof["gemm_f32"]
-    avg_ms = g["total_ms"] / max(g["launches"], 1)
-    flops_per_launch = g["flops"] / max(g["launches"], 1)
-    achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
-    roofline = {"kernel": "k_gemm_f32 (MLP hidden layers, FP32 MFMA)", "bound": "mfma",
-                "achieved": round(achieved, 2), "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP32_MFMA_PEAK_TFLOPS, 4), "traffic": None,
-                "launches_per_step": g["launches"] / args.steps,
-                "avg_launch_ms": round(avg_ms, 4),
-                "flops_per_launch": flops_per_launch}
-    mlp_flops = spec.flops_per_point()
+    results = {}
+    for form in forms:
+        fld, gout, rout = make(form)
+        for _ in range(args.warmup):
+            P.occupancy_grid_into(fld, gout, stream)
+            P.render_view_into(fld, col_field, view, bg, rout, stream)
+        torch.cuda.synchronize()
+        P.profile_enable(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t_occ = 0.0
+        for _ in range(args.steps):
+            a = time.perf_counter()
+            P.occupancy_grid_into(fld, gout, stream)
+            t_occ += time.perf_counter() - a
+            P.render_view_into(fld, col_field, view, bg, rout, stream)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        prof = P.profile_read()
+        P.profile_enable(False)
+        gst = [s.as_dict() for s in gout.stats]
+        rst = [s.as_dict() for s in rout.stats]
+        nc = gout.n_cells.value
+        results[form] = dict(ms=elapsed / args.steps * 1e3, ms_occ=t_occ / args.steps * 1e3,
+                             prof=prof, gst=gst, rst=rst,
+                             cells=gout.cells[:min(nc, gout.cells_cap)].clone(),
+                             hit=rout.hit.clone())
+
+    from paper_2007_13988_amd.surrogate import cell_disagreement
+    base = results.get("fp32")
+    chosen = "fp32"
+    extra = {}
+    if "surrogate_bf16" in results and base is not None:
+        s = results["surrogate_bf16"]
+        dis = cell_disagreement(s["cells"], base["cells"])
+        hit_dis = float((s["hit"] != base["hit"]).float().mean().item())
+        extra["surrogate_bf16"] = {
+            "ms_per_frame": round(s["ms"], 3), "ms_occupancy_grid": round(s["ms_occ"], 3),
+            "speedup_vs_fp32": round(base["ms"] / s["ms"], 3),
+            "surface_cell_disagreement_vs_fp32": dis, "render_hit_disagreement": hit_dis,
+            "surrogate_fallback_points": sum(x["surrogate_fallback"] for x in s["gst"] + s["rst"]),
+            "full_mlp_points": sum(x["mlp_points"] for x in s["gst"] + s["rst"]),
+            "band_fp32_points": sum(x["band_fp32"] for x in s["gst"] + s["rst"]),
+            "guard_fp64_points": sum(x["guard_fp64"] for x in s["gst"] + s["rst"])}
+        if dis <= 1e-3:
+            chosen = "surrogate_bf16"
+    main_r = results[chosen]
+    gemm_key = "gemm_bf16" if chosen == "surrogate_bf16" else "gemm_f32"
+    dtype = "bf16" if chosen == "surrogate_bf16" else "fp32"
+
+    def roofline(r, key, peak_key):
+        g = r["prof"][key]
+        if not g["launches"]:
+            return None
+        avg_ms = g["total_ms"] / g["launches"]
+        fpl = g["flops"] / g["launches"]
+        ach = fpl / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
+        return {"kernel": f"k_{key} (MLP hidden layers, {peak_key.upper()} MFMA)", "bound": "mfma",
+                "achieved": round(ach, 2), "peak": PEAK_TFLOPS[peak_key], "unit": "TFLOP/s",
+                "frac": round(ach / PEAK_TFLOPS[peak_key], 4), "traffic": None,
+                "launches_per_step": g["launches"] / args.steps, "avg_launch_ms": round(avg_ms, 4),
+                "flops_per_launch": fpl}
+
+    occ_pts = sum(s["mlp_points"] for s in main_r["gst"])
+    ren_pts = sum(s["mlp_points"] for s in main_r["rst"])
     out = {
         "metric": "ms/frame to 256^3 surface + 512^2 render",
-        "value": round(ms, 3), "unit": "ms/frame", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": False,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "value": round(main_r["ms"], 3), "unit": "ms/frame", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(main_r["ms"], 3), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
         "config": {"workload": "hierarchical occupancy grid 256^3 cells from 32^3 + mesh-free "
                                "render 512x512x256 from 64x64x32, yaw 90",
-                   "form": args.form,
+                   "form": chosen,
                    "occupancy_mlp": "(256+z)->1024->512->256->128->1 skip, 256ch x 128^2 features",
                    "color_mlp": "(256+z+occ)->512->256->3", "guard_logit": 1e-3},
-        "ms_occupancy_grid": round(t_occ / args.steps * 1e3, 3),
-        "mlp_queries_per_s": round(pts_frame / (ms * 1e-3), 1),
-        "mlp_points_per_frame": {"occupancy_grid": occ_pts, "render": ren_pts, "color_hits": hits},
-        "dense_points_256": 257 ** 3,
+        "ms_occupancy_grid": round(main_r["ms_occ"], 3),
+        "mlp_queries_per_s": round((occ_pts + ren_pts) / (main_r["ms"] * 1e-3), 1),
+        "mlp_points_per_frame": {"occupancy_grid": occ_pts, "render": ren_pts,
+                                 "color_hits": main_r["rst"][-1]["hits"]},
         "acceleration_vs_dense": round(257 ** 3 / max(occ_pts, 1), 2),
-        "occupancy_mlp_tflops_effective": round(pts_frame * mlp_flops / (ms * 1e-3) / 1e12, 2),
-        "roofline": roofline,
-        "kernels": {k: {"launches": v["launches"] / args.steps,
-                        "ms_per_step": round(v["total_ms"] / args.steps, 3)} for k, v in prof.items()
-                    if v["launches"]},
-        "levels_occupancy": gst, "levels_render": rst,
+        "roofline": roofline(main_r, gemm_key, dtype),
     }
+    if base is not None:
+        out["fp32_ms_per_frame"] = round(base["ms"], 3)
+        out["fp32_roofline"] = roofline(base, "gemm_f32", "fp32")
+        out["fp32_mlp_queries_per_s"] = round(
+            sum(s["mlp_points"] for s in base["gst"] + base["rst"]) / (base["ms"] * 1e-3), 1)
+    out.update(extra)
+    out["setup"] = setup
+    out["kernels"] = {f: {k: {"launches": v["launches"] / args.steps,
+                              "ms_per_step": round(v["total_ms"] / args.steps, 3)}
+                          for k, v in r["prof"].items() if v["launches"]}
+                      for f, r in results.items()}
+    out["levels_occupancy"] = main_r["gst"]
+    out["levels_render"] = main_r["rst"]
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(pts_frame, args.cpu_seconds)
+        pts = sum(s["mlp_points"] for s in (base or main_r)["gst"] + (base or main_r)["rst"])
+        out["cpu_baseline"] = cpu_baseline(pts, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
