@@ -72,6 +72,7 @@ void prof_resolve(pifu_ctx* c) {
 
 constexpr size_t kAlign = 256;
 constexpr int kCounters = 64;
+constexpr int kHostWords = 256;   // pinned read-back buffer (>= every device counter block)
 constexpr uint32_t kDefaultChunk = 65536;
 
 // Device-side counters (words of the counters array).
@@ -769,7 +770,7 @@ int32_t pifu_create(pifu_ctx** out) {
   pifu_ctx* c = new (std::nothrow) pifu_ctx;
   if (!c) return PIFU_ERR_HIP;
   c->device = dev;
-  if (hipHostMalloc(reinterpret_cast<void**>(&c->host_counters), sizeof(uint32_t) * kCounters,
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->host_counters), sizeof(uint32_t) * kHostWords,
                     hipHostMallocDefault) != hipSuccess) {
     delete c;
     return PIFU_ERR_HIP;
