@@ -22,7 +22,7 @@ struct ProfRecord {
 
 struct pifu_ctx {
   int device;
-  uint32_t* host_counters;   // pinned, 64 words
+  uint32_t* host_counters;   // pinned read-back buffer, kHostWords words
   // autotuned point tile per (precision, N, K, batch bucket); filled by pifu_autotune_mlp
   std::map<uint64_t, int> tile_cache;
   bool prof_on = false;
