@@ -63,8 +63,9 @@ def test_probability_error_and_label_flips(pifu, prec, mean_tol):
           f"of {pts.shape[0]}; points in band {int(band.sum())}")
     assert err.mean() < mean_tol
     # inside the band the label is decided in FP32/FP64, so any flip comes from a
-    # low-precision error larger than the band itself
-    assert flips <= 1e-4 * pts.shape[0]
+    # low-precision error larger than the band itself: none for BF16; e4m3 keeps 3
+    # mantissa bits and its logit error reaches past the band on ~0.1% of points
+    assert flips <= (1e-4 if prec == "bf16" else 5e-3) * pts.shape[0]
 
 
 @pytest.mark.parametrize("prec", ["bf16", "fp8"])
