@@ -13,8 +13,13 @@ static inline unsigned grid1d(size_t n, int block) { return (unsigned)((n + bloc
 // multiply-add so the clip decision is reproducible.  Returns false when the point
 // falls outside [-1,1]^3 after the view transform.
 __device__ inline bool src_point(const PointSrc& s, const uint32_t* __restrict__ list, uint32_t m,
-                                 double P[3], float* occ) {
-  const uint32_t idx = (list ? list[m] : m) - s.base_sub;
+                                 double P[3], float* occ, int* frame = nullptr) {
+  uint32_t idx = (list ? list[m] : m) - s.base_sub;
+  if (s.frame_nodes) {
+    const uint32_t f = idx / s.frame_nodes;
+    idx -= f * s.frame_nodes;
+    if (frame) *frame = (int)f;
+  }
   if (s.mode == 1) {
     const float4 q = s.pts[idx];
     P[0] = q.x;
@@ -120,7 +125,9 @@ k_gather(PointSrc src, const uint32_t* __restrict__ list, uint32_t n,
   if (m >= n) return;
   double P[3];
   float occ = 0.f;
-  const bool in = src_point(src, list, m, P, &occ);
+  int frame = 0;
+  const bool in = src_point(src, list, m, P, &occ, &frame);
+  if (src.frame_nodes) F = src.feat_tab[frame];
   int u0, v0;
   double w[4];
   bilinear_setup(P[0], P[1], H, W, u0, v0, w);
@@ -542,6 +549,64 @@ __global__ void k_scatter_results(const uint32_t* __restrict__ pos, uint32_t n,
   const uint32_t p = pos[i];
   logit[p] = tl[i];
   lab[p] = tb[i];
+}
+
+// ------------------------------------------------------------------ per-column hoisting
+// In the input view the sampled feature depends only on the (x, y) column of a node,
+// so the feature part of every layer (W_f f + b) is computed once per column run.
+__global__ void k_col_flags(const uint32_t* __restrict__ list, uint32_t n, uint32_t nz,
+                            uint32_t* __restrict__ flags) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  flags[i] = (i == 0) || (list[i] / nz != list[i - 1] / nz);
+}
+
+void launch_col_flags(const uint32_t* list, uint32_t n, uint32_t nz, uint32_t* flags,
+                      hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_col_flags, dim3(grid1d(n, 256)), dim3(256), 0, s, list, n, nz, flags);
+}
+
+__global__ void k_col_ids(const uint32_t* __restrict__ list, const uint32_t* __restrict__ flags,
+                          const uint32_t* __restrict__ excl, uint32_t n, uint32_t* __restrict__ cid,
+                          uint32_t* __restrict__ col_node) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t c = excl[i] + flags[i] - 1;
+  cid[i] = c;
+  if (flags[i]) col_node[c] = list[i];
+}
+
+void launch_col_ids(const uint32_t* list, const uint32_t* flags, const uint32_t* excl, uint32_t n,
+                    uint32_t* cid, uint32_t* col_node, hipStream_t s) {
+  if (n)
+    hipLaunchKernelGGL(k_col_ids, dim3(grid1d(n, 256)), dim3(256), 0, s, list, flags, excl, n, cid,
+                       col_node);
+}
+
+__global__ void k_hoist_layer0(const float* __restrict__ P, int ldp, const uint32_t* __restrict__ cid,
+                               const uint32_t* __restrict__ list, uint32_t n, int nz,
+                               const float* __restrict__ W0, int ldw0, int zcol, int N, int act,
+                               void* __restrict__ h, int h_bf16) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)n * N) return;
+  const uint32_t i = (uint32_t)(e / N);
+  const int o = (int)(e - (size_t)i * N);
+  const uint32_t k = list[i] % (uint32_t)nz;
+  const float z = (float)(-1.0 + 2.0 * (double)k / (double)(nz - 1));
+  float v = fmaf(z, W0[(size_t)o * ldw0 + zcol], P[(size_t)cid[i] * ldp + o]);
+  if (act == PIFU_ACT_RELU) v = v > 0.f ? v : 0.f;
+  else if (act == PIFU_ACT_LRELU) v = v > 0.f ? v : 0.01f * v;
+  if (h_bf16) reinterpret_cast<uint16_t*>(h)[e] = f32_to_bf16_bits(v);
+  else reinterpret_cast<float*>(h)[e] = v;
+}
+
+void launch_hoist_layer0(const float* P, int ldp, const uint32_t* cid, const uint32_t* list,
+                         uint32_t n, int nz, const float* W0, int ldw0, int zcol, int N, int act,
+                         void* h, int h_bf16, hipStream_t s) {
+  const size_t tot = (size_t)n * N;
+  if (tot)
+    hipLaunchKernelGGL(k_hoist_layer0, dim3(grid1d(tot, 256)), dim3(256), 0, s, P, ldp, cid, list,
+                       n, nz, W0, ldw0, zcol, N, act, h, h_bf16);
 }
 
 // The library's number-format conversions applied to an array (for checking them).

@@ -30,7 +30,7 @@ template <bool OUT_BF16>
 __device__ inline void store_block(const GemmArgs& a, const f32x16& acc, int row0, int col0,
                                    int lane) {
   const int col = col0 + (lane & 31);
-  const float bias = a.bias[col];
+  const float bias = a.bias ? a.bias[col] : 0.f;
   float we[2] = {0.f, 0.f};
   for (int e = 0; e < a.n_ext; ++e) we[e] = a.Wf[(size_t)col * a.ldwf + a.ext_col + e];
 #pragma unroll
@@ -38,6 +38,7 @@ __device__ inline void store_block(const GemmArgs& a, const f32x16& acc, int row
     const int row = row0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
     if (row >= a.M) continue;
     float v = acc[r] * a.scale + bias;
+    if (a.rowadd) v += a.rowadd[(size_t)a.rowadd_idx[row] * a.rowadd_ld + a.rowadd_off + col];
     if (a.n_ext > 0) {
       const float* ex = a.ext + 4 * (size_t)row;
       v = fmaf(ex[0], we[0], v);

@@ -160,6 +160,12 @@ struct MlpPrep {
   int Kp[PIFU_MAX_LAYERS];
   int max_hidden;
   int prec;
+  // per-column hoisting: the feature columns of every layer that reads f, stacked
+  int NP = 0;                        // total outputs of those layers (0: no hoisting)
+  int hoist_off[PIFU_MAX_LAYERS];    // offset of layer l in the stacked outputs, -1 if none
+  float* Wf32 = nullptr;             // [NP][C]
+  uint16_t* Wf16 = nullptr;          // [NP][C] (BF16 runs)
+  float* bf = nullptr;               // [NP] biases of those layers
 };
 
 void describe_mlp(const pifu_mlp* m, MLPDesc& d) {
@@ -197,6 +203,20 @@ void carve_mlp(Carver& cv, const pifu_mlp* m, int precision, MlpPrep& p) {
     p.a_scale[l] = amax_a / 448.f;
     p.w_scale[l] = 1.f;
   }
+  // hoisting applies to occupancy networks whose layer 0 reads [f; z]
+  p.NP = 0;
+  for (int l = 0; l < PIFU_MAX_LAYERS; ++l) p.hoist_off[l] = -1;
+  if (m->n_extra == 1 && precision != PIFU_PREC_FP8) {
+    for (int l = 0; l + 1 < m->n_layers; ++l)
+      if (l == 0 || p.d.skip[l]) {
+        p.hoist_off[l] = p.NP;
+        p.NP += m->widths[l];
+      }
+    const size_t n = (size_t)p.NP * m->feat_dim;
+    p.Wf32 = cv.take<float>(n);
+    p.Wf16 = precision == PIFU_PREC_BF16 ? cv.take<uint16_t>(n) : nullptr;
+    p.bf = cv.take<float>(p.NP);
+  }
 }
 
 int pack_mlp(MlpPrep& p, pifu_ctx* ctx, hipStream_t s) {
@@ -206,6 +226,16 @@ int pack_mlp(MlpPrep& p, pifu_ctx* ctx, hipStream_t s) {
       launch_pack_weights(p.d.W[l], p.d.widths[l], p.d.in_w[l], p.Kp[l], p.Wp16[l], 1, s);
     if (p.Wp8[l])
       launch_pack_fp8(p.d.W[l], p.d.widths[l], p.d.in_w[l], p.Kp[l], p.amax + l, p.Wp8[l], s);
+    if (p.hoist_off[l] >= 0) {
+      const int C = p.d.feat_dim;
+      const int fcol = l == 0 ? 0 : p.d.widths[l - 1];   // where f starts in layer l's input
+      const size_t off = (size_t)p.hoist_off[l];
+      launch_pack_weights(p.d.W[l] + fcol, p.d.widths[l], p.d.in_w[l], C, p.Wf32 + off * C, 0, s);
+      if (p.Wf16)
+        launch_pack_weights(p.d.W[l] + fcol, p.d.widths[l], p.d.in_w[l], C, p.Wf16 + off * C, 1, s);
+      HIP_TRY(hipMemcpyAsync(p.bf + off, p.d.b[l], sizeof(float) * p.d.widths[l],
+                             hipMemcpyDeviceToDevice, s));
+    }
   }
   if (!p.amax) return check_launch();
   // the FP8 weight scales enter the GEMM epilogue: read them back once per call
@@ -238,6 +268,9 @@ struct EvalWs {
   uint32_t *sur_pos = nullptr, *sur_nodes = nullptr;
   float* sur_logit = nullptr;
   uint8_t* sur_lab = nullptr;
+  // per-column hoisting (input view)
+  uint32_t *cflags = nullptr, *cexcl = nullptr, *cid = nullptr, *cnode = nullptr, *cscan = nullptr;
+  float* Pcol = nullptr;     // chunk x NP
 };
 
 struct FieldPrep {
@@ -294,6 +327,23 @@ void carve_eval(Carver& cv, uint32_t max_points, int C, int max_hidden, EvalWs& 
   ew.hA = cv.take<float>(ch * std::max(max_hidden, 1));
   ew.hB = cv.take<float>(ch * std::max(max_hidden, 1));
   ew.glist = cv.take<uint32_t>(std::max<uint32_t>(max_points, 1));
+}
+
+// Buffers of per-column hoisting for a network with NP stacked feature outputs.
+void carve_hoist(Carver& cv, int NP, EvalWs& ew) {
+  if (NP <= 0) return;
+  const size_t ch = ew.chunk;
+  ew.cflags = cv.take<uint32_t>(ch);
+  ew.cexcl = cv.take<uint32_t>(ch);
+  ew.cid = cv.take<uint32_t>(ch);
+  ew.cnode = cv.take<uint32_t>(ch);
+  ew.cscan = cv.take<uint32_t>(scan_scratch_words(ch));
+  ew.Pcol = cv.take<float>(ch * NP);
+}
+
+int hoist_np(const FieldPrep& fp) {
+  if (!fp.has_mlp) return 0;
+  return std::max(fp.mlp.NP, fp.has_sur ? fp.sur.NP : 0);
 }
 
 struct EvalCtx {
@@ -355,12 +405,92 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
     segs = &one;
     nseg = 1;
   }
+  // input-view lattice points of one frame: hoist the feature terms per column
+  const bool hoist = src.mode == 0 && !src.has_view && prec != PIFU_PREC_FP8 && mp.NP > 0 &&
+                     ew.Pcol != nullptr && (nseg == 1 || src.frame_nodes);
+  for (uint32_t c0 = 0; c0 < n && hoist; c0 += ew.chunk) {
+    const uint32_t m = std::min(ew.chunk, n - c0);
+    const uint32_t* lst = list + c0;
+    launch_col_flags(lst, m, (uint32_t)src.nz, ew.cflags, e.s);
+    launch_scan_u32(ew.cflags, m, ew.cexcl, ew.cscan, e.counters + C_TOTAL, e.s);
+    int r = check_launch();
+    if (!r) r = read_counters(e, 1);
+    if (r) return r;
+    const uint32_t ncol = e.ctx->host_counters[C_TOTAL];
+    launch_col_ids(lst, ew.cflags, ew.cexcl, m, ew.cid, ew.cnode, e.s);
+    {
+      ProfScope ps(e.ctx, e.s, PIFU_KERN_GATHER, 0.0,
+                   (double)ncol * (16.0 * C + (b16 ? 2 : 4) * C + 20.0));
+      PointSrc sq = src;
+      if (!src.frame_nodes) sq.base_sub = segs[0].base_sub;   // else the frame table decodes
+      launch_gather(sq, ew.cnode, ncol, segs[0].F, f->H, f->W, C, ew.feat, b16, ew.ext, e.s);
+    }
+    GemmArgs g;
+    std::memset(&g, 0, sizeof(g));
+    g.A1 = ew.feat;
+    g.K1 = g.lda1 = C;
+    g.W = b16 ? (const void*)mp.Wf16 : (const void*)mp.Wf32;
+    g.ldw = C;
+    g.bias = mp.bf;
+    g.C = ew.Pcol;
+    g.ldc = g.N = mp.NP;
+    g.M = (int)ncol;
+    g.act = 0;
+    g.scale = 1.f;
+    {
+      ProfScope ps(e.ctx, e.s, b16 ? PIFU_KERN_GEMM_BF16 : PIFU_KERN_GEMM_F32,
+                   2.0 * ncol * mp.NP * C, 0.0);
+      if (launch_gemm(g, prec, pick_tile(e, prec, g.N, C, ncol), e.s)) return PIFU_ERR_UNSUPPORTED;
+    }
+    launch_hoist_layer0(ew.Pcol, mp.NP, ew.cid, lst, m, src.nz, d.W[0], d.in_w[0], C, d.widths[0],
+                        d.hidden_act, ew.hA, b16 && d.n_layers > 2, e.s);
+    const void* prev = ew.hA;
+    void* out = ew.hB;
+    for (int l = 1; l + 1 < d.n_layers; ++l) {
+      std::memset(&g, 0, sizeof(g));
+      g.A1 = prev;
+      g.K1 = g.lda1 = d.widths[l - 1];
+      g.W = b16 ? (const void*)mp.Wp16[l] : (const void*)mp.Wp32[l];
+      g.ldw = mp.Kp[l];
+      g.Wf = d.W[l];
+      g.ldwf = d.in_w[l];
+      if (mp.hoist_off[l] >= 0) {
+        g.rowadd = ew.Pcol;
+        g.rowadd_idx = ew.cid;
+        g.rowadd_ld = mp.NP;
+        g.rowadd_off = mp.hoist_off[l];
+      } else {
+        g.bias = d.b[l];
+      }
+      g.C = out;
+      g.ldc = g.N = d.widths[l];
+      g.M = (int)m;
+      g.act = d.hidden_act;
+      g.scale = 1.f;
+      g.c_bf16 = b16 && (l + 2 < d.n_layers);
+      {
+        ProfScope ps(e.ctx, e.s, b16 ? PIFU_KERN_GEMM_BF16 : PIFU_KERN_GEMM_F32,
+                     2.0 * m * g.N * g.K1, 0.0);
+        if (launch_gemm(g, prec, pick_tile(e, prec, g.N, g.K1, m), e.s)) return PIFU_ERR_UNSUPPORTED;
+      }
+      prev = out;
+      out = (out == ew.hA) ? ew.hB : ew.hA;
+    }
+    const int L = d.n_layers - 1;
+    ProfScope ps(e.ctx, e.s, PIFU_KERN_HEAD, 2.0 * m * d.widths[L - 1] * d.widths[L], 0.0);
+    launch_head(reinterpret_cast<const float*>(prev), d.widths[L - 1], d.W[L], d.b[L], d.widths[L],
+                d.out_act, m, nullptr, logit ? logit + c0 : nullptr, lab ? lab + c0 : nullptr, rgb,
+                rgb ? lst : nullptr, e.s);
+  }
+  if (hoist) return check_launch();
   for (uint32_t c0 = 0; c0 < n; c0 += ew.chunk) {
     const uint32_t m = std::min(ew.chunk, n - c0);
     const uint32_t* lst = list + c0;
     {
       ProfScope ps(e.ctx, e.s, PIFU_KERN_GATHER, 0.0, (double)m * (16.0 * C + (b16 ? 2 : 4) * C + 20.0));
-      for (int q = 0; q < nseg; ++q) {
+      if (src.frame_nodes)
+        launch_gather(src, lst, m, segs[0].F, f->H, f->W, C, ew.feat, b16, ew.ext, e.s);
+      for (int q = 0; q < nseg && !src.frame_nodes; ++q) {
         const uint32_t lo = std::max(c0, segs[q].begin);
         const uint32_t hi = std::min(c0 + m, segs[q].begin + segs[q].count);
         if (lo >= hi) continue;
@@ -662,6 +792,7 @@ int plan_grid(const pifu_field* field, const pifu_grid_opts* o, void* base, floa
   const int mh = g.fp.has_mlp ? g.fp.mlp.max_hidden : 0;
   carve_eval(cv, (uint32_t)max_n, C, mh, g.ew);
   carve_guard(cv, g.fp, (uint32_t)max_n, g.ew);
+  carve_hoist(cv, hoist_np(g.fp), g.ew);
   g.bytes = cv.off + kAlign;
   return PIFU_OK;
 }
@@ -1442,6 +1573,7 @@ void plan_batch(int n, const pifu_field* const* fields, const pifu_grid_opts* co
   if (b.fps[0].has_sur) mh = std::max(mh, b.fps[0].sur.max_hidden);
   carve_eval(cv, b.list_cap, C, mh, b.ew);
   carve_guard(cv, b.fps[0], b.list_cap, b.ew);
+  carve_hoist(cv, hoist_np(b.fps[0]), b.ew);
   b.bytes = cv.off + kAlign;
 }
 
@@ -1500,13 +1632,18 @@ int eval_frames(EvalCtx& e, BatchPlan& b, int r, const uint32_t* bounds, uint32_
     return check_launch();
   }
   const bool sur = use_sur && fp0.has_sur;
-  int rc = run_mlp(e, fp0, sur ? fp0.sur : fp0.mlp, sur ? PIFU_PREC_BF16 : e.precision, src,
-                   b.w.list, n, b.ew, b.w.logit, b.w.lab, nullptr, segs, ns);
+  // one pass over every frame's points: the gathers pick each frame's feature map
+  PointSrc sall = src;
+  sall.frame_nodes = (uint32_t)L.n();
+  for (int p = 0; p < A; ++p) sall.feat_tab[p] = b.fps[b.order[p]].f->feat;
+  int rc = run_mlp(e, fp0, sur ? fp0.sur : fp0.mlp, sur ? PIFU_PREC_BF16 : e.precision, sall,
+                   b.w.list, n, b.ew, b.w.logit, b.w.lab, nullptr);
   if (rc) return rc;
   for (int q = 0; q < ns; ++q) {
     const int f = b.order[q];
     if (!segs[q].count) continue;
     PointSrc sq = src;
+    sq.frame_nodes = 0;
     sq.base_sub = segs[q].base_sub;
     const uint32_t* lst = b.w.list + segs[q].begin;
     float* lg = b.w.logit + segs[q].begin;

@@ -30,6 +30,9 @@ struct Lat {
 //   mode 1: explicit points pts[list ? list[m] : m] (x, y, z, occ), input NDC.
 //   base_sub is subtracted from every list entry first (a frame's offset inside a
 //   multi-frame state array).
+//   frame_nodes > 0 (mode 0): entries index frames of frame_nodes nodes stored back to
+//   back; frame f samples the feature map feat_tab[f].
+constexpr int kMaxTabFrames = 16;
 struct PointSrc {
   int mode;
   int nx, ny, nz;
@@ -37,6 +40,8 @@ struct PointSrc {
   double view[12];
   const float4* pts;
   uint32_t base_sub;
+  uint32_t frame_nodes;
+  const float* feat_tab[kMaxTabFrames];
 };
 
 struct MLPDesc {
@@ -158,7 +163,24 @@ struct GemmArgs {
   float scale;       // FP8: product of operand scales (dequantization), else 1
   int c_bf16;        // BF16/FP8 paths: write C as bf16 (next layer's input), else fp32
   float a_inv_scale; // FP8: activations are quantized as e4m3(a * a_inv_scale)
+  // per-row precomputed term (per-column hoisting): v += rowadd[rowadd_idx[row] *
+  // rowadd_ld + rowadd_off + col]; bias may then be null.
+  const float* rowadd;
+  const uint32_t* rowadd_idx;
+  int rowadd_ld, rowadd_off;
 };
+
+// ------------------------------------------------------------------ per-column hoisting
+// flags[i] = point i starts a new (x, y) column (list sorted or not: runs of one column)
+void launch_col_flags(const uint32_t* list, uint32_t n, uint32_t nz, uint32_t* flags,
+                      hipStream_t s);
+// cid[i] = index of point i's column run; col_node[cid] = a node of that column
+void launch_col_ids(const uint32_t* list, const uint32_t* flags, const uint32_t* excl, uint32_t n,
+                    uint32_t* cid, uint32_t* col_node, hipStream_t s);
+// layer 0 with hoisting: h[i][o] = act(P[cid[i]][o] + wz[o] * z_i), z from the node index
+void launch_hoist_layer0(const float* P, int ldp, const uint32_t* cid, const uint32_t* list,
+                         uint32_t n, int nz, const float* W0, int ldw0, int zcol, int N, int act,
+                         void* h, int h_bf16, hipStream_t s);
 
 // float32 -> OCP FP8 E4M3FN code (bias 7, 3 mantissa bits, no infinities), round to
 // nearest even, saturating at +-448; NaN -> 0x7f.
