@@ -37,6 +37,9 @@ def parse():
     ap.add_argument("--train-frames", type=int, default=6)
     ap.add_argument("--train-samples", type=int, default=524288)
     ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="after timing, copy this many MiB device-to-device once (a plain copy "
+                         "of known size to calibrate hardware byte counters)")
     return ap.parse_args()
 
 
@@ -143,6 +146,14 @@ def main():
                              prof=prof, gst=gst, rst=rst,
                              cells=gout.cells[:min(nc, gout.cells_cap)].clone(),
                              hit=rout.hit.clone())
+
+    if args.copy_probe_mb:
+        src = torch.ones(args.copy_probe_mb << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     from paper_2007_13988_amd.surrogate import cell_disagreement
     base = results.get("fp32")

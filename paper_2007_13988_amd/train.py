@@ -65,6 +65,31 @@ class MLPTrainer:
                                    P._stream(stream))
         P._check(st, "pifu_rmsprop_step")
 
+    def save(self, path: str, step: int = 0, extra: Optional[dict] = None) -> None:
+        """Checkpoint: FP32 master weights, RMSProp state and the step count (.npz)."""
+        arrs = {}
+        for l, (w, b, vw, vb) in enumerate(zip(self.net.W, self.net.b, self.vW, self.vb)):
+            arrs[f"W{l}"] = w.cpu().numpy()
+            arrs[f"b{l}"] = b.cpu().numpy()
+            arrs[f"vW{l}"] = vw.cpu().numpy()
+            arrs[f"vb{l}"] = vb.cpu().numpy()
+        arrs["step"] = np.array([step], np.int64)
+        arrs["hyper"] = np.array([self.lr, self.alpha, self.eps], np.float64)
+        for k, v in (extra or {}).items():
+            arrs[k] = np.asarray(v)
+        np.savez(path, **arrs)
+
+    def load(self, path: str) -> int:
+        """Restores a checkpoint written by save(); returns its step count."""
+        z = np.load(path)
+        for l in range(len(self.net.W)):
+            self.net.W[l].copy_(torch.from_numpy(z[f"W{l}"]))
+            self.net.b[l].copy_(torch.from_numpy(z[f"b{l}"]))
+            self.vW[l].copy_(torch.from_numpy(z[f"vW{l}"]))
+            self.vb[l].copy_(torch.from_numpy(z[f"vb{l}"]))
+        self.lr, self.alpha, self.eps = (float(x) for x in z["hyper"])
+        return int(z["step"][0])
+
     def to_spec(self, template):
         """Copies the trained weights into a synth-style MLPSpec (host float32)."""
         import copy

@@ -93,6 +93,32 @@ def test_rmsprop_step_matches_oracle(pifu):
         assert np.max(np.abs(net.W[l].cpu().numpy() - W0[l])) <= 1e-6
 
 
+def test_checkpoint_resume_is_bit_exact(pifu, tmp_path):
+    """Stopping after k steps, checkpointing, and resuming in a fresh trainer gives the
+    same weights as training straight through (deterministic kernels)."""
+    from paper_2007_13988_amd.train import MLPTrainer
+    spec = synth.surrogate_mlp(77)
+    feat, pts = _batch(256, 8192, 49)
+    ft, pt = torch.from_numpy(feat).cuda(), torch.from_numpy(pts).cuda()
+    a = MLPTrainer(pifu.DeviceMLP(spec), 8192)
+    for _ in range(6):
+        a.grad(ft, pt)
+        a.step()
+    b = MLPTrainer(pifu.DeviceMLP(spec), 8192)
+    for _ in range(3):
+        b.grad(ft, pt)
+        b.step()
+    ck = str(tmp_path / "ck.npz")
+    b.save(ck, step=3)
+    c = MLPTrainer(pifu.DeviceMLP(synth.surrogate_mlp(78)), 8192)
+    assert c.load(ck) == 3
+    for _ in range(3):
+        c.grad(ft, pt)
+        c.step()
+    for wa, wc in zip(a.net.W + a.net.b, c.net.W + c.net.b):
+        assert torch.equal(wa, wc)
+
+
 def test_training_lowers_the_distillation_loss(pifu):
     from paper_2007_13988_amd.train import MLPTrainer
     teacher = synth.tiny_mlp()
