@@ -31,8 +31,8 @@ __device__ inline void store_block(const GemmArgs& a, const f32x16& acc, int row
                                    int lane) {
   const int col = col0 + (lane & 31);
   const float bias = a.bias ? a.bias[col] : 0.f;
-  float we[2] = {0.f, 0.f};
-  for (int e = 0; e < a.n_ext; ++e) we[e] = a.Wf[(size_t)col * a.ldwf + a.ext_col + e];
+  const float we0 = a.n_ext > 0 ? a.Wf[(size_t)col * a.ldwf + a.ext_col] : 0.f;
+  const float we1 = a.n_ext > 1 ? a.Wf[(size_t)col * a.ldwf + a.ext_col + 1] : 0.f;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int row = row0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
@@ -41,8 +41,8 @@ __device__ inline void store_block(const GemmArgs& a, const f32x16& acc, int row
     if (a.rowadd) v += a.rowadd[(size_t)a.rowadd_idx[row] * a.rowadd_ld + a.rowadd_off + col];
     if (a.n_ext > 0) {
       const float* ex = a.ext + 4 * (size_t)row;
-      v = fmaf(ex[0], we[0], v);
-      if (a.n_ext > 1) v = fmaf(ex[1], we[1], v);
+      v = fmaf(ex[0], we0, v);
+      if (a.n_ext > 1) v = fmaf(ex[1], we1, v);
     }
     v = act_apply(v, a.act);
     if (OUT_BF16)
@@ -175,8 +175,9 @@ __global__ void __launch_bounds__(256, MINB) k_gemm_f32(GemmArgs a) {
 // ------------------------------------------------------------------ BF16 operands
 // v_mfma_f32_32x32x16_bf16: 8 bf16 per lane per MFMA (one 16-byte LDS read);
 // BK = 64 bf16 per stage.
-template <int BM, int BN, int WM, int WN, int MINB, bool OUT_BF16>
-__global__ void __launch_bounds__(256, MINB) k_gemm_bf16(GemmArgs a) {
+template <int BM, int BN, int WM, int WN, int MINB, bool OUT_BF16, int NT = 256>
+__global__ void __launch_bounds__(NT, MINB) k_gemm_bf16(GemmArgs a) {
+  // NT = 64 * WM * WN threads; the 256 x 256 tile uses 512 threads (8 waves of 128 x 64)
   constexpr int BK = 64;
   constexpr int LD = BK + 8;   // in bf16 elements
   constexpr int TI = BM / WM / 32, TJ = BN / WN / 32;
@@ -187,8 +188,8 @@ __global__ void __launch_bounds__(256, MINB) k_gemm_bf16(GemmArgs a) {
   const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
   const int K = a.K1 + a.K2;
   const int nk = K / BK;
-  constexpr int A_LOADS = BM * (BK / 8) / 256;
-  constexpr int B_LOADS = BN * (BK / 8) / 256;
+  constexpr int A_LOADS = BM * (BK / 8) / NT;
+  constexpr int B_LOADS = BN * (BK / 8) / NT;
   uint4 ra[A_LOADS], rb[B_LOADS];
   const __bf16* A1 = reinterpret_cast<const __bf16*>(a.A1);
   const __bf16* A2 = reinterpret_cast<const __bf16*>(a.A2);
@@ -209,7 +210,7 @@ __global__ void __launch_bounds__(256, MINB) k_gemm_bf16(GemmArgs a) {
     }
 #pragma unroll
     for (int i = 0; i < A_LOADS; ++i) {
-      const int e = tid + 256 * i;
+      const int e = tid + NT * i;
       const int row = e >> 3, c8 = e & 7;
       const int gm = m0 + row;
       ra[i] = gm < a.M ? *reinterpret_cast<const uint4*>(src + (size_t)gm * ld + kk0 + 8 * c8)
@@ -217,7 +218,7 @@ __global__ void __launch_bounds__(256, MINB) k_gemm_bf16(GemmArgs a) {
     }
 #pragma unroll
     for (int i = 0; i < B_LOADS; ++i) {
-      const int e = tid + 256 * i;
+      const int e = tid + NT * i;
       const int row = e >> 3, c8 = e & 7;
       rb[i] = *reinterpret_cast<const uint4*>(Wp + (size_t)(n0 + row) * a.ldw + k0 + 8 * c8);
     }
@@ -225,12 +226,12 @@ __global__ void __launch_bounds__(256, MINB) k_gemm_bf16(GemmArgs a) {
   auto sstore = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < A_LOADS; ++i) {
-      const int e = tid + 256 * i;
+      const int e = tid + NT * i;
       *reinterpret_cast<uint4*>(&As[buf][(e >> 3) * LD + 8 * (e & 7)]) = ra[i];
     }
 #pragma unroll
     for (int i = 0; i < B_LOADS; ++i) {
-      const int e = tid + 256 * i;
+      const int e = tid + NT * i;
       *reinterpret_cast<uint4*>(&Bs[buf][(e >> 3) * LD + 8 * (e & 7)]) = rb[i];
     }
   };
@@ -508,7 +509,15 @@ int launch_gemm(const GemmArgs& a, int precision, int tile_m, hipStream_t s) {
     if (bn128) {
       if (bm == 64) PIFU_B16(64, 128, 1, 4, 2);
       else if (bm == 128) PIFU_B16(128, 128, 2, 2, 2);
-      else PIFU_B16(256, 128, 2, 2, 1);
+      else if (a.N % 256 == 0) {
+        // 256 x 256 tile, 8 waves: half the L2 traffic per FLOP of the 128-wide tiles
+        if (a.c_bf16)
+          hipLaunchKernelGGL((k_gemm_bf16<256, 256, 2, 4, 1, true, 512>),
+                             dim3((a.M + 255) / 256, a.N / 256), dim3(512), 0, s, a);
+        else
+          hipLaunchKernelGGL((k_gemm_bf16<256, 256, 2, 4, 1, false, 512>),
+                             dim3((a.M + 255) / 256, a.N / 256), dim3(512), 0, s, a);
+      } else PIFU_B16(256, 128, 2, 2, 1);
     } else {
       if (bm == 64) PIFU_B16(64, 64, 2, 2, 2);
       else if (bm == 128) PIFU_B16(128, 64, 4, 1, 2);
