@@ -17,6 +17,10 @@ namespace pifu {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
+// Native vectors for the global->LDS staging registers (HIP's float4/uint4 structs are
+// copied as memcpy, which keeps the staging array in scratch memory).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ inline float act_apply(float v, int act) {
   if (act == PIFU_ACT_RELU) return v > 0.f ? v : 0.f;
@@ -69,7 +73,7 @@ __global__ void __launch_bounds__(256, MINB) k_gemm_f32(GemmArgs a) {
   const int nk = K / BK;
   constexpr int A_LOADS = BM * (BK / 4) / 256;
   constexpr int B_LOADS = BN * (BK / 4) / 256;
-  float4 ra[A_LOADS], rb[B_LOADS];
+  f32x4 ra[A_LOADS], rb[B_LOADS];
   const float* A1 = reinterpret_cast<const float*>(a.A1);
   const float* A2 = reinterpret_cast<const float*>(a.A2);
   const float* Wp = reinterpret_cast<const float*>(a.W);
@@ -92,26 +96,26 @@ __global__ void __launch_bounds__(256, MINB) k_gemm_f32(GemmArgs a) {
       const int e = tid + 256 * i;
       const int row = e >> 3, c4 = e & 7;
       const int gm = m0 + row;
-      ra[i] = gm < a.M ? *reinterpret_cast<const float4*>(src + (size_t)gm * ld + kk0 + 4 * c4)
-                       : make_float4(0.f, 0.f, 0.f, 0.f);
+      ra[i] = gm < a.M ? *reinterpret_cast<const f32x4*>(src + (size_t)gm * ld + kk0 + 4 * c4)
+                       : (f32x4){0.f, 0.f, 0.f, 0.f};
     }
 #pragma unroll
     for (int i = 0; i < B_LOADS; ++i) {
       const int e = tid + 256 * i;
       const int row = e >> 3, c4 = e & 7;
-      rb[i] = *reinterpret_cast<const float4*>(Wp + (size_t)(n0 + row) * a.ldw + k0 + 4 * c4);
+      rb[i] = *reinterpret_cast<const f32x4*>(Wp + (size_t)(n0 + row) * a.ldw + k0 + 4 * c4);
     }
   };
   auto sstore = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < A_LOADS; ++i) {
       const int e = tid + 256 * i;
-      *reinterpret_cast<float4*>(&As[buf][(e >> 3) * LD + 4 * (e & 7)]) = ra[i];
+      *reinterpret_cast<f32x4*>(&As[buf][(e >> 3) * LD + 4 * (e & 7)]) = ra[i];
     }
 #pragma unroll
     for (int i = 0; i < B_LOADS; ++i) {
       const int e = tid + 256 * i;
-      *reinterpret_cast<float4*>(&Bs[buf][(e >> 3) * LD + 4 * (e & 7)]) = rb[i];
+      *reinterpret_cast<f32x4*>(&Bs[buf][(e >> 3) * LD + 4 * (e & 7)]) = rb[i];
     }
   };
 
@@ -190,7 +194,7 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_bf16(GemmArgs a) {
   const int nk = K / BK;
   constexpr int A_LOADS = BM * (BK / 8) / NT;
   constexpr int B_LOADS = BN * (BK / 8) / NT;
-  uint4 ra[A_LOADS], rb[B_LOADS];
+  u32x4 ra[A_LOADS], rb[B_LOADS];
   const __bf16* A1 = reinterpret_cast<const __bf16*>(a.A1);
   const __bf16* A2 = reinterpret_cast<const __bf16*>(a.A2);
   const __bf16* Wp = reinterpret_cast<const __bf16*>(a.W);
@@ -213,26 +217,26 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_bf16(GemmArgs a) {
       const int e = tid + NT * i;
       const int row = e >> 3, c8 = e & 7;
       const int gm = m0 + row;
-      ra[i] = gm < a.M ? *reinterpret_cast<const uint4*>(src + (size_t)gm * ld + kk0 + 8 * c8)
-                       : make_uint4(0, 0, 0, 0);
+      ra[i] = gm < a.M ? *reinterpret_cast<const u32x4*>(src + (size_t)gm * ld + kk0 + 8 * c8)
+                       : (u32x4){0u, 0u, 0u, 0u};
     }
 #pragma unroll
     for (int i = 0; i < B_LOADS; ++i) {
       const int e = tid + NT * i;
       const int row = e >> 3, c8 = e & 7;
-      rb[i] = *reinterpret_cast<const uint4*>(Wp + (size_t)(n0 + row) * a.ldw + k0 + 8 * c8);
+      rb[i] = *reinterpret_cast<const u32x4*>(Wp + (size_t)(n0 + row) * a.ldw + k0 + 8 * c8);
     }
   };
   auto sstore = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < A_LOADS; ++i) {
       const int e = tid + NT * i;
-      *reinterpret_cast<uint4*>(&As[buf][(e >> 3) * LD + 8 * (e & 7)]) = ra[i];
+      *reinterpret_cast<u32x4*>(&As[buf][(e >> 3) * LD + 8 * (e & 7)]) = ra[i];
     }
 #pragma unroll
     for (int i = 0; i < B_LOADS; ++i) {
       const int e = tid + NT * i;
-      *reinterpret_cast<uint4*>(&Bs[buf][(e >> 3) * LD + 8 * (e & 7)]) = rb[i];
+      *reinterpret_cast<u32x4*>(&Bs[buf][(e >> 3) * LD + 8 * (e & 7)]) = rb[i];
     }
   };
 
@@ -331,7 +335,7 @@ __global__ void __launch_bounds__(256, MINB) k_gemm_fp8(GemmArgs a) {
   constexpr int AV = BK / 8, BV = BK / 16;
   constexpr int A_LOADS = BM * AV / 256;
   constexpr int B_LOADS = BN * BV / 256 > 0 ? BN * BV / 256 : 1;
-  uint4 ra[A_LOADS], rb[B_LOADS];
+  u32x4 ra[A_LOADS], rb[B_LOADS];
   const uint16_t* A1 = reinterpret_cast<const uint16_t*>(a.A1);
   const uint16_t* A2 = reinterpret_cast<const uint16_t*>(a.A2);
   const uint8_t* Wp = reinterpret_cast<const uint8_t*>(a.W);
@@ -355,15 +359,15 @@ __global__ void __launch_bounds__(256, MINB) k_gemm_fp8(GemmArgs a) {
       const int e = tid + 256 * i;
       const int row = e / AV, c8 = e % AV;
       const int gm = m0 + row;
-      ra[i] = gm < a.M ? *reinterpret_cast<const uint4*>(src + (size_t)gm * ld + kk0 + 8 * c8)
-                       : make_uint4(0, 0, 0, 0);
+      ra[i] = gm < a.M ? *reinterpret_cast<const u32x4*>(src + (size_t)gm * ld + kk0 + 8 * c8)
+                       : (u32x4){0u, 0u, 0u, 0u};
     }
 #pragma unroll
     for (int i = 0; i < B_LOADS; ++i) {
       const int e = tid + 256 * i;
       const int row = e / BV, c16 = e % BV;
       if (row < BN)
-        rb[i] = *reinterpret_cast<const uint4*>(Wp + (size_t)(n0 + row) * a.ldw + k0 + 16 * c16);
+        rb[i] = *reinterpret_cast<const u32x4*>(Wp + (size_t)(n0 + row) * a.ldw + k0 + 16 * c16);
     }
   };
   auto sstore = [&](int buf) {
@@ -379,7 +383,7 @@ __global__ void __launch_bounds__(256, MINB) k_gemm_fp8(GemmArgs a) {
 #pragma unroll
     for (int i = 0; i < B_LOADS; ++i) {
       const int e = tid + 256 * i;
-      if (e / BV < BN) *reinterpret_cast<uint4*>(&Bs[buf][(e / BV) * LD + 16 * (e % BV)]) = rb[i];
+      if (e / BV < BN) *reinterpret_cast<u32x4*>(&Bs[buf][(e / BV) * LD + 16 * (e % BV)]) = rb[i];
     }
   };
 
