@@ -147,6 +147,43 @@ def pifu_features(seed: int = 102):
     return feature_map(128, 128, 256, 16.0, seed)
 
 
+def sequence_frame(H: int, W: int, C: int, sigma_px: float, seed: int, t: int, eps: float = 0.3,
+                   step_px=(1.5, 0.7)) -> np.ndarray:
+    """Frame t of a video-like feature sequence around feature_map(H, W, C, sigma_px, seed).
+
+    Frame 0 is that map itself.  Frame t != 0 is the same underlying field moved by
+    t * step_px pixels (x, y; periodic, sub-pixel Fourier shift), mixed with a fresh
+    smooth field of the same spectrum: sqrt(1 - eps^2) * moved + eps * fresh, then
+    re-standardized per channel.  Consecutive frames of one performance are similar
+    in this way, unlike independent seeds.
+    """
+    if t == 0:
+        return feature_map(H, W, C, sigma_px, seed)
+    g = rng(seed)
+    white = g.standard_normal((C, H, W))
+    fy = np.fft.fftfreq(H)[:, None]
+    fx = np.fft.fftfreq(W)[None, :]
+    tf = np.exp(-2.0 * (math.pi ** 2) * (sigma_px ** 2) * (fx ** 2 + fy ** 2))
+    phase = np.exp(-2j * math.pi * (fx * step_px[0] * t + fy * step_px[1] * t))
+    moved = np.real(np.fft.ifft2(np.fft.fft2(white, axes=(1, 2)) * (tf * phase)[None], axes=(1, 2)))
+    moved -= moved.mean(axis=(1, 2), keepdims=True)
+    moved /= moved.std(axis=(1, 2), keepdims=True)
+    g2 = np.random.Generator(np.random.PCG64([int(seed), int(t) + (1 << 20)]))
+    fresh = np.real(np.fft.ifft2(np.fft.fft2(g2.standard_normal((C, H, W)), axes=(1, 2)) * tf[None],
+                                 axes=(1, 2)))
+    fresh -= fresh.mean(axis=(1, 2), keepdims=True)
+    fresh /= fresh.std(axis=(1, 2), keepdims=True)
+    sm = math.sqrt(1.0 - eps * eps) * moved + eps * fresh
+    sm -= sm.mean(axis=(1, 2), keepdims=True)
+    sm /= sm.std(axis=(1, 2), keepdims=True)
+    return np.ascontiguousarray(np.transpose(sm, (1, 2, 0)).astype(np.float32))
+
+
+def pifu_sequence(seed: int, t: int):
+    """Frame t of the sequence whose frame 0 is pifu_features(seed)."""
+    return sequence_frame(128, 128, 256, 16.0, seed, t)
+
+
 def pifu_mlp(seed: int = 202, out_bias: float = 0.0):
     """(256+z)->1024->512->256->128->1 with the feature concatenated into hidden layers 2-4."""
     return he_mlp(256, 1, [1024, 512, 256, 128, 1], [False, True, True, True, False], seed,
