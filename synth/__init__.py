@@ -10,7 +10,12 @@ Recipe (the paper's workloads stand in as synthetic arrays of the same shape):
     Shapes follow the encoder outputs of Sec. 3.1 / appendix A1.2
     (256 ch x 128 x 128 for the shape encoder).
   * MLP weights: W ~ N(0, 2 / fan_in) (fan_in includes skip inputs), zero biases
-    except an optional output bias; row-major [out][in].
+    except an optional output bias; row-major [out][in].  The PIFu-size occupancy
+    network additionally carries a depth-slab field on four units per layer
+    (depth_slab_mlp): each pixel's feature sets one depth interval, so the surface
+    is closed and compact like a body's, and the logit is sharp near it.
+  * feature sequences: frame t of a performance is frame 0 moved by t * (1.5, 0.7)
+    pixels plus a fresh smooth field (sequence_frame).
   * ellipsoid unions: centres U[-0.4,0.4]^3, semi-axes U[0.15,0.45], rotations
     from normalised Gaussian quaternions.
   * views: yaw rotation about the y axis, no translation (3x4 row-major).
@@ -184,10 +189,61 @@ def pifu_sequence(seed: int, t: int):
     return sequence_frame(128, 128, 256, 16.0, seed, t)
 
 
+def depth_slab_mlp(spec: MLPSpec, seed: int, kappa: float = 16.0, mu_scale: float = 0.3,
+                   tau0: float = -0.05, tau_scale: float = 0.25, eps: float = 0.1) -> MLPSpec:
+    """Turns a He-init ReLU occupancy network into a pixel-aligned depth-slab field.
+
+    Hidden units 0-3 of every hidden layer are set to carry
+        u0 = relu(z - mu(f)),  u1 = relu(mu(f) - z),  t+ = relu(tau(f)),  t- = relu(-tau(f))
+    with mu(f) = mu_scale * a.f and tau(f) = tau0 + tau_scale * b.f (a, b random unit
+    vectors): layer 0 computes them, later layers pass them through unchanged (weight 1
+    on the unit itself, 0 elsewhere; relu is the identity on them).  The head reads
+        logit = kappa * (t+ - t- - u0 - u1 + eps * r),
+    i.e. kappa * (tau(f) - |z - mu(f)|) plus eps times the He-init head over the other
+    units (r).  Each pixel thus holds one depth interval |z - mu| < tau whose centre and
+    half-thickness follow its feature, the way a pixel-aligned occupancy network encodes
+    a body, and the field is closed and compact; kappa sets the logit slope
+    (kappa * 2 / 2^L per voxel of a 2^L grid).  The other units keep their random weights,
+    so the arithmetic per point is unchanged.
+    """
+    assert len(spec.widths) >= 2 and spec.n_extra >= 1 and spec.hidden_act == "relu"
+    g = rng(seed)
+    C = spec.feat_dim
+    a = g.standard_normal(C)
+    a /= np.linalg.norm(a)
+    b = g.standard_normal(C)
+    b /= np.linalg.norm(b)
+    W = [w.astype(np.float64) for w in spec.W]
+    B = [x.astype(np.float64) for x in spec.b]
+    # layer 0 reads [f; z(; extras)]
+    W[0][:4, :] = 0.0
+    W[0][0, :C], W[0][0, C] = -mu_scale * a, 1.0
+    W[0][1, :C], W[0][1, C] = mu_scale * a, -1.0
+    W[0][2, :C] = tau_scale * b
+    W[0][3, :C] = -tau_scale * b
+    B[0][:4] = [0.0, 0.0, tau0, -tau0]
+    n = len(spec.widths)
+    for l in range(1, n - 1):
+        W[l][:4, :] = 0.0
+        for k in range(4):
+            W[l][k, k] = 1.0
+        B[l][:4] = 0.0
+    head = W[n - 1]
+    head[:, 4:] *= eps
+    head[:, :4] = np.array([-1.0, -1.0, 1.0, -1.0])
+    head *= kappa
+    B[n - 1] = B[n - 1] * kappa * eps
+    spec.W = [np.ascontiguousarray(w.astype(np.float32)) for w in W]
+    spec.b = [np.ascontiguousarray(x.astype(np.float32)) for x in B]
+    return spec
+
+
 def pifu_mlp(seed: int = 202, out_bias: float = 0.0):
-    """(256+z)->1024->512->256->128->1 with the feature concatenated into hidden layers 2-4."""
-    return he_mlp(256, 1, [1024, 512, 256, 128, 1], [False, True, True, True, False], seed,
+    """(256+z)->1024->512->256->128->1 with the feature concatenated into hidden layers 2-4;
+    a depth-slab occupancy field (see depth_slab_mlp) on He-init weights."""
+    spec = he_mlp(256, 1, [1024, 512, 256, 128, 1], [False, True, True, True, False], seed,
                   out_bias=out_bias)
+    return depth_slab_mlp(spec, seed + 1)
 
 
 def surrogate_mlp(seed: int = 203):
