@@ -1,6 +1,7 @@
 """Benchmark: ms/frame for a 256^3 hierarchical surface + a 512^2 mesh-free render.
 
-One step = one frame of the hot path on synthetic inputs already resident in HBM:
+One step = one frame of the hot path on synthetic inputs already resident in HBM (frame 0
+of a synthetic performance: a feature sequence whose earlier frames train the surrogate):
   * pifu_occupancy_grid: 256^3 cells (257^3 nodes) from a 32^3 coarse level, PIFu-size
     MLP (256+z)->1024->512->256->128->1 with feature skips over a 256 ch x 128 x 128
     feature map;
@@ -36,7 +37,12 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--train-frames", type=int, default=6)
     ap.add_argument("--train-samples", type=int, default=1747627)   # 6 x 1.75 M = 10.5 M
-    ap.add_argument("--epochs", type=int, default=2)
+    ap.add_argument("--train-steps", type=int, default=4000)
+    ap.add_argument("--save-surrogate", default="",
+                    help="write the trained surrogate's weights and chosen delta to this .npz")
+    ap.add_argument("--load-surrogate", default="",
+                    help="use a surrogate written by --save-surrogate instead of training one "
+                         "(keeps training kernels out of a profiled run)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after timing, copy this many MiB device-to-device once (a plain copy "
                          "of known size to calibrate hardware byte counters)")
@@ -51,7 +57,7 @@ def cpu_baseline(points_per_frame, budget_s):
 
     import synth
     from oracle import pifu_oracle as O
-    feat = synth.pifu_features()
+    feat = synth.pifu_sequence(102, 0)   # frame 0 of a performance
     spec = synth.pifu_mlp()
     fld = O.Field("mlp", feat=feat, mlp=spec)
     pts = synth.precision_points(200000, 7)
@@ -84,7 +90,7 @@ def main():
     torch.cuda.set_device(0)
     forms = args.forms.split(",")
     teacher = synth.pifu_mlp()
-    feat = synth.pifu_features()
+    feat = synth.pifu_sequence(102, 0)   # frame 0 of a performance
     t_net = P.DeviceMLP(teacher)
     col_field = P.DeviceField.mlp_field(synth.color_features(), synth.color_mlp())
     view = synth.yaw_view(90.0)
@@ -93,14 +99,22 @@ def main():
     setup = {}
 
     sur_net, delta = None, None
-    if "surrogate_bf16" in forms:
+    if "surrogate_bf16" in forms and args.load_surrogate:
+        import numpy as np
+        z = np.load(args.load_surrogate)
+        spec = synth.surrogate_mlp()
+        spec.W = [z[f"W{l}"] for l in range(len(spec.widths))]
+        spec.b = [z[f"b{l}"] for l in range(len(spec.widths))]
+        sur_net, delta = P.DeviceMLP(spec), float(z["delta"][0])
+        setup = {"surrogate_loaded_from": args.load_surrogate, "surrogate_delta": delta}
+    elif "surrogate_bf16" in forms:
         from paper_2007_13988_amd.surrogate import choose_delta, distill
         t0 = time.perf_counter()
         # the surrogate is distilled on the performance's earlier frames (t = -1 .. -n) and
         # its fallback band chosen on two older held-out frames; the timed frame is t = 0
         sur_net, losses = distill(teacher, synth.surrogate_mlp(),
                                   [synth.pifu_sequence(102, -t) for t in range(1, args.train_frames + 1)],
-                                  samples_per_frame=args.train_samples, epochs=args.epochs, seed=0)
+                                  samples_per_frame=args.train_samples, steps=args.train_steps, seed=0)
         t_train = time.perf_counter() - t0
         n_tr = args.train_frames
         delta, report = choose_delta(teacher, sur_net,
@@ -108,8 +122,15 @@ def main():
                                       synth.pifu_sequence(102, -(n_tr + 2))])
         setup = {"surrogate_train_s": round(t_train, 2),
                  "surrogate_samples": args.train_frames * args.train_samples,
+                 "surrogate_steps": args.train_steps,
                  "surrogate_loss_first_last": [round(losses[0], 5), round(losses[-1], 5)],
                  "surrogate_delta": delta, "delta_sweep": report}
+        if args.save_surrogate:
+            import numpy as np
+            arrs = {f"W{l}": w.cpu().numpy() for l, w in enumerate(sur_net.W)}
+            arrs.update({f"b{l}": b.cpu().numpy() for l, b in enumerate(sur_net.b)})
+            arrs["delta"] = np.array([delta], np.float64)
+            np.savez(args.save_surrogate, **arrs)
 
     def make(form):
         if form == "fp32":

@@ -149,26 +149,23 @@ def make_distill_data(teacher_spec, feats_np: Sequence[np.ndarray], per_frame: i
     return DistillData(feats, samples)
 
 
-def train_surrogate(net: P.DeviceMLP, data: DistillData, epochs: int = 4, batch: int = 65536,
-                    lr: float = 1e-3, seed: int = 0, log_every: int = 0):
-    """RMSProp on the soft-target BCE; batches are drawn frame by frame."""
+def train_surrogate(net: P.DeviceMLP, data: DistillData, steps: int = 4000, batch: int = 65536,
+                    lr: float = 3e-3, lr_final: float = 1e-4, seed: int = 0, log_every: int = 0):
+    """RMSProp on the soft-target BCE.  Step s draws a batch (with replacement) from
+    frame s mod n_frames; the learning rate follows a cosine from lr to lr_final."""
+    import math
     tr = MLPTrainer(net, batch, lr=lr)
     g = torch.Generator(device="cuda")
     g.manual_seed(seed)
     losses = []
-    step = 0
-    for ep in range(epochs):
-        perms = [torch.randperm(s.shape[0], generator=g, device="cuda") for s in data.samples]
-        n_batches = max(s.shape[0] // batch for s in data.samples)
-        for b in range(n_batches):
-            for f, (feat, smp) in enumerate(zip(data.feats, data.samples)):
-                sel = perms[f][b * batch:(b + 1) * batch]
-                if sel.numel() == 0:
-                    continue
-                pts = smp[sel].contiguous()
-                loss = tr.grad(feat, pts)
-                tr.step()
-                step += 1
-                if log_every and step % log_every == 0:
-                    losses.append(float(loss.item()))
+    nf = len(data.samples)
+    for step in range(steps):
+        tr.lr = lr_final + 0.5 * (lr - lr_final) * (1.0 + math.cos(math.pi * step / max(steps, 1)))
+        f = step % nf
+        smp = data.samples[f]
+        sel = torch.randint(0, smp.shape[0], (min(batch, smp.shape[0]),), generator=g, device="cuda")
+        loss = tr.grad(data.feats[f], smp[sel].contiguous())
+        tr.step()
+        if log_every and (step + 1) % log_every == 0:
+            losses.append(float(loss.item()))
     return tr, losses

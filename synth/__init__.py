@@ -14,8 +14,8 @@ Recipe (the paper's workloads stand in as synthetic arrays of the same shape):
     network additionally carries a depth-slab field on four units per layer
     (depth_slab_mlp): each pixel's feature sets one depth interval, so the surface
     is closed and compact like a body's, and the logit is sharp near it.
-  * feature sequences: frame t of a performance is frame 0 moved by t * (1.5, 0.7)
-    pixels plus a fresh smooth field (sequence_frame).
+  * feature sequences: frame t of a performance is the seed's field moved by
+    t * (1.5, 0.7) pixels, mixed with a fresh smooth field (sequence_frame).
   * ellipsoid unions: centres U[-0.4,0.4]^3, semi-axes U[0.15,0.45], rotations
     from normalised Gaussian quaternions.
   * views: yaw rotation about the y axis, no translation (3x4 row-major).
@@ -152,18 +152,16 @@ def pifu_features(seed: int = 102):
     return feature_map(128, 128, 256, 16.0, seed)
 
 
-def sequence_frame(H: int, W: int, C: int, sigma_px: float, seed: int, t: int, eps: float = 0.3,
+def sequence_frame(H: int, W: int, C: int, sigma_px: float, seed: int, t: int, eps: float = 0.1,
                    step_px=(1.5, 0.7)) -> np.ndarray:
-    """Frame t of a video-like feature sequence around feature_map(H, W, C, sigma_px, seed).
+    """Frame t of a video-like feature sequence built on feature_map(H, W, C, sigma_px, seed).
 
-    Frame 0 is that map itself.  Frame t != 0 is the same underlying field moved by
-    t * step_px pixels (x, y; periodic, sub-pixel Fourier shift), mixed with a fresh
-    smooth field of the same spectrum: sqrt(1 - eps^2) * moved + eps * fresh, then
-    re-standardized per channel.  Consecutive frames of one performance are similar
-    in this way, unlike independent seeds.
+    Every frame (t = 0 included) is the seed's underlying field moved by t * step_px
+    pixels (x, y; periodic, sub-pixel Fourier shift), mixed with a fresh smooth field of
+    the same spectrum drawn for that frame: sqrt(1 - eps^2) * moved + eps * fresh, then
+    re-standardized per channel.  Consecutive frames of one performance are similar in
+    this way, unlike independent seeds; eps sets how much new content each frame has.
     """
-    if t == 0:
-        return feature_map(H, W, C, sigma_px, seed)
     g = rng(seed)
     white = g.standard_normal((C, H, W))
     fy = np.fft.fftfreq(H)[:, None]
@@ -185,7 +183,7 @@ def sequence_frame(H: int, W: int, C: int, sigma_px: float, seed: int, t: int, e
 
 
 def pifu_sequence(seed: int, t: int):
-    """Frame t of the sequence whose frame 0 is pifu_features(seed)."""
+    """Frame t of a 256 ch x 128 x 128 feature sequence on the field of pifu_features(seed)."""
     return sequence_frame(128, 128, 256, 16.0, seed, t)
 
 
