@@ -182,7 +182,7 @@ def main():
 
     from paper_2007_13988_amd.surrogate import cell_disagreement
     base = results.get("fp32")
-    chosen = "fp32"
+    chosen = "fp32" if base is not None else forms[0]
     extra = {}
     if "surrogate_bf16" in results and base is not None:
         s = results["surrogate_bf16"]
@@ -213,7 +213,7 @@ def main():
                 "achieved": round(ach, 2), "peak": PEAK_TFLOPS[peak_key], "unit": "TFLOP/s",
                 "frac": round(ach / PEAK_TFLOPS[peak_key], 4), "traffic": None,
                 "launches_per_step": g["launches"] / args.steps, "avg_launch_ms": round(avg_ms, 4),
-                "flops_per_launch": fpl}
+                "flops_per_launch": fpl, "algorithmic_bytes_per_launch": g["bytes"] / g["launches"]}
 
     occ_pts = sum(s["mlp_points"] for s in main_r["gst"])
     ren_pts = sum(s["mlp_points"] for s in main_r["rst"])

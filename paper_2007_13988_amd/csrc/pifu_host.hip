@@ -390,6 +390,18 @@ struct Seg {
   uint32_t base_sub;
 };
 
+// Algorithmic HBM bytes of one GEMM launch: each operand read once, the output written
+// once (A and C in the launch's activation types, W in its operand type).
+double gemm_bytes(const GemmArgs& g, int prec) {
+  const double ea = prec == PIFU_PREC_FP32 ? 4.0 : 2.0;
+  const double ew = prec == PIFU_PREC_FP32 ? 4.0 : prec == PIFU_PREC_BF16 ? 2.0 : 1.0;
+  const double K = (double)g.K1 + g.K2, M = g.M, N = g.N;
+  double b = M * K * ea + N * K * ew + M * N * (g.c_bf16 ? 2.0 : 4.0);
+  if (g.rowadd) b += M * N * 4.0;
+  if (g.n_ext) b += M * 16.0;
+  return b;
+}
+
 // Runs an MLP over n points (chunked): gather -> hidden GEMMs -> head.  prec selects
 // the MFMA operand type of the hidden layers.  segs (nullable) splits the list into
 // frames that share the network but not the feature map; the GEMMs span all frames.
@@ -439,7 +451,7 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
     g.scale = 1.f;
     {
       ProfScope ps(e.ctx, e.s, b16 ? PIFU_KERN_GEMM_BF16 : PIFU_KERN_GEMM_F32,
-                   2.0 * ncol * mp.NP * C, 0.0);
+                   2.0 * ncol * mp.NP * C, gemm_bytes(g, prec));
       if (launch_gemm(g, prec, pick_tile(e, prec, g.N, C, ncol), e.s)) return PIFU_ERR_UNSUPPORTED;
     }
     launch_hoist_layer0(ew.Pcol, mp.NP, ew.cid, lst, m, src.nz, d.W[0], d.in_w[0], C, d.widths[0],
@@ -470,7 +482,7 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
       g.c_bf16 = b16 && (l + 2 < d.n_layers);
       {
         ProfScope ps(e.ctx, e.s, b16 ? PIFU_KERN_GEMM_BF16 : PIFU_KERN_GEMM_F32,
-                     2.0 * m * g.N * g.K1, 0.0);
+                     2.0 * m * g.N * g.K1, gemm_bytes(g, prec));
         if (launch_gemm(g, prec, pick_tile(e, prec, g.N, g.K1, m), e.s)) return PIFU_ERR_UNSUPPORTED;
       }
       prev = out;
@@ -542,7 +554,7 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
         const int kind = prec == PIFU_PREC_FP32   ? PIFU_KERN_GEMM_F32
                          : prec == PIFU_PREC_BF16 ? PIFU_KERN_GEMM_BF16
                                                   : PIFU_KERN_GEMM_FP8;
-        ProfScope ps(e.ctx, e.s, kind, 2.0 * m * g.N * (g.K1 + g.K2 + g.n_ext), 0.0);
+        ProfScope ps(e.ctx, e.s, kind, 2.0 * m * g.N * (g.K1 + g.K2 + g.n_ext), gemm_bytes(g, prec));
         if (launch_gemm(g, prec, pick_tile(e, prec, g.N, g.K1 + g.K2, m), e.s))
           return PIFU_ERR_UNSUPPORTED;
       }
