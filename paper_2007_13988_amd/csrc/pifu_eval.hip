@@ -336,26 +336,51 @@ void launch_guard_fp64(const PointSrc& src, const uint32_t* list, const uint32_t
 // Level-L interpolation along a pixel column (u, v) of the target lattice, from the
 // binarized labels of level L-1: S(kc) sums the labels of the 1/2/4 coarse columns
 // around (u, v); even k use S(k/2), odd k the two neighbours.
+// The render's last level reads the level-(L-1) labels of up to 4 coarse columns per
+// pixel column.  A workgroup takes a 16 x 16 tile of pixel columns; their 9 x 9 coarse
+// columns are contiguous runs of nz bytes per coarse row, so the tile stages the
+// label bits of all of them into LDS with coalesced loads and the rays walk LDS.
+constexpr int kRayTile = 16;
+constexpr int kRayCoarse = kRayTile / 2 + 1;
+
+size_t ray_lds_bytes(Lat c) { return (size_t)kRayCoarse * kRayCoarse * c.nz; }
+
+__device__ inline void stage_ray_labels(const uint8_t* __restrict__ stc, Lat c, int cu0, int cv0,
+                                        uint8_t* sl) {
+  const int row = kRayCoarse * c.nz;   // one coarse row of the tile: kRayCoarse columns of nz
+  const int n = kRayCoarse * row;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int a = e / row, r = e - a * row;
+    const int cu = cu0 + a, cv = cv0 + r / c.nz;
+    uint8_t val = 0;
+    if (cu < c.nx && cv < c.ny) val = stc[((size_t)cu * c.ny + cv0) * c.nz + r] & ST_LABEL;
+    sl[e] = val;
+  }
+  __syncthreads();
+}
+
+// The (up to 4) coarse columns around pixel column (u, v), as LDS offsets.
 struct RayCol {
-  const uint8_t* col[4];
+  int off[4];
   int ncol;
-  __device__ inline int S(int kc) const {
+  __device__ inline int S(const uint8_t* sl, int kc) const {
     int s = 0;
-    for (int i = 0; i < ncol; ++i) s += col[i][kc] & ST_LABEL;
+    for (int i = 0; i < ncol; ++i) s += sl[off[i] + kc];
     return s;
   }
-  __device__ inline void at(int k, int& sum, int& cnt) const {
+  // interpolated value of fine node k of the column as sum / count of coarse labels
+  __device__ inline void at(const uint8_t* sl, int k, int& sum, int& cnt) const {
     if (k & 1) {
-      sum = S(k >> 1) + S((k >> 1) + 1);
+      sum = S(sl, k >> 1) + S(sl, (k >> 1) + 1);
       cnt = 2 * ncol;
     } else {
-      sum = S(k >> 1);
+      sum = S(sl, k >> 1);
       cnt = ncol;
     }
   }
 };
 
-__device__ inline RayCol make_raycol(const uint8_t* stc, Lat c, int u, int v) {
+__device__ inline RayCol make_raycol(int nz, int u, int v, int cu0, int cv0) {
   RayCol r;
   r.ncol = 0;
   const int ua = u >> 1, ub = (u + 1) >> 1, va = v >> 1, vb = (v + 1) >> 1;
@@ -365,7 +390,7 @@ __device__ inline RayCol make_raycol(const uint8_t* stc, Lat c, int u, int v) {
     for (int j = 0; j < 2; ++j) {
       int cv = j ? vb : va;
       if (j && vb == va) continue;
-      r.col[r.ncol++] = stc + ((size_t)cu * c.ny + cv) * c.nz;
+      r.off[r.ncol++] = ((cu - cu0) * kRayCoarse + (cv - cv0)) * nz;
     }
   }
   return r;
@@ -374,25 +399,29 @@ __device__ inline RayCol make_raycol(const uint8_t* stc, Lat c, int u, int v) {
 // Per column: k* = the node nearest the observer whose interpolated value is 1;
 // nodes below it are shadow nodes.  Counts the non-shadow nodes with a fractional
 // interpolated value (the ones the network evaluates).
-__global__ void k_ray_count(const uint8_t* __restrict__ stc, Lat c, int W, int H, int D,
-                            uint32_t* __restrict__ cnt, uint32_t* __restrict__ kstar,
-                            uint32_t* __restrict__ shadow_total) {
-  const uint32_t col = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) k_ray_count(const uint8_t* __restrict__ stc, Lat c, int W,
+                                                   int H, int D, uint32_t* __restrict__ cnt,
+                                                   uint32_t* __restrict__ kstar,
+                                                   uint32_t* __restrict__ shadow_total) {
+  extern __shared__ uint8_t sl[];
+  const int u0 = blockIdx.x * kRayTile, v0 = blockIdx.y * kRayTile;
+  stage_ray_labels(stc, c, u0 >> 1, v0 >> 1, sl);
+  const int u = u0 + (int)(threadIdx.x >> 4), v = v0 + (int)(threadIdx.x & 15);
   uint32_t shadow = 0;
-  if (col < (uint32_t)W * H) {
-    const int u = col / H, v = col - (col / H) * H;
-    RayCol rc = make_raycol(stc, c, u, v);
+  if (u < W && v < H) {
+    const RayCol rc = make_raycol(c.nz, u, v, u0 >> 1, v0 >> 1);
     int ks = -1;
     uint32_t n = 0;
     for (int k = D; k >= 0; --k) {
       int s, t;
-      rc.at(k, s, t);
+      rc.at(sl, k, s, t);
       if (s == t) {
         ks = k;
         break;
       }
       if (s > 0) ++n;
     }
+    const uint32_t col = (uint32_t)u * H + v;
     cnt[col] = n;
     kstar[col] = (uint32_t)ks;
     shadow = ks > 0 ? (uint32_t)ks : 0u;
@@ -401,84 +430,102 @@ __global__ void k_ray_count(const uint8_t* __restrict__ stc, Lat c, int W, int H
   if ((threadIdx.x & 63) == 0 && shadow) atomicAdd(shadow_total, shadow);
 }
 
+dim3 ray_grid(int W, int H) {
+  return dim3((unsigned)((W + kRayTile - 1) / kRayTile), (unsigned)((H + kRayTile - 1) / kRayTile));
+}
+
 void launch_ray_count(const uint8_t* stc, Lat c, int W, int H, int D, uint32_t* cnt,
                       uint32_t* kstar, uint32_t* shadow_total, hipStream_t s) {
-  hipLaunchKernelGGL(k_ray_count, dim3(grid1d((size_t)W * H, 256)), dim3(256), 0, s, stc, c, W, H,
-                     D, cnt, kstar, shadow_total);
+  hipLaunchKernelGGL(k_ray_count, ray_grid(W, H), dim3(kRayTile * kRayTile), ray_lds_bytes(c), s,
+                     stc, c, W, H, D, cnt, kstar, shadow_total);
 }
 
 // Writes the level-L lattice indices of each column's candidates in increasing k.
-__global__ void k_ray_list(const uint8_t* __restrict__ stc, Lat c, int W, int H, int D,
-                           const uint32_t* __restrict__ kstar, const uint32_t* __restrict__ off,
-                           uint32_t* __restrict__ list) {
-  const uint32_t col = blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= (uint32_t)W * H) return;
-  const int u = col / H, v = col - (col / H) * H;
-  RayCol rc = make_raycol(stc, c, u, v);
+__global__ void __launch_bounds__(256) k_ray_list(const uint8_t* __restrict__ stc, Lat c, int W,
+                                                  int H, int D, const uint32_t* __restrict__ kstar,
+                                                  const uint32_t* __restrict__ off,
+                                                  uint32_t* __restrict__ list) {
+  extern __shared__ uint8_t sl[];
+  const int u0 = blockIdx.x * kRayTile, v0 = blockIdx.y * kRayTile;
+  stage_ray_labels(stc, c, u0 >> 1, v0 >> 1, sl);
+  const int u = u0 + (int)(threadIdx.x >> 4), v = v0 + (int)(threadIdx.x & 15);
+  if (u >= W || v >= H) return;
+  const uint32_t col = (uint32_t)u * H + v;
+  const RayCol rc = make_raycol(c.nz, u, v, u0 >> 1, v0 >> 1);
   const int ks = (int)kstar[col];
   uint32_t pos = off[col];
   const size_t base = ((size_t)u * (H + 1) + v) * (size_t)(D + 1);
   for (int k = ks + 1; k <= D; ++k) {
     int s, t;
-    rc.at(k, s, t);
+    rc.at(sl, k, s, t);
     if (s > 0 && s < t) list[pos++] = (uint32_t)(base + k);
   }
 }
 
 void launch_ray_list(const uint8_t* stc, Lat c, int W, int H, int D, const uint32_t* kstar,
                      const uint32_t* off, uint32_t* list, hipStream_t s) {
-  hipLaunchKernelGGL(k_ray_list, dim3(grid1d((size_t)W * H, 256)), dim3(256), 0, s, stc, c, W, H,
-                     D, kstar, off, list);
+  hipLaunchKernelGGL(k_ray_list, ray_grid(W, H), dim3(kRayTile * kRayTile), ray_lds_bytes(c), s,
+                     stc, c, W, H, D, kstar, off, list);
 }
 
 // Second argmax after evaluation: k1 = first node from the observer labelled inside;
 // the surface point is the 0.5 crossing of the occupancy values of k1 and k1 + 1.
-__global__ void k_ray_hit(const uint8_t* __restrict__ stc, const float* __restrict__ occc, Lat c,
-                          int W, int H, int D, const uint32_t* __restrict__ off,
-                          const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ list,
-                          const float* __restrict__ logit, const uint8_t* __restrict__ lab,
-                          const double* __restrict__ view_unused, float* __restrict__ depth,
-                          uint8_t* __restrict__ hit, float4* __restrict__ hitpts, double4 v0,
-                          double4 v1, double4 v2) {
-  const uint32_t col = blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= (uint32_t)W * H) return;
-  const int u = col / H, v = col - (col / H) * H;
-  RayCol rc = make_raycol(stc, c, u, v);
+// The walk reads labels only; the two occupancy values are fetched at the end.
+__global__ void __launch_bounds__(256) k_ray_hit(
+    const uint8_t* __restrict__ stc, const float* __restrict__ occc, Lat c, int W, int H, int D,
+    const uint32_t* __restrict__ off, const uint32_t* __restrict__ cnt,
+    const uint32_t* __restrict__ list, const float* __restrict__ logit,
+    const uint8_t* __restrict__ lab, float* __restrict__ depth, uint8_t* __restrict__ hit,
+    float4* __restrict__ hitpts, double4 v0, double4 v1, double4 v2) {
+  extern __shared__ uint8_t sl[];
+  const int u0 = blockIdx.x * kRayTile, vt0 = blockIdx.y * kRayTile;
+  const int cu0 = u0 >> 1, cv0 = vt0 >> 1;
+  stage_ray_labels(stc, c, cu0, cv0, sl);
+  const int u = u0 + (int)(threadIdx.x >> 4), v = vt0 + (int)(threadIdx.x & 15);
+  if (u >= W || v >= H) return;
+  const uint32_t col = (uint32_t)u * H + v;
+  const RayCol rc = make_raycol(c.nz, u, v, cu0, cv0);
+  const bool even_col = !((u | v) & 1);
+  const int own = (((u >> 1) - cu0) * kRayCoarse + ((v >> 1) - cv0)) * c.nz;  // even columns
   int j = (int)off[col] + (int)cnt[col] - 1;
   const int jmin = (int)off[col];
-  float cur_prev = 0.f;
-  int k1 = -1;
-  float ob = 0.f, of = 0.f;
+  int k1 = -1, j1 = -1, jprev = -1;
   for (int k = D; k >= 0; --k) {
-    float cur;
-    int l;
-    if (!((u | v | k) & 1)) {
-      const size_t cn = ((size_t)(u >> 1) * c.ny + (v >> 1)) * c.nz + (k >> 1);
-      l = stc[cn] & ST_LABEL;
-      cur = occc[cn];
+    int l, jk = -1;
+    if (even_col && !(k & 1)) {
+      l = sl[own + (k >> 1)];
     } else {
       int s, t;
-      rc.at(k, s, t);
+      rc.at(sl, k, s, t);
       const uint32_t lid = ((uint32_t)u * (H + 1) + v) * (uint32_t)(D + 1) + k;
       if (s > 0 && s < t && j >= jmin && list[j] == lid) {
         l = lab[j];
-        cur = 1.0f / (1.0f + expf(-logit[j]));
+        jk = j;
         --j;
       } else {
         l = (s == t);
-        cur = (float)s / (float)t;
       }
     }
     if (l) {
       k1 = k;
-      ob = cur;
-      of = cur_prev;
+      j1 = jk;
       break;
     }
-    cur_prev = cur;
+    jprev = jk;
   }
-  const uint32_t pix = (uint32_t)v * W + u;
   if (k1 < 0) return;
+  // occupancy of node k of this column: a coarse node's stored value, an evaluated
+  // node's sigmoid, else the interpolated fraction
+  auto value = [&](int k, int jk) -> float {
+    if (even_col && !(k & 1)) return occc[((size_t)(u >> 1) * c.ny + (v >> 1)) * c.nz + (k >> 1)];
+    if (jk >= 0) return 1.0f / (1.0f + expf(-logit[jk]));
+    int s, t;
+    rc.at(sl, k, s, t);
+    return (float)s / (float)t;
+  };
+  const float ob = value(k1, j1);
+  const float of = k1 < D ? value(k1 + 1, jprev) : 0.f;
+  const uint32_t pix = (uint32_t)v * W + u;
   double z;
   if (k1 == D) {
     z = 1.0;
@@ -504,8 +551,8 @@ void launch_ray_hit(const uint8_t* stc, const float* occc, Lat c, int W, int H, 
   double4 v0 = make_double4(view[0], view[1], view[2], view[3]);
   double4 v1 = make_double4(view[4], view[5], view[6], view[7]);
   double4 v2 = make_double4(view[8], view[9], view[10], view[11]);
-  hipLaunchKernelGGL(k_ray_hit, dim3(grid1d((size_t)W * H, 256)), dim3(256), 0, s, stc, occc, c, W,
-                     H, D, off, cnt, list, logit, lab, nullptr, depth, hit, hitpts, v0, v1, v2);
+  hipLaunchKernelGGL(k_ray_hit, ray_grid(W, H), dim3(kRayTile * kRayTile), ray_lds_bytes(c), s, stc,
+                     occc, c, W, H, D, off, cnt, list, logit, lab, depth, hit, hitpts, v0, v1, v2);
 }
 
 __global__ void k_fill_image(float* __restrict__ rgb, float* __restrict__ depth,
@@ -587,23 +634,39 @@ __global__ void k_hoist_layer0(const float* __restrict__ P, int ldp, const uint3
                                const uint32_t* __restrict__ list, uint32_t n, int nz,
                                const float* __restrict__ W0, int ldw0, int zcol, int N, int act,
                                void* __restrict__ h, int h_bf16) {
+  // four consecutive outputs per thread (N % 4 == 0, ldp % 4 == 0)
+  const int n4 = N >> 2;
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (size_t)n * N) return;
-  const uint32_t i = (uint32_t)(e / N);
-  const int o = (int)(e - (size_t)i * N);
+  if (e >= (size_t)n * n4) return;
+  const uint32_t i = (uint32_t)(e / n4);
+  const int o = (int)(e - (size_t)i * n4) << 2;
   const uint32_t k = list[i] % (uint32_t)nz;
   const float z = (float)(-1.0 + 2.0 * (double)k / (double)(nz - 1));
-  float v = fmaf(z, W0[(size_t)o * ldw0 + zcol], P[(size_t)cid[i] * ldp + o]);
-  if (act == PIFU_ACT_RELU) v = v > 0.f ? v : 0.f;
-  else if (act == PIFU_ACT_LRELU) v = v > 0.f ? v : 0.01f * v;
-  if (h_bf16) reinterpret_cast<uint16_t*>(h)[e] = f32_to_bf16_bits(v);
-  else reinterpret_cast<float*>(h)[e] = v;
+  const float4 p = *reinterpret_cast<const float4*>(P + (size_t)cid[i] * ldp + o);
+  float v[4] = {fmaf(z, W0[(size_t)o * ldw0 + zcol], p.x),
+                fmaf(z, W0[(size_t)(o + 1) * ldw0 + zcol], p.y),
+                fmaf(z, W0[(size_t)(o + 2) * ldw0 + zcol], p.z),
+                fmaf(z, W0[(size_t)(o + 3) * ldw0 + zcol], p.w)};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (act == PIFU_ACT_RELU) v[q] = v[q] > 0.f ? v[q] : 0.f;
+    else if (act == PIFU_ACT_LRELU) v[q] = v[q] > 0.f ? v[q] : 0.01f * v[q];
+  }
+  const size_t at = (size_t)i * N + o;
+  if (h_bf16) {
+    uint2 w;
+    w.x = (uint32_t)f32_to_bf16_bits(v[0]) | ((uint32_t)f32_to_bf16_bits(v[1]) << 16);
+    w.y = (uint32_t)f32_to_bf16_bits(v[2]) | ((uint32_t)f32_to_bf16_bits(v[3]) << 16);
+    *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(h) + at) = w;
+  } else {
+    *reinterpret_cast<float4*>(reinterpret_cast<float*>(h) + at) = make_float4(v[0], v[1], v[2], v[3]);
+  }
 }
 
 void launch_hoist_layer0(const float* P, int ldp, const uint32_t* cid, const uint32_t* list,
                          uint32_t n, int nz, const float* W0, int ldw0, int zcol, int N, int act,
                          void* h, int h_bf16, hipStream_t s) {
-  const size_t tot = (size_t)n * N;
+  const size_t tot = (size_t)n * (N >> 2);
   if (tot)
     hipLaunchKernelGGL(k_hoist_layer0, dim3(grid1d(tot, 256)), dim3(256), 0, s, P, ldp, cid, list,
                        n, nz, W0, ldw0, zcol, N, act, h, h_bf16);

@@ -114,86 +114,66 @@ struct Gemm64Args {
   int M, N, act;
 };
 
-// 64 x 64 output tile, 4 waves of 32 x 32 (2 x 2 blocks of v_mfma_f64_16x16x4f64).
-// Lane group g = lane/16 feeds the k values [4g, 4g+4) of each 16-wide k step
-// (same permutation for A and B).  Output block layout (checked on gfx950 with a
-// lane probe): lane l, register r holds row 4*r + l/16, column l%16.
+// One 16 x 16 output tile per workgroup (v_mfma_f64_16x16x4f64).  The guard band
+// holds few points, so the tile is small (many workgroups) and the four waves split
+// the contraction: wave q sums the q-th quarter of the 16-wide k steps, and the
+// partial tiles are added in wave order through LDS, so every output is the same
+// fixed-order sum whatever the number of points.  Lane group g = lane/16 feeds the
+// k values {4g .. 4g+3} of each 16-wide step (s-th MFMA: k = 4g + s; same
+// permutation for A and B).  Output layout (checked on gfx950 with a lane probe):
+// lane l, register r holds row 4*r + l/16, column l%16.
 __global__ void __launch_bounds__(256) k_gemm64(Gemm64Args a) {
-  constexpr int BM = 64, BN = 64, BK = 16, LD = BK + 2;
-  __shared__ __attribute__((aligned(16))) double As[BM * LD];
-  __shared__ __attribute__((aligned(16))) double Bs[BN * LD];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  __shared__ double red[3][4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int m0 = blockIdx.x * 16, n0 = blockIdx.y * 16;
   const int K = a.K1 + a.K2;
   const int g = lane >> 4, r16 = lane & 15;
-  f64x4 acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = (f64x4){0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < K; k0 += BK) {
-    const double* src;
-    int ld, kk0;
-    if (k0 < a.K1) {
-      src = a.A1;
-      ld = a.lda1;
-      kk0 = k0;
-    } else {
-      src = a.A2;
-      ld = a.lda2;
-      kk0 = k0 - a.K1;
+  const int arow = m0 + r16;
+  const bool arow_ok = arow < a.M;
+  const double* wrow = a.W + (size_t)(n0 + r16) * K;
+  const int nst = K >> 4;
+  const int s0 = nst * wave / 4, s1 = nst * (wave + 1) / 4;
+  f64x4 acc = (f64x4){0.0, 0.0, 0.0, 0.0};
+  for (int st = s0; st < s1; ++st) {
+    const int k = st * 16 + 4 * g;
+    double2 a01 = make_double2(0.0, 0.0), a23 = make_double2(0.0, 0.0);
+    if (arow_ok) {
+      const double* ap = k < a.K1 ? a.A1 + (size_t)arow * a.lda1 + k
+                                  : a.A2 + (size_t)arow * a.lda2 + (k - a.K1);
+      a01 = *reinterpret_cast<const double2*>(ap);
+      a23 = *reinterpret_cast<const double2*>(ap + 2);
     }
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int e = tid + 256 * i;          // 512 double2 per 64 x 16 tile
-      const int row = e >> 3, c2 = e & 7;
-      const int gm = m0 + row;
-      double2 va = gm < a.M ? *reinterpret_cast<const double2*>(src + (size_t)gm * ld + kk0 + 2 * c2)
-                            : make_double2(0.0, 0.0);
-      *reinterpret_cast<double2*>(&As[row * LD + 2 * c2]) = va;
-      double2 vb = *reinterpret_cast<const double2*>(a.W + (size_t)(n0 + row) * K + k0 + 2 * c2);
-      *reinterpret_cast<double2*>(&Bs[row * LD + 2 * c2]) = vb;
-    }
-    __syncthreads();
-    double av[2][4], bv[2][4];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        av[i][s] = As[(wm * 32 + 16 * i + r16) * LD + 4 * g + s];
-        bv[i][s] = Bs[(wn * 32 + 16 * i + r16) * LD + 4 * g + s];
-      }
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][s], bv[j][s], acc[i][j], 0, 0, 0);
-    __syncthreads();
+    const double2 b01 = *reinterpret_cast<const double2*>(wrow + k);
+    const double2 b23 = *reinterpret_cast<const double2*>(wrow + k + 2);
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a01.x, b01.x, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a01.y, b01.y, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a23.x, b23.x, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a23.y, b23.y, acc, 0, 0, 0);
   }
+  if (wave) {
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+    for (int r = 0; r < 4; ++r) red[wave - 1][r][lane] = acc[r];
+  }
+  __syncthreads();
+  if (wave) return;
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int col = n0 + wn * 32 + 16 * j + r16;
-      const double bias = a.bias[col];
-      double we0 = 0.0, we1 = 0.0;
-      if (a.n_ext > 0) we0 = a.Wf[(size_t)col * a.ldwf + a.ext_col];
-      if (a.n_ext > 1) we1 = a.Wf[(size_t)col * a.ldwf + a.ext_col + 1];
+  for (int r = 0; r < 4; ++r) acc[r] = ((acc[r] + red[0][r][lane]) + red[1][r][lane]) + red[2][r][lane];
+  const int col = n0 + r16;
+  const double bias = a.bias[col];
+  double we0 = 0.0, we1 = 0.0;
+  if (a.n_ext > 0) we0 = a.Wf[(size_t)col * a.ldwf + a.ext_col];
+  if (a.n_ext > 1) we1 = a.Wf[(size_t)col * a.ldwf + a.ext_col + 1];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm * 32 + 16 * i + 4 * r + g;
-        if (row >= a.M) continue;
-        double v = acc[i][j][r] + bias;
-        if (a.n_ext > 0) v += a.ext[4 * (size_t)row] * we0;
-        if (a.n_ext > 1) v += a.ext[4 * (size_t)row + 1] * we1;
-        if (a.act == PIFU_ACT_RELU) v = v > 0.0 ? v : 0.0;
-        else if (a.act == PIFU_ACT_LRELU) v = v > 0.0 ? v : 0.01 * v;
-        a.C[(size_t)row * a.N + col] = v;
-      }
-    }
+  for (int r = 0; r < 4; ++r) {
+    const int row = m0 + 4 * r + g;
+    if (row >= a.M) continue;
+    double v = acc[r] + bias;
+    if (a.n_ext > 0) v += a.ext[4 * (size_t)row] * we0;
+    if (a.n_ext > 1) v += a.ext[4 * (size_t)row + 1] * we1;
+    if (a.act == PIFU_ACT_RELU) v = v > 0.0 ? v : 0.0;
+    else if (a.act == PIFU_ACT_LRELU) v = v > 0.0 ? v : 0.01 * v;
+    a.C[(size_t)row * a.N + col] = v;
+  }
 }
 
 // One wave per point: last layer in float64, then scatter to the guarded positions.
@@ -232,7 +212,7 @@ size_t guard64_ws_bytes(const MLPDesc& d, uint32_t chunk) {
 // float64 and overwrites their logit and label.  ws holds guard64_ws_bytes(d, chunk).
 void run_guard64(const PointSrc& src, const uint32_t* list, const uint32_t* glist, uint32_t gn,
                  const MLPDesc& d, const float* F, int H, int W, int C, float* logit, uint8_t* lab,
-                 void* ws, uint32_t chunk, hipStream_t s) {
+                 void* ws, uint32_t chunk, bool pack, hipStream_t s) {
   if (!gn) return;
   double* base = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(ws) + 255) & ~uintptr_t(255));
   double* Wp[PIFU_MAX_LAYERS];
@@ -241,8 +221,9 @@ void run_guard64(const PointSrc& src, const uint32_t* list, const uint32_t* glis
     const int Kp = l == 0 ? d.feat_dim : d.in_w[l];
     Wp[l] = base;
     base += (size_t)d.widths[l] * Kp;
-    hipLaunchKernelGGL(k_pack64, dim3(grid1d((size_t)d.widths[l] * Kp, 256)), dim3(256), 0, s,
-                       d.W[l], d.widths[l], d.in_w[l], Kp, Wp[l]);
+    if (pack)   // the float64 weight copies persist in ws for the rest of the call
+      hipLaunchKernelGGL(k_pack64, dim3(grid1d((size_t)d.widths[l] * Kp, 256)), dim3(256), 0, s,
+                         d.W[l], d.widths[l], d.in_w[l], Kp, Wp[l]);
     maxw = d.widths[l] > maxw ? d.widths[l] : maxw;
   }
   double* feat = base;
@@ -289,7 +270,7 @@ void run_guard64(const PointSrc& src, const uint32_t* list, const uint32_t* glis
       g.M = (int)m;
       g.N = d.widths[l];
       g.act = d.hidden_act;
-      hipLaunchKernelGGL(k_gemm64, dim3((m + 63) / 64, d.widths[l] / 64), dim3(256), 0, s, g);
+      hipLaunchKernelGGL(k_gemm64, dim3((m + 15) / 16, d.widths[l] / 16), dim3(256), 0, s, g);
       prev = out;
       out = out == hA ? hB : hA;
     }

@@ -355,6 +355,7 @@ struct EvalCtx {
   float band = 0.f;       // |logit| below which BF16/FP8 results are re-run in FP32
   float sur_band = 0.f;   // |logit| below which surrogate results go to the full MLP
   int tile_m = 0;         // forced point tile (64/128/256), 0 = autotuned or 128
+  bool g64_packed = false;  // float64 guard weights already written into the workspace
 };
 
 int batch_bucket(uint32_t m) { return m <= 8192 ? 0 : (m <= 32768 ? 1 : 2); }
@@ -363,10 +364,23 @@ uint64_t tile_key(int prec, int N, int K, uint32_t m) {
   return ((uint64_t)prec << 48) | ((uint64_t)N << 32) | ((uint64_t)K << 8) | (uint64_t)batch_bucket(m);
 }
 
+// Point tile without an autotuned entry: the largest tile that still gives the launch
+// at least 256 workgroups (one per CU).  BF16's 256-point tiles pay off on long
+// contractions (K >= 512) or wide layers (N a multiple of 256, >= 512).
+int default_tile(int prec, int N, int K, uint32_t m) {
+  auto blocks = [&](int bm, int bn) { return ((m + bm - 1) / bm) * (uint64_t)((N + bn - 1) / bn); };
+  const int bn128 = N % 128 == 0 ? 128 : 64;
+  if (prec == PIFU_PREC_BF16 && (K >= 512 || (N % 256 == 0 && N >= 512)) &&
+      blocks(256, N % 256 == 0 ? 256 : bn128) >= 256)
+    return 256;
+  if (blocks(128, bn128) >= 256) return 128;
+  return 64;
+}
+
 int pick_tile(const EvalCtx& e, int prec, int N, int K, uint32_t m) {
   if (e.tile_m) return e.tile_m;
   auto it = e.ctx->tile_cache.find(tile_key(prec, N, K, m));
-  return it == e.ctx->tile_cache.end() ? 128 : it->second;
+  return it == e.ctx->tile_cache.end() ? default_tile(prec, N, K, m) : it->second;
 }
 
 int read_counters(EvalCtx& e, int nwords) {
@@ -418,8 +432,10 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
     nseg = 1;
   }
   // input-view lattice points of one frame: hoist the feature terms per column
+  // (the layer-0 kernel handles four outputs per thread: widths and NP multiples of 4)
   const bool hoist = src.mode == 0 && !src.has_view && prec != PIFU_PREC_FP8 && mp.NP > 0 &&
-                     ew.Pcol != nullptr && (nseg == 1 || src.frame_nodes);
+                     mp.NP % 4 == 0 && d.widths[0] % 4 == 0 && ew.Pcol != nullptr &&
+                     (nseg == 1 || src.frame_nodes);
   for (uint32_t c0 = 0; c0 < n && hoist; c0 += ew.chunk) {
     const uint32_t m = std::min(ew.chunk, n - c0);
     const uint32_t* lst = list + c0;
@@ -613,7 +629,8 @@ int post_full(EvalCtx& e, const FieldPrep& fp, const PointSrc& src, const float*
     r = select_near(e, logit, n, e.guard, ew.glist, &gn);
     if (r) return r;
     run_guard64(src, list, ew.glist, gn, fp.mlp.d, F, f->H, f->W, f->C, logit, lab, ew.g64,
-                ew.chunk64, e.s);
+                ew.chunk64, !e.g64_packed, e.s);
+    if (gn) e.g64_packed = true;
     if (st) st->guard_fp64 += gn;
     r = check_launch();
   }

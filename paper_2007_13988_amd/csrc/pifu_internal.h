@@ -121,9 +121,10 @@ void launch_convert(const float* in, uint32_t n, int fmt, void* out, hipStream_t
 void launch_scatter_results(const uint32_t* pos, uint32_t n, const float* tl, const uint8_t* tb,
                             float* logit, uint8_t* lab, hipStream_t s);
 size_t guard64_ws_bytes(const MLPDesc& d, uint32_t chunk);
+// pack: write the float64 weight copies into ws (once per call; later calls reuse them)
 void run_guard64(const PointSrc& src, const uint32_t* list, const uint32_t* glist, uint32_t gn,
                  const MLPDesc& d, const float* F, int H, int W, int C, float* logit, uint8_t* lab,
-                 void* ws, uint32_t chunk, hipStream_t s);
+                 void* ws, uint32_t chunk, bool pack, hipStream_t s);
 
 // ------------------------------------------------------------------ render kernels
 void launch_ray_count(const uint8_t* stc, Lat c, int W, int H, int D, uint32_t* cnt,
