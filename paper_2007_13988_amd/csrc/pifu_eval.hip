@@ -115,14 +115,14 @@ void launch_eval_analytic(const PointSrc& src, const uint32_t* list, uint32_t n,
 template <bool BF16>
 __global__ void __launch_bounds__(256)
 k_gather(PointSrc src, const uint32_t* __restrict__ list, uint32_t n,
-         const float* __restrict__ F, int H, int W, int C, void* __restrict__ feat,
-         float* __restrict__ ext) {
+         const uint32_t* __restrict__ n_dev, const float* __restrict__ F, int H, int W, int C,
+         void* __restrict__ feat, float* __restrict__ ext) {
   const int lanes = C >> 2;
   const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int per = lanes < 64 ? lanes : 64;   // lanes per point group (<= one wave)
   const uint32_t m = gid / per;
   const int lane = gid % per;
-  if (m >= n) return;
+  if (m >= n || (n_dev && m >= *n_dev)) return;
   double P[3];
   float occ = 0.f;
   int frame = 0;
@@ -160,17 +160,18 @@ k_gather(PointSrc src, const uint32_t* __restrict__ list, uint32_t n,
 }
 
 void launch_gather(const PointSrc& src, const uint32_t* list, uint32_t n, const float* F, int H,
-                   int W, int C, void* feat, int feat_bf16, float* ext, hipStream_t s) {
+                   int W, int C, void* feat, int feat_bf16, float* ext, hipStream_t s,
+                   const uint32_t* n_dev) {
   if (!n) return;
   const int lanes = C >> 2;
   const int per = lanes < 64 ? lanes : 64;
   size_t threads = (size_t)n * per;
   if (feat_bf16)
-    hipLaunchKernelGGL(k_gather<true>, dim3(grid1d(threads, 256)), dim3(256), 0, s, src, list, n, F,
-                       H, W, C, feat, ext);
+    hipLaunchKernelGGL(k_gather<true>, dim3(grid1d(threads, 256)), dim3(256), 0, s, src, list, n,
+                       n_dev, F, H, W, C, feat, ext);
   else
     hipLaunchKernelGGL(k_gather<false>, dim3(grid1d(threads, 256)), dim3(256), 0, s, src, list, n,
-                       F, H, W, C, feat, ext);
+                       n_dev, F, H, W, C, feat, ext);
 }
 
 // ------------------------------------------------------------------ output head
@@ -222,21 +223,25 @@ void launch_head(const float* h, int K, const float* W, const float* b, int n_ou
 }
 
 // ------------------------------------------------------------------ FP64 guard band
+// Appends the positions m < n with |logit[m]| < g (map[m] instead of m when map is
+// given).  The order of the appended positions is unspecified; every consumer treats
+// the points independently.
 __global__ void k_guard_select(const float* __restrict__ logit, uint32_t n, float g,
-                               uint32_t* __restrict__ glist, uint32_t* __restrict__ gcount) {
+                               const uint32_t* __restrict__ map, uint32_t* __restrict__ glist,
+                               uint32_t* __restrict__ gcount) {
   uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= n) return;
   if (fabsf(logit[m]) < g) {
     uint32_t slot = atomicAdd(gcount, 1u);
-    glist[slot] = m;
+    glist[slot] = map ? map[m] : m;
   }
 }
 
 void launch_guard_select(const float* logit, uint32_t n, float g, uint32_t* glist,
-                         uint32_t* gcount, hipStream_t s) {
+                         uint32_t* gcount, hipStream_t s, const uint32_t* map) {
   if (!n || !(g > 0.f)) return;
-  hipLaunchKernelGGL(k_guard_select, dim3(grid1d(n, 256)), dim3(256), 0, s, logit, n, g, glist,
-                     gcount);
+  hipLaunchKernelGGL(k_guard_select, dim3(grid1d(n, 256)), dim3(256), 0, s, logit, n, g, map,
+                     glist, gcount);
 }
 
 constexpr int GUARD_MAXW = 1024;
@@ -632,21 +637,19 @@ void launch_col_ids(const uint32_t* list, const uint32_t* flags, const uint32_t*
 
 __global__ void k_hoist_layer0(const float* __restrict__ P, int ldp, const uint32_t* __restrict__ cid,
                                const uint32_t* __restrict__ list, uint32_t n, int nz,
-                               const float* __restrict__ W0, int ldw0, int zcol, int N, int act,
+                               const float* __restrict__ wz, int N, int act,
                                void* __restrict__ h, int h_bf16) {
-  // four consecutive outputs per thread (N % 4 == 0, ldp % 4 == 0)
-  const int n4 = N >> 2;
-  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (size_t)n * n4) return;
-  const uint32_t i = (uint32_t)(e / n4);
-  const int o = (int)(e - (size_t)i * n4) << 2;
+  // four consecutive outputs per thread (N % 4 == 0, ldp % 4 == 0; n * N / 4 < 2^32)
+  const uint32_t n4 = (uint32_t)N >> 2;
+  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * n4) return;
+  const uint32_t i = e / n4;
+  const uint32_t o = (e - i * n4) << 2;
   const uint32_t k = list[i] % (uint32_t)nz;
   const float z = (float)(-1.0 + 2.0 * (double)k / (double)(nz - 1));
   const float4 p = *reinterpret_cast<const float4*>(P + (size_t)cid[i] * ldp + o);
-  float v[4] = {fmaf(z, W0[(size_t)o * ldw0 + zcol], p.x),
-                fmaf(z, W0[(size_t)(o + 1) * ldw0 + zcol], p.y),
-                fmaf(z, W0[(size_t)(o + 2) * ldw0 + zcol], p.z),
-                fmaf(z, W0[(size_t)(o + 3) * ldw0 + zcol], p.w)};
+  const float4 w = *reinterpret_cast<const float4*>(wz + o);
+  float v[4] = {fmaf(z, w.x, p.x), fmaf(z, w.y, p.y), fmaf(z, w.z, p.z), fmaf(z, w.w, p.w)};
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     if (act == PIFU_ACT_RELU) v[q] = v[q] > 0.f ? v[q] : 0.f;
@@ -654,22 +657,22 @@ __global__ void k_hoist_layer0(const float* __restrict__ P, int ldp, const uint3
   }
   const size_t at = (size_t)i * N + o;
   if (h_bf16) {
-    uint2 w;
-    w.x = (uint32_t)f32_to_bf16_bits(v[0]) | ((uint32_t)f32_to_bf16_bits(v[1]) << 16);
-    w.y = (uint32_t)f32_to_bf16_bits(v[2]) | ((uint32_t)f32_to_bf16_bits(v[3]) << 16);
-    *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(h) + at) = w;
+    uint2 u;
+    u.x = (uint32_t)f32_to_bf16_bits(v[0]) | ((uint32_t)f32_to_bf16_bits(v[1]) << 16);
+    u.y = (uint32_t)f32_to_bf16_bits(v[2]) | ((uint32_t)f32_to_bf16_bits(v[3]) << 16);
+    *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(h) + at) = u;
   } else {
     *reinterpret_cast<float4*>(reinterpret_cast<float*>(h) + at) = make_float4(v[0], v[1], v[2], v[3]);
   }
 }
 
 void launch_hoist_layer0(const float* P, int ldp, const uint32_t* cid, const uint32_t* list,
-                         uint32_t n, int nz, const float* W0, int ldw0, int zcol, int N, int act,
-                         void* h, int h_bf16, hipStream_t s) {
+                         uint32_t n, int nz, const float* wz, int N, int act, void* h, int h_bf16,
+                         hipStream_t s) {
   const size_t tot = (size_t)n * (N >> 2);
   if (tot)
     hipLaunchKernelGGL(k_hoist_layer0, dim3(grid1d(tot, 256)), dim3(256), 0, s, P, ldp, cid, list,
-                       n, nz, W0, ldw0, zcol, N, act, h, h_bf16);
+                       n, nz, wz, N, act, h, h_bf16);
 }
 
 // The library's number-format conversions applied to an array (for checking them).

@@ -32,7 +32,7 @@ __device__ inline float act_apply(float v, int act) {
 // lane l, register r holds row 8*(r/4) + 4*(l/32) + (r%4), column l%32.
 template <bool OUT_BF16>
 __device__ inline void store_block(const GemmArgs& a, const f32x16& acc, int row0, int col0,
-                                   int lane) {
+                                   int lane, int M) {
   const int col = col0 + (lane & 31);
   const float bias = a.bias ? a.bias[col] : 0.f;
   const float we0 = a.n_ext > 0 ? a.Wf[(size_t)col * a.ldwf + a.ext_col] : 0.f;
@@ -40,7 +40,7 @@ __device__ inline void store_block(const GemmArgs& a, const f32x16& acc, int row
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int row = row0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-    if (row >= a.M) continue;
+    if (row >= M) continue;
     float v = acc[r] * a.scale + bias;
     if (a.rowadd) v += a.rowadd[(size_t)a.rowadd_idx[row] * a.rowadd_ld + a.rowadd_off + col];
     if (a.n_ext > 0) {
@@ -69,6 +69,8 @@ __global__ void __launch_bounds__(256, MINB) k_gemm_f32(GemmArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
   const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const int M = a.M_dev ? min(a.M, (int)*a.M_dev) : a.M;
+  if (m0 >= M) return;
   const int K = a.K1 + a.K2;
   const int nk = K / BK;
   constexpr int A_LOADS = BM * (BK / 4) / 256;
@@ -96,7 +98,7 @@ __global__ void __launch_bounds__(256, MINB) k_gemm_f32(GemmArgs a) {
       const int e = tid + 256 * i;
       const int row = e >> 3, c4 = e & 7;
       const int gm = m0 + row;
-      ra[i] = gm < a.M ? *reinterpret_cast<const f32x4*>(src + (size_t)gm * ld + kk0 + 4 * c4)
+      ra[i] = gm < M ? *reinterpret_cast<const f32x4*>(src + (size_t)gm * ld + kk0 + 4 * c4)
                        : (f32x4){0.f, 0.f, 0.f, 0.f};
     }
 #pragma unroll
@@ -173,7 +175,7 @@ __global__ void __launch_bounds__(256, MINB) k_gemm_f32(GemmArgs a) {
   for (int i = 0; i < TI; ++i)
 #pragma unroll
     for (int j = 0; j < TJ; ++j)
-      store_block<false>(a, acc[i][j], m0 + wrow + 32 * i, n0 + wcol + 32 * j, lane);
+      store_block<false>(a, acc[i][j], m0 + wrow + 32 * i, n0 + wcol + 32 * j, lane, M);
 }
 
 // ------------------------------------------------------------------ BF16 operands
@@ -190,6 +192,8 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_bf16(GemmArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
   const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const int M = a.M_dev ? min(a.M, (int)*a.M_dev) : a.M;
+  if (m0 >= M) return;
   const int K = a.K1 + a.K2;
   const int nk = K / BK;
   constexpr int A_LOADS = BM * (BK / 8) / NT;
@@ -217,7 +221,7 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_bf16(GemmArgs a) {
       const int e = tid + NT * i;
       const int row = e >> 3, c8 = e & 7;
       const int gm = m0 + row;
-      ra[i] = gm < a.M ? *reinterpret_cast<const u32x4*>(src + (size_t)gm * ld + kk0 + 8 * c8)
+      ra[i] = gm < M ? *reinterpret_cast<const u32x4*>(src + (size_t)gm * ld + kk0 + 8 * c8)
                        : (u32x4){0u, 0u, 0u, 0u};
     }
 #pragma unroll
@@ -278,7 +282,7 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_bf16(GemmArgs a) {
   for (int i = 0; i < TI; ++i)
 #pragma unroll
     for (int j = 0; j < TJ; ++j)
-      store_block<OUT_BF16>(a, acc[i][j], m0 + wrow + 32 * i, n0 + wcol + 32 * j, lane);
+      store_block<OUT_BF16>(a, acc[i][j], m0 + wrow + 32 * i, n0 + wcol + 32 * j, lane, M);
 }
 
 // Copies the first K columns of a row-major [N][ldw_src] fp32 weight matrix into a
@@ -329,6 +333,8 @@ __global__ void __launch_bounds__(256, MINB) k_gemm_fp8(GemmArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
   const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const int M = a.M_dev ? min(a.M, (int)*a.M_dev) : a.M;
+  if (m0 >= M) return;
   const int K = a.K1 + a.K2;
   const int nk = K / BK;
   // A: BM rows x BK bf16 = BK/8 uint4 per row; B: BN rows x BK bytes = BK/16 uint4 per row
@@ -359,7 +365,7 @@ __global__ void __launch_bounds__(256, MINB) k_gemm_fp8(GemmArgs a) {
       const int e = tid + 256 * i;
       const int row = e / AV, c8 = e % AV;
       const int gm = m0 + row;
-      ra[i] = gm < a.M ? *reinterpret_cast<const u32x4*>(src + (size_t)gm * ld + kk0 + 8 * c8)
+      ra[i] = gm < M ? *reinterpret_cast<const u32x4*>(src + (size_t)gm * ld + kk0 + 8 * c8)
                        : (u32x4){0u, 0u, 0u, 0u};
     }
 #pragma unroll
@@ -436,7 +442,7 @@ __global__ void __launch_bounds__(256, MINB) k_gemm_fp8(GemmArgs a) {
   for (int i = 0; i < TI; ++i)
 #pragma unroll
     for (int j = 0; j < TJ; ++j)
-      store_block<OUT_BF16>(a, acc[i][j], m0 + wrow + 32 * i, n0 + wcol + 32 * j, lane);
+      store_block<OUT_BF16>(a, acc[i][j], m0 + wrow + 32 * i, n0 + wcol + 32 * j, lane, M);
 }
 
 // Per-layer weight quantization: dst = e4m3(W / s_w) for the first K columns, where

@@ -18,7 +18,11 @@ struct ProfRecord {
   int kind;
   int ev;            // index of the start event; stop is ev + 1
   double flops, bytes;
+  int slot = -1;     // pinned slot holding a device-side unit count (-1: none)
+  double flops_per = 0.0, bytes_per = 0.0;   // added per counted unit
 };
+
+constexpr int kProfSlots = 16384;   // device-side counts per call that the profiler can hold
 
 struct pifu_ctx {
   int device;
@@ -28,6 +32,8 @@ struct pifu_ctx {
   bool prof_on = false;
   std::vector<hipEvent_t> events;
   std::vector<ProfRecord> pending;
+  uint32_t* prof_slots = nullptr;   // pinned, kProfSlots words (allocated when profiling starts)
+  int prof_used = 0;
   pifu_kernel_profile prof[PIFU_KERN_COUNT];
 };
 
@@ -38,7 +44,11 @@ struct ProfScope {
   pifu_ctx* c;
   hipStream_t s;
   int idx = -1;
-  ProfScope(pifu_ctx* ctx, hipStream_t st, int kind, double flops, double bytes) : c(ctx), s(st) {
+  // flops/bytes: fixed part; with dev_count, flops_per/bytes_per per unit counted on
+  // the device (copied asynchronously to a pinned slot, read when the call resolves)
+  ProfScope(pifu_ctx* ctx, hipStream_t st, int kind, double flops, double bytes,
+            const uint32_t* dev_count = nullptr, double flops_per = 0.0, double bytes_per = 0.0)
+      : c(ctx), s(st) {
     if (!c || !c->prof_on) return;
     const size_t need = 2 * (c->pending.size() + 1);
     while (c->events.size() < need) {
@@ -47,7 +57,15 @@ struct ProfScope {
       c->events.push_back(e);
     }
     idx = (int)(2 * c->pending.size());
-    c->pending.push_back(ProfRecord{kind, idx, flops, bytes});
+    ProfRecord rec{kind, idx, flops, bytes};
+    if (dev_count && c->prof_slots && c->prof_used < kProfSlots &&
+        hipMemcpyAsync(c->prof_slots + c->prof_used, dev_count, sizeof(uint32_t),
+                       hipMemcpyDeviceToHost, s) == hipSuccess) {
+      rec.slot = c->prof_used++;
+      rec.flops_per = flops_per;
+      rec.bytes_per = bytes_per;
+    }
+    c->pending.push_back(rec);
     (void)hipEventRecord(c->events[idx], s);
   }
   ~ProfScope() {
@@ -62,12 +80,14 @@ void prof_resolve(pifu_ctx* c) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, c->events[r.ev], c->events[r.ev + 1]) != hipSuccess) continue;
     pifu_kernel_profile& p = c->prof[r.kind];
+    const double units = r.slot >= 0 ? (double)c->prof_slots[r.slot] : 0.0;
     p.launches += 1;
     p.total_ms += ms;
-    p.flops += r.flops;
-    p.bytes += r.bytes;
+    p.flops += r.flops + r.flops_per * units;
+    p.bytes += r.bytes + r.bytes_per * units;
   }
   c->pending.clear();
+  c->prof_used = 0;
 }
 
 constexpr size_t kAlign = 256;
@@ -166,6 +186,7 @@ struct MlpPrep {
   float* Wf32 = nullptr;             // [NP][C]
   uint16_t* Wf16 = nullptr;          // [NP][C] (BF16 runs)
   float* bf = nullptr;               // [NP] biases of those layers
+  float* wz = nullptr;               // [widths[0]] layer 0's weights of z, contiguous
 };
 
 void describe_mlp(const pifu_mlp* m, MLPDesc& d) {
@@ -216,6 +237,7 @@ void carve_mlp(Carver& cv, const pifu_mlp* m, int precision, MlpPrep& p) {
     p.Wf32 = cv.take<float>(n);
     p.Wf16 = precision == PIFU_PREC_BF16 ? cv.take<uint16_t>(n) : nullptr;
     p.bf = cv.take<float>(p.NP);
+    p.wz = cv.take<float>(m->widths[0]);
   }
 }
 
@@ -235,6 +257,8 @@ int pack_mlp(MlpPrep& p, pifu_ctx* ctx, hipStream_t s) {
         launch_pack_weights(p.d.W[l] + fcol, p.d.widths[l], p.d.in_w[l], C, p.Wf16 + off * C, 1, s);
       HIP_TRY(hipMemcpyAsync(p.bf + off, p.d.b[l], sizeof(float) * p.d.widths[l],
                              hipMemcpyDeviceToDevice, s));
+      if (l == 0)   // the z column of layer 0 (input [f; z])
+        launch_pack_weights(p.d.W[0] + C, p.d.widths[0], p.d.in_w[0], 1, p.wz, 0, s);
     }
   }
   if (!p.amax) return check_launch();
@@ -439,19 +463,18 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
   for (uint32_t c0 = 0; c0 < n && hoist; c0 += ew.chunk) {
     const uint32_t m = std::min(ew.chunk, n - c0);
     const uint32_t* lst = list + c0;
+    // the number of column runs (<= m) stays on the device: the column gather and
+    // GEMM cover m rows and skip the rows past the count
+    const uint32_t* ncol_dev = e.counters + C_TOTAL;
     launch_col_flags(lst, m, (uint32_t)src.nz, ew.cflags, e.s);
     launch_scan_u32(ew.cflags, m, ew.cexcl, ew.cscan, e.counters + C_TOTAL, e.s);
-    int r = check_launch();
-    if (!r) r = read_counters(e, 1);
-    if (r) return r;
-    const uint32_t ncol = e.ctx->host_counters[C_TOTAL];
     launch_col_ids(lst, ew.cflags, ew.cexcl, m, ew.cid, ew.cnode, e.s);
     {
-      ProfScope ps(e.ctx, e.s, PIFU_KERN_GATHER, 0.0,
-                   (double)ncol * (16.0 * C + (b16 ? 2 : 4) * C + 20.0));
+      ProfScope ps(e.ctx, e.s, PIFU_KERN_GATHER, 0.0, 0.0, ncol_dev, 0.0,
+                   16.0 * C + (b16 ? 2 : 4) * C + 20.0);
       PointSrc sq = src;
       if (!src.frame_nodes) sq.base_sub = segs[0].base_sub;   // else the frame table decodes
-      launch_gather(sq, ew.cnode, ncol, segs[0].F, f->H, f->W, C, ew.feat, b16, ew.ext, e.s);
+      launch_gather(sq, ew.cnode, m, segs[0].F, f->H, f->W, C, ew.feat, b16, ew.ext, e.s, ncol_dev);
     }
     GemmArgs g;
     std::memset(&g, 0, sizeof(g));
@@ -462,16 +485,18 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
     g.bias = mp.bf;
     g.C = ew.Pcol;
     g.ldc = g.N = mp.NP;
-    g.M = (int)ncol;
+    g.M = (int)m;
+    g.M_dev = ncol_dev;
     g.act = 0;
     g.scale = 1.f;
     {
-      ProfScope ps(e.ctx, e.s, b16 ? PIFU_KERN_GEMM_BF16 : PIFU_KERN_GEMM_F32,
-                   2.0 * ncol * mp.NP * C, gemm_bytes(g, prec));
-      if (launch_gemm(g, prec, pick_tile(e, prec, g.N, C, ncol), e.s)) return PIFU_ERR_UNSUPPORTED;
+      const double ea = b16 ? 2.0 : 4.0;
+      ProfScope ps(e.ctx, e.s, b16 ? PIFU_KERN_GEMM_BF16 : PIFU_KERN_GEMM_F32, 0.0,
+                   (double)mp.NP * C * ea, ncol_dev, 2.0 * mp.NP * C, C * ea + mp.NP * 4.0);
+      if (launch_gemm(g, prec, pick_tile(e, prec, g.N, C, m), e.s)) return PIFU_ERR_UNSUPPORTED;
     }
-    launch_hoist_layer0(ew.Pcol, mp.NP, ew.cid, lst, m, src.nz, d.W[0], d.in_w[0], C, d.widths[0],
-                        d.hidden_act, ew.hA, b16 && d.n_layers > 2, e.s);
+    launch_hoist_layer0(ew.Pcol, mp.NP, ew.cid, lst, m, src.nz, mp.wz, d.widths[0], d.hidden_act,
+                        ew.hA, b16 && d.n_layers > 2, e.s);
     const void* prev = ew.hA;
     void* out = ew.hB;
     for (int l = 1; l + 1 < d.n_layers; ++l) {
@@ -588,11 +613,11 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
 
 // Positions m < n with |logit[m]| < bound (any order) and their count.
 int select_near(EvalCtx& e, const float* logit, uint32_t n, float bound, uint32_t* pos,
-                uint32_t* count) {
+                uint32_t* count, const uint32_t* map = nullptr) {
   *count = 0;
   if (!(bound > 0.f) || !n) return PIFU_OK;
   HIP_TRY(hipMemsetAsync(e.counters + C_GUARD, 0, 4, e.s));
-  launch_guard_select(logit, n, bound, pos, e.counters + C_GUARD, e.s);
+  launch_guard_select(logit, n, bound, pos, e.counters + C_GUARD, e.s, map);
   int r = check_launch();
   if (r) return r;
   r = read_counters(e, C_GUARD + 1);
@@ -609,10 +634,12 @@ int post_full(EvalCtx& e, const FieldPrep& fp, const PointSrc& src, const float*
   const pifu_field* f = fp.f;
   int r = PIFU_OK;
   const Seg one{0, n, F, src.base_sub};
+  uint32_t nb_run = 0;   // points re-run in FP32 by the band
   if (e.precision != PIFU_PREC_FP32 && e.band > 0.f) {
     uint32_t nb = 0;
     r = select_near(e, logit, n, e.band, ew.band_pos, &nb);
     if (r) return r;
+    nb_run = nb;
     if (nb) {
       launch_gather_u32(list, ew.band_pos, nb, ew.band_nodes, e.s);
       const Seg bseg{0, nb, F, src.base_sub};
@@ -626,7 +653,13 @@ int post_full(EvalCtx& e, const FieldPrep& fp, const PointSrc& src, const float*
   (void)one;
   if (e.guard > 0.f) {
     uint32_t gn = 0;
-    r = select_near(e, logit, n, e.guard, ew.glist, &gn);
+    if (e.precision != PIFU_PREC_FP32 && e.band > e.guard) {
+      // every point with |logit| < guard lies inside the band and now holds its FP32
+      // result: the guard picks from the band's results only
+      if (nb_run) r = select_near(e, ew.band_logit, nb_run, e.guard, ew.glist, &gn, ew.band_pos);
+    } else {
+      r = select_near(e, logit, n, e.guard, ew.glist, &gn);
+    }
     if (r) return r;
     run_guard64(src, list, ew.glist, gn, fp.mlp.d, F, f->H, f->W, f->C, logit, lab, ew.g64,
                 ew.chunk64, !e.g64_packed, e.s);
@@ -942,6 +975,7 @@ int32_t pifu_create(pifu_ctx** out) {
 void pifu_destroy(pifu_ctx* ctx) {
   if (!ctx) return;
   if (ctx->host_counters) (void)hipHostFree(ctx->host_counters);
+  if (ctx->prof_slots) (void)hipHostFree(ctx->prof_slots);
   for (hipEvent_t ev : ctx->events) (void)hipEventDestroy(ev);
   delete ctx;
 }
@@ -1189,7 +1223,13 @@ int32_t pifu_eval_points(pifu_ctx* ctx, const pifu_field* field, int32_t precisi
 int32_t pifu_profile_enable(pifu_ctx* ctx, int32_t on) {
   if (!ctx) return PIFU_ERR_INVALID_ARGUMENT;
   ctx->prof_on = on != 0;
+  if (ctx->prof_on && !ctx->prof_slots &&
+      hipHostMalloc(reinterpret_cast<void**>(&ctx->prof_slots), sizeof(uint32_t) * kProfSlots,
+                    hipHostMallocDefault) != hipSuccess) {
+    ctx->prof_slots = nullptr;   // counted launches then report their fixed part only
+  }
   ctx->pending.clear();
+  ctx->prof_used = 0;
   std::memset(ctx->prof, 0, sizeof(ctx->prof));
   return PIFU_OK;
 }

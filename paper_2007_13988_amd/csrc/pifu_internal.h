@@ -103,13 +103,15 @@ void launch_eval_analytic(const PointSrc& src, const uint32_t* list, uint32_t n,
                           uint8_t* lab, hipStream_t s);
 // Bilinear gather of C channels (Eq. 1's sampler) for points m in [0, n); writes
 // feat (n x C, fp32 or bf16) and ext (n x 4: z', occ, clipped, 0).
+// n_dev (nullable): device-side point count <= n; the grid covers n points
 void launch_gather(const PointSrc& src, const uint32_t* list, uint32_t n, const float* F, int H,
-                   int W, int C, void* feat, int feat_bf16, float* ext, hipStream_t s);
+                   int W, int C, void* feat, int feat_bf16, float* ext, hipStream_t s,
+                   const uint32_t* n_dev = nullptr);
 void launch_head(const float* h, int K, const float* W, const float* b, int n_out, int out_act,
                  uint32_t n, const float* ext, float* logit, uint8_t* lab, float* rgb_out,
                  const uint32_t* rgb_index, hipStream_t s);
 void launch_guard_select(const float* logit, uint32_t n, float g, uint32_t* glist,
-                         uint32_t* gcount, hipStream_t s);
+                         uint32_t* gcount, hipStream_t s, const uint32_t* map = nullptr);
 void launch_guard_fp64(const PointSrc& src, const uint32_t* list, const uint32_t* glist,
                        uint32_t gn, const MLPDesc& mlp, const float* F, int H, int W, int C,
                        float* logit, uint8_t* lab, hipStream_t s);
@@ -169,6 +171,9 @@ struct GemmArgs {
   const float* rowadd;
   const uint32_t* rowadd_idx;
   int rowadd_ld, rowadd_off;
+  // device-side row count (nullable): rows = min(M, *M_dev); the grid covers M rows and
+  // workgroups past the count exit at once (no host read-back of the count)
+  const uint32_t* M_dev;
 };
 
 // ------------------------------------------------------------------ per-column hoisting
@@ -180,8 +185,8 @@ void launch_col_ids(const uint32_t* list, const uint32_t* flags, const uint32_t*
                     uint32_t* cid, uint32_t* col_node, hipStream_t s);
 // layer 0 with hoisting: h[i][o] = act(P[cid[i]][o] + wz[o] * z_i), z from the node index
 void launch_hoist_layer0(const float* P, int ldp, const uint32_t* cid, const uint32_t* list,
-                         uint32_t n, int nz, const float* W0, int ldw0, int zcol, int N, int act,
-                         void* h, int h_bf16, hipStream_t s);
+                         uint32_t n, int nz, const float* wz, int N, int act, void* h, int h_bf16,
+                         hipStream_t s);
 
 // float32 -> OCP FP8 E4M3FN code (bias 7, 3 mantissa bits, no infinities), round to
 // nearest even, saturating at +-448; NaN -> 0x7f.
