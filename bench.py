@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--load-surrogate", default="",
                     help="use a surrogate written by --save-surrogate instead of training one "
                          "(keeps training kernels out of a profiled run)")
+    ap.add_argument("--batched", action="store_true",
+                    help="also time 16-frame batched occupancy grids against one call per frame")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after timing, copy this many MiB device-to-device once (a plain copy "
                          "of known size to calibrate hardware byte counters)")
@@ -74,6 +76,53 @@ def cpu_baseline(points_per_frame, budget_s):
             "sample": f"FP64 oracle occupancy MLP on {done} points ({dt:.1f} s), scaled to the "
                       f"frame's {points_per_frame} MLP-evaluated points (occupancy grid + render) "
                       f"of the plain FP32 form; level logic and colour MLP not included"}
+
+
+def batched_bench(P, synth, steps):
+    """16 frames of uneven content in one pifu_occupancy_grid_batched call against 16
+    single calls: PIFu-MLP frames (different feature maps) at 256^3 from 32^3 with the
+    autotuned point tile, and ellipsoid-union frames (2-40% occupied) at 256^3 and 512^3."""
+    import torch
+    from paper_2007_13988_amd.pifu import BatchedGrid
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps * 1e3
+
+    res = {}
+    teacher = P.DeviceMLP(synth.pifu_mlp())
+    mlp_frames = [P.DeviceField(P.FIELD_MLP, feat=synth.pifu_sequence(400 + i, 0), mlp=teacher)
+                  for i in range(16)]
+    P.autotune(mlp_frames[0], "fp32")
+    scales = [0.5 + 0.08 * i for i in range(16)]
+    ell_frames = [P.DeviceField.ellipsoids(synth.ellipsoids(8, 500 + i, sc)) for i, sc in enumerate(scales)]
+    for name, frames, L, l0 in (("mlp_256", mlp_frames, 8, 5), ("ellipsoids_256", ell_frames, 8, 5),
+                                ("ellipsoids_512", ell_frames, 9, 6)):
+        opts = [P.grid_opts(L, l0) for _ in frames]
+        bg = BatchedGrid(frames, opts)
+        ms_b = timed(bg.run) / len(frames)
+        outs = P.GridOutputs(frames[0], opts[0])
+        from paper_2007_13988_amd.pifu import occupancy_grid_workspace_size
+        ws_need = max(occupancy_grid_workspace_size(f, opts[0]) for f in frames)
+        if ws_need > outs.ws_bytes:
+            outs.ws = torch.empty(ws_need, dtype=torch.uint8, device="cuda")
+            outs.ws_bytes = ws_need
+        ms_s = timed(lambda: [P.occupancy_grid_into(f, outs) for f in frames]) / len(frames)
+        occ = [float(bg.labels[i].float().mean().item()) for i in range(len(frames))]
+        pts = [sum(s.mlp_points if name.startswith("mlp") else s.evaluated for s in st) for st in bg.stats]
+        res[name] = {"frames": len(frames), "final": f"{(1 << L)}^3 from {(1 << l0)}^3",
+                     "ms_per_frame_batched": round(ms_b, 3), "ms_per_frame_single_calls": round(ms_s, 3),
+                     "speedup": round(ms_s / ms_b, 3),
+                     "occupied_fraction_min_max": [round(min(occ), 4), round(max(occ), 4)],
+                     "evaluated_points_min_max": [min(pts), max(pts)]}
+        del bg, outs
+        torch.cuda.empty_cache()
+    return res
 
 
 def main():
@@ -247,6 +296,8 @@ def main():
                       for f, r in results.items()}
     out["levels_occupancy"] = main_r["gst"]
     out["levels_render"] = main_r["rst"]
+    if args.batched:
+        out["batched"] = batched_bench(P, synth, max(1, min(args.steps, 3)))
     if not args.no_cpu:
         pts = sum(s["mlp_points"] for s in (base or main_r)["gst"] + (base or main_r)["rst"])
         out["cpu_baseline"] = cpu_baseline(pts, args.cpu_seconds)
