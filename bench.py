@@ -78,6 +78,36 @@ def cpu_baseline(points_per_frame, budget_s):
                       f"of the plain FP32 form; level logic and colour MLP not included"}
 
 
+def sources_sha256():
+    """SHA-256 over the library's kernel and host sources (name + bytes, sorted)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2007_13988_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel):
+    """HBM bytes per launch from the committed counter summaries (profiles/traffic_*.md),
+    or None when none matches the kernel or the library has changed since."""
+    import glob
+    sha = sources_sha256()
+    for path in glob.glob(os.path.join(ROOT, "profiles", "traffic_*.md")):
+        rec = {}
+        with open(path) as fh:
+            for line in fh:
+                k, _, v = line.strip().partition(": ")
+                if k in ("traffic_bytes_per_launch", "kernel", "sources_sha256"):
+                    rec[k] = v
+        if rec.get("kernel") == kernel and rec.get("sources_sha256") == sha:
+            return float(rec["traffic_bytes_per_launch"])
+    return None
+
+
 def batched_bench(P, synth, steps):
     """16 frames of uneven content in one pifu_occupancy_grid_batched call against 16
     single calls: PIFu-MLP frames (different feature maps) at 256^3 from 32^3 with the
@@ -260,7 +290,8 @@ def main():
         ach = fpl / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
         return {"kernel": f"k_{key} (MLP hidden layers, {peak_key.upper()} MFMA)", "bound": "mfma",
                 "achieved": round(ach, 2), "peak": PEAK_TFLOPS[peak_key], "unit": "TFLOP/s",
-                "frac": round(ach / PEAK_TFLOPS[peak_key], 4), "traffic": None,
+                "frac": round(ach / PEAK_TFLOPS[peak_key], 4), "traffic": recorded_traffic(key),
+                "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "launches_per_step": g["launches"] / args.steps, "avg_launch_ms": round(avg_ms, 4),
                 "flops_per_launch": fpl, "algorithmic_bytes_per_launch": g["bytes"] / g["launches"]}
 
