@@ -1648,12 +1648,16 @@ void plan_batch(int n, const pifu_field* const* fields, const pifu_grid_opts* co
 
 // Stable compaction over the combined array, then the per-frame bounds of the list;
 // one read-back carries the total and the bounds.
-int compact_frames(EvalCtx& e, BatchPlan& b, int r, uint32_t* n_out, uint32_t* bounds) {
+// Compacts the pending nodes of frames [p_lo, p_hi) of the combined level-r state (the
+// other frames have none); the list holds combined indices p * n_nodes + node.
+int compact_frames(EvalCtx& e, BatchPlan& b, int r, uint32_t* n_out, uint32_t* bounds, int p_lo,
+                   int p_hi) {
   const Lat L = b.lat[r];
   const int A = b.active[r];
-  const size_t tot = L.n() * A;
-  launch_compact(b.st[r], tot, ST_PEND, ST_PEND, b.w.cscratch, e.counters + C_TOTAL, b.w.list,
-                 b.list_cap, 0, L, e.s);
+  const size_t start = (L.n() * (size_t)p_lo) & ~(size_t)15;   // keeps 16-byte state loads aligned
+  const size_t end = L.n() * (size_t)p_hi;
+  launch_compact(b.st[r] + start, end - start, ST_PEND, ST_PEND, b.w.cscratch,
+                 e.counters + C_TOTAL, b.w.list, b.list_cap, 0, L, e.s, (uint32_t)start);
   int rc = check_launch();
   if (rc) return rc;
   rc = read_counters(e, 1);
@@ -1826,7 +1830,7 @@ int32_t pifu_occupancy_grid_batched(pifu_ctx* ctx, int32_t n, const pifu_field* 
       for (int p = 0; p < A; ++p)
         launch_count_bits(b.st[r] + (size_t)p * nl, nl, ST_B0, b.counters + C_B0_F + p, s);
       launch_select(b.st[r], L, s, A);
-      rc = compact_frames(e, b, r, &cnt, bounds);
+      rc = compact_frames(e, b, r, &cnt, bounds, 0, A);
       if (rc) break;
       for (int p = 0; p < A; ++p) st[b.order[p]].dilated = bounds[p + 1] - bounds[p];
       int waves = 0;
@@ -1842,7 +1846,15 @@ int32_t pifu_occupancy_grid_batched(pifu_ctx* ctx, int32_t n, const pifu_field* 
         }
         if (o.max_waves > 0 && waves >= o.max_waves) break;
         launch_expand(b.w.list, cnt, b.st[r], L, s, nl);
-        rc = compact_frames(e, b, r, &cnt, bounds);
+        // only frames with nodes in this wave can gain pending nodes (expansion stays
+        // inside a frame): compact the range of those frames
+        int p_lo = A, p_hi = 0;
+        for (int p = 0; p < A; ++p)
+          if (bounds[p + 1] > bounds[p]) {
+            p_lo = std::min(p_lo, p);
+            p_hi = p + 1;
+          }
+        rc = compact_frames(e, b, r, &cnt, bounds, p_lo, p_hi);
         if (rc) break;
         if (cnt) ++waves;
       }

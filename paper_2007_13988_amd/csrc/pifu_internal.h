@@ -83,9 +83,11 @@ void launch_select(uint8_t* st, Lat f, hipStream_t s, int frames = 1);
 void launch_segment_bounds(const uint32_t* list, uint32_t n, uint32_t frame_nodes, int frames,
                            uint32_t* bounds, hipStream_t s);
 // Stable compaction of the nodes whose state byte satisfies (st & mask) == val.
-// mode 0 writes node indices, mode 1 cell indices (i*(nx-1)+j)*(nz... of lattice f).
+// mode 0 writes node indices (plus index_base), mode 1 cell indices (i*(nx-1)+j)*(nz... of
+// lattice f).  st must be 16-byte aligned.
 void launch_compact(const uint8_t* st, size_t n, uint8_t mask, uint8_t val, uint32_t* bcount,
-                    uint32_t* total, uint32_t* out, uint32_t cap, int mode, Lat f, hipStream_t s);
+                    uint32_t* total, uint32_t* out, uint32_t cap, int mode, Lat f, hipStream_t s,
+                    uint32_t index_base = 0);
 size_t compact_scratch_words(size_t n);
 void launch_apply_grid(const uint32_t* list, uint32_t n, const float* logit, const uint8_t* lab,
                        uint8_t* st, float* occ, uint32_t* conflicts, uint8_t* eval_level,

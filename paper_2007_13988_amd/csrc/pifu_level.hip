@@ -214,7 +214,7 @@ k_scan_small(const uint32_t* __restrict__ in, uint32_t n, uint32_t* __restrict__
 __global__ void __launch_bounds__(COMPACT_BLOCK)
 k_compact_write(const uint8_t* __restrict__ st, size_t n, uint8_t mask, uint8_t val,
                 const uint32_t* __restrict__ boff, uint32_t* __restrict__ out, uint32_t cap,
-                int mode, Lat f) {
+                int mode, Lat f, uint32_t index_base) {
   __shared__ uint32_t wsum[COMPACT_BLOCK / 64];
   size_t base = (size_t)blockIdx.x * COMPACT_TILE + (size_t)threadIdx.x * COMPACT_PER_THREAD;
   uint32_t m = pred_mask16(st, base, n, mask, val);
@@ -231,7 +231,7 @@ k_compact_write(const uint8_t* __restrict__ st, size_t n, uint8_t mask, uint8_t 
     m &= m - 1;
     if (pos < cap) {
       size_t node = base + i;
-      uint32_t v = (uint32_t)node;
+      uint32_t v = index_base + (uint32_t)node;
       if (mode == 1) {
         uint32_t a = (uint32_t)(node / nyz);
         uint32_t r = (uint32_t)(node - (size_t)a * nyz);
@@ -245,10 +245,16 @@ k_compact_write(const uint8_t* __restrict__ st, size_t n, uint8_t mask, uint8_t 
   }
 }
 
-size_t compact_scratch_words(size_t n) { return (n + COMPACT_TILE - 1) / COMPACT_TILE * 2 + 64; }
+size_t scan_scratch_words(size_t n);
+// tile counts + tile offsets (+ the multi-workgroup scan's scratch for long inputs)
+size_t compact_scratch_words(size_t n) {
+  const size_t nb = (n + COMPACT_TILE - 1) / COMPACT_TILE;
+  return nb * 2 + scan_scratch_words(nb) + 64;
+}
 
 void launch_compact(const uint8_t* st, size_t n, uint8_t mask, uint8_t val, uint32_t* bcount,
-                    uint32_t* total, uint32_t* out, uint32_t cap, int mode, Lat f, hipStream_t s) {
+                    uint32_t* total, uint32_t* out, uint32_t cap, int mode, Lat f, hipStream_t s,
+                    uint32_t index_base) {
   uint32_t nb = (uint32_t)((n + COMPACT_TILE - 1) / COMPACT_TILE);
   if (nb == 0) {
     (void)hipMemsetAsync(total, 0, 4, s);
@@ -256,9 +262,14 @@ void launch_compact(const uint8_t* st, size_t n, uint8_t mask, uint8_t val, uint
   }
   uint32_t* boff = bcount + nb;
   hipLaunchKernelGGL(k_compact_count, dim3(nb), dim3(COMPACT_BLOCK), 0, s, st, n, mask, val, bcount);
-  hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, bcount, nb, boff, total);
+  // one workgroup scans up to a few thousand tile counts quickly; longer inputs (many
+  // frames of a batch) take the multi-workgroup scan
+  if (nb <= 8192)
+    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, bcount, nb, boff, total);
+  else
+    launch_scan_u32(bcount, nb, boff, bcount + 2 * (size_t)nb, total, s);
   hipLaunchKernelGGL(k_compact_write, dim3(nb), dim3(COMPACT_BLOCK), 0, s, st, n, mask, val, boff,
-                     out, cap, mode, f);
+                     out, cap, mode, f, index_base);
 }
 
 // ------------------------------------------------------------------ generic scan (render)
