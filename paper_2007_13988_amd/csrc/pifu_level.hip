@@ -31,16 +31,16 @@ void launch_iota(uint32_t* list, uint32_t n, hipStream_t s) {
 // boundary candidates (ST_B0); integral ones are the culled value.
 __global__ void k_transition(const uint8_t* __restrict__ cst, const float* __restrict__ cocc,
                              Lat c, uint8_t* __restrict__ fst, float* __restrict__ focc, Lat f) {
-  size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= f.n()) return;
+  const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;   // one frame has < 2^32 nodes
+  if (n >= (uint32_t)f.n()) return;
   // frame blockIdx.y of a multi-frame state array
   cst += (size_t)blockIdx.y * c.n();
   cocc += (size_t)blockIdx.y * c.n();
   fst += (size_t)blockIdx.y * f.n();
   focc += (size_t)blockIdx.y * f.n();
   const uint32_t nyz = (uint32_t)f.ny * f.nz;
-  const uint32_t a = (uint32_t)(n / nyz);
-  const uint32_t r = (uint32_t)(n - (size_t)a * nyz);
+  const uint32_t a = n / nyz;
+  const uint32_t r = n - a * nyz;
   const uint32_t b = r / f.nz;
   const uint32_t k = r - b * f.nz;
   const uint32_t a0 = a >> 1, a1 = (a + 1) >> 1;
@@ -96,14 +96,15 @@ void launch_transition(const uint8_t* cst, const float* cocc, Lat c, uint8_t* fs
 // 1-ring dilation of the boundary candidates: a node not evaluated before is selected
 // when any node of its 3x3x3 neighbourhood (clipped at the grid edge) is a candidate.
 __global__ void k_select(uint8_t* __restrict__ st, Lat f) {
-  size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= f.n()) return;
+  // one frame has < 2^32 nodes: 32-bit index arithmetic
+  const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= (uint32_t)f.n()) return;
   st += (size_t)blockIdx.y * f.n();   // frame of a multi-frame state array
   uint8_t s = st[n];
   if (s & ST_EVAL) return;
   const uint32_t nyz = (uint32_t)f.ny * f.nz;
   const int a = (int)(n / nyz);
-  const int r = (int)(n - (size_t)a * nyz);
+  const int r = (int)(n - (uint32_t)a * nyz);
   const int b = r / f.nz;
   const int k = r - b * f.nz;
   bool any = false;
@@ -327,18 +328,34 @@ __global__ void k_apply_grid(const uint32_t* __restrict__ list, uint32_t n,
                              uint32_t frame_nodes) {
   uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
   bool conf = false;
-  if (m < n && frame_nodes) {
+  if (frame_nodes) {
     // multi-frame: one conflict counter per frame (no evaluation-level map)
-    const uint32_t node = list[m];
-    const uint8_t s = st[node];
-    const uint8_t l = lab[m] ? ST_LABEL : 0;
-    occ[node] = 1.0f / (1.0f + expf(-logit[m]));
-    uint8_t ns = (uint8_t)((s & ~(ST_LABEL | ST_PEND | ST_CONF)) | ST_EVAL | ST_NOW | l);
-    if (check_conflict && ((l != 0) != ((s & ST_HI) != 0))) {
-      ns |= ST_CONF;
-      if (conflicts) atomicAdd(conflicts + node / frame_nodes, 1u);
+    uint32_t frame = 0;
+    if (m < n) {
+      const uint32_t node = list[m];
+      const uint8_t s = st[node];
+      const uint8_t l = lab[m] ? ST_LABEL : 0;
+      occ[node] = 1.0f / (1.0f + expf(-logit[m]));
+      uint8_t ns = (uint8_t)((s & ~(ST_LABEL | ST_PEND | ST_CONF)) | ST_EVAL | ST_NOW | l);
+      if (check_conflict && ((l != 0) != ((s & ST_HI) != 0))) {
+        ns |= ST_CONF;
+        conf = true;
+      }
+      st[node] = ns;
+      frame = node / frame_nodes;
     }
-    st[node] = ns;
+    if (!conflicts) return;
+    // the list is sorted, so a wave's conflicts nearly always share one frame: one atomic
+    // per wave then, one per conflict where a wave straddles frames
+    const unsigned long long bal = __ballot(conf);
+    if (!bal) return;
+    const int first = __ffsll((long long)bal) - 1;
+    const uint32_t f0 = __shfl(frame, first, 64);
+    if (__all(!conf || frame == f0)) {
+      if ((int)(threadIdx.x & 63) == first) atomicAdd(conflicts + f0, (uint32_t)__popcll(bal));
+    } else if (conf) {
+      atomicAdd(conflicts + frame, 1u);
+    }
     return;
   }
   if (m < n) {
