@@ -1545,7 +1545,7 @@ int32_t pifu_rmsprop_step(pifu_ctx* ctx, const pifu_mlp* net, const float* const
 // ================================================================== multi-frame batching
 namespace {
 
-constexpr int kMaxFrames = 16;
+constexpr int kMaxFrames = kMaxBatch;
 constexpr uint32_t kBatchListCap = 1u << 28;
 enum { C_SEG = 16, C_CONF_F = 40, C_B0_F = 56 };   // counter words (per frame blocks of 16)
 
@@ -1811,6 +1811,10 @@ int32_t pifu_occupancy_grid_batched(pifu_ctx* ctx, int32_t n, const pifu_field* 
       break;
     }
     const bool use_sur = level_id <= o.surrogate_max_log2;
+    // frames whose final level this is write their occupancy straight into their output
+    FrameOcc fo{};
+    for (int p = 0; p < A; ++p)
+      if (b.T[b.order[p]] == r) fo.p[p] = outs[b.order[p]].occ;
     uint32_t cnt = 0;
     if (r == 0) {
       const uint32_t tot = nl * (uint32_t)A;
@@ -1820,13 +1824,13 @@ int32_t pifu_occupancy_grid_batched(pifu_ctx* ctx, int32_t n, const pifu_field* 
       rc = eval_frames(e, b, 0, bounds, tot, st, use_sur);
       if (rc) break;
       launch_apply_grid(b.w.list, tot, b.w.logit, b.w.lab, b.st[0], b.occ[0], nullptr, nullptr,
-                        level_id, L, 1, L, 0, s, nl);
+                        level_id, L, 1, L, 0, s, nl, &fo);
       for (int p = 0; p < A; ++p) {
         st[b.order[p]].dilated = nl;
         st[b.order[p]].evaluated = nl;
       }
     } else {
-      launch_transition(b.st[r - 1], b.occ[r - 1], b.lat[r - 1], b.st[r], b.occ[r], L, s, A);
+      launch_transition(b.st[r - 1], b.occ[r - 1], b.lat[r - 1], b.st[r], b.occ[r], L, s, A, &fo);
       for (int p = 0; p < A; ++p)
         launch_count_bits(b.st[r] + (size_t)p * nl, nl, ST_B0, b.counters + C_B0_F + p, s);
       launch_select(b.st[r], L, s, A);
@@ -1838,7 +1842,7 @@ int32_t pifu_occupancy_grid_batched(pifu_ctx* ctx, int32_t n, const pifu_field* 
         rc = eval_frames(e, b, r, bounds, cnt, st, use_sur);
         if (rc) break;
         launch_apply_grid(b.w.list, cnt, b.w.logit, b.w.lab, b.st[r], b.occ[r],
-                          b.counters + C_CONF_F, nullptr, level_id, L, 1, L, 1, s, nl);
+                          b.counters + C_CONF_F, nullptr, level_id, L, 1, L, 1, s, nl, &fo);
         for (int p = 0; p < A; ++p) {
           const uint32_t c = bounds[p + 1] - bounds[p];
           st[b.order[p]].evaluated += c;
@@ -1879,9 +1883,6 @@ int32_t pifu_occupancy_grid_batched(pifu_ctx* ctx, int32_t n, const pifu_field* 
       rc = compact_count(e, sf, nl, ST_CELL, ST_CELL, b.w.cscratch, outs[f].cells, outs[f].cells_cap,
                          1, L, &nc);
       outs[f].n_cells = nc;
-      if (!rc && hipMemcpyAsync(outs[f].occ, b.occ[r] + (size_t)p * nl, sizeof(float) * nl,
-                                hipMemcpyDeviceToDevice, s) != hipSuccess)
-        rc = PIFU_ERR_HIP;
     }
   }
   if (!rc) rc = hipStreamSynchronize(s) == hipSuccess ? PIFU_OK : PIFU_ERR_HIP;

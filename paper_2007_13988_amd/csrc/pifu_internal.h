@@ -76,8 +76,15 @@ constexpr int COMPACT_TILE = COMPACT_BLOCK * COMPACT_PER_THREAD;
 void launch_fill_u8(uint8_t* p, uint8_t v, size_t n, hipStream_t s);
 void launch_iota(uint32_t* list, uint32_t n, hipStream_t s);
 // frames > 1: `frames` lattices stored back to back (coarse and fine), one grid row each.
+// Frames of one batched call; per frame, where its occupancy goes at a level (null:
+// the combined array's slice of that frame).
+constexpr int kMaxBatch = 16;
+struct FrameOcc {
+  float* p[kMaxBatch];
+};
+
 void launch_transition(const uint8_t* cst, const float* cocc, Lat c, uint8_t* fst, float* focc,
-                       Lat f, hipStream_t s, int frames = 1);
+                       Lat f, hipStream_t s, int frames = 1, const FrameOcc* fo = nullptr);
 void launch_select(uint8_t* st, Lat f, hipStream_t s, int frames = 1);
 // bounds[f] (f = 0..frames) = first list position with entry >= f * frame_nodes.
 void launch_segment_bounds(const uint32_t* list, uint32_t n, uint32_t frame_nodes, int frames,
@@ -92,7 +99,7 @@ size_t compact_scratch_words(size_t n);
 void launch_apply_grid(const uint32_t* list, uint32_t n, const float* logit, const uint8_t* lab,
                        uint8_t* st, float* occ, uint32_t* conflicts, uint8_t* eval_level,
                        int level_id, Lat lvl, int stride, Lat fin, int check_conflict,
-                       hipStream_t s, uint32_t frame_nodes = 0);
+                       hipStream_t s, uint32_t frame_nodes = 0, const FrameOcc* fo = nullptr);
 // frame_nodes > 0: list entries index a multi-frame state array of frames of that size.
 void launch_expand(const uint32_t* list, uint32_t n, uint8_t* st, Lat f, hipStream_t s,
                    uint32_t frame_nodes = 0);

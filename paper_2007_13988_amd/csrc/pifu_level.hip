@@ -30,14 +30,15 @@ void launch_iota(uint32_t* list, uint32_t n, hipStream_t s) {
 // coarse corners (trilinear interpolation of the binary field).  Fractional means are
 // boundary candidates (ST_B0); integral ones are the culled value.
 __global__ void k_transition(const uint8_t* __restrict__ cst, const float* __restrict__ cocc,
-                             Lat c, uint8_t* __restrict__ fst, float* __restrict__ focc, Lat f) {
+                             Lat c, uint8_t* __restrict__ fst, float* __restrict__ focc, Lat f,
+                             FrameOcc fo) {
   const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;   // one frame has < 2^32 nodes
   if (n >= (uint32_t)f.n()) return;
   // frame blockIdx.y of a multi-frame state array
   cst += (size_t)blockIdx.y * c.n();
   cocc += (size_t)blockIdx.y * c.n();
   fst += (size_t)blockIdx.y * f.n();
-  focc += (size_t)blockIdx.y * f.n();
+  focc = fo.p[blockIdx.y] ? fo.p[blockIdx.y] : focc + (size_t)blockIdx.y * f.n();
   const uint32_t nyz = (uint32_t)f.ny * f.nz;
   const uint32_t a = n / nyz;
   const uint32_t r = n - a * nyz;
@@ -88,9 +89,11 @@ __global__ void k_transition(const uint8_t* __restrict__ cst, const float* __res
 }
 
 void launch_transition(const uint8_t* cst, const float* cocc, Lat c, uint8_t* fst, float* focc,
-                       Lat f, hipStream_t s, int frames) {
+                       Lat f, hipStream_t s, int frames, const FrameOcc* fo) {
+  FrameOcc t{};
+  if (fo) t = *fo;
   hipLaunchKernelGGL(k_transition, dim3(grid1d(f.n(), 256), frames), dim3(256), 0, s, cst, cocc, c,
-                     fst, focc, f);
+                     fst, focc, f, t);
 }
 
 // 1-ring dilation of the boundary candidates: a node not evaluated before is selected
@@ -325,7 +328,7 @@ __global__ void k_apply_grid(const uint32_t* __restrict__ list, uint32_t n,
                              uint8_t* __restrict__ st, float* __restrict__ occ,
                              uint32_t* __restrict__ conflicts, uint8_t* __restrict__ eval_level,
                              int level_id, Lat lvl, int stride, Lat fin, int check_conflict,
-                             uint32_t frame_nodes) {
+                             uint32_t frame_nodes, FrameOcc fo) {
   uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
   bool conf = false;
   if (frame_nodes) {
@@ -335,14 +338,16 @@ __global__ void k_apply_grid(const uint32_t* __restrict__ list, uint32_t n,
       const uint32_t node = list[m];
       const uint8_t s = st[node];
       const uint8_t l = lab[m] ? ST_LABEL : 0;
-      occ[node] = 1.0f / (1.0f + expf(-logit[m]));
+      frame = node / frame_nodes;
+      const float p = 1.0f / (1.0f + expf(-logit[m]));
+      if (fo.p[frame]) fo.p[frame][node - frame * frame_nodes] = p;
+      else occ[node] = p;
       uint8_t ns = (uint8_t)((s & ~(ST_LABEL | ST_PEND | ST_CONF)) | ST_EVAL | ST_NOW | l);
       if (check_conflict && ((l != 0) != ((s & ST_HI) != 0))) {
         ns |= ST_CONF;
         conf = true;
       }
       st[node] = ns;
-      frame = node / frame_nodes;
     }
     if (!conflicts) return;
     // the list is sorted, so a wave's conflicts nearly always share one frame: one atomic
@@ -390,11 +395,13 @@ __global__ void k_apply_grid(const uint32_t* __restrict__ list, uint32_t n,
 void launch_apply_grid(const uint32_t* list, uint32_t n, const float* logit, const uint8_t* lab,
                        uint8_t* st, float* occ, uint32_t* conflicts, uint8_t* eval_level,
                        int level_id, Lat lvl, int stride, Lat fin, int check_conflict,
-                       hipStream_t s, uint32_t frame_nodes) {
+                       hipStream_t s, uint32_t frame_nodes, const FrameOcc* fo) {
   if (!n) return;
+  FrameOcc t{};
+  if (fo) t = *fo;
   hipLaunchKernelGGL(k_apply_grid, dim3(grid1d(n, 256)), dim3(256), 0, s, list, n, logit, lab, st,
                      occ, conflicts, eval_level, level_id, lvl, stride, fin, check_conflict,
-                     frame_nodes);
+                     frame_nodes, t);
 }
 
 // Conflict expansion: every not-yet-evaluated node of the 26-neighbourhood of a
