@@ -198,12 +198,14 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_bf16(GemmArgs a) {
   const int nk = K / BK;
   constexpr int A_LOADS = BM * (BK / 8) / NT;
   constexpr int B_LOADS = BN * (BK / 8) / NT;
-  u32x4 ra[A_LOADS], rb[B_LOADS];
+  constexpr int S_LOADS = A_LOADS > B_LOADS ? A_LOADS : B_LOADS;
+  // one staging set, used in turn for the next stage's A tile and then its B tile
+  u32x4 rs[S_LOADS];
   const __bf16* A1 = reinterpret_cast<const __bf16*>(a.A1);
   const __bf16* A2 = reinterpret_cast<const __bf16*>(a.A2);
   const __bf16* Wp = reinterpret_cast<const __bf16*>(a.W);
 
-  auto gload = [&](int kt) {
+  auto gload_a = [&](int kt) {
     const int k0 = kt * BK;
     const __bf16* src;
     int ld, kk0;
@@ -221,26 +223,31 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_bf16(GemmArgs a) {
       const int e = tid + NT * i;
       const int row = e >> 3, c8 = e & 7;
       const int gm = m0 + row;
-      ra[i] = gm < M ? *reinterpret_cast<const u32x4*>(src + (size_t)gm * ld + kk0 + 8 * c8)
-                       : (u32x4){0u, 0u, 0u, 0u};
+      rs[i] = gm < M ? *reinterpret_cast<const u32x4*>(src + (size_t)gm * ld + kk0 + 8 * c8)
+                     : (u32x4){0u, 0u, 0u, 0u};
     }
+  };
+  auto gload_b = [&](int kt) {
+    const int k0 = kt * BK;
 #pragma unroll
     for (int i = 0; i < B_LOADS; ++i) {
       const int e = tid + NT * i;
       const int row = e >> 3, c8 = e & 7;
-      rb[i] = *reinterpret_cast<const u32x4*>(Wp + (size_t)(n0 + row) * a.ldw + k0 + 8 * c8);
+      rs[i] = *reinterpret_cast<const u32x4*>(Wp + (size_t)(n0 + row) * a.ldw + k0 + 8 * c8);
     }
   };
-  auto sstore = [&](int buf) {
+  auto sstore_a = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < A_LOADS; ++i) {
       const int e = tid + NT * i;
-      *reinterpret_cast<u32x4*>(&As[buf][(e >> 3) * LD + 8 * (e & 7)]) = ra[i];
+      *reinterpret_cast<u32x4*>(&As[buf][(e >> 3) * LD + 8 * (e & 7)]) = rs[i];
     }
+  };
+  auto sstore_b = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < B_LOADS; ++i) {
       const int e = tid + NT * i;
-      *reinterpret_cast<u32x4*>(&Bs[buf][(e >> 3) * LD + 8 * (e & 7)]) = rb[i];
+      *reinterpret_cast<u32x4*>(&Bs[buf][(e >> 3) * LD + 8 * (e & 7)]) = rs[i];
     }
   };
 
@@ -252,30 +259,50 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_bf16(GemmArgs a) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-  gload(0);
-  sstore(0);
-  __syncthreads();
   const int h = lane >> 5, l32 = lane & 31;
   const int wrow = wm * (BM / WM), wcol = wn * (BN / WN);
-  for (int kt = 0; kt < nk; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < nk) gload(kt + 1);
+  // operand fragments of one 16-wide k step, double-buffered across the steps
+  bf16x8 av[2][TI], bv[2][TJ];
+  auto load_frags = [&](int buf, int kk, int q) {
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 16) {
-      bf16x8 av[TI], bv[TJ];
+    for (int i = 0; i < TI; ++i)
+      av[q][i] = *reinterpret_cast<const bf16x8*>(&As[buf][(wrow + 32 * i + l32) * LD + kk + 8 * h]);
 #pragma unroll
-      for (int i = 0; i < TI; ++i)
-        av[i] = *reinterpret_cast<const bf16x8*>(&As[buf][(wrow + 32 * i + l32) * LD + kk + 8 * h]);
+    for (int j = 0; j < TJ; ++j)
+      bv[q][j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][(wcol + 32 * j + l32) * LD + kk + 8 * h]);
+  };
+  auto mfmas = [&](int q) {
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
 #pragma unroll
       for (int j = 0; j < TJ; ++j)
-        bv[j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][(wcol + 32 * j + l32) * LD + kk + 8 * h]);
-#pragma unroll
-      for (int i = 0; i < TI; ++i)
-#pragma unroll
-        for (int j = 0; j < TJ; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[q][i], bv[q][j], acc[i][j], 0, 0, 0);
+  };
+
+  gload_a(0);
+  sstore_a(0);
+  gload_b(0);
+  sstore_b(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    const bool more = kt + 1 < nk;
+    if (more) gload_a(kt + 1);
+    load_frags(buf, 0, 0);
+    load_frags(buf, 16, 1);
+    mfmas(0);
+    load_frags(buf, 32, 0);
+    mfmas(1);
+    // the other buffer was last read before the previous barrier: stage A there, then
+    // reuse the staging registers for B
+    if (more) {
+      sstore_a(buf ^ 1);
+      gload_b(kt + 1);
     }
-    if (kt + 1 < nk) sstore(buf ^ 1);
+    load_frags(buf, 48, 1);
+    mfmas(0);
+    mfmas(1);
+    if (more) sstore_b(buf ^ 1);
     __syncthreads();
   }
 #pragma unroll
