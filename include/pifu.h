@@ -68,7 +68,8 @@ typedef struct pifu_ctx pifu_ctx;
  * occupancy value (n_extra = 2).  Layer l >= 1 reads [h_{l-1}; f] when skip[l]
  * is non-zero, else h_{l-1}.  Hidden layers use hidden_act; the last layer
  * (1 or 3 outputs) is followed by out_act.
- * W[l] is device float32 row-major [widths[l]][in_width(l)]; b[l] device float32.
+ * W[l] is device float32 row-major [widths[l]][in_width(l)], 16-byte aligned;
+ * b[l] device float32.  A null or misaligned pointer is INVALID_ARGUMENT.
  * Supported: feat_dim % 32 == 0, hidden widths % 64 == 0, last width <= 4.
  * fp8_amax[l] (host value) is the calibrated max |input| of layer l, used for the
  * static FP8 activation scale; 0 selects the default amax 16.

@@ -175,29 +175,39 @@ void launch_gather(const PointSrc& src, const uint32_t* list, uint32_t n, const 
 }
 
 // ------------------------------------------------------------------ output head
-// One wave per point: the last linear layer (<= 4 outputs) as a wave-wide dot
-// product, then the output rule.  n_out == 1: occupancy logit (-inf when clipped),
-// label = [logit > 0].  n_out == 3: colour, tanh, written to rgb_out[pixel * 3 + c].
+// Sixteen lanes per point (four points per wave): the last linear layer (<= 4 outputs)
+// as a dot product over K (a multiple of 64; each lane takes float4 slices 64 apart),
+// reduced across the 16 lanes, then the output rule.  n_out == 1: occupancy logit
+// (-inf when clipped), label = [logit > 0].  n_out == 3: colour, tanh, written to
+// rgb_out[pixel * 3 + c].
 __global__ void __launch_bounds__(256)
 k_head(const float* __restrict__ h, int K, const float* __restrict__ W, const float* __restrict__ b,
        int n_out, int out_act, uint32_t n, const float* __restrict__ ext, float* __restrict__ logit,
        uint8_t* __restrict__ lab, float* __restrict__ rgb_out, const uint32_t* __restrict__ rgb_index) {
-  const uint32_t m = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int lane = threadIdx.x & 63;
-  if (m >= n) return;
+  const uint32_t m = (blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+  const int q = threadIdx.x & 15;
+  if (m >= n) return;   // whole 16-lane groups leave together
   float acc[4] = {0.f, 0.f, 0.f, 0.f};
   const float* hr = h + (size_t)m * K;
-  for (int k = lane; k < K; k += 64) {
-    const float x = hr[k];
-    for (int o = 0; o < n_out; ++o) acc[o] = fmaf(x, W[(size_t)o * K + k], acc[o]);
+  for (int k = 4 * q; k < K; k += 64) {
+    const float4 x = *reinterpret_cast<const float4*>(hr + k);
+    for (int o = 0; o < n_out; ++o) {
+      const float4 w = *reinterpret_cast<const float4*>(W + (size_t)o * K + k);
+      float a = acc[o];
+      a = fmaf(x.x, w.x, a);
+      a = fmaf(x.y, w.y, a);
+      a = fmaf(x.z, w.z, a);
+      a = fmaf(x.w, w.w, a);
+      acc[o] = a;
+    }
   }
   for (int o = 0; o < n_out; ++o) {
     float v = acc[o];
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    for (int d = 8; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
     acc[o] = v + b[o];
   }
-  if (lane != 0) return;
+  if (q != 0) return;
   if (n_out == 1) {
     float v = acc[0];
     if (ext && ext[4 * (size_t)m + 2] != 0.f) v = -INFINITY;
@@ -218,7 +228,7 @@ void launch_head(const float* h, int K, const float* W, const float* b, int n_ou
                  uint32_t n, const float* ext, float* logit, uint8_t* lab, float* rgb_out,
                  const uint32_t* rgb_index, hipStream_t s) {
   if (!n) return;
-  hipLaunchKernelGGL(k_head, dim3(grid1d((size_t)n * 64, 256)), dim3(256), 0, s, h, K, W, b, n_out,
+  hipLaunchKernelGGL(k_head, dim3(grid1d((size_t)n * 16, 256)), dim3(256), 0, s, h, K, W, b, n_out,
                      out_act, n, ext, logit, lab, rgb_out, rgb_index);
 }
 

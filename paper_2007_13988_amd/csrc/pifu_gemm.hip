@@ -37,22 +37,38 @@ __device__ inline void store_block(const GemmArgs& a, const f32x16& acc, int row
   const float bias = a.bias ? a.bias[col] : 0.f;
   const float we0 = a.n_ext > 0 ? a.Wf[(size_t)col * a.ldwf + a.ext_col] : 0.f;
   const float we1 = a.n_ext > 1 ? a.Wf[(size_t)col * a.ldwf + a.ext_col + 1] : 0.f;
+  // loads use the row clamped into range (M >= 1 here), so all of them can be in
+  // flight together; only the stores are predicated
+  int rr[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) rr[r] = min(row0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), M - 1);
+  float v[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = acc[r] * a.scale + bias;
+  if (a.rowadd) {
+    uint32_t ix[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) ix[r] = a.rowadd_idx[rr[r]];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] += a.rowadd[(size_t)ix[r] * a.rowadd_ld + a.rowadd_off + col];
+  }
+  if (a.n_ext > 0) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const float* ex = a.ext + 4 * (size_t)rr[r];
+      v[r] = fmaf(ex[0], we0, v[r]);
+      if (a.n_ext > 1) v[r] = fmaf(ex[1], we1, v[r]);
+    }
+  }
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int row = row0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
     if (row >= M) continue;
-    float v = acc[r] * a.scale + bias;
-    if (a.rowadd) v += a.rowadd[(size_t)a.rowadd_idx[row] * a.rowadd_ld + a.rowadd_off + col];
-    if (a.n_ext > 0) {
-      const float* ex = a.ext + 4 * (size_t)row;
-      v = fmaf(ex[0], we0, v);
-      if (a.n_ext > 1) v = fmaf(ex[1], we1, v);
-    }
-    v = act_apply(v, a.act);
+    const float x = act_apply(v[r], a.act);
     if (OUT_BF16)
-      reinterpret_cast<uint16_t*>(a.C)[(size_t)row * a.ldc + col] = f32_to_bf16_bits(v);
+      reinterpret_cast<uint16_t*>(a.C)[(size_t)row * a.ldc + col] = f32_to_bf16_bits(x);
     else
-      reinterpret_cast<float*>(a.C)[(size_t)row * a.ldc + col] = v;
+      reinterpret_cast<float*>(a.C)[(size_t)row * a.ldc + col] = x;
   }
 }
 

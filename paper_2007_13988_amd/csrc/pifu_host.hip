@@ -130,6 +130,7 @@ int validate_mlp(const pifu_mlp* m, int C, int n_extra_expected, int n_out_expec
     return PIFU_ERR_INVALID_ARGUMENT;
   for (int l = 0; l < m->n_layers; ++l) {
     if (!m->W[l] || !m->b[l]) return PIFU_ERR_INVALID_ARGUMENT;
+    if (reinterpret_cast<uintptr_t>(m->W[l]) % 16 != 0) return PIFU_ERR_INVALID_ARGUMENT;
     const bool last = l == m->n_layers - 1;
     if (last) {
       if (m->widths[l] != n_out_expected) return PIFU_ERR_INVALID_ARGUMENT;

@@ -111,3 +111,33 @@ def test_status_strings(P):
     lib = P.load_library()
     assert lib.pifu_status_string(0) == b"ok"
     assert lib.pifu_status_string(-2) == b"workspace too small"
+
+
+def test_mlp_field_validation_checks_weight_pointers(P):
+    """Host-side checks of a network descriptor (no device memory is touched: the
+    workspace query validates before anything launches)."""
+    from paper_2007_13988_amd.pifu import PifuField, PifuMLP
+    widths = [128, 64, 1]
+    m = PifuMLP()
+    m.n_layers, m.feat_dim, m.n_extra = 3, 64, 1
+    m.hidden_act, m.out_act = P.ACT["relu"], P.ACT["sigmoid"]
+    for l, w in enumerate(widths):
+        m.widths[l] = w
+        m.W[l] = 0x100000 + 0x10000 * l      # stand-in addresses, 16-byte aligned
+        m.b[l] = 0x200000 + 0x10000 * l
+    f = PifuField()
+    f.kind, f.H, f.W, f.C = P.FIELD_MLP, 32, 32, 64
+    f.feat = 0x300000
+    f.mlp = C.pointer(m)
+
+    class _F:
+        struct = f
+    assert _ws(P, _F, P.grid_opts(5, 3))[0] == 0
+    m.W[2] = 0x120004                          # misaligned head weights
+    assert _ws(P, _F, P.grid_opts(5, 3))[0] == -1
+    m.W[2] = 0x120000
+    m.b[1] = 0                                 # null bias
+    assert _ws(P, _F, P.grid_opts(5, 3))[0] == -1
+    m.b[1] = 0x210000
+    m.widths[0] = 96                           # hidden width not a multiple of 64
+    assert _ws(P, _F, P.grid_opts(5, 3))[0] == -1
