@@ -139,7 +139,9 @@ typedef struct pifu_level_stats {
  *   exactly (0 disables).  surrogate_max_log2: levels with at most this log2
  *   size use field->surrogate when present (points with |p_s - 0.5| <
  *   surrogate_delta go to the full MLP); -1 disables.  tile_m: MLP point tile
- *   (0 = default 128; 64/128/256).  max_waves: cap on conflict waves per level
+ *   (0 = chosen per launch: autotuned, else by size; 32 (FP32 only, else 64), 64,
+ *   128 or 256).  Every tile gives bit-identical results.  max_waves: cap on
+ *   conflict waves per level
  *   (0 = none).
  */
 typedef struct pifu_grid_opts {

@@ -364,12 +364,24 @@ __device__ inline void stage_ray_labels(const uint8_t* __restrict__ stc, Lat c, 
                                         uint8_t* sl) {
   const int row = kRayCoarse * c.nz;   // one coarse row of the tile: kRayCoarse columns of nz
   const int n = kRayCoarse * row;
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const int a = e / row, r = e - a * row;
-    const int cu = cu0 + a, cv = cv0 + r / c.nz;
-    uint8_t val = 0;
-    if (cu < c.nx && cv < c.ny) val = stc[((size_t)cu * c.ny + cv0) * c.nz + r] & ST_LABEL;
-    sl[e] = val;
+  // eight independent byte loads in flight per thread
+  for (int e0 = threadIdx.x; e0 < n; e0 += 8 * blockDim.x) {
+    uint8_t v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * (int)blockDim.x;
+      v[u] = 0;
+      if (e < n) {
+        const int a = e / row, r = e - a * row;
+        const int cu = cu0 + a, cv = cv0 + r / c.nz;
+        if (cu < c.nx && cv < c.ny) v[u] = stc[((size_t)cu * c.ny + cv0) * c.nz + r] & ST_LABEL;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * (int)blockDim.x;
+      if (e < n) sl[e] = v[u];
+    }
   }
   __syncthreads();
 }

@@ -75,8 +75,9 @@ __device__ inline void store_block(const GemmArgs& a, const f32x16& acc, int row
 // ------------------------------------------------------------------ FP32 operands
 // v_mfma_f32_32x32x2_f32: per lane one A and one B element per MFMA; 4 MFMAs consume
 // a float4 of k from LDS (k-group of 8).
-template <int BM, int BN, int WM, int WN, int MINB>
-__global__ void __launch_bounds__(256, MINB) k_gemm_f32(GemmArgs a) {
+template <int BM, int BN, int WM, int WN, int MINB, int NT = 256>
+__global__ void __launch_bounds__(NT, MINB) k_gemm_f32(GemmArgs a) {
+  // NT = 64 * WM * WN threads (the 32-point tile for tiny launches uses 2 waves)
   constexpr int BK = 32;
   constexpr int LD = BK + 4;
   constexpr int TI = BM / WM / 32, TJ = BN / WN / 32;
@@ -89,8 +90,8 @@ __global__ void __launch_bounds__(256, MINB) k_gemm_f32(GemmArgs a) {
   if (m0 >= M) return;
   const int K = a.K1 + a.K2;
   const int nk = K / BK;
-  constexpr int A_LOADS = BM * (BK / 4) / 256;
-  constexpr int B_LOADS = BN * (BK / 4) / 256;
+  constexpr int A_LOADS = BM * (BK / 4) / NT;
+  constexpr int B_LOADS = BN * (BK / 4) / NT;
   f32x4 ra[A_LOADS], rb[B_LOADS];
   const float* A1 = reinterpret_cast<const float*>(a.A1);
   const float* A2 = reinterpret_cast<const float*>(a.A2);
@@ -111,7 +112,7 @@ __global__ void __launch_bounds__(256, MINB) k_gemm_f32(GemmArgs a) {
     }
 #pragma unroll
     for (int i = 0; i < A_LOADS; ++i) {
-      const int e = tid + 256 * i;
+      const int e = tid + NT * i;
       const int row = e >> 3, c4 = e & 7;
       const int gm = m0 + row;
       ra[i] = gm < M ? *reinterpret_cast<const f32x4*>(src + (size_t)gm * ld + kk0 + 4 * c4)
@@ -119,7 +120,7 @@ __global__ void __launch_bounds__(256, MINB) k_gemm_f32(GemmArgs a) {
     }
 #pragma unroll
     for (int i = 0; i < B_LOADS; ++i) {
-      const int e = tid + 256 * i;
+      const int e = tid + NT * i;
       const int row = e >> 3, c4 = e & 7;
       rb[i] = *reinterpret_cast<const f32x4*>(Wp + (size_t)(n0 + row) * a.ldw + k0 + 4 * c4);
     }
@@ -127,12 +128,12 @@ __global__ void __launch_bounds__(256, MINB) k_gemm_f32(GemmArgs a) {
   auto sstore = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < A_LOADS; ++i) {
-      const int e = tid + 256 * i;
+      const int e = tid + NT * i;
       *reinterpret_cast<f32x4*>(&As[buf][(e >> 3) * LD + 4 * (e & 7)]) = ra[i];
     }
 #pragma unroll
     for (int i = 0; i < B_LOADS; ++i) {
-      const int e = tid + 256 * i;
+      const int e = tid + NT * i;
       *reinterpret_cast<f32x4*>(&Bs[buf][(e >> 3) * LD + 4 * (e & 7)]) = rb[i];
     }
   };
@@ -543,9 +544,15 @@ int launch_gemm(const GemmArgs& a, int precision, int tile_m, hipStream_t s) {
   if (a.M <= 0) return 0;
   const bool bn128 = (a.N % 128) == 0;
   if (!bn128 && (a.N % 64) != 0) return -1;
-  const int bm = tile_m == 64 ? 64 : (tile_m == 256 ? 256 : 128);
+  int bm = tile_m == 64 ? 64 : (tile_m == 256 ? 256 : (tile_m == 32 ? 32 : 128));
   if (precision == PIFU_PREC_FP32) {
     if ((a.K1 % 32) || (a.K2 % 32)) return -1;
+    if (bm == 32) {
+      // tiny launches: 32 x 64 tiles of two 32 x 32 waves spread the work over more CUs
+      hipLaunchKernelGGL((k_gemm_f32<32, 64, 1, 2, 2, 128>), dim3((a.M + 31) / 32, a.N / 64),
+                         dim3(128), 0, s, a);
+      return 0;
+    }
     if (bn128) {
       if (bm == 64) PIFU_F32(64, 128, 1, 4, 2);
       else if (bm == 128) PIFU_F32(128, 128, 2, 2, 2);
@@ -557,6 +564,7 @@ int launch_gemm(const GemmArgs& a, int precision, int tile_m, hipStream_t s) {
     }
     return 0;
   }
+  if (bm == 32) bm = 64;   // the 32-point tile exists for FP32 only
   if (precision == PIFU_PREC_BF16) {
     if ((a.K1 % 64) || (a.K2 % 64)) return -1;
     if (bn128) {

@@ -379,7 +379,7 @@ struct EvalCtx {
   float guard;            // |logit| below which FP32 results are re-run in FP64
   float band = 0.f;       // |logit| below which BF16/FP8 results are re-run in FP32
   float sur_band = 0.f;   // |logit| below which surrogate results go to the full MLP
-  int tile_m = 0;         // forced point tile (64/128/256), 0 = autotuned or 128
+  int tile_m = 0;         // forced point tile (32/64/128/256), 0 = chosen per launch
   bool g64_packed = false;  // float64 guard weights already written into the workspace
 };
 
@@ -404,6 +404,8 @@ int default_tile(int prec, int N, int K, uint32_t m) {
 
 int pick_tile(const EvalCtx& e, int prec, int N, int K, uint32_t m) {
   if (e.tile_m) return e.tile_m;
+  // a few dozen points: FP32 32-point tiles put twice the workgroups on the chip
+  if (prec == PIFU_PREC_FP32 && m <= 96) return 32;
   auto it = e.ctx->tile_cache.find(tile_key(prec, N, K, m));
   return it == e.ctx->tile_cache.end() ? default_tile(prec, N, K, m) : it->second;
 }

@@ -52,13 +52,13 @@ def test_batched_ellipsoid_frames_match_single_calls(pifu):
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_tile_choice_never_changes_results(pifu, prec):
-    """Forced point tiles 64/128/256 and the autotuned choice give identical grids."""
+    """Forced point tiles 32/64/128/256 and the autotuned choice give identical grids."""
     from paper_2007_13988_amd import pifu as PP
     feat = synth.pifu_features(513)
     spec = synth.pifu_mlp()
     fld = pifu.DeviceField.mlp_field(feat, spec)
     ref = pifu.occupancy_grid(fld, 6, 4, precision=prec, tile_m=128)
-    for t in (64, 256):
+    for t in (32, 64, 256):
         o = pifu.occupancy_grid(fld, 6, 4, precision=prec, tile_m=t)
         assert torch.equal(o["labels"], ref["labels"]) and torch.equal(o["occ"], ref["occ"]), t
     chosen = PP.autotune(fld, prec, batch_sizes=(4096, 16384))
