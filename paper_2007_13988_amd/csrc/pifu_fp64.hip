@@ -2,6 +2,8 @@
 // |logit| < g, so that the binary label [logit > 0] is decided in float64.  The
 // guarded points are batched: float64 gather, float64 MFMA GEMMs per hidden layer,
 // float64 head -- the same network as the FP32 path, evaluated in double precision.
+#include <algorithm>
+
 #include "pifu_internal.h"
 
 namespace pifu {
@@ -49,19 +51,21 @@ __device__ inline bool src_point64(const PointSrc& s, uint32_t idx, double P[3],
 
 // Node list of the guarded points: gnode[i] = list[glist[i]].
 __global__ void k_guard_nodes(const uint32_t* __restrict__ list, const uint32_t* __restrict__ glist,
-                              uint32_t gn, uint32_t* __restrict__ gnode) {
+                              uint32_t gn, const uint32_t* __restrict__ gn_dev,
+                              uint32_t* __restrict__ gnode) {
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < gn) gnode[i] = list ? list[glist[i]] : glist[i];
+  if (i < gn && (!gn_dev || i < *gn_dev)) gnode[i] = list ? list[glist[i]] : glist[i];
 }
 
 // One wave per point: float64 bilinear blend of C channels; ext64 = (z', occ, clipped, 0).
 __global__ void __launch_bounds__(256)
 k_gather64(PointSrc src, const uint32_t* __restrict__ nodes, uint32_t n,
-           const float* __restrict__ F, int H, int W, int C, double* __restrict__ feat,
-           double* __restrict__ ext) {
-  const uint32_t m = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+           const uint32_t* __restrict__ n_dev, const float* __restrict__ F, int H, int W, int C,
+           double* __restrict__ feat, double* __restrict__ ext) {
   const int lane = threadIdx.x & 63;
-  if (m >= n) return;
+  const uint32_t lim = n_dev ? min(n, *n_dev) : n;
+  const uint32_t waves = (gridDim.x * blockDim.x) >> 6;
+  for (uint32_t m = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; m < lim; m += waves) {
   double P[3], occ;
   const bool in = src_point64(src, nodes[m], P, &occ);
   double u = __dmul_rn(__dmul_rn(__dadd_rn(P[0], 1.0), 0.5), (double)(W - 1));
@@ -88,6 +92,7 @@ k_gather64(PointSrc src, const uint32_t* __restrict__ nodes, uint32_t n,
     e[2] = in ? 0.0 : 1.0;
     e[3] = 0.0;
   }
+  }
 }
 
 // Dense float64 operand copy of the first K columns of a [N][ldw_src] fp32 matrix.
@@ -112,6 +117,7 @@ struct Gemm64Args {
   int n_ext, ext_col;
   double* C;
   int M, N, act;
+  const uint32_t* M_dev;   // device-side row count (nullable): rows = min(M, *M_dev)
 };
 
 // One 16 x 16 output tile per workgroup (v_mfma_f64_16x16x4f64).  The guard band
@@ -125,75 +131,86 @@ struct Gemm64Args {
 __global__ void __launch_bounds__(256) k_gemm64(Gemm64Args a) {
   __shared__ double red[3][4][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int m0 = blockIdx.x * 16, n0 = blockIdx.y * 16;
+  const int n0 = blockIdx.y * 16;
   const int K = a.K1 + a.K2;
+  const int M = a.M_dev ? min(a.M, (int)*a.M_dev) : a.M;
   const int g = lane >> 4, r16 = lane & 15;
-  const int arow = m0 + r16;
-  const bool arow_ok = arow < a.M;
   const double* wrow = a.W + (size_t)(n0 + r16) * K;
   const int nst = K >> 4;
   const int s0 = nst * wave / 4, s1 = nst * (wave + 1) / 4;
-  f64x4 acc = (f64x4){0.0, 0.0, 0.0, 0.0};
-  for (int st = s0; st < s1; ++st) {
-    const int k = st * 16 + 4 * g;
-    double2 a01 = make_double2(0.0, 0.0), a23 = make_double2(0.0, 0.0);
-    if (arow_ok) {
-      const double* ap = k < a.K1 ? a.A1 + (size_t)arow * a.lda1 + k
-                                  : a.A2 + (size_t)arow * a.lda2 + (k - a.K1);
-      a01 = *reinterpret_cast<const double2*>(ap);
-      a23 = *reinterpret_cast<const double2*>(ap + 2);
+  // row tiles in turn (a fixed grid covers any device-side count)
+  for (int m0 = blockIdx.x * 16; m0 < M; m0 += gridDim.x * 16) {
+    const int arow = m0 + r16;
+    const bool arow_ok = arow < M;
+    f64x4 acc = (f64x4){0.0, 0.0, 0.0, 0.0};
+    for (int st = s0; st < s1; ++st) {
+      const int k = st * 16 + 4 * g;
+      double2 a01 = make_double2(0.0, 0.0), a23 = make_double2(0.0, 0.0);
+      if (arow_ok) {
+        const double* ap = k < a.K1 ? a.A1 + (size_t)arow * a.lda1 + k
+                                    : a.A2 + (size_t)arow * a.lda2 + (k - a.K1);
+        a01 = *reinterpret_cast<const double2*>(ap);
+        a23 = *reinterpret_cast<const double2*>(ap + 2);
+      }
+      const double2 b01 = *reinterpret_cast<const double2*>(wrow + k);
+      const double2 b23 = *reinterpret_cast<const double2*>(wrow + k + 2);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a01.x, b01.x, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a01.y, b01.y, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a23.x, b23.x, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a23.y, b23.y, acc, 0, 0, 0);
     }
-    const double2 b01 = *reinterpret_cast<const double2*>(wrow + k);
-    const double2 b23 = *reinterpret_cast<const double2*>(wrow + k + 2);
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a01.x, b01.x, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a01.y, b01.y, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a23.x, b23.x, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a23.y, b23.y, acc, 0, 0, 0);
-  }
-  if (wave) {
+    if (wave) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) red[wave - 1][r][lane] = acc[r];
-  }
-  __syncthreads();
-  if (wave) return;
+      for (int r = 0; r < 4; ++r) red[wave - 1][r][lane] = acc[r];
+    }
+    __syncthreads();
+    if (wave == 0) {
 #pragma unroll
-  for (int r = 0; r < 4; ++r) acc[r] = ((acc[r] + red[0][r][lane]) + red[1][r][lane]) + red[2][r][lane];
-  const int col = n0 + r16;
-  const double bias = a.bias[col];
-  double we0 = 0.0, we1 = 0.0;
-  if (a.n_ext > 0) we0 = a.Wf[(size_t)col * a.ldwf + a.ext_col];
-  if (a.n_ext > 1) we1 = a.Wf[(size_t)col * a.ldwf + a.ext_col + 1];
+      for (int r = 0; r < 4; ++r)
+        acc[r] = ((acc[r] + red[0][r][lane]) + red[1][r][lane]) + red[2][r][lane];
+      const int col = n0 + r16;
+      const double bias = a.bias[col];
+      double we0 = 0.0, we1 = 0.0;
+      if (a.n_ext > 0) we0 = a.Wf[(size_t)col * a.ldwf + a.ext_col];
+      if (a.n_ext > 1) we1 = a.Wf[(size_t)col * a.ldwf + a.ext_col + 1];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int row = m0 + 4 * r + g;
-    if (row >= a.M) continue;
-    double v = acc[r] + bias;
-    if (a.n_ext > 0) v += a.ext[4 * (size_t)row] * we0;
-    if (a.n_ext > 1) v += a.ext[4 * (size_t)row + 1] * we1;
-    if (a.act == PIFU_ACT_RELU) v = v > 0.0 ? v : 0.0;
-    else if (a.act == PIFU_ACT_LRELU) v = v > 0.0 ? v : 0.01 * v;
-    a.C[(size_t)row * a.N + col] = v;
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + 4 * r + g;
+        if (row >= M) continue;
+        double v = acc[r] + bias;
+        if (a.n_ext > 0) v += a.ext[4 * (size_t)row] * we0;
+        if (a.n_ext > 1) v += a.ext[4 * (size_t)row + 1] * we1;
+        if (a.act == PIFU_ACT_RELU) v = v > 0.0 ? v : 0.0;
+        else if (a.act == PIFU_ACT_LRELU) v = v > 0.0 ? v : 0.01 * v;
+        a.C[(size_t)row * a.N + col] = v;
+      }
+    }
+    __syncthreads();   // red is reused by the next row tile
   }
 }
 
 // One wave per point: last layer in float64, then scatter to the guarded positions.
 __global__ void __launch_bounds__(256)
 k_head64(const double* __restrict__ h, int K, const float* __restrict__ W,
-         const float* __restrict__ b, uint32_t n, const double* __restrict__ ext,
-         const uint32_t* __restrict__ glist, float* __restrict__ logit, uint8_t* __restrict__ lab) {
-  const uint32_t m = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+         const float* __restrict__ b, uint32_t n, const uint32_t* __restrict__ n_dev,
+         const double* __restrict__ ext, const uint32_t* __restrict__ glist,
+         float* __restrict__ logit, uint8_t* __restrict__ lab) {
   const int lane = threadIdx.x & 63;
-  if (m >= n) return;
-  double acc = 0.0;
-  for (int k = lane; k < K; k += 64) acc += h[(size_t)m * K + k] * (double)W[k];
+  const uint32_t lim = n_dev ? min(n, *n_dev) : n;
+  const uint32_t waves = (gridDim.x * blockDim.x) >> 6;
+  for (uint32_t m = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; m < lim; m += waves) {
+    double acc = 0.0;
+    for (int k = lane; k < K; k += 64) acc += h[(size_t)m * K + k] * (double)W[k];
 #pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
-  if (lane) return;
-  double v = acc + (double)b[0];
-  if (ext[4 * (size_t)m + 2] != 0.0) v = -INFINITY;
-  const uint32_t pos = glist[m];
-  logit[pos] = (float)v;
-  lab[pos] = v > 0.0;
+    for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
+    if (lane == 0) {
+      double v = acc + (double)b[0];
+      if (ext[4 * (size_t)m + 2] != 0.0) v = -INFINITY;
+      const uint32_t pos = glist[m];
+      logit[pos] = (float)v;
+      lab[pos] = v > 0.0;
+    }
+  }
 }
 
 size_t guard64_ws_bytes(const MLPDesc& d, uint32_t chunk) {
@@ -212,8 +229,10 @@ size_t guard64_ws_bytes(const MLPDesc& d, uint32_t chunk) {
 // float64 and overwrites their logit and label.  ws holds guard64_ws_bytes(d, chunk).
 void run_guard64(const PointSrc& src, const uint32_t* list, const uint32_t* glist, uint32_t gn,
                  const MLPDesc& d, const float* F, int H, int W, int C, float* logit, uint8_t* lab,
-                 void* ws, uint32_t chunk, bool pack, hipStream_t s) {
+                 void* ws, uint32_t chunk, bool pack, hipStream_t s, const uint32_t* gn_dev) {
   if (!gn) return;
+  // with gn_dev, gn is a capacity (<= chunk) and the kernels stop at the device count
+  const uint32_t max_waves = 2048;
   double* base = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(ws) + 255) & ~uintptr_t(255));
   double* Wp[PIFU_MAX_LAYERS];
   int maxw = 1;
@@ -238,9 +257,10 @@ void run_guard64(const PointSrc& src, const uint32_t* list, const uint32_t* glis
   for (uint32_t c0 = 0; c0 < gn; c0 += chunk) {
     const uint32_t m = gn - c0 < chunk ? gn - c0 : chunk;
     hipLaunchKernelGGL(k_guard_nodes, dim3(grid1d(m, 256)), dim3(256), 0, s, list, glist + c0, m,
-                       gnode);
-    hipLaunchKernelGGL(k_gather64, dim3(grid1d((size_t)m * 64, 256)), dim3(256), 0, s, src, gnode,
-                       m, F, H, W, C, feat, ext);
+                       gn_dev, gnode);
+    const uint32_t pw = std::min(m, max_waves);   // point-per-wave kernels: waves in the grid
+    hipLaunchKernelGGL(k_gather64, dim3(grid1d((size_t)pw * 64, 256)), dim3(256), 0, s, src, gnode,
+                       m, gn_dev, F, H, W, C, feat, ext);
     const double* prev = nullptr;
     double* out = hA;
     for (int l = 0; l + 1 < d.n_layers; ++l) {
@@ -270,13 +290,15 @@ void run_guard64(const PointSrc& src, const uint32_t* list, const uint32_t* glis
       g.M = (int)m;
       g.N = d.widths[l];
       g.act = d.hidden_act;
-      hipLaunchKernelGGL(k_gemm64, dim3((m + 15) / 16, d.widths[l] / 16), dim3(256), 0, s, g);
+      g.M_dev = gn_dev;
+      hipLaunchKernelGGL(k_gemm64, dim3(std::min<uint32_t>((m + 15) / 16, 64), d.widths[l] / 16),
+                         dim3(256), 0, s, g);
       prev = out;
       out = out == hA ? hB : hA;
     }
     const int L = d.n_layers - 1;
-    hipLaunchKernelGGL(k_head64, dim3(grid1d((size_t)m * 64, 256)), dim3(256), 0, s, prev,
-                       d.widths[L - 1], d.W[L], d.b[L], m, ext, glist + c0, logit, lab);
+    hipLaunchKernelGGL(k_head64, dim3(grid1d((size_t)pw * 64, 256)), dim3(256), 0, s, prev,
+                       d.widths[L - 1], d.W[L], d.b[L], m, gn_dev, ext, glist + c0, logit, lab);
   }
 }
 
