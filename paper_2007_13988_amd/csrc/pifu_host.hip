@@ -97,11 +97,6 @@ constexpr uint32_t kDefaultChunk = 65536;
 
 // Device-side counters (words of the counters array).
 enum { C_TOTAL = 0, C_CONFLICTS = 1, C_B0 = 2, C_GUARD = 3, C_SHADOW = 4 };
-// Device-side per-level statistics of the single-frame evaluation (band, guard and
-// surrogate-fallback point counts, accumulated without host read-backs) and the
-// per-chunk counts of those subsets.
-enum { C_DS_BAND = 5, C_DS_GUARD = 6, C_DS_SURFB = 7, C_N_BAND = 8, C_N_GUARD = 9, C_N_SUR = 10,
-       C_DS_END = 11 };
 
 struct Carver {
   char* base;
@@ -334,8 +329,7 @@ int pack_field(FieldPrep& fp, pifu_ctx* ctx, hipStream_t s) {
 
 void carve_guard(Carver& cv, const FieldPrep& fp, uint32_t max_points, EvalWs& ew) {
   if (!fp.has_mlp) return;
-  // a chunk's guard points are counted on the device: room for a whole chunk
-  ew.chunk64 = std::max<uint32_t>(64, std::min<uint32_t>(ew.chunk, max_points));
+  ew.chunk64 = std::max<uint32_t>(64, std::min<uint32_t>(16384, max_points));
   ew.g64 = cv.take<char>(guard64_ws_bytes(fp.mlp.d, ew.chunk64));
   const size_t n = std::max<uint32_t>(max_points, 1);
   ew.band_pos = cv.take<uint32_t>(n);
@@ -439,15 +433,6 @@ struct Seg {
 
 // Algorithmic HBM bytes of one GEMM launch: each operand read once, the output written
 // once (A and C in the launch's activation types, W in its operand type).
-// fixed part (weights) and per-row part (activations in and out) of gemm_bytes
-void gemm_bytes_split(const GemmArgs& g, int prec, double* fixed, double* per_row) {
-  const double ea = prec == PIFU_PREC_FP32 ? 4.0 : 2.0;
-  const double ew = prec == PIFU_PREC_FP32 ? 4.0 : prec == PIFU_PREC_BF16 ? 2.0 : 1.0;
-  const double K = (double)g.K1 + g.K2, N = g.N;
-  *fixed = N * K * ew;
-  *per_row = K * ea + N * (g.c_bf16 ? 2.0 : 4.0) + (g.rowadd ? N * 4.0 : 0.0) + (g.n_ext ? 16.0 : 0.0);
-}
-
 double gemm_bytes(const GemmArgs& g, int prec) {
   const double ea = prec == PIFU_PREC_FP32 ? 4.0 : 2.0;
   const double ew = prec == PIFU_PREC_FP32 ? 4.0 : prec == PIFU_PREC_BF16 ? 2.0 : 1.0;
@@ -461,13 +446,9 @@ double gemm_bytes(const GemmArgs& g, int prec) {
 // Runs an MLP over n points (chunked): gather -> hidden GEMMs -> head.  prec selects
 // the MFMA operand type of the hidden layers.  segs (nullable) splits the list into
 // frames that share the network but not the feature map; the GEMMs span all frames.
-// n_dev (nullable): the list holds *n_dev <= n points, counted on the device; n is
-// then a capacity of at most one chunk and every launch stops at the device count.
 int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const PointSrc& src,
             const uint32_t* list, uint32_t n, const EvalWs& ew, float* logit, uint8_t* lab,
-            float* rgb, const Seg* segs = nullptr, int nseg = 0,
-            const uint32_t* n_dev = nullptr) {
-  if (n_dev && n > ew.chunk) return PIFU_ERR_INVALID_ARGUMENT;
+            float* rgb, const Seg* segs = nullptr, int nseg = 0) {
   const pifu_field* f = fp.f;
   const MLPDesc& d = mp.d;
   const int C = f->C;
@@ -488,9 +469,9 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
     // the number of column runs (<= m) stays on the device: the column gather and
     // GEMM cover m rows and skip the rows past the count
     const uint32_t* ncol_dev = e.counters + C_TOTAL;
-    launch_col_flags(lst, m, (uint32_t)src.nz, ew.cflags, e.s, n_dev);
+    launch_col_flags(lst, m, (uint32_t)src.nz, ew.cflags, e.s);
     launch_scan_u32(ew.cflags, m, ew.cexcl, ew.cscan, e.counters + C_TOTAL, e.s);
-    launch_col_ids(lst, ew.cflags, ew.cexcl, m, ew.cid, ew.cnode, e.s, n_dev);
+    launch_col_ids(lst, ew.cflags, ew.cexcl, m, ew.cid, ew.cnode, e.s);
     {
       ProfScope ps(e.ctx, e.s, PIFU_KERN_GATHER, 0.0, 0.0, ncol_dev, 0.0,
                    16.0 * C + (b16 ? 2 : 4) * C + 20.0);
@@ -518,7 +499,7 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
       if (launch_gemm(g, prec, pick_tile(e, prec, g.N, C, m), e.s)) return PIFU_ERR_UNSUPPORTED;
     }
     launch_hoist_layer0(ew.Pcol, mp.NP, ew.cid, lst, m, src.nz, mp.wz, d.widths[0], d.hidden_act,
-                        ew.hA, b16 && d.n_layers > 2, e.s, n_dev);
+                        ew.hA, b16 && d.n_layers > 2, e.s);
     const void* prev = ew.hA;
     void* out = ew.hB;
     for (int l = 1; l + 1 < d.n_layers; ++l) {
@@ -540,39 +521,31 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
       g.C = out;
       g.ldc = g.N = d.widths[l];
       g.M = (int)m;
-      g.M_dev = n_dev;
       g.act = d.hidden_act;
       g.scale = 1.f;
       g.c_bf16 = b16 && (l + 2 < d.n_layers);
       {
-        double bf, br;
-        gemm_bytes_split(g, prec, &bf, &br);
-        const int kind = b16 ? PIFU_KERN_GEMM_BF16 : PIFU_KERN_GEMM_F32;
-        ProfScope ps = n_dev ? ProfScope(e.ctx, e.s, kind, 0.0, bf, n_dev, 2.0 * g.N * g.K1, br)
-                             : ProfScope(e.ctx, e.s, kind, 2.0 * m * g.N * g.K1, bf + br * m);
+        ProfScope ps(e.ctx, e.s, b16 ? PIFU_KERN_GEMM_BF16 : PIFU_KERN_GEMM_F32,
+                     2.0 * m * g.N * g.K1, gemm_bytes(g, prec));
         if (launch_gemm(g, prec, pick_tile(e, prec, g.N, g.K1, m), e.s)) return PIFU_ERR_UNSUPPORTED;
       }
       prev = out;
       out = (out == ew.hA) ? ew.hB : ew.hA;
     }
     const int L = d.n_layers - 1;
-    const double hf = 2.0 * d.widths[L - 1] * d.widths[L];
-    ProfScope ps = n_dev ? ProfScope(e.ctx, e.s, PIFU_KERN_HEAD, 0.0, 0.0, n_dev, hf, 0.0)
-                         : ProfScope(e.ctx, e.s, PIFU_KERN_HEAD, hf * m, 0.0);
+    ProfScope ps(e.ctx, e.s, PIFU_KERN_HEAD, 2.0 * m * d.widths[L - 1] * d.widths[L], 0.0);
     launch_head(reinterpret_cast<const float*>(prev), d.widths[L - 1], d.W[L], d.b[L], d.widths[L],
                 d.out_act, m, nullptr, logit ? logit + c0 : nullptr, lab ? lab + c0 : nullptr, rgb,
-                rgb ? lst : nullptr, e.s, n_dev);
+                rgb ? lst : nullptr, e.s);
   }
   if (hoist) return check_launch();
   for (uint32_t c0 = 0; c0 < n; c0 += ew.chunk) {
     const uint32_t m = std::min(ew.chunk, n - c0);
     const uint32_t* lst = list + c0;
     {
-      const double gb = 16.0 * C + (b16 ? 2 : 4) * C + 20.0;
-      ProfScope ps = n_dev ? ProfScope(e.ctx, e.s, PIFU_KERN_GATHER, 0.0, 0.0, n_dev, 0.0, gb)
-                           : ProfScope(e.ctx, e.s, PIFU_KERN_GATHER, 0.0, (double)m * gb);
+      ProfScope ps(e.ctx, e.s, PIFU_KERN_GATHER, 0.0, (double)m * (16.0 * C + (b16 ? 2 : 4) * C + 20.0));
       if (src.frame_nodes)
-        launch_gather(src, lst, m, segs[0].F, f->H, f->W, C, ew.feat, b16, ew.ext, e.s, n_dev);
+        launch_gather(src, lst, m, segs[0].F, f->H, f->W, C, ew.feat, b16, ew.ext, e.s);
       for (int q = 0; q < nseg && !src.frame_nodes; ++q) {
         const uint32_t lo = std::max(c0, segs[q].begin);
         const uint32_t hi = std::min(c0 + m, segs[q].begin + segs[q].count);
@@ -581,7 +554,7 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
         sq.base_sub = segs[q].base_sub;
         char* fb = reinterpret_cast<char*>(ew.feat) + (size_t)(lo - c0) * C * (b16 ? 2 : 4);
         launch_gather(sq, list + lo, hi - lo, segs[q].F, f->H, f->W, C, fb, b16,
-                      ew.ext + 4 * (size_t)(lo - c0), e.s, n_dev);   // n_dev: one segment at 0
+                      ew.ext + 4 * (size_t)(lo - c0), e.s);
       }
     }
     const void* prev = nullptr;
@@ -617,7 +590,6 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
       g.C = out;
       g.ldc = d.widths[l];
       g.M = (int)m;
-      g.M_dev = n_dev;
       g.N = d.widths[l];
       g.act = d.hidden_act;
       g.scale = prec == PIFU_PREC_FP8 ? mp.a_scale[l] * mp.w_scale[l] : 1.f;
@@ -626,11 +598,7 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
         const int kind = prec == PIFU_PREC_FP32   ? PIFU_KERN_GEMM_F32
                          : prec == PIFU_PREC_BF16 ? PIFU_KERN_GEMM_BF16
                                                   : PIFU_KERN_GEMM_FP8;
-        double bf, br;
-        gemm_bytes_split(g, prec, &bf, &br);
-        const double fr = 2.0 * g.N * (g.K1 + g.K2 + g.n_ext);
-        ProfScope ps = n_dev ? ProfScope(e.ctx, e.s, kind, 0.0, bf, n_dev, fr, br)
-                             : ProfScope(e.ctx, e.s, kind, fr * m, bf + br * m);
+        ProfScope ps(e.ctx, e.s, kind, 2.0 * m * g.N * (g.K1 + g.K2 + g.n_ext), gemm_bytes(g, prec));
         if (launch_gemm(g, prec, pick_tile(e, prec, g.N, g.K1 + g.K2, m), e.s))
           return PIFU_ERR_UNSUPPORTED;
       }
@@ -638,12 +606,10 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
       out = (out == ew.hA) ? ew.hB : ew.hA;
     }
     const int L = d.n_layers - 1;
-    const double hf = 2.0 * d.widths[L - 1] * d.widths[L];
-    ProfScope ps = n_dev ? ProfScope(e.ctx, e.s, PIFU_KERN_HEAD, 0.0, 0.0, n_dev, hf, 0.0)
-                         : ProfScope(e.ctx, e.s, PIFU_KERN_HEAD, hf * m, 0.0);
+    ProfScope ps(e.ctx, e.s, PIFU_KERN_HEAD, 2.0 * m * d.widths[L - 1] * d.widths[L], 0.0);
     launch_head(reinterpret_cast<const float*>(prev), d.widths[L - 1], d.W[L], d.b[L], d.widths[L],
                 d.out_act, m, ew.ext, logit ? logit + c0 : nullptr, lab ? lab + c0 : nullptr, rgb,
-                rgb ? lst : nullptr, e.s, n_dev);
+                rgb ? lst : nullptr, e.s);
   }
   return check_launch();
 }
@@ -719,59 +685,9 @@ int eval_full(EvalCtx& e, const FieldPrep& fp, const PointSrc& src, const uint32
   return post_full(e, fp, src, F, list, n, ew, logit, lab, st);
 }
 
-// Appends the positions m < cap (m < *n_dev when given) with |logit[m]| < bound to pos;
-// the count goes to *count_dev (zeroed first) and is added to *acc.  No host read-back.
-int select_dev(EvalCtx& e, const float* logit, uint32_t cap, const uint32_t* n_dev, float bound,
-               uint32_t* pos, uint32_t* count_dev, uint32_t* acc, const uint32_t* map = nullptr) {
-  HIP_TRY(hipMemsetAsync(count_dev, 0, 4, e.s));
-  launch_guard_select(logit, cap, bound, pos, count_dev, e.s, map, n_dev, acc);
-  return PIFU_OK;
-}
-
-// The FP32 band and the FP64 guard for the first *n_dev (all cap when null) points of
-// one chunk (cap <= chunk), with every subset counted on the device: no host
-// read-back.  ds accumulates the band and guard counts (words C_DS_BAND, C_DS_GUARD).
-int post_full_dev(EvalCtx& e, const FieldPrep& fp, const PointSrc& src, const float* F,
-                  const uint32_t* list, uint32_t cap, const uint32_t* n_dev, const EvalWs& ew,
-                  float* logit, uint8_t* lab) {
-  const pifu_field* f = fp.f;
-  uint32_t* nb = e.counters + C_N_BAND;
-  bool band_run = false;
-  int r = PIFU_OK;
-  if (e.precision != PIFU_PREC_FP32 && e.band > 0.f) {
-    r = select_dev(e, logit, cap, n_dev, e.band, ew.band_pos, nb, e.counters + C_DS_BAND);
-    if (r) return r;
-    launch_gather_u32(list, ew.band_pos, cap, ew.band_nodes, e.s, nb);
-    const Seg bseg{0, cap, F, src.base_sub};
-    r = run_mlp(e, fp, fp.mlp, PIFU_PREC_FP32, src, ew.band_nodes, cap, ew, ew.band_logit,
-                ew.band_lab, nullptr, &bseg, 1, nb);
-    if (r) return r;
-    launch_scatter_results(ew.band_pos, cap, ew.band_logit, ew.band_lab, logit, lab, e.s, nb);
-    band_run = true;
-  }
-  if (e.guard > 0.f) {
-    uint32_t* ng = e.counters + C_N_GUARD;
-    // in BF16/FP8 runs every point with |logit| < guard lies in the band and holds its
-    // FP32 result: the guard picks from the band's results only
-    if (band_run && e.band > e.guard)
-      r = select_dev(e, ew.band_logit, cap, nb, e.guard, ew.glist, ng, e.counters + C_DS_GUARD,
-                     ew.band_pos);
-    else
-      r = select_dev(e, logit, cap, n_dev, e.guard, ew.glist, ng, e.counters + C_DS_GUARD);
-    if (r) return r;
-    run_guard64(src, list, ew.glist, cap, fp.mlp.d, F, f->H, f->W, f->C, logit, lab, ew.g64,
-                ew.chunk64, !e.g64_packed, e.s, ng);
-    e.g64_packed = true;
-  }
-  return check_launch();
-}
-
-// Evaluates the occupancy field at n points; fills logit and label per point.  One
-// chunk at a time: the run-precision pass, then the FP32 band and the FP64 guard on
-// the chunk's subsets, counted on the device.  With use_surrogate, the surrogate
-// network (BF16) runs first and the points whose surrogate occupancy lies within the
-// fallback band of 0.5 go to the full network.  st gets the host-known counts; the
-// device-counted ones accumulate in counters C_DS_* (fold_dev_stats adds them).
+// Evaluates the occupancy field at n points; fills logit and label per point.  With
+// use_surrogate, the surrogate network (BF16) runs first and the points whose
+// surrogate occupancy lies within the fallback band of 0.5 go to the full network.
 int eval_occupancy(EvalCtx& e, const FieldPrep& fp, const PointSrc& src, const uint32_t* list,
                    uint32_t n, const EvalWs& ew, float* logit, uint8_t* lab, pifu_level_stats* st,
                    bool use_surrogate = false) {
@@ -780,46 +696,20 @@ int eval_occupancy(EvalCtx& e, const FieldPrep& fp, const PointSrc& src, const u
     launch_eval_analytic(src, list, n, fp.f->kind, fp.ell, fp.f->plane, logit, lab, e.s);
     return check_launch();
   }
-  const float* F = fp.f->feat;
-  for (uint32_t c0 = 0; c0 < n; c0 += ew.chunk) {
-    const uint32_t m = std::min(ew.chunk, n - c0);
-    const uint32_t* lst = list + c0;
-    float* lg = logit + c0;
-    uint8_t* lb = lab + c0;
-    int r;
-    if (use_surrogate && fp.has_sur) {
-      r = run_mlp(e, fp, fp.sur, PIFU_PREC_BF16, src, lst, m, ew, lg, lb, nullptr);
-      if (r) return r;
-      uint32_t* ns = e.counters + C_N_SUR;
-      r = select_dev(e, lg, m, nullptr, e.sur_band, ew.sur_pos, ns, e.counters + C_DS_SURFB);
-      if (r) return r;
-      launch_gather_u32(lst, ew.sur_pos, m, ew.sur_nodes, e.s, ns);
-      const Seg one{0, m, F, src.base_sub};
-      r = run_mlp(e, fp, fp.mlp, e.precision, src, ew.sur_nodes, m, ew, ew.sur_logit, ew.sur_lab,
-                  nullptr, &one, 1, ns);
-      if (r) return r;
-      r = post_full_dev(e, fp, src, F, ew.sur_nodes, m, ns, ew, ew.sur_logit, ew.sur_lab);
-      if (r) return r;
-      launch_scatter_results(ew.sur_pos, m, ew.sur_logit, ew.sur_lab, lg, lb, e.s, ns);
-    } else {
-      const Seg one{0, m, F, src.base_sub};
-      r = run_mlp(e, fp, fp.mlp, e.precision, src, lst, m, ew, lg, lb, nullptr, &one, 1);
-      if (r) return r;
-      r = post_full_dev(e, fp, src, F, lst, m, nullptr, ew, lg, lb);
-      if (r) return r;
-      if (st) st->mlp_points += m;
-    }
+  if (!(use_surrogate && fp.has_sur)) return eval_full(e, fp, src, list, n, ew, logit, lab, st);
+  int r = run_mlp(e, fp, fp.sur, PIFU_PREC_BF16, src, list, n, ew, logit, lab, nullptr);
+  if (r) return r;
+  uint32_t ns = 0;
+  r = select_near(e, logit, n, e.sur_band, ew.sur_pos, &ns);
+  if (r) return r;
+  if (ns) {
+    launch_gather_u32(list, ew.sur_pos, ns, ew.sur_nodes, e.s);
+    r = eval_full(e, fp, src, ew.sur_nodes, ns, ew, ew.sur_logit, ew.sur_lab, st);
+    if (r) return r;
+    launch_scatter_results(ew.sur_pos, ns, ew.sur_logit, ew.sur_lab, logit, lab, e.s);
   }
+  if (st) st->surrogate_fallback += ns;
   return check_launch();
-}
-
-// Adds the device-counted statistics (read back with the level's counters) to st:
-// surrogate fallbacks are also full-network points.
-void fold_dev_stats(const uint32_t* host_counters, pifu_level_stats* st) {
-  st->band_fp32 += host_counters[C_DS_BAND];
-  st->guard_fp64 += host_counters[C_DS_GUARD];
-  st->surrogate_fallback += host_counters[C_DS_SURFB];
-  st->mlp_points += host_counters[C_DS_SURFB];
 }
 
 // ------------------------------------------------------------------ localization
@@ -920,11 +810,10 @@ int localize(EvalCtx& e, const FieldPrep& fp, const EvalWs& ew, const double* vi
     }
     int r = check_launch();
     if (r) return r;
-    r = read_counters(e, C_DS_END);
+    r = read_counters(e, C_SHADOW + 1);
     if (r) return r;
     st.conflicts = e.ctx->host_counters[C_CONFLICTS];
     st.b0 = e.ctx->host_counters[C_B0];
-    fold_dev_stats(e.ctx->host_counters, &st);
     if (stats) stats[t] = st;
   }
   return PIFU_OK;
@@ -1257,8 +1146,6 @@ int32_t pifu_render_view(pifu_ctx* ctx, const pifu_field* occ_field, const pifu_
     r = compact_count(e, hit, (size_t)W * H, 1, 1, g.w.cscratch, g.hitlist, (uint32_t)(W * H), 0,
                       img, &nh);
     st.hits = nh;
-    if (!r) r = read_counters(e, C_DS_END);   // the stream is idle after compact_count
-    if (!r) fold_dev_stats(ctx->host_counters, &st);
     if (!r && nh) {
       PointSrc ps;
       std::memset(&ps, 0, sizeof(ps));
