@@ -404,8 +404,11 @@ int default_tile(int prec, int N, int K, uint32_t m) {
 
 int pick_tile(const EvalCtx& e, int prec, int N, int K, uint32_t m) {
   if (e.tile_m) return e.tile_m;
-  // a few dozen points: FP32 32-point tiles put twice the workgroups on the chip
-  if (prec == PIFU_PREC_FP32 && m <= 96) return 32;
+  // FP32 launches too small to fill the chip with 64-point tiles take 32 x 64 tiles:
+  // more workgroups, each with half the serial work
+  if (prec == PIFU_PREC_FP32 && N % 64 == 0 &&
+      ((m + 63) / 64) * (uint64_t)(N % 128 == 0 ? N / 128 : N / 64) < 256)
+    return 32;
   auto it = e.ctx->tile_cache.find(tile_key(prec, N, K, m));
   return it == e.ctx->tile_cache.end() ? default_tile(prec, N, K, m) : it->second;
 }
