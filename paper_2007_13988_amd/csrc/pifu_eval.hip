@@ -270,98 +270,6 @@ void launch_guard_select(const float* logit, uint32_t n, float g, uint32_t* glis
                      glist, gcount, n_dev, acc);
 }
 
-constexpr int GUARD_MAXW = 1024;
-constexpr int GUARD_MAXC = 512;
-
-// One workgroup per guarded point: the whole evaluation (gather + every layer) in
-// float64 with wave-wide dot products, so the label is decided in float64.
-__global__ void __launch_bounds__(256)
-k_guard_fp64(PointSrc src, const uint32_t* __restrict__ list, const uint32_t* __restrict__ glist,
-             MLPDesc mlp, const float* __restrict__ F, int H, int W, int C,
-             float* __restrict__ logit, uint8_t* __restrict__ lab) {
-  __shared__ double f[GUARD_MAXC];
-  __shared__ double hbuf[2][GUARD_MAXW + GUARD_MAXC + 4];
-  const uint32_t m = glist[blockIdx.x];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  double P[3];
-  float occ = 0.f;
-  const bool in = src_point(src, list, m, P, &occ);
-  if (!in) {
-    if (tid == 0) {
-      logit[m] = -INFINITY;
-      lab[m] = 0;
-    }
-    return;
-  }
-  int u0, v0;
-  double w[4];
-  bilinear_setup(P[0], P[1], H, W, u0, v0, w);
-  for (int c = tid; c < C; c += 256) {
-    double acc = 0.0;
-    const int tu[4] = {u0, u0 + 1, u0, u0 + 1};
-    const int tv[4] = {v0, v0, v0 + 1, v0 + 1};
-    for (int t = 0; t < 4; ++t) {
-      if (tu[t] < 0 || tu[t] > W - 1 || tv[t] < 0 || tv[t] > H - 1) continue;
-      acc += w[t] * (double)F[((size_t)tv[t] * W + tu[t]) * C + c];
-    }
-    f[c] = acc;
-  }
-  __syncthreads();
-  // layer 0 input: [f; z (; occ)]
-  double* in_buf = hbuf[0];
-  for (int c = tid; c < C; c += 256) in_buf[c] = f[c];
-  if (tid == 0) {
-    in_buf[C] = P[2];
-    if (mlp.n_extra > 1) in_buf[C + 1] = occ;
-  }
-  __syncthreads();
-  int cur = 0;
-  double result = 0.0;
-  for (int l = 0; l < mlp.n_layers; ++l) {
-    const int K = mlp.in_w[l];
-    const int N = mlp.widths[l];
-    double* xin = hbuf[cur];
-    double* xout = hbuf[cur ^ 1];
-    const float* Wl = mlp.W[l];
-    const bool last = l == mlp.n_layers - 1;
-    for (int o = wave; o < N; o += 4) {
-      double acc = 0.0;
-      for (int k = lane; k < K; k += 64) acc += (double)Wl[(size_t)o * K + k] * xin[k];
-#pragma unroll
-      for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
-      acc += (double)mlp.b[l][o];
-      if (!last) {
-        if (mlp.hidden_act == PIFU_ACT_RELU) acc = acc > 0.0 ? acc : 0.0;
-        else acc = acc > 0.0 ? acc : 0.01 * acc;
-      }
-      if (lane == 0) {
-        if (last) {
-          if (o == 0) result = acc;
-        } else {
-          xout[o] = acc;
-        }
-      }
-    }
-    __syncthreads();
-    if (!last && mlp.skip[l + 1]) {
-      for (int c = tid; c < C; c += 256) xout[N + c] = f[c];
-      __syncthreads();
-    }
-    cur ^= 1;
-  }
-  if (tid == 0) {
-    logit[m] = (float)result;
-    lab[m] = result > 0.0;
-  }
-}
-
-void launch_guard_fp64(const PointSrc& src, const uint32_t* list, const uint32_t* glist,
-                       uint32_t gn, const MLPDesc& mlp, const float* F, int H, int W, int C,
-                       float* logit, uint8_t* lab, hipStream_t s) {
-  if (!gn) return;
-  hipLaunchKernelGGL(k_guard_fp64, dim3(gn), dim3(256), 0, s, src, list, glist, mlp, F, H, W, C,
-                     logit, lab);
-}
 
 // ------------------------------------------------------------------ mesh-free rendering
 // Level-L interpolation along a pixel column (u, v) of the target lattice, from the

@@ -123,9 +123,7 @@ void launch_head(const float* h, int K, const float* W, const float* b, int n_ou
 void launch_guard_select(const float* logit, uint32_t n, float g, uint32_t* glist,
                          uint32_t* gcount, hipStream_t s, const uint32_t* map = nullptr,
                          const uint32_t* n_dev = nullptr, uint32_t* acc = nullptr);
-void launch_guard_fp64(const PointSrc& src, const uint32_t* list, const uint32_t* glist,
-                       uint32_t gn, const MLPDesc& mlp, const float* F, int H, int W, int C,
-                       float* logit, uint8_t* lab, hipStream_t s);
+
 // out[i] = src[pos[i]]
 void launch_gather_u32(const uint32_t* src, const uint32_t* pos, uint32_t n, uint32_t* out,
                        hipStream_t s, const uint32_t* n_dev = nullptr);
