@@ -1,0 +1,16 @@
+"""bench.py's command-line contract that holds without a GPU."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    line = r.stdout.strip().splitlines()[-1]
+    msg = json.loads(line)
+    assert "one GPU" in msg["error"]
