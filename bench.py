@@ -8,11 +8,14 @@ of a synthetic performance: a feature sequence whose earlier frames train the su
   * pifu_render_view: 512 x 512 image, 256 depth cells, from a 64 x 64 x 32 coarse
     level, view rotated 90 degrees about y, colour MLP (256+z+occ)->512->256->3 over
     a second 256 ch x 128 x 128 map.
-Two forms are timed on the same frame: the plain FP32 method (FP64 guard band) and
-the surrogate + BF16 form (distilled (256+z)->128->64->1 network on the 32^3..128^3
-levels, full network in BF16 with an FP32 band at |p-0.5| < 0.02 and the FP64 guard).
-`value` is the surrogate + BF16 form when its surface cells agree with the FP32 form
-within 0.1%, else the FP32 form.  Prints one JSON line.
+Forms timed on the same frame (all with the FP64 guard at |logit| < 1e-3):
+  * fp32: the plain method, FP32 MFMA;
+  * fp16: full network in FP16 MFMA, FP32 re-run of the points with |p-0.5| < 0.0075;
+  * surrogate_fp16: distilled (256+z)->128->64->1 network (BF16) on the 32^3..128^3
+    levels, points it leaves undecided and the finer levels as in fp16;
+  * bf16 / surrogate_bf16 (on request): as above with BF16 and a band of 0.02.
+`value` is the fastest form whose surface cells and render hits agree with the FP32
+form within 0.1%, else the FP32 form.  Prints one JSON line.
 """
 import argparse
 import json
@@ -23,7 +26,14 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0, "fp8": 5000.0}
+# run precision and FP32 band of each form; the band is the logit error of the
+# precision over near-surface points with a margin (FP16: 0.0117 max, band 0.030 in
+# logit; BF16: 0.082 max, band 0.080)
+FORMS = {"fp32": ("fp32", 0.0, False), "fp16": ("fp16", 0.0075, False),
+         "bf16": ("bf16", 0.02, False), "surrogate_fp16": ("fp16", 0.0075, True),
+         "surrogate_bf16": ("bf16", 0.02, True)}
+GEMM_DTYPE = {"gemm_f32": "fp32", "gemm_bf16": "bf16", "gemm_f16": "fp16", "gemm_fp8": "fp8"}
 
 
 def parse():
@@ -31,7 +41,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--forms", default="fp32,surrogate_bf16")
+    ap.add_argument("--forms", default="fp32,fp16,surrogate_fp16")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="budget of the oracle timing sample (cpu_baseline)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -169,6 +179,11 @@ def main():
 
     torch.cuda.set_device(0)
     forms = args.forms.split(",")
+    for f in forms:
+        if f not in FORMS:
+            print(json.dumps({"error": f"unknown form {f}; known: {sorted(FORMS)}"}))
+            sys.exit(2)
+    want_sur = any(FORMS[f][2] for f in forms)
     teacher = synth.pifu_mlp()
     feat = synth.pifu_sequence(102, 0)   # frame 0 of a performance
     t_net = P.DeviceMLP(teacher)
@@ -179,7 +194,7 @@ def main():
     setup = {}
 
     sur_net, delta = None, None
-    if "surrogate_bf16" in forms and args.load_surrogate:
+    if want_sur and args.load_surrogate:
         import numpy as np
         z = np.load(args.load_surrogate)
         spec = synth.surrogate_mlp()
@@ -187,7 +202,7 @@ def main():
         spec.b = [z[f"b{l}"] for l in range(len(spec.widths))]
         sur_net, delta = P.DeviceMLP(spec), float(z["delta"][0])
         setup = {"surrogate_loaded_from": args.load_surrogate, "surrogate_delta": delta}
-    elif "surrogate_bf16" in forms:
+    elif want_sur:
         from paper_2007_13988_amd.surrogate import choose_delta, distill
         t0 = time.perf_counter()
         # the surrogate is distilled on the performance's earlier frames (t = -1 .. -n) and
@@ -213,13 +228,13 @@ def main():
             np.savez(args.save_surrogate, **arrs)
 
     def make(form):
-        if form == "fp32":
-            fld = P.DeviceField(P.FIELD_MLP, feat=feat, mlp=t_net)
-            kw = dict(precision="fp32", guard_logit=1e-3)
-        else:
+        prec, band, sur = FORMS[form]
+        kw = dict(precision=prec, guard_logit=1e-3, band_delta=band)
+        if sur:
             fld = P.DeviceField(P.FIELD_MLP, feat=feat, mlp=t_net, surrogate=sur_net)
-            kw = dict(precision="bf16", guard_logit=1e-3, band_delta=0.02, surrogate_max_log2=7,
-                      surrogate_delta=delta)
+            kw.update(surrogate_max_log2=7, surrogate_delta=delta)
+        else:
+            fld = P.DeviceField(P.FIELD_MLP, feat=feat, mlp=t_net)
         gout = P.GridOutputs(fld, P.grid_opts(8, 5, **kw))
         rout = P.RenderOutputs(fld, col_field, P.render_opts(9, 8, 6, **kw))
         return fld, gout, rout
@@ -264,23 +279,26 @@ def main():
     base = results.get("fp32")
     chosen = "fp32" if base is not None else forms[0]
     extra = {}
-    if "surrogate_bf16" in results and base is not None:
-        s = results["surrogate_bf16"]
-        dis = cell_disagreement(s["cells"], base["cells"])
-        hit_dis = float((s["hit"] != base["hit"]).float().mean().item())
-        extra["surrogate_bf16"] = {
-            "ms_per_frame": round(s["ms"], 3), "ms_occupancy_grid": round(s["ms_occ"], 3),
-            "speedup_vs_fp32": round(base["ms"] / s["ms"], 3),
+    for form, r in results.items():
+        if form == "fp32" or base is None:
+            continue
+        dis = cell_disagreement(r["cells"], base["cells"])
+        hit_dis = float((r["hit"] != base["hit"]).float().mean().item())
+        extra[form] = {
+            "ms_per_frame": round(r["ms"], 3), "ms_occupancy_grid": round(r["ms_occ"], 3),
+            "speedup_vs_fp32": round(base["ms"] / r["ms"], 3),
             "surface_cell_disagreement_vs_fp32": dis, "render_hit_disagreement": hit_dis,
-            "surrogate_fallback_points": sum(x["surrogate_fallback"] for x in s["gst"] + s["rst"]),
-            "full_mlp_points": sum(x["mlp_points"] for x in s["gst"] + s["rst"]),
-            "band_fp32_points": sum(x["band_fp32"] for x in s["gst"] + s["rst"]),
-            "guard_fp64_points": sum(x["guard_fp64"] for x in s["gst"] + s["rst"])}
-        if dis <= 1e-3:
-            chosen = "surrogate_bf16"
+            "surrogate_fallback_points": sum(x["surrogate_fallback"] for x in r["gst"] + r["rst"]),
+            "full_mlp_points": sum(x["mlp_points"] for x in r["gst"] + r["rst"]),
+            "band_fp32_points": sum(x["band_fp32"] for x in r["gst"] + r["rst"]),
+            "guard_fp64_points": sum(x["guard_fp64"] for x in r["gst"] + r["rst"])}
+        if dis <= 1e-3 and hit_dis <= 1e-3 and r["ms"] < results[chosen]["ms"]:
+            chosen = form
     main_r = results[chosen]
-    gemm_key = "gemm_bf16" if chosen == "surrogate_bf16" else "gemm_f32"
-    dtype = "bf16" if chosen == "surrogate_bf16" else "fp32"
+    dtype = FORMS[chosen][0]
+    # the dominant kernel: the GEMM family with the most time in the chosen form
+    gemms = {k: v for k, v in main_r["prof"].items() if k in GEMM_DTYPE and v["launches"]}
+    gemm_key = max(gemms, key=lambda k: gemms[k]["total_ms"]) if gemms else "gemm_f32"
 
     def roofline(r, key, peak_key):
         g = r["prof"][key]
@@ -294,7 +312,9 @@ def main():
                 "frac": round(ach / PEAK_TFLOPS[peak_key], 4), "traffic": recorded_traffic(key),
                 "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "launches_per_step": g["launches"] / args.steps, "avg_launch_ms": round(avg_ms, 4),
-                "flops_per_launch": fpl, "algorithmic_bytes_per_launch": g["bytes"] / g["launches"]}
+                "flops_per_launch": fpl, "algorithmic_bytes_per_launch": g["bytes"] / g["launches"],
+                "share_of_gemm_time": round(g["total_ms"] / sum(v["total_ms"] for v in gemms.values()), 3)
+                if key in gemms else None}
 
     occ_pts = sum(s["mlp_points"] for s in main_r["gst"])
     ren_pts = sum(s["mlp_points"] for s in main_r["rst"])
@@ -313,7 +333,7 @@ def main():
         "mlp_points_per_frame": {"occupancy_grid": occ_pts, "render": ren_pts,
                                  "color_hits": main_r["rst"][-1]["hits"]},
         "acceleration_vs_dense": round(257 ** 3 / max(occ_pts, 1), 2),
-        "roofline": roofline(main_r, gemm_key, dtype),
+        "roofline": roofline(main_r, gemm_key, GEMM_DTYPE[gemm_key]),
     }
     if base is not None:
         out["fp32_ms_per_frame"] = round(base["ms"], 3)

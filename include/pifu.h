@@ -54,6 +54,8 @@ extern "C" {
 #define PIFU_PREC_FP32 0          /* MFMA f32 inputs, f32 accumulation */
 #define PIFU_PREC_BF16 1          /* MFMA bf16 inputs, f32 accumulation */
 #define PIFU_PREC_FP8 2           /* MFMA OCP e4m3 inputs with per-layer scales, f32 accumulation */
+#define PIFU_PREC_FP16 3          /* MFMA IEEE binary16 inputs, f32 accumulation; a value outside
+                                     the binary16 range sends the call's evaluations to FP32 */
 
 #define PIFU_MAX_LAYERS 8
 #define PIFU_MAX_ELLIPSOIDS 32
@@ -133,8 +135,11 @@ typedef struct pifu_level_stats {
  *   2^log2_final cells per axis and the coarsest (densely evaluated) level
  *   2^log2_coarse.  dense != 0 evaluates every final node instead (the
  *   brute-force baseline) and ignores log2_coarse.
- *   precision: PIFU_PREC_*.  band_delta: for BF16/FP8, points with
- *   |p - 0.5| < band_delta are re-run in FP32.  guard_logit: points whose FP32
+ *   precision: PIFU_PREC_*.  band_delta: for BF16/FP16/FP8, points with
+ *   |p - 0.5| < band_delta are re-run in FP32.  FP16 runs check every converted
+ *   operand (feature, weight, hidden activation) against the binary16 range; once
+ *   one falls outside it, every evaluation of the call from then on (including the
+ *   one that overflowed) is re-run in FP32 and counted in band_fp32.  guard_logit: points whose FP32
  *   logit has |logit| < guard_logit are re-run in FP64 so that labels are decided
  *   exactly (0 disables).  surrogate_max_log2: levels with at most this log2
  *   size use field->surrogate when present (points with |p_s - 0.5| <
@@ -332,6 +337,8 @@ int32_t pifu_autotune_clear(pifu_ctx* ctx);
 /*
  * The library's operand conversions applied to n float32 values (device in/out):
  * PIFU_PREC_BF16 -> uint16 bfloat16 bits (round to nearest even);
+ * PIFU_PREC_FP16 -> uint16 IEEE binary16 bits (round to nearest even, overflow to
+ * infinity);
  * PIFU_PREC_FP8 -> uint8 OCP e4m3fn codes (nearest even, saturating at +-448, no
  * scaling).  The MLP kernels use exactly these conversions.  Blocks until done.
  */
@@ -346,6 +353,7 @@ int32_t pifu_convert_f32(pifu_ctx* ctx, const float* in, uint32_t n, int32_t pre
 #define PIFU_KERN_GEMM_FP8 2      /* MLP hidden layer, FP8 MFMA */
 #define PIFU_KERN_GATHER 3        /* point projection + bilinear feature gather */
 #define PIFU_KERN_HEAD 4          /* last MLP layer + output rule */
+#define PIFU_KERN_GEMM_F16 5      /* MLP hidden layer, FP16 MFMA */
 #define PIFU_KERN_COUNT 8
 
 /* Accumulated over the launches of one kernel family since the last enable. flops

@@ -111,12 +111,13 @@ void launch_eval_analytic(const PointSrc& src, const uint32_t* list, uint32_t n,
 
 // ------------------------------------------------------------------ bilinear gather
 // A group of C/4 lanes handles one point; each lane blends 4 channels of the four
-// texels (float4 loads from the HWC map) and writes them to row m of feat.
-template <bool BF16>
+// texels (float4 loads from the HWC map) and writes them to row m of feat in format
+// FMT (FMT_F16: a value outside the binary16 range sets *ovf).
+template <int FMT>
 __global__ void __launch_bounds__(256)
 k_gather(PointSrc src, const uint32_t* __restrict__ list, uint32_t n,
          const uint32_t* __restrict__ n_dev, const float* __restrict__ F, int H, int W, int C,
-         void* __restrict__ feat, float* __restrict__ ext) {
+         void* __restrict__ feat, float* __restrict__ ext, uint32_t* __restrict__ ovf) {
   const int lanes = C >> 2;
   const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int per = lanes < 64 ? lanes : 64;   // lanes per point group (<= one wave)
@@ -145,11 +146,18 @@ k_gather(PointSrc src, const uint32_t* __restrict__ list, uint32_t n,
       acc.z = fmaf(wf[t], q.z, acc.z);
       acc.w = fmaf(wf[t], q.w, acc.w);
     }
-    if (BF16) {
+    if (FMT == FMT_BF16) {
       uint2 o;
       o.x = (uint32_t)f32_to_bf16_bits(acc.x) | ((uint32_t)f32_to_bf16_bits(acc.y) << 16);
       o.y = (uint32_t)f32_to_bf16_bits(acc.z) | ((uint32_t)f32_to_bf16_bits(acc.w) << 16);
       *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(feat) + (size_t)m * C + 4 * c4) = o;
+    } else if (FMT == FMT_F16) {
+      uint2 o;
+      o.x = (uint32_t)f32_to_f16_bits(acc.x) | ((uint32_t)f32_to_f16_bits(acc.y) << 16);
+      o.y = (uint32_t)f32_to_f16_bits(acc.z) | ((uint32_t)f32_to_f16_bits(acc.w) << 16);
+      *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(feat) + (size_t)m * C + 4 * c4) = o;
+      const float big = fmaxf(fmaxf(fabsf(acc.x), fabsf(acc.y)), fmaxf(fabsf(acc.z), fabsf(acc.w)));
+      if (!(big <= kF16Max) && ovf) atomicOr(ovf, 1u);
     } else {
       *reinterpret_cast<float4*>(reinterpret_cast<float*>(feat) + (size_t)m * C + 4 * c4) = acc;
     }
@@ -160,18 +168,21 @@ k_gather(PointSrc src, const uint32_t* __restrict__ list, uint32_t n,
 }
 
 void launch_gather(const PointSrc& src, const uint32_t* list, uint32_t n, const float* F, int H,
-                   int W, int C, void* feat, int feat_bf16, float* ext, hipStream_t s,
-                   const uint32_t* n_dev) {
+                   int W, int C, void* feat, int feat_fmt, float* ext, hipStream_t s,
+                   const uint32_t* n_dev, uint32_t* ovf) {
   if (!n) return;
   const int lanes = C >> 2;
   const int per = lanes < 64 ? lanes : 64;
   size_t threads = (size_t)n * per;
-  if (feat_bf16)
-    hipLaunchKernelGGL(k_gather<true>, dim3(grid1d(threads, 256)), dim3(256), 0, s, src, list, n,
-                       n_dev, F, H, W, C, feat, ext);
+  if (feat_fmt == FMT_BF16)
+    hipLaunchKernelGGL(k_gather<FMT_BF16>, dim3(grid1d(threads, 256)), dim3(256), 0, s, src, list,
+                       n, n_dev, F, H, W, C, feat, ext, ovf);
+  else if (feat_fmt == FMT_F16)
+    hipLaunchKernelGGL(k_gather<FMT_F16>, dim3(grid1d(threads, 256)), dim3(256), 0, s, src, list,
+                       n, n_dev, F, H, W, C, feat, ext, ovf);
   else
-    hipLaunchKernelGGL(k_gather<false>, dim3(grid1d(threads, 256)), dim3(256), 0, s, src, list, n,
-                       n_dev, F, H, W, C, feat, ext);
+    hipLaunchKernelGGL(k_gather<FMT_F32>, dim3(grid1d(threads, 256)), dim3(256), 0, s, src, list,
+                       n, n_dev, F, H, W, C, feat, ext, ovf);
 }
 
 // ------------------------------------------------------------------ output head
@@ -585,7 +596,8 @@ void launch_col_ids(const uint32_t* list, const uint32_t* flags, const uint32_t*
 __global__ void k_hoist_layer0(const float* __restrict__ P, int ldp, const uint32_t* __restrict__ cid,
                                const uint32_t* __restrict__ list, uint32_t n, int nz,
                                const float* __restrict__ wz, int N, int act,
-                               void* __restrict__ h, int h_bf16, const uint32_t* __restrict__ n_dev) {
+                               void* __restrict__ h, int h_fmt, const uint32_t* __restrict__ n_dev,
+                               uint32_t* __restrict__ ovf) {
   // four consecutive outputs per thread (N % 4 == 0, ldp % 4 == 0; n * N / 4 < 2^32)
   const uint32_t n4 = (uint32_t)N >> 2;
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -604,23 +616,30 @@ __global__ void k_hoist_layer0(const float* __restrict__ P, int ldp, const uint3
     else if (act == PIFU_ACT_LRELU) v[q] = v[q] > 0.f ? v[q] : 0.01f * v[q];
   }
   const size_t at = (size_t)i * N + o;
-  if (h_bf16) {
+  if (h_fmt == FMT_BF16) {
     uint2 u;
     u.x = (uint32_t)f32_to_bf16_bits(v[0]) | ((uint32_t)f32_to_bf16_bits(v[1]) << 16);
     u.y = (uint32_t)f32_to_bf16_bits(v[2]) | ((uint32_t)f32_to_bf16_bits(v[3]) << 16);
     *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(h) + at) = u;
+  } else if (h_fmt == FMT_F16) {
+    uint2 u;
+    u.x = (uint32_t)f32_to_f16_bits(v[0]) | ((uint32_t)f32_to_f16_bits(v[1]) << 16);
+    u.y = (uint32_t)f32_to_f16_bits(v[2]) | ((uint32_t)f32_to_f16_bits(v[3]) << 16);
+    *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(h) + at) = u;
+    const float big = fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3])));
+    if (!(big <= kF16Max) && ovf) atomicOr(ovf, 1u);
   } else {
     *reinterpret_cast<float4*>(reinterpret_cast<float*>(h) + at) = make_float4(v[0], v[1], v[2], v[3]);
   }
 }
 
 void launch_hoist_layer0(const float* P, int ldp, const uint32_t* cid, const uint32_t* list,
-                         uint32_t n, int nz, const float* wz, int N, int act, void* h, int h_bf16,
-                         hipStream_t s, const uint32_t* n_dev) {
+                         uint32_t n, int nz, const float* wz, int N, int act, void* h, int h_fmt,
+                         hipStream_t s, const uint32_t* n_dev, uint32_t* ovf) {
   const size_t tot = (size_t)n * (N >> 2);
   if (tot)
     hipLaunchKernelGGL(k_hoist_layer0, dim3(grid1d(tot, 256)), dim3(256), 0, s, P, ldp, cid, list,
-                       n, nz, wz, N, act, h, h_bf16, n_dev);
+                       n, nz, wz, N, act, h, h_fmt, n_dev, ovf);
 }
 
 // The library's number-format conversions applied to an array (for checking them).
@@ -628,6 +647,7 @@ __global__ void k_convert(const float* __restrict__ in, uint32_t n, int fmt, voi
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   if (fmt == PIFU_PREC_BF16) reinterpret_cast<uint16_t*>(out)[i] = f32_to_bf16_bits(in[i]);
+  else if (fmt == PIFU_PREC_FP16) reinterpret_cast<uint16_t*>(out)[i] = f32_to_f16_bits(in[i]);
   else reinterpret_cast<uint8_t*>(out)[i] = f32_to_e4m3(in[i]);
 }
 

@@ -16,6 +16,7 @@ namespace pifu {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 // Native vectors for the global->LDS staging registers (HIP's float4/uint4 structs are
 // copied as memcpy, which keeps the staging array in scratch memory).
@@ -28,9 +29,10 @@ __device__ inline float act_apply(float v, int act) {
   return v;
 }
 
-// Epilogue: 32x32 accumulator block -> C.  Output layout of a 32x32 MFMA block:
-// lane l, register r holds row 8*(r/4) + 4*(l/32) + (r%4), column l%32.
-template <bool OUT_BF16>
+// Epilogue: 32x32 accumulator block -> C in format OUT (FMT_*).  Output layout of a
+// 32x32 MFMA block: lane l, register r holds row 8*(r/4) + 4*(l/32) + (r%4), column l%32.
+// FMT_F16: a value outside the binary16 range sets *a.ovf.
+template <int OUT>
 __device__ inline void store_block(const GemmArgs& a, const f32x16& acc, int row0, int col0,
                                    int lane, int M) {
   const int col = col0 + (lane & 31);
@@ -60,16 +62,22 @@ __device__ inline void store_block(const GemmArgs& a, const f32x16& acc, int row
       if (a.n_ext > 1) v[r] = fmaf(ex[1], we1, v[r]);
     }
   }
+  bool big = false;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int row = row0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
     if (row >= M) continue;
     const float x = act_apply(v[r], a.act);
-    if (OUT_BF16)
+    if (OUT == FMT_BF16) {
       reinterpret_cast<uint16_t*>(a.C)[(size_t)row * a.ldc + col] = f32_to_bf16_bits(x);
-    else
+    } else if (OUT == FMT_F16) {
+      big |= !(__builtin_fabsf(x) <= kF16Max);
+      reinterpret_cast<uint16_t*>(a.C)[(size_t)row * a.ldc + col] = f32_to_f16_bits(x);
+    } else {
       reinterpret_cast<float*>(a.C)[(size_t)row * a.ldc + col] = x;
+    }
   }
+  if (OUT == FMT_F16 && big && a.ovf) atomicOr(a.ovf, 1u);
 }
 
 // ------------------------------------------------------------------ FP32 operands
@@ -192,14 +200,15 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_f32(GemmArgs a) {
   for (int i = 0; i < TI; ++i)
 #pragma unroll
     for (int j = 0; j < TJ; ++j)
-      store_block<false>(a, acc[i][j], m0 + wrow + 32 * i, n0 + wcol + 32 * j, lane, M);
+      store_block<FMT_F32>(a, acc[i][j], m0 + wrow + 32 * i, n0 + wcol + 32 * j, lane, M);
 }
 
-// ------------------------------------------------------------------ BF16 operands
-// v_mfma_f32_32x32x16_bf16: 8 bf16 per lane per MFMA (one 16-byte LDS read);
-// BK = 64 bf16 per stage.
-template <int BM, int BN, int WM, int WN, int MINB, bool OUT_BF16, int NT = 256>
-__global__ void __launch_bounds__(NT, MINB) k_gemm_bf16(GemmArgs a) {
+// ------------------------------------------------------------------ 16-bit operands
+// v_mfma_f32_32x32x16_bf16 (F16 = false) or v_mfma_f32_32x32x16_f16 (F16 = true): 8
+// 16-bit values per lane per MFMA (one 16-byte LDS read); BK = 64 per stage.  A, W and
+// (OUT16) C hold the same 16-bit format.
+template <int BM, int BN, int WM, int WN, int MINB, bool OUT16, bool F16, int NT = 256>
+__global__ void __launch_bounds__(NT, MINB) k_gemm_h16(GemmArgs a) {
   // NT = 64 * WM * WN threads; the 256 x 256 tile uses 512 threads (8 waves of 128 x 64)
   constexpr int BK = 64;
   constexpr int LD = BK + 8;   // in bf16 elements
@@ -293,7 +302,12 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_bf16(GemmArgs a) {
     for (int i = 0; i < TI; ++i)
 #pragma unroll
       for (int j = 0; j < TJ; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[q][i], bv[q][j], acc[i][j], 0, 0, 0);
+        if constexpr (F16)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, av[q][i]),
+                                                              __builtin_bit_cast(f16x8, bv[q][j]),
+                                                              acc[i][j], 0, 0, 0);
+        else
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[q][i], bv[q][j], acc[i][j], 0, 0, 0);
   };
 
   gload_a(0);
@@ -326,29 +340,35 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_bf16(GemmArgs a) {
   for (int i = 0; i < TI; ++i)
 #pragma unroll
     for (int j = 0; j < TJ; ++j)
-      store_block<OUT_BF16>(a, acc[i][j], m0 + wrow + 32 * i, n0 + wcol + 32 * j, lane, M);
+      store_block<OUT16 ? (F16 ? FMT_F16 : FMT_BF16) : FMT_F32>(a, acc[i][j], m0 + wrow + 32 * i,
+                                                                n0 + wcol + 32 * j, lane, M);
 }
 
 // Copies the first K columns of a row-major [N][ldw_src] fp32 weight matrix into a
-// dense [N][K] operand matrix of the requested precision (fp32 or bf16).
+// dense [N][K] operand matrix of format fmt (FMT_*); FMT_F16 flags values outside the
+// binary16 range in *ovf.
 __global__ void k_pack_weights(const float* __restrict__ W, int N, int ldw_src, int K,
-                               void* __restrict__ dst, int bf16) {
+                               void* __restrict__ dst, int fmt, uint32_t* __restrict__ ovf) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (size_t)N * K) return;
   const int n = (int)(i / K), k = (int)(i - (size_t)n * K);
   const float v = W[(size_t)n * ldw_src + k];
-  if (bf16)
+  if (fmt == FMT_BF16) {
     reinterpret_cast<uint16_t*>(dst)[i] = f32_to_bf16_bits(v);
-  else
+  } else if (fmt == FMT_F16) {
+    reinterpret_cast<uint16_t*>(dst)[i] = f32_to_f16_bits(v);
+    if (!(__builtin_fabsf(v) <= kF16Max) && ovf) atomicOr(ovf, 1u);
+  } else {
     reinterpret_cast<float*>(dst)[i] = v;
+  }
 }
 
-void launch_pack_weights(const float* W, int N, int ldw_src, int K, void* dst, int bf16,
-                         hipStream_t s) {
+void launch_pack_weights(const float* W, int N, int ldw_src, int K, void* dst, int fmt,
+                         hipStream_t s, uint32_t* ovf) {
   size_t n = (size_t)N * K;
   if (n)
     hipLaunchKernelGGL(k_pack_weights, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, W, N,
-                       ldw_src, K, dst, bf16);
+                       ldw_src, K, dst, fmt, ovf);
 }
 
 // ------------------------------------------------------------------ FP8 (OCP e4m3) operands
@@ -486,7 +506,8 @@ __global__ void __launch_bounds__(256, MINB) k_gemm_fp8(GemmArgs a) {
   for (int i = 0; i < TI; ++i)
 #pragma unroll
     for (int j = 0; j < TJ; ++j)
-      store_block<OUT_BF16>(a, acc[i][j], m0 + wrow + 32 * i, n0 + wcol + 32 * j, lane, M);
+      store_block<OUT_BF16 ? FMT_BF16 : FMT_F32>(a, acc[i][j], m0 + wrow + 32 * i, n0 + wcol + 32 * j,
+                                                 lane, M);
 }
 
 // Per-layer weight quantization: dst = e4m3(W / s_w) for the first K columns, where
@@ -530,15 +551,38 @@ void launch_pack_fp8(const float* W, int N, int ldw, int K, uint32_t* amax_bits,
 #define PIFU_F32(BM_, BN_, WM_, WN_, MB_) \
   hipLaunchKernelGGL((k_gemm_f32<BM_, BN_, WM_, WN_, MB_>), dim3((a.M + BM_ - 1) / BM_, a.N / BN_), \
                      dim3(256), 0, s, a)
-#define PIFU_B16(BM_, BN_, WM_, WN_, MB_)                                                        \
+#define PIFU_H16(BM_, BN_, WM_, WN_, MB_, F16_)                                                  \
   do {                                                                                           \
     if (a.c_bf16)                                                                                \
-      hipLaunchKernelGGL((k_gemm_bf16<BM_, BN_, WM_, WN_, MB_, true>),                           \
+      hipLaunchKernelGGL((k_gemm_h16<BM_, BN_, WM_, WN_, MB_, true, F16_>),                      \
                          dim3((a.M + BM_ - 1) / BM_, a.N / BN_), dim3(256), 0, s, a);             \
     else                                                                                         \
-      hipLaunchKernelGGL((k_gemm_bf16<BM_, BN_, WM_, WN_, MB_, false>),                          \
+      hipLaunchKernelGGL((k_gemm_h16<BM_, BN_, WM_, WN_, MB_, false, F16_>),                     \
                          dim3((a.M + BM_ - 1) / BM_, a.N / BN_), dim3(256), 0, s, a);             \
   } while (0)
+
+template <bool F16>
+void launch_h16(const GemmArgs& a, int bm, hipStream_t s) {
+  const bool bn128 = (a.N % 128) == 0;
+  if (bn128) {
+    if (bm == 64) PIFU_H16(64, 128, 1, 4, 2, F16);
+    else if (bm == 128) PIFU_H16(128, 128, 2, 2, 2, F16);
+    else if (a.N % 256 == 0) {
+      // 256 x 256 tile, 8 waves: half the L2 traffic per FLOP of the 128-wide tiles
+      if (a.c_bf16)
+        hipLaunchKernelGGL((k_gemm_h16<256, 256, 2, 4, 1, true, F16, 512>),
+                           dim3((a.M + 255) / 256, a.N / 256), dim3(512), 0, s, a);
+      else
+        hipLaunchKernelGGL((k_gemm_h16<256, 256, 2, 4, 1, false, F16, 512>),
+                           dim3((a.M + 255) / 256, a.N / 256), dim3(512), 0, s, a);
+    } else PIFU_H16(256, 128, 2, 2, 1, F16);
+  } else {
+    if (bm == 64) PIFU_H16(64, 64, 2, 2, 2, F16);
+    else if (bm == 128) PIFU_H16(128, 64, 4, 1, 2, F16);
+    else PIFU_H16(256, 64, 4, 1, 1, F16);
+  }
+}
+#undef PIFU_H16
 
 int launch_gemm(const GemmArgs& a, int precision, int tile_m, hipStream_t s) {
   if (a.M <= 0) return 0;
@@ -565,25 +609,10 @@ int launch_gemm(const GemmArgs& a, int precision, int tile_m, hipStream_t s) {
     return 0;
   }
   if (bm == 32) bm = 64;   // the 32-point tile exists for FP32 only
-  if (precision == PIFU_PREC_BF16) {
+  if (precision == PIFU_PREC_BF16 || precision == PIFU_PREC_FP16) {
     if ((a.K1 % 64) || (a.K2 % 64)) return -1;
-    if (bn128) {
-      if (bm == 64) PIFU_B16(64, 128, 1, 4, 2);
-      else if (bm == 128) PIFU_B16(128, 128, 2, 2, 2);
-      else if (a.N % 256 == 0) {
-        // 256 x 256 tile, 8 waves: half the L2 traffic per FLOP of the 128-wide tiles
-        if (a.c_bf16)
-          hipLaunchKernelGGL((k_gemm_bf16<256, 256, 2, 4, 1, true, 512>),
-                             dim3((a.M + 255) / 256, a.N / 256), dim3(512), 0, s, a);
-        else
-          hipLaunchKernelGGL((k_gemm_bf16<256, 256, 2, 4, 1, false, 512>),
-                             dim3((a.M + 255) / 256, a.N / 256), dim3(512), 0, s, a);
-      } else PIFU_B16(256, 128, 2, 2, 1);
-    } else {
-      if (bm == 64) PIFU_B16(64, 64, 2, 2, 2);
-      else if (bm == 128) PIFU_B16(128, 64, 4, 1, 2);
-      else PIFU_B16(256, 64, 4, 1, 1);
-    }
+    if (precision == PIFU_PREC_FP16) launch_h16<true>(a, bm, s);
+    else launch_h16<false>(a, bm, s);
     return 0;
   }
   if (precision == PIFU_PREC_FP8) {

@@ -96,7 +96,10 @@ constexpr int kHostWords = 256;   // pinned read-back buffer (>= every device co
 constexpr uint32_t kDefaultChunk = 65536;
 
 // Device-side counters (words of the counters array).
-enum { C_TOTAL = 0, C_CONFLICTS = 1, C_B0 = 2, C_GUARD = 3, C_SHADOW = 4 };
+// C_OVF: FP16 runs set it when a value leaves the binary16 range.  It is cleared once
+// per call (before the weights are packed) and kept by the per-level counter clears,
+// so that an overflow sends every later evaluation of the call to FP32 as well.
+enum { C_TOTAL = 0, C_CONFLICTS = 1, C_B0 = 2, C_GUARD = 3, C_SHADOW = 4, C_OVF = 15 };
 
 struct Carver {
   char* base;
@@ -165,7 +168,8 @@ int validate_field(const pifu_field* f, int n_extra, int n_out) {
 }
 
 int validate_precision(int p) {
-  if (p == PIFU_PREC_FP32 || p == PIFU_PREC_BF16 || p == PIFU_PREC_FP8) return PIFU_OK;
+  if (p == PIFU_PREC_FP32 || p == PIFU_PREC_BF16 || p == PIFU_PREC_FP8 || p == PIFU_PREC_FP16)
+    return PIFU_OK;
   return PIFU_ERR_INVALID_ARGUMENT;
 }
 
@@ -173,7 +177,7 @@ int validate_precision(int p) {
 struct MlpPrep {
   MLPDesc d;
   float* Wp32[PIFU_MAX_LAYERS];      // FP32 operand copies [N][Kp]
-  uint16_t* Wp16[PIFU_MAX_LAYERS];   // BF16 operand copies (BF16/FP8 runs)
+  uint16_t* Wp16[PIFU_MAX_LAYERS];   // 16-bit operand copies (BF16 or FP16 runs, that format)
   uint8_t* Wp8[PIFU_MAX_LAYERS];     // FP8 e4m3 operand copies (FP8 runs), scaled by 1/w_scale
   uint32_t* amax;                    // device: per-layer max |W| (float bits), FP8 runs
   float w_scale[PIFU_MAX_LAYERS];    // FP8 weight scale amax/448 (host, after pack)
@@ -185,7 +189,7 @@ struct MlpPrep {
   int NP = 0;                        // total outputs of those layers (0: no hoisting)
   int hoist_off[PIFU_MAX_LAYERS];    // offset of layer l in the stacked outputs, -1 if none
   float* Wf32 = nullptr;             // [NP][C]
-  uint16_t* Wf16 = nullptr;          // [NP][C] (BF16 runs)
+  uint16_t* Wf16 = nullptr;          // [NP][C] (BF16 or FP16 runs)
   float* bf = nullptr;               // [NP] biases of those layers
   float* wz = nullptr;               // [widths[0]] layer 0's weights of z, contiguous
 };
@@ -208,7 +212,7 @@ void describe_mlp(const pifu_mlp* m, MLPDesc& d) {
 }
 
 // Carves the packed operand copies of the hidden layers: one in the run precision
-// and, for BF16/FP8 runs, an FP32 copy for the threshold-band re-evaluation.
+// and, for BF16/FP16/FP8 runs, an FP32 copy for the threshold-band re-evaluation.
 void carve_mlp(Carver& cv, const pifu_mlp* m, int precision, MlpPrep& p) {
   describe_mlp(m, p.d);
   p.max_hidden = 0;
@@ -218,7 +222,8 @@ void carve_mlp(Carver& cv, const pifu_mlp* m, int precision, MlpPrep& p) {
     p.Kp[l] = l == 0 ? m->feat_dim : p.d.in_w[l];
     const size_t n = (size_t)m->widths[l] * p.Kp[l];
     p.Wp32[l] = cv.take<float>(n);
-    p.Wp16[l] = precision == PIFU_PREC_BF16 ? cv.take<uint16_t>(n) : nullptr;
+    p.Wp16[l] = precision == PIFU_PREC_BF16 || precision == PIFU_PREC_FP16 ? cv.take<uint16_t>(n)
+                                                                           : nullptr;
     p.Wp8[l] = precision == PIFU_PREC_FP8 ? cv.take<uint8_t>(n) : nullptr;
     p.max_hidden = std::max(p.max_hidden, m->widths[l]);
     const float amax_a = m->fp8_amax[l] > 0.f ? m->fp8_amax[l] : 16.f;
@@ -236,30 +241,34 @@ void carve_mlp(Carver& cv, const pifu_mlp* m, int precision, MlpPrep& p) {
       }
     const size_t n = (size_t)p.NP * m->feat_dim;
     p.Wf32 = cv.take<float>(n);
-    p.Wf16 = precision == PIFU_PREC_BF16 ? cv.take<uint16_t>(n) : nullptr;
+    p.Wf16 = precision == PIFU_PREC_BF16 || precision == PIFU_PREC_FP16 ? cv.take<uint16_t>(n)
+                                                                        : nullptr;
     p.bf = cv.take<float>(p.NP);
     p.wz = cv.take<float>(m->widths[0]);
   }
 }
 
-int pack_mlp(MlpPrep& p, pifu_ctx* ctx, hipStream_t s) {
+int pack_mlp(MlpPrep& p, pifu_ctx* ctx, hipStream_t s, uint32_t* ovf) {
+  const int f16 = h16_fmt(p.prec);
   for (int l = 0; l + 1 < p.d.n_layers; ++l) {
-    launch_pack_weights(p.d.W[l], p.d.widths[l], p.d.in_w[l], p.Kp[l], p.Wp32[l], 0, s);
+    launch_pack_weights(p.d.W[l], p.d.widths[l], p.d.in_w[l], p.Kp[l], p.Wp32[l], FMT_F32, s);
     if (p.Wp16[l])
-      launch_pack_weights(p.d.W[l], p.d.widths[l], p.d.in_w[l], p.Kp[l], p.Wp16[l], 1, s);
+      launch_pack_weights(p.d.W[l], p.d.widths[l], p.d.in_w[l], p.Kp[l], p.Wp16[l], f16, s, ovf);
     if (p.Wp8[l])
       launch_pack_fp8(p.d.W[l], p.d.widths[l], p.d.in_w[l], p.Kp[l], p.amax + l, p.Wp8[l], s);
     if (p.hoist_off[l] >= 0) {
       const int C = p.d.feat_dim;
       const int fcol = l == 0 ? 0 : p.d.widths[l - 1];   // where f starts in layer l's input
       const size_t off = (size_t)p.hoist_off[l];
-      launch_pack_weights(p.d.W[l] + fcol, p.d.widths[l], p.d.in_w[l], C, p.Wf32 + off * C, 0, s);
+      launch_pack_weights(p.d.W[l] + fcol, p.d.widths[l], p.d.in_w[l], C, p.Wf32 + off * C, FMT_F32,
+                          s);
       if (p.Wf16)
-        launch_pack_weights(p.d.W[l] + fcol, p.d.widths[l], p.d.in_w[l], C, p.Wf16 + off * C, 1, s);
+        launch_pack_weights(p.d.W[l] + fcol, p.d.widths[l], p.d.in_w[l], C, p.Wf16 + off * C, f16, s,
+                            ovf);
       HIP_TRY(hipMemcpyAsync(p.bf + off, p.d.b[l], sizeof(float) * p.d.widths[l],
                              hipMemcpyDeviceToDevice, s));
       if (l == 0)   // the z column of layer 0 (input [f; z])
-        launch_pack_weights(p.d.W[0] + C, p.d.widths[0], p.d.in_w[0], 1, p.wz, 0, s);
+        launch_pack_weights(p.d.W[0] + C, p.d.widths[0], p.d.in_w[0], 1, p.wz, FMT_F32, s);
     }
   }
   if (!p.amax) return check_launch();
@@ -320,10 +329,17 @@ void carve_field(Carver& cv, const pifu_field* f, int precision, FieldPrep& fp) 
   }
 }
 
-int pack_field(FieldPrep& fp, pifu_ctx* ctx, hipStream_t s) {
+// Packs the operand copies of the field's networks.  An FP16 network first clears the
+// call's overflow flag (counters[C_OVF]); its weight copies then report into it.
+int pack_field(FieldPrep& fp, pifu_ctx* ctx, hipStream_t s, uint32_t* counters) {
   int r = PIFU_OK;
-  if (fp.has_mlp) r = pack_mlp(fp.mlp, ctx, s);
-  if (!r && fp.has_sur) r = pack_mlp(fp.sur, ctx, s);
+  uint32_t* ovf = nullptr;
+  if (fp.has_mlp && fp.mlp.prec == PIFU_PREC_FP16) {
+    ovf = counters + C_OVF;
+    HIP_TRY(hipMemsetAsync(ovf, 0, sizeof(uint32_t), s));
+  }
+  if (fp.has_mlp) r = pack_mlp(fp.mlp, ctx, s, ovf);
+  if (!r && fp.has_sur) r = pack_mlp(fp.sur, ctx, s, nullptr);
   return r;
 }
 
@@ -395,8 +411,8 @@ uint64_t tile_key(int prec, int N, int K, uint32_t m) {
 int default_tile(int prec, int N, int K, uint32_t m) {
   auto blocks = [&](int bm, int bn) { return ((m + bm - 1) / bm) * (uint64_t)((N + bn - 1) / bn); };
   const int bn128 = N % 128 == 0 ? 128 : 64;
-  if (prec == PIFU_PREC_BF16 && (K >= 512 || (N % 256 == 0 && N >= 512)) &&
-      blocks(256, N % 256 == 0 ? 256 : bn128) >= 256)
+  const bool h16 = prec == PIFU_PREC_BF16 || prec == PIFU_PREC_FP16;
+  if (h16 && (K >= 512 || (N % 256 == 0 && N >= 512)) && blocks(256, N % 256 == 0 ? 256 : bn128) >= 256)
     return 256;
   if (blocks(128, bn128) >= 256) return 128;
   return 64;
@@ -438,12 +454,28 @@ struct Seg {
 // once (A and C in the launch's activation types, W in its operand type).
 double gemm_bytes(const GemmArgs& g, int prec) {
   const double ea = prec == PIFU_PREC_FP32 ? 4.0 : 2.0;
-  const double ew = prec == PIFU_PREC_FP32 ? 4.0 : prec == PIFU_PREC_BF16 ? 2.0 : 1.0;
+  const double ew = prec == PIFU_PREC_FP32 ? 4.0 : prec == PIFU_PREC_FP8 ? 1.0 : 2.0;
   const double K = (double)g.K1 + g.K2, M = g.M, N = g.N;
   double b = M * K * ea + N * K * ew + M * N * (g.c_bf16 ? 2.0 : 4.0);
   if (g.rowadd) b += M * N * 4.0;
   if (g.n_ext) b += M * 16.0;
   return b;
+}
+
+// Profiler family of a hidden-layer GEMM of the given run precision.
+int gemm_kind(int prec) {
+  return prec == PIFU_PREC_FP32   ? PIFU_KERN_GEMM_F32
+         : prec == PIFU_PREC_BF16 ? PIFU_KERN_GEMM_BF16
+         : prec == PIFU_PREC_FP16 ? PIFU_KERN_GEMM_F16
+                                  : PIFU_KERN_GEMM_FP8;
+}
+
+// Operand copy of hidden layer l for a run precision (16-bit copies hold the format the
+// network was prepared for).
+const void* layer_weights(const MlpPrep& mp, int prec, int l) {
+  return prec == PIFU_PREC_FP8    ? (const void*)mp.Wp8[l]
+         : prec == PIFU_PREC_FP32 ? (const void*)mp.Wp32[l]
+                                  : (const void*)mp.Wp16[l];
 }
 
 // Runs an MLP over n points (chunked): gather -> hidden GEMMs -> head.  prec selects
@@ -456,6 +488,11 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
   const MLPDesc& d = mp.d;
   const int C = f->C;
   const bool b16 = prec != PIFU_PREC_FP32;
+  const int hf = h16_fmt(prec);
+  // a 16-bit run needs the operand copies of its own format
+  if ((prec == PIFU_PREC_BF16 || prec == PIFU_PREC_FP16) && mp.prec != prec)
+    return PIFU_ERR_UNSUPPORTED;
+  uint32_t* ovf = prec == PIFU_PREC_FP16 ? e.counters + C_OVF : nullptr;
   Seg one{0, n, f->feat, src.base_sub};
   if (!segs) {
     segs = &one;
@@ -480,7 +517,8 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
                    16.0 * C + (b16 ? 2 : 4) * C + 20.0);
       PointSrc sq = src;
       if (!src.frame_nodes) sq.base_sub = segs[0].base_sub;   // else the frame table decodes
-      launch_gather(sq, ew.cnode, m, segs[0].F, f->H, f->W, C, ew.feat, b16, ew.ext, e.s, ncol_dev);
+      launch_gather(sq, ew.cnode, m, segs[0].F, f->H, f->W, C, ew.feat, hf, ew.ext, e.s, ncol_dev,
+                    ovf);
     }
     GemmArgs g;
     std::memset(&g, 0, sizeof(g));
@@ -497,19 +535,19 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
     g.scale = 1.f;
     {
       const double ea = b16 ? 2.0 : 4.0;
-      ProfScope ps(e.ctx, e.s, b16 ? PIFU_KERN_GEMM_BF16 : PIFU_KERN_GEMM_F32, 0.0,
+      ProfScope ps(e.ctx, e.s, gemm_kind(prec), 0.0,
                    (double)mp.NP * C * ea, ncol_dev, 2.0 * mp.NP * C, C * ea + mp.NP * 4.0);
       if (launch_gemm(g, prec, pick_tile(e, prec, g.N, C, m), e.s)) return PIFU_ERR_UNSUPPORTED;
     }
     launch_hoist_layer0(ew.Pcol, mp.NP, ew.cid, lst, m, src.nz, mp.wz, d.widths[0], d.hidden_act,
-                        ew.hA, b16 && d.n_layers > 2, e.s);
+                        ew.hA, d.n_layers > 2 ? hf : FMT_F32, e.s, nullptr, ovf);
     const void* prev = ew.hA;
     void* out = ew.hB;
     for (int l = 1; l + 1 < d.n_layers; ++l) {
       std::memset(&g, 0, sizeof(g));
       g.A1 = prev;
       g.K1 = g.lda1 = d.widths[l - 1];
-      g.W = b16 ? (const void*)mp.Wp16[l] : (const void*)mp.Wp32[l];
+      g.W = layer_weights(mp, prec, l);
       g.ldw = mp.Kp[l];
       g.Wf = d.W[l];
       g.ldwf = d.in_w[l];
@@ -527,9 +565,9 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
       g.act = d.hidden_act;
       g.scale = 1.f;
       g.c_bf16 = b16 && (l + 2 < d.n_layers);
+      g.ovf = ovf;
       {
-        ProfScope ps(e.ctx, e.s, b16 ? PIFU_KERN_GEMM_BF16 : PIFU_KERN_GEMM_F32,
-                     2.0 * m * g.N * g.K1, gemm_bytes(g, prec));
+        ProfScope ps(e.ctx, e.s, gemm_kind(prec), 2.0 * m * g.N * g.K1, gemm_bytes(g, prec));
         if (launch_gemm(g, prec, pick_tile(e, prec, g.N, g.K1, m), e.s)) return PIFU_ERR_UNSUPPORTED;
       }
       prev = out;
@@ -548,7 +586,7 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
     {
       ProfScope ps(e.ctx, e.s, PIFU_KERN_GATHER, 0.0, (double)m * (16.0 * C + (b16 ? 2 : 4) * C + 20.0));
       if (src.frame_nodes)
-        launch_gather(src, lst, m, segs[0].F, f->H, f->W, C, ew.feat, b16, ew.ext, e.s);
+        launch_gather(src, lst, m, segs[0].F, f->H, f->W, C, ew.feat, hf, ew.ext, e.s, nullptr, ovf);
       for (int q = 0; q < nseg && !src.frame_nodes; ++q) {
         const uint32_t lo = std::max(c0, segs[q].begin);
         const uint32_t hi = std::min(c0 + m, segs[q].begin + segs[q].count);
@@ -556,8 +594,8 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
         PointSrc sq = src;
         sq.base_sub = segs[q].base_sub;
         char* fb = reinterpret_cast<char*>(ew.feat) + (size_t)(lo - c0) * C * (b16 ? 2 : 4);
-        launch_gather(sq, list + lo, hi - lo, segs[q].F, f->H, f->W, C, fb, b16,
-                      ew.ext + 4 * (size_t)(lo - c0), e.s);
+        launch_gather(sq, list + lo, hi - lo, segs[q].F, f->H, f->W, C, fb, hf,
+                      ew.ext + 4 * (size_t)(lo - c0), e.s, nullptr, ovf);
       }
     }
     const void* prev = nullptr;
@@ -581,9 +619,7 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
           g.lda2 = C;
         }
       }
-      g.W = prec == PIFU_PREC_FP8    ? (const void*)mp.Wp8[l]
-            : prec == PIFU_PREC_BF16 ? (const void*)mp.Wp16[l]
-                                     : (const void*)mp.Wp32[l];
+      g.W = layer_weights(mp, prec, l);
       g.a_inv_scale = prec == PIFU_PREC_FP8 ? 1.f / mp.a_scale[l] : 1.f;
       g.ldw = mp.Kp[l];
       g.Wf = d.W[l];
@@ -597,11 +633,10 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
       g.act = d.hidden_act;
       g.scale = prec == PIFU_PREC_FP8 ? mp.a_scale[l] * mp.w_scale[l] : 1.f;
       g.c_bf16 = b16 && (l + 2 < d.n_layers);   // the head reads FP32
+      g.ovf = ovf;
       {
-        const int kind = prec == PIFU_PREC_FP32   ? PIFU_KERN_GEMM_F32
-                         : prec == PIFU_PREC_BF16 ? PIFU_KERN_GEMM_BF16
-                                                  : PIFU_KERN_GEMM_FP8;
-        ProfScope ps(e.ctx, e.s, kind, 2.0 * m * g.N * (g.K1 + g.K2 + g.n_ext), gemm_bytes(g, prec));
+        ProfScope ps(e.ctx, e.s, gemm_kind(prec), 2.0 * m * g.N * (g.K1 + g.K2 + g.n_ext),
+                     gemm_bytes(g, prec));
         if (launch_gemm(g, prec, pick_tile(e, prec, g.N, g.K1 + g.K2, m), e.s))
           return PIFU_ERR_UNSUPPORTED;
       }
@@ -626,14 +661,15 @@ int select_near(EvalCtx& e, const float* logit, uint32_t n, float bound, uint32_
   launch_guard_select(logit, n, bound, pos, e.counters + C_GUARD, e.s, map);
   int r = check_launch();
   if (r) return r;
-  r = read_counters(e, C_GUARD + 1);
+  r = read_counters(e, C_OVF + 1);   // the overflow flag comes back with the count
   if (r) return r;
   *count = e.ctx->host_counters[C_GUARD];
   return PIFU_OK;
 }
 
-// After the run-precision pass: the FP32 band (BF16/FP8 runs), then the FP64 guard.
-// F is the feature map of the points' frame.
+// After the run-precision pass: the FP32 band (BF16/FP16/FP8 runs), then the FP64 guard.
+// F is the feature map of the points' frame.  An FP16 run whose call has seen a value
+// outside the binary16 range is re-run whole in FP32 instead of the band.
 int post_full(EvalCtx& e, const FieldPrep& fp, const PointSrc& src, const float* F,
               const uint32_t* list, uint32_t n, const EvalWs& ew, float* logit, uint8_t* lab,
               pifu_level_stats* st) {
@@ -641,12 +677,14 @@ int post_full(EvalCtx& e, const FieldPrep& fp, const PointSrc& src, const float*
   int r = PIFU_OK;
   const Seg one{0, n, F, src.base_sub};
   uint32_t nb_run = 0;   // points re-run in FP32 by the band
+  bool over = false;     // FP16 overflow: all n points re-run in FP32
   if (e.precision != PIFU_PREC_FP32 && e.band > 0.f) {
     uint32_t nb = 0;
     r = select_near(e, logit, n, e.band, ew.band_pos, &nb);
     if (r) return r;
-    nb_run = nb;
-    if (nb) {
+    over = e.precision == PIFU_PREC_FP16 && e.ctx->host_counters[C_OVF] != 0;
+    if (nb && !over) {
+      nb_run = nb;
       launch_gather_u32(list, ew.band_pos, nb, ew.band_nodes, e.s);
       const Seg bseg{0, nb, F, src.base_sub};
       r = run_mlp(e, fp, fp.mlp, PIFU_PREC_FP32, src, ew.band_nodes, nb, ew, ew.band_logit,
@@ -655,11 +693,19 @@ int post_full(EvalCtx& e, const FieldPrep& fp, const PointSrc& src, const float*
       launch_scatter_results(ew.band_pos, nb, ew.band_logit, ew.band_lab, logit, lab, e.s);
       if (st) st->band_fp32 += nb;
     }
+  } else if (e.precision == PIFU_PREC_FP16) {
+    r = read_counters(e, C_OVF + 1);
+    if (r) return r;
+    over = e.ctx->host_counters[C_OVF] != 0;
   }
-  (void)one;
+  if (over) {
+    r = run_mlp(e, fp, fp.mlp, PIFU_PREC_FP32, src, list, n, ew, logit, lab, nullptr, &one, 1);
+    if (r) return r;
+    if (st) st->band_fp32 += n;
+  }
   if (e.guard > 0.f) {
     uint32_t gn = 0;
-    if (e.precision != PIFU_PREC_FP32 && e.band > e.guard) {
+    if (e.precision != PIFU_PREC_FP32 && e.band > e.guard && !over) {
       // every point with |logit| < guard lies inside the band and now holds its FP32
       // result: the guard picks from the band's results only
       if (nb_run) r = select_near(e, ew.band_logit, nb_run, e.guard, ew.glist, &gn, ew.band_pos);
@@ -772,7 +818,7 @@ int localize(EvalCtx& e, const FieldPrep& fp, const EvalWs& ew, const double* vi
     src.nz = L.lat.nz;
     const int stride = 1 << (last - t);
     const uint32_t n_nodes = (uint32_t)L.lat.n();
-    HIP_TRY(hipMemsetAsync(e.counters, 0, sizeof(uint32_t) * kCounters, e.s));
+    HIP_TRY(hipMemsetAsync(e.counters, 0, sizeof(uint32_t) * C_OVF, e.s));   // keeps C_OVF
     if (t == 0) {
       // coarsest level: every node is evaluated
       launch_fill_u8(L.st, 0, n_nodes, e.s);
@@ -1035,7 +1081,7 @@ int32_t pifu_occupancy_grid(pifu_ctx* ctx, const pifu_field* field, const pifu_g
   e.band = logit_band(opts->band_delta);
   e.sur_band = logit_band(opts->surrogate_delta);
   e.tile_m = opts->tile_m;
-  if (int pr = pack_field(g.fp, ctx, s)) {
+  if (int pr = pack_field(g.fp, ctx, s, g.counters)) {
     delete gp;
     return pr;
   }
@@ -1092,11 +1138,11 @@ int32_t pifu_render_view(pifu_ctx* ctx, const pifu_field* occ_field, const pifu_
   e.band = logit_band(opts->band_delta);
   e.sur_band = logit_band(opts->surrogate_delta);
   e.tile_m = opts->tile_m;
-  if (int pr = pack_field(g.fp, ctx, s)) {
+  if (int pr = pack_field(g.fp, ctx, s, g.counters)) {
     delete gp;
     return pr;
   }
-  if (int pr = pack_field(g.cp, ctx, s)) {
+  if (int pr = pack_field(g.cp, ctx, s, g.counters)) {
     delete gp;
     return pr;
   }
@@ -1117,7 +1163,7 @@ int32_t pifu_render_view(pifu_ctx* ctx, const pifu_field* occ_field, const pifu_
   st.level = opts->log2_w;
   st.nodes = (uint32_t)((size_t)W * H * (D + 1));
   const LevelBuf& C = g.lv[T - 1];
-  HIP_TRY(hipMemsetAsync(g.counters, 0, sizeof(uint32_t) * kCounters, s));
+  HIP_TRY(hipMemsetAsync(g.counters, 0, sizeof(uint32_t) * C_OVF, s));   // keeps C_OVF
   launch_fill_image(rgb, depth, hit, (uint32_t)(W * H), bg[0], bg[1], bg[2], s);
   launch_ray_count(C.st, C.lat, W, H, D, g.cnt, g.kstar, g.counters + C_SHADOW, s);
   launch_scan_u32(g.cnt, (uint32_t)(W * H), g.off, g.scan_scratch, g.counters + C_TOTAL, s);
@@ -1212,7 +1258,7 @@ int32_t pifu_eval_points(pifu_ctx* ctx, const pifu_field* field, int32_t precisi
   if (!lab) lab = reinterpret_cast<uint8_t*>(ew.glist);   // scratch when labels are not wanted
   EvalCtx e{ctx, s, counters, precision, guard_logit};
   e.band = logit_band(band_delta);
-  if (int pr = pack_field(fp, ctx, s)) return pr;
+  if (int pr = pack_field(fp, ctx, s, counters)) return pr;
   launch_iota(iota, n, s);
   PointSrc src;
   std::memset(&src, 0, sizeof(src));
@@ -1263,7 +1309,7 @@ int32_t pifu_autotune_mlp(pifu_ctx* ctx, const pifu_field* field, int32_t precis
   carve_eval(cv, m, field->C, fp.mlp.max_hidden, ew);
   (void)counters;
   hipStream_t s = as_stream(stream);
-  if (int pr = pack_field(fp, ctx, s)) return pr;
+  if (int pr = pack_field(fp, ctx, s, counters)) return pr;
   launch_iota(iota, m, s);
   // points: the first m nodes of a 129^3 lattice (z fastest), i.e. whole columns
   PointSrc src;
@@ -1279,7 +1325,8 @@ int32_t pifu_autotune_mlp(pifu_ctx* ctx, const pifu_field* field, int32_t precis
     const MlpPrep& mp = net ? fp.sur : fp.mlp;
     const int prec = net ? PIFU_PREC_BF16 : precision;
     const bool b16 = prec != PIFU_PREC_FP32;
-    launch_gather(src, iota, mm, field->feat, field->H, field->W, field->C, ew.feat, b16, ew.ext, s);
+    launch_gather(src, iota, mm, field->feat, field->H, field->W, field->C, ew.feat, h16_fmt(prec),
+                  ew.ext, s);
     const MLPDesc& d = mp.d;
     const void* prev = nullptr;
     void* out = ew.hA;
@@ -1300,9 +1347,7 @@ int32_t pifu_autotune_mlp(pifu_ctx* ctx, const pifu_field* field, int32_t precis
           g.K2 = g.lda2 = field->C;
         }
       }
-      g.W = prec == PIFU_PREC_FP8    ? (const void*)mp.Wp8[l]
-            : prec == PIFU_PREC_BF16 ? (const void*)mp.Wp16[l]
-                                     : (const void*)mp.Wp32[l];
+      g.W = layer_weights(mp, prec, l);
       g.a_inv_scale = prec == PIFU_PREC_FP8 ? 1.f / mp.a_scale[l] : 1.f;
       g.ldw = mp.Kp[l];
       g.Wf = d.W[l];
@@ -1354,7 +1399,8 @@ int32_t pifu_autotune_mlp(pifu_ctx* ctx, const pifu_field* field, int32_t precis
 int32_t pifu_convert_f32(pifu_ctx* ctx, const float* in, uint32_t n, int32_t precision, void* out,
                          pifu_stream stream) {
   if (!ctx || !in || !out) return PIFU_ERR_INVALID_ARGUMENT;
-  if (precision != PIFU_PREC_BF16 && precision != PIFU_PREC_FP8) return PIFU_ERR_INVALID_ARGUMENT;
+  if (precision != PIFU_PREC_BF16 && precision != PIFU_PREC_FP8 && precision != PIFU_PREC_FP16)
+    return PIFU_ERR_INVALID_ARGUMENT;
   hipStream_t s = as_stream(stream);
   launch_convert(in, n, precision, out, s);
   int r = check_launch();
@@ -1457,7 +1503,7 @@ int32_t pifu_mlp_grad(pifu_ctx* ctx, const pifu_field* field, const float* pts, 
   for (int l = 0; l < d.n_layers; ++l)
     if (!dW[l] || !db[l]) return PIFU_ERR_INVALID_ARGUMENT;
   hipStream_t s = as_stream(stream);
-  if (int pr = pack_mlp(t.mp, ctx, s)) return pr;
+  if (int pr = pack_mlp(t.mp, ctx, s, nullptr)) return pr;
   const int C = field->C;
   PointSrc src;
   std::memset(&src, 0, sizeof(src));
@@ -1791,7 +1837,7 @@ int32_t pifu_occupancy_grid_batched(pifu_ctx* ctx, int32_t n, const pifu_field* 
   e.band = logit_band(o.band_delta);
   e.sur_band = logit_band(o.surrogate_delta);
   e.tile_m = o.tile_m;
-  if (int pr = pack_field(b.fps[0], ctx, s)) {
+  if (int pr = pack_field(b.fps[0], ctx, s, b.counters)) {
     delete bp;
     return pr;
   }
@@ -1811,8 +1857,11 @@ int32_t pifu_occupancy_grid_batched(pifu_ctx* ctx, int32_t n, const pifu_field* 
       st[f].level = level_id;
       st[f].nodes = nl;
     }
-    if (hipMemsetAsync(b.counters, 0, sizeof(uint32_t) * (kCounters + 2 * kMaxFrames + 64), s) !=
-        hipSuccess) {
+    // every word but C_OVF
+    if (hipMemsetAsync(b.counters, 0, sizeof(uint32_t) * C_OVF, s) != hipSuccess ||
+        hipMemsetAsync(b.counters + C_OVF + 1, 0,
+                       sizeof(uint32_t) * (kCounters + 2 * kMaxFrames + 64 - C_OVF - 1),
+                       s) != hipSuccess) {
       rc = PIFU_ERR_HIP;
       break;
     }

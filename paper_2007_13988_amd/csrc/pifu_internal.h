@@ -68,6 +68,21 @@ __host__ __device__ inline uint16_t f32_to_bf16_bits(float x) {
   return (uint16_t)(u >> 16);
 }
 
+// float32 -> IEEE binary16 bits, round to nearest even (overflow gives infinity).
+__host__ __device__ inline uint16_t f32_to_f16_bits(float x) {
+  return __builtin_bit_cast(uint16_t, (_Float16)x);
+}
+
+// Largest finite binary16 magnitude: a value above it does not convert faithfully.
+constexpr float kF16Max = 65504.f;
+
+// Storage format of an MLP operand or activation array.
+enum { FMT_F32 = 0, FMT_BF16 = 1, FMT_F16 = 2 };
+// The 16-bit format a run precision stores activations in (FP8 stages bf16 values).
+inline int h16_fmt(int precision) {
+  return precision == PIFU_PREC_FP32 ? FMT_F32 : precision == PIFU_PREC_FP16 ? FMT_F16 : FMT_BF16;
+}
+
 constexpr int COMPACT_BLOCK = 256;
 constexpr int COMPACT_PER_THREAD = 16;
 constexpr int COMPACT_TILE = COMPACT_BLOCK * COMPACT_PER_THREAD;
@@ -111,11 +126,12 @@ void launch_eval_analytic(const PointSrc& src, const uint32_t* list, uint32_t n,
                           const Ellipsoids& ell, const float plane[4], float* logit,
                           uint8_t* lab, hipStream_t s);
 // Bilinear gather of C channels (Eq. 1's sampler) for points m in [0, n); writes
-// feat (n x C, fp32 or bf16) and ext (n x 4: z', occ, clipped, 0).
-// n_dev (nullable): device-side point count <= n; the grid covers n points
+// feat (n x C, in format feat_fmt: FMT_F32 / FMT_BF16 / FMT_F16) and ext (n x 4: z',
+// occ, clipped, 0).  n_dev (nullable): device-side point count <= n; the grid covers
+// n points.  ovf (FMT_F16): set to 1 when a feature exceeds the binary16 range.
 void launch_gather(const PointSrc& src, const uint32_t* list, uint32_t n, const float* F, int H,
-                   int W, int C, void* feat, int feat_bf16, float* ext, hipStream_t s,
-                   const uint32_t* n_dev = nullptr);
+                   int W, int C, void* feat, int feat_fmt, float* ext, hipStream_t s,
+                   const uint32_t* n_dev = nullptr, uint32_t* ovf = nullptr);
 void launch_head(const float* h, int K, const float* W, const float* b, int n_out, int out_act,
                  uint32_t n, const float* ext, float* logit, uint8_t* lab, float* rgb_out,
                  const uint32_t* rgb_index, hipStream_t s, const uint32_t* n_dev = nullptr);
@@ -158,7 +174,8 @@ void launch_fill_image(float* rgb, float* depth, uint8_t* hit, uint32_t npix, fl
 // ------------------------------------------------------------------ GEMM (MFMA)
 // C[m][n] = act(sum_k A[m][k] W[n][k] + b[n] + sum_e ext[m][e] W[n][ext_col + e]) for m < M,
 // A = [A1 (K1 columns, ld lda1) ; A2 (K2 columns, ld lda2)].  precision selects the MFMA
-// operand type; for BF16/FP8 A1, A2 and C are bf16 and W is the pre-converted copy.
+// operand type; for BF16/FP16 A1, A2 and C are in that 16-bit format (FP8: bf16) and W is
+// the pre-converted copy.
 struct GemmArgs {
   const void* A1;
   int K1, lda1;
@@ -176,7 +193,7 @@ struct GemmArgs {
   int M, N;
   int act;
   float scale;       // FP8: product of operand scales (dequantization), else 1
-  int c_bf16;        // BF16/FP8 paths: write C as bf16 (next layer's input), else fp32
+  int c_bf16;        // 16-bit/FP8 paths: write C in the run's 16-bit format, else fp32
   float a_inv_scale; // FP8: activations are quantized as e4m3(a * a_inv_scale)
   // per-row precomputed term (per-column hoisting): v += rowadd[rowadd_idx[row] *
   // rowadd_ld + rowadd_off + col]; bias may then be null.
@@ -186,6 +203,8 @@ struct GemmArgs {
   // device-side row count (nullable): rows = min(M, *M_dev); the grid covers M rows and
   // workgroups past the count exit at once (no host read-back of the count)
   const uint32_t* M_dev;
+  // FP16 (nullable): set to 1 when a value written as binary16 exceeds its range
+  uint32_t* ovf;
 };
 
 // ------------------------------------------------------------------ per-column hoisting
@@ -196,10 +215,11 @@ void launch_col_flags(const uint32_t* list, uint32_t n, uint32_t nz, uint32_t* f
 void launch_col_ids(const uint32_t* list, const uint32_t* flags, const uint32_t* excl, uint32_t n,
                     uint32_t* cid, uint32_t* col_node, hipStream_t s,
                     const uint32_t* n_dev = nullptr);
-// layer 0 with hoisting: h[i][o] = act(P[cid[i]][o] + wz[o] * z_i), z from the node index
+// layer 0 with hoisting: h[i][o] = act(P[cid[i]][o] + wz[o] * z_i), z from the node index;
+// h in format h_fmt (ovf as for launch_gather)
 void launch_hoist_layer0(const float* P, int ldp, const uint32_t* cid, const uint32_t* list,
-                         uint32_t n, int nz, const float* wz, int N, int act, void* h, int h_bf16,
-                         hipStream_t s, const uint32_t* n_dev = nullptr);
+                         uint32_t n, int nz, const float* wz, int N, int act, void* h, int h_fmt,
+                         hipStream_t s, const uint32_t* n_dev = nullptr, uint32_t* ovf = nullptr);
 
 // float32 -> OCP FP8 E4M3FN code (bias 7, 3 mantissa bits, no infinities), round to
 // nearest even, saturating at +-448; NaN -> 0x7f.
@@ -225,8 +245,9 @@ int launch_gemm(const GemmArgs& a, int precision, int tile_m, hipStream_t s);
 // FP8 operand copy: amax_bits <- max |W| (float bits), dst = e4m3(W * 448 / amax).
 void launch_pack_fp8(const float* W, int N, int ldw, int K, uint32_t* amax_bits, uint8_t* dst,
                      hipStream_t s);
-void launch_pack_weights(const float* W, int N, int ldw_src, int K, void* dst, int bf16,
-                         hipStream_t s);
+// dst = the first K columns of W in format fmt (ovf as for launch_gather)
+void launch_pack_weights(const float* W, int N, int ldw_src, int K, void* dst, int fmt,
+                         hipStream_t s, uint32_t* ovf = nullptr);
 
 }  // namespace pifu
 

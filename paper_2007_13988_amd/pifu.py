@@ -21,7 +21,7 @@ INCLUDE = os.path.join(os.path.dirname(_HERE), "include", "pifu.h")
 MAX_LAYERS = 8
 FIELD_MLP, FIELD_ELLIPSOIDS, FIELD_PLANE = 0, 1, 2
 ACT = {"relu": 1, "lrelu": 2, "sigmoid": 3, "tanh": 4}
-PREC = {"fp32": 0, "bf16": 1, "fp8": 2}
+PREC = {"fp32": 0, "bf16": 1, "fp8": 2, "fp16": 3}
 STATUS = {0: "ok", -1: "invalid argument", -2: "workspace too small", -3: "unsupported",
           -4: "HIP runtime error"}
 
@@ -77,7 +77,7 @@ class PifuKernelProfile(C.Structure):
                 ("bytes", C.c_double)]
 
 
-KERN = {"gemm_f32": 0, "gemm_bf16": 1, "gemm_fp8": 2, "gather": 3, "head": 4}
+KERN = {"gemm_f32": 0, "gemm_bf16": 1, "gemm_fp8": 2, "gather": 3, "head": 4, "gemm_f16": 5}
 KERN_COUNT = 8
 
 EXPORTS = ["pifu_create", "pifu_destroy", "pifu_status_string",
@@ -181,9 +181,9 @@ def autotune(field: "DeviceField", precision="fp32", batch_sizes=(4096, 16384, 6
 
 
 def convert(x: torch.Tensor, precision: str) -> torch.Tensor:
-    """The library's bf16 / e4m3 conversion of a device float32 tensor (raw bits)."""
+    """The library's bf16 / fp16 / e4m3 conversion of a device float32 tensor (raw bits)."""
     x = x.contiguous().to(device="cuda", dtype=torch.float32)
-    out = torch.empty(x.numel(), dtype=torch.int16 if precision == "bf16" else torch.uint8,
+    out = torch.empty(x.numel(), dtype=torch.int16 if precision in ("bf16", "fp16") else torch.uint8,
                       device="cuda")
     _check(load_library().pifu_convert_f32(context(), x.data_ptr(), x.numel(), PREC[precision],
                                            out.data_ptr(), _stream(None)), "pifu_convert_f32")

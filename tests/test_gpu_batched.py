@@ -50,7 +50,7 @@ def test_batched_ellipsoid_frames_match_single_calls(pifu):
     _same(pifu, fields, [6, 7, 6, 7, 6, 7], 4)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
 def test_tile_choice_never_changes_results(pifu, prec):
     """Forced point tiles 32/64/128/256 and the autotuned choice give identical grids."""
     from paper_2007_13988_amd import pifu as PP
@@ -68,9 +68,10 @@ def test_tile_choice_never_changes_results(pifu, prec):
     PP.autotune_clear()
 
 
-def test_batched_pifu_frames_bf16_match_single_calls(pifu):
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_batched_pifu_frames_match_single_calls(pifu, prec):
     spec = synth.pifu_mlp()
     net = pifu.DeviceMLP(spec)
     fields = [pifu.DeviceField(pifu.FIELD_MLP, feat=synth.feature_map(128, 128, 256, 16.0, 510 + f),
                                mlp=net) for f in range(3)]
-    _same(pifu, fields, [6, 7, 6], 4, precision="bf16")
+    _same(pifu, fields, [6, 7, 6], 4, precision=prec)

@@ -1,7 +1,8 @@
-"""Precision ladder (BF16 and FP8 e4m3 MFMA with FP32 accumulation, FP32 re-run of
-the points within 0.02 of p = 0.5, FP64 guard): operand conversions bit-checked
+"""Precision ladder (BF16, FP16 and FP8 e4m3 MFMA with FP32 accumulation, FP32 re-run
+of the points within 0.02 of p = 0.5, FP64 guard): operand conversions bit-checked
 against torch's casts, probability error against the FP64 oracle on sampled points,
-label flips, and surface-cell agreement of the hierarchical grid."""
+label flips, surface-cell agreement of the hierarchical grid, and the FP32 re-run of
+FP16 evaluations whose values leave the binary16 range."""
 import numpy as np
 import pytest
 import torch
@@ -30,6 +31,8 @@ def test_operand_conversions_match_torch_casts(pifu):
     xt = torch.from_numpy(x)
     b = convert(xt, "bf16").cpu()
     assert torch.equal(b, xt.to(torch.bfloat16).view(torch.int16))
+    h = convert(xt, "fp16").cpu()   # round to nearest even, overflow to infinity
+    assert torch.equal(h, xt.to(torch.float16).view(torch.int16))
     f8 = convert(xt, "fp8").cpu()
     ref = xt.clamp(-448, 448).to(torch.float8_e4m3fn).view(torch.uint8)   # saturating reading
     assert torch.equal(f8, ref)
@@ -46,7 +49,7 @@ def _sample_points(fo, n_uniform, seed):
     return pts.astype(np.float32).astype(np.float64)
 
 
-@pytest.mark.parametrize("prec,mean_tol", [("bf16", 5e-3), ("fp8", 3e-2)])
+@pytest.mark.parametrize("prec,mean_tol", [("bf16", 5e-3), ("fp16", 1e-3), ("fp8", 3e-2)])
 def test_probability_error_and_label_flips(pifu, prec, mean_tol):
     fo = O.Field("mlp", feat=synth.tiny_features(), mlp=synth.tiny_mlp())
     fg = pifu.DeviceField.mlp_field(synth.tiny_features(), synth.tiny_mlp())
@@ -65,10 +68,10 @@ def test_probability_error_and_label_flips(pifu, prec, mean_tol):
     # inside the band the label is decided in FP32/FP64, so any flip comes from a
     # low-precision error larger than the band itself: none for BF16; e4m3 keeps 3
     # mantissa bits and its logit error reaches past the band on ~0.1% of points
-    assert flips <= (1e-4 if prec == "bf16" else 5e-3) * pts.shape[0]
+    assert flips <= (5e-3 if prec == "fp8" else 1e-4) * pts.shape[0]
 
 
-@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+@pytest.mark.parametrize("prec", ["bf16", "fp16", "fp8"])
 def test_grid_surface_cells_against_oracle(pifu, prec):
     from paper_2007_13988_amd.surrogate import cell_disagreement
     fo = O.Field("mlp", feat=synth.tiny_features(), mlp=synth.tiny_mlp())
@@ -80,3 +83,70 @@ def test_grid_surface_cells_against_oracle(pifu, prec):
     print(f"{prec}: label flips {int(np.sum(lab != ref['labels']))} of {lab.size}, "
           f"surface-cell disagreement {d:.2e}")
     assert d <= 1e-3 or prec == "fp8"
+
+
+def test_fp16_error_is_below_bf16(pifu):
+    """binary16 keeps 3 more mantissa bits than bfloat16: its logit error is several
+    times smaller on the same points, and a band of 0.005 leaves no label flip."""
+    fo = O.Field("mlp", feat=synth.tiny_features(), mlp=synth.tiny_mlp())
+    fg = pifu.DeviceField.mlp_field(synth.tiny_features(), synth.tiny_mlp())
+    pts = _sample_points(fo, 200000, 405)
+    ref = O.field_logit(fo, pts)
+    err = {}
+    for prec in ("bf16", "fp16"):
+        raw, _ = pifu.eval_points(fg, pts, precision=prec, band_delta=0.0, guard_logit=0.0)
+        err[prec] = np.abs(raw.cpu().numpy().astype(np.float64) - ref)
+    print(f"logit error max bf16 {err['bf16'].max():.3e} fp16 {err['fp16'].max():.3e}; "
+          f"mean bf16 {err['bf16'].mean():.3e} fp16 {err['fp16'].mean():.3e}")
+    assert err["fp16"].mean() * 4 < err["bf16"].mean()
+    assert err["fp16"].max() * 4 < err["bf16"].max()
+    _, lab = pifu.eval_points(fg, pts, precision="fp16", band_delta=0.005, guard_logit=1e-3)
+    assert int(np.sum(lab.cpu().numpy() != (ref > 0))) == 0
+
+
+def _scaled(spec, s0, feat_scale=1.0):
+    """The same function with layer 0's outputs scaled by s0 (undone by layer 1's weights
+    of h0) and the features scaled by feat_scale (undone by every weight of f).  Powers
+    of two: FP32 arithmetic on the scaled network is the original's, exactly."""
+    import copy
+    t = copy.deepcopy(spec)
+    C = t.feat_dim
+    t.W[0] = (t.W[0] * s0).astype(np.float32)
+    t.W[0][:, :C] = (t.W[0][:, :C] / feat_scale).astype(np.float32)
+    t.b[0] = (t.b[0] * s0).astype(np.float32)
+    h0 = t.widths[0]
+    t.W[1] = t.W[1].copy()
+    t.W[1][:, :h0] = (t.W[1][:, :h0] / s0).astype(np.float32)
+    for l in range(1, len(t.widths)):
+        if t.skip[l]:
+            t.W[l] = t.W[l].copy()
+            t.W[l][:, -C:] = (t.W[l][:, -C:] / feat_scale).astype(np.float32)
+    return t
+
+
+@pytest.mark.parametrize("case", ["activation", "feature"])
+def test_fp16_overflow_reruns_in_fp32(pifu, case):
+    """Values outside the binary16 range (a hidden activation, or a sampled feature) send
+    the call's evaluations to FP32: the results are those of the FP32 run, bit for bit."""
+    spec = synth.he_mlp(64, 1, [128, 64, 1], [False, True, False], 207)
+    feat = synth.tiny_features()
+    if case == "activation":
+        big, big_feat = _scaled(spec, 2.0 ** 17), feat
+    else:
+        big, big_feat = _scaled(spec, 1.0, 2.0 ** 17), (feat * 2.0 ** 17).astype(np.float32)
+    f32 = pifu.DeviceField.mlp_field(feat, spec)
+    f16 = pifu.DeviceField.mlp_field(big_feat, big)
+    fo = O.Field("mlp", feat=feat, mlp=spec)
+    pts = _sample_points(fo, 50000, 409)
+    l32, b32 = pifu.eval_points(f32, pts, precision="fp32", guard_logit=1e-3)
+    l16, b16 = pifu.eval_points(f16, pts, precision="fp16", band_delta=0.005, guard_logit=1e-3)
+    assert torch.equal(b16, b32)
+    assert torch.equal(l16, l32)
+    g32 = pifu.occupancy_grid(f32, 6, 4, precision="fp32")
+    g16 = pifu.occupancy_grid(f16, 6, 4, precision="fp16", band_delta=0.005)
+    assert torch.equal(g16["labels"], g32["labels"])
+    for s in g16["stats"]:
+        assert s["band_fp32"] == s["mlp_points"]
+    # the same networks unscaled stay in FP16 apart from the band
+    g = pifu.occupancy_grid(f32, 6, 4, precision="fp16", band_delta=0.005)
+    assert sum(s["band_fp32"] for s in g["stats"]) < 0.5 * sum(s["mlp_points"] for s in g["stats"])
