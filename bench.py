@@ -41,7 +41,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--forms", default="fp32,fp16,surrogate_fp16")
+    ap.add_argument("--forms", default="fp32,fp16,surrogate_fp16,surrogate_bf16")
+    ap.add_argument("--sur-max-log2", type=int, default=-1,
+                    help="surrogate forms: finest level (log2 size) the surrogate stands in on; "
+                         "-1 = each call's densely evaluated coarsest level (32^3 grid, "
+                         "64x64x32 render), the only levels where it decides most points")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="budget of the oracle timing sample (cpu_baseline)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -214,7 +218,9 @@ def main():
         n_tr = args.train_frames
         delta, report = choose_delta(teacher, sur_net,
                                      [synth.pifu_sequence(102, -(n_tr + 1)),
-                                      synth.pifu_sequence(102, -(n_tr + 2))])
+                                      synth.pifu_sequence(102, -(n_tr + 2))],
+                                     sur_max_log2=5 if args.sur_max_log2 < 0 else args.sur_max_log2,
+                                     precision="fp16")
         setup = {"surrogate_train_s": round(t_train, 2),
                  "surrogate_samples": args.train_frames * args.train_samples,
                  "surrogate_steps": args.train_steps,
@@ -230,13 +236,16 @@ def main():
     def make(form):
         prec, band, sur = FORMS[form]
         kw = dict(precision=prec, guard_logit=1e-3, band_delta=band)
+        kw_g, kw_r = dict(kw), dict(kw)
         if sur:
             fld = P.DeviceField(P.FIELD_MLP, feat=feat, mlp=t_net, surrogate=sur_net)
-            kw.update(surrogate_max_log2=7, surrogate_delta=delta)
+            m = args.sur_max_log2
+            kw_g.update(surrogate_max_log2=5 if m < 0 else m, surrogate_delta=delta)
+            kw_r.update(surrogate_max_log2=6 if m < 0 else m, surrogate_delta=delta)
         else:
             fld = P.DeviceField(P.FIELD_MLP, feat=feat, mlp=t_net)
-        gout = P.GridOutputs(fld, P.grid_opts(8, 5, **kw))
-        rout = P.RenderOutputs(fld, col_field, P.render_opts(9, 8, 6, **kw))
+        gout = P.GridOutputs(fld, P.grid_opts(8, 5, **kw_g))
+        rout = P.RenderOutputs(fld, col_field, P.render_opts(9, 8, 6, **kw_r))
         return fld, gout, rout
 
     results = {}

@@ -393,7 +393,7 @@ struct EvalCtx {
   uint32_t* counters;     // device
   int precision;
   float guard;            // |logit| below which FP32 results are re-run in FP64
-  float band = 0.f;       // |logit| below which BF16/FP8 results are re-run in FP32
+  float band = 0.f;       // |logit| below which BF16/FP16/FP8 results are re-run in FP32
   float sur_band = 0.f;   // |logit| below which surrogate results go to the full MLP
   int tile_m = 0;         // forced point tile (32/64/128/256), 0 = chosen per launch
   bool g64_packed = false;  // float64 guard weights already written into the workspace
@@ -789,7 +789,7 @@ int compact_count(EvalCtx& e, const uint8_t* st, size_t n, uint8_t mask, uint8_t
   launch_compact(st, n, mask, val, scratch, e.counters + C_TOTAL, out, cap, mode, f, e.s);
   int r = check_launch();
   if (r) return r;
-  r = read_counters(e, 1);
+  r = read_counters(e, C_SHADOW + 1);   // the level's other counters come back with the count
   if (r) return r;
   *count = e.ctx->host_counters[C_TOTAL];
   return PIFU_OK;
@@ -819,6 +819,7 @@ int localize(EvalCtx& e, const FieldPrep& fp, const EvalWs& ew, const double* vi
     const int stride = 1 << (last - t);
     const uint32_t n_nodes = (uint32_t)L.lat.n();
     HIP_TRY(hipMemsetAsync(e.counters, 0, sizeof(uint32_t) * C_OVF, e.s));   // keeps C_OVF
+    bool fresh = false;   // the host copy holds every counter of this level
     if (t == 0) {
       // coarsest level: every node is evaluated
       launch_fill_u8(L.st, 0, n_nodes, e.s);
@@ -839,6 +840,7 @@ int localize(EvalCtx& e, const FieldPrep& fp, const EvalWs& ew, const double* vi
       int r = compact_count(e, L.st, n_nodes, ST_PEND, ST_PEND, w.cscratch, w.list, n_nodes, 0,
                             L.lat, &n);
       if (r) return r;
+      fresh = true;
       st.dilated = n;
       int waves = 0;
       while (n) {
@@ -847,19 +849,22 @@ int localize(EvalCtx& e, const FieldPrep& fp, const EvalWs& ew, const double* vi
         if (r) return r;
         launch_apply_grid(w.list, n, w.logit, w.lab, L.st, L.occ, e.counters + C_CONFLICTS,
                           eval_level, L.level_id, L.lat, stride, eval_lat, 1, e.s);
+        fresh = false;
         st.evaluated += n;
         if (max_waves > 0 && waves >= max_waves) break;
         launch_expand(w.list, n, L.st, L.lat, e.s);
         r = compact_count(e, L.st, n_nodes, ST_PEND, ST_PEND, w.cscratch, w.list, n_nodes, 0,
                           L.lat, &n);
         if (r) return r;
+        fresh = true;
         if (n) ++waves;
       }
       st.waves = (uint32_t)waves;
     }
     int r = check_launch();
     if (r) return r;
-    r = read_counters(e, C_SHADOW + 1);
+    // a level that ended on an empty wave has its counters from that wave's read-back
+    if (!fresh) r = read_counters(e, C_SHADOW + 1);
     if (r) return r;
     st.conflicts = e.ctx->host_counters[C_CONFLICTS];
     st.b0 = e.ctx->host_counters[C_B0];
