@@ -23,6 +23,26 @@ typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
+// Tile of this workgroup.  Workgroups are dispatched in order x + gridDim.x * y and dealt
+// round-robin to the 8 XCDs, each with its own L2.  When the row-tile count divides by 8,
+// XCD k takes the row tiles k, k + 8, k + 16, ... in increasing order, with the column
+// tiles of one row tile dispatched next to each other: a row tile of A is fetched from
+// HBM once and its other column tiles read it from the same L2, and the rows a launch
+// covers stay spread over all XCDs (launches whose device-side row count is below the
+// grid's exit their last row tiles on every XCD alike).  The tile set is unchanged.
+__device__ inline void tile_of_block(int& rt, int& ct) {
+  const int nbx = gridDim.x, nby = gridDim.y;
+  if (nbx & 7) {
+    rt = blockIdx.x;
+    ct = blockIdx.y;
+    return;
+  }
+  const int id = blockIdx.x + nbx * blockIdx.y;
+  const int q = id >> 3;
+  rt = (q / nby) * 8 + (id & 7);
+  ct = q - (q / nby) * nby;
+}
+
 __device__ inline float act_apply(float v, int act) {
   if (act == PIFU_ACT_RELU) return v > 0.f ? v : 0.f;
   if (act == PIFU_ACT_LRELU) return v > 0.f ? v : 0.01f * v;
@@ -80,6 +100,56 @@ __device__ inline void store_block(const GemmArgs& a, const f32x16& acc, int row
   if (OUT == FMT_F16 && big && a.ovf) atomicOr(a.ovf, 1u);
 }
 
+// As store_block, for a 16-bit output staged in LDS: the block's converted values go to
+// T[(lrow0 + row) * ldt + lcol0 + col] (tile-local rows and columns; rows past M are
+// staged too and skipped when the tile is written out).  Returns whether a value left
+// the binary16 range (FMT_F16).
+template <int OUT>
+__device__ inline bool stage_block(const GemmArgs& a, const f32x16& acc, int m0, int lrow0, int col0,
+                                   int lcol0, int lane, int M, uint16_t* T, int ldt) {
+  const int col = col0 + (lane & 31);
+  const float bias = a.bias ? a.bias[col] : 0.f;
+  const float we0 = a.n_ext > 0 ? a.Wf[(size_t)col * a.ldwf + a.ext_col] : 0.f;
+  const float we1 = a.n_ext > 1 ? a.Wf[(size_t)col * a.ldwf + a.ext_col + 1] : 0.f;
+  int rr[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r)
+    rr[r] = min(m0 + lrow0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), M - 1);
+  float v[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = acc[r] * a.scale + bias;
+  if (a.rowadd) {
+    uint32_t ix[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) ix[r] = a.rowadd_idx[rr[r]];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] += a.rowadd[(size_t)ix[r] * a.rowadd_ld + a.rowadd_off + col];
+  }
+  if (a.n_ext > 0) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const float* ex = a.ext + 4 * (size_t)rr[r];
+      v[r] = fmaf(ex[0], we0, v[r]);
+      if (a.n_ext > 1) v[r] = fmaf(ex[1], we1, v[r]);
+    }
+  }
+  bool big = false;
+  uint16_t* t = T + (size_t)(lrow0 + 4 * (lane >> 5)) * ldt + lcol0 + (lane & 31);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const float x = act_apply(v[r], a.act);
+    uint16_t bits;
+    if (OUT == FMT_F16) {
+      big |= !(__builtin_fabsf(x) <= kF16Max);
+      bits = f32_to_f16_bits(x);
+    } else {
+      bits = f32_to_bf16_bits(x);
+    }
+    t[(8 * (r >> 2) + (r & 3)) * ldt] = bits;
+  }
+  return big;
+}
+
 // ------------------------------------------------------------------ FP32 operands
 // v_mfma_f32_32x32x2_f32: per lane one A and one B element per MFMA; 4 MFMAs consume
 // a float4 of k from LDS (k-group of 8).
@@ -93,7 +163,9 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_f32(GemmArgs a) {
   __shared__ __attribute__((aligned(16))) float Bs[2][BN * LD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
-  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  int rt, ct;
+  tile_of_block(rt, ct);
+  const int m0 = rt * BM, n0 = ct * BN;
   const int M = a.M_dev ? min(a.M, (int)*a.M_dev) : a.M;
   if (m0 >= M) return;
   const int K = a.K1 + a.K2;
@@ -213,11 +285,17 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_h16(GemmArgs a) {
   constexpr int BK = 64;
   constexpr int LD = BK + 8;   // in bf16 elements
   constexpr int TI = BM / WM / 32, TJ = BN / WN / 32;
-  __shared__ __attribute__((aligned(16))) __bf16 As[2][BM * LD];
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[2][BN * LD];
+  // one LDS block: the double-buffered A and B stages, and after the k loop the
+  // converted output tile (OUT16)
+  constexpr int SMEM = 2 * (BM + BN) * LD;
+  __shared__ __attribute__((aligned(16))) __bf16 smem[SMEM];
+  __bf16* const As = smem;                  // stage b of A at As + b * BM * LD
+  __bf16* const Bs = smem + 2 * BM * LD;    // stage b of B at Bs + b * BN * LD
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
-  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  int rt, ct;
+  tile_of_block(rt, ct);
+  const int m0 = rt * BM, n0 = ct * BN;
   const int M = a.M_dev ? min(a.M, (int)*a.M_dev) : a.M;
   if (m0 >= M) return;
   const int K = a.K1 + a.K2;
@@ -266,14 +344,14 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_h16(GemmArgs a) {
 #pragma unroll
     for (int i = 0; i < A_LOADS; ++i) {
       const int e = tid + NT * i;
-      *reinterpret_cast<u32x4*>(&As[buf][(e >> 3) * LD + 8 * (e & 7)]) = rs[i];
+      *reinterpret_cast<u32x4*>(&As[buf * BM * LD + (e >> 3) * LD + 8 * (e & 7)]) = rs[i];
     }
   };
   auto sstore_b = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < B_LOADS; ++i) {
       const int e = tid + NT * i;
-      *reinterpret_cast<u32x4*>(&Bs[buf][(e >> 3) * LD + 8 * (e & 7)]) = rs[i];
+      *reinterpret_cast<u32x4*>(&Bs[buf * BN * LD + (e >> 3) * LD + 8 * (e & 7)]) = rs[i];
     }
   };
 
@@ -292,10 +370,10 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_h16(GemmArgs a) {
   auto load_frags = [&](int buf, int kk, int q) {
 #pragma unroll
     for (int i = 0; i < TI; ++i)
-      av[q][i] = *reinterpret_cast<const bf16x8*>(&As[buf][(wrow + 32 * i + l32) * LD + kk + 8 * h]);
+      av[q][i] = *reinterpret_cast<const bf16x8*>(&As[buf * BM * LD + (wrow + 32 * i + l32) * LD + kk + 8 * h]);
 #pragma unroll
     for (int j = 0; j < TJ; ++j)
-      bv[q][j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][(wcol + 32 * j + l32) * LD + kk + 8 * h]);
+      bv[q][j] = *reinterpret_cast<const bf16x8*>(&Bs[buf * BN * LD + (wcol + 32 * j + l32) * LD + kk + 8 * h]);
   };
   auto mfmas = [&](int q) {
 #pragma unroll
@@ -336,12 +414,39 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_h16(GemmArgs a) {
     if (more) sstore_b(buf ^ 1);
     __syncthreads();
   }
+  if constexpr (OUT16) {
+    // the loop's last barrier has retired every read of the operand stages: stage the
+    // converted tile there (row-major, LDT per row), then write whole rows with 16-byte
+    // stores instead of one 2-byte store per element
+    constexpr int LDT = BN + 8;
+    static_assert(BM * LDT <= SMEM, "output tile exceeds the operand stages");
+    uint16_t* T = reinterpret_cast<uint16_t*>(smem);
+    bool big = false;
 #pragma unroll
-  for (int i = 0; i < TI; ++i)
+    for (int i = 0; i < TI; ++i)
 #pragma unroll
-    for (int j = 0; j < TJ; ++j)
-      store_block<OUT16 ? (F16 ? FMT_F16 : FMT_BF16) : FMT_F32>(a, acc[i][j], m0 + wrow + 32 * i,
-                                                                n0 + wcol + 32 * j, lane, M);
+      for (int j = 0; j < TJ; ++j)
+        big |= stage_block<F16 ? FMT_F16 : FMT_BF16>(a, acc[i][j], m0, wrow + 32 * i,
+                                                     n0 + wcol + 32 * j, wcol + 32 * j, lane, M, T,
+                                                     LDT);
+    if (F16 && big && a.ovf) atomicOr(a.ovf, 1u);
+    __syncthreads();
+    constexpr int CPR = BN / 8;   // 16-byte chunks per tile row
+    uint16_t* Cg = reinterpret_cast<uint16_t*>(a.C);
+#pragma unroll 4
+    for (int e = tid; e < BM * CPR; e += NT) {
+      const int r = e / CPR, c8 = e - (e / CPR) * CPR;
+      if (m0 + r < M)
+        *reinterpret_cast<u32x4*>(Cg + (size_t)(m0 + r) * a.ldc + n0 + 8 * c8) =
+            *reinterpret_cast<const u32x4*>(T + r * LDT + 8 * c8);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+      for (int j = 0; j < TJ; ++j)
+        store_block<FMT_F32>(a, acc[i][j], m0 + wrow + 32 * i, n0 + wcol + 32 * j, lane, M);
+  }
 }
 
 // Copies the first K columns of a row-major [N][ldw_src] fp32 weight matrix into a
@@ -396,7 +501,9 @@ __global__ void __launch_bounds__(256, MINB) k_gemm_fp8(GemmArgs a) {
   __shared__ __attribute__((aligned(16))) uint8_t Bs[2][BN * LD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
-  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  int rt, ct;
+  tile_of_block(rt, ct);
+  const int m0 = rt * BM, n0 = ct * BN;
   const int M = a.M_dev ? min(a.M, (int)*a.M_dev) : a.M;
   if (m0 >= M) return;
   const int K = a.K1 + a.K2;
