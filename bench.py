@@ -15,7 +15,9 @@ Forms timed on the same frame (all with the FP64 guard at |logit| < 1e-3):
     levels, points it leaves undecided and the finer levels as in fp16;
   * bf16 / surrogate_bf16 (on request): as above with BF16 and a band of 0.02.
 `value` is the fastest form whose surface cells and render hits agree with the FP32
-form within 0.1%, else the FP32 form.  Prints one JSON line.
+form within 0.1%, else the FP32 form.  The timed steps run without instrumentation; the
+roofline's per-launch durations come from the same steps run again with HIP events
+around every MLP launch (events cost ~9 us of stream time each).  Prints one JSON line.
 """
 import argparse
 import json
@@ -49,6 +51,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="budget of the oracle timing sample (cpu_baseline)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="skip the second, event-instrumented pass (no roofline)")
     ap.add_argument("--train-frames", type=int, default=6)
     ap.add_argument("--train-samples", type=int, default=1747627)   # 6 x 1.75 M = 10.5 M
     ap.add_argument("--train-steps", type=int, default=4000)
@@ -255,24 +259,36 @@ def main():
             P.occupancy_grid_into(fld, gout, stream)
             P.render_view_into(fld, col_field, view, bg, rout, stream)
         torch.cuda.synchronize()
-        P.profile_enable(True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        t_occ = 0.0
-        for _ in range(args.steps):
-            a = time.perf_counter()
-            P.occupancy_grid_into(fld, gout, stream)
-            t_occ += time.perf_counter() - a
-            P.render_view_into(fld, col_field, view, bg, rout, stream)
-        torch.cuda.synchronize()
-        elapsed = time.perf_counter() - t0
-        prof = P.profile_read()
-        P.profile_enable(False)
+
+        def timed_steps():
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            t_occ = 0.0
+            for _ in range(args.steps):
+                a = time.perf_counter()
+                P.occupancy_grid_into(fld, gout, stream)
+                t_occ += time.perf_counter() - a
+                P.render_view_into(fld, col_field, view, bg, rout, stream)
+            torch.cuda.synchronize()
+            return time.perf_counter() - t0, t_occ
+
+        # the timed steps run uninstrumented: a HIP event pair around a launch costs about
+        # 9 us of stream time, ~3.7 ms over the ~370 MLP launches of a frame
+        elapsed, t_occ = timed_steps()
+        # per-launch durations: the same steps again with HIP events around every launch
+        # of the GEMM, gather and head families, on the stream they are launched on
+        prof, instr = None, None
+        if not args.no_profile:
+            P.profile_enable(True)
+            instr, _ = timed_steps()
+            prof = P.profile_read()
+            P.profile_enable(False)
         gst = [s.as_dict() for s in gout.stats]
         rst = [s.as_dict() for s in rout.stats]
         nc = gout.n_cells.value
         results[form] = dict(ms=elapsed / args.steps * 1e3, ms_occ=t_occ / args.steps * 1e3,
-                             prof=prof, gst=gst, rst=rst,
+                             ms_instrumented=instr / args.steps * 1e3 if instr else None,
+                             prof=prof or {}, gst=gst, rst=rst,
                              cells=gout.cells[:min(nc, gout.cells_cap)].clone(),
                              hit=rout.hit.clone())
 
@@ -310,8 +326,8 @@ def main():
     gemm_key = max(gemms, key=lambda k: gemms[k]["total_ms"]) if gemms else "gemm_f32"
 
     def roofline(r, key, peak_key):
-        g = r["prof"][key]
-        if not g["launches"]:
+        g = r["prof"].get(key)
+        if not g or not g["launches"]:
             return None
         avg_ms = g["total_ms"] / g["launches"]
         fpl = g["flops"] / g["launches"]
@@ -323,7 +339,10 @@ def main():
                 "launches_per_step": g["launches"] / args.steps, "avg_launch_ms": round(avg_ms, 4),
                 "flops_per_launch": fpl, "algorithmic_bytes_per_launch": g["bytes"] / g["launches"],
                 "share_of_gemm_time": round(g["total_ms"] / sum(v["total_ms"] for v in gemms.values()), 3)
-                if key in gemms else None}
+                if key in gemms else None,
+                "events_pass": f"launch durations from {args.steps} further steps of the same frame "
+                               f"with HIP events around every MLP launch ({r['ms_instrumented']:.3f} "
+                               f"ms/frame with the events, {r['ms']:.3f} without)"}
 
     occ_pts = sum(s["mlp_points"] for s in main_r["gst"])
     ren_pts = sum(s["mlp_points"] for s in main_r["rst"])
