@@ -285,69 +285,126 @@ void launch_guard_select(const float* logit, uint32_t n, float g, uint32_t* glis
 // ------------------------------------------------------------------ mesh-free rendering
 // Level-L interpolation along a pixel column (u, v) of the target lattice, from the
 // binarized labels of level L-1: S(kc) sums the labels of the 1/2/4 coarse columns
-// around (u, v); even k use S(k/2), odd k the two neighbours.
-// The render's last level reads the level-(L-1) labels of up to 4 coarse columns per
-// pixel column.  A workgroup takes a 16 x 16 tile of pixel columns; their 9 x 9 coarse
-// columns are contiguous runs of nz bytes per coarse row, so the tile stages the
-// label bits of all of them into LDS with coalesced loads and the rays walk LDS.
+// around (u, v); even k use S(k/2), odd k the two neighbours.  A fine node is full
+// (S = count) where every coarse label involved is 1 and fractional where some but not
+// all are.  A workgroup takes a 16 x 16 tile of pixel columns and stages the labels of
+// their 9 x 9 coarse columns into LDS as bit masks along z (one wave ballot per 64
+// nodes); a ray then works on the AND and OR of its columns' masks:
+//   full(2m) = A_m,           nonzero(2m) = O_m,
+//   full(2m+1) = A_m A_m+1,   nonzero(2m+1) = O_m | O_m+1.
 constexpr int kRayTile = 16;
 constexpr int kRayCoarse = kRayTile / 2 + 1;
+constexpr int kRayMaxWords = 9;   // coarse columns of up to 576 nodes (depth 2^10)
 
-size_t ray_lds_bytes(Lat c) { return (size_t)kRayCoarse * kRayCoarse * c.nz; }
+__host__ __device__ inline int ray_words(int nz) { return (nz + 63) >> 6; }
 
-__device__ inline void stage_ray_labels(const uint8_t* __restrict__ stc, Lat c, int cu0, int cv0,
-                                        uint8_t* sl) {
-  // coarse row a of the tile is one contiguous run of kRayCoarse * nz bytes in global
-  // memory; bytes past the lattice edge are staged as 0 (no pixel column reads them)
-  const int row = kRayCoarse * c.nz;
-  const int ncv = min(kRayCoarse, c.ny - cv0);
-#pragma unroll
-  for (int a = 0; a < kRayCoarse; ++a) {
-    const int cu = cu0 + a;
-    const int rlim = cu < c.nx ? ncv * c.nz : 0;
-    const uint8_t* src = stc + ((size_t)min(cu, c.nx - 1) * c.ny + cv0) * c.nz;
-    for (int r = threadIdx.x; r < row; r += blockDim.x)
-      sl[a * row + r] = r < rlim ? (uint8_t)(src[r] & ST_LABEL) : (uint8_t)0;
+size_t ray_lds_bytes(Lat c) {
+  return (size_t)kRayCoarse * kRayCoarse * ray_words(c.nz) * sizeof(uint64_t);
+}
+
+__device__ inline void stage_ray_bits(const uint8_t* __restrict__ stc, Lat c, int cu0, int cv0,
+                                      uint64_t* bits) {
+  // columns past the lattice edge are staged as 0 (no pixel column reads them)
+  const int nw = ray_words(c.nz);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  for (int idx = wave; idx < kRayCoarse * kRayCoarse; idx += nwaves) {
+    const int cu = cu0 + idx / kRayCoarse, cv = cv0 + idx % kRayCoarse;
+    const bool in = cu < c.nx && cv < c.ny;
+    const uint8_t* src = stc + ((size_t)(in ? cu : 0) * c.ny + (in ? cv : 0)) * c.nz;
+    for (int q = 0; q < nw; ++q) {
+      const int k = 64 * q + lane;
+      const bool l = in && k < c.nz && (src[k] & ST_LABEL);
+      const uint64_t m = __ballot(l);
+      if (lane == 0) bits[idx * nw + q] = m;
+    }
   }
   __syncthreads();
 }
 
-// The (up to 4) coarse columns around pixel column (u, v), as LDS offsets.
-struct RayCol {
+// The ray of pixel column (u, v): its coarse columns (LDS word offsets) and the AND / OR
+// of their label masks.
+struct Ray {
   int off[4];
-  int ncol;
-  __device__ inline int S(const uint8_t* sl, int kc) const {
-    int s = 0;
-    for (int i = 0; i < ncol; ++i) s += sl[off[i] + kc];
-    return s;
+  int ncol, nw, nzc;
+  uint64_t A[kRayMaxWords], O[kRayMaxWords];
+
+  __device__ inline void init(const uint64_t* bits, int nz, int u, int v, int cu0, int cv0) {
+    nzc = nz;
+    nw = ray_words(nz);
+    ncol = 0;
+    const int ua = u >> 1, ub = (u + 1) >> 1, va = v >> 1, vb = (v + 1) >> 1;
+    for (int i = 0; i < 2; ++i) {
+      const int cu = i ? ub : ua;
+      if (i && ub == ua) continue;
+      for (int j = 0; j < 2; ++j) {
+        const int cv = j ? vb : va;
+        if (j && vb == va) continue;
+        off[ncol++] = ((cu - cu0) * kRayCoarse + (cv - cv0)) * nw;
+      }
+    }
+    for (int q = 0; q < kRayMaxWords; ++q) {
+      uint64_t a = ~0ull, o = 0ull;
+      if (q < nw) {
+        for (int i = 0; i < ncol; ++i) {
+          const uint64_t m = bits[off[i] + q];
+          a &= m;
+          o |= m;
+        }
+      } else {
+        a = 0ull;
+      }
+      A[q] = a;
+      O[q] = o;
+    }
   }
-  // interpolated value of fine node k of the column as sum / count of coarse labels
-  __device__ inline void at(const uint8_t* sl, int k, int& sum, int& cnt) const {
+  // bit m of word q of the mask shifted down by one node (m + 1 -> m)
+  __device__ static inline uint64_t next(const uint64_t* X, int q) {
+    return (X[q] >> 1) | (q + 1 < kRayMaxWords ? X[q + 1] << 63 : 0ull);
+  }
+  // odd node 2m + 1 exists for m <= nzc - 2
+  __device__ inline uint64_t odd_valid(int q) const {
+    const int lim = nzc - 1 - 64 * q;   // bits [0, lim) of word q
+    return lim >= 64 ? ~0ull : (lim <= 0 ? 0ull : ((1ull << lim) - 1ull));
+  }
+  // bits m >= m0 of word q
+  __device__ static inline uint64_t from(int m0, int q) {
+    const int r = m0 - 64 * q;
+    return r <= 0 ? ~0ull : (r >= 64 ? 0ull : ~0ull << r);
+  }
+  // k* = the node nearest the observer (largest k) that is full, -1 if none
+  __device__ inline int kstar() const {
+    int ke = -1, ko = -1;
+    for (int q = nw - 1; q >= 0 && ke < 0; --q)
+      if (A[q]) ke = 2 * (64 * q + 63 - __clzll(A[q]));
+    for (int q = nw - 1; q >= 0 && ko < 0; --q) {
+      const uint64_t aa = A[q] & next(A, q) & odd_valid(q);
+      if (aa) ko = 2 * (64 * q + 63 - __clzll(aa)) + 1;
+    }
+    return ke > ko ? ke : ko;
+  }
+  // candidates above k (the nodes the network evaluates): nonzero, not full
+  __device__ inline uint64_t even_cand(int ks, int q) const {
+    return O[q] & from(ks < 0 ? 0 : ks / 2 + 1, q);
+  }
+  __device__ inline uint64_t odd_cand(int ks, int q) const {
+    return (O[q] | next(O, q)) & odd_valid(q) & from(ks < 0 ? 0 : (ks + 1) / 2, q);
+  }
+  // sum and count of the coarse labels behind fine node k
+  __device__ inline void at(const uint64_t* bits, int k, int& sum, int& cnt) const {
+    auto S = [&](int kc) {
+      int s = 0;
+      for (int i = 0; i < ncol; ++i) s += (int)((bits[off[i] + (kc >> 6)] >> (kc & 63)) & 1ull);
+      return s;
+    };
     if (k & 1) {
-      sum = S(sl, k >> 1) + S(sl, (k >> 1) + 1);
+      sum = S(k >> 1) + S((k >> 1) + 1);
       cnt = 2 * ncol;
     } else {
-      sum = S(sl, k >> 1);
+      sum = S(k >> 1);
       cnt = ncol;
     }
   }
 };
-
-__device__ inline RayCol make_raycol(int nz, int u, int v, int cu0, int cv0) {
-  RayCol r;
-  r.ncol = 0;
-  const int ua = u >> 1, ub = (u + 1) >> 1, va = v >> 1, vb = (v + 1) >> 1;
-  for (int i = 0; i < 2; ++i) {
-    int cu = i ? ub : ua;
-    if (i && ub == ua) continue;
-    for (int j = 0; j < 2; ++j) {
-      int cv = j ? vb : va;
-      if (j && vb == va) continue;
-      r.off[r.ncol++] = ((cu - cu0) * kRayCoarse + (cv - cv0)) * nz;
-    }
-  }
-  return r;
-}
 
 // Per column: k* = the node nearest the observer whose interpolated value is 1;
 // nodes below it are shadow nodes.  Counts the non-shadow nodes with a fractional
@@ -356,24 +413,18 @@ __global__ void __launch_bounds__(256) k_ray_count(const uint8_t* __restrict__ s
                                                    int H, int D, uint32_t* __restrict__ cnt,
                                                    uint32_t* __restrict__ kstar,
                                                    uint32_t* __restrict__ shadow_total) {
-  extern __shared__ uint8_t sl[];
+  extern __shared__ uint64_t bits[];
   const int u0 = blockIdx.x * kRayTile, v0 = blockIdx.y * kRayTile;
-  stage_ray_labels(stc, c, u0 >> 1, v0 >> 1, sl);
+  stage_ray_bits(stc, c, u0 >> 1, v0 >> 1, bits);
   const int u = u0 + (int)(threadIdx.x >> 4), v = v0 + (int)(threadIdx.x & 15);
   uint32_t shadow = 0;
   if (u < W && v < H) {
-    const RayCol rc = make_raycol(c.nz, u, v, u0 >> 1, v0 >> 1);
-    int ks = -1;
+    Ray r;
+    r.init(bits, c.nz, u, v, u0 >> 1, v0 >> 1);
+    const int ks = r.kstar();
     uint32_t n = 0;
-    for (int k = D; k >= 0; --k) {
-      int s, t;
-      rc.at(sl, k, s, t);
-      if (s == t) {
-        ks = k;
-        break;
-      }
-      if (s > 0) ++n;
-    }
+    for (int q = 0; q < r.nw; ++q)
+      n += (uint32_t)(__popcll(r.even_cand(ks, q)) + __popcll(r.odd_cand(ks, q)));
     const uint32_t col = (uint32_t)u * H + v;
     cnt[col] = n;
     kstar[col] = (uint32_t)ks;
@@ -398,20 +449,27 @@ __global__ void __launch_bounds__(256) k_ray_list(const uint8_t* __restrict__ st
                                                   int H, int D, const uint32_t* __restrict__ kstar,
                                                   const uint32_t* __restrict__ off,
                                                   uint32_t* __restrict__ list) {
-  extern __shared__ uint8_t sl[];
+  extern __shared__ uint64_t bits[];
   const int u0 = blockIdx.x * kRayTile, v0 = blockIdx.y * kRayTile;
-  stage_ray_labels(stc, c, u0 >> 1, v0 >> 1, sl);
+  stage_ray_bits(stc, c, u0 >> 1, v0 >> 1, bits);
   const int u = u0 + (int)(threadIdx.x >> 4), v = v0 + (int)(threadIdx.x & 15);
   if (u >= W || v >= H) return;
   const uint32_t col = (uint32_t)u * H + v;
-  const RayCol rc = make_raycol(c.nz, u, v, u0 >> 1, v0 >> 1);
+  Ray r;
+  r.init(bits, c.nz, u, v, u0 >> 1, v0 >> 1);
   const int ks = (int)kstar[col];
   uint32_t pos = off[col];
   const size_t base = ((size_t)u * (H + 1) + v) * (size_t)(D + 1);
-  for (int k = ks + 1; k <= D; ++k) {
-    int s, t;
-    rc.at(sl, k, s, t);
-    if (s > 0 && s < t) list[pos++] = (uint32_t)(base + k);
+  for (int q = 0; q < r.nw; ++q) {
+    const uint64_t ev = r.even_cand(ks, q), od = r.odd_cand(ks, q);
+    uint64_t any = ev | od;
+    while (any) {
+      const int bit = __ffsll((unsigned long long)any) - 1;
+      any &= any - 1ull;
+      const int m = 64 * q + bit;
+      if ((ev >> bit) & 1ull) list[pos++] = (uint32_t)(base + 2 * m);
+      if ((od >> bit) & 1ull) list[pos++] = (uint32_t)(base + 2 * m + 1);
+    }
   }
 }
 
@@ -421,59 +479,46 @@ void launch_ray_list(const uint8_t* stc, Lat c, int W, int H, int D, const uint3
                      stc, c, W, H, D, kstar, off, list);
 }
 
-// Second argmax after evaluation: k1 = first node from the observer labelled inside;
-// the surface point is the 0.5 crossing of the occupancy values of k1 and k1 + 1.
-// The walk reads labels only; the two occupancy values are fetched at the end.
+// Second argmax after evaluation: k1 = the node nearest the observer labelled inside,
+// i.e. the highest evaluated candidate labelled inside, else k*; the surface point is
+// the 0.5 crossing of the occupancy values of k1 and k1 + 1.
 __global__ void __launch_bounds__(256) k_ray_hit(
     const uint8_t* __restrict__ stc, const float* __restrict__ occc, Lat c, int W, int H, int D,
     const uint32_t* __restrict__ off, const uint32_t* __restrict__ cnt,
     const uint32_t* __restrict__ list, const float* __restrict__ logit,
     const uint8_t* __restrict__ lab, float* __restrict__ depth, uint8_t* __restrict__ hit,
     float4* __restrict__ hitpts, double4 v0, double4 v1, double4 v2) {
-  extern __shared__ uint8_t sl[];
+  extern __shared__ uint64_t bits[];
   const int u0 = blockIdx.x * kRayTile, vt0 = blockIdx.y * kRayTile;
   const int cu0 = u0 >> 1, cv0 = vt0 >> 1;
-  stage_ray_labels(stc, c, cu0, cv0, sl);
+  stage_ray_bits(stc, c, cu0, cv0, bits);
   const int u = u0 + (int)(threadIdx.x >> 4), v = vt0 + (int)(threadIdx.x & 15);
   if (u >= W || v >= H) return;
   const uint32_t col = (uint32_t)u * H + v;
-  const RayCol rc = make_raycol(c.nz, u, v, cu0, cv0);
+  Ray r;
+  r.init(bits, c.nz, u, v, cu0, cv0);
   const bool even_col = !((u | v) & 1);
-  const int own = (((u >> 1) - cu0) * kRayCoarse + ((v >> 1) - cv0)) * c.nz;  // even columns
-  int j = (int)off[col] + (int)cnt[col] - 1;
-  const int jmin = (int)off[col];
-  int k1 = -1, j1 = -1, jprev = -1;
-  for (int k = D; k >= 0; --k) {
-    int l, jk = -1;
-    if (even_col && !(k & 1)) {
-      l = sl[own + (k >> 1)];
-    } else {
-      int s, t;
-      rc.at(sl, k, s, t);
-      const uint32_t lid = ((uint32_t)u * (H + 1) + v) * (uint32_t)(D + 1) + k;
-      if (s > 0 && s < t && j >= jmin && list[j] == lid) {
-        l = lab[j];
-        jk = j;
-        --j;
-      } else {
-        l = (s == t);
-      }
-    }
-    if (l) {
-      k1 = k;
-      j1 = jk;
+  const uint32_t base = ((uint32_t)u * (H + 1) + v) * (uint32_t)(D + 1);
+  const int jmin = (int)off[col], jend = (int)off[col] + (int)cnt[col] - 1;
+  int k1 = -1, j1 = -1;
+  for (int j = jend; j >= jmin; --j)
+    if (lab[j]) {
+      k1 = (int)(list[j] - base);
+      j1 = j;
       break;
     }
-    jprev = jk;
-  }
+  if (k1 < 0) k1 = r.kstar();
   if (k1 < 0) return;
+  // node k1 + 1, when evaluated, is the list entry after k1's (or the first entry)
+  const int jn = j1 >= 0 ? j1 + 1 : jmin;
+  const int jprev = (k1 < D && jn <= jend && list[jn] == base + (uint32_t)(k1 + 1)) ? jn : -1;
   // occupancy of node k of this column: a coarse node's stored value, an evaluated
   // node's sigmoid, else the interpolated fraction
   auto value = [&](int k, int jk) -> float {
     if (even_col && !(k & 1)) return occc[((size_t)(u >> 1) * c.ny + (v >> 1)) * c.nz + (k >> 1)];
     if (jk >= 0) return 1.0f / (1.0f + expf(-logit[jk]));
     int s, t;
-    rc.at(sl, k, s, t);
+    r.at(bits, k, s, t);
     return (float)s / (float)t;
   };
   const float ob = value(k1, j1);

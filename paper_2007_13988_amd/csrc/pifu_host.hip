@@ -834,8 +834,15 @@ int localize(EvalCtx& e, const FieldPrep& fp, const EvalWs& ew, const double* vi
     } else {
       LevelBuf& Cc = lv[t - 1];
       launch_transition(Cc.st, Cc.occ, Cc.lat, L.st, L.occ, L.lat, e.s);
-      launch_count_bits(L.st, n_nodes, ST_B0, e.counters + C_B0, e.s);
-      launch_select(L.st, L.lat, e.s);
+      // the candidate list is consumed: its buffer (n_nodes words) holds the candidate
+      // bit masks until this level's compaction rewrites it
+      if (2 * b0_mask_words(L.lat) <= n_nodes) {
+        launch_select_b0(L.st, L.lat, 1, reinterpret_cast<uint64_t*>(w.list), e.counters + C_B0, 0,
+                         e.s);
+      } else {
+        launch_count_bits(L.st, n_nodes, ST_B0, e.counters + C_B0, e.s);
+        launch_select(L.st, L.lat, e.s);
+      }
       uint32_t n = 0;
       int r = compact_count(e, L.st, n_nodes, ST_PEND, ST_PEND, w.cscratch, w.list, n_nodes, 0,
                             L.lat, &n);
@@ -1891,9 +1898,15 @@ int32_t pifu_occupancy_grid_batched(pifu_ctx* ctx, int32_t n, const pifu_field* 
       }
     } else {
       launch_transition(b.st[r - 1], b.occ[r - 1], b.lat[r - 1], b.st[r], b.occ[r], L, s, A, &fo);
-      for (int p = 0; p < A; ++p)
-        launch_count_bits(b.st[r] + (size_t)p * nl, nl, ST_B0, b.counters + C_B0_F + p, s);
-      launch_select(b.st[r], L, s, A);
+      if (2 * b0_mask_words(L) * (size_t)A <= b.list_cap) {
+        // the candidate list is consumed until compact_frames rewrites it
+        launch_select_b0(b.st[r], L, A, reinterpret_cast<uint64_t*>(b.w.list), b.counters + C_B0_F,
+                         1, s);
+      } else {
+        for (int p = 0; p < A; ++p)
+          launch_count_bits(b.st[r] + (size_t)p * nl, nl, ST_B0, b.counters + C_B0_F + p, s);
+        launch_select(b.st[r], L, s, A);
+      }
       rc = compact_frames(e, b, r, &cnt, bounds, 0, A);
       if (rc) break;
       for (int p = 0; p < A; ++p) st[b.order[p]].dilated = bounds[p + 1] - bounds[p];

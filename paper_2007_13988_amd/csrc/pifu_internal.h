@@ -101,6 +101,12 @@ struct FrameOcc {
 void launch_transition(const uint8_t* cst, const float* cocc, Lat c, uint8_t* fst, float* focc,
                        Lat f, hipStream_t s, int frames = 1, const FrameOcc* fo = nullptr);
 void launch_select(uint8_t* st, Lat f, hipStream_t s, int frames = 1);
+// The same selection from bit masks of the boundary candidates, and their count per frame
+// (counts[p * count_stride] += candidates of frame p).  masks: b0_mask_words(f) words per
+// frame, 8-byte aligned scratch that nothing reads afterwards.
+size_t b0_mask_words(Lat f);
+void launch_select_b0(uint8_t* st, Lat f, int frames, uint64_t* masks, uint32_t* counts,
+                      int count_stride, hipStream_t s);
 // bounds[f] (f = 0..frames) = first list position with entry >= f * frame_nodes.
 void launch_segment_bounds(const uint32_t* list, uint32_t n, uint32_t frame_nodes, int frames,
                            uint32_t* bounds, hipStream_t s);

@@ -1,6 +1,8 @@
 // Level kernels of hierarchical surface localization (Sec. 3.2): level transition
 // (binarize + trilinear x2), 1-ring dilation, stable stream compaction, conflict
 // expansion, surface-cell extraction.  All are HBM/L2-bound byte-state passes.
+#include <algorithm>
+
 #include "pifu_internal.h"
 
 namespace pifu {
@@ -133,6 +135,113 @@ __global__ void k_select(uint8_t* __restrict__ st, Lat f) {
 
 void launch_select(uint8_t* st, Lat f, hipStream_t s, int frames) {
   hipLaunchKernelGGL(k_select, dim3(grid1d(f.n(), 256), frames), dim3(256), 0, s, st, f);
+}
+
+// Boundary-candidate bit masks: word w of column c (c = a * ny + b) holds the ST_B0 bits
+// of nodes [64 w, 64 w + 64) of that column, one thread per word.  The word's 64 state
+// bytes start at an arbitrary byte address: five aligned 16-byte loads cover them (a load
+// starting at or past the frame's end is skipped; the state arrays carry 16 bytes of
+// padding), each 4 bytes give 4 bits, and an 80-bit funnel shift aligns the word.  The
+// count of candidates goes to counts[frame * count_stride], one atomic per workgroup.
+__device__ inline uint32_t b0_nibble(uint32_t x) {
+  const uint32_t v = (x >> 2) & 0x01010101u;   // ST_B0 is bit 2 of each byte
+  return (v | (v >> 7) | (v >> 14) | (v >> 21)) & 0xFu;
+}
+
+__global__ void __launch_bounds__(256)
+k_b0_masks(const uint8_t* __restrict__ st, Lat f, uint64_t* __restrict__ masks,
+           uint32_t* __restrict__ counts, int count_stride) {
+  static_assert(ST_B0 == 0x04, "b0_nibble reads bit 2");
+  __shared__ uint32_t wsum[4];
+  const uint32_t nw = (uint32_t)(f.nz + 63) >> 6;
+  const uint32_t units = (uint32_t)f.nx * f.ny * nw;
+  const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+  st += (size_t)blockIdx.y * f.n();
+  masks += (size_t)blockIdx.y * units;
+  uint32_t c = 0;
+  if (u < units) {
+    const uint32_t col = u / nw, w = u - col * nw;
+    const uint8_t* p = st + (size_t)col * f.nz + 64 * w;
+    const uintptr_t addr = reinterpret_cast<uintptr_t>(p);
+    const int sh = (int)(addr & 15u);
+    const uint8_t* q = reinterpret_cast<const uint8_t*>(addr - (uintptr_t)sh);
+    const uint8_t* end = st + f.n();
+    uint64_t lo = 0ull, hi = 0ull;   // 80 bits: byte i of the window -> bit i
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      uint4 x = make_uint4(0u, 0u, 0u, 0u);
+      if (q + 16 * i < end) x = *reinterpret_cast<const uint4*>(q + 16 * i);
+      const uint32_t b16 = b0_nibble(x.x) | (b0_nibble(x.y) << 4) | (b0_nibble(x.z) << 8) |
+                           (b0_nibble(x.w) << 12);
+      if (i < 4) lo |= (uint64_t)b16 << (16 * i);
+      else hi = b16;
+    }
+    uint64_t m = sh ? (lo >> sh) | (hi << (64 - sh)) : lo;
+    const int valid = f.nz - 64 * (int)w;   // nodes of this word inside the column
+    if (valid < 64) m &= (1ull << valid) - 1ull;
+    masks[u] = m;
+    c = (uint32_t)__popcll(m);
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d, 64);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t t = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    if (t && counts) atomicAdd(counts + (size_t)blockIdx.y * count_stride, t);
+  }
+}
+
+// Marks the nodes that are not evaluated yet and have a boundary candidate among their
+// 26 neighbours (or are one) as pending: one thread per mask word; the OR of the 3 x 3
+// neighbouring columns' words, each widened by one node along z, gives the word's
+// selected nodes, and only those state bytes are read and written.
+__global__ void __launch_bounds__(256)
+k_select_masks(uint8_t* __restrict__ st, Lat f, const uint64_t* __restrict__ masks) {
+  const uint32_t nw = (uint32_t)(f.nz + 63) >> 6;
+  const uint32_t units = (uint32_t)f.nx * f.ny * nw;
+  const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= units) return;
+  st += (size_t)blockIdx.y * f.n();
+  masks += (size_t)blockIdx.y * units;
+  const uint32_t col = u / nw, w = u - col * nw;
+  const int a = (int)(col / (uint32_t)f.ny), b = (int)(col - (uint32_t)a * f.ny);
+  uint64_t d = 0;
+  for (int da = -1; da <= 1; ++da) {
+    const int ia = a + da;
+    if (ia < 0 || ia >= f.nx) continue;
+    for (int db = -1; db <= 1; ++db) {
+      const int ib = b + db;
+      if (ib < 0 || ib >= f.ny) continue;
+      const uint64_t* m = masks + ((size_t)ia * f.ny + ib) * nw;
+      const uint64_t m0 = m[w];
+      const uint64_t lo = w > 0 ? m[w - 1] : 0ull;
+      const uint64_t hi = w + 1 < nw ? m[w + 1] : 0ull;
+      d |= m0 | (m0 << 1) | (lo >> 63) | (m0 >> 1) | (hi << 63);
+    }
+  }
+  const int valid = f.nz - 64 * (int)w;   // nodes of this word inside the column
+  if (valid < 64) d &= (1ull << valid) - 1ull;
+  uint8_t* p = st + (size_t)col * f.nz + 64 * w;
+  while (d) {
+    const int bit = __ffsll((unsigned long long)d) - 1;
+    d &= d - 1ull;
+    const uint8_t sv = p[bit];
+    if (!(sv & ST_EVAL)) p[bit] = sv | ST_PEND;
+  }
+}
+
+size_t b0_mask_words(Lat f) { return (size_t)f.nx * f.ny * (size_t)((f.nz + 63) / 64); }
+
+void launch_select_b0(uint8_t* st, Lat f, int frames, uint64_t* masks, uint32_t* counts,
+                      int count_stride, hipStream_t s) {
+  const size_t units = b0_mask_words(f);
+  if (!units) return;
+  const unsigned gb = (unsigned)((units + 255) / 256);
+  hipLaunchKernelGGL(k_b0_masks, dim3(gb, frames), dim3(256), 0, s, st, f, masks, counts,
+                     count_stride);
+  hipLaunchKernelGGL(k_select_masks, dim3((unsigned)((units + 255) / 256), frames), dim3(256), 0, s,
+                     st, f, masks);
 }
 
 // ------------------------------------------------------------------ compaction
