@@ -449,6 +449,155 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_h16(GemmArgs a) {
   }
 }
 
+// ------------------------------------------------------------------ FP32 from FP16 x 3
+// An FP32-accurate product on the FP16 MFMA (v_mfma_f32_32x32x16_f16): every operand x
+// is split into x_hi = f16(x) and x_lo = f16((x - x_hi) * 2^11), and
+//   sum_k a w = sum_k a_hi w_hi + 2^-11 sum_k (a_hi w_lo + a_lo w_hi)
+// up to the dropped a_lo w_lo term (relative 2^-22), with the two sums in separate FP32
+// accumulators.  A arrives as FP32 and is split while it is staged into LDS; W arrives as
+// its hi / lo copies (W, Wlo).  Values must lie in the binary16 range.  BK = 32; every
+// tile walks k in the same order.
+template <int BM, int BN, int WM, int WN, int MINB, int NT = 256>
+__global__ void __launch_bounds__(NT, MINB) k_gemm_x3(GemmArgs a) {
+  constexpr int BK = 32;
+  constexpr int LD = BK + 8;   // halves per LDS row
+  constexpr int TI = BM / WM / 32, TJ = BN / WN / 32;
+  // per stage: A hi, A lo, W hi, W lo
+  __shared__ __attribute__((aligned(16))) _Float16 smem[2 * 2 * (BM + BN) * LD];
+  auto Ah = [&](int b) { return smem + (size_t)b * 2 * (BM + BN) * LD; };
+  auto Al = [&](int b) { return Ah(b) + BM * LD; };
+  auto Bh = [&](int b) { return Ah(b) + 2 * BM * LD; };
+  auto Bl = [&](int b) { return Ah(b) + 2 * BM * LD + BN * LD; };
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  int rt, ct;
+  tile_of_block(rt, ct);
+  const int m0 = rt * BM, n0 = ct * BN;
+  const int M = a.M_dev ? min(a.M, (int)*a.M_dev) : a.M;
+  if (m0 >= M) return;
+  const int K = a.K1 + a.K2;
+  const int nk = K / BK;
+  constexpr int A_LOADS = BM * (BK / 4) / NT;   // f32x4 per thread
+  constexpr int B_LOADS = BN * (BK / 8) / NT;   // u32x4 (8 halves) per thread, each of hi / lo
+  f32x4 ra[A_LOADS];
+  u32x4 rbh[B_LOADS], rbl[B_LOADS];
+  const float* A1 = reinterpret_cast<const float*>(a.A1);
+  const float* A2 = reinterpret_cast<const float*>(a.A2);
+  const uint16_t* Wh = reinterpret_cast<const uint16_t*>(a.W);
+  const uint16_t* Wl = reinterpret_cast<const uint16_t*>(a.Wlo);
+
+  auto gload = [&](int kt) {
+    const int k0 = kt * BK;
+    const float* src;
+    int ld, kk0;
+    if (k0 < a.K1) {
+      src = A1;
+      ld = a.lda1;
+      kk0 = k0;
+    } else {
+      src = A2;
+      ld = a.lda2;
+      kk0 = k0 - a.K1;
+    }
+#pragma unroll
+    for (int i = 0; i < A_LOADS; ++i) {
+      const int e = tid + NT * i;
+      const int row = e >> 3, c4 = e & 7;
+      const int gm = m0 + row;
+      ra[i] = gm < M ? *reinterpret_cast<const f32x4*>(src + (size_t)gm * ld + kk0 + 4 * c4)
+                     : (f32x4){0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int i = 0; i < B_LOADS; ++i) {
+      const int e = tid + NT * i;
+      const int row = e >> 2, c8 = e & 3;
+      const size_t o = (size_t)(n0 + row) * a.ldw + k0 + 8 * c8;
+      rbh[i] = *reinterpret_cast<const u32x4*>(Wh + o);
+      rbl[i] = *reinterpret_cast<const u32x4*>(Wl + o);
+    }
+  };
+  auto sstore = [&](int b) {
+    _Float16* ah = Ah(b);
+    _Float16* al = Al(b);
+#pragma unroll
+    for (int i = 0; i < A_LOADS; ++i) {
+      const int e = tid + NT * i;
+      const int at = (e >> 3) * LD + 4 * (e & 7);
+      typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+      h4 hi, lo;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const _Float16 x = (_Float16)ra[i][q];
+        hi[q] = x;
+        lo[q] = (_Float16)((ra[i][q] - (float)x) * 2048.f);
+      }
+      *reinterpret_cast<h4*>(ah + at) = hi;
+      *reinterpret_cast<h4*>(al + at) = lo;
+    }
+#pragma unroll
+    for (int i = 0; i < B_LOADS; ++i) {
+      const int e = tid + NT * i;
+      const int at = (e >> 2) * LD + 8 * (e & 3);
+      *reinterpret_cast<u32x4*>(Bh(b) + at) = rbh[i];
+      *reinterpret_cast<u32x4*>(Bl(b) + at) = rbl[i];
+    }
+  };
+
+  f32x16 am[TI][TJ], ac[TI][TJ];
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) am[i][j][r] = ac[i][j][r] = 0.f;
+
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  const int h = lane >> 5, l32 = lane & 31;
+  const int wrow = wm * (BM / WM), wcol = wn * (BN / WN);
+  for (int kt = 0; kt < nk; ++kt) {
+    const int b = kt & 1;
+    const bool more = kt + 1 < nk;
+    if (more) gload(kt + 1);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 16) {
+      f16x8 ahv[TI], alv[TI], bhv[TJ], blv[TJ];
+#pragma unroll
+      for (int i = 0; i < TI; ++i) {
+        const int at = (wrow + 32 * i + l32) * LD + kk + 8 * h;
+        ahv[i] = *reinterpret_cast<const f16x8*>(Ah(b) + at);
+        alv[i] = *reinterpret_cast<const f16x8*>(Al(b) + at);
+      }
+#pragma unroll
+      for (int j = 0; j < TJ; ++j) {
+        const int at = (wcol + 32 * j + l32) * LD + kk + 8 * h;
+        bhv[j] = *reinterpret_cast<const f16x8*>(Bh(b) + at);
+        blv[j] = *reinterpret_cast<const f16x8*>(Bl(b) + at);
+      }
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) {
+          am[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ahv[i], bhv[j], am[i][j], 0, 0, 0);
+          ac[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ahv[i], blv[j], ac[i][j], 0, 0, 0);
+          ac[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(alv[i], bhv[j], ac[i][j], 0, 0, 0);
+        }
+    }
+    if (more) sstore(b ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) {
+      f32x16 v;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v[r] = am[i][j][r] + ac[i][j][r] * (1.f / 2048.f);
+      store_block<FMT_F32>(a, v, m0 + wrow + 32 * i, n0 + wcol + 32 * j, lane, M);
+    }
+}
+
 // Copies the first K columns of a row-major [N][ldw_src] fp32 weight matrix into a
 // dense [N][K] operand matrix of format fmt (FMT_*); FMT_F16 flags values outside the
 // binary16 range in *ovf.
@@ -463,6 +612,10 @@ __global__ void k_pack_weights(const float* __restrict__ W, int N, int ldw_src, 
   } else if (fmt == FMT_F16) {
     reinterpret_cast<uint16_t*>(dst)[i] = f32_to_f16_bits(v);
     if (!(__builtin_fabsf(v) <= kF16Max) && ovf) atomicOr(ovf, 1u);
+  } else if (fmt == FMT_F16LO) {
+    // the residual of the binary16 copy, scaled by 2^11 (FP16 x 3 products)
+    const _Float16 hi = (_Float16)v;
+    reinterpret_cast<uint16_t*>(dst)[i] = f32_to_f16_bits((v - (float)hi) * 2048.f);
   } else {
     reinterpret_cast<float*>(dst)[i] = v;
   }
@@ -713,6 +866,15 @@ int launch_gemm(const GemmArgs& a, int precision, int tile_m, hipStream_t s) {
       else if (bm == 128) PIFU_F32(128, 64, 4, 1, 2);
       else PIFU_F32(256, 64, 4, 1, 1);
     }
+    return 0;
+  }
+  if (precision == PREC_F32X3) {
+    // one shape for every launch: 64 x 64 tiles of four 32 x 32 waves keep four waves per
+    // SIMD (a 128 x 128 tile holds both accumulator sets in 369 registers, one wave per
+    // SIMD, and ran 1.3-1.7x slower at every band size measured)
+    if ((a.K1 % 32) || (a.K2 % 32)) return -1;
+    hipLaunchKernelGGL((k_gemm_x3<64, 64, 2, 2, 2>), dim3((a.M + 63) / 64, a.N / 64), dim3(256), 0,
+                       s, a);
     return 0;
   }
   if (bm == 32) bm = 64;   // the 32-point tile exists for FP32 only

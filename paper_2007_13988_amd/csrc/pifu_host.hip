@@ -178,6 +178,7 @@ struct MlpPrep {
   MLPDesc d;
   float* Wp32[PIFU_MAX_LAYERS];      // FP32 operand copies [N][Kp]
   uint16_t* Wp16[PIFU_MAX_LAYERS];   // 16-bit operand copies (BF16 or FP16 runs, that format)
+  uint16_t* Wlo16[PIFU_MAX_LAYERS];  // FP16 runs: scaled binary16 residuals (FP16 x 3 band)
   uint8_t* Wp8[PIFU_MAX_LAYERS];     // FP8 e4m3 operand copies (FP8 runs), scaled by 1/w_scale
   uint32_t* amax;                    // device: per-layer max |W| (float bits), FP8 runs
   float w_scale[PIFU_MAX_LAYERS];    // FP8 weight scale amax/448 (host, after pack)
@@ -190,6 +191,7 @@ struct MlpPrep {
   int hoist_off[PIFU_MAX_LAYERS];    // offset of layer l in the stacked outputs, -1 if none
   float* Wf32 = nullptr;             // [NP][C]
   uint16_t* Wf16 = nullptr;          // [NP][C] (BF16 or FP16 runs)
+  uint16_t* Wflo16 = nullptr;        // [NP][C] residuals (FP16 runs)
   float* bf = nullptr;               // [NP] biases of those layers
   float* wz = nullptr;               // [widths[0]] layer 0's weights of z, contiguous
 };
@@ -224,6 +226,7 @@ void carve_mlp(Carver& cv, const pifu_mlp* m, int precision, MlpPrep& p) {
     p.Wp32[l] = cv.take<float>(n);
     p.Wp16[l] = precision == PIFU_PREC_BF16 || precision == PIFU_PREC_FP16 ? cv.take<uint16_t>(n)
                                                                            : nullptr;
+    p.Wlo16[l] = precision == PIFU_PREC_FP16 ? cv.take<uint16_t>(n) : nullptr;
     p.Wp8[l] = precision == PIFU_PREC_FP8 ? cv.take<uint8_t>(n) : nullptr;
     p.max_hidden = std::max(p.max_hidden, m->widths[l]);
     const float amax_a = m->fp8_amax[l] > 0.f ? m->fp8_amax[l] : 16.f;
@@ -243,6 +246,7 @@ void carve_mlp(Carver& cv, const pifu_mlp* m, int precision, MlpPrep& p) {
     p.Wf32 = cv.take<float>(n);
     p.Wf16 = precision == PIFU_PREC_BF16 || precision == PIFU_PREC_FP16 ? cv.take<uint16_t>(n)
                                                                         : nullptr;
+    p.Wflo16 = precision == PIFU_PREC_FP16 ? cv.take<uint16_t>(n) : nullptr;
     p.bf = cv.take<float>(p.NP);
     p.wz = cv.take<float>(m->widths[0]);
   }
@@ -254,6 +258,8 @@ int pack_mlp(MlpPrep& p, pifu_ctx* ctx, hipStream_t s, uint32_t* ovf) {
     launch_pack_weights(p.d.W[l], p.d.widths[l], p.d.in_w[l], p.Kp[l], p.Wp32[l], FMT_F32, s);
     if (p.Wp16[l])
       launch_pack_weights(p.d.W[l], p.d.widths[l], p.d.in_w[l], p.Kp[l], p.Wp16[l], f16, s, ovf);
+    if (p.Wlo16[l])
+      launch_pack_weights(p.d.W[l], p.d.widths[l], p.d.in_w[l], p.Kp[l], p.Wlo16[l], FMT_F16LO, s);
     if (p.Wp8[l])
       launch_pack_fp8(p.d.W[l], p.d.widths[l], p.d.in_w[l], p.Kp[l], p.amax + l, p.Wp8[l], s);
     if (p.hoist_off[l] >= 0) {
@@ -265,6 +271,9 @@ int pack_mlp(MlpPrep& p, pifu_ctx* ctx, hipStream_t s, uint32_t* ovf) {
       if (p.Wf16)
         launch_pack_weights(p.d.W[l] + fcol, p.d.widths[l], p.d.in_w[l], C, p.Wf16 + off * C, f16, s,
                             ovf);
+      if (p.Wflo16)
+        launch_pack_weights(p.d.W[l] + fcol, p.d.widths[l], p.d.in_w[l], C, p.Wflo16 + off * C,
+                            FMT_F16LO, s);
       HIP_TRY(hipMemcpyAsync(p.bf + off, p.d.b[l], sizeof(float) * p.d.widths[l],
                              hipMemcpyDeviceToDevice, s));
       if (l == 0)   // the z column of layer 0 (input [f; z])
@@ -453,8 +462,9 @@ struct Seg {
 // Algorithmic HBM bytes of one GEMM launch: each operand read once, the output written
 // once (A and C in the launch's activation types, W in its operand type).
 double gemm_bytes(const GemmArgs& g, int prec) {
-  const double ea = prec == PIFU_PREC_FP32 ? 4.0 : 2.0;
-  const double ew = prec == PIFU_PREC_FP32 ? 4.0 : prec == PIFU_PREC_FP8 ? 1.0 : 2.0;
+  const bool f32a = prec == PIFU_PREC_FP32 || prec == PREC_F32X3;   // FP32 activations
+  const double ea = f32a ? 4.0 : 2.0;
+  const double ew = f32a ? 4.0 : prec == PIFU_PREC_FP8 ? 1.0 : 2.0;   // X3: hi + lo copies
   const double K = (double)g.K1 + g.K2, M = g.M, N = g.N;
   double b = M * K * ea + N * K * ew + M * N * (g.c_bf16 ? 2.0 : 4.0);
   if (g.rowadd) b += M * N * 4.0;
@@ -467,6 +477,7 @@ int gemm_kind(int prec) {
   return prec == PIFU_PREC_FP32   ? PIFU_KERN_GEMM_F32
          : prec == PIFU_PREC_BF16 ? PIFU_KERN_GEMM_BF16
          : prec == PIFU_PREC_FP16 ? PIFU_KERN_GEMM_F16
+         : prec == PREC_F32X3     ? PIFU_KERN_GEMM_F16X3
                                   : PIFU_KERN_GEMM_FP8;
 }
 
@@ -487,11 +498,13 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
   const pifu_field* f = fp.f;
   const MLPDesc& d = mp.d;
   const int C = f->C;
-  const bool b16 = prec != PIFU_PREC_FP32;
-  const int hf = h16_fmt(prec);
-  // a 16-bit run needs the operand copies of its own format
+  const bool x3 = prec == PREC_F32X3;   // FP32 activations, split-FP16 products
+  const bool b16 = prec != PIFU_PREC_FP32 && !x3;
+  const int hf = x3 ? FMT_F32 : h16_fmt(prec);
+  // a 16-bit run needs the operand copies of its own format; X3 the FP16 hi / lo copies
   if ((prec == PIFU_PREC_BF16 || prec == PIFU_PREC_FP16) && mp.prec != prec)
     return PIFU_ERR_UNSUPPORTED;
+  if (x3 && mp.prec != PIFU_PREC_FP16) return PIFU_ERR_UNSUPPORTED;
   uint32_t* ovf = prec == PIFU_PREC_FP16 ? e.counters + C_OVF : nullptr;
   Seg one{0, n, f->feat, src.base_sub};
   if (!segs) {
@@ -524,7 +537,8 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
     std::memset(&g, 0, sizeof(g));
     g.A1 = ew.feat;
     g.K1 = g.lda1 = C;
-    g.W = b16 ? (const void*)mp.Wf16 : (const void*)mp.Wf32;
+    g.W = b16 || x3 ? (const void*)mp.Wf16 : (const void*)mp.Wf32;
+    g.Wlo = x3 ? (const void*)mp.Wflo16 : nullptr;
     g.ldw = C;
     g.bias = mp.bf;
     g.C = ew.Pcol;
@@ -548,6 +562,7 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
       g.A1 = prev;
       g.K1 = g.lda1 = d.widths[l - 1];
       g.W = layer_weights(mp, prec, l);
+      g.Wlo = x3 ? (const void*)mp.Wlo16[l] : nullptr;
       g.ldw = mp.Kp[l];
       g.Wf = d.W[l];
       g.ldwf = d.in_w[l];
@@ -620,6 +635,7 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
         }
       }
       g.W = layer_weights(mp, prec, l);
+      g.Wlo = x3 ? (const void*)mp.Wlo16[l] : nullptr;
       g.a_inv_scale = prec == PIFU_PREC_FP8 ? 1.f / mp.a_scale[l] : 1.f;
       g.ldw = mp.Kp[l];
       g.Wf = d.W[l];
@@ -687,8 +703,11 @@ int post_full(EvalCtx& e, const FieldPrep& fp, const PointSrc& src, const float*
       nb_run = nb;
       launch_gather_u32(list, ew.band_pos, nb, ew.band_nodes, e.s);
       const Seg bseg{0, nb, F, src.base_sub};
-      r = run_mlp(e, fp, fp.mlp, PIFU_PREC_FP32, src, ew.band_nodes, nb, ew, ew.band_logit,
-                  ew.band_lab, nullptr, &bseg, 1);
+      // an FP16 run's band: every value passed the binary16 range check (no overflow), so
+      // the FP32-accurate split-FP16 products apply
+      const int bprec = e.precision == PIFU_PREC_FP16 ? PREC_F32X3 : PIFU_PREC_FP32;
+      r = run_mlp(e, fp, fp.mlp, bprec, src, ew.band_nodes, nb, ew, ew.band_logit, ew.band_lab,
+                  nullptr, &bseg, 1);
       if (r) return r;
       launch_scatter_results(ew.band_pos, nb, ew.band_logit, ew.band_lab, logit, lab, e.s);
       if (st) st->band_fp32 += nb;

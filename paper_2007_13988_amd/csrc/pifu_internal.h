@@ -76,8 +76,12 @@ __host__ __device__ inline uint16_t f32_to_f16_bits(float x) {
 // Largest finite binary16 magnitude: a value above it does not convert faithfully.
 constexpr float kF16Max = 65504.f;
 
-// Storage format of an MLP operand or activation array.
-enum { FMT_F32 = 0, FMT_BF16 = 1, FMT_F16 = 2 };
+// Storage format of an MLP operand or activation array (FMT_F16LO: the binary16 residual
+// x - f16(x), scaled by 2^11, of an FP16 x 3 operand).
+enum { FMT_F32 = 0, FMT_BF16 = 1, FMT_F16 = 2, FMT_F16LO = 3 };
+// Internal run precision: FP32-accurate GEMMs from three FP16 MFMA products per k step
+// (operands split into binary16 hi and scaled lo parts); FP32 activations.
+constexpr int PREC_F32X3 = 16;
 // The 16-bit format a run precision stores activations in (FP8 stages bf16 values).
 inline int h16_fmt(int precision) {
   return precision == PIFU_PREC_FP32 ? FMT_F32 : precision == PIFU_PREC_FP16 ? FMT_F16 : FMT_BF16;
@@ -211,6 +215,8 @@ struct GemmArgs {
   const uint32_t* M_dev;
   // FP16 (nullable): set to 1 when a value written as binary16 exceeds its range
   uint32_t* ovf;
+  // PREC_F32X3: the lo copy of W (W holds the hi copy)
+  const void* Wlo;
 };
 
 // ------------------------------------------------------------------ per-column hoisting

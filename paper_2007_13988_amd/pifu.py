@@ -77,7 +77,8 @@ class PifuKernelProfile(C.Structure):
                 ("bytes", C.c_double)]
 
 
-KERN = {"gemm_f32": 0, "gemm_bf16": 1, "gemm_fp8": 2, "gather": 3, "head": 4, "gemm_f16": 5}
+KERN = {"gemm_f32": 0, "gemm_bf16": 1, "gemm_fp8": 2, "gather": 3, "head": 4, "gemm_f16": 5,
+        "gemm_f16x3": 6}
 KERN_COUNT = 8
 
 EXPORTS = ["pifu_create", "pifu_destroy", "pifu_status_string",

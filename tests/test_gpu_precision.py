@@ -150,3 +150,27 @@ def test_fp16_overflow_reruns_in_fp32(pifu, case):
     # the same networks unscaled stay in FP16 apart from the band
     g = pifu.occupancy_grid(f32, 6, 4, precision="fp16", band_delta=0.005)
     assert sum(s["band_fp32"] for s in g["stats"]) < 0.5 * sum(s["mlp_points"] for s in g["stats"])
+
+
+@pytest.mark.parametrize("net", ["tiny", "pifu"])
+def test_fp16_band_products_are_fp32_accurate(pifu, net):
+    """An FP16 run re-evaluates its band with FP32-accurate products of binary16 hi / lo
+    operand splits (three FP16 MFMAs per step).  With the band covering every point the
+    logits are those products: their error against the FP64 oracle stays within a small
+    multiple of the FP32 path's and far below the FP64 guard (1e-3)."""
+    if net == "tiny":
+        feat, spec, n = synth.tiny_features(), synth.tiny_mlp(), 100000
+    else:
+        feat, spec, n = synth.pifu_sequence(102, 0), synth.pifu_mlp(), 6000
+    fo = O.Field("mlp", feat=feat, mlp=spec)
+    fg = pifu.DeviceField.mlp_field(feat, spec)
+    pts = np.clip(synth.precision_points(n, 411) * 0.9, -1, 1).astype(np.float32).astype(np.float64)
+    ref = O.field_logit(fo, pts)
+    l32, _ = pifu.eval_points(fg, pts, precision="fp32", guard_logit=0.0, band_delta=0.0)
+    lx3, _ = pifu.eval_points(fg, pts, precision="fp16", guard_logit=0.0, band_delta=0.5)
+    e32 = np.abs(l32.cpu().numpy().astype(np.float64) - ref)
+    ex3 = np.abs(lx3.cpu().numpy().astype(np.float64) - ref)
+    print(f"{net}: logit error max FP32 {e32.max():.3e} split-FP16 {ex3.max():.3e}; "
+          f"mean {e32.mean():.3e} / {ex3.mean():.3e}")
+    assert ex3.max() < 1e-4
+    assert ex3.max() < 8 * e32.max() + 1e-6
