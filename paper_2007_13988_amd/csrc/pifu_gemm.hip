@@ -10,6 +10,8 @@
 // k values [c*h, c*h + c) of the group (c = elements per lane per MFMA) so that a
 // lane's operand is one contiguous 16-byte LDS read.  A and B use the same
 // permutation, so the sum over k is unchanged.
+#include <hip/hip_ext.h>
+
 #include "pifu_internal.h"
 
 namespace pifu {
@@ -24,24 +26,23 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // Tile of this workgroup.  Workgroups are dispatched in order x + gridDim.x * y and dealt
-// round-robin to the 8 XCDs, each with its own L2.  When the row-tile count divides by 8,
+// round-robin to the 8 XCDs, each with its own L2.  The grid's row-tile count is a
+// multiple of 8 (launches round it up; the extra tiles lie past M and exit at once).
 // XCD k takes the row tiles k, k + 8, k + 16, ... in increasing order, with the column
 // tiles of one row tile dispatched next to each other: a row tile of A is fetched from
 // HBM once and its other column tiles read it from the same L2, and the rows a launch
 // covers stay spread over all XCDs (launches whose device-side row count is below the
 // grid's exit their last row tiles on every XCD alike).  The tile set is unchanged.
 __device__ inline void tile_of_block(int& rt, int& ct) {
-  const int nbx = gridDim.x, nby = gridDim.y;
-  if (nbx & 7) {
-    rt = blockIdx.x;
-    ct = blockIdx.y;
-    return;
-  }
-  const int id = blockIdx.x + nbx * blockIdx.y;
+  const int nby = gridDim.y;
+  const int id = blockIdx.x + gridDim.x * blockIdx.y;
   const int q = id >> 3;
   rt = (q / nby) * 8 + (id & 7);
   ct = q - (q / nby) * nby;
 }
+
+// Row tiles of a launch over M rows in tiles of bm, rounded up to a multiple of 8.
+inline unsigned row_tiles(int M, int bm) { return (unsigned)(((M + bm - 1) / bm + 7) / 8 * 8); }
 
 __device__ inline float act_apply(float v, int act) {
   if (act == PIFU_ACT_RELU) return v > 0.f ? v : 0.f;
@@ -805,24 +806,33 @@ void launch_pack_fp8(const float* W, int N, int ldw, int K, uint32_t* amax_bits,
                      amax_bits, dst);
 }
 
+// A GEMM launch, carrying the caller's event pair when it has one.
+#define PIFU_GO(K, G, B, SH, ST, ...)                                                           \
+  do {                                                                                           \
+    if (ev0)                                                                                     \
+      hipExtLaunchKernelGGL(K, G, B, SH, ST, ev0, ev1, 0, __VA_ARGS__);                          \
+    else                                                                                         \
+      hipLaunchKernelGGL(K, G, B, SH, ST, __VA_ARGS__);                                          \
+  } while (0)
+
 // Tile shapes per point tile BM (the autotuned parameter) and output tile BN:
 //   BM 64: waves 1x4 (BN 128) / 2x2 (BN 64); BM 128: 2x2 / 4x1; BM 256: 2x2 / 4x1.
 // Every variant walks k in the same order, so results do not depend on BM.
 #define PIFU_F32(BM_, BN_, WM_, WN_, MB_) \
-  hipLaunchKernelGGL((k_gemm_f32<BM_, BN_, WM_, WN_, MB_>), dim3((a.M + BM_ - 1) / BM_, a.N / BN_), \
+  PIFU_GO((k_gemm_f32<BM_, BN_, WM_, WN_, MB_>), dim3(row_tiles(a.M, BM_), a.N / BN_), \
                      dim3(256), 0, s, a)
 #define PIFU_H16(BM_, BN_, WM_, WN_, MB_, F16_)                                                  \
   do {                                                                                           \
     if (a.c_bf16)                                                                                \
-      hipLaunchKernelGGL((k_gemm_h16<BM_, BN_, WM_, WN_, MB_, true, F16_>),                      \
-                         dim3((a.M + BM_ - 1) / BM_, a.N / BN_), dim3(256), 0, s, a);             \
+      PIFU_GO((k_gemm_h16<BM_, BN_, WM_, WN_, MB_, true, F16_>),                      \
+                         dim3(row_tiles(a.M, BM_), a.N / BN_), dim3(256), 0, s, a);             \
     else                                                                                         \
-      hipLaunchKernelGGL((k_gemm_h16<BM_, BN_, WM_, WN_, MB_, false, F16_>),                     \
-                         dim3((a.M + BM_ - 1) / BM_, a.N / BN_), dim3(256), 0, s, a);             \
+      PIFU_GO((k_gemm_h16<BM_, BN_, WM_, WN_, MB_, false, F16_>),                     \
+                         dim3(row_tiles(a.M, BM_), a.N / BN_), dim3(256), 0, s, a);             \
   } while (0)
 
 template <bool F16>
-void launch_h16(const GemmArgs& a, int bm, hipStream_t s) {
+void launch_h16(const GemmArgs& a, int bm, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   const bool bn128 = (a.N % 128) == 0;
   if (bn128) {
     if (bm == 64) PIFU_H16(64, 128, 1, 4, 2, F16);
@@ -830,11 +840,11 @@ void launch_h16(const GemmArgs& a, int bm, hipStream_t s) {
     else if (a.N % 256 == 0) {
       // 256 x 256 tile, 8 waves: half the L2 traffic per FLOP of the 128-wide tiles
       if (a.c_bf16)
-        hipLaunchKernelGGL((k_gemm_h16<256, 256, 2, 4, 1, true, F16, 512>),
-                           dim3((a.M + 255) / 256, a.N / 256), dim3(512), 0, s, a);
+        PIFU_GO((k_gemm_h16<256, 256, 2, 4, 1, true, F16, 512>),
+                           dim3(row_tiles(a.M, 256), a.N / 256), dim3(512), 0, s, a);
       else
-        hipLaunchKernelGGL((k_gemm_h16<256, 256, 2, 4, 1, false, F16, 512>),
-                           dim3((a.M + 255) / 256, a.N / 256), dim3(512), 0, s, a);
+        PIFU_GO((k_gemm_h16<256, 256, 2, 4, 1, false, F16, 512>),
+                           dim3(row_tiles(a.M, 256), a.N / 256), dim3(512), 0, s, a);
     } else PIFU_H16(256, 128, 2, 2, 1, F16);
   } else {
     if (bm == 64) PIFU_H16(64, 64, 2, 2, 2, F16);
@@ -844,7 +854,8 @@ void launch_h16(const GemmArgs& a, int bm, hipStream_t s) {
 }
 #undef PIFU_H16
 
-int launch_gemm(const GemmArgs& a, int precision, int tile_m, hipStream_t s) {
+int launch_gemm(const GemmArgs& a, int precision, int tile_m, hipStream_t s, hipEvent_t ev0,
+                hipEvent_t ev1) {
   if (a.M <= 0) return 0;
   const bool bn128 = (a.N % 128) == 0;
   if (!bn128 && (a.N % 64) != 0) return -1;
@@ -853,7 +864,7 @@ int launch_gemm(const GemmArgs& a, int precision, int tile_m, hipStream_t s) {
     if ((a.K1 % 32) || (a.K2 % 32)) return -1;
     if (bm == 32) {
       // tiny launches: 32 x 64 tiles of two 32 x 32 waves spread the work over more CUs
-      hipLaunchKernelGGL((k_gemm_f32<32, 64, 1, 2, 2, 128>), dim3((a.M + 31) / 32, a.N / 64),
+      PIFU_GO((k_gemm_f32<32, 64, 1, 2, 2, 128>), dim3(row_tiles(a.M, 32), a.N / 64),
                          dim3(128), 0, s, a);
       return 0;
     }
@@ -873,15 +884,15 @@ int launch_gemm(const GemmArgs& a, int precision, int tile_m, hipStream_t s) {
     // SIMD (a 128 x 128 tile holds both accumulator sets in 369 registers, one wave per
     // SIMD, and ran 1.3-1.7x slower at every band size measured)
     if ((a.K1 % 32) || (a.K2 % 32)) return -1;
-    hipLaunchKernelGGL((k_gemm_x3<64, 64, 2, 2, 2>), dim3((a.M + 63) / 64, a.N / 64), dim3(256), 0,
+    PIFU_GO((k_gemm_x3<64, 64, 2, 2, 2>), dim3(row_tiles(a.M, 64), a.N / 64), dim3(256), 0,
                        s, a);
     return 0;
   }
   if (bm == 32) bm = 64;   // the 32-point tile exists for FP32 only
   if (precision == PIFU_PREC_BF16 || precision == PIFU_PREC_FP16) {
     if ((a.K1 % 64) || (a.K2 % 64)) return -1;
-    if (precision == PIFU_PREC_FP16) launch_h16<true>(a, bm, s);
-    else launch_h16<false>(a, bm, s);
+    if (precision == PIFU_PREC_FP16) launch_h16<true>(a, bm, s, ev0, ev1);
+    else launch_h16<false>(a, bm, s, ev0, ev1);
     return 0;
   }
   if (precision == PIFU_PREC_FP8) {
@@ -890,11 +901,11 @@ int launch_gemm(const GemmArgs& a, int precision, int tile_m, hipStream_t s) {
 #define PIFU_F8(BM_, BN_, WM_, WN_, MB_, BK_)                                                    \
   do {                                                                                           \
     if (a.c_bf16)                                                                                \
-      hipLaunchKernelGGL((k_gemm_fp8<BM_, BN_, WM_, WN_, MB_, true, BK_>),                       \
-                         dim3((a.M + BM_ - 1) / BM_, a.N / BN_), dim3(256), 0, s, a);             \
+      PIFU_GO((k_gemm_fp8<BM_, BN_, WM_, WN_, MB_, true, BK_>),                       \
+                         dim3(row_tiles(a.M, BM_), a.N / BN_), dim3(256), 0, s, a);             \
     else                                                                                         \
-      hipLaunchKernelGGL((k_gemm_fp8<BM_, BN_, WM_, WN_, MB_, false, BK_>),                      \
-                         dim3((a.M + BM_ - 1) / BM_, a.N / BN_), dim3(256), 0, s, a);             \
+      PIFU_GO((k_gemm_fp8<BM_, BN_, WM_, WN_, MB_, false, BK_>),                      \
+                         dim3(row_tiles(a.M, BM_), a.N / BN_), dim3(256), 0, s, a);             \
   } while (0)
     if (k128) {
       if (bn128) {

@@ -44,11 +44,16 @@ struct ProfScope {
   pifu_ctx* c;
   hipStream_t s;
   int idx = -1;
+  bool carry = false;
   // flops/bytes: fixed part; with dev_count, flops_per/bytes_per per unit counted on
-  // the device (copied asynchronously to a pinned slot, read when the call resolves)
+  // the device (copied asynchronously to a pinned slot, read when the call resolves).
+  // carry: the launch itself records the event pair (start(), stop() passed to a
+  // hipExtLaunchKernelGGL, which stamps the kernel's own dispatch: no marker packets
+  // around it); else markers are recorded around the scope.
   ProfScope(pifu_ctx* ctx, hipStream_t st, int kind, double flops, double bytes,
-            const uint32_t* dev_count = nullptr, double flops_per = 0.0, double bytes_per = 0.0)
-      : c(ctx), s(st) {
+            const uint32_t* dev_count = nullptr, double flops_per = 0.0, double bytes_per = 0.0,
+            bool carried = false)
+      : c(ctx), s(st), carry(carried) {
     if (!c || !c->prof_on) return;
     const size_t need = 2 * (c->pending.size() + 1);
     while (c->events.size() < need) {
@@ -66,10 +71,12 @@ struct ProfScope {
       rec.bytes_per = bytes_per;
     }
     c->pending.push_back(rec);
-    (void)hipEventRecord(c->events[idx], s);
+    if (!carry) (void)hipEventRecord(c->events[idx], s);
   }
+  hipEvent_t start() const { return idx >= 0 && carry ? c->events[idx] : nullptr; }
+  hipEvent_t stop() const { return idx >= 0 && carry ? c->events[idx + 1] : nullptr; }
   ~ProfScope() {
-    if (idx >= 0) (void)hipEventRecord(c->events[idx + 1], s);
+    if (idx >= 0 && !carry) (void)hipEventRecord(c->events[idx + 1], s);
   }
 };
 
@@ -550,8 +557,9 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
     {
       const double ea = b16 ? 2.0 : 4.0;
       ProfScope ps(e.ctx, e.s, gemm_kind(prec), 0.0,
-                   (double)mp.NP * C * ea, ncol_dev, 2.0 * mp.NP * C, C * ea + mp.NP * 4.0);
-      if (launch_gemm(g, prec, pick_tile(e, prec, g.N, C, m), e.s)) return PIFU_ERR_UNSUPPORTED;
+                   (double)mp.NP * C * ea, ncol_dev, 2.0 * mp.NP * C, C * ea + mp.NP * 4.0, true);
+      if (launch_gemm(g, prec, pick_tile(e, prec, g.N, C, m), e.s, ps.start(), ps.stop()))
+        return PIFU_ERR_UNSUPPORTED;
     }
     launch_hoist_layer0(ew.Pcol, mp.NP, ew.cid, lst, m, src.nz, mp.wz, d.widths[0], d.hidden_act,
                         ew.hA, d.n_layers > 2 ? hf : FMT_F32, e.s, nullptr, ovf);
@@ -582,8 +590,10 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
       g.c_bf16 = b16 && (l + 2 < d.n_layers);
       g.ovf = ovf;
       {
-        ProfScope ps(e.ctx, e.s, gemm_kind(prec), 2.0 * m * g.N * g.K1, gemm_bytes(g, prec));
-        if (launch_gemm(g, prec, pick_tile(e, prec, g.N, g.K1, m), e.s)) return PIFU_ERR_UNSUPPORTED;
+        ProfScope ps(e.ctx, e.s, gemm_kind(prec), 2.0 * m * g.N * g.K1, gemm_bytes(g, prec), nullptr,
+                     0.0, 0.0, true);
+        if (launch_gemm(g, prec, pick_tile(e, prec, g.N, g.K1, m), e.s, ps.start(), ps.stop()))
+          return PIFU_ERR_UNSUPPORTED;
       }
       prev = out;
       out = (out == ew.hA) ? ew.hB : ew.hA;
@@ -652,8 +662,9 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
       g.ovf = ovf;
       {
         ProfScope ps(e.ctx, e.s, gemm_kind(prec), 2.0 * m * g.N * (g.K1 + g.K2 + g.n_ext),
-                     gemm_bytes(g, prec));
-        if (launch_gemm(g, prec, pick_tile(e, prec, g.N, g.K1 + g.K2, m), e.s))
+                     gemm_bytes(g, prec), nullptr, 0.0, 0.0, true);
+        if (launch_gemm(g, prec, pick_tile(e, prec, g.N, g.K1 + g.K2, m), e.s, ps.start(),
+                        ps.stop()))
           return PIFU_ERR_UNSUPPORTED;
       }
       prev = out;

@@ -253,7 +253,10 @@ __host__ __device__ inline uint8_t f32_to_e4m3(float x) {
   if (code > 0x7e) code = 0x7e;
   return sign | (uint8_t)code;
 }
-int launch_gemm(const GemmArgs& a, int precision, int tile_m, hipStream_t s);
+// ev0/ev1 (nullable): an event pair the launch carries (hipExtLaunchKernelGGL), stamped
+// with the kernel's own start and end
+int launch_gemm(const GemmArgs& a, int precision, int tile_m, hipStream_t s,
+                hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // FP8 operand copy: amax_bits <- max |W| (float bits), dst = e4m3(W * 448 / amax).
 void launch_pack_fp8(const float* W, int N, int ldw, int K, uint32_t* amax_bits, uint8_t* dst,
                      hipStream_t s);
