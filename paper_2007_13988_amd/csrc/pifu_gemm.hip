@@ -456,8 +456,9 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_h16(GemmArgs a) {
 //   sum_k a w = sum_k a_hi w_hi + 2^-11 sum_k (a_hi w_lo + a_lo w_hi)
 // up to the dropped a_lo w_lo term (relative 2^-22), with the two sums in separate FP32
 // accumulators.  A arrives as FP32 and is split while it is staged into LDS; W arrives as
-// its hi / lo copies (W, Wlo).  Values must lie in the binary16 range.  BK = 32; every
-// tile walks k in the same order.
+// its hi / lo copies (W, Wlo).  Values must lie in the binary16 range: an A value outside
+// it sets *a.ovf (the caller then re-runs in FP32).  BK = 32; every tile walks k in the
+// same order.
 template <int BM, int BN, int WM, int WN, int MINB, int NT = 256>
 __global__ void __launch_bounds__(NT, MINB) k_gemm_x3(GemmArgs a) {
   constexpr int BK = 32;
@@ -517,6 +518,7 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_x3(GemmArgs a) {
       rbl[i] = *reinterpret_cast<const u32x4*>(Wl + o);
     }
   };
+  bool big = false;   // an A operand outside the binary16 range (reported through a.ovf)
   auto sstore = [&](int b) {
     _Float16* ah = Ah(b);
     _Float16* al = Al(b);
@@ -531,6 +533,7 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_x3(GemmArgs a) {
         const _Float16 x = (_Float16)ra[i][q];
         hi[q] = x;
         lo[q] = (_Float16)((ra[i][q] - (float)x) * 2048.f);
+        big |= !(__builtin_fabsf(ra[i][q]) <= kF16Max);
       }
       *reinterpret_cast<h4*>(ah + at) = hi;
       *reinterpret_cast<h4*>(al + at) = lo;
@@ -597,6 +600,7 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_x3(GemmArgs a) {
       for (int r = 0; r < 16; ++r) v[r] = am[i][j][r] + ac[i][j][r] * (1.f / 2048.f);
       store_block<FMT_F32>(a, v, m0 + wrow + 32 * i, n0 + wcol + 32 * j, lane, M);
     }
+  if (big && a.ovf) atomicOr(a.ovf, 1u);
 }
 
 // Copies the first K columns of a row-major [N][ldw_src] fp32 weight matrix into a

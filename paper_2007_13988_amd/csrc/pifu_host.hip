@@ -345,14 +345,16 @@ void carve_field(Carver& cv, const pifu_field* f, int precision, FieldPrep& fp) 
   }
 }
 
-// Packs the operand copies of the field's networks.  An FP16 network first clears the
-// call's overflow flag (counters[C_OVF]); its weight copies then report into it.
-int pack_field(FieldPrep& fp, pifu_ctx* ctx, hipStream_t s, uint32_t* counters) {
+// Packs the operand copies of the field's networks.  The binary16 copies of an FP16
+// network report values outside the binary16 range into the call's overflow flag
+// (counters[C_OVF]), which `clear` resets first (once per call).
+int pack_field(FieldPrep& fp, pifu_ctx* ctx, hipStream_t s, uint32_t* counters,
+               bool clear = true) {
   int r = PIFU_OK;
   uint32_t* ovf = nullptr;
   if (fp.has_mlp && fp.mlp.prec == PIFU_PREC_FP16) {
     ovf = counters + C_OVF;
-    HIP_TRY(hipMemsetAsync(ovf, 0, sizeof(uint32_t), s));
+    if (clear) HIP_TRY(hipMemsetAsync(ovf, 0, sizeof(uint32_t), s));
   }
   if (fp.has_mlp) r = pack_mlp(fp.mlp, ctx, s, ovf);
   if (!r && fp.has_sur) r = pack_mlp(fp.sur, ctx, s, nullptr);
@@ -512,7 +514,8 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
   if ((prec == PIFU_PREC_BF16 || prec == PIFU_PREC_FP16) && mp.prec != prec)
     return PIFU_ERR_UNSUPPORTED;
   if (x3 && mp.prec != PIFU_PREC_FP16) return PIFU_ERR_UNSUPPORTED;
-  uint32_t* ovf = prec == PIFU_PREC_FP16 ? e.counters + C_OVF : nullptr;
+  // FP16 conversions and split-FP16 operands report values outside the binary16 range
+  uint32_t* ovf = prec == PIFU_PREC_FP16 || x3 ? e.counters + C_OVF : nullptr;
   Seg one{0, n, f->feat, src.base_sub};
   if (!segs) {
     segs = &one;
@@ -546,6 +549,7 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
     g.K1 = g.lda1 = C;
     g.W = b16 || x3 ? (const void*)mp.Wf16 : (const void*)mp.Wf32;
     g.Wlo = x3 ? (const void*)mp.Wflo16 : nullptr;
+    g.ovf = ovf;
     g.ldw = C;
     g.bias = mp.bf;
     g.C = ew.Pcol;
@@ -696,60 +700,75 @@ int select_near(EvalCtx& e, const float* logit, uint32_t n, float bound, uint32_
 
 // After the run-precision pass: the FP32 band (BF16/FP16/FP8 runs), then the FP64 guard.
 // F is the feature map of the points' frame.  An FP16 run whose call has seen a value
-// outside the binary16 range is re-run whole in FP32 instead of the band.
+// outside the binary16 range is re-run whole in FP32 instead of the band; so is one whose
+// split-FP16 band reports such a value (read back with the guard's count).
 int post_full(EvalCtx& e, const FieldPrep& fp, const PointSrc& src, const float* F,
               const uint32_t* list, uint32_t n, const EvalWs& ew, float* logit, uint8_t* lab,
               pifu_level_stats* st) {
   const pifu_field* f = fp.f;
   int r = PIFU_OK;
   const Seg one{0, n, F, src.base_sub};
-  uint32_t nb_run = 0;   // points re-run in FP32 by the band
+  uint32_t nb_run = 0;   // points re-run by the band
   bool over = false;     // FP16 overflow: all n points re-run in FP32
+  const bool f16 = e.precision == PIFU_PREC_FP16;
+  auto rerun_fp32 = [&]() {
+    int q = run_mlp(e, fp, fp.mlp, PIFU_PREC_FP32, src, list, n, ew, logit, lab, nullptr, &one, 1);
+    if (!q && st) st->band_fp32 += n - nb_run;
+    nb_run = 0;
+    return q;
+  };
   if (e.precision != PIFU_PREC_FP32 && e.band > 0.f) {
     uint32_t nb = 0;
     r = select_near(e, logit, n, e.band, ew.band_pos, &nb);
     if (r) return r;
-    over = e.precision == PIFU_PREC_FP16 && e.ctx->host_counters[C_OVF] != 0;
+    over = f16 && e.ctx->host_counters[C_OVF] != 0;
     if (nb && !over) {
       nb_run = nb;
       launch_gather_u32(list, ew.band_pos, nb, ew.band_nodes, e.s);
       const Seg bseg{0, nb, F, src.base_sub};
-      // an FP16 run's band: every value passed the binary16 range check (no overflow), so
-      // the FP32-accurate split-FP16 products apply
-      const int bprec = e.precision == PIFU_PREC_FP16 ? PREC_F32X3 : PIFU_PREC_FP32;
+      // an FP16 run's band: FP32-accurate split-FP16 products (operands inside the
+      // binary16 range, which the FP16 pass checked; the band reports its own)
+      const int bprec = f16 ? PREC_F32X3 : PIFU_PREC_FP32;
       r = run_mlp(e, fp, fp.mlp, bprec, src, ew.band_nodes, nb, ew, ew.band_logit, ew.band_lab,
                   nullptr, &bseg, 1);
       if (r) return r;
       launch_scatter_results(ew.band_pos, nb, ew.band_logit, ew.band_lab, logit, lab, e.s);
       if (st) st->band_fp32 += nb;
     }
-  } else if (e.precision == PIFU_PREC_FP16) {
+  } else if (f16) {
     r = read_counters(e, C_OVF + 1);
     if (r) return r;
     over = e.ctx->host_counters[C_OVF] != 0;
   }
   if (over) {
-    r = run_mlp(e, fp, fp.mlp, PIFU_PREC_FP32, src, list, n, ew, logit, lab, nullptr, &one, 1);
+    r = rerun_fp32();
     if (r) return r;
-    if (st) st->band_fp32 += n;
   }
-  if (e.guard > 0.f) {
-    uint32_t gn = 0;
-    if (e.precision != PIFU_PREC_FP32 && e.band > e.guard && !over) {
-      // every point with |logit| < guard lies inside the band and now holds its FP32
-      // result: the guard picks from the band's results only
-      if (nb_run) r = select_near(e, ew.band_logit, nb_run, e.guard, ew.glist, &gn, ew.band_pos);
-    } else {
-      r = select_near(e, logit, n, e.guard, ew.glist, &gn);
+  if (!(e.guard > 0.f)) {
+    if (f16 && nb_run) {   // no guard read-back to carry the band's overflow report
+      r = read_counters(e, C_OVF + 1);
+      if (!r && e.ctx->host_counters[C_OVF]) r = rerun_fp32();
     }
-    if (r) return r;
-    run_guard64(src, list, ew.glist, gn, fp.mlp.d, F, f->H, f->W, f->C, logit, lab, ew.g64,
-                ew.chunk64, !e.g64_packed, e.s);
-    if (gn) e.g64_packed = true;
-    if (st) st->guard_fp64 += gn;
-    r = check_launch();
+    return r;
   }
-  return r;
+  uint32_t gn = 0;
+  if (e.precision != PIFU_PREC_FP32 && e.band > e.guard && !over) {
+    // every point with |logit| < guard lies inside the band and now holds its FP32
+    // result: the guard picks from the band's results only
+    if (nb_run) r = select_near(e, ew.band_logit, nb_run, e.guard, ew.glist, &gn, ew.band_pos);
+    if (!r && f16 && nb_run && e.ctx->host_counters[C_OVF]) {
+      r = rerun_fp32();
+      if (!r) r = select_near(e, logit, n, e.guard, ew.glist, &gn);
+    }
+  } else {
+    r = select_near(e, logit, n, e.guard, ew.glist, &gn);
+  }
+  if (r) return r;
+  run_guard64(src, list, ew.glist, gn, fp.mlp.d, F, f->H, f->W, f->C, logit, lab, ew.g64,
+              ew.chunk64, !e.g64_packed, e.s);
+  if (gn) e.g64_packed = true;
+  if (st) st->guard_fp64 += gn;
+  return check_launch();
 }
 
 // Full-network evaluation: run precision, then the FP32 band, then the FP64 guard.
@@ -819,7 +838,7 @@ int compact_count(EvalCtx& e, const uint8_t* st, size_t n, uint8_t mask, uint8_t
   launch_compact(st, n, mask, val, scratch, e.counters + C_TOTAL, out, cap, mode, f, e.s);
   int r = check_launch();
   if (r) return r;
-  r = read_counters(e, C_SHADOW + 1);   // the level's other counters come back with the count
+  r = read_counters(e, C_OVF + 1);   // the level's other counters come back with the count
   if (r) return r;
   *count = e.ctx->host_counters[C_TOTAL];
   return PIFU_OK;
@@ -1025,7 +1044,9 @@ int plan_render(const pifu_field* occ, const pifu_field* col, const pifu_render_
   g.hitlist = cv.take<uint32_t>(ncol);
   g.hitpts = cv.take<float4>(ncol);
   carve_field(cv, occ, o->precision, g.fp);
-  carve_field(cv, col, PIFU_PREC_FP32, g.cp);
+  // FP16 runs colour the hits with FP32-accurate split-FP16 products (binary16 hi / lo
+  // copies of the colour network); other runs in FP32
+  carve_field(cv, col, o->precision == PIFU_PREC_FP16 ? PIFU_PREC_FP16 : PIFU_PREC_FP32, g.cp);
   int C = 0, mh = 0;
   if (g.fp.has_mlp) {
     C = occ->C;
@@ -1184,7 +1205,9 @@ int32_t pifu_render_view(pifu_ctx* ctx, const pifu_field* occ_field, const pifu_
     delete gp;
     return pr;
   }
-  if (int pr = pack_field(g.cp, ctx, s, g.counters)) {
+  // one clear of the overflow flag per call: by the occupancy network's pack when FP16
+  if (int pr = pack_field(g.cp, ctx, s, g.counters,
+                          !(g.fp.has_mlp && g.fp.mlp.prec == PIFU_PREC_FP16))) {
     delete gp;
     return pr;
   }
@@ -1243,8 +1266,15 @@ int32_t pifu_render_view(pifu_ctx* ctx, const pifu_field* occ_field, const pifu_
       ps.mode = 1;
       ps.pts = g.hitpts;
       EvalCtx ec{ctx, s, g.counters, PIFU_PREC_FP32, 0.f};
-      r = run_mlp(ec, g.cp, g.cp.mlp, PIFU_PREC_FP32, ps, g.hitlist, nh, g.ew, nullptr, nullptr,
-                  rgb);
+      // split-FP16 colour unless a value of this call already left the binary16 range;
+      // the split kernels report their own operands, and an overflow re-runs in FP32
+      const bool x3 = g.cp.mlp.prec == PIFU_PREC_FP16 && ctx->host_counters[C_OVF] == 0;
+      r = run_mlp(ec, g.cp, g.cp.mlp, x3 ? PREC_F32X3 : PIFU_PREC_FP32, ps, g.hitlist, nh, g.ew,
+                  nullptr, nullptr, rgb);
+      if (!r && x3) r = read_counters(e, C_OVF + 1);
+      if (!r && x3 && ctx->host_counters[C_OVF])
+        r = run_mlp(ec, g.cp, g.cp.mlp, PIFU_PREC_FP32, ps, g.hitlist, nh, g.ew, nullptr, nullptr,
+                    rgb);
     }
   }
   if (!r) r = check_launch();

@@ -195,3 +195,31 @@ def test_render_tiny(pifu, yaw):
     assert last["evaluated"] == ref["stats"]["evaluated_last"]
     assert last["shadow"] == ref["stats"]["shadow"]
     assert last["hits"] == ref["stats"]["hits"]
+
+
+@pytest.mark.parametrize("yaw", [0.0, 90.0])
+def test_render_fp16_colour_is_fp32_accurate(pifu, yaw):
+    """FP16 runs colour the hits with FP32-accurate split-FP16 products.  On an analytic
+    occupancy field the hits, depths and occupancy inputs do not depend on the MLP
+    precision, so the colours are compared as they are: against the FP32 run and the
+    oracle."""
+    ell = synth.ellipsoids(8, 302)
+    fo = O.Field("ellipsoids", ell=ell, sharpness=8.0)
+    fg = pifu.DeviceField.ellipsoids(ell, 8.0)
+    cfeat, cspec = _color()
+    co = O.Field("mlp", feat=cfeat, mlp=cspec)
+    cg = pifu.DeviceField.mlp_field(cfeat, cspec)
+    view = synth.yaw_view(yaw)
+    bg = (0.2, 0.4, 0.6)
+    ref = O.render_view(fo, co, view, 6, 5, 4, bg)
+    g32 = pifu.render_view(fg, cg, view, 6, 5, 4, bg)
+    g16 = pifu.render_view(fg, cg, view, 6, 5, 4, bg, precision="fp16", band_delta=0.0075)
+    assert torch.equal(g16["hit"], g32["hit"])
+    assert np.array_equal(g16["hit"].cpu().numpy(), ref["hit"])
+    assert torch.equal(torch.isnan(g16["depth"]), torch.isnan(g32["depth"]))
+    h = g16["hit"] == 1
+    assert torch.equal(g16["depth"][h], g32["depth"][h])
+    d16 = np.abs(g16["rgb"].cpu().numpy() - g32["rgb"].cpu().numpy()).max()
+    dref = np.abs(g16["rgb"].cpu().numpy() - ref["rgb"]).max()
+    print(f"yaw {yaw}: {int(h.sum())} hits; |rgb16 - rgb32| max {d16:.2e}, vs oracle {dref:.2e}")
+    assert d16 <= 2e-5 and dref <= 1e-4
