@@ -28,14 +28,16 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0, "fp8": 5000.0}
+# fp16x3: FP32-equivalent FLOP/s of the split-FP16 band (three FP16 MFMA products per step)
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0, "fp8": 5000.0, "fp16x3": 2500.0 / 3}
 # run precision and FP32 band of each form; the band is the logit error of the
 # precision over near-surface points with a margin (FP16: 0.0117 max, band 0.030 in
 # logit; BF16: 0.082 max, band 0.080)
 FORMS = {"fp32": ("fp32", 0.0, False), "fp16": ("fp16", 0.0075, False),
          "bf16": ("bf16", 0.02, False), "surrogate_fp16": ("fp16", 0.0075, True),
          "surrogate_bf16": ("bf16", 0.02, True)}
-GEMM_DTYPE = {"gemm_f32": "fp32", "gemm_bf16": "bf16", "gemm_f16": "fp16", "gemm_fp8": "fp8"}
+GEMM_DTYPE = {"gemm_f32": "fp32", "gemm_bf16": "bf16", "gemm_f16": "fp16", "gemm_fp8": "fp8",
+              "gemm_f16x3": "fp16x3"}
 
 
 def parse():
