@@ -180,7 +180,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(multi-GPU sharding is described in DESIGN.md only)"}))
+                                   "(frames and lattice slabs would shard across GPUs; not built)"}))
         sys.exit(2)
     import torch
 

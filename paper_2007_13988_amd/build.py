@@ -11,7 +11,8 @@ SOURCES = ["pifu_level.hip", "pifu_eval.hip", "pifu_gemm.hip", "pifu_fp64.hip", 
            "pifu_host.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-shared", "-std=c++17",
-    # packed FP32 instructions stay off (build notes)
+    # packed FP32 instructions stay off: the compiler forms them from plain float code, and
+    # some of their forms have given wrong results on this hardware
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",
 ]
