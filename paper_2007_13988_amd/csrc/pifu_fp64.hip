@@ -121,15 +121,18 @@ struct Gemm64Args {
 };
 
 // One 16 x 16 output tile per workgroup (v_mfma_f64_16x16x4f64).  The guard band
-// holds few points, so the tile is small (many workgroups) and the four waves split
-// the contraction: wave q sums the q-th quarter of the 16-wide k steps, and the
+// holds few points, so the tile is small (many workgroups) and the kGuardWaves waves
+// split the contraction: wave q sums the q-th share of the 16-wide k steps, and the
 // partial tiles are added in wave order through LDS, so every output is the same
-// fixed-order sum whatever the number of points.  Lane group g = lane/16 feeds the
+// fixed-order sum whatever the number of points.  A launch is a chain of dependent
+// loads and MFMAs per wave; eight waves keep that chain short.  Lane group g = lane/16 feeds the
 // k values {4g .. 4g+3} of each 16-wide step (s-th MFMA: k = 4g + s; same
 // permutation for A and B).  Output layout (checked on gfx950 with a lane probe):
 // lane l, register r holds row 4*r + l/16, column l%16.
-__global__ void __launch_bounds__(256) k_gemm64(Gemm64Args a) {
-  __shared__ double red[3][4][64];
+constexpr int kGuardWaves = 8;
+
+__global__ void __launch_bounds__(64 * kGuardWaves) k_gemm64(Gemm64Args a) {
+  __shared__ double red[kGuardWaves - 1][4][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int n0 = blockIdx.y * 16;
   const int K = a.K1 + a.K2;
@@ -137,7 +140,7 @@ __global__ void __launch_bounds__(256) k_gemm64(Gemm64Args a) {
   const int g = lane >> 4, r16 = lane & 15;
   const double* wrow = a.W + (size_t)(n0 + r16) * K;
   const int nst = K >> 4;
-  const int s0 = nst * wave / 4, s1 = nst * (wave + 1) / 4;
+  const int s0 = nst * wave / kGuardWaves, s1 = nst * (wave + 1) / kGuardWaves;
   // row tiles in turn (a fixed grid covers any device-side count)
   for (int m0 = blockIdx.x * 16; m0 < M; m0 += gridDim.x * 16) {
     const int arow = m0 + r16;
@@ -167,7 +170,8 @@ __global__ void __launch_bounds__(256) k_gemm64(Gemm64Args a) {
     if (wave == 0) {
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        acc[r] = ((acc[r] + red[0][r][lane]) + red[1][r][lane]) + red[2][r][lane];
+#pragma unroll
+        for (int q = 0; q < kGuardWaves - 1; ++q) acc[r] += red[q][r][lane];   // wave order
       const int col = n0 + r16;
       const double bias = a.bias[col];
       double we0 = 0.0, we1 = 0.0;
@@ -292,7 +296,7 @@ void run_guard64(const PointSrc& src, const uint32_t* list, const uint32_t* glis
       g.act = d.hidden_act;
       g.M_dev = gn_dev;
       hipLaunchKernelGGL(k_gemm64, dim3(std::min<uint32_t>((m + 15) / 16, 64), d.widths[l] / 16),
-                         dim3(256), 0, s, g);
+                         dim3(64 * kGuardWaves), 0, s, g);
       prev = out;
       out = out == hA ? hB : hA;
     }
