@@ -457,12 +457,12 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_h16(GemmArgs a) {
 // up to the dropped a_lo w_lo term (relative 2^-22), with the two sums in separate FP32
 // accumulators.  A arrives as FP32 and is split while it is staged into LDS; W arrives as
 // its hi / lo copies (W, Wlo).  Values must lie in the binary16 range: an A value outside
-// it sets *a.ovf (the caller then re-runs in FP32).  BK = 32; every tile walks k in the
-// same order.
-template <int BM, int BN, int WM, int WN, int MINB, int NT = 256>
+// it sets *a.ovf (the caller then re-runs in FP32).  BK = 32 or 64; every variant walks k
+// in the same 16-wide steps in the same order.
+template <int BM, int BN, int WM, int WN, int MINB, int NT = 256, int BK = 32>
 __global__ void __launch_bounds__(NT, MINB) k_gemm_x3(GemmArgs a) {
-  constexpr int BK = 32;
   constexpr int LD = BK + 8;   // halves per LDS row
+  constexpr int CA = BK / 4, CB = BK / 8;   // 16-byte chunks per staged A / W row
   constexpr int TI = BM / WM / 32, TJ = BN / WN / 32;
   // per stage: A hi, A lo, W hi, W lo
   __shared__ __attribute__((aligned(16))) _Float16 smem[2 * 2 * (BM + BN) * LD];
@@ -504,7 +504,7 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_x3(GemmArgs a) {
 #pragma unroll
     for (int i = 0; i < A_LOADS; ++i) {
       const int e = tid + NT * i;
-      const int row = e >> 3, c4 = e & 7;
+      const int row = e / CA, c4 = e % CA;
       const int gm = m0 + row;
       ra[i] = gm < M ? *reinterpret_cast<const f32x4*>(src + (size_t)gm * ld + kk0 + 4 * c4)
                      : (f32x4){0.f, 0.f, 0.f, 0.f};
@@ -512,7 +512,7 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_x3(GemmArgs a) {
 #pragma unroll
     for (int i = 0; i < B_LOADS; ++i) {
       const int e = tid + NT * i;
-      const int row = e >> 2, c8 = e & 3;
+      const int row = e / CB, c8 = e % CB;
       const size_t o = (size_t)(n0 + row) * a.ldw + k0 + 8 * c8;
       rbh[i] = *reinterpret_cast<const u32x4*>(Wh + o);
       rbl[i] = *reinterpret_cast<const u32x4*>(Wl + o);
@@ -525,7 +525,7 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_x3(GemmArgs a) {
 #pragma unroll
     for (int i = 0; i < A_LOADS; ++i) {
       const int e = tid + NT * i;
-      const int at = (e >> 3) * LD + 4 * (e & 7);
+      const int at = (e / CA) * LD + 4 * (e % CA);
       typedef _Float16 h4 __attribute__((ext_vector_type(4)));
       h4 hi, lo;
 #pragma unroll
@@ -541,7 +541,7 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_x3(GemmArgs a) {
 #pragma unroll
     for (int i = 0; i < B_LOADS; ++i) {
       const int e = tid + NT * i;
-      const int at = (e >> 2) * LD + 8 * (e & 3);
+      const int at = (e / CB) * LD + 8 * (e % CB);
       *reinterpret_cast<u32x4*>(Bh(b) + at) = rbh[i];
       *reinterpret_cast<u32x4*>(Bl(b) + at) = rbl[i];
     }
@@ -893,8 +893,16 @@ int launch_gemm(const GemmArgs& a, int precision, int tile_m, hipStream_t s, hip
     // SIMD (a 128 x 128 tile holds both accumulator sets in 369 registers, one wave per
     // SIMD, and ran 1.3-1.7x slower at every band size measured)
     if ((a.K1 % 32) || (a.K2 % 32)) return -1;
-    PIFU_GO((k_gemm_x3<64, 64, 2, 2, 2>), dim3(row_tiles(a.M, 64), a.N / 64), dim3(256), 0,
-                       s, a);
+    // a launch that fits one round at two workgroups per CU and has a deep contraction
+    // takes 64-deep k stages (half the stages of its latency chain; e.g. layer 1 at 1k /
+    // 3k points 24.4 / 33.5 -> 20.6 / 27.2 us); larger ones keep 32-deep stages, whose
+    // smaller LDS footprint doubles the workgroups per CU (8k points: 42 vs 52 us)
+    const unsigned rows = row_tiles(a.M, 64);
+    if ((a.K1 % 64) == 0 && (a.K2 % 64) == 0 && a.K1 + a.K2 >= 512 &&
+        (size_t)rows * (a.N / 64) <= 512)
+      PIFU_GO((k_gemm_x3<64, 64, 2, 2, 2, 256, 64>), dim3(rows, a.N / 64), dim3(256), 0, s, a);
+    else
+      PIFU_GO((k_gemm_x3<64, 64, 2, 2, 2>), dim3(rows, a.N / 64), dim3(256), 0, s, a);
     return 0;
   }
   if (bm == 32) bm = 64;   // the 32-point tile exists for FP32 only
