@@ -132,7 +132,8 @@ def recorded_traffic(kernel):
 def batched_bench(P, synth, steps):
     """16 frames of uneven content in one pifu_occupancy_grid_batched call against 16
     single calls: PIFu-MLP frames (different feature maps) at 256^3 from 32^3 with the
-    autotuned point tile, and ellipsoid-union frames (2-40% occupied) at 256^3 and 512^3."""
+    autotuned point tile, in FP32 and in FP16 (band 0.0075), and ellipsoid-union frames
+    (2-40% occupied) at 256^3 and 512^3."""
     import torch
     from paper_2007_13988_amd.pifu import BatchedGrid
 
@@ -150,11 +151,15 @@ def batched_bench(P, synth, steps):
     mlp_frames = [P.DeviceField(P.FIELD_MLP, feat=synth.pifu_sequence(400 + i, 0), mlp=teacher)
                   for i in range(16)]
     P.autotune(mlp_frames[0], "fp32")
+    P.autotune(mlp_frames[0], "fp16")
     scales = [0.5 + 0.08 * i for i in range(16)]
     ell_frames = [P.DeviceField.ellipsoids(synth.ellipsoids(8, 500 + i, sc)) for i, sc in enumerate(scales)]
-    for name, frames, L, l0 in (("mlp_256", mlp_frames, 8, 5), ("ellipsoids_256", ell_frames, 8, 5),
-                                ("ellipsoids_512", ell_frames, 9, 6)):
-        opts = [P.grid_opts(L, l0) for _ in frames]
+    f16 = dict(precision="fp16", band_delta=FORMS["fp16"][1])
+    for name, frames, L, l0, kw in (("mlp_256", mlp_frames, 8, 5, {}),
+                                    ("mlp_256_fp16", mlp_frames, 8, 5, f16),
+                                    ("ellipsoids_256", ell_frames, 8, 5, {}),
+                                    ("ellipsoids_512", ell_frames, 9, 6, {})):
+        opts = [P.grid_opts(L, l0, **kw) for _ in frames]
         bg = BatchedGrid(frames, opts)
         ms_b = timed(bg.run) / len(frames)
         outs = P.GridOutputs(frames[0], opts[0])
