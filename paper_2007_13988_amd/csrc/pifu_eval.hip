@@ -253,7 +253,7 @@ void launch_head(const float* h, int K, const float* W, const float* b, int n_ou
 __global__ void k_guard_select(const float* __restrict__ logit, uint32_t n, float g,
                                const uint32_t* __restrict__ map, uint32_t* __restrict__ glist,
                                uint32_t* __restrict__ gcount, const uint32_t* __restrict__ n_dev,
-                               uint32_t* __restrict__ acc) {
+                               uint32_t* __restrict__ acc, uint32_t start) {
   const uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t lim = n_dev ? min(n, *n_dev) : n;
   const bool take = m < lim && fabsf(logit[m]) < g;
@@ -266,7 +266,7 @@ __global__ void k_guard_select(const float* __restrict__ logit, uint32_t n, floa
     base = atomicAdd(gcount, (uint32_t)__popcll(bal));
     if (acc) atomicAdd(acc, (uint32_t)__popcll(bal));
   }
-  base = __shfl(base, first, 64);
+  base = __shfl(base, first, 64) - start;   // the counter held `start` before this launch
   if (take) {
     const uint32_t slot = base + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
     glist[slot] = map ? map[m] : m;
@@ -275,10 +275,10 @@ __global__ void k_guard_select(const float* __restrict__ logit, uint32_t n, floa
 
 void launch_guard_select(const float* logit, uint32_t n, float g, uint32_t* glist,
                          uint32_t* gcount, hipStream_t s, const uint32_t* map,
-                         const uint32_t* n_dev, uint32_t* acc) {
+                         const uint32_t* n_dev, uint32_t* acc, uint32_t start) {
   if (!n || !(g > 0.f)) return;
   hipLaunchKernelGGL(k_guard_select, dim3(grid1d(n, 256)), dim3(256), 0, s, logit, n, g, map,
-                     glist, gcount, n_dev, acc);
+                     glist, gcount, n_dev, acc, start);
 }
 
 

@@ -415,6 +415,9 @@ struct EvalCtx {
   float sur_band = 0.f;   // |logit| below which surrogate results go to the full MLP
   int tile_m = 0;         // forced point tile (32/64/128/256), 0 = chosen per launch
   bool g64_packed = false;  // float64 guard weights already written into the workspace
+  // value of counters[C_GUARD], a running selection counter: known after every read-back,
+  // 0 after every clear of the counters
+  uint32_t sel_base = 0;
 };
 
 int batch_bucket(uint32_t m) { return m <= 8192 ? 0 : (m <= 32768 ? 1 : 2); }
@@ -688,13 +691,15 @@ int select_near(EvalCtx& e, const float* logit, uint32_t n, float bound, uint32_
                 uint32_t* count, const uint32_t* map = nullptr) {
   *count = 0;
   if (!(bound > 0.f) || !n) return PIFU_OK;
-  HIP_TRY(hipMemsetAsync(e.counters + C_GUARD, 0, 4, e.s));
-  launch_guard_select(logit, n, bound, pos, e.counters + C_GUARD, e.s, map);
+  launch_guard_select(logit, n, bound, pos, e.counters + C_GUARD, e.s, map, nullptr, nullptr,
+                      e.sel_base);
   int r = check_launch();
   if (r) return r;
   r = read_counters(e, C_OVF + 1);   // the overflow flag comes back with the count
   if (r) return r;
-  *count = e.ctx->host_counters[C_GUARD];
+  const uint32_t now = e.ctx->host_counters[C_GUARD];
+  *count = now - e.sel_base;
+  e.sel_base = now;
   return PIFU_OK;
 }
 
@@ -868,6 +873,7 @@ int localize(EvalCtx& e, const FieldPrep& fp, const EvalWs& ew, const double* vi
     const int stride = 1 << (last - t);
     const uint32_t n_nodes = (uint32_t)L.lat.n();
     HIP_TRY(hipMemsetAsync(e.counters, 0, sizeof(uint32_t) * C_OVF, e.s));   // keeps C_OVF
+    e.sel_base = 0;
     bool fresh = false;   // the host copy holds every counter of this level
     if (t == 0) {
       // coarsest level: every node is evaluated
@@ -1229,6 +1235,7 @@ int32_t pifu_render_view(pifu_ctx* ctx, const pifu_field* occ_field, const pifu_
   st.nodes = (uint32_t)((size_t)W * H * (D + 1));
   const LevelBuf& C = g.lv[T - 1];
   HIP_TRY(hipMemsetAsync(g.counters, 0, sizeof(uint32_t) * C_OVF, s));   // keeps C_OVF
+  e.sel_base = 0;
   launch_fill_image(rgb, depth, hit, (uint32_t)(W * H), bg[0], bg[1], bg[2], s);
   launch_ray_count(C.st, C.lat, W, H, D, g.cnt, g.kstar, g.counters + C_SHADOW, s);
   launch_scan_u32(g.cnt, (uint32_t)(W * H), g.off, g.scan_scratch, g.counters + C_TOTAL, s);
@@ -1330,6 +1337,7 @@ int32_t pifu_eval_points(pifu_ctx* ctx, const pifu_field* field, int32_t precisi
   if (!lab) lab = reinterpret_cast<uint8_t*>(ew.glist);   // scratch when labels are not wanted
   EvalCtx e{ctx, s, counters, precision, guard_logit};
   e.band = logit_band(band_delta);
+  HIP_TRY(hipMemsetAsync(counters, 0, sizeof(uint32_t) * C_OVF, s));   // selection counter = 0
   if (int pr = pack_field(fp, ctx, s, counters)) return pr;
   launch_iota(iota, n, s);
   PointSrc src;
@@ -1937,6 +1945,7 @@ int32_t pifu_occupancy_grid_batched(pifu_ctx* ctx, int32_t n, const pifu_field* 
       rc = PIFU_ERR_HIP;
       break;
     }
+    e.sel_base = 0;
     const bool use_sur = level_id <= o.surrogate_max_log2;
     // frames whose final level this is write their occupancy straight into their output
     FrameOcc fo{};

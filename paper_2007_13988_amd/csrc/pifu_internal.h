@@ -145,10 +145,14 @@ void launch_gather(const PointSrc& src, const uint32_t* list, uint32_t n, const 
 void launch_head(const float* h, int K, const float* W, const float* b, int n_out, int out_act,
                  uint32_t n, const float* ext, float* logit, uint8_t* lab, float* rgb_out,
                  const uint32_t* rgb_index, hipStream_t s, const uint32_t* n_dev = nullptr);
+// Positions m < n with |logit[m]| < g (any order) into glist (map[m] with a map).
+// *gcount is a running counter that holds `start` before the launch: the positions go to
+// glist[0 ..) and the count is *gcount - start afterwards (no reset between launches).
 // n_dev (nullable): device-side bound on n; acc (nullable): accumulates the count
 void launch_guard_select(const float* logit, uint32_t n, float g, uint32_t* glist,
                          uint32_t* gcount, hipStream_t s, const uint32_t* map = nullptr,
-                         const uint32_t* n_dev = nullptr, uint32_t* acc = nullptr);
+                         const uint32_t* n_dev = nullptr, uint32_t* acc = nullptr,
+                         uint32_t start = 0);
 
 // out[i] = src[pos[i]]
 void launch_gather_u32(const uint32_t* src, const uint32_t* pos, uint32_t n, uint32_t* out,
