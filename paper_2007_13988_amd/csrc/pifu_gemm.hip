@@ -12,6 +12,8 @@
 // permutation, so the sum over k is unchanged.
 #include <hip/hip_ext.h>
 
+#include <algorithm>
+
 #include "pifu_internal.h"
 
 namespace pifu {
@@ -605,11 +607,9 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_x3(GemmArgs a) {
 
 // Copies the first K columns of a row-major [N][ldw_src] fp32 weight matrix into a
 // dense [N][K] operand matrix of format fmt (FMT_*); FMT_F16 flags values outside the
-// binary16 range in *ovf.
-__global__ void k_pack_weights(const float* __restrict__ W, int N, int ldw_src, int K,
-                               void* __restrict__ dst, int fmt, uint32_t* __restrict__ ovf) {
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (size_t)N * K) return;
+// binary16 range in *ovf.  Element i of the dense matrix:
+__device__ inline void pack_element(const float* __restrict__ W, int ldw_src, int K, size_t i,
+                                    void* __restrict__ dst, int fmt, uint32_t* __restrict__ ovf) {
   const int n = (int)(i / K), k = (int)(i - (size_t)n * K);
   const float v = W[(size_t)n * ldw_src + k];
   if (fmt == FMT_BF16) {
@@ -626,12 +626,36 @@ __global__ void k_pack_weights(const float* __restrict__ W, int N, int ldw_src, 
   }
 }
 
+__global__ void k_pack_weights(const float* __restrict__ W, int N, int ldw_src, int K,
+                               void* __restrict__ dst, int fmt, uint32_t* __restrict__ ovf) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)N * K) return;
+  pack_element(W, ldw_src, K, i, dst, fmt, ovf);
+}
+
 void launch_pack_weights(const float* W, int N, int ldw_src, int K, void* dst, int fmt,
                          hipStream_t s, uint32_t* ovf) {
   size_t n = (size_t)N * K;
   if (n)
     hipLaunchKernelGGL(k_pack_weights, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, W, N,
                        ldw_src, K, dst, fmt, ovf);
+}
+
+// Every copy of a network's preparation in one launch: workgroup row y takes job y.
+__global__ void k_pack_many(PackJobs jobs) {
+  const PackJob& J = jobs.j[blockIdx.y];
+  const size_t tot = (size_t)J.N * J.K;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < tot;
+       i += (size_t)gridDim.x * blockDim.x)
+    pack_element(J.W, J.ldw, J.K, i, J.dst, J.fmt, J.ovf);
+}
+
+void launch_pack_many(const PackJobs& jobs, hipStream_t s) {
+  if (!jobs.n) return;
+  size_t most = 0;
+  for (int q = 0; q < jobs.n; ++q) most = std::max(most, (size_t)jobs.j[q].N * jobs.j[q].K);
+  const unsigned gx = (unsigned)std::min<size_t>((most + 255) / 256, 256);
+  hipLaunchKernelGGL(k_pack_many, dim3(gx, (unsigned)jobs.n), dim3(256), 0, s, jobs);
 }
 
 // ------------------------------------------------------------------ FP8 (OCP e4m3) operands

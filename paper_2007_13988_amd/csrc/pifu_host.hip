@@ -261,32 +261,36 @@ void carve_mlp(Carver& cv, const pifu_mlp* m, int precision, MlpPrep& p) {
 
 int pack_mlp(MlpPrep& p, pifu_ctx* ctx, hipStream_t s, uint32_t* ovf) {
   const int f16 = h16_fmt(p.prec);
+  // the copies go out in batches of one launch each
+  PackJobs jobs;
+  auto add = [&](const float* W, int N, int ldw, int K, void* dst, int fmt, uint32_t* ov) {
+    if (jobs.n == kMaxPackJobs) {
+      launch_pack_many(jobs, s);
+      jobs.n = 0;
+    }
+    jobs.j[jobs.n++] = PackJob{W, dst, ov, N, ldw, K, fmt};
+  };
   for (int l = 0; l + 1 < p.d.n_layers; ++l) {
-    launch_pack_weights(p.d.W[l], p.d.widths[l], p.d.in_w[l], p.Kp[l], p.Wp32[l], FMT_F32, s);
-    if (p.Wp16[l])
-      launch_pack_weights(p.d.W[l], p.d.widths[l], p.d.in_w[l], p.Kp[l], p.Wp16[l], f16, s, ovf);
-    if (p.Wlo16[l])
-      launch_pack_weights(p.d.W[l], p.d.widths[l], p.d.in_w[l], p.Kp[l], p.Wlo16[l], FMT_F16LO, s);
+    add(p.d.W[l], p.d.widths[l], p.d.in_w[l], p.Kp[l], p.Wp32[l], FMT_F32, nullptr);
+    if (p.Wp16[l]) add(p.d.W[l], p.d.widths[l], p.d.in_w[l], p.Kp[l], p.Wp16[l], f16, ovf);
+    if (p.Wlo16[l]) add(p.d.W[l], p.d.widths[l], p.d.in_w[l], p.Kp[l], p.Wlo16[l], FMT_F16LO, nullptr);
     if (p.Wp8[l])
       launch_pack_fp8(p.d.W[l], p.d.widths[l], p.d.in_w[l], p.Kp[l], p.amax + l, p.Wp8[l], s);
     if (p.hoist_off[l] >= 0) {
       const int C = p.d.feat_dim;
       const int fcol = l == 0 ? 0 : p.d.widths[l - 1];   // where f starts in layer l's input
       const size_t off = (size_t)p.hoist_off[l];
-      launch_pack_weights(p.d.W[l] + fcol, p.d.widths[l], p.d.in_w[l], C, p.Wf32 + off * C, FMT_F32,
-                          s);
-      if (p.Wf16)
-        launch_pack_weights(p.d.W[l] + fcol, p.d.widths[l], p.d.in_w[l], C, p.Wf16 + off * C, f16, s,
-                            ovf);
+      add(p.d.W[l] + fcol, p.d.widths[l], p.d.in_w[l], C, p.Wf32 + off * C, FMT_F32, nullptr);
+      if (p.Wf16) add(p.d.W[l] + fcol, p.d.widths[l], p.d.in_w[l], C, p.Wf16 + off * C, f16, ovf);
       if (p.Wflo16)
-        launch_pack_weights(p.d.W[l] + fcol, p.d.widths[l], p.d.in_w[l], C, p.Wflo16 + off * C,
-                            FMT_F16LO, s);
-      HIP_TRY(hipMemcpyAsync(p.bf + off, p.d.b[l], sizeof(float) * p.d.widths[l],
-                             hipMemcpyDeviceToDevice, s));
+        add(p.d.W[l] + fcol, p.d.widths[l], p.d.in_w[l], C, p.Wflo16 + off * C, FMT_F16LO, nullptr);
+      // the layer's biases, as a one-row copy
+      add(p.d.b[l], 1, p.d.widths[l], p.d.widths[l], p.bf + off, FMT_F32, nullptr);
       if (l == 0)   // the z column of layer 0 (input [f; z])
-        launch_pack_weights(p.d.W[0] + C, p.d.widths[0], p.d.in_w[0], 1, p.wz, FMT_F32, s);
+        add(p.d.W[0] + C, p.d.widths[0], p.d.in_w[0], 1, p.wz, FMT_F32, nullptr);
     }
   }
+  launch_pack_many(jobs, s);
   if (!p.amax) return check_launch();
   // the FP8 weight scales enter the GEMM epilogue: read them back once per call
   const int nl = p.d.n_layers - 1;

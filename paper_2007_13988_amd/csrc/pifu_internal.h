@@ -267,6 +267,19 @@ void launch_pack_fp8(const float* W, int N, int ldw, int K, uint32_t* amax_bits,
 // dst = the first K columns of W in format fmt (ovf as for launch_gather)
 void launch_pack_weights(const float* W, int N, int ldw_src, int K, void* dst, int fmt,
                          hipStream_t s, uint32_t* ovf = nullptr);
+// Several such copies in one launch.
+struct PackJob {
+  const float* W;
+  void* dst;
+  uint32_t* ovf;
+  int N, ldw, K, fmt;
+};
+constexpr int kMaxPackJobs = 40;
+struct PackJobs {
+  PackJob j[kMaxPackJobs];
+  int n = 0;
+};
+void launch_pack_many(const PackJobs& jobs, hipStream_t s);
 
 }  // namespace pifu
 
