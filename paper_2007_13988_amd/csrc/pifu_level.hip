@@ -424,6 +424,10 @@ void launch_scan_u32(const uint32_t* in, uint32_t n, uint32_t* out_excl, uint32_
     (void)hipMemsetAsync(total, 0, 4, s);
     return;
   }
+  if (n <= 8192) {   // up to 8 words per thread: one workgroup, one launch
+    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, in, n, out_excl, total);
+    return;
+  }
   hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(1024), 0, s, in, n, scratch);
   hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, scratch, nt, scratch + nt, total);
   hipLaunchKernelGGL(k_scan_apply, dim3(nt), dim3(1024), 0, s, in, n, scratch + nt, out_excl);
