@@ -194,11 +194,10 @@ void launch_gather(const PointSrc& src, const uint32_t* list, uint32_t n, const 
 __global__ void __launch_bounds__(256)
 k_head(const float* __restrict__ h, int K, const float* __restrict__ W, const float* __restrict__ b,
        int n_out, int out_act, uint32_t n, const float* __restrict__ ext, float* __restrict__ logit,
-       uint8_t* __restrict__ lab, float* __restrict__ rgb_out, const uint32_t* __restrict__ rgb_index,
-       const uint32_t* __restrict__ n_dev) {
+       uint8_t* __restrict__ lab, float* __restrict__ rgb_out, const uint32_t* __restrict__ rgb_index) {
   const uint32_t m = (blockIdx.x * blockDim.x + threadIdx.x) >> 4;
   const int q = threadIdx.x & 15;
-  if (m >= n || (n_dev && m >= *n_dev)) return;   // whole 16-lane groups leave together
+  if (m >= n) return;   // whole 16-lane groups leave together
   float acc[4] = {0.f, 0.f, 0.f, 0.f};
   const float* hr = h + (size_t)m * K;
   for (int k = 4 * q; k < K; k += 64) {
@@ -238,34 +237,28 @@ k_head(const float* __restrict__ h, int K, const float* __restrict__ W, const fl
 
 void launch_head(const float* h, int K, const float* W, const float* b, int n_out, int out_act,
                  uint32_t n, const float* ext, float* logit, uint8_t* lab, float* rgb_out,
-                 const uint32_t* rgb_index, hipStream_t s, const uint32_t* n_dev) {
+                 const uint32_t* rgb_index, hipStream_t s) {
   if (!n) return;
   hipLaunchKernelGGL(k_head, dim3(grid1d((size_t)n * 16, 256)), dim3(256), 0, s, h, K, W, b, n_out,
-                     out_act, n, ext, logit, lab, rgb_out, rgb_index, n_dev);
+                     out_act, n, ext, logit, lab, rgb_out, rgb_index);
 }
 
 // ------------------------------------------------------------------ FP64 guard band
-// Appends the positions m < n (and m < *n_dev when given) with |logit[m]| < g
-// (map[m] instead of m when map is given); one atomic per wave reserves the wave's
-// slots, and acc (nullable) accumulates the count.  The order of the appended
+// Appends the positions m < n with |logit[m]| < g (map[m] instead of m when map is
+// given); one atomic per wave reserves the wave's slots.  The order of the appended
 // positions across waves is unspecified; every consumer treats the points
 // independently.
 __global__ void k_guard_select(const float* __restrict__ logit, uint32_t n, float g,
                                const uint32_t* __restrict__ map, uint32_t* __restrict__ glist,
-                               uint32_t* __restrict__ gcount, const uint32_t* __restrict__ n_dev,
-                               uint32_t* __restrict__ acc, uint32_t start) {
+                               uint32_t* __restrict__ gcount, uint32_t start) {
   const uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t lim = n_dev ? min(n, *n_dev) : n;
-  const bool take = m < lim && fabsf(logit[m]) < g;
+  const bool take = m < n && fabsf(logit[m]) < g;
   const unsigned long long bal = __ballot(take);
   if (!bal) return;
   const int lane = threadIdx.x & 63;
   const int first = __ffsll((long long)bal) - 1;
   uint32_t base = 0;
-  if (lane == first) {
-    base = atomicAdd(gcount, (uint32_t)__popcll(bal));
-    if (acc) atomicAdd(acc, (uint32_t)__popcll(bal));
-  }
+  if (lane == first) base = atomicAdd(gcount, (uint32_t)__popcll(bal));
   base = __shfl(base, first, 64) - start;   // the counter held `start` before this launch
   if (take) {
     const uint32_t slot = base + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
@@ -274,11 +267,10 @@ __global__ void k_guard_select(const float* __restrict__ logit, uint32_t n, floa
 }
 
 void launch_guard_select(const float* logit, uint32_t n, float g, uint32_t* glist,
-                         uint32_t* gcount, hipStream_t s, const uint32_t* map,
-                         const uint32_t* n_dev, uint32_t* acc, uint32_t start) {
+                         uint32_t* gcount, hipStream_t s, const uint32_t* map, uint32_t start) {
   if (!n || !(g > 0.f)) return;
   hipLaunchKernelGGL(k_guard_select, dim3(grid1d(n, 256)), dim3(256), 0, s, logit, n, g, map,
-                     glist, gcount, n_dev, acc, start);
+                     glist, gcount, start);
 }
 
 
@@ -576,24 +568,22 @@ void launch_fill_image(float* rgb, float* depth, uint8_t* hit, uint32_t npix, fl
 namespace pifu {
 
 __global__ void k_gather_u32(const uint32_t* __restrict__ src, const uint32_t* __restrict__ pos,
-                             uint32_t n, const uint32_t* __restrict__ n_dev,
-                             uint32_t* __restrict__ out) {
+                             uint32_t n, uint32_t* __restrict__ out) {
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n && (!n_dev || i < *n_dev)) out[i] = src[pos[i]];
+  if (i < n) out[i] = src[pos[i]];
 }
 
 void launch_gather_u32(const uint32_t* src, const uint32_t* pos, uint32_t n, uint32_t* out,
-                       hipStream_t s, const uint32_t* n_dev) {
+                       hipStream_t s) {
   if (n)
-    hipLaunchKernelGGL(k_gather_u32, dim3(grid1d(n, 256)), dim3(256), 0, s, src, pos, n, n_dev, out);
+    hipLaunchKernelGGL(k_gather_u32, dim3(grid1d(n, 256)), dim3(256), 0, s, src, pos, n, out);
 }
 
 __global__ void k_scatter_results(const uint32_t* __restrict__ pos, uint32_t n,
-                                  const uint32_t* __restrict__ n_dev,
                                   const float* __restrict__ tl, const uint8_t* __restrict__ tb,
                                   float* __restrict__ logit, uint8_t* __restrict__ lab) {
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || (n_dev && i >= *n_dev)) return;
+  if (i >= n) return;
   const uint32_t p = pos[i];
   logit[p] = tl[i];
   lab[p] = tb[i];
@@ -603,52 +593,44 @@ __global__ void k_scatter_results(const uint32_t* __restrict__ pos, uint32_t n,
 // In the input view the sampled feature depends only on the (x, y) column of a node,
 // so the feature part of every layer (W_f f + b) is computed once per column run.
 __global__ void k_col_flags(const uint32_t* __restrict__ list, uint32_t n, uint32_t nz,
-                            const uint32_t* __restrict__ n_dev, uint32_t* __restrict__ flags) {
+                            uint32_t* __restrict__ flags) {
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  // points past the device-side count start no column
-  if (n_dev && i >= *n_dev) {
-    flags[i] = 0;
-    return;
-  }
   flags[i] = (i == 0) || (list[i] / nz != list[i - 1] / nz);
 }
 
 void launch_col_flags(const uint32_t* list, uint32_t n, uint32_t nz, uint32_t* flags,
-                      hipStream_t s, const uint32_t* n_dev) {
+                      hipStream_t s) {
   if (n)
-    hipLaunchKernelGGL(k_col_flags, dim3(grid1d(n, 256)), dim3(256), 0, s, list, n, nz, n_dev, flags);
+    hipLaunchKernelGGL(k_col_flags, dim3(grid1d(n, 256)), dim3(256), 0, s, list, n, nz, flags);
 }
 
 __global__ void k_col_ids(const uint32_t* __restrict__ list, const uint32_t* __restrict__ flags,
                           const uint32_t* __restrict__ excl, uint32_t n,
-                          const uint32_t* __restrict__ n_dev, uint32_t* __restrict__ cid,
-                          uint32_t* __restrict__ col_node) {
+                          uint32_t* __restrict__ cid, uint32_t* __restrict__ col_node) {
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || (n_dev && i >= *n_dev)) return;
+  if (i >= n) return;
   const uint32_t c = excl[i] + flags[i] - 1;
   cid[i] = c;
   if (flags[i]) col_node[c] = list[i];
 }
 
 void launch_col_ids(const uint32_t* list, const uint32_t* flags, const uint32_t* excl, uint32_t n,
-                    uint32_t* cid, uint32_t* col_node, hipStream_t s, const uint32_t* n_dev) {
+                    uint32_t* cid, uint32_t* col_node, hipStream_t s) {
   if (n)
-    hipLaunchKernelGGL(k_col_ids, dim3(grid1d(n, 256)), dim3(256), 0, s, list, flags, excl, n, n_dev,
-                       cid, col_node);
+    hipLaunchKernelGGL(k_col_ids, dim3(grid1d(n, 256)), dim3(256), 0, s, list, flags, excl, n, cid,
+                       col_node);
 }
 
 __global__ void k_hoist_layer0(const float* __restrict__ P, int ldp, const uint32_t* __restrict__ cid,
                                const uint32_t* __restrict__ list, uint32_t n, int nz,
                                const float* __restrict__ wz, int N, int act,
-                               void* __restrict__ h, int h_fmt, const uint32_t* __restrict__ n_dev,
-                               uint32_t* __restrict__ ovf) {
+                               void* __restrict__ h, int h_fmt, uint32_t* __restrict__ ovf) {
   // four consecutive outputs per thread (N % 4 == 0, ldp % 4 == 0; n * N / 4 < 2^32)
   const uint32_t n4 = (uint32_t)N >> 2;
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n * n4) return;
   const uint32_t i = e / n4;
-  if (n_dev && i >= *n_dev) return;
   const uint32_t o = (e - i * n4) << 2;
   const uint32_t k = list[i] % (uint32_t)nz;
   const float z = (float)(-1.0 + 2.0 * (double)k / (double)(nz - 1));
@@ -680,11 +662,11 @@ __global__ void k_hoist_layer0(const float* __restrict__ P, int ldp, const uint3
 
 void launch_hoist_layer0(const float* P, int ldp, const uint32_t* cid, const uint32_t* list,
                          uint32_t n, int nz, const float* wz, int N, int act, void* h, int h_fmt,
-                         hipStream_t s, const uint32_t* n_dev, uint32_t* ovf) {
+                         hipStream_t s, uint32_t* ovf) {
   const size_t tot = (size_t)n * (N >> 2);
   if (tot)
     hipLaunchKernelGGL(k_hoist_layer0, dim3(grid1d(tot, 256)), dim3(256), 0, s, P, ldp, cid, list,
-                       n, nz, wz, N, act, h, h_fmt, n_dev, ovf);
+                       n, nz, wz, N, act, h, h_fmt, ovf);
 }
 
 // The library's number-format conversions applied to an array (for checking them).
@@ -701,9 +683,9 @@ void launch_convert(const float* in, uint32_t n, int fmt, void* out, hipStream_t
 }
 
 void launch_scatter_results(const uint32_t* pos, uint32_t n, const float* tl, const uint8_t* tb,
-                            float* logit, uint8_t* lab, hipStream_t s, const uint32_t* n_dev) {
+                            float* logit, uint8_t* lab, hipStream_t s) {
   if (n)
-    hipLaunchKernelGGL(k_scatter_results, dim3(grid1d(n, 256)), dim3(256), 0, s, pos, n, n_dev, tl,
+    hipLaunchKernelGGL(k_scatter_results, dim3(grid1d(n, 256)), dim3(256), 0, s, pos, n, tl,
                        tb, logit, lab);
 }
 

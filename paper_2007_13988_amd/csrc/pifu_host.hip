@@ -573,7 +573,7 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
         return PIFU_ERR_UNSUPPORTED;
     }
     launch_hoist_layer0(ew.Pcol, mp.NP, ew.cid, lst, m, src.nz, mp.wz, d.widths[0], d.hidden_act,
-                        ew.hA, d.n_layers > 2 ? hf : FMT_F32, e.s, nullptr, ovf);
+                        ew.hA, d.n_layers > 2 ? hf : FMT_F32, e.s, ovf);
     const void* prev = ew.hA;
     void* out = ew.hB;
     for (int l = 1; l + 1 < d.n_layers; ++l) {
@@ -695,8 +695,7 @@ int select_near(EvalCtx& e, const float* logit, uint32_t n, float bound, uint32_
                 uint32_t* count, const uint32_t* map = nullptr) {
   *count = 0;
   if (!(bound > 0.f) || !n) return PIFU_OK;
-  launch_guard_select(logit, n, bound, pos, e.counters + C_GUARD, e.s, map, nullptr, nullptr,
-                      e.sel_base);
+  launch_guard_select(logit, n, bound, pos, e.counters + C_GUARD, e.s, map, e.sel_base);
   int r = check_launch();
   if (r) return r;
   r = read_counters(e, C_OVF + 1);   // the overflow flag comes back with the count

@@ -144,31 +144,26 @@ void launch_gather(const PointSrc& src, const uint32_t* list, uint32_t n, const 
                    const uint32_t* n_dev = nullptr, uint32_t* ovf = nullptr);
 void launch_head(const float* h, int K, const float* W, const float* b, int n_out, int out_act,
                  uint32_t n, const float* ext, float* logit, uint8_t* lab, float* rgb_out,
-                 const uint32_t* rgb_index, hipStream_t s, const uint32_t* n_dev = nullptr);
+                 const uint32_t* rgb_index, hipStream_t s);
 // Positions m < n with |logit[m]| < g (any order) into glist (map[m] with a map).
 // *gcount is a running counter that holds `start` before the launch: the positions go to
 // glist[0 ..) and the count is *gcount - start afterwards (no reset between launches).
-// n_dev (nullable): device-side bound on n; acc (nullable): accumulates the count
 void launch_guard_select(const float* logit, uint32_t n, float g, uint32_t* glist,
                          uint32_t* gcount, hipStream_t s, const uint32_t* map = nullptr,
-                         const uint32_t* n_dev = nullptr, uint32_t* acc = nullptr,
                          uint32_t start = 0);
 
 // out[i] = src[pos[i]]
 void launch_gather_u32(const uint32_t* src, const uint32_t* pos, uint32_t n, uint32_t* out,
-                       hipStream_t s, const uint32_t* n_dev = nullptr);
+                       hipStream_t s);
 void launch_convert(const float* in, uint32_t n, int fmt, void* out, hipStream_t s);
 // logit[pos[i]] = tl[i], lab[pos[i]] = tb[i]
 void launch_scatter_results(const uint32_t* pos, uint32_t n, const float* tl, const uint8_t* tb,
-                            float* logit, uint8_t* lab, hipStream_t s,
-                            const uint32_t* n_dev = nullptr);
+                            float* logit, uint8_t* lab, hipStream_t s);
 size_t guard64_ws_bytes(const MLPDesc& d, uint32_t chunk);
 // pack: write the float64 weight copies into ws (once per call; later calls reuse them).
-// gn_dev (nullable): device-side count; gn is then a capacity <= chunk (one pass)
 void run_guard64(const PointSrc& src, const uint32_t* list, const uint32_t* glist, uint32_t gn,
                  const MLPDesc& d, const float* F, int H, int W, int C, float* logit, uint8_t* lab,
-                 void* ws, uint32_t chunk, bool pack, hipStream_t s,
-                 const uint32_t* gn_dev = nullptr);
+                 void* ws, uint32_t chunk, bool pack, hipStream_t s);
 
 // ------------------------------------------------------------------ render kernels
 void launch_ray_count(const uint8_t* stc, Lat c, int W, int H, int D, uint32_t* cnt,
@@ -226,16 +221,15 @@ struct GemmArgs {
 // ------------------------------------------------------------------ per-column hoisting
 // flags[i] = point i starts a new (x, y) column (list sorted or not: runs of one column)
 void launch_col_flags(const uint32_t* list, uint32_t n, uint32_t nz, uint32_t* flags,
-                      hipStream_t s, const uint32_t* n_dev = nullptr);
+                      hipStream_t s);
 // cid[i] = index of point i's column run; col_node[cid] = a node of that column
 void launch_col_ids(const uint32_t* list, const uint32_t* flags, const uint32_t* excl, uint32_t n,
-                    uint32_t* cid, uint32_t* col_node, hipStream_t s,
-                    const uint32_t* n_dev = nullptr);
+                    uint32_t* cid, uint32_t* col_node, hipStream_t s);
 // layer 0 with hoisting: h[i][o] = act(P[cid[i]][o] + wz[o] * z_i), z from the node index;
 // h in format h_fmt (ovf as for launch_gather)
 void launch_hoist_layer0(const float* P, int ldp, const uint32_t* cid, const uint32_t* list,
                          uint32_t n, int nz, const float* wz, int N, int act, void* h, int h_fmt,
-                         hipStream_t s, const uint32_t* n_dev = nullptr, uint32_t* ovf = nullptr);
+                         hipStream_t s, uint32_t* ovf = nullptr);
 
 // float32 -> OCP FP8 E4M3FN code (bias 7, 3 mantissa bits, no infinities), round to
 // nearest even, saturating at +-448; NaN -> 0x7f.
