@@ -1,7 +1,8 @@
 """Benchmark: ms/frame for a 256^3 hierarchical surface + a 512^2 mesh-free render.
 
 One step = one frame of the hot path on synthetic inputs already resident in HBM (frame 0
-of a synthetic performance: a feature sequence whose earlier frames train the surrogate):
+of a synthetic performance: a feature sequence whose earlier frames train the surrogate),
+one pifu_grid_and_render call that runs its two parts concurrently on two streams:
   * pifu_occupancy_grid: 256^3 cells (257^3 nodes) from a 32^3 coarse level, PIFu-size
     MLP (256+z)->1024->512->256->128->1 with feature skips over a 256 ch x 128 x 128
     feature map;
@@ -11,13 +12,16 @@ of a synthetic performance: a feature sequence whose earlier frames train the su
 Forms timed on the same frame (all with the FP64 guard at |logit| < 1e-3):
   * fp32: the plain method, FP32 MFMA;
   * fp16: full network in FP16 MFMA, FP32 re-run of the points with |p-0.5| < 0.0075;
-  * surrogate_fp16: distilled (256+z)->128->64->1 network (BF16) on the 32^3..128^3
-    levels, points it leaves undecided and the finer levels as in fp16;
+  * surrogate_fp16: distilled (256+z)->128->64->1 network (BF16) on the densely
+    evaluated coarsest levels (32^3 grid, 64 x 64 x 32 render), points it leaves
+    undecided and the finer levels as in fp16;
   * bf16 / surrogate_bf16 (on request): as above with BF16 and a band of 0.02.
 `value` is the fastest form whose surface cells and render hits agree with the FP32
 form within 0.1%, else the FP32 form.  The timed steps run without instrumentation; the
 roofline's per-launch durations come from the same steps run again with HIP events
-around every MLP launch (events cost ~9 us of stream time each).  Prints one JSON line.
+around every MLP launch (events cost ~9 us of stream time each).  A last uninstrumented
+pass runs the two calls one after the other on one stream (ms_per_frame_serial, and the
+grid's own time).  Prints one JSON line.
 """
 import argparse
 import json
@@ -55,6 +59,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the second, event-instrumented pass (no roofline)")
+    ap.add_argument("--no-serial", action="store_true",
+                    help="skip the last pass that runs grid and render one after the other")
     ap.add_argument("--train-frames", type=int, default=6)
     ap.add_argument("--train-samples", type=int, default=1747627)   # 6 x 1.75 M = 10.5 M
     ap.add_argument("--train-steps", type=int, default=4000)
@@ -206,6 +212,7 @@ def main():
     view = synth.yaw_view(90.0)
     bg = (0.0, 0.0, 0.0)
     stream = torch.cuda.current_stream()
+    stream2 = torch.cuda.Stream()   # the render's stream (default priority)
     setup = {}
 
     sur_net, delta = None, None
@@ -263,11 +270,19 @@ def main():
     for form in forms:
         fld, gout, rout = make(form)
         for _ in range(args.warmup):
-            P.occupancy_grid_into(fld, gout, stream)
-            P.render_view_into(fld, col_field, view, bg, rout, stream)
+            P.grid_and_render_into(fld, gout, col_field, view, bg, rout, stream, stream2)
         torch.cuda.synchronize()
 
         def timed_steps():
+            # one frame = one call: the grid on `stream`, the render on `stream2`, concurrently
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                P.grid_and_render_into(fld, gout, col_field, view, bg, rout, stream, stream2)
+            torch.cuda.synchronize()
+            return time.perf_counter() - t0
+
+        def serial_steps():
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             t_occ = 0.0
@@ -281,21 +296,33 @@ def main():
 
         # the timed steps run uninstrumented: a HIP event pair around a launch costs about
         # 9 us of stream time, ~3.7 ms over the ~370 MLP launches of a frame
-        elapsed, t_occ = timed_steps()
+        elapsed = timed_steps()
         # per-launch durations: the same steps again with HIP events around every launch
         # of the GEMM, gather and head families, on the stream they are launched on
         prof, instr = None, None
         if not args.no_profile:
             P.profile_enable(True)
-            instr, _ = timed_steps()
+            instr = timed_steps()
             prof = P.profile_read()
+            P.profile_enable(False)
+        ser, t_occ = serial_steps() if not args.no_serial else (None, None)
+        # the kernels on their own: the serial calls again with events (one stream, nothing
+        # running beside them)
+        prof_iso, instr_iso = None, None
+        if not args.no_profile and not args.no_serial:
+            P.profile_enable(True)
+            instr_iso, _ = serial_steps()
+            prof_iso = P.profile_read()
             P.profile_enable(False)
         gst = [s.as_dict() for s in gout.stats]
         rst = [s.as_dict() for s in rout.stats]
         nc = gout.n_cells.value
-        results[form] = dict(ms=elapsed / args.steps * 1e3, ms_occ=t_occ / args.steps * 1e3,
+        results[form] = dict(ms=elapsed / args.steps * 1e3,
+                             ms_serial=ser / args.steps * 1e3 if ser else None,
+                             ms_occ=t_occ / args.steps * 1e3 if t_occ else None,
                              ms_instrumented=instr / args.steps * 1e3 if instr else None,
-                             prof=prof or {}, gst=gst, rst=rst,
+                             prof=prof or {}, prof_iso=prof_iso or {},
+                             ms_iso_instrumented=instr_iso / args.steps * 1e3 if instr_iso else None, gst=gst, rst=rst,
                              cells=gout.cells[:min(nc, gout.cells_cap)].clone(),
                              hit=rout.hit.clone())
 
@@ -308,6 +335,10 @@ def main():
         del src, dst
 
     from paper_2007_13988_amd.surrogate import cell_disagreement
+
+    def rnd(x):
+        return round(x, 3) if x is not None else None
+
     base = results.get("fp32")
     chosen = "fp32" if base is not None else forms[0]
     extra = {}
@@ -317,7 +348,8 @@ def main():
         dis = cell_disagreement(r["cells"], base["cells"])
         hit_dis = float((r["hit"] != base["hit"]).float().mean().item())
         extra[form] = {
-            "ms_per_frame": round(r["ms"], 3), "ms_occupancy_grid": round(r["ms_occ"], 3),
+            "ms_per_frame": round(r["ms"], 3), "ms_per_frame_serial": rnd(r["ms_serial"]),
+            "ms_occupancy_grid": rnd(r["ms_occ"]),
             "speedup_vs_fp32": round(base["ms"] / r["ms"], 3),
             "surface_cell_disagreement_vs_fp32": dis, "render_hit_disagreement": hit_dis,
             "surrogate_fallback_points": sum(x["surrogate_fallback"] for x in r["gst"] + r["rst"]),
@@ -332,8 +364,8 @@ def main():
     gemms = {k: v for k, v in main_r["prof"].items() if k in GEMM_DTYPE and v["launches"]}
     gemm_key = max(gemms, key=lambda k: gemms[k]["total_ms"]) if gemms else "gemm_f32"
 
-    def roofline(r, key, peak_key):
-        g = r["prof"].get(key)
+    def roofline(r, key, peak_key, isolated=False):
+        g = r["prof_iso" if isolated else "prof"].get(key)
         if not g or not g["launches"]:
             return None
         avg_ms = g["total_ms"] / g["launches"]
@@ -347,9 +379,14 @@ def main():
                 "flops_per_launch": fpl, "algorithmic_bytes_per_launch": g["bytes"] / g["launches"],
                 "share_of_gemm_time": round(g["total_ms"] / sum(v["total_ms"] for v in gemms.values()), 3)
                 if key in gemms else None,
-                "events_pass": f"launch durations from {args.steps} further steps of the same frame "
-                               f"with HIP events around every MLP launch ({r['ms_instrumented']:.3f} "
-                               f"ms/frame with the events, {r['ms']:.3f} without)"}
+                "events_pass": (f"launch durations from {args.steps} further steps of the same frame "
+                                f"(grid and render concurrently, as timed) with HIP events around "
+                                f"every MLP launch ({r['ms_instrumented']:.3f} "
+                                f"ms/frame with the events, {r['ms']:.3f} without)") if not isolated
+                else (f"launch durations from {args.steps} steps of the grid and render calls one "
+                      f"after the other on one stream, with HIP events around every MLP launch "
+                      f"({r['ms_iso_instrumented']:.3f} ms/frame with the events, "
+                      f"{r['ms_serial']:.3f} without)")}
 
     occ_pts = sum(s["mlp_points"] for s in main_r["gst"])
     ren_pts = sum(s["mlp_points"] for s in main_r["rst"])
@@ -362,17 +399,24 @@ def main():
                                "render 512x512x256 from 64x64x32, yaw 90",
                    "form": chosen,
                    "occupancy_mlp": "(256+z)->1024->512->256->128->1 skip, 256ch x 128^2 features",
-                   "color_mlp": "(256+z+occ)->512->256->3", "guard_logit": 1e-3},
-        "ms_occupancy_grid": round(main_r["ms_occ"], 3),
+                   "color_mlp": "(256+z+occ)->512->256->3", "guard_logit": 1e-3,
+                   "schedule": "grid and render concurrently on two streams "
+                               "(pifu_grid_and_render)"},
+        "ms_per_frame_serial": rnd(main_r["ms_serial"]),
+        "ms_occupancy_grid": rnd(main_r["ms_occ"]),
         "mlp_queries_per_s": round((occ_pts + ren_pts) / (main_r["ms"] * 1e-3), 1),
         "mlp_points_per_frame": {"occupancy_grid": occ_pts, "render": ren_pts,
                                  "color_hits": main_r["rst"][-1]["hits"]},
         "acceleration_vs_dense": round(257 ** 3 / max(occ_pts, 1), 2),
         "roofline": roofline(main_r, gemm_key, GEMM_DTYPE[gemm_key]),
+        # the same kernel family with nothing running beside it (serial calls)
+        "roofline_isolated": roofline(main_r, gemm_key, GEMM_DTYPE[gemm_key], isolated=True),
     }
     if base is not None:
         out["fp32_ms_per_frame"] = round(base["ms"], 3)
+        out["fp32_ms_per_frame_serial"] = rnd(base["ms_serial"])
         out["fp32_roofline"] = roofline(base, "gemm_f32", "fp32")
+        out["fp32_roofline_isolated"] = roofline(base, "gemm_f32", "fp32", isolated=True)
         out["fp32_mlp_queries_per_s"] = round(
             sum(s["mlp_points"] for s in base["gst"] + base["rst"]) / (base["ms"] * 1e-3), 1)
     out.update(extra)

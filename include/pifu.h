@@ -272,6 +272,58 @@ int32_t pifu_render_view(pifu_ctx* ctx, const pifu_field* occ_field, const pifu_
                          float* rgb, float* depth, uint8_t* hit, pifu_level_stats* stats,
                          void* workspace, size_t workspace_bytes, pifu_stream stream);
 
+/* ---------------------------------------------------------------- one frame */
+
+/* The arguments of one pifu_occupancy_grid call, as one record. */
+typedef struct pifu_grid_call {
+  const pifu_field* field;
+  const pifu_grid_opts* opts;
+  float* occ;
+  uint8_t* labels;
+  uint8_t* eval_level;          /* nullable */
+  uint32_t* cells;
+  uint32_t cells_cap;
+  uint32_t* n_cells;            /* host */
+  pifu_level_stats* stats;      /* host, nullable */
+  void* workspace;
+  size_t workspace_bytes;
+  pifu_stream stream;
+} pifu_grid_call;
+
+/* The arguments of one pifu_render_view call, as one record. */
+typedef struct pifu_render_call {
+  const pifu_field* occ_field;
+  const pifu_field* color_field;
+  const float* view;            /* host, 12 floats */
+  const pifu_render_opts* opts;
+  const float* bg;              /* host, 3 floats */
+  float* rgb;
+  float* depth;
+  uint8_t* hit;
+  pifu_level_stats* stats;      /* host, nullable */
+  void* workspace;
+  size_t workspace_bytes;
+  pifu_stream stream;
+} pifu_render_call;
+
+/*
+ * One frame of the method (Sec. 3.2): the surface localized on the input-view grid
+ * and a target view rendered without a mesh.  The two are independent (the render
+ * localizes the surface along its own rays, Eq. 3), so they run concurrently: the
+ * grid on the calling thread and grid->stream, the render on a second host thread
+ * with the handle's companion state and render->stream.  Many launches of either
+ * are too small to fill the GPU, and the other's work fills the gaps.  Every
+ * output, including the stats, is identical to pifu_occupancy_grid followed by
+ * pifu_render_view with the same arguments.  When the two streams are the same
+ * (or a second thread cannot be started) the calls run one after the other.
+ * Each call's arguments are validated as by its own entry point; the two
+ * workspaces and all outputs must not overlap.  Returns the grid's status if it
+ * failed, else the render's.  Kernel profiling (pifu_profile_enable on ctx)
+ * covers both.  Blocks until both are done.
+ */
+int32_t pifu_grid_and_render(pifu_ctx* ctx, const pifu_grid_call* grid,
+                             const pifu_render_call* render);
+
 /* ---------------------------------------------------------------- point evaluation */
 
 int32_t pifu_eval_points_workspace_size(const pifu_field* field, int32_t precision, uint32_t n,

@@ -5,4 +5,4 @@ from .pifu import (FIELD_ELLIPSOIDS, FIELD_MLP, FIELD_PLANE, BatchedGrid,  # noq
                    DeviceField, DeviceMLP, GridOutputs, RenderOutputs, autotune, autotune_clear,
                    convert, eval_points, grid_opts, load_library, occupancy_grid,
                    occupancy_grid_into, profile_enable, profile_read, render_opts, render_view,
-                   render_view_into)
+                   render_view_into, grid_and_render_into)

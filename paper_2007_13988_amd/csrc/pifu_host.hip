@@ -8,6 +8,7 @@
 #include <cstring>
 #include <map>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "pifu_internal.h"
@@ -35,6 +36,8 @@ struct pifu_ctx {
   uint32_t* prof_slots = nullptr;   // pinned, kProfSlots words (allocated when profiling starts)
   int prof_used = 0;
   pifu_kernel_profile prof[PIFU_KERN_COUNT];
+  // companion state for the second host thread of pifu_grid_and_render (null in a companion)
+  pifu_ctx* peer = nullptr;
 };
 
 namespace {
@@ -1076,6 +1079,46 @@ hipStream_t as_stream(pifu_stream s) { return reinterpret_cast<hipStream_t>(s); 
 // ================================================================== C ABI
 extern "C" {
 
+}  // extern "C"
+
+namespace {
+
+pifu_ctx* ctx_new(int dev) {
+  pifu_ctx* c = new (std::nothrow) pifu_ctx;
+  if (!c) return nullptr;
+  c->device = dev;
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->host_counters), sizeof(uint32_t) * kHostWords,
+                    hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return nullptr;
+  }
+  return c;
+}
+
+void ctx_free(pifu_ctx* c) {
+  if (!c) return;
+  if (c->host_counters) (void)hipHostFree(c->host_counters);
+  if (c->prof_slots) (void)hipHostFree(c->prof_slots);
+  for (hipEvent_t ev : c->events) (void)hipEventDestroy(ev);
+  delete c;
+}
+
+void prof_enable_one(pifu_ctx* c, bool on) {
+  c->prof_on = on;
+  if (on && !c->prof_slots &&
+      hipHostMalloc(reinterpret_cast<void**>(&c->prof_slots), sizeof(uint32_t) * kProfSlots,
+                    hipHostMallocDefault) != hipSuccess) {
+    c->prof_slots = nullptr;   // counted launches then report their fixed part only
+  }
+  c->pending.clear();
+  c->prof_used = 0;
+  std::memset(c->prof, 0, sizeof(c->prof));
+}
+
+}  // namespace
+
+extern "C" {
+
 int32_t pifu_create(pifu_ctx** out) {
   if (!out) return PIFU_ERR_INVALID_ARGUMENT;
   *out = nullptr;
@@ -1084,12 +1127,11 @@ int32_t pifu_create(pifu_ctx** out) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return PIFU_ERR_HIP;
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return PIFU_ERR_UNSUPPORTED;
-  pifu_ctx* c = new (std::nothrow) pifu_ctx;
+  pifu_ctx* c = ctx_new(dev);
   if (!c) return PIFU_ERR_HIP;
-  c->device = dev;
-  if (hipHostMalloc(reinterpret_cast<void**>(&c->host_counters), sizeof(uint32_t) * kHostWords,
-                    hipHostMallocDefault) != hipSuccess) {
-    delete c;
+  c->peer = ctx_new(dev);
+  if (!c->peer) {
+    ctx_free(c);
     return PIFU_ERR_HIP;
   }
   *out = c;
@@ -1098,10 +1140,8 @@ int32_t pifu_create(pifu_ctx** out) {
 
 void pifu_destroy(pifu_ctx* ctx) {
   if (!ctx) return;
-  if (ctx->host_counters) (void)hipHostFree(ctx->host_counters);
-  if (ctx->prof_slots) (void)hipHostFree(ctx->prof_slots);
-  for (hipEvent_t ev : ctx->events) (void)hipEventDestroy(ev);
-  delete ctx;
+  ctx_free(ctx->peer);
+  ctx_free(ctx);
 }
 
 const char* pifu_status_string(int32_t s) {
@@ -1295,6 +1335,54 @@ int32_t pifu_render_view(pifu_ctx* ctx, const pifu_field* occ_field, const pifu_
   return r;
 }
 
+// One frame: the grid on the calling thread, the render on a second host thread with
+// the companion state (its own pinned read-back words, events and profile records).
+// Both argument sets are checked before either call starts, so a rejected frame
+// launches nothing.
+int32_t pifu_grid_and_render(pifu_ctx* ctx, const pifu_grid_call* gc, const pifu_render_call* rc) {
+  if (!ctx || !gc || !rc) return PIFU_ERR_INVALID_ARGUMENT;
+  if (!gc->occ || !gc->labels || !gc->n_cells || !gc->workspace || (gc->cells_cap && !gc->cells) ||
+      !aligned(gc->workspace, kAlign))
+    return PIFU_ERR_INVALID_ARGUMENT;
+  if (!rc->view || !rc->bg || !rc->rgb || !rc->depth || !rc->hit || !rc->workspace ||
+      !aligned(rc->workspace, kAlign))
+    return PIFU_ERR_INVALID_ARGUMENT;
+  size_t need = 0;
+  if (int r = pifu_occupancy_grid_workspace_size(gc->field, gc->opts, &need)) return r;
+  if (gc->workspace_bytes < need) return PIFU_ERR_WORKSPACE_TOO_SMALL;
+  if (int r = pifu_render_view_workspace_size(rc->occ_field, rc->color_field, rc->opts, &need))
+    return r;
+  if (rc->workspace_bytes < need) return PIFU_ERR_WORKSPACE_TOO_SMALL;
+
+  auto grid = [gc](pifu_ctx* c) -> int32_t {
+    return pifu_occupancy_grid(c, gc->field, gc->opts, gc->occ, gc->labels, gc->eval_level,
+                               gc->cells, gc->cells_cap, gc->n_cells, gc->stats, gc->workspace,
+                               gc->workspace_bytes, gc->stream);
+  };
+  auto render = [rc](pifu_ctx* c) -> int32_t {
+    return pifu_render_view(c, rc->occ_field, rc->color_field, rc->view, rc->opts, rc->bg,
+                            rc->rgb, rc->depth, rc->hit, rc->stats, rc->workspace,
+                            rc->workspace_bytes, rc->stream);
+  };
+  pifu_ctx* p = ctx->peer;
+  std::thread t;
+  int32_t r_render = PIFU_OK;
+  if (p && gc->stream != rc->stream) {
+    try {
+      p->tile_cache = ctx->tile_cache;   // the render picks the same autotuned tiles
+      t = std::thread([p, &render, &r_render] {
+        r_render = hipSetDevice(p->device) == hipSuccess ? render(p) : PIFU_ERR_HIP;
+      });
+    } catch (...) {
+      // no second thread: the render runs after the grid on this thread
+    }
+  }
+  const int32_t r_grid = grid(ctx);
+  if (t.joinable()) t.join();
+  else r_render = render(ctx);
+  return r_grid ? r_grid : r_render;
+}
+
 int32_t pifu_eval_points_workspace_size(const pifu_field* field, int32_t precision, uint32_t n,
                                         size_t* bytes) {
   if (!bytes || !field) return PIFU_ERR_INVALID_ARGUMENT;
@@ -1357,15 +1445,8 @@ int32_t pifu_eval_points(pifu_ctx* ctx, const pifu_field* field, int32_t precisi
 
 int32_t pifu_profile_enable(pifu_ctx* ctx, int32_t on) {
   if (!ctx) return PIFU_ERR_INVALID_ARGUMENT;
-  ctx->prof_on = on != 0;
-  if (ctx->prof_on && !ctx->prof_slots &&
-      hipHostMalloc(reinterpret_cast<void**>(&ctx->prof_slots), sizeof(uint32_t) * kProfSlots,
-                    hipHostMallocDefault) != hipSuccess) {
-    ctx->prof_slots = nullptr;   // counted launches then report their fixed part only
-  }
-  ctx->pending.clear();
-  ctx->prof_used = 0;
-  std::memset(ctx->prof, 0, sizeof(ctx->prof));
+  prof_enable_one(ctx, on != 0);
+  if (ctx->peer) prof_enable_one(ctx->peer, on != 0);
   return PIFU_OK;
 }
 
@@ -1500,6 +1581,14 @@ int32_t pifu_autotune_clear(pifu_ctx* ctx) {
 int32_t pifu_profile_read(pifu_ctx* ctx, pifu_kernel_profile* out) {
   if (!ctx || !out) return PIFU_ERR_INVALID_ARGUMENT;
   std::memcpy(out, ctx->prof, sizeof(ctx->prof));
+  if (const pifu_ctx* p = ctx->peer) {   // launches made by pifu_grid_and_render's second thread
+    for (int k = 0; k < PIFU_KERN_COUNT; ++k) {
+      out[k].launches += p->prof[k].launches;
+      out[k].total_ms += p->prof[k].total_ms;
+      out[k].flops += p->prof[k].flops;
+      out[k].bytes += p->prof[k].bytes;
+    }
+  }
   return PIFU_OK;
 }
 

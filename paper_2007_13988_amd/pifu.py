@@ -72,6 +72,24 @@ class PifuGridOut(C.Structure):
                 ("stats", C.POINTER(PifuLevelStats))]
 
 
+class PifuGridCall(C.Structure):
+    _fields_ = [("field", C.POINTER(PifuField)), ("opts", C.POINTER(PifuGridOpts)),
+                ("occ", C.c_void_p), ("labels", C.c_void_p), ("eval_level", C.c_void_p),
+                ("cells", C.c_void_p), ("cells_cap", C.c_uint32),
+                ("n_cells", C.POINTER(C.c_uint32)), ("stats", C.POINTER(PifuLevelStats)),
+                ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
+                ("stream", C.c_void_p)]
+
+
+class PifuRenderCall(C.Structure):
+    _fields_ = [("occ_field", C.POINTER(PifuField)), ("color_field", C.POINTER(PifuField)),
+                ("view", C.POINTER(C.c_float)), ("opts", C.POINTER(PifuRenderOpts)),
+                ("bg", C.POINTER(C.c_float)), ("rgb", C.c_void_p), ("depth", C.c_void_p),
+                ("hit", C.c_void_p), ("stats", C.POINTER(PifuLevelStats)),
+                ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
+                ("stream", C.c_void_p)]
+
+
 class PifuKernelProfile(C.Structure):
     _fields_ = [("launches", C.c_uint64), ("total_ms", C.c_double), ("flops", C.c_double),
                 ("bytes", C.c_double)]
@@ -88,7 +106,7 @@ EXPORTS = ["pifu_create", "pifu_destroy", "pifu_status_string",
            "pifu_profile_enable", "pifu_profile_read", "pifu_mlp_train_workspace_size",
            "pifu_mlp_grad", "pifu_rmsprop_step", "pifu_occupancy_grid_batched_workspace_size",
            "pifu_occupancy_grid_batched", "pifu_autotune_mlp", "pifu_autotune_clear",
-           "pifu_convert_f32"]
+           "pifu_convert_f32", "pifu_grid_and_render"]
 
 _lib = None
 
@@ -132,6 +150,7 @@ def load_library():
     lib.pifu_autotune_mlp.argtypes = [P, C.POINTER(PifuField), i32, u32, C.POINTER(i32), P, sz, P]
     lib.pifu_autotune_clear.argtypes = [P]
     lib.pifu_convert_f32.argtypes = [P, P, u32, i32, P, P]
+    lib.pifu_grid_and_render.argtypes = [P, C.POINTER(PifuGridCall), C.POINTER(PifuRenderCall)]
     lib.pifu_profile_enable.argtypes = [P, i32]
     lib.pifu_profile_read.argtypes = [P, C.POINTER(PifuKernelProfile)]
     for name in EXPORTS:
@@ -392,6 +411,25 @@ def render_view_into(occ_field: DeviceField, color_field: DeviceField, view, bg,
                               C.byref(out.opts), b, _ptr(out.rgb), _ptr(out.depth), _ptr(out.hit),
                               out.stats, _ptr(out.ws), out.ws_bytes, _stream(stream))
     _check(st, "pifu_render_view")
+
+
+def grid_and_render_into(field: DeviceField, gout: GridOutputs, color_field: DeviceField, view, bg,
+                         rout: RenderOutputs, grid_stream=None, render_stream=None) -> None:
+    """One frame (see pifu_grid_and_render in include/pifu.h): the occupancy grid on
+    grid_stream and the render of `view` on render_stream, run concurrently when the
+    two streams differ.  Same outputs as occupancy_grid_into + render_view_into."""
+    lib = load_library()
+    v = (C.c_float * 12)(*[float(x) for x in np.asarray(view, np.float32).reshape(-1)])
+    b = (C.c_float * 3)(*[float(x) for x in bg])
+    g = PifuGridCall(C.pointer(field.struct), C.pointer(gout.opts), _ptr(gout.occ),
+                     _ptr(gout.labels), _ptr(gout.eval_level), _ptr(gout.cells), gout.cells_cap,
+                     C.pointer(gout.n_cells), C.cast(gout.stats, C.POINTER(PifuLevelStats)),
+                     _ptr(gout.ws), gout.ws_bytes, _stream(grid_stream))
+    r = PifuRenderCall(C.pointer(field.struct), C.pointer(color_field.struct), v,
+                       C.pointer(rout.opts), b, _ptr(rout.rgb), _ptr(rout.depth), _ptr(rout.hit),
+                       C.cast(rout.stats, C.POINTER(PifuLevelStats)), _ptr(rout.ws),
+                       rout.ws_bytes, _stream(render_stream))
+    _check(lib.pifu_grid_and_render(context(), C.byref(g), C.byref(r)), "pifu_grid_and_render")
 
 
 def render_view(occ_field: DeviceField, color_field: DeviceField, view, log2_w: int, log2_d: int,

@@ -49,6 +49,9 @@ int main(void) {
          sizeof(pifu_grid_opts), sizeof(pifu_render_opts), sizeof(pifu_kernel_profile));
   printf("%zu %zu %zu\n", offsetof(pifu_field, feat), offsetof(pifu_field, ell),
          offsetof(pifu_mlp, fp8_amax));
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(pifu_grid_call), sizeof(pifu_render_call),
+         offsetof(pifu_grid_call, n_cells), offsetof(pifu_grid_call, stream),
+         offsetof(pifu_render_call, stats), offsetof(pifu_render_call, stream));
   return 0;
 }
 """
@@ -64,6 +67,10 @@ int main(void) {
                      C.sizeof(P.PifuKernelProfile)]
     offs = [int(x) for x in lines[1].split()]
     assert offs == [P.PifuField.feat.offset, P.PifuField.ell.offset, P.PifuMLP.fp8_amax.offset]
+    calls = [int(x) for x in lines[2].split()]
+    assert calls == [C.sizeof(P.PifuGridCall), C.sizeof(P.PifuRenderCall),
+                     P.PifuGridCall.n_cells.offset, P.PifuGridCall.stream.offset,
+                     P.PifuRenderCall.stats.offset, P.PifuRenderCall.stream.offset]
 
 
 def _ell_field(P):
@@ -141,3 +148,54 @@ def test_mlp_field_validation_checks_weight_pointers(P):
     m.b[1] = 0x210000
     m.widths[0] = 96                           # hidden width not a multiple of 64
     assert _ws(P, _F, P.grid_opts(5, 3))[0] == -1
+
+
+def test_grid_and_render_validates_both_calls_first(P):
+    """pifu_grid_and_render checks both argument sets before either call starts; a
+    rejected frame returns before the handle is touched, so a stand-in handle
+    address serves here."""
+    lib = P.load_library()
+    f = _ell_field(P)
+    go = P.grid_opts(5, 3)
+    ro = P.render_opts(6, 5, 3)
+    n_cells = C.c_uint32()
+    v = (C.c_float * 12)(1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0)
+    b = (C.c_float * 3)(0, 0, 0)
+    _, gws = _ws(P, f, go)
+    rws = C.c_size_t()
+    assert lib.pifu_render_view_workspace_size(C.byref(f.struct), C.byref(f.struct), C.byref(ro),
+                                               C.byref(rws)) == -1   # colour field must be an MLP
+    col = P.PifuField()
+    col.kind, col.H, col.W, col.C = P.FIELD_MLP, 32, 32, 64
+    m = P.PifuMLP()
+    m.n_layers, m.feat_dim, m.n_extra = 2, 64, 2
+    m.hidden_act, m.out_act = P.ACT["relu"], P.ACT["tanh"]
+    m.widths[0], m.widths[1] = 64, 3
+    for l in range(2):
+        m.W[l] = 0x100000 + 0x10000 * l
+        m.b[l] = 0x200000 + 0x10000 * l
+    col.feat = 0x300000
+    col.mlp = C.pointer(m)
+    assert lib.pifu_render_view_workspace_size(C.byref(f.struct), C.byref(col), C.byref(ro),
+                                               C.byref(rws)) == 0
+    fake = C.c_void_p(0x1000)   # stand-in device addresses (256-byte aligned); nothing launches
+
+    def calls(gws_bytes=gws, rws_bytes=rws.value, occ=0x400000, rgb=0x500000):
+        g = P.PifuGridCall(C.pointer(f.struct), C.pointer(go), occ, 0x410000, None, None, 0,
+                           C.pointer(n_cells), None, 0x420000, gws_bytes, None)
+        r = P.PifuRenderCall(C.pointer(f.struct), C.pointer(col), v, C.pointer(ro), b, rgb,
+                             0x510000, 0x520000, None, 0x530000, rws_bytes, None)
+        return g, r
+
+    assert lib.pifu_grid_and_render(None, None, None) == -1
+    g, r = calls()
+    assert lib.pifu_grid_and_render(fake, None, C.byref(r)) == -1
+    assert lib.pifu_grid_and_render(fake, C.byref(g), None) == -1
+    g, r = calls(occ=0)                         # grid output missing
+    assert lib.pifu_grid_and_render(fake, C.byref(g), C.byref(r)) == -1
+    g, r = calls(rgb=0)                         # render output missing
+    assert lib.pifu_grid_and_render(fake, C.byref(g), C.byref(r)) == -1
+    g, r = calls(gws_bytes=gws - 1)
+    assert lib.pifu_grid_and_render(fake, C.byref(g), C.byref(r)) == -2
+    g, r = calls(rws_bytes=rws.value - 1)
+    assert lib.pifu_grid_and_render(fake, C.byref(g), C.byref(r)) == -2
