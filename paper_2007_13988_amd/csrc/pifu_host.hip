@@ -3,7 +3,10 @@
 // Eq. 3) and the C ABI declared in include/pifu.h.
 #include <hip/hip_runtime.h>
 
+#include <immintrin.h>
+
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -27,7 +30,11 @@ constexpr int kProfSlots = 16384;   // device-side counts per call that the prof
 
 struct pifu_ctx {
   int device;
-  uint32_t* host_counters;   // pinned read-back buffer, kHostWords words
+  // read-back words: mapped, fine-grained pinned memory (kHostWords words, then the
+  // sequence word that the publish kernel sets last); host_counters_dev is its device view
+  uint32_t* host_counters;
+  uint32_t* host_counters_dev = nullptr;
+  uint32_t seq = 0;          // sequence number of the last read-back
   // autotuned point tile per (precision, N, K, batch bucket); filled by pifu_autotune_mlp
   std::map<uint64_t, int> tile_cache;
   bool prof_on = false;
@@ -457,11 +464,29 @@ int pick_tile(const EvalCtx& e, int prec, int N, int K, uint32_t m) {
   return it == e.ctx->tile_cache.end() ? default_tile(prec, N, K, m) : it->second;
 }
 
+// Brings counters [0, nwords) back to host_counters.  A one-workgroup kernel writes them
+// into mapped host memory and then a sequence number; it runs after all earlier work on
+// the stream, so the counts are final.  The host spins on the sequence word (a round
+// trip about 4 us shorter than a copy plus a stream synchronization), and after 2 ms
+// falls back to blocking on the stream, so the wait always ends.
 int read_counters(EvalCtx& e, int nwords) {
-  HIP_TRY(hipMemcpyAsync(e.ctx->host_counters, e.counters, sizeof(uint32_t) * nwords,
-                         hipMemcpyDeviceToHost, e.s));
+  pifu_ctx* c = e.ctx;
+  if (nwords < 1 || nwords > kHostWords) return PIFU_ERR_INVALID_ARGUMENT;
+  const uint32_t seq = ++c->seq;
+  launch_publish(e.counters, nwords, c->host_counters_dev, c->host_counters_dev + kHostWords, seq,
+                 e.s);
+  HIP_TRY(hipGetLastError());
+  uint32_t* word = c->host_counters + kHostWords;
+  const auto t0 = std::chrono::steady_clock::now();
+  for (uint32_t i = 1;; ++i) {
+    if (__atomic_load_n(word, __ATOMIC_ACQUIRE) == seq) return PIFU_OK;
+    if ((i & 1023) == 0 &&
+        std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(2000))
+      break;
+    _mm_pause();
+  }
   HIP_TRY(hipStreamSynchronize(e.s));
-  return PIFU_OK;
+  return __atomic_load_n(word, __ATOMIC_ACQUIRE) == seq ? PIFU_OK : PIFU_ERR_HIP;
 }
 
 // |p - 0.5| < delta  <=>  |logit| < log((0.5 + delta) / (0.5 - delta)).
@@ -1087,8 +1112,16 @@ pifu_ctx* ctx_new(int dev) {
   pifu_ctx* c = new (std::nothrow) pifu_ctx;
   if (!c) return nullptr;
   c->device = dev;
-  if (hipHostMalloc(reinterpret_cast<void**>(&c->host_counters), sizeof(uint32_t) * kHostWords,
-                    hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->host_counters),
+                    sizeof(uint32_t) * (kHostWords + 64),
+                    hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+    delete c;
+    return nullptr;
+  }
+  std::memset(c->host_counters, 0, sizeof(uint32_t) * (kHostWords + 64));
+  if (hipHostGetDevicePointer(reinterpret_cast<void**>(&c->host_counters_dev), c->host_counters,
+                              0) != hipSuccess) {
+    (void)hipHostFree(c->host_counters);
     delete c;
     return nullptr;
   }
@@ -1208,6 +1241,7 @@ int32_t pifu_occupancy_grid(pifu_ctx* ctx, const pifu_field* field, const pifu_g
                       1, fin, &nc);
     *n_cells = nc;
   }
+  if (!r) r = hipStreamSynchronize(s) == hipSuccess ? PIFU_OK : PIFU_ERR_HIP;
   prof_resolve(ctx);
   delete gp;
   return r;

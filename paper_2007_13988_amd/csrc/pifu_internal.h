@@ -93,6 +93,10 @@ constexpr int COMPACT_TILE = COMPACT_BLOCK * COMPACT_PER_THREAD;
 
 // ------------------------------------------------------------------ level kernels
 void launch_fill_u8(uint8_t* p, uint8_t v, size_t n, hipStream_t s);
+// host[0 .. n) = c[0 .. n) (host: device view of mapped fine-grained host memory), then
+// *seq_word = seq once those stores are visible to the host
+void launch_publish(const uint32_t* c, int n, uint32_t* host, uint32_t* seq_word, uint32_t seq,
+                    hipStream_t s);
 void launch_iota(uint32_t* list, uint32_t n, hipStream_t s);
 // frames > 1: `frames` lattices stored back to back (coarse and fine), one grid row each.
 // Frames of one batched call; per frame, where its occupancy goes at a level (null:

@@ -18,6 +18,24 @@ void launch_fill_u8(uint8_t* p, uint8_t v, size_t n, hipStream_t s) {
   if (n) hipLaunchKernelGGL(k_fill_u8, dim3(grid1d(n, 256)), dim3(256), 0, s, p, v, n);
 }
 
+// Count read-back: words c[0 .. n) to host-mapped, fine-grained memory, then the
+// sequence number the host waits for.  Every lane makes its stores visible at system
+// scope before the barrier, so the release store of the sequence word is ordered
+// after all of them.
+__global__ void __launch_bounds__(256) k_publish(const uint32_t* __restrict__ c, int n,
+                                                 uint32_t* host, uint32_t* seq_word, uint32_t seq) {
+  for (int t = threadIdx.x; t < n; t += blockDim.x)
+    __hip_atomic_store(host + t, c[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(seq_word, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+void launch_publish(const uint32_t* c, int n, uint32_t* host, uint32_t* seq_word, uint32_t seq,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(k_publish, dim3(1), dim3(256), 0, s, c, n, host, seq_word, seq);
+}
+
 __global__ void k_iota(uint32_t* __restrict__ list, uint32_t n) {
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) list[i] = i;
