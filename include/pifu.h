@@ -18,9 +18,10 @@
  *  - Every call validates its arguments on the host before any launch and
  *    returns a negative status without touching device memory on failure.
  *    No C++ exception crosses this boundary.
- *  - pifu_occupancy_grid and pifu_render_view block until their work on
- *    `stream` is complete (the conflict loop's trip count is read back between
- *    waves); results are then visible to later work on any stream.
+ *  - pifu_occupancy_grid, pifu_render_view and pifu_grid_and_render block until
+ *    their work on their streams is complete (the conflict loop's trip count is
+ *    read back between waves); results are then visible to later work on any
+ *    stream.
  *  - The library never allocates device memory during a call: scratch comes
  *    from the caller's workspace, sized by the matching *_workspace_size query.
  */
@@ -186,8 +187,10 @@ typedef struct pifu_render_opts {
 /* ---------------------------------------------------------------- handle */
 
 /* Creates a handle bound to the current HIP device (must be gfx950).  The
- * handle owns a few bytes of pinned host memory for count read-back and never
- * allocates device memory.  One handle must not be used by two threads at once. */
+ * handle owns about 1 KB of mapped pinned host memory for count read-back (and
+ * the same again for the companion state that pifu_grid_and_render's second
+ * thread uses) and never allocates device memory.  One handle must not be used
+ * by two threads at once. */
 int32_t pifu_create(pifu_ctx** out);
 void pifu_destroy(pifu_ctx* ctx);
 const char* pifu_status_string(int32_t status);
