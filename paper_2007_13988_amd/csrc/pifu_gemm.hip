@@ -306,8 +306,13 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_h16(GemmArgs a) {
   constexpr int A_LOADS = BM * (BK / 8) / NT;
   constexpr int B_LOADS = BN * (BK / 8) / NT;
   constexpr int S_LOADS = A_LOADS > B_LOADS ? A_LOADS : B_LOADS;
-  // one staging set, used in turn for the next stage's A tile and then its B tile
+  // Large tiles: one staging set, used in turn for the next stage's A tile and then its
+  // B tile (registers are scarce).  Tiles up to 128 x 128 give B a set of its own, so
+  // that both loads of the next stage are in flight while this stage computes: their
+  // short k loops are bound by load latency, not by MFMA time.
+  constexpr bool kTwoSets = BM * BN <= 128 * 128;
   u32x4 rs[S_LOADS];
+  u32x4 rb[kTwoSets ? B_LOADS : 1];
   const __bf16* A1 = reinterpret_cast<const __bf16*>(a.A1);
   const __bf16* A2 = reinterpret_cast<const __bf16*>(a.A2);
   const __bf16* Wp = reinterpret_cast<const __bf16*>(a.W);
@@ -334,13 +339,13 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_h16(GemmArgs a) {
                      : (u32x4){0u, 0u, 0u, 0u};
     }
   };
-  auto gload_b = [&](int kt) {
+  auto gload_b = [&](int kt, u32x4* dst) {
     const int k0 = kt * BK;
 #pragma unroll
     for (int i = 0; i < B_LOADS; ++i) {
       const int e = tid + NT * i;
       const int row = e >> 3, c8 = e & 7;
-      rs[i] = *reinterpret_cast<const u32x4*>(Wp + (size_t)(n0 + row) * a.ldw + k0 + 8 * c8);
+      dst[i] = *reinterpret_cast<const u32x4*>(Wp + (size_t)(n0 + row) * a.ldw + k0 + 8 * c8);
     }
   };
   auto sstore_a = [&](int buf) {
@@ -350,11 +355,11 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_h16(GemmArgs a) {
       *reinterpret_cast<u32x4*>(&As[buf * BM * LD + (e >> 3) * LD + 8 * (e & 7)]) = rs[i];
     }
   };
-  auto sstore_b = [&](int buf) {
+  auto sstore_b = [&](int buf, const u32x4* src) {
 #pragma unroll
     for (int i = 0; i < B_LOADS; ++i) {
       const int e = tid + NT * i;
-      *reinterpret_cast<u32x4*>(&Bs[buf * BN * LD + (e >> 3) * LD + 8 * (e & 7)]) = rs[i];
+      *reinterpret_cast<u32x4*>(&Bs[buf * BN * LD + (e >> 3) * LD + 8 * (e & 7)]) = src[i];
     }
   };
 
@@ -393,28 +398,48 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_h16(GemmArgs a) {
 
   gload_a(0);
   sstore_a(0);
-  gload_b(0);
-  sstore_b(0);
+  gload_b(0, rs);
+  sstore_b(0, rs);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
     const bool more = kt + 1 < nk;
-    if (more) gload_a(kt + 1);
-    load_frags(buf, 0, 0);
-    load_frags(buf, 16, 1);
-    mfmas(0);
-    load_frags(buf, 32, 0);
-    mfmas(1);
-    // the other buffer was last read before the previous barrier: stage A there, then
-    // reuse the staging registers for B
-    if (more) {
-      sstore_a(buf ^ 1);
-      gload_b(kt + 1);
+    if constexpr (kTwoSets) {
+      if (more) {
+        gload_a(kt + 1);
+        gload_b(kt + 1, rb);
+      }
+      load_frags(buf, 0, 0);
+      load_frags(buf, 16, 1);
+      mfmas(0);
+      load_frags(buf, 32, 0);
+      mfmas(1);
+      load_frags(buf, 48, 1);
+      mfmas(0);
+      mfmas(1);
+      // the other buffer was last read before the previous barrier
+      if (more) {
+        sstore_a(buf ^ 1);
+        sstore_b(buf ^ 1, rb);
+      }
+    } else {
+      if (more) gload_a(kt + 1);
+      load_frags(buf, 0, 0);
+      load_frags(buf, 16, 1);
+      mfmas(0);
+      load_frags(buf, 32, 0);
+      mfmas(1);
+      // the other buffer was last read before the previous barrier: stage A there, then
+      // reuse the staging registers for B
+      if (more) {
+        sstore_a(buf ^ 1);
+        gload_b(kt + 1, rs);
+      }
+      load_frags(buf, 48, 1);
+      mfmas(0);
+      mfmas(1);
+      if (more) sstore_b(buf ^ 1, rs);
     }
-    load_frags(buf, 48, 1);
-    mfmas(0);
-    mfmas(1);
-    if (more) sstore_b(buf ^ 1);
     __syncthreads();
   }
   if constexpr (OUT16) {
