@@ -177,3 +177,21 @@ def test_concurrent_frame_dense_grid_with_eval_level(pifu):
     assert torch.equal(r1.hit, r2.hit) and int(r2.hit.sum()) > 0
     assert torch.equal(_bits(r1.depth), _bits(r2.depth))
     assert torch.equal(_bits(r1.rgb), _bits(r2.rgb))
+
+
+def test_concurrent_frame_full_size_matches_separate_calls(pifu):
+    """The benchmark's sizes and launch configuration: a 256^3 grid from 32^3 and a
+    512 x 512 x 256 render from 64 x 64 x 32 on the PIFu-size network, FP16 with the
+    split-FP16 band.  The concurrent frame equals the two calls bit for bit."""
+    fld = pifu.DeviceField.mlp_field(synth.pifu_sequence(102, 0), synth.pifu_mlp())
+    col = pifu.DeviceField.mlp_field(synth.color_features(), synth.color_mlp())
+    view, bg = synth.yaw_view(90.0), (0.0, 0.0, 0.0)
+    kw = dict(precision="fp16", band_delta=0.0075, guard_logit=1e-3)
+    g1, r1 = _frame_outputs(pifu, fld, col, kw, kw, grid=(8, 5), render=(9, 8, 6))
+    g2, r2 = _frame_outputs(pifu, fld, col, kw, kw, grid=(8, 5), render=(9, 8, 6))
+    s1, s2 = torch.cuda.current_stream(), torch.cuda.Stream()
+    pifu.occupancy_grid_into(fld, g1, s1)
+    pifu.render_view_into(fld, col, view, bg, r1, s1)
+    pifu.grid_and_render_into(fld, g2, col, view, bg, r2, s1, s2)
+    _assert_same(g1, r1, g2, r2)
+    assert g2.n_cells.value > 100000 and int(r2.hit.sum()) > 50000
