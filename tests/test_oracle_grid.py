@@ -5,7 +5,6 @@ definition (explicit corner enumeration, scipy's morphology, a randomized work-l
 closure written with plain loops, dense evaluation, the half-space argument).
 """
 import itertools
-import random
 
 import numpy as np
 import pytest
@@ -13,6 +12,7 @@ import scipy.ndimage as ndi
 
 import synth
 from oracle import pifu_oracle as O
+from brute import brute_localize as _brute_localize
 
 
 # ---------------------------------------------------------------- trilinear x2
@@ -61,70 +61,16 @@ def test_neighbourhood26_matches_scipy_binary_dilation(seed):
 
 # ---------------------------------------------------------------- brute-force localization
 
-def _brute_localize(logit_fn, n0, T, seed):
-    """Independent implementation with plain loops and a randomized work list.
-
-    Cube lattices only: level t has n0 * 2^t cells per axis.  Returns per-level
-    sets of evaluated (i, j, k) on each level's lattice and the final labels.
-    """
-    rnd = random.Random(seed)
-    cells = n0
-    nodes = [(i, j, k) for i in range(cells + 1) for j in range(cells + 1) for k in range(cells + 1)]
-    coord = lambda q, c: tuple(-1.0 + 2.0 * x / c for x in q)
-    label = {q: int(logit_fn(coord(q, cells)) > 0) for q in nodes}
-    done = set(nodes)
-    per_level = [set(nodes)]
-    for t in range(1, T + 1):
-        cells *= 2
-        rng_ = range(cells + 1)
-        new_label = {}
-        interp = {}
-        new_done = set()
-        for q in itertools.product(rng_, rng_, rng_):
-            corners = list(itertools.product(*[sorted({x // 2, (x + 1) // 2}) for x in q]))
-            vals = [label[c] for c in corners]
-            interp[q] = sum(vals) / len(vals)
-            if all(x % 2 == 0 for x in q):
-                new_label[q] = label[tuple(x // 2 for x in q)]
-                if tuple(x // 2 for x in q) in done:
-                    new_done.add(q)
-            else:
-                new_label[q] = 1 if interp[q] > 0.5 else 0
-        nb = lambda q: [(q[0] + a, q[1] + b, q[2] + c) for a in (-1, 0, 1) for b in (-1, 0, 1)
-                        for c in (-1, 0, 1)
-                        if 0 <= q[0] + a <= cells and 0 <= q[1] + b <= cells and 0 <= q[2] + c <= cells]
-        b0 = [q for q in interp if 0 < interp[q] < 1]
-        work = sorted({w for q in b0 for w in nb(q) if w not in new_done})
-        rnd.shuffle(work)
-        queued = set(work)
-        evaluated_here = set()
-        while work:
-            q = work.pop()
-            lg = logit_fn(coord(q, cells))
-            new_label[q] = int(lg > 0)
-            new_done.add(q)
-            evaluated_here.add(q)
-            if new_label[q] != int(interp[q] > 0.5):
-                for w in nb(q):
-                    if w not in new_done and w not in queued:
-                        queued.add(w)
-                        work.insert(rnd.randrange(len(work) + 1), w)
-        label = new_label
-        done = new_done
-        per_level.append(evaluated_here)
-    return per_level, label, cells
-
-
 def _check_against_brute(fld, n0_log2, T, seeds=(0, 1)):
     res = O.occupancy_grid(fld, n0_log2 + T, n0_log2)
     fn = lambda P: float(O.field_logit(fld, np.array([P]))[0])
     for seed in seeds:
-        per_level, label, cells = _brute_localize(fn, 1 << n0_log2, T, seed)
+        per_level, label, cells, _, _ = _brute_localize(fn, 1 << n0_log2, T, seed)
         for t, rec in enumerate(res["levels"]):
             n = rec.dims[0]
             got = {(int(x // (n * n)), int((x // n) % n), int(x % n)) for x in rec.evaluated}
             assert got == per_level[t], f"level {t} evaluated sets differ"
-        lab = np.zeros((cells + 1,) * 3, np.uint8)
+        lab = np.zeros(tuple(c + 1 for c in cells), np.uint8)
         for q, v in label.items():
             lab[q] = v
         assert np.array_equal(lab, res["labels"])
@@ -139,6 +85,47 @@ def test_localization_matches_randomized_worklist_closure_mlp():
 def test_localization_matches_randomized_worklist_closure_ellipsoids():
     ell = synth.ellipsoids(3, 11, scale=0.6)
     _check_against_brute(O.Field("ellipsoids", ell=ell, sharpness=8.0), 1, 3)
+
+
+def _check_aniso_against_brute(logit_fn_vec, n0, T, seeds=(0, 1)):
+    """O.localize on an anisotropic lattice (the render's: 2^Lw x 2^Lw x 2^Ld cells,
+    all axes refined together) against the plain-loop closure."""
+    fin = tuple(int(np.log2(c)) + T for c in n0)
+    res = O.localize(logit_fn_vec, fin, T)
+    fn = lambda P: float(logit_fn_vec(np.array([P]))[0])
+    for seed in seeds:
+        per_level, label, cells, _, _ = _brute_localize(fn, n0, T, seed)
+        for t, rec in enumerate(res.levels):
+            nx, ny, nz = rec.dims
+            got = {(int(x // (ny * nz)), int((x // nz) % ny), int(x % nz)) for x in rec.evaluated}
+            assert got == per_level[t], f"level {t} evaluated sets differ"
+        lab = np.zeros(tuple(c + 1 for c in cells), np.uint8)
+        for q, v in label.items():
+            lab[q] = v
+        assert np.array_equal(lab, res.label)
+    return res
+
+
+def test_anisotropic_localization_matches_brute_mlp():
+    feat = synth.feature_map(16, 16, 8, 2.0, 7)
+    fld = O.Field("mlp", feat=feat, mlp=synth.he_mlp(8, 1, [16, 8, 1], [False] * 3, 8))
+    res = _check_aniso_against_brute(lambda P: O.field_logit(fld, P), (4, 4, 2), 2)
+    assert res.dims == (17, 17, 9)
+    assert sum(r.stats["evaluated"] for r in res.levels[1:]) > 0
+
+
+@pytest.mark.parametrize("yaw", [0.0, 90.0])
+def test_anisotropic_localization_matches_brute_ellipsoids_through_a_view(yaw):
+    """The render localizes on its target lattice through the view transform (with the
+    clip to the input volume); the closure must be the same on that lattice."""
+    # semi-axes scaled 1.5x: some shapes reach past the input volume, so the clip to
+    # [-1,1]^3 after the view transform is exercised too
+    fld = O.Field("ellipsoids", ell=synth.ellipsoids(4, 12, scale=1.5), sharpness=8.0)
+    view = synth.yaw_view(yaw)
+    res = _check_aniso_against_brute(lambda P: O.view_logit(fld, view, P), (4, 4, 2), 2,
+                                     seeds=(3,))
+    assert res.label.any()
+    assert all(r.stats["evaluated"] > 0 for r in res.levels)
 
 
 # ---------------------------------------------------------------- invariants
@@ -201,6 +188,67 @@ def test_sphere_logit_closed_form():
                        rtol=0, atol=1e-12)
     on = np.array([[1, 0, 0], [0, -1, 0], [0, 0, 1.0]]) / inv
     assert np.allclose(O.field_logit(fld, on), 0, atol=1e-12)
+
+
+def _ellipsoid_record(c, a, quat_xyzw):
+    """A 12-float record (centre, then M = diag(1/a) R^T) built with scipy's rotation
+    from a unit quaternion: independent of the input generator's own formula."""
+    from scipy.spatial.transform import Rotation
+    R = Rotation.from_quat(quat_xyzw).as_matrix()
+    M = np.diag(1.0 / np.asarray(a, np.float64)) @ R.T
+    return np.concatenate([np.asarray(c, np.float64), M.reshape(-1)]), R
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_rotated_offcentre_ellipsoid_closed_form(seed):
+    """logit = k (1 - |diag(1/a) R^T (P - c)|^2) for a rotated, off-centre ellipsoid
+    (the analytic stand-in): the points c + R diag(a) s u with |u| = 1 give exactly
+    k (1 - s^2) -- 0 on the surface, k at the centre.  A transposed M, a sign error in
+    the centre or a misplaced semi-axis all move these points off their values."""
+    g = np.random.default_rng(seed)
+    c = g.uniform(-0.4, 0.4, 3)
+    a = np.array([0.2, 0.3, 0.45])[g.permutation(3)]
+    q = g.standard_normal(4)
+    q /= np.linalg.norm(q)
+    rec, R = _ellipsoid_record(c, a, q)
+    k = 8.0
+    fld = O.Field("ellipsoids", ell=rec[None, :], sharpness=k)
+    u = g.standard_normal((200, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    for s in (0.0, 0.5, 1.0, 1.5):
+        P = c + (s * u * a) @ R.T
+        assert np.allclose(O.field_logit(fld, P), k * (1.0 - s * s), rtol=0, atol=1e-12)
+    # the principal axes: c +- a_i R e_i are on the surface, c +- a_i R e_j (j != i,
+    # a_j != a_i) are not
+    for i in range(3):
+        P = c + np.array([a[i] * R[:, i], -a[i] * R[:, i]])
+        assert np.allclose(O.field_logit(fld, P), 0.0, atol=1e-12)
+        j = (i + 1) % 3
+        P = c + a[i] * R[:, j][None, :]
+        assert abs(O.field_logit(fld, P)[0]) > 0.1
+
+
+def test_ellipsoid_union_takes_the_nearest_inside_shape():
+    """Union of two disjoint rotated ellipsoids: each one's centre has logit k (the
+    minimum of q is 0 there) and a point on either surface, outside the other, has
+    logit 0; far points are negative."""
+    g = np.random.default_rng(9)
+    recs, Rs, cs, As = [], [], [], []
+    for c in (np.array([-0.5, 0.1, 0.0]), np.array([0.5, -0.2, 0.1])):
+        a = g.uniform(0.1, 0.3, 3)
+        q = g.standard_normal(4)
+        rec, R = _ellipsoid_record(c, a, q / np.linalg.norm(q))
+        recs.append(rec)
+        Rs.append(R)
+        cs.append(c)
+        As.append(a)
+    fld = O.Field("ellipsoids", ell=np.stack(recs), sharpness=4.0)
+    assert np.allclose(O.field_logit(fld, np.stack(cs)), 4.0, atol=1e-12)
+    u = g.standard_normal((50, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    for c, a, R in zip(cs, As, Rs):
+        assert np.allclose(O.field_logit(fld, c + (u * a) @ R.T), 0.0, atol=1e-12)
+    assert np.all(O.field_logit(fld, np.array([[0.0, 0.9, 0.9], [0.95, 0.95, -0.95]])) < 0)
 
 
 def test_surface_cells_bruteforce():

@@ -12,6 +12,7 @@ import pytest
 import torch
 
 import synth
+from brute import brute_localize
 from oracle import pifu_oracle as O
 
 
@@ -30,8 +31,9 @@ def _brute_render(occ_fld, col_fld, view, lw, ld, lcw, bg):
     """Per-ray brute force of the last render level (plain loops)."""
     T = lw - lcw
     W, D = 1 << lw, 1 << ld
-    loc = O.localize(lambda P: O.view_logit(occ_fld, view, P), (lw, lw, ld), T, last_level=T - 1)
-    labc, valc, evc = loc.label, loc.val, loc.evaluated
+    # levels below L: the plain-loop closure on the anisotropic target lattice
+    fn = lambda P: float(O.view_logit(occ_fld, view, np.array([P]))[0])
+    _, labc, _, valc, _ = brute_localize(fn, (1 << (lw - T), 1 << (lw - T), 1 << (ld - T)), T - 1, 7)
     V = np.asarray(view, np.float64).reshape(3, 4)
     rgb = np.zeros((W, W, 3)) + np.asarray(bg)
     depth = np.full((W, W), np.nan)
@@ -98,7 +100,8 @@ def _brute_render(occ_fld, col_fld, view, lw, ld, lcw, bg):
 
 
 @pytest.mark.parametrize("yaw,kind,sizes", [(0.0, "mlp", (4, 3, 2)), (45.0, "mlp", (4, 3, 2)),
-                                            (45.0, "ell", (5, 4, 3))])
+                                            (45.0, "ell", (5, 4, 3)), (180.0, "ell", (5, 4, 3)),
+                                            (90.0, "mlp", (4, 4, 2))])
 def test_render_matches_per_ray_brute_force(yaw, kind, sizes):
     if kind == "mlp":
         feat = synth.feature_map(16, 16, 8, 2.0, 3)
