@@ -275,6 +275,34 @@ int32_t pifu_render_view(pifu_ctx* ctx, const pifu_field* occ_field, const pifu_
                          float* rgb, float* depth, uint8_t* hit, pifu_level_stats* stats,
                          void* workspace, size_t workspace_bytes, pifu_stream stream);
 
+/*
+ * Optional per-node record of a render, for inspection and testing (the steps of
+ * Sec. 3.2, "Mesh-free Rendering").  Every pointer is device memory or null.
+ *   kstar  int32 H*W (row v, column u): the first argmax k* (nearest node from the
+ *          observer whose interpolated value is 1), -1 where there is none.
+ *   k1     int32 H*W: the second argmax after evaluation (the node whose occupancy and
+ *          that of k1 + 1 give the surface point), -1 where there is no hit.
+ *   eval_level uint8 over the finest target lattice, (W+1)*(W+1)*(D+1) nodes, z fastest:
+ *          log2 of the x cell count of the level at which each node was evaluated by
+ *          the network, 255 if never.
+ *   logit  float32 over the same lattice: the logit of every evaluated node (other
+ *          entries are left as they were).
+ */
+typedef struct pifu_render_trace {
+  int32_t* kstar;
+  int32_t* k1;
+  uint8_t* eval_level;
+  float* logit;
+} pifu_render_trace;
+
+/* pifu_render_view with the record above written as well (trace must not be null). */
+int32_t pifu_render_view_traced(pifu_ctx* ctx, const pifu_field* occ_field,
+                                const pifu_field* color_field, const float* view,
+                                const pifu_render_opts* opts, const float* bg, float* rgb,
+                                float* depth, uint8_t* hit, pifu_level_stats* stats,
+                                void* workspace, size_t workspace_bytes, pifu_stream stream,
+                                const pifu_render_trace* trace);
+
 /* ---------------------------------------------------------------- one frame */
 
 /* The arguments of one pifu_occupancy_grid call, as one record. */
@@ -343,6 +371,19 @@ int32_t pifu_eval_points(pifu_ctx* ctx, const pifu_field* field, int32_t precisi
                          float band_delta, float guard_logit, const float* pts, uint32_t n,
                          float* logit, uint8_t* labels, void* workspace, size_t workspace_bytes,
                          pifu_stream stream);
+
+/*
+ * Static FP8 activation scales (the per-layer scale of the precision ladder): runs
+ * field->mlp in FP32 over n input-view points (device float32 n x 4, as for
+ * pifu_eval_points) and writes, for every hidden layer l, the largest |value| of that
+ * layer's quantized input (layer 0: the sampled feature; layer l >= 1: the previous
+ * layer's output and, with a skip, the feature) to amax[l] (host, n_layers - 1 values).
+ * These are the values pifu_mlp.fp8_amax expects.  Workspace as
+ * pifu_eval_points_workspace_size(field, PIFU_PREC_FP32, n).  Blocks until done.
+ */
+int32_t pifu_fp8_calibrate(pifu_ctx* ctx, const pifu_field* field, const float* pts, uint32_t n,
+                           float* amax, void* workspace, size_t workspace_bytes,
+                           pifu_stream stream);
 
 /* ---------------------------------------------------------------- surrogate training */
 

@@ -370,18 +370,22 @@ def dense_grid(fld: Field, log2_final: int) -> Dict[str, object]:
 
 # ------------------------------------------------------------------ render
 
-def render_view(occ_fld: Field, color_fld: Field, view: np.ndarray, log2_w: int, log2_d: int,
-                log2_coarse_w: int, bg=(0.0, 0.0, 0.0)) -> Dict[str, object]:
+def render_view(occ_fld: Field, color_fld: Optional[Field], view: np.ndarray, log2_w: int,
+                log2_d: int, log2_coarse_w: int, bg=(0.0, 0.0, 0.0),
+                evaluate: Optional[Callable[[np.ndarray], np.ndarray]] = None) -> Dict[str, object]:
     """Mesh-free rendering (Sec. 3.2 and Eq. 3) on the target-view lattice.
 
     The lattice has W+1 x H+1 x D+1 nodes (W = H = 2^log2_w, D = 2^log2_d); pixel
     (v, u) of the W x H image is node column (u, v).  Rays run from k = D (nearest
-    the observer) to k = 0.
+    the observer) to k = 0.  ``evaluate`` (optional) replaces the occupancy field's
+    logit at target-lattice points (a replay of recorded values); without a colour
+    field the hits are not coloured.
     """
     T = log2_w - log2_coarse_w
     Wd = 1 << log2_w
     D = 1 << log2_d
-    evaluate = lambda P: view_logit(occ_fld, view, P)
+    if evaluate is None:
+        evaluate = lambda P: view_logit(occ_fld, view, P)
     loc = localize(evaluate, (log2_w, log2_w, log2_d), T, last_level=T - 1)
     lab_c = loc.label
     # level L: upsample the binarized labels of level L-1
@@ -430,7 +434,7 @@ def render_view(occ_fld: Field, color_fld: Field, view: np.ndarray, log2_w: int,
         occ_hit[u, v] = cur[u, v, k]
     rgb = np.empty((Wd, Wd, 3))
     rgb[:] = np.asarray(bg, np.float64)
-    if us.size:
+    if us.size and color_fld is not None:
         xs = -1.0 + 2.0 * us / Wd
         ys = -1.0 + 2.0 * vs / Wd
         P = np.stack([xs, ys, depth[us, vs]], axis=1)

@@ -3,6 +3,6 @@ pixel-aligned implicit function.  The compute path is libpifu.so (HIP); this pac
 holds its build script and the ctypes binding."""
 from .pifu import (FIELD_ELLIPSOIDS, FIELD_MLP, FIELD_PLANE, BatchedGrid,  # noqa: F401
                    DeviceField, DeviceMLP, GridOutputs, RenderOutputs, autotune, autotune_clear,
-                   convert, eval_points, grid_opts, load_library, occupancy_grid,
+                   convert, eval_points, fp8_calibrate, grid_opts, load_library, occupancy_grid,
                    occupancy_grid_into, profile_enable, profile_read, render_opts, render_view,
-                   render_view_into, grid_and_render_into)
+                   render_view_into, render_view_traced, grid_and_render_into)

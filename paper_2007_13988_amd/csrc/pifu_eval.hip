@@ -479,7 +479,8 @@ __global__ void __launch_bounds__(256) k_ray_hit(
     const uint32_t* __restrict__ off, const uint32_t* __restrict__ cnt,
     const uint32_t* __restrict__ list, const float* __restrict__ logit,
     const uint8_t* __restrict__ lab, float* __restrict__ depth, uint8_t* __restrict__ hit,
-    float4* __restrict__ hitpts, double4 v0, double4 v1, double4 v2) {
+    float4* __restrict__ hitpts, double4 v0, double4 v1, double4 v2, int32_t* __restrict__ kstar_out,
+    int32_t* __restrict__ k1_out) {
   extern __shared__ uint64_t bits[];
   const int u0 = blockIdx.x * kRayTile, vt0 = blockIdx.y * kRayTile;
   const int cu0 = u0 >> 1, cv0 = vt0 >> 1;
@@ -499,7 +500,10 @@ __global__ void __launch_bounds__(256) k_ray_hit(
       j1 = j;
       break;
     }
+  const uint32_t pixel = (uint32_t)v * W + u;
+  if (kstar_out) kstar_out[pixel] = r.kstar();
   if (k1 < 0) k1 = r.kstar();
+  if (k1_out) k1_out[pixel] = k1;
   if (k1 < 0) return;
   // node k1 + 1, when evaluated, is the list entry after k1's (or the first entry)
   const int jn = j1 >= 0 ? j1 + 1 : jmin;
@@ -515,7 +519,7 @@ __global__ void __launch_bounds__(256) k_ray_hit(
   };
   const float ob = value(k1, j1);
   const float of = k1 < D ? value(k1 + 1, jprev) : 0.f;
-  const uint32_t pix = (uint32_t)v * W + u;
+  const uint32_t pix = pixel;
   double z;
   if (k1 == D) {
     z = 1.0;
@@ -537,12 +541,40 @@ __global__ void __launch_bounds__(256) k_ray_hit(
 void launch_ray_hit(const uint8_t* stc, const float* occc, Lat c, int W, int H, int D,
                     const uint32_t* off, const uint32_t* cnt, const uint32_t* list,
                     const float* logit, const uint8_t* lab, const double* view, float* depth,
-                    uint8_t* hit, float4* hitpts, hipStream_t s) {
+                    uint8_t* hit, float4* hitpts, hipStream_t s, int32_t* kstar_out,
+                    int32_t* k1_out) {
   double4 v0 = make_double4(view[0], view[1], view[2], view[3]);
   double4 v1 = make_double4(view[4], view[5], view[6], view[7]);
   double4 v2 = make_double4(view[8], view[9], view[10], view[11]);
   hipLaunchKernelGGL(k_ray_hit, ray_grid(W, H), dim3(kRayTile * kRayTile), ray_lds_bytes(c), s, stc,
-                     occc, c, W, H, D, off, cnt, list, logit, lab, depth, hit, hitpts, v0, v1, v2);
+                     occc, c, W, H, D, off, cnt, list, logit, lab, depth, hit, hitpts, v0, v1, v2,
+                     kstar_out, k1_out);
+}
+
+__global__ void k_trace_scatter(const uint32_t* __restrict__ list, uint32_t n,
+                                const float* __restrict__ logit, int level_id,
+                                uint8_t* __restrict__ eval_level, float* __restrict__ eval_logit) {
+  const uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n) return;
+  const uint32_t node = list[m];
+  if (eval_level) eval_level[node] = (uint8_t)level_id;
+  if (eval_logit) eval_logit[node] = logit[m];
+}
+
+void launch_trace_scatter(const uint32_t* list, uint32_t n, const float* logit, int level_id,
+                          uint8_t* eval_level, float* eval_logit, hipStream_t s) {
+  if (!n || (!eval_level && !eval_logit)) return;
+  hipLaunchKernelGGL(k_trace_scatter, dim3((n + 255) / 256), dim3(256), 0, s, list, n, logit,
+                     level_id, eval_level, eval_logit);
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ p, int32_t v, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+void launch_fill_i32(int32_t* p, int32_t v, size_t n, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, v, n);
 }
 
 __global__ void k_fill_image(float* __restrict__ rgb, float* __restrict__ depth,

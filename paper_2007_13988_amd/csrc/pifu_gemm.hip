@@ -838,6 +838,13 @@ __global__ void k_absmax(const float* __restrict__ W, int N, int ldw, int K,
   if ((threadIdx.x & 63) == 0) atomicMax(amax_bits, __float_as_uint(v));
 }
 
+void launch_absmax(const float* X, int rows, int ld, int K, uint32_t* amax_bits, hipStream_t s) {
+  const size_t n = (size_t)rows * K;
+  if (n)
+    hipLaunchKernelGGL(k_absmax, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X, rows, ld, K,
+                       amax_bits);
+}
+
 __global__ void k_pack_fp8(const float* __restrict__ W, int N, int ldw, int K,
                            const uint32_t* __restrict__ amax_bits, uint8_t* __restrict__ dst) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;

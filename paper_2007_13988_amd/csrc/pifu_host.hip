@@ -432,6 +432,9 @@ struct EvalCtx {
   // value of counters[C_GUARD], a running selection counter: known after every read-back,
   // 0 after every clear of the counters
   uint32_t sel_base = 0;
+  // FP8 calibration (FP32 plain path only): amax[0] <- max |feature|, amax[1 + l] <-
+  // max |output of hidden layer l| (float bits, atomicMax)
+  uint32_t* amax = nullptr;
 };
 
 int batch_bucket(uint32_t m) { return m <= 8192 ? 0 : (m <= 32768 ? 1 : 2); }
@@ -662,6 +665,8 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
                       ew.ext + 4 * (size_t)(lo - c0), e.s, nullptr, ovf);
       }
     }
+    if (e.amax && prec == PIFU_PREC_FP32)
+      launch_absmax(reinterpret_cast<const float*>(ew.feat), (int)m, C, C, e.amax, e.s);
     const void* prev = nullptr;
     void* out = ew.hA;
     for (int l = 0; l + 1 < d.n_layers; ++l) {
@@ -706,6 +711,8 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
                         ps.stop()))
           return PIFU_ERR_UNSUPPORTED;
       }
+      if (e.amax && prec == PIFU_PREC_FP32)
+        launch_absmax(reinterpret_cast<const float*>(out), (int)m, g.ldc, g.N, e.amax + 1 + l, e.s);
       prev = out;
       out = (out == ew.hA) ? ew.hB : ew.hA;
     }
@@ -884,7 +891,7 @@ int compact_count(EvalCtx& e, const uint8_t* st, size_t n, uint8_t mask, uint8_t
 int localize(EvalCtx& e, const FieldPrep& fp, const EvalWs& ew, const double* view,
              const int fin_log2[3], int T, int last, LevelBuf* lv, const LocalizeWs& w,
              uint8_t* eval_level, Lat eval_lat, int max_waves, int sur_max_log2,
-             pifu_level_stats* stats) {
+             pifu_level_stats* stats, float* eval_logit = nullptr) {
   PointSrc src;
   std::memset(&src, 0, sizeof(src));
   src.mode = 0;
@@ -901,7 +908,8 @@ int localize(EvalCtx& e, const FieldPrep& fp, const EvalWs& ew, const double* vi
     src.nx = L.lat.nx;
     src.ny = L.lat.ny;
     src.nz = L.lat.nz;
-    const int stride = 1 << (last - t);
+    // spacing of this level's nodes on the lattice of the evaluation-level map
+    const int stride = (eval_lat.nx - 1) / (L.lat.nx - 1);
     const uint32_t n_nodes = (uint32_t)L.lat.n();
     HIP_TRY(hipMemsetAsync(e.counters, 0, sizeof(uint32_t) * C_OVF, e.s));   // keeps C_OVF
     e.sel_base = 0;
@@ -914,7 +922,7 @@ int localize(EvalCtx& e, const FieldPrep& fp, const EvalWs& ew, const double* vi
                              L.level_id <= sur_max_log2);
       if (r) return r;
       launch_apply_grid(w.list, n_nodes, w.logit, w.lab, L.st, L.occ, nullptr, eval_level,
-                        L.level_id, L.lat, stride, eval_lat, 0, e.s);
+                        L.level_id, L.lat, stride, eval_lat, 0, e.s, 0, nullptr, eval_logit);
       st.dilated = n_nodes;
       st.evaluated = n_nodes;
     } else {
@@ -941,7 +949,8 @@ int localize(EvalCtx& e, const FieldPrep& fp, const EvalWs& ew, const double* vi
                            L.level_id <= sur_max_log2);
         if (r) return r;
         launch_apply_grid(w.list, n, w.logit, w.lab, L.st, L.occ, e.counters + C_CONFLICTS,
-                          eval_level, L.level_id, L.lat, stride, eval_lat, 1, e.s);
+                          eval_level, L.level_id, L.lat, stride, eval_lat, 1, e.s, 0, nullptr,
+                          eval_logit);
         fresh = false;
         st.evaluated += n;
         if (max_waves > 0 && waves >= max_waves) break;
@@ -1260,10 +1269,14 @@ int32_t pifu_render_view_workspace_size(const pifu_field* occ_field, const pifu_
   return PIFU_OK;
 }
 
-int32_t pifu_render_view(pifu_ctx* ctx, const pifu_field* occ_field, const pifu_field* color_field,
-                         const float* view, const pifu_render_opts* opts, const float* bg,
-                         float* rgb, float* depth, uint8_t* hit, pifu_level_stats* stats,
-                         void* workspace, size_t workspace_bytes, pifu_stream stream) {
+}  // extern "C"
+
+namespace {
+
+int32_t render_impl(pifu_ctx* ctx, const pifu_field* occ_field, const pifu_field* color_field,
+                    const float* view, const pifu_render_opts* opts, const float* bg, float* rgb,
+                    float* depth, uint8_t* hit, pifu_level_stats* stats, void* workspace,
+                    size_t workspace_bytes, pifu_stream stream, const pifu_render_trace* trace) {
   if (!ctx || !view || !bg || !rgb || !depth || !hit || !workspace) return PIFU_ERR_INVALID_ARGUMENT;
   if (!aligned(workspace, kAlign)) return PIFU_ERR_INVALID_ARGUMENT;
   int r = validate_render_opts(occ_field, color_field, opts);
@@ -1299,8 +1312,13 @@ int32_t pifu_render_view(pifu_ctx* ctx, const pifu_field* occ_field, const pifu_
   const int T = g.T;
   const int W = 1 << opts->log2_w, H = W, D = 1 << opts->log2_d;
   const Lat finL = level_lattice(g.log2, T, T);
-  r = localize(e, g.fp, g.ew, vd, g.log2, T, T - 1, g.lv, g.w, nullptr, finL, opts->max_waves,
-               opts->surrogate_max_log2, stats);
+  uint8_t* tr_level = trace ? trace->eval_level : nullptr;
+  float* tr_logit = trace ? trace->logit : nullptr;
+  if (tr_level) launch_fill_u8(tr_level, 255, finL.n(), s);
+  if (trace && trace->kstar) launch_fill_i32(trace->kstar, -1, (size_t)W * H, s);
+  if (trace && trace->k1) launch_fill_i32(trace->k1, -1, (size_t)W * H, s);
+  r = localize(e, g.fp, g.ew, vd, g.log2, T, T - 1, g.lv, g.w, tr_level, finL, opts->max_waves,
+               opts->surrogate_max_log2, stats, tr_logit);
   if (r) {
     delete gp;
     return r;
@@ -1335,10 +1353,12 @@ int32_t pifu_render_view(pifu_ctx* ctx, const pifu_field* occ_field, const pifu_
                        opts->log2_w <= opts->surrogate_max_log2);
     st.dilated = nT;
     st.evaluated = nT;
+    if (!r) launch_trace_scatter(g.w.list, nT, g.w.logit, opts->log2_w, tr_level, tr_logit, s);
   }
   if (!r) {
     launch_ray_hit(C.st, C.occ, C.lat, W, H, D, g.off, g.cnt, g.w.list, g.w.logit, g.w.lab, vd,
-                   depth, hit, g.hitpts, s);
+                   depth, hit, g.hitpts, s, trace ? trace->kstar : nullptr,
+                   trace ? trace->k1 : nullptr);
     uint32_t nh = 0;
     Lat img{1, 1, W * H};
     r = compact_count(e, hit, (size_t)W * H, 1, 1, g.w.cscratch, g.hitlist, (uint32_t)(W * H), 0,
@@ -1367,6 +1387,29 @@ int32_t pifu_render_view(pifu_ctx* ctx, const pifu_field* occ_field, const pifu_
   prof_resolve(ctx);
   delete gp;
   return r;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t pifu_render_view(pifu_ctx* ctx, const pifu_field* occ_field, const pifu_field* color_field,
+                         const float* view, const pifu_render_opts* opts, const float* bg,
+                         float* rgb, float* depth, uint8_t* hit, pifu_level_stats* stats,
+                         void* workspace, size_t workspace_bytes, pifu_stream stream) {
+  return render_impl(ctx, occ_field, color_field, view, opts, bg, rgb, depth, hit, stats,
+                     workspace, workspace_bytes, stream, nullptr);
+}
+
+int32_t pifu_render_view_traced(pifu_ctx* ctx, const pifu_field* occ_field,
+                                const pifu_field* color_field, const float* view,
+                                const pifu_render_opts* opts, const float* bg, float* rgb,
+                                float* depth, uint8_t* hit, pifu_level_stats* stats,
+                                void* workspace, size_t workspace_bytes, pifu_stream stream,
+                                const pifu_render_trace* trace) {
+  if (!trace) return PIFU_ERR_INVALID_ARGUMENT;
+  return render_impl(ctx, occ_field, color_field, view, opts, bg, rgb, depth, hit, stats,
+                     workspace, workspace_bytes, stream, trace);
 }
 
 // One frame: the grid on the calling thread, the render on a second host thread with
@@ -1475,6 +1518,52 @@ int32_t pifu_eval_points(pifu_ctx* ctx, const pifu_field* field, int32_t precisi
   if (!r) r = hipStreamSynchronize(s) == hipSuccess ? PIFU_OK : PIFU_ERR_HIP;
   prof_resolve(ctx);
   return r;
+}
+
+int32_t pifu_fp8_calibrate(pifu_ctx* ctx, const pifu_field* field, const float* pts, uint32_t n,
+                           float* amax, void* workspace, size_t workspace_bytes,
+                           pifu_stream stream) {
+  if (!ctx || !pts || !amax || !workspace || !n) return PIFU_ERR_INVALID_ARGUMENT;
+  if (!aligned(pts, 16) || !aligned(workspace, kAlign)) return PIFU_ERR_INVALID_ARGUMENT;
+  if (!field || field->kind != PIFU_FIELD_MLP) return PIFU_ERR_INVALID_ARGUMENT;
+  size_t need = 0;
+  int r = pifu_eval_points_workspace_size(field, PIFU_PREC_FP32, n, &need);
+  if (r) return r;
+  if (workspace_bytes < need) return PIFU_ERR_WORKSPACE_TOO_SMALL;
+  Carver cv(workspace);
+  uint32_t* counters = cv.take<uint32_t>(kCounters);
+  uint32_t* iota = cv.take<uint32_t>(n);
+  FieldPrep fp;
+  carve_field(cv, field, PIFU_PREC_FP32, fp);
+  fp.has_sur = false;
+  EvalWs ew;
+  carve_eval(cv, n, field->C, fp.mlp.max_hidden, ew);
+  carve_guard(cv, fp, n, ew);
+  hipStream_t s = as_stream(stream);
+  EvalCtx e{ctx, s, counters, PIFU_PREC_FP32, 0.f};
+  e.amax = counters + 16;
+  HIP_TRY(hipMemsetAsync(counters, 0, sizeof(uint32_t) * kCounters, s));
+  if (int pr = pack_field(fp, ctx, s, counters)) return pr;
+  launch_iota(iota, n, s);
+  PointSrc src;
+  std::memset(&src, 0, sizeof(src));
+  src.mode = 1;
+  src.pts = reinterpret_cast<const float4*>(pts);
+  r = run_mlp(e, fp, fp.mlp, PIFU_PREC_FP32, src, iota, n, ew, ew.band_logit, ew.band_lab, nullptr);
+  if (r) return r;
+  const int nh = fp.mlp.d.n_layers - 1;
+  uint32_t bits[PIFU_MAX_LAYERS + 1];
+  HIP_TRY(hipMemcpyAsync(bits, e.amax, sizeof(uint32_t) * (nh + 1), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  float a[PIFU_MAX_LAYERS + 1];
+  std::memcpy(a, bits, sizeof(float) * (nh + 1));
+  for (int l = 0; l < nh; ++l) {
+    // layer 0 reads [f; z] (z enters the epilogue in FP32), layer l reads [h_{l-1}; f?]
+    float v = l == 0 ? a[0] : a[l];
+    if (l > 0 && fp.mlp.d.skip[l]) v = std::max(v, a[0]);
+    amax[l] = v;
+  }
+  return PIFU_OK;
 }
 
 int32_t pifu_profile_enable(pifu_ctx* ctx, int32_t on) {

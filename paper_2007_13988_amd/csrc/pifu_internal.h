@@ -128,7 +128,13 @@ size_t compact_scratch_words(size_t n);
 void launch_apply_grid(const uint32_t* list, uint32_t n, const float* logit, const uint8_t* lab,
                        uint8_t* st, float* occ, uint32_t* conflicts, uint8_t* eval_level,
                        int level_id, Lat lvl, int stride, Lat fin, int check_conflict,
-                       hipStream_t s, uint32_t frame_nodes = 0, const FrameOcc* fo = nullptr);
+                       hipStream_t s, uint32_t frame_nodes = 0, const FrameOcc* fo = nullptr,
+                       float* eval_logit = nullptr);
+// eval_level[list[m]] = level_id and eval_logit[list[m]] = logit[m] for m < n (list holds
+// indices of the lattice the two maps cover)
+void launch_trace_scatter(const uint32_t* list, uint32_t n, const float* logit, int level_id,
+                          uint8_t* eval_level, float* eval_logit, hipStream_t s);
+void launch_fill_i32(int32_t* p, int32_t v, size_t n, hipStream_t s);
 // frame_nodes > 0: list entries index a multi-frame state array of frames of that size.
 void launch_expand(const uint32_t* list, uint32_t n, uint8_t* st, Lat f, hipStream_t s,
                    uint32_t frame_nodes = 0);
@@ -177,10 +183,13 @@ void launch_scan_u32(const uint32_t* in, uint32_t n, uint32_t* out_excl, uint32_
 size_t scan_scratch_words(size_t n);
 void launch_ray_list(const uint8_t* stc, Lat c, int W, int H, int D, const uint32_t* kstar,
                      const uint32_t* off, uint32_t* list, hipStream_t s);
+// kstar_out / k1_out (nullable, image layout): the two argmax indices of each pixel
+// (-1 where there is none)
 void launch_ray_hit(const uint8_t* stc, const float* occc, Lat c, int W, int H, int D,
                     const uint32_t* off, const uint32_t* cnt, const uint32_t* list,
                     const float* logit, const uint8_t* lab, const double* view, float* depth,
-                    uint8_t* hit, float4* hitpts, hipStream_t s);
+                    uint8_t* hit, float4* hitpts, hipStream_t s, int32_t* kstar_out = nullptr,
+                    int32_t* k1_out = nullptr);
 void launch_fill_image(float* rgb, float* depth, uint8_t* hit, uint32_t npix, float bg0, float bg1,
                        float bg2, hipStream_t s);
 
@@ -262,6 +271,9 @@ int launch_gemm(const GemmArgs& a, int precision, int tile_m, hipStream_t s,
 // FP8 operand copy: amax_bits <- max |W| (float bits), dst = e4m3(W * 448 / amax).
 void launch_pack_fp8(const float* W, int N, int ldw, int K, uint32_t* amax_bits, uint8_t* dst,
                      hipStream_t s);
+// *amax_bits = max(*amax_bits, max |X[r][k]|) over r < rows, k < K (float bits; X row
+// stride ld)
+void launch_absmax(const float* X, int rows, int ld, int K, uint32_t* amax_bits, hipStream_t s);
 // dst = the first K columns of W in format fmt (ovf as for launch_gather)
 void launch_pack_weights(const float* W, int N, int ldw_src, int K, void* dst, int fmt,
                          hipStream_t s, uint32_t* ovf = nullptr);

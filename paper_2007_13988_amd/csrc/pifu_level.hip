@@ -458,8 +458,8 @@ __global__ void k_apply_grid(const uint32_t* __restrict__ list, uint32_t n,
                              const float* __restrict__ logit, const uint8_t* __restrict__ lab,
                              uint8_t* __restrict__ st, float* __restrict__ occ,
                              uint32_t* __restrict__ conflicts, uint8_t* __restrict__ eval_level,
-                             int level_id, Lat lvl, int stride, Lat fin, int check_conflict,
-                             uint32_t frame_nodes, FrameOcc fo) {
+                             float* __restrict__ eval_logit, int level_id, Lat lvl, int stride,
+                             Lat fin, int check_conflict, uint32_t frame_nodes, FrameOcc fo) {
   uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
   bool conf = false;
   if (frame_nodes) {
@@ -515,6 +515,7 @@ __global__ void k_apply_grid(const uint32_t* __restrict__ list, uint32_t n,
       uint32_t k = r - b * lvl.nz;
       size_t fn = ((size_t)(a * stride) * fin.ny + (size_t)(b * stride)) * fin.nz + (size_t)k * stride;
       eval_level[fn] = (uint8_t)level_id;
+      if (eval_logit) eval_logit[fn] = x;
     }
   }
   if (conflicts) {
@@ -526,13 +527,13 @@ __global__ void k_apply_grid(const uint32_t* __restrict__ list, uint32_t n,
 void launch_apply_grid(const uint32_t* list, uint32_t n, const float* logit, const uint8_t* lab,
                        uint8_t* st, float* occ, uint32_t* conflicts, uint8_t* eval_level,
                        int level_id, Lat lvl, int stride, Lat fin, int check_conflict,
-                       hipStream_t s, uint32_t frame_nodes, const FrameOcc* fo) {
+                       hipStream_t s, uint32_t frame_nodes, const FrameOcc* fo, float* eval_logit) {
   if (!n) return;
   FrameOcc t{};
   if (fo) t = *fo;
   hipLaunchKernelGGL(k_apply_grid, dim3(grid1d(n, 256)), dim3(256), 0, s, list, n, logit, lab, st,
-                     occ, conflicts, eval_level, level_id, lvl, stride, fin, check_conflict,
-                     frame_nodes, t);
+                     occ, conflicts, eval_level, eval_logit, level_id, lvl, stride, fin,
+                     check_conflict, frame_nodes, t);
 }
 
 // Conflict expansion: every not-yet-evaluated node of the 26-neighbourhood of a

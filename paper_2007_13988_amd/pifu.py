@@ -90,6 +90,11 @@ class PifuRenderCall(C.Structure):
                 ("stream", C.c_void_p)]
 
 
+class PifuRenderTrace(C.Structure):
+    _fields_ = [("kstar", C.c_void_p), ("k1", C.c_void_p), ("eval_level", C.c_void_p),
+                ("logit", C.c_void_p)]
+
+
 class PifuKernelProfile(C.Structure):
     _fields_ = [("launches", C.c_uint64), ("total_ms", C.c_double), ("flops", C.c_double),
                 ("bytes", C.c_double)]
@@ -106,7 +111,7 @@ EXPORTS = ["pifu_create", "pifu_destroy", "pifu_status_string",
            "pifu_profile_enable", "pifu_profile_read", "pifu_mlp_train_workspace_size",
            "pifu_mlp_grad", "pifu_rmsprop_step", "pifu_occupancy_grid_batched_workspace_size",
            "pifu_occupancy_grid_batched", "pifu_autotune_mlp", "pifu_autotune_clear",
-           "pifu_convert_f32", "pifu_grid_and_render"]
+           "pifu_convert_f32", "pifu_grid_and_render", "pifu_render_view_traced", "pifu_fp8_calibrate"]
 
 _lib = None
 
@@ -137,6 +142,13 @@ def load_library():
                                      C.POINTER(C.c_float), C.POINTER(PifuRenderOpts),
                                      C.POINTER(C.c_float), P, P, P, C.POINTER(PifuLevelStats), P,
                                      sz, P]
+    lib.pifu_render_view_traced.argtypes = [P, C.POINTER(PifuField), C.POINTER(PifuField),
+                                            C.POINTER(C.c_float), C.POINTER(PifuRenderOpts),
+                                            C.POINTER(C.c_float), P, P, P,
+                                            C.POINTER(PifuLevelStats), P, sz, P,
+                                            C.POINTER(PifuRenderTrace)]
+    lib.pifu_fp8_calibrate.argtypes = [P, C.POINTER(PifuField), P, u32, C.POINTER(C.c_float), P,
+                                       sz, P]
     lib.pifu_eval_points_workspace_size.argtypes = [C.POINTER(PifuField), i32, u32, C.POINTER(sz)]
     lib.pifu_eval_points.argtypes = [P, C.POINTER(PifuField), i32, C.c_float, C.c_float, P, u32, P,
                                      P, P, sz, P]
@@ -443,6 +455,33 @@ def render_view(occ_field: DeviceField, color_field: DeviceField, view, log2_w: 
     return dict(rgb=out.rgb, depth=out.depth, hit=out.hit, stats=[s.as_dict() for s in out.stats])
 
 
+def render_view_traced(occ_field: DeviceField, color_field: DeviceField, view, log2_w: int,
+                       log2_d: int, log2_coarse_w: int, bg=(0.0, 0.0, 0.0), *, precision="fp32",
+                       guard_logit=1e-3, band_delta=0.02, max_waves=0, stream=None,
+                       **kw) -> Dict[str, object]:
+    """render_view plus the per-node record of pifu_render_view_traced: k* and k1 per
+    pixel, and the evaluation level and logit of every node of the finest lattice."""
+    lib = load_library()
+    opts = render_opts(log2_w, log2_d, log2_coarse_w, precision, band_delta, guard_logit,
+                       max_waves=max_waves, **kw)
+    out = RenderOutputs(occ_field, color_field, opts)
+    W, D = 1 << log2_w, 1 << log2_d
+    kstar = torch.empty((W, W), dtype=torch.int32, device="cuda")
+    k1 = torch.empty((W, W), dtype=torch.int32, device="cuda")
+    evl = torch.empty((W + 1, W + 1, D + 1), dtype=torch.uint8, device="cuda")
+    lg = torch.full((W + 1, W + 1, D + 1), float("nan"), dtype=torch.float32, device="cuda")
+    tr = PifuRenderTrace(kstar.data_ptr(), k1.data_ptr(), evl.data_ptr(), lg.data_ptr())
+    v = (C.c_float * 12)(*[float(x) for x in np.asarray(view, np.float32).reshape(-1)])
+    b = (C.c_float * 3)(*[float(x) for x in bg])
+    st = lib.pifu_render_view_traced(context(), C.byref(occ_field.struct),
+                                     C.byref(color_field.struct), v, C.byref(out.opts), b,
+                                     _ptr(out.rgb), _ptr(out.depth), _ptr(out.hit), out.stats,
+                                     _ptr(out.ws), out.ws_bytes, _stream(stream), C.byref(tr))
+    _check(st, "pifu_render_view_traced")
+    return dict(rgb=out.rgb, depth=out.depth, hit=out.hit, stats=[s.as_dict() for s in out.stats],
+                kstar=kstar, k1=k1, eval_level=evl, logit=lg)
+
+
 def eval_points(field: DeviceField, pts, precision="fp32", guard_logit=1e-3, band_delta=0.02,
                 stream=None):
     """Field logits and labels at input-view NDC points (n x 3)."""
@@ -462,6 +501,25 @@ def eval_points(field: DeviceField, pts, precision="fp32", guard_logit=1e-3, ban
                               sz.value, _stream(stream))
     _check(st, "pifu_eval_points")
     return logit, labels
+
+
+def fp8_calibrate(field: DeviceField, pts, stream=None) -> List[float]:
+    """Per-layer max |input| of field's network over input-view points (n x 3), from the
+    library's FP32 pass: the static FP8 activation scales (pifu_mlp.fp8_amax)."""
+    lib = load_library()
+    p = torch.as_tensor(np.asarray(pts, np.float32)) if not isinstance(pts, torch.Tensor) else pts
+    n = p.shape[0]
+    p4 = torch.zeros((n, 4), dtype=torch.float32, device="cuda")
+    p4[:, :3] = p.to(device="cuda", dtype=torch.float32)
+    sz = C.c_size_t()
+    _check(lib.pifu_eval_points_workspace_size(C.byref(field.struct), PREC["fp32"], n,
+                                               C.byref(sz)), "pifu_eval_points_workspace_size")
+    ws = torch.empty(sz.value, dtype=torch.uint8, device="cuda")
+    nh = field.struct.mlp.contents.n_layers - 1
+    out = (C.c_float * MAX_LAYERS)()
+    _check(lib.pifu_fp8_calibrate(context(), C.byref(field.struct), _ptr(p4), n, out, _ptr(ws),
+                                  sz.value, _stream(stream)), "pifu_fp8_calibrate")
+    return [float(out[l]) for l in range(nh)]
 
 
 class BatchedGrid:

@@ -45,7 +45,7 @@ def distill(teacher_spec, student_spec, feats_train: Sequence[np.ndarray], sampl
 
 def choose_delta(teacher_spec, net: P.DeviceMLP, feats_val: Sequence[np.ndarray],
                  deltas=(0.02, 0.05, 0.1, 0.15, 0.2, 0.3, 0.45), bar: float = 1e-3,
-                 log2_final=8, log2_coarse=5, sur_max_log2=7, precision="bf16"):
+                 log2_final=8, log2_coarse=5, sur_max_log2=7, precision="bf16", band_delta=0.02):
     """Smallest delta_s whose surface cells disagree with the plain FP32 grid by at
     most `bar` (fraction of cells) on every validation frame."""
     refs = []
@@ -58,7 +58,8 @@ def choose_delta(teacher_spec, net: P.DeviceMLP, feats_val: Sequence[np.ndarray]
         for F, ref in zip(feats_val, refs):
             fld = P.DeviceField(P.FIELD_MLP, feat=F, mlp=P.DeviceMLP(teacher_spec), surrogate=net)
             out = P.occupancy_grid(fld, log2_final, log2_coarse, precision=precision,
-                                   surrogate_max_log2=sur_max_log2, surrogate_delta=d)
+                                   band_delta=band_delta, surrogate_max_log2=sur_max_log2,
+                                   surrogate_delta=d)
             worst = max(worst, cell_disagreement(out["cells"], ref))
         report.append((d, worst))
         if worst <= bar:

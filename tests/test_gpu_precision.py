@@ -49,10 +49,42 @@ def _sample_points(fo, n_uniform, seed):
     return pts.astype(np.float32).astype(np.float64)
 
 
+def _dense_grid_points(L=5):
+    n = (1 << L) + 1
+    idx = np.arange(n ** 3)
+    return O.lattice_coords((n, n, n), idx)
+
+
+def _calibrated_tiny(pifu):
+    """The tiny network with its static FP8 activation scales calibrated on the dense
+    33^3 grid of the tiny workload (the library's FP32 pass)."""
+    spec = synth.tiny_mlp()
+    fg = pifu.DeviceField.mlp_field(synth.tiny_features(), spec)
+    spec.fp8_amax = pifu.fp8_calibrate(fg, _dense_grid_points())
+    return spec
+
+
+def test_fp8_calibration_matches_oracle_layer_inputs(pifu):
+    """The calibrated amax of every layer input equals max |input| of the FP64 forward
+    pass over the same points (layer 0: the feature; later layers: the previous output
+    and, with a skip, the feature)."""
+    feat = synth.tiny_features()
+    spec = synth.he_mlp(64, 1, [128, 64, 64, 1], [False, False, True, False], 221)
+    fg = pifu.DeviceField.mlp_field(feat, spec)
+    P = _dense_grid_points().astype(np.float32).astype(np.float64)
+    got = pifu.fp8_calibrate(fg, P)
+    f = O.bilinear_sample(feat, P[:, 0], P[:, 1])
+    ins, pres = O.mlp_forward_cache(spec, f, P[:, 2:3])
+    want = [np.max(np.abs(f))] + [np.max(np.abs(ins[l])) for l in range(1, len(spec.widths) - 1)]
+    print("fp8 amax", got, want)
+    assert np.allclose(got, want, rtol=1e-5, atol=0)
+
+
 @pytest.mark.parametrize("prec,mean_tol", [("bf16", 5e-3), ("fp16", 1e-3), ("fp8", 3e-2)])
 def test_probability_error_and_label_flips(pifu, prec, mean_tol):
+    spec = _calibrated_tiny(pifu) if prec == "fp8" else synth.tiny_mlp()
     fo = O.Field("mlp", feat=synth.tiny_features(), mlp=synth.tiny_mlp())
-    fg = pifu.DeviceField.mlp_field(synth.tiny_features(), synth.tiny_mlp())
+    fg = pifu.DeviceField.mlp_field(synth.tiny_features(), spec)
     pts = _sample_points(fo, 500000, 403)
     ref = O.field_logit(fo, pts)
     p64 = O.sigmoid(ref)
@@ -71,18 +103,28 @@ def test_probability_error_and_label_flips(pifu, prec, mean_tol):
     assert flips <= (5e-3 if prec == "fp8" else 1e-4) * pts.shape[0]
 
 
-@pytest.mark.parametrize("prec", ["bf16", "fp16", "fp8"])
-def test_grid_surface_cells_against_oracle(pifu, prec):
+# Surface-cell disagreement with the FP64 oracle on the tiny 33^3 grid.  With the band of
+# the precision workload (|p - 0.5| < 0.02) BF16 and FP16 keep every label exact.  e4m3
+# keeps 3 mantissa bits: with calibrated scales its logit error passes that band on a few
+# dozen nodes, which moves 1.3% of the surface cells (measured), so its bound at 0.02 is
+# 2%; a band sized to its error (0.1) brings it within the 0.1% bar.
+CELL_CASES = [("bf16", 0.02, 1e-3), ("fp16", 0.02, 1e-3), ("fp8", 0.02, 2e-2),
+              ("fp8", 0.1, 1e-3)]
+
+
+@pytest.mark.parametrize("prec,band,bound", CELL_CASES)
+def test_grid_surface_cells_against_oracle(pifu, prec, band, bound):
     from paper_2007_13988_amd.surrogate import cell_disagreement
+    spec = _calibrated_tiny(pifu) if prec == "fp8" else synth.tiny_mlp()
     fo = O.Field("mlp", feat=synth.tiny_features(), mlp=synth.tiny_mlp())
-    fg = pifu.DeviceField.mlp_field(synth.tiny_features(), synth.tiny_mlp())
+    fg = pifu.DeviceField.mlp_field(synth.tiny_features(), spec)
     ref = O.occupancy_grid(fo, 5, 3)
-    out = pifu.occupancy_grid(fg, 5, 3, precision=prec, band_delta=0.02)
+    out = pifu.occupancy_grid(fg, 5, 3, precision=prec, band_delta=band)
     lab = out["labels"].cpu().numpy()
     d = cell_disagreement(out["cells"], torch.from_numpy(ref["cells"].astype(np.int64)).cuda())
-    print(f"{prec}: label flips {int(np.sum(lab != ref['labels']))} of {lab.size}, "
+    print(f"{prec} band {band}: label flips {int(np.sum(lab != ref['labels']))} of {lab.size}, "
           f"surface-cell disagreement {d:.2e}")
-    assert d <= 1e-3 or prec == "fp8"
+    assert d <= bound
 
 
 def test_fp16_error_is_below_bf16(pifu):
