@@ -21,7 +21,8 @@
  *  - pifu_occupancy_grid, pifu_render_view and pifu_grid_and_render block until
  *    their work on their streams is complete (the conflict loop's trip count is
  *    read back between waves); results are then visible to later work on any
- *    stream.
+ *    stream.  The *_async forms enqueue the same work without any host read-back
+ *    (graph-capturable) and keep every count in device memory.
  *  - The library never allocates device memory during a call: scratch comes
  *    from the caller's workspace, sized by the matching *_workspace_size query.
  */
@@ -354,6 +355,61 @@ typedef struct pifu_render_call {
  */
 int32_t pifu_grid_and_render(pifu_ctx* ctx, const pifu_grid_call* grid,
                              const pifu_render_call* render);
+
+/* ---------------------------------------------------------------- device-driven calls */
+
+/* Status bits of the device-driven calls (written to *status_dev). */
+#define PIFU_STATUS_LIST_OVER 1u    /* a point list exceeded max_points: results are invalid */
+#define PIFU_STATUS_WAVES_LEFT 2u   /* conflicts remained after the wave budget: results are
+                                       those of a capped conflict loop */
+#define PIFU_STATUS_GUARD_OVER 4u   /* more FP64-guard points than one guard pass holds: some
+                                       labels were decided in FP32 only */
+#define PIFU_STATUS_CELLS_OVER 8u   /* more surface cells than cells_cap (truncated list) */
+
+/*
+ * Asynchronous pifu_occupancy_grid (Sec. 3.2, "Octree-based Robust Surface Localization"):
+ * the same method and results, enqueued on `stream` without any host read-back or
+ * synchronization, so the call can be captured into a HIP graph and replayed.  Every
+ * count stays in device memory:
+ *   n_cells_dev  (device uint32) the true number of surface cells (cells holds
+ *                min(*n_cells_dev, cells_cap) of them);
+ *   stats_dev    (device, log2_final - log2_coarse + 1 records, 4-byte aligned);
+ *   status_dev   (device uint32) PIFU_STATUS_* bits, 0 when the results are complete.
+ * max_points bounds the points of one network evaluation (0: min(largest level, 2^20));
+ * the workspace holds the activations of that many points, so a larger bound trades
+ * memory for range.  The conflict loop runs a fixed ladder of waves per level:
+ * opts->max_waves when non-zero (the cap of the blocking call), else 12 waves with
+ * PIFU_STATUS_WAVES_LEFT set if a level still has conflicts after them.  Waves past the
+ * last conflict launch kernels that find empty lists.  Unsupported: PIFU_PREC_FP8 (its
+ * weight scales are read back on the host).  Argument errors are returned before
+ * anything is enqueued; device-side conditions arrive in *status_dev.  The workspace
+ * and outputs must stay valid until the stream (or graph) has run.
+ */
+int32_t pifu_occupancy_grid_async_workspace_size(const pifu_field* field,
+                                                 const pifu_grid_opts* opts, uint32_t max_points,
+                                                 size_t* bytes);
+int32_t pifu_occupancy_grid_async(pifu_ctx* ctx, const pifu_field* field,
+                                  const pifu_grid_opts* opts, uint32_t max_points, float* occ,
+                                  uint8_t* labels, uint8_t* eval_level, uint32_t* cells,
+                                  uint32_t cells_cap, uint32_t* n_cells_dev,
+                                  pifu_level_stats* stats_dev, uint32_t* status_dev,
+                                  void* workspace, size_t workspace_bytes, pifu_stream stream);
+
+/*
+ * Asynchronous pifu_render_view (Sec. 3.2, "Mesh-free Rendering"; Eq. 3): as above, with
+ * stats_dev holding log2_w - log2_coarse_w + 1 device records.  max_points is raised to
+ * at least W * W (the colour network's points).
+ */
+int32_t pifu_render_view_async_workspace_size(const pifu_field* occ_field,
+                                              const pifu_field* color_field,
+                                              const pifu_render_opts* opts, uint32_t max_points,
+                                              size_t* bytes);
+int32_t pifu_render_view_async(pifu_ctx* ctx, const pifu_field* occ_field,
+                               const pifu_field* color_field, const float* view,
+                               const pifu_render_opts* opts, uint32_t max_points, const float* bg,
+                               float* rgb, float* depth, uint8_t* hit, pifu_level_stats* stats_dev,
+                               uint32_t* status_dev, void* workspace, size_t workspace_bytes,
+                               pifu_stream stream);
 
 /* ---------------------------------------------------------------- point evaluation */
 

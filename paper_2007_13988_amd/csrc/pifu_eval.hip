@@ -8,6 +8,17 @@ namespace pifu {
 
 static inline unsigned grid1d(size_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
+// Grid of a list kernel.  With the length known on the host the grid covers the list
+// once; with a device-side count (n_dev) the list may be anything up to its capacity n,
+// so the grid is bounded and the threads stride over the count.
+static inline unsigned list_grid(size_t threads, int block, const uint32_t* n_dev) {
+  const unsigned g = grid1d(threads, block);
+  return n_dev && g > kStrideBlocks ? kStrideBlocks : g;
+}
+__device__ inline uint32_t eff_count(uint32_t n, const uint32_t* n_dev) {
+  return n_dev ? min(n, *n_dev) : n;
+}
+
 // Node or explicit point -> input-view NDC.  Lattice coordinates are exact dyadic
 // values; the view product is taken in float64 in a fixed order without fused
 // multiply-add so the clip decision is reproducible.  Returns false when the point
@@ -70,10 +81,10 @@ __device__ inline void bilinear_setup(double x, double y, int H, int W, int& u0,
 
 // ------------------------------------------------------------------ analytic fields
 __global__ void k_eval_analytic(PointSrc src, const uint32_t* __restrict__ list, uint32_t n,
-                                int kind, Ellipsoids ell, float4 plane,
-                                float* __restrict__ logit, uint8_t* __restrict__ lab) {
-  uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= n) return;
+                                const uint32_t* __restrict__ n_dev, int kind, Ellipsoids ell,
+                                float4 plane, float* __restrict__ logit, uint8_t* __restrict__ lab) {
+  const uint32_t ne = eff_count(n, n_dev);
+  for (uint32_t m = blockIdx.x * blockDim.x + threadIdx.x; m < ne; m += gridDim.x * blockDim.x) {
   double P[3];
   bool in = src_point(src, list, m, P, nullptr);
   double lg;
@@ -98,15 +109,16 @@ __global__ void k_eval_analytic(PointSrc src, const uint32_t* __restrict__ list,
   }
   logit[m] = (float)lg;
   lab[m] = lg > 0.0;
+  }
 }
 
 void launch_eval_analytic(const PointSrc& src, const uint32_t* list, uint32_t n, int kind,
                           const Ellipsoids& ell, const float plane[4], float* logit, uint8_t* lab,
-                          hipStream_t s) {
+                          hipStream_t s, const uint32_t* n_dev) {
   if (!n) return;
   float4 pl = make_float4(plane[0], plane[1], plane[2], plane[3]);
-  hipLaunchKernelGGL(k_eval_analytic, dim3(grid1d(n, 128)), dim3(128), 0, s, src, list, n, kind,
-                     ell, pl, logit, lab);
+  hipLaunchKernelGGL(k_eval_analytic, dim3(list_grid(n, 128, n_dev)), dim3(128), 0, s, src, list,
+                     n, n_dev, kind, ell, pl, logit, lab);
 }
 
 // ------------------------------------------------------------------ bilinear gather
@@ -119,11 +131,12 @@ k_gather(PointSrc src, const uint32_t* __restrict__ list, uint32_t n,
          const uint32_t* __restrict__ n_dev, const float* __restrict__ F, int H, int W, int C,
          void* __restrict__ feat, float* __restrict__ ext, uint32_t* __restrict__ ovf) {
   const int lanes = C >> 2;
-  const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int per = lanes < 64 ? lanes : 64;   // lanes per point group (<= one wave)
+  const uint32_t ne = eff_count(n, n_dev);
+  for (uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x; gid < ne * (uint32_t)per;
+       gid += gridDim.x * blockDim.x) {
   const uint32_t m = gid / per;
   const int lane = gid % per;
-  if (m >= n || (n_dev && m >= *n_dev)) return;
   double P[3];
   float occ = 0.f;
   int frame = 0;
@@ -165,6 +178,7 @@ k_gather(PointSrc src, const uint32_t* __restrict__ list, uint32_t n,
   if (lane == 0)
     *reinterpret_cast<float4*>(ext + 4 * (size_t)m) =
         make_float4((float)P[2], occ, in ? 0.f : 1.f, 0.f);
+  }
 }
 
 void launch_gather(const PointSrc& src, const uint32_t* list, uint32_t n, const float* F, int H,
@@ -174,15 +188,16 @@ void launch_gather(const PointSrc& src, const uint32_t* list, uint32_t n, const 
   const int lanes = C >> 2;
   const int per = lanes < 64 ? lanes : 64;
   size_t threads = (size_t)n * per;
+  const unsigned g = list_grid(threads, 256, n_dev);
   if (feat_fmt == FMT_BF16)
-    hipLaunchKernelGGL(k_gather<FMT_BF16>, dim3(grid1d(threads, 256)), dim3(256), 0, s, src, list,
-                       n, n_dev, F, H, W, C, feat, ext, ovf);
+    hipLaunchKernelGGL(k_gather<FMT_BF16>, dim3(g), dim3(256), 0, s, src, list, n, n_dev, F, H, W,
+                       C, feat, ext, ovf);
   else if (feat_fmt == FMT_F16)
-    hipLaunchKernelGGL(k_gather<FMT_F16>, dim3(grid1d(threads, 256)), dim3(256), 0, s, src, list,
-                       n, n_dev, F, H, W, C, feat, ext, ovf);
+    hipLaunchKernelGGL(k_gather<FMT_F16>, dim3(g), dim3(256), 0, s, src, list, n, n_dev, F, H, W,
+                       C, feat, ext, ovf);
   else
-    hipLaunchKernelGGL(k_gather<FMT_F32>, dim3(grid1d(threads, 256)), dim3(256), 0, s, src, list,
-                       n, n_dev, F, H, W, C, feat, ext, ovf);
+    hipLaunchKernelGGL(k_gather<FMT_F32>, dim3(g), dim3(256), 0, s, src, list, n, n_dev, F, H, W,
+                       C, feat, ext, ovf);
 }
 
 // ------------------------------------------------------------------ output head
@@ -193,11 +208,14 @@ void launch_gather(const PointSrc& src, const uint32_t* list, uint32_t n, const 
 // rgb_out[pixel * 3 + c].
 __global__ void __launch_bounds__(256)
 k_head(const float* __restrict__ h, int K, const float* __restrict__ W, const float* __restrict__ b,
-       int n_out, int out_act, uint32_t n, const float* __restrict__ ext, float* __restrict__ logit,
-       uint8_t* __restrict__ lab, float* __restrict__ rgb_out, const uint32_t* __restrict__ rgb_index) {
-  const uint32_t m = (blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+       int n_out, int out_act, uint32_t n, const uint32_t* __restrict__ n_dev,
+       const float* __restrict__ ext, float* __restrict__ logit, uint8_t* __restrict__ lab,
+       float* __restrict__ rgb_out, const uint32_t* __restrict__ rgb_index) {
   const int q = threadIdx.x & 15;
-  if (m >= n) return;   // whole 16-lane groups leave together
+  const uint32_t ne = eff_count(n, n_dev);
+  // whole 16-lane groups take the same points and leave together
+  for (uint32_t m = (blockIdx.x * blockDim.x + threadIdx.x) >> 4; m < ne;
+       m += (gridDim.x * blockDim.x) >> 4) {
   float acc[4] = {0.f, 0.f, 0.f, 0.f};
   const float* hr = h + (size_t)m * K;
   for (int k = 4 * q; k < K; k += 64) {
@@ -218,7 +236,7 @@ k_head(const float* __restrict__ h, int K, const float* __restrict__ W, const fl
     for (int d = 8; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
     acc[o] = v + b[o];
   }
-  if (q != 0) return;
+  if (q != 0) continue;
   if (n_out == 1) {
     float v = acc[0];
     if (ext && ext[4 * (size_t)m + 2] != 0.f) v = -INFINITY;
@@ -233,14 +251,15 @@ k_head(const float* __restrict__ h, int K, const float* __restrict__ W, const fl
       rgb_out[(size_t)pix * n_out + o] = v;
     }
   }
+  }
 }
 
 void launch_head(const float* h, int K, const float* W, const float* b, int n_out, int out_act,
                  uint32_t n, const float* ext, float* logit, uint8_t* lab, float* rgb_out,
-                 const uint32_t* rgb_index, hipStream_t s) {
+                 const uint32_t* rgb_index, hipStream_t s, const uint32_t* n_dev) {
   if (!n) return;
-  hipLaunchKernelGGL(k_head, dim3(grid1d((size_t)n * 16, 256)), dim3(256), 0, s, h, K, W, b, n_out,
-                     out_act, n, ext, logit, lab, rgb_out, rgb_index);
+  hipLaunchKernelGGL(k_head, dim3(list_grid((size_t)n * 16, 256, n_dev)), dim3(256), 0, s, h, K, W,
+                     b, n_out, out_act, n, n_dev, ext, logit, lab, rgb_out, rgb_index);
 }
 
 // ------------------------------------------------------------------ FP64 guard band
@@ -248,29 +267,35 @@ void launch_head(const float* h, int K, const float* W, const float* b, int n_ou
 // given); one atomic per wave reserves the wave's slots.  The order of the appended
 // positions across waves is unspecified; every consumer treats the points
 // independently.
-__global__ void k_guard_select(const float* __restrict__ logit, uint32_t n, float g,
+__global__ void k_guard_select(const float* __restrict__ logit, uint32_t n,
+                               const uint32_t* __restrict__ n_dev, float g,
                                const uint32_t* __restrict__ map, uint32_t* __restrict__ glist,
                                uint32_t* __restrict__ gcount, uint32_t start) {
-  const uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool take = m < n && fabsf(logit[m]) < g;
-  const unsigned long long bal = __ballot(take);
-  if (!bal) return;
-  const int lane = threadIdx.x & 63;
-  const int first = __ffsll((long long)bal) - 1;
-  uint32_t base = 0;
-  if (lane == first) base = atomicAdd(gcount, (uint32_t)__popcll(bal));
-  base = __shfl(base, first, 64) - start;   // the counter held `start` before this launch
-  if (take) {
-    const uint32_t slot = base + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
-    glist[slot] = map ? map[m] : m;
+  const uint32_t ne = eff_count(n, n_dev);
+  // the block's base index is uniform, so every lane of a wave runs the same iterations
+  for (uint32_t b0 = blockIdx.x * blockDim.x; b0 < ne; b0 += gridDim.x * blockDim.x) {
+    const uint32_t m = b0 + threadIdx.x;
+    const bool take = m < ne && fabsf(logit[m]) < g;
+    const unsigned long long bal = __ballot(take);
+    if (!bal) continue;
+    const int lane = threadIdx.x & 63;
+    const int first = __ffsll((long long)bal) - 1;
+    uint32_t base = 0;
+    if (lane == first) base = atomicAdd(gcount, (uint32_t)__popcll(bal));
+    base = __shfl(base, first, 64) - start;   // the counter held `start` before this launch
+    if (take) {
+      const uint32_t slot = base + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
+      glist[slot] = map ? map[m] : m;
+    }
   }
 }
 
 void launch_guard_select(const float* logit, uint32_t n, float g, uint32_t* glist,
-                         uint32_t* gcount, hipStream_t s, const uint32_t* map, uint32_t start) {
+                         uint32_t* gcount, hipStream_t s, const uint32_t* map, uint32_t start,
+                         const uint32_t* n_dev) {
   if (!n || !(g > 0.f)) return;
-  hipLaunchKernelGGL(k_guard_select, dim3(grid1d(n, 256)), dim3(256), 0, s, logit, n, g, map,
-                     glist, gcount, start);
+  hipLaunchKernelGGL(k_guard_select, dim3(list_grid(n, 256, n_dev)), dim3(256), 0, s, logit, n,
+                     n_dev, g, map, glist, gcount, start);
 }
 
 
@@ -552,20 +577,23 @@ void launch_ray_hit(const uint8_t* stc, const float* occc, Lat c, int W, int H, 
 }
 
 __global__ void k_trace_scatter(const uint32_t* __restrict__ list, uint32_t n,
-                                const float* __restrict__ logit, int level_id,
-                                uint8_t* __restrict__ eval_level, float* __restrict__ eval_logit) {
-  const uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= n) return;
-  const uint32_t node = list[m];
-  if (eval_level) eval_level[node] = (uint8_t)level_id;
-  if (eval_logit) eval_logit[node] = logit[m];
+                                const uint32_t* __restrict__ n_dev, const float* __restrict__ logit,
+                                int level_id, uint8_t* __restrict__ eval_level,
+                                float* __restrict__ eval_logit) {
+  const uint32_t ne = eff_count(n, n_dev);
+  for (uint32_t m = blockIdx.x * blockDim.x + threadIdx.x; m < ne; m += gridDim.x * blockDim.x) {
+    const uint32_t node = list[m];
+    if (eval_level) eval_level[node] = (uint8_t)level_id;
+    if (eval_logit) eval_logit[node] = logit[m];
+  }
 }
 
 void launch_trace_scatter(const uint32_t* list, uint32_t n, const float* logit, int level_id,
-                          uint8_t* eval_level, float* eval_logit, hipStream_t s) {
+                          uint8_t* eval_level, float* eval_logit, hipStream_t s,
+                          const uint32_t* n_dev) {
   if (!n || (!eval_level && !eval_logit)) return;
-  hipLaunchKernelGGL(k_trace_scatter, dim3((n + 255) / 256), dim3(256), 0, s, list, n, logit,
-                     level_id, eval_level, eval_logit);
+  hipLaunchKernelGGL(k_trace_scatter, dim3(list_grid(n, 256, n_dev)), dim3(256), 0, s, list, n,
+                     n_dev, logit, level_id, eval_level, eval_logit);
 }
 
 __global__ void k_fill_i32(int32_t* __restrict__ p, int32_t v, size_t n) {
@@ -600,68 +628,79 @@ void launch_fill_image(float* rgb, float* depth, uint8_t* hit, uint32_t npix, fl
 namespace pifu {
 
 __global__ void k_gather_u32(const uint32_t* __restrict__ src, const uint32_t* __restrict__ pos,
-                             uint32_t n, uint32_t* __restrict__ out) {
-  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = src[pos[i]];
+                             uint32_t n, const uint32_t* __restrict__ n_dev,
+                             uint32_t* __restrict__ out) {
+  const uint32_t ne = eff_count(n, n_dev);
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ne; i += gridDim.x * blockDim.x)
+    out[i] = src[pos[i]];
 }
 
 void launch_gather_u32(const uint32_t* src, const uint32_t* pos, uint32_t n, uint32_t* out,
-                       hipStream_t s) {
+                       hipStream_t s, const uint32_t* n_dev) {
   if (n)
-    hipLaunchKernelGGL(k_gather_u32, dim3(grid1d(n, 256)), dim3(256), 0, s, src, pos, n, out);
+    hipLaunchKernelGGL(k_gather_u32, dim3(list_grid(n, 256, n_dev)), dim3(256), 0, s, src, pos, n,
+                       n_dev, out);
 }
 
 __global__ void k_scatter_results(const uint32_t* __restrict__ pos, uint32_t n,
+                                  const uint32_t* __restrict__ n_dev,
                                   const float* __restrict__ tl, const uint8_t* __restrict__ tb,
                                   float* __restrict__ logit, uint8_t* __restrict__ lab) {
-  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint32_t p = pos[i];
-  logit[p] = tl[i];
-  lab[p] = tb[i];
+  const uint32_t ne = eff_count(n, n_dev);
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ne; i += gridDim.x * blockDim.x) {
+    const uint32_t p = pos[i];
+    logit[p] = tl[i];
+    lab[p] = tb[i];
+  }
 }
 
 // ------------------------------------------------------------------ per-column hoisting
 // In the input view the sampled feature depends only on the (x, y) column of a node,
 // so the feature part of every layer (W_f f + b) is computed once per column run.
-__global__ void k_col_flags(const uint32_t* __restrict__ list, uint32_t n, uint32_t nz,
+__global__ void k_col_flags(const uint32_t* __restrict__ list, uint32_t n,
+                            const uint32_t* __restrict__ n_dev, uint32_t nz,
                             uint32_t* __restrict__ flags) {
-  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  flags[i] = (i == 0) || (list[i] / nz != list[i - 1] / nz);
+  const uint32_t ne = eff_count(n, n_dev);
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ne; i += gridDim.x * blockDim.x)
+    flags[i] = (i == 0) || (list[i] / nz != list[i - 1] / nz);
 }
 
 void launch_col_flags(const uint32_t* list, uint32_t n, uint32_t nz, uint32_t* flags,
-                      hipStream_t s) {
+                      hipStream_t s, const uint32_t* n_dev) {
   if (n)
-    hipLaunchKernelGGL(k_col_flags, dim3(grid1d(n, 256)), dim3(256), 0, s, list, n, nz, flags);
+    hipLaunchKernelGGL(k_col_flags, dim3(list_grid(n, 256, n_dev)), dim3(256), 0, s, list, n, n_dev,
+                       nz, flags);
 }
 
 __global__ void k_col_ids(const uint32_t* __restrict__ list, const uint32_t* __restrict__ flags,
                           const uint32_t* __restrict__ excl, uint32_t n,
-                          uint32_t* __restrict__ cid, uint32_t* __restrict__ col_node) {
-  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint32_t c = excl[i] + flags[i] - 1;
-  cid[i] = c;
-  if (flags[i]) col_node[c] = list[i];
+                          const uint32_t* __restrict__ n_dev, uint32_t* __restrict__ cid,
+                          uint32_t* __restrict__ col_node) {
+  const uint32_t ne = eff_count(n, n_dev);
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ne; i += gridDim.x * blockDim.x) {
+    const uint32_t c = excl[i] + flags[i] - 1;
+    cid[i] = c;
+    if (flags[i]) col_node[c] = list[i];
+  }
 }
 
 void launch_col_ids(const uint32_t* list, const uint32_t* flags, const uint32_t* excl, uint32_t n,
-                    uint32_t* cid, uint32_t* col_node, hipStream_t s) {
+                    uint32_t* cid, uint32_t* col_node, hipStream_t s, const uint32_t* n_dev) {
   if (n)
-    hipLaunchKernelGGL(k_col_ids, dim3(grid1d(n, 256)), dim3(256), 0, s, list, flags, excl, n, cid,
-                       col_node);
+    hipLaunchKernelGGL(k_col_ids, dim3(list_grid(n, 256, n_dev)), dim3(256), 0, s, list, flags,
+                       excl, n, n_dev, cid, col_node);
 }
 
 __global__ void k_hoist_layer0(const float* __restrict__ P, int ldp, const uint32_t* __restrict__ cid,
-                               const uint32_t* __restrict__ list, uint32_t n, int nz,
+                               const uint32_t* __restrict__ list, uint32_t n,
+                               const uint32_t* __restrict__ n_dev, int nz,
                                const float* __restrict__ wz, int N, int act,
                                void* __restrict__ h, int h_fmt, uint32_t* __restrict__ ovf) {
   // four consecutive outputs per thread (N % 4 == 0, ldp % 4 == 0; n * N / 4 < 2^32)
   const uint32_t n4 = (uint32_t)N >> 2;
-  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n * n4) return;
+  const uint32_t ne = eff_count(n, n_dev);
+  for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < ne * n4;
+       e += gridDim.x * blockDim.x) {
   const uint32_t i = e / n4;
   const uint32_t o = (e - i * n4) << 2;
   const uint32_t k = list[i] % (uint32_t)nz;
@@ -690,15 +729,16 @@ __global__ void k_hoist_layer0(const float* __restrict__ P, int ldp, const uint3
   } else {
     *reinterpret_cast<float4*>(reinterpret_cast<float*>(h) + at) = make_float4(v[0], v[1], v[2], v[3]);
   }
+  }
 }
 
 void launch_hoist_layer0(const float* P, int ldp, const uint32_t* cid, const uint32_t* list,
                          uint32_t n, int nz, const float* wz, int N, int act, void* h, int h_fmt,
-                         hipStream_t s, uint32_t* ovf) {
+                         hipStream_t s, uint32_t* ovf, const uint32_t* n_dev) {
   const size_t tot = (size_t)n * (N >> 2);
   if (tot)
-    hipLaunchKernelGGL(k_hoist_layer0, dim3(grid1d(tot, 256)), dim3(256), 0, s, P, ldp, cid, list,
-                       n, nz, wz, N, act, h, h_fmt, ovf);
+    hipLaunchKernelGGL(k_hoist_layer0, dim3(list_grid(tot, 256, n_dev)), dim3(256), 0, s, P, ldp,
+                       cid, list, n, n_dev, nz, wz, N, act, h, h_fmt, ovf);
 }
 
 // The library's number-format conversions applied to an array (for checking them).
@@ -715,10 +755,10 @@ void launch_convert(const float* in, uint32_t n, int fmt, void* out, hipStream_t
 }
 
 void launch_scatter_results(const uint32_t* pos, uint32_t n, const float* tl, const uint8_t* tb,
-                            float* logit, uint8_t* lab, hipStream_t s) {
+                            float* logit, uint8_t* lab, hipStream_t s, const uint32_t* n_dev) {
   if (n)
-    hipLaunchKernelGGL(k_scatter_results, dim3(grid1d(n, 256)), dim3(256), 0, s, pos, n, tl,
-                       tb, logit, lab);
+    hipLaunchKernelGGL(k_scatter_results, dim3(list_grid(n, 256, n_dev)), dim3(256), 0, s, pos, n,
+                       n_dev, tl, tb, logit, lab);
 }
 
 }  // namespace pifu

@@ -51,17 +51,20 @@ __device__ inline bool src_point64(const PointSrc& s, uint32_t idx, double P[3],
 
 // Node list of the guarded points: gnode[i] = list[glist[i]].
 __global__ void k_guard_nodes(const uint32_t* __restrict__ list, const uint32_t* __restrict__ glist,
-                              uint32_t gn, uint32_t* __restrict__ gnode) {
-  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < gn) gnode[i] = list ? list[glist[i]] : glist[i];
+                              uint32_t gn, const uint32_t* __restrict__ gn_dev,
+                              uint32_t* __restrict__ gnode) {
+  if (gn_dev) gn = min(gn, *gn_dev);
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < gn; i += gridDim.x * blockDim.x)
+    gnode[i] = list ? list[glist[i]] : glist[i];
 }
 
 // One wave per point: float64 bilinear blend of C channels; ext64 = (z', occ, clipped, 0).
 __global__ void __launch_bounds__(256)
 k_gather64(PointSrc src, const uint32_t* __restrict__ nodes, uint32_t n,
-           const float* __restrict__ F, int H, int W, int C, double* __restrict__ feat,
-           double* __restrict__ ext) {
+           const uint32_t* __restrict__ n_dev, const float* __restrict__ F, int H, int W, int C,
+           double* __restrict__ feat, double* __restrict__ ext) {
   const int lane = threadIdx.x & 63;
+  if (n_dev) n = min(n, *n_dev);
   const uint32_t waves = (gridDim.x * blockDim.x) >> 6;
   for (uint32_t m = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; m < n; m += waves) {
   double P[3], occ;
@@ -115,6 +118,7 @@ struct Gemm64Args {
   int n_ext, ext_col;
   double* C;
   int M, N, act;
+  const uint32_t* M_dev;   // device-side row count (nullable): rows = min(M, *M_dev)
 };
 
 // One 16 x 16 output tile per workgroup (v_mfma_f64_16x16x4f64).  The guard band
@@ -133,7 +137,7 @@ __global__ void __launch_bounds__(64 * kGuardWaves) k_gemm64(Gemm64Args a) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int n0 = blockIdx.y * 16;
   const int K = a.K1 + a.K2;
-  const int M = a.M;
+  const int M = a.M_dev ? min(a.M, (int)*a.M_dev) : a.M;
   const int g = lane >> 4, r16 = lane & 15;
   const double* wrow = a.W + (size_t)(n0 + r16) * K;
   const int nst = K >> 4;
@@ -193,10 +197,11 @@ __global__ void __launch_bounds__(64 * kGuardWaves) k_gemm64(Gemm64Args a) {
 // One wave per point: last layer in float64, then scatter to the guarded positions.
 __global__ void __launch_bounds__(256)
 k_head64(const double* __restrict__ h, int K, const float* __restrict__ W,
-         const float* __restrict__ b, uint32_t n, const double* __restrict__ ext,
-         const uint32_t* __restrict__ glist, float* __restrict__ logit,
-         uint8_t* __restrict__ lab) {
+         const float* __restrict__ b, uint32_t n, const uint32_t* __restrict__ n_dev,
+         const double* __restrict__ ext, const uint32_t* __restrict__ glist,
+         float* __restrict__ logit, uint8_t* __restrict__ lab) {
   const int lane = threadIdx.x & 63;
+  if (n_dev) n = min(n, *n_dev);
   const uint32_t waves = (gridDim.x * blockDim.x) >> 6;
   for (uint32_t m = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; m < n; m += waves) {
     double acc = 0.0;
@@ -229,8 +234,10 @@ size_t guard64_ws_bytes(const MLPDesc& d, uint32_t chunk) {
 // float64 and overwrites their logit and label.  ws holds guard64_ws_bytes(d, chunk).
 void run_guard64(const PointSrc& src, const uint32_t* list, const uint32_t* glist, uint32_t gn,
                  const MLPDesc& d, const float* F, int H, int W, int C, float* logit, uint8_t* lab,
-                 void* ws, uint32_t chunk, bool pack, hipStream_t s) {
+                 void* ws, uint32_t chunk, bool pack, hipStream_t s, const uint32_t* gn_dev) {
   if (!gn) return;
+  // with a device-side count the list holds at most one chunk (gn is its capacity)
+  if (gn_dev && gn > chunk) gn = chunk;
   const uint32_t max_waves = 2048;
   double* base = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(ws) + 255) & ~uintptr_t(255));
   double* Wp[PIFU_MAX_LAYERS];
@@ -255,11 +262,11 @@ void run_guard64(const PointSrc& src, const uint32_t* list, const uint32_t* glis
   uint32_t* gnode = reinterpret_cast<uint32_t*>(base);
   for (uint32_t c0 = 0; c0 < gn; c0 += chunk) {
     const uint32_t m = gn - c0 < chunk ? gn - c0 : chunk;
-    hipLaunchKernelGGL(k_guard_nodes, dim3(grid1d(m, 256)), dim3(256), 0, s, list, glist + c0, m,
-                       gnode);
+    hipLaunchKernelGGL(k_guard_nodes, dim3(std::min(grid1d(m, 256), kStrideBlocks)), dim3(256), 0,
+                       s, list, glist + c0, m, gn_dev, gnode);
     const uint32_t pw = std::min(m, max_waves);   // point-per-wave kernels: waves in the grid
     hipLaunchKernelGGL(k_gather64, dim3(grid1d((size_t)pw * 64, 256)), dim3(256), 0, s, src, gnode,
-                       m, F, H, W, C, feat, ext);
+                       m, gn_dev, F, H, W, C, feat, ext);
     const double* prev = nullptr;
     double* out = hA;
     for (int l = 0; l + 1 < d.n_layers; ++l) {
@@ -289,6 +296,7 @@ void run_guard64(const PointSrc& src, const uint32_t* list, const uint32_t* glis
       g.M = (int)m;
       g.N = d.widths[l];
       g.act = d.hidden_act;
+      g.M_dev = gn_dev;
       hipLaunchKernelGGL(k_gemm64, dim3(std::min<uint32_t>((m + 15) / 16, 64), d.widths[l] / 16),
                          dim3(64 * kGuardWaves), 0, s, g);
       prev = out;
@@ -296,7 +304,7 @@ void run_guard64(const PointSrc& src, const uint32_t* list, const uint32_t* glis
     }
     const int L = d.n_layers - 1;
     hipLaunchKernelGGL(k_head64, dim3(grid1d((size_t)pw * 64, 256)), dim3(256), 0, s, prev,
-                       d.widths[L - 1], d.W[L], d.b[L], m, ext, glist + c0, logit, lab);
+                       d.widths[L - 1], d.W[L], d.b[L], m, gn_dev, ext, glist + c0, logit, lab);
   }
 }
 

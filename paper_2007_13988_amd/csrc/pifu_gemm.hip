@@ -46,6 +46,21 @@ __device__ inline void tile_of_block(int& rt, int& ct) {
 // Row tiles of a launch over M rows in tiles of bm, rounded up to a multiple of 8.
 inline unsigned row_tiles(int M, int bm) { return (unsigned)(((M + bm - 1) / bm + 7) / 8 * 8); }
 
+// The same order for a persistent launch: a 1-D grid (a multiple of 8 workgroups) whose
+// workgroups take tile ids id, id + gridDim.x, ... of the tile set of the device-side
+// row count; tile id maps to (rt, ct) as workgroup id does above, so a workgroup stays
+// on one XCD's row tiles.
+__device__ inline void tile_of_id(int id, int nby, int& rt, int& ct) {
+  const int q = id >> 3;
+  rt = (q / nby) * 8 + (id & 7);
+  ct = q - (q / nby) * nby;
+}
+__device__ inline int tiles_of(int M, int bm, int nby) {
+  return ((M + bm - 1) / bm + 7) / 8 * 8 * nby;
+}
+// Workgroups of a persistent GEMM launch.
+constexpr unsigned kPersistBlocks = 512;
+
 __device__ inline float act_apply(float v, int act) {
   if (act == PIFU_ACT_RELU) return v > 0.f ? v : 0.f;
   if (act == PIFU_ACT_LRELU) return v > 0.f ? v : 0.01f * v;
@@ -156,7 +171,7 @@ __device__ inline bool stage_block(const GemmArgs& a, const f32x16& acc, int m0,
 // ------------------------------------------------------------------ FP32 operands
 // v_mfma_f32_32x32x2_f32: per lane one A and one B element per MFMA; 4 MFMAs consume
 // a float4 of k from LDS (k-group of 8).
-template <int BM, int BN, int WM, int WN, int MINB, int NT = 256>
+template <int BM, int BN, int WM, int WN, int MINB, int NT = 256, bool PERSIST = false>
 __global__ void __launch_bounds__(NT, MINB) k_gemm_f32(GemmArgs a) {
   // NT = 64 * WM * WN threads (the 32-point tile for tiny launches uses 2 waves)
   constexpr int BK = 32;
@@ -166,11 +181,17 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_f32(GemmArgs a) {
   __shared__ __attribute__((aligned(16))) float Bs[2][BN * LD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
-  int rt, ct;
-  tile_of_block(rt, ct);
-  const int m0 = rt * BM, n0 = ct * BN;
   const int M = a.M_dev ? min(a.M, (int)*a.M_dev) : a.M;
-  if (m0 >= M) return;
+  // persistent launches stride over the tiles of the device-side row count; others
+  // take the one tile of their workgroup
+  const int nby = a.N / BN;
+  const int n_ids = PERSIST ? tiles_of(M, BM, nby) : 1;
+  for (int id = PERSIST ? (int)blockIdx.x : 0; id < n_ids; id += PERSIST ? (int)gridDim.x : 1) {
+  int rt, ct;
+  if (PERSIST) tile_of_id(id, nby, rt, ct);
+  else tile_of_block(rt, ct);
+  const int m0 = rt * BM, n0 = ct * BN;
+  if (m0 >= M) continue;
   const int K = a.K1 + a.K2;
   const int nk = K / BK;
   constexpr int A_LOADS = BM * (BK / 4) / NT;
@@ -276,13 +297,16 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_f32(GemmArgs a) {
 #pragma unroll
     for (int j = 0; j < TJ; ++j)
       store_block<FMT_F32>(a, acc[i][j], m0 + wrow + 32 * i, n0 + wcol + 32 * j, lane, M);
+  if (PERSIST) __syncthreads();   // LDS is reused by the next tile
+  }
 }
 
 // ------------------------------------------------------------------ 16-bit operands
 // v_mfma_f32_32x32x16_bf16 (F16 = false) or v_mfma_f32_32x32x16_f16 (F16 = true): 8
 // 16-bit values per lane per MFMA (one 16-byte LDS read); BK = 64 per stage.  A, W and
 // (OUT16) C hold the same 16-bit format.
-template <int BM, int BN, int WM, int WN, int MINB, bool OUT16, bool F16, int NT = 256>
+template <int BM, int BN, int WM, int WN, int MINB, bool OUT16, bool F16, int NT = 256,
+          bool PERSIST = false>
 __global__ void __launch_bounds__(NT, MINB) k_gemm_h16(GemmArgs a) {
   // NT = 64 * WM * WN threads; the 256 x 256 tile uses 512 threads (8 waves of 128 x 64)
   constexpr int BK = 64;
@@ -296,11 +320,17 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_h16(GemmArgs a) {
   __bf16* const Bs = smem + 2 * BM * LD;    // stage b of B at Bs + b * BN * LD
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
-  int rt, ct;
-  tile_of_block(rt, ct);
-  const int m0 = rt * BM, n0 = ct * BN;
   const int M = a.M_dev ? min(a.M, (int)*a.M_dev) : a.M;
-  if (m0 >= M) return;
+  // persistent launches stride over the tiles of the device-side row count; others
+  // take the one tile of their workgroup
+  const int nby = a.N / BN;
+  const int n_ids = PERSIST ? tiles_of(M, BM, nby) : 1;
+  for (int id = PERSIST ? (int)blockIdx.x : 0; id < n_ids; id += PERSIST ? (int)gridDim.x : 1) {
+  int rt, ct;
+  if (PERSIST) tile_of_id(id, nby, rt, ct);
+  else tile_of_block(rt, ct);
+  const int m0 = rt * BM, n0 = ct * BN;
+  if (m0 >= M) continue;
   const int K = a.K1 + a.K2;
   const int nk = K / BK;
   constexpr int A_LOADS = BM * (BK / 8) / NT;
@@ -475,6 +505,8 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_h16(GemmArgs a) {
       for (int j = 0; j < TJ; ++j)
         store_block<FMT_F32>(a, acc[i][j], m0 + wrow + 32 * i, n0 + wcol + 32 * j, lane, M);
   }
+  if (PERSIST) __syncthreads();   // LDS is reused by the next tile
+  }
 }
 
 // ------------------------------------------------------------------ FP32 from FP16 x 3
@@ -486,7 +518,7 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_h16(GemmArgs a) {
 // its hi / lo copies (W, Wlo).  Values must lie in the binary16 range: an A value outside
 // it sets *a.ovf (the caller then re-runs in FP32).  BK = 32 or 64; every variant walks k
 // in the same 16-wide steps in the same order.
-template <int BM, int BN, int WM, int WN, int MINB, int NT = 256, int BK = 32>
+template <int BM, int BN, int WM, int WN, int MINB, int NT = 256, int BK = 32, bool PERSIST = false>
 __global__ void __launch_bounds__(NT, MINB) k_gemm_x3(GemmArgs a) {
   constexpr int LD = BK + 8;   // halves per LDS row
   constexpr int CA = BK / 4, CB = BK / 8;   // 16-byte chunks per staged A / W row
@@ -499,11 +531,17 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_x3(GemmArgs a) {
   auto Bl = [&](int b) { return Ah(b) + 2 * BM * LD + BN * LD; };
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
-  int rt, ct;
-  tile_of_block(rt, ct);
-  const int m0 = rt * BM, n0 = ct * BN;
   const int M = a.M_dev ? min(a.M, (int)*a.M_dev) : a.M;
-  if (m0 >= M) return;
+  // persistent launches stride over the tiles of the device-side row count; others
+  // take the one tile of their workgroup
+  const int nby = a.N / BN;
+  const int n_ids = PERSIST ? tiles_of(M, BM, nby) : 1;
+  for (int id = PERSIST ? (int)blockIdx.x : 0; id < n_ids; id += PERSIST ? (int)gridDim.x : 1) {
+  int rt, ct;
+  if (PERSIST) tile_of_id(id, nby, rt, ct);
+  else tile_of_block(rt, ct);
+  const int m0 = rt * BM, n0 = ct * BN;
+  if (m0 >= M) continue;
   const int K = a.K1 + a.K2;
   const int nk = K / BK;
   constexpr int A_LOADS = BM * (BK / 4) / NT;   // f32x4 per thread
@@ -628,6 +666,8 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_x3(GemmArgs a) {
       store_block<FMT_F32>(a, v, m0 + wrow + 32 * i, n0 + wcol + 32 * j, lane, M);
     }
   if (big && a.ovf) atomicOr(a.ovf, 1u);
+  if (PERSIST) __syncthreads();   // LDS is reused by the next tile
+  }
 }
 
 // Copies the first K columns of a row-major [N][ldw_src] fp32 weight matrix into a
@@ -918,6 +958,57 @@ void launch_h16(const GemmArgs& a, int bm, hipStream_t s, hipEvent_t ev0, hipEve
   }
 }
 #undef PIFU_H16
+
+// Persistent launch for a device-side row count (a.M_dev; a.M is the capacity): one tile
+// shape per precision, a 1-D grid of at most kPersistBlocks workgroups striding over the
+// tiles.  Same k order as every other tile, so the same results.
+int launch_gemm_persist(const GemmArgs& a, int precision, hipStream_t s) {
+  if (a.M <= 0) return 0;
+  const bool bn128 = (a.N % 128) == 0;
+  if (!bn128 && (a.N % 64) != 0) return -1;
+  auto grid = [&](int bm, int bn) {
+    size_t t = (size_t)row_tiles(a.M, bm) * (a.N / bn);
+    if (t > kPersistBlocks) t = kPersistBlocks;
+    return dim3((unsigned)t);   // row_tiles is a multiple of 8, so is t
+  };
+  if (precision == PIFU_PREC_FP32) {
+    if ((a.K1 % 32) || (a.K2 % 32)) return -1;
+    if (bn128)
+      hipLaunchKernelGGL((k_gemm_f32<128, 128, 2, 2, 2, 256, true>), grid(128, 128), dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_gemm_f32<128, 64, 4, 1, 2, 256, true>), grid(128, 64), dim3(256), 0, s, a);
+    return 0;
+  }
+  if (precision == PREC_F32X3) {
+    if ((a.K1 % 32) || (a.K2 % 32)) return -1;
+    hipLaunchKernelGGL((k_gemm_x3<64, 64, 2, 2, 2, 256, 32, true>), grid(64, 64), dim3(256), 0, s, a);
+    return 0;
+  }
+  if (precision == PIFU_PREC_BF16 || precision == PIFU_PREC_FP16) {
+    if ((a.K1 % 64) || (a.K2 % 64)) return -1;
+    const bool f16 = precision == PIFU_PREC_FP16;
+#define PIFU_HP(BN_, WM_, WN_)                                                                    \
+  do {                                                                                           \
+    if (f16 && a.c_bf16)                                                                         \
+      hipLaunchKernelGGL((k_gemm_h16<128, BN_, WM_, WN_, 2, true, true, 256, true>), grid(128, BN_), \
+                         dim3(256), 0, s, a);                                                    \
+    else if (f16)                                                                                \
+      hipLaunchKernelGGL((k_gemm_h16<128, BN_, WM_, WN_, 2, false, true, 256, true>),           \
+                         grid(128, BN_), dim3(256), 0, s, a);                                    \
+    else if (a.c_bf16)                                                                           \
+      hipLaunchKernelGGL((k_gemm_h16<128, BN_, WM_, WN_, 2, true, false, 256, true>),           \
+                         grid(128, BN_), dim3(256), 0, s, a);                                    \
+    else                                                                                         \
+      hipLaunchKernelGGL((k_gemm_h16<128, BN_, WM_, WN_, 2, false, false, 256, true>),          \
+                         grid(128, BN_), dim3(256), 0, s, a);                                    \
+  } while (0)
+    if (bn128) PIFU_HP(128, 2, 2);
+    else PIFU_HP(64, 4, 1);
+#undef PIFU_HP
+    return 0;
+  }
+  return -1;   // FP8 runs read their weight scales back on the host: no persistent form
+}
 
 int launch_gemm(const GemmArgs& a, int precision, int tile_m, hipStream_t s, hipEvent_t ev0,
                 hipEvent_t ev1) {

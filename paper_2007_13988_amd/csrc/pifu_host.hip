@@ -109,6 +109,7 @@ void prof_resolve(pifu_ctx* c) {
 
 constexpr size_t kAlign = 256;
 constexpr int kCounters = 64;
+constexpr int AW_COUNT_WORDS = 16;   // count words of a device-driven call
 constexpr int kHostWords = 256;   // pinned read-back buffer (>= every device counter block)
 constexpr uint32_t kDefaultChunk = 65536;
 
@@ -334,7 +335,8 @@ struct EvalWs {
   uint8_t* sur_lab = nullptr;
   // per-column hoisting (input view)
   uint32_t *cflags = nullptr, *cexcl = nullptr, *cid = nullptr, *cnode = nullptr, *cscan = nullptr;
-  float* Pcol = nullptr;     // chunk x NP
+  float* Pcol = nullptr;     // col_rows x NP
+  uint32_t col_rows = 0;
 };
 
 struct FieldPrep {
@@ -368,7 +370,7 @@ int pack_field(FieldPrep& fp, pifu_ctx* ctx, hipStream_t s, uint32_t* counters,
   uint32_t* ovf = nullptr;
   if (fp.has_mlp && fp.mlp.prec == PIFU_PREC_FP16) {
     ovf = counters + C_OVF;
-    if (clear) HIP_TRY(hipMemsetAsync(ovf, 0, sizeof(uint32_t), s));
+    if (clear) launch_set_u32(ovf, 0, s);   // a kernel: the call may be captured
   }
   if (fp.has_mlp) r = pack_mlp(fp.mlp, ctx, s, ovf);
   if (!r && fp.has_sur) r = pack_mlp(fp.sur, ctx, s, nullptr);
@@ -392,8 +394,13 @@ void carve_guard(Carver& cv, const FieldPrep& fp, uint32_t max_points, EvalWs& e
   }
 }
 
-void carve_eval(Carver& cv, uint32_t max_points, int C, int max_hidden, EvalWs& ew) {
-  ew.chunk = std::max<uint32_t>(128, std::min<uint32_t>(kDefaultChunk, (max_points + 127) / 128 * 128));
+// whole: one chunk holds max_points (device-driven calls, whose lists have device-side
+// lengths); else chunks of at most kDefaultChunk points.
+void carve_eval(Carver& cv, uint32_t max_points, int C, int max_hidden, EvalWs& ew,
+                bool whole = false) {
+  ew.chunk = whole ? std::max<uint32_t>(128, (max_points + 127) / 128 * 128)
+                   : std::max<uint32_t>(128, std::min<uint32_t>(kDefaultChunk,
+                                                                 (max_points + 127) / 128 * 128));
   const size_t ch = ew.chunk;
   ew.feat = cv.take<float>(ch * std::max(C, 1));
   ew.ext = cv.take<float>(ch * 4);
@@ -403,15 +410,18 @@ void carve_eval(Carver& cv, uint32_t max_points, int C, int max_hidden, EvalWs& 
 }
 
 // Buffers of per-column hoisting for a network with NP stacked feature outputs.
-void carve_hoist(Carver& cv, int NP, EvalWs& ew) {
+// col_cap (non-zero): at most this many columns per evaluation (the lattice's x-y
+// columns), so the hoisted rows need no more than that.
+void carve_hoist(Carver& cv, int NP, EvalWs& ew, uint32_t col_cap = 0) {
   if (NP <= 0) return;
   const size_t ch = ew.chunk;
+  ew.col_rows = col_cap ? std::min<uint32_t>(ew.chunk, col_cap) : ew.chunk;
   ew.cflags = cv.take<uint32_t>(ch);
   ew.cexcl = cv.take<uint32_t>(ch);
   ew.cid = cv.take<uint32_t>(ch);
   ew.cnode = cv.take<uint32_t>(ch);
   ew.cscan = cv.take<uint32_t>(scan_scratch_words(ch));
-  ew.Pcol = cv.take<float>(ch * NP);
+  ew.Pcol = cv.take<float>((size_t)ew.col_rows * NP);
 }
 
 int hoist_np(const FieldPrep& fp) {
@@ -435,6 +445,10 @@ struct EvalCtx {
   // FP8 calibration (FP32 plain path only): amax[0] <- max |feature|, amax[1 + l] <-
   // max |output of hidden layer l| (float bits, atomicMax)
   uint32_t* amax = nullptr;
+  // device-driven calls: their count words (AW_*) and the device stats record of the
+  // level being evaluated
+  uint32_t* aw = nullptr;
+  pifu_level_stats* st_dev = nullptr;
 };
 
 int batch_bucket(uint32_t m) { return m <= 8192 ? 0 : (m <= 32768 ? 1 : 2); }
@@ -982,13 +996,16 @@ struct GridWs {
   EvalWs ew;
   FieldPrep fp;
   uint32_t* counters;
+  uint32_t* aw = nullptr;    // device-driven calls: count words
   int T;
   int log2[3];
   size_t bytes;
 };
 
+// async_cap > 0: the layout of the device-driven call, whose evaluations hold up to
+// async_cap points in one pass.
 int plan_grid(const pifu_field* field, const pifu_grid_opts* o, void* base, float* occ_out,
-              GridWs& g) {
+              GridWs& g, uint32_t async_cap = 0) {
   const int L = o->log2_final;
   const int l0 = o->dense ? L : o->log2_coarse;
   g.T = L - l0;
@@ -1011,9 +1028,20 @@ int plan_grid(const pifu_field* field, const pifu_grid_opts* o, void* base, floa
   carve_field(cv, field, o->precision, g.fp);
   const int C = field->kind == PIFU_FIELD_MLP ? field->C : 0;
   const int mh = g.fp.has_mlp ? g.fp.mlp.max_hidden : 0;
-  carve_eval(cv, (uint32_t)max_n, C, mh, g.ew);
-  carve_guard(cv, g.fp, (uint32_t)max_n, g.ew);
-  carve_hoist(cv, hoist_np(g.fp), g.ew);
+  if (async_cap) {
+    g.aw = cv.take<uint32_t>(AW_COUNT_WORDS);
+    const uint32_t cap = (uint32_t)std::min<size_t>(async_cap, max_n);
+    if (g.fp.has_mlp) {
+      carve_eval(cv, cap, C, mh, g.ew, true);
+      carve_guard(cv, g.fp, cap, g.ew);
+      const Lat fin = g.lv[g.T].lat;
+      carve_hoist(cv, hoist_np(g.fp), g.ew, (uint32_t)fin.nx * fin.ny);
+    }
+  } else {
+    carve_eval(cv, (uint32_t)max_n, C, mh, g.ew);
+    carve_guard(cv, g.fp, (uint32_t)max_n, g.ew);
+    carve_hoist(cv, hoist_np(g.fp), g.ew);
+  }
   g.bytes = cv.off + kAlign;
   return PIFU_OK;
 }
@@ -1035,6 +1063,7 @@ struct RenderWs {
   EvalWs ew;
   FieldPrep fp, cp;
   uint32_t* counters;
+  uint32_t* aw = nullptr;    // device-driven calls: count words
   uint32_t *cnt, *kstar, *off, *scan_scratch, *hitlist;
   float4* hitpts;
   int T;
@@ -1060,7 +1089,7 @@ int validate_render_opts(const pifu_field* occ, const pifu_field* col, const pif
 }
 
 int plan_render(const pifu_field* occ, const pifu_field* col, const pifu_render_opts* o, void* base,
-                RenderWs& g) {
+                RenderWs& g, uint32_t async_cap = 0) {
   g.T = o->log2_w - o->log2_coarse_w;
   g.log2[0] = g.log2[1] = o->log2_w;
   g.log2[2] = o->log2_d;
@@ -1100,8 +1129,16 @@ int plan_render(const pifu_field* occ, const pifu_field* col, const pifu_render_
   }
   C = std::max(C, col->C);
   mh = std::max(mh, g.cp.mlp.max_hidden);
-  carve_eval(cv, (uint32_t)max_n, C, mh, g.ew);
-  carve_guard(cv, g.fp, (uint32_t)max_n, g.ew);
+  if (async_cap) {
+    // every evaluation, the colour of all W x W pixels included, fits one pass
+    g.aw = cv.take<uint32_t>(AW_COUNT_WORDS);
+    const uint32_t cap = (uint32_t)std::min<size_t>(std::max<size_t>(async_cap, ncol), max_n);
+    carve_eval(cv, cap, C, mh, g.ew, true);
+    carve_guard(cv, g.fp, cap, g.ew);
+  } else {
+    carve_eval(cv, (uint32_t)max_n, C, mh, g.ew);
+    carve_guard(cv, g.fp, (uint32_t)max_n, g.ew);
+  }
   g.bytes = cv.off + kAlign;
   return PIFU_OK;
 }
@@ -2246,6 +2283,561 @@ int32_t pifu_occupancy_grid_batched(pifu_ctx* ctx, int32_t n, const pifu_field* 
   prof_resolve(ctx);
   delete bp;
   return rc;
+}
+
+}  // extern "C"
+
+// ================================================================== device-driven calls
+// Asynchronous forms of pifu_occupancy_grid and pifu_render_view: every count stays in
+// device memory, every launch is sized from host-known capacities, and the level loop
+// runs a fixed ladder of conflict waves whose kernels find an empty list once the
+// waves have converged.  Nothing is read back and nothing is allocated, so a call can
+// be captured into a HIP graph and replayed.  The kernels and their arithmetic are the
+// blocking calls' own (persistent GEMM launches walk k in the same order), so results
+// are identical.
+namespace {
+
+// count words of a device-driven call (AW_*), after the level counters
+enum {
+  AW_NCOL = 0,   // columns of the hoisted evaluation
+  AW_NB,         // points of the precision band
+  AW_NS,         // surrogate points sent to the full network
+  AW_GN,         // points of the FP64 guard
+  AW_RR,         // points re-run in FP32 after an FP16 range overflow (0 or all)
+  AW_N0,         // a host-known count, stored for kernels that read counts from memory
+  AW_NH,         // render hits
+  AW_STATUS,     // status bits (kStatus*)
+  AW_COUNT = 16
+};
+// bits of the status word
+constexpr uint32_t kStatusListOver = 1;    // a list exceeded max_points (results invalid)
+constexpr uint32_t kStatusWavesLeft = 2;   // conflicts remained after the wave budget
+constexpr uint32_t kStatusGuardOver = 4;   // more guard points than the FP64 chunk holds
+constexpr uint32_t kStatusCellsOver = 8;   // more surface cells than cells_cap
+constexpr int kDefaultWaveBudget = 12;
+
+struct Book {
+  BookOps ops;
+  hipStream_t s;
+  explicit Book(hipStream_t st) : s(st) {}
+  void add(int kind, uint32_t* dst, const uint32_t* src = nullptr, uint32_t imm = 0,
+           uint32_t bit = 0, const uint32_t* aux = nullptr, const uint32_t* src2 = nullptr) {
+    if (ops.n == kMaxBookOps) flush();
+    ops.op[ops.n++] = BookOp{dst, src, src2, aux, imm, bit, kind};
+  }
+  void flush() {
+    launch_book(ops, s);
+    ops.n = 0;
+  }
+  ~Book() { flush(); }
+};
+
+uint32_t* stat_word(pifu_level_stats* st, uint32_t pifu_level_stats::*f) {
+  return reinterpret_cast<uint32_t*>(&(st->*f));
+}
+
+// run_mlp over a list whose length lives on the device (at most cap <= ew.chunk
+// points): one pass, persistent GEMMs, list kernels striding over the count.
+int run_mlp_dev(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const PointSrc& src,
+                const uint32_t* list, uint32_t cap, const uint32_t* n_dev, const EvalWs& ew,
+                float* logit, uint8_t* lab, float* rgb, const float* F = nullptr) {
+  const pifu_field* f = fp.f;
+  const MLPDesc& d = mp.d;
+  const int C = f->C;
+  if (!cap) return PIFU_OK;
+  if (cap > ew.chunk) return PIFU_ERR_WORKSPACE_TOO_SMALL;
+  const bool x3 = prec == PREC_F32X3;
+  const bool b16 = prec != PIFU_PREC_FP32 && !x3;
+  const int hf = x3 ? FMT_F32 : h16_fmt(prec);
+  if ((prec == PIFU_PREC_BF16 || prec == PIFU_PREC_FP16) && mp.prec != prec)
+    return PIFU_ERR_UNSUPPORTED;
+  if (x3 && mp.prec != PIFU_PREC_FP16) return PIFU_ERR_UNSUPPORTED;
+  if (prec == PIFU_PREC_FP8) return PIFU_ERR_UNSUPPORTED;
+  if (!F) F = f->feat;
+  uint32_t* ovf = prec == PIFU_PREC_FP16 || x3 ? e.counters + C_OVF : nullptr;
+  const bool hoist = src.mode == 0 && !src.has_view && mp.NP > 0 && mp.NP % 4 == 0 &&
+                     d.widths[0] % 4 == 0 && ew.Pcol != nullptr;
+  const void* prev = nullptr;
+  void* out = ew.hA;
+  int l0 = 0;
+  GemmArgs g;
+  if (hoist) {
+    uint32_t* ncol = e.aw + AW_NCOL;
+    const uint32_t ccap = std::min(cap, ew.col_rows);
+    launch_col_flags(list, cap, (uint32_t)src.nz, ew.cflags, e.s, n_dev);
+    launch_scan_u32(ew.cflags, cap, ew.cexcl, ew.cscan, ncol, e.s, n_dev);
+    launch_col_ids(list, ew.cflags, ew.cexcl, cap, ew.cid, ew.cnode, e.s, n_dev);
+    launch_gather(src, ew.cnode, ccap, F, f->H, f->W, C, ew.feat, hf, ew.ext, e.s, ncol, ovf);
+    std::memset(&g, 0, sizeof(g));
+    g.A1 = ew.feat;
+    g.K1 = g.lda1 = C;
+    g.W = b16 || x3 ? (const void*)mp.Wf16 : (const void*)mp.Wf32;
+    g.Wlo = x3 ? (const void*)mp.Wflo16 : nullptr;
+    g.ovf = ovf;
+    g.ldw = C;
+    g.bias = mp.bf;
+    g.C = ew.Pcol;
+    g.ldc = g.N = mp.NP;
+    g.M = (int)ccap;
+    g.M_dev = ncol;
+    g.scale = 1.f;
+    if (launch_gemm_persist(g, prec, e.s)) return PIFU_ERR_UNSUPPORTED;
+    launch_hoist_layer0(ew.Pcol, mp.NP, ew.cid, list, cap, src.nz, mp.wz, d.widths[0],
+                        d.hidden_act, ew.hA, d.n_layers > 2 ? hf : FMT_F32, e.s, ovf, n_dev);
+    prev = ew.hA;
+    out = ew.hB;
+    l0 = 1;
+  } else {
+    launch_gather(src, list, cap, F, f->H, f->W, C, ew.feat, hf, ew.ext, e.s, n_dev, ovf);
+  }
+  for (int l = l0; l + 1 < d.n_layers; ++l) {
+    std::memset(&g, 0, sizeof(g));
+    if (l == 0) {
+      g.A1 = ew.feat;
+      g.K1 = g.lda1 = C;
+      g.n_ext = d.n_extra;
+      g.ext_col = C;
+      g.bias = d.b[l];
+    } else {
+      g.A1 = prev;
+      g.K1 = g.lda1 = d.widths[l - 1];
+      if (hoist && mp.hoist_off[l] >= 0) {
+        g.rowadd = ew.Pcol;
+        g.rowadd_idx = ew.cid;
+        g.rowadd_ld = mp.NP;
+        g.rowadd_off = mp.hoist_off[l];
+      } else {
+        g.bias = d.b[l];
+        if (d.skip[l]) {
+          g.A2 = ew.feat;
+          g.K2 = g.lda2 = C;
+        }
+      }
+    }
+    g.W = layer_weights(mp, prec, l);
+    g.Wlo = x3 ? (const void*)mp.Wlo16[l] : nullptr;
+    g.ldw = mp.Kp[l];
+    g.Wf = d.W[l];
+    g.ldwf = d.in_w[l];
+    g.ext = ew.ext;
+    g.C = out;
+    g.ldc = g.N = d.widths[l];
+    g.M = (int)cap;
+    g.M_dev = n_dev;
+    g.act = d.hidden_act;
+    g.scale = 1.f;
+    g.c_bf16 = b16 && (l + 2 < d.n_layers);
+    g.ovf = ovf;
+    if (launch_gemm_persist(g, prec, e.s)) return PIFU_ERR_UNSUPPORTED;
+    prev = out;
+    out = (out == ew.hA) ? ew.hB : ew.hA;
+  }
+  const int L = d.n_layers - 1;
+  launch_head(reinterpret_cast<const float*>(prev), d.widths[L - 1], d.W[L], d.b[L], d.widths[L],
+              d.out_act, cap, hoist ? nullptr : ew.ext, logit, lab, rgb, rgb ? list : nullptr, e.s,
+              n_dev);
+  return check_launch();
+}
+
+// Positions m < *n_dev with |logit[m]| < bound into pos; their count into *cnt.
+void select_dev(EvalCtx& e, const float* logit, uint32_t cap, const uint32_t* n_dev, float bound,
+                uint32_t* pos, uint32_t* cnt) {
+  launch_set_u32(cnt, 0, e.s);
+  launch_guard_select(logit, cap, bound, pos, cnt, e.s, nullptr, 0, n_dev);
+}
+
+// post_full for a device-side count: the precision band (with the FP32 re-run of an FP16
+// call whose values left the binary16 range), then the FP64 guard.
+int post_full_dev(EvalCtx& e, const FieldPrep& fp, const PointSrc& src, const float* F,
+                  const uint32_t* list, uint32_t cap, const uint32_t* n_dev, const EvalWs& ew,
+                  float* logit, uint8_t* lab) {
+  const pifu_field* f = fp.f;
+  int r = PIFU_OK;
+  const bool f16 = e.precision == PIFU_PREC_FP16;
+  const bool band = e.precision != PIFU_PREC_FP32 && e.band > 0.f;
+  uint32_t* nb = e.aw + AW_NB;
+  if (band) {
+    select_dev(e, logit, cap, n_dev, e.band, ew.band_pos, nb);
+    launch_gather_u32(list, ew.band_pos, cap, ew.band_nodes, e.s, nb);
+    r = run_mlp_dev(e, fp, fp.mlp, f16 ? PREC_F32X3 : PIFU_PREC_FP32, src, ew.band_nodes, cap, nb,
+                    ew, ew.band_logit, ew.band_lab, nullptr, F);
+    if (r) return r;
+    launch_scatter_results(ew.band_pos, cap, ew.band_logit, ew.band_lab, logit, lab, e.s, nb);
+  }
+  Book b(e.s);
+  uint32_t* band_stat = stat_word(e.st_dev, &pifu_level_stats::band_fp32);
+  if (f16) {
+    // a value outside the binary16 range so far in this call: all points in FP32
+    uint32_t* rr = e.aw + AW_RR;
+    b.add(BK_SEL, rr, n_dev, 0, 0, e.counters + C_OVF);
+    b.add(BK_ADD_SEL, band_stat, n_dev, 0, 0, e.counters + C_OVF, band ? nb : nullptr);
+    b.flush();
+    r = run_mlp_dev(e, fp, fp.mlp, PIFU_PREC_FP32, src, list, cap, rr, ew, logit, lab, nullptr, F);
+    if (r) return r;
+  } else if (band) {
+    b.add(BK_ADD, band_stat, nb);
+  }
+  if (!(e.guard > 0.f)) return PIFU_OK;
+  uint32_t* gn = e.aw + AW_GN;
+  select_dev(e, logit, cap, n_dev, e.guard, ew.glist, gn);
+  run_guard64(src, list, ew.glist, std::min(cap, ew.chunk64), fp.mlp.d, F, f->H, f->W, f->C, logit,
+              lab, ew.g64, ew.chunk64, !e.g64_packed, e.s, gn);
+  e.g64_packed = true;
+  b.add(BK_ADD, stat_word(e.st_dev, &pifu_level_stats::guard_fp64), gn);
+  b.add(BK_FLAG_GT, e.aw + AW_STATUS, gn, ew.chunk64, kStatusGuardOver);
+  return check_launch();
+}
+
+int eval_full_dev(EvalCtx& e, const FieldPrep& fp, const PointSrc& src, const uint32_t* list,
+                  uint32_t cap, const uint32_t* n_dev, const EvalWs& ew, float* logit,
+                  uint8_t* lab) {
+  int r = run_mlp_dev(e, fp, fp.mlp, e.precision, src, list, cap, n_dev, ew, logit, lab, nullptr);
+  if (r) return r;
+  {
+    Book b(e.s);
+    b.add(BK_ADD, stat_word(e.st_dev, &pifu_level_stats::mlp_points), n_dev);
+  }
+  return post_full_dev(e, fp, src, fp.f->feat, list, cap, n_dev, ew, logit, lab);
+}
+
+// eval_occupancy for a device-side count.
+int eval_occupancy_dev(EvalCtx& e, const FieldPrep& fp, const PointSrc& src, const uint32_t* list,
+                       uint32_t cap, const uint32_t* n_dev, const EvalWs& ew, float* logit,
+                       uint8_t* lab, bool use_surrogate) {
+  if (!cap) return PIFU_OK;
+  if (!fp.has_mlp) {
+    launch_eval_analytic(src, list, cap, fp.f->kind, fp.ell, fp.f->plane, logit, lab, e.s, n_dev);
+    return check_launch();
+  }
+  if (!(use_surrogate && fp.has_sur)) return eval_full_dev(e, fp, src, list, cap, n_dev, ew, logit, lab);
+  int r = run_mlp_dev(e, fp, fp.sur, PIFU_PREC_BF16, src, list, cap, n_dev, ew, logit, lab, nullptr);
+  if (r) return r;
+  uint32_t* ns = e.aw + AW_NS;
+  select_dev(e, logit, cap, n_dev, e.sur_band, ew.sur_pos, ns);
+  launch_gather_u32(list, ew.sur_pos, cap, ew.sur_nodes, e.s, ns);
+  r = eval_full_dev(e, fp, src, ew.sur_nodes, cap, ns, ew, ew.sur_logit, ew.sur_lab);
+  if (r) return r;
+  launch_scatter_results(ew.sur_pos, cap, ew.sur_logit, ew.sur_lab, logit, lab, e.s, ns);
+  Book b(e.s);
+  b.add(BK_ADD, stat_word(e.st_dev, &pifu_level_stats::surrogate_fallback), ns);
+  return check_launch();
+}
+
+// localize with device-side counts and a fixed ladder of waves per level: rung 0
+// evaluates the candidates, rungs 1 .. budget the conflict waves.  max_waves > 0 is the
+// caller's own cap (as in the blocking call); with max_waves == 0 the ladder has
+// kDefaultWaveBudget waves and a level with conflicts left after it sets
+// kStatusWavesLeft.  stats_dev: one device record per level.
+int localize_dev(EvalCtx& e, const FieldPrep& fp, const EvalWs& ew, const double* view,
+                 int T, int last, LevelBuf* lv, const LocalizeWs& w, uint8_t* eval_level,
+                 Lat eval_lat, int max_waves, int sur_max_log2, pifu_level_stats* stats_dev,
+                 uint32_t cap, float* eval_logit = nullptr) {
+  PointSrc src;
+  std::memset(&src, 0, sizeof(src));
+  src.mode = 0;
+  if (view) {
+    src.has_view = 1;
+    for (int i = 0; i < 12; ++i) src.view[i] = view[i];
+  }
+  const bool bounded = max_waves > 0;
+  const int budget = bounded ? max_waves : kDefaultWaveBudget;
+  uint32_t* n_dev = e.counters + C_TOTAL;
+  for (int t = 0; t <= last; ++t) {
+    LevelBuf& L = lv[t];
+    pifu_level_stats* sd = stats_dev + t;
+    e.st_dev = sd;
+    src.nx = L.lat.nx;
+    src.ny = L.lat.ny;
+    src.nz = L.lat.nz;
+    const int stride = (eval_lat.nx - 1) / (L.lat.nx - 1);
+    const uint32_t n_nodes = (uint32_t)L.lat.n();
+    const bool sur = L.level_id <= sur_max_log2;
+    launch_set_u32(e.counters, 0, e.s, C_OVF);   // keeps C_OVF
+    {
+      Book b(e.s);
+      b.add(BK_SET_IMM, reinterpret_cast<uint32_t*>(&sd->level), nullptr, (uint32_t)L.level_id);
+      b.add(BK_SET_IMM, stat_word(sd, &pifu_level_stats::nodes), nullptr, n_nodes);
+    }
+    if (t == 0) {
+      if (n_nodes > cap) return PIFU_ERR_WORKSPACE_TOO_SMALL;
+      launch_fill_u8(L.st, 0, n_nodes, e.s);
+      launch_iota(w.list, n_nodes, e.s);
+      {
+        Book b(e.s);
+        b.add(BK_SET_IMM, e.aw + AW_N0, nullptr, n_nodes);
+      }
+      int r = eval_occupancy_dev(e, fp, src, w.list, n_nodes, e.aw + AW_N0, ew, w.logit, w.lab, sur);
+      if (r) return r;
+      launch_apply_grid(w.list, n_nodes, w.logit, w.lab, L.st, L.occ, nullptr, eval_level,
+                        L.level_id, L.lat, stride, eval_lat, 0, e.s, 0, nullptr, eval_logit);
+      Book b(e.s);
+      b.add(BK_SET_IMM, stat_word(sd, &pifu_level_stats::dilated), nullptr, n_nodes);
+      b.add(BK_SET_IMM, stat_word(sd, &pifu_level_stats::evaluated), nullptr, n_nodes);
+      continue;
+    }
+    LevelBuf& Cc = lv[t - 1];
+    launch_transition(Cc.st, Cc.occ, Cc.lat, L.st, L.occ, L.lat, e.s);
+    if (2 * b0_mask_words(L.lat) <= n_nodes) {
+      launch_select_b0(L.st, L.lat, 1, reinterpret_cast<uint64_t*>(w.list), e.counters + C_B0, 0,
+                       e.s);
+    } else {
+      launch_count_bits(L.st, n_nodes, ST_B0, e.counters + C_B0, e.s);
+      launch_select(L.st, L.lat, e.s);
+    }
+    launch_compact(L.st, n_nodes, ST_PEND, ST_PEND, w.cscratch, n_dev, w.list, n_nodes, 0, L.lat,
+                   e.s);
+    const uint32_t ecap = std::min(n_nodes, cap);
+    {
+      Book b(e.s);
+      b.add(BK_SET, stat_word(sd, &pifu_level_stats::dilated), n_dev);
+      b.add(BK_FLAG_GT, e.aw + AW_STATUS, n_dev, cap, kStatusListOver);
+    }
+    for (int rung = 0; rung <= budget; ++rung) {
+      int r = eval_occupancy_dev(e, fp, src, w.list, ecap, n_dev, ew, w.logit, w.lab, sur);
+      if (r) return r;
+      launch_apply_grid(w.list, ecap, w.logit, w.lab, L.st, L.occ, e.counters + C_CONFLICTS,
+                        eval_level, L.level_id, L.lat, stride, eval_lat, 1, e.s, 0, nullptr,
+                        eval_logit, n_dev);
+      {
+        Book b(e.s);
+        b.add(BK_ADD, stat_word(sd, &pifu_level_stats::evaluated), n_dev);
+      }
+      if (rung == budget && bounded) break;
+      launch_expand(w.list, ecap, L.st, L.lat, e.s, 0, n_dev);
+      launch_compact(L.st, n_nodes, ST_PEND, ST_PEND, w.cscratch, n_dev, w.list, n_nodes, 0, L.lat,
+                     e.s);
+      Book b(e.s);
+      if (rung < budget) {
+        b.add(BK_ADD_NZ, stat_word(sd, &pifu_level_stats::waves), n_dev);
+        b.add(BK_FLAG_GT, e.aw + AW_STATUS, n_dev, cap, kStatusListOver);
+      } else {
+        b.add(BK_FLAG_GT, e.aw + AW_STATUS, n_dev, 0, kStatusWavesLeft);
+      }
+    }
+    Book b(e.s);
+    b.add(BK_SET, stat_word(sd, &pifu_level_stats::conflicts), e.counters + C_CONFLICTS);
+    b.add(BK_SET, stat_word(sd, &pifu_level_stats::b0), e.counters + C_B0);
+  }
+  return check_launch();
+}
+
+}  // namespace
+
+namespace {
+
+uint32_t default_async_cap(size_t max_n) {
+  return (uint32_t)std::min<size_t>(max_n, (size_t)1 << 20);
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t pifu_occupancy_grid_async_workspace_size(const pifu_field* field,
+                                                 const pifu_grid_opts* opts, uint32_t max_points,
+                                                 size_t* bytes) {
+  if (!bytes) return PIFU_ERR_INVALID_ARGUMENT;
+  int r = validate_grid_opts(field, opts);
+  if (r) return r;
+  if (opts->precision == PIFU_PREC_FP8) return PIFU_ERR_UNSUPPORTED;
+  GridWs* g = new (std::nothrow) GridWs;
+  if (!g) return PIFU_ERR_HIP;
+  plan_grid(field, opts, nullptr, nullptr, *g, 1);
+  size_t max_n = 0;
+  for (int t = 0; t <= g->T; ++t) max_n = std::max(max_n, g->lv[t].lat.n());
+  const uint32_t cap = max_points ? max_points : default_async_cap(max_n);
+  plan_grid(field, opts, nullptr, nullptr, *g, cap);
+  *bytes = g->bytes;
+  delete g;
+  return PIFU_OK;
+}
+
+int32_t pifu_occupancy_grid_async(pifu_ctx* ctx, const pifu_field* field,
+                                  const pifu_grid_opts* opts, uint32_t max_points, float* occ,
+                                  uint8_t* labels, uint8_t* eval_level, uint32_t* cells,
+                                  uint32_t cells_cap, uint32_t* n_cells_dev,
+                                  pifu_level_stats* stats_dev, uint32_t* status_dev,
+                                  void* workspace, size_t workspace_bytes, pifu_stream stream) {
+  if (!ctx || !occ || !labels || !n_cells_dev || !stats_dev || !status_dev || !workspace)
+    return PIFU_ERR_INVALID_ARGUMENT;
+  if (cells_cap && !cells) return PIFU_ERR_INVALID_ARGUMENT;
+  if (!aligned(workspace, kAlign) || !aligned(stats_dev, 4) || !aligned(n_cells_dev, 4) ||
+      !aligned(status_dev, 4))
+    return PIFU_ERR_INVALID_ARGUMENT;
+  size_t need = 0;
+  int r = pifu_occupancy_grid_async_workspace_size(field, opts, max_points, &need);
+  if (r) return r;
+  if (workspace_bytes < need) return PIFU_ERR_WORKSPACE_TOO_SMALL;
+  GridWs* gp = new (std::nothrow) GridWs;
+  if (!gp) return PIFU_ERR_HIP;
+  GridWs& g = *gp;
+  plan_grid(field, opts, nullptr, nullptr, g, 1);
+  size_t max_n = 0;
+  for (int t = 0; t <= g.T; ++t) max_n = std::max(max_n, g.lv[t].lat.n());
+  const uint32_t cap = (uint32_t)std::min<size_t>(max_points ? max_points : default_async_cap(max_n),
+                                                  max_n);
+  plan_grid(field, opts, workspace, occ, g, cap);
+  hipStream_t s = as_stream(stream);
+  EvalCtx e{ctx, s, g.counters, opts->precision, opts->guard_logit};
+  e.band = logit_band(opts->band_delta);
+  e.sur_band = logit_band(opts->surrogate_delta);
+  e.aw = g.aw;
+  const int n_levels = g.T + 1;
+  launch_set_u32(g.aw, 0, s, AW_COUNT_WORDS);
+  launch_set_u32(reinterpret_cast<uint32_t*>(stats_dev), 0, s,
+                 (uint32_t)(n_levels * sizeof(pifu_level_stats) / 4));
+  r = pack_field(g.fp, ctx, s, g.counters);
+  const Lat fin = g.lv[g.T].lat;
+  if (!r && eval_level) launch_fill_u8(eval_level, 255, fin.n(), s);
+  if (!r)
+    r = localize_dev(e, g.fp, g.ew, nullptr, g.T, g.T, g.lv, g.w, eval_level, fin, opts->max_waves,
+                     opts->surrogate_max_log2, stats_dev, cap);
+  if (!r) {
+    launch_cells(g.lv[g.T].st, fin, labels, s);
+    launch_compact(g.lv[g.T].st, fin.n(), ST_CELL, ST_CELL, g.w.cscratch, g.counters + C_TOTAL,
+                   cells, cells_cap, 1, fin, s);
+    Book b(s);
+    b.add(BK_SET, n_cells_dev, g.counters + C_TOTAL);
+    b.add(BK_FLAG_GT, g.aw + AW_STATUS, g.counters + C_TOTAL, cells_cap, kStatusCellsOver);
+    b.add(BK_SET, status_dev, g.aw + AW_STATUS);
+  }
+  if (!r) r = check_launch();
+  delete gp;
+  return r;
+}
+
+int32_t pifu_render_view_async_workspace_size(const pifu_field* occ_field,
+                                              const pifu_field* color_field,
+                                              const pifu_render_opts* opts, uint32_t max_points,
+                                              size_t* bytes) {
+  if (!bytes) return PIFU_ERR_INVALID_ARGUMENT;
+  int r = validate_render_opts(occ_field, color_field, opts);
+  if (r) return r;
+  if (opts->precision == PIFU_PREC_FP8) return PIFU_ERR_UNSUPPORTED;
+  RenderWs* g = new (std::nothrow) RenderWs;
+  if (!g) return PIFU_ERR_HIP;
+  const size_t W = (size_t)1 << opts->log2_w, D = (size_t)1 << opts->log2_d;
+  const uint32_t cap = max_points ? max_points : default_async_cap(W * W * (D + 1));
+  plan_render(occ_field, color_field, opts, nullptr, *g, cap);
+  *bytes = g->bytes;
+  delete g;
+  return PIFU_OK;
+}
+
+int32_t pifu_render_view_async(pifu_ctx* ctx, const pifu_field* occ_field,
+                               const pifu_field* color_field, const float* view,
+                               const pifu_render_opts* opts, uint32_t max_points, const float* bg,
+                               float* rgb, float* depth, uint8_t* hit, pifu_level_stats* stats_dev,
+                               uint32_t* status_dev, void* workspace, size_t workspace_bytes,
+                               pifu_stream stream) {
+  if (!ctx || !view || !bg || !rgb || !depth || !hit || !stats_dev || !status_dev || !workspace)
+    return PIFU_ERR_INVALID_ARGUMENT;
+  if (!aligned(workspace, kAlign) || !aligned(stats_dev, 4) || !aligned(status_dev, 4))
+    return PIFU_ERR_INVALID_ARGUMENT;
+  size_t need = 0;
+  int r = pifu_render_view_async_workspace_size(occ_field, color_field, opts, max_points, &need);
+  if (r) return r;
+  if (workspace_bytes < need) return PIFU_ERR_WORKSPACE_TOO_SMALL;
+  RenderWs* gp = new (std::nothrow) RenderWs;
+  if (!gp) return PIFU_ERR_HIP;
+  RenderWs& g = *gp;
+  const int T = opts->log2_w - opts->log2_coarse_w;
+  const int W = 1 << opts->log2_w, H = W, D = 1 << opts->log2_d;
+  const size_t ncol = (size_t)W * H, last_n = ncol * (D + 1);
+  const uint32_t cap0 = max_points ? max_points : default_async_cap(last_n);
+  plan_render(occ_field, color_field, opts, workspace, g, cap0);
+  const uint32_t cap = g.ew.chunk ? g.ew.chunk : cap0;   // what one pass holds
+  hipStream_t s = as_stream(stream);
+  EvalCtx e{ctx, s, g.counters, opts->precision, opts->guard_logit};
+  e.band = logit_band(opts->band_delta);
+  e.sur_band = logit_band(opts->surrogate_delta);
+  e.aw = g.aw;
+  launch_set_u32(g.aw, 0, s, AW_COUNT_WORDS);
+  launch_set_u32(reinterpret_cast<uint32_t*>(stats_dev), 0, s,
+                 (uint32_t)((T + 1) * sizeof(pifu_level_stats) / 4));
+  r = pack_field(g.fp, ctx, s, g.counters);
+  if (!r)
+    r = pack_field(g.cp, ctx, s, g.counters, !(g.fp.has_mlp && g.fp.mlp.prec == PIFU_PREC_FP16));
+  double vd[12];
+  for (int i = 0; i < 12; ++i) vd[i] = view[i];
+  const Lat finL = level_lattice(g.log2, T, T);
+  if (!r)
+    r = localize_dev(e, g.fp, g.ew, vd, T, T - 1, g.lv, g.w, nullptr, finL, opts->max_waves,
+                     opts->surrogate_max_log2, stats_dev, cap);
+  if (r) {
+    delete gp;
+    return r;
+  }
+  // last level: interpolate, argmax along z from the observer, shadow nodes
+  pifu_level_stats* sd = stats_dev + T;
+  e.st_dev = sd;
+  const LevelBuf& C = g.lv[T - 1];
+  uint32_t* n_dev = g.counters + C_TOTAL;
+  launch_set_u32(g.counters, 0, s, C_OVF);   // keeps C_OVF
+  launch_fill_image(rgb, depth, hit, (uint32_t)(W * H), bg[0], bg[1], bg[2], s);
+  launch_ray_count(C.st, C.lat, W, H, D, g.cnt, g.kstar, g.counters + C_SHADOW, s);
+  launch_scan_u32(g.cnt, (uint32_t)(W * H), g.off, g.scan_scratch, n_dev, s);
+  launch_ray_list(C.st, C.lat, W, H, D, g.kstar, g.off, g.w.list, s);
+  {
+    Book b(s);
+    b.add(BK_SET_IMM, reinterpret_cast<uint32_t*>(&sd->level), nullptr, (uint32_t)opts->log2_w);
+    b.add(BK_SET_IMM, stat_word(sd, &pifu_level_stats::nodes), nullptr, (uint32_t)last_n);
+    b.add(BK_SET, stat_word(sd, &pifu_level_stats::shadow), g.counters + C_SHADOW);
+    b.add(BK_SET, stat_word(sd, &pifu_level_stats::dilated), n_dev);
+    b.add(BK_SET, stat_word(sd, &pifu_level_stats::evaluated), n_dev);
+    b.add(BK_FLAG_GT, g.aw + AW_STATUS, n_dev, cap, kStatusListOver);
+  }
+  PointSrc src;
+  std::memset(&src, 0, sizeof(src));
+  src.mode = 0;
+  src.nx = finL.nx;
+  src.ny = finL.ny;
+  src.nz = finL.nz;
+  src.has_view = 1;
+  for (int i = 0; i < 12; ++i) src.view[i] = vd[i];
+  const uint32_t ecap = (uint32_t)std::min<size_t>(last_n, cap);
+  r = eval_occupancy_dev(e, g.fp, src, g.w.list, ecap, n_dev, g.ew, g.w.logit, g.w.lab,
+                         opts->log2_w <= opts->surrogate_max_log2);
+  if (!r) {
+    launch_ray_hit(C.st, C.occ, C.lat, W, H, D, g.off, g.cnt, g.w.list, g.w.logit, g.w.lab, vd,
+                   depth, hit, g.hitpts, s);
+    Lat img{1, 1, W * H};
+    uint32_t* nh = g.aw + AW_NH;
+    launch_compact(hit, (size_t)W * H, 1, 1, g.w.cscratch, nh, g.hitlist, (uint32_t)(W * H), 0, img,
+                   s);
+    {
+      Book b(s);
+      b.add(BK_SET, stat_word(sd, &pifu_level_stats::hits), nh);
+    }
+    PointSrc ps;
+    std::memset(&ps, 0, sizeof(ps));
+    ps.mode = 1;
+    ps.pts = g.hitpts;
+    EvalCtx ec{ctx, s, g.counters, PIFU_PREC_FP32, 0.f};
+    ec.aw = g.aw;
+    ec.st_dev = sd;
+    // FP16 renders colour with split-FP16 products; a value of this call outside the
+    // binary16 range (the occupancy passes' or these products') re-runs them in FP32
+    const bool x3 = g.cp.mlp.prec == PIFU_PREC_FP16;
+    r = run_mlp_dev(ec, g.cp, g.cp.mlp, x3 ? PREC_F32X3 : PIFU_PREC_FP32, ps, g.hitlist,
+                    (uint32_t)(W * H), nh, g.ew, nullptr, nullptr, rgb);
+    if (!r && x3) {
+      uint32_t* rr = g.aw + AW_RR;
+      {
+        Book b(s);
+        b.add(BK_SEL, rr, nh, 0, 0, g.counters + C_OVF);
+      }
+      r = run_mlp_dev(ec, g.cp, g.cp.mlp, PIFU_PREC_FP32, ps, g.hitlist, (uint32_t)(W * H), rr,
+                      g.ew, nullptr, nullptr, rgb);
+    }
+  }
+  if (!r) {
+    Book b(s);
+    b.add(BK_SET, status_dev, g.aw + AW_STATUS);
+  }
+  if (!r) r = check_launch();
+  delete gp;
+  return r;
 }
 
 }  // extern "C"

@@ -87,12 +87,36 @@ inline int h16_fmt(int precision) {
   return precision == PIFU_PREC_FP32 ? FMT_F32 : precision == PIFU_PREC_FP16 ? FMT_F16 : FMT_BF16;
 }
 
+// Blocks of a list kernel whose length lives on the device: the grid strides over it.
+constexpr unsigned kStrideBlocks = 1024;
+
 constexpr int COMPACT_BLOCK = 256;
 constexpr int COMPACT_PER_THREAD = 16;
 constexpr int COMPACT_TILE = COMPACT_BLOCK * COMPACT_PER_THREAD;
 
 // ------------------------------------------------------------------ level kernels
 void launch_fill_u8(uint8_t* p, uint8_t v, size_t n, hipStream_t s);
+// Counter updates of the device-driven calls, applied in order by one thread:
+//   ADD: *dst += *src;  ADD_NZ: *dst += (*src != 0);  SET: *dst = *src;  SET_IMM: *dst = imm;
+//   FLAG_GT: *dst |= bit if *src > imm;  SEL: *dst = *aux ? *src : 0;
+//   ADD_SEL: *dst += *aux ? *src : *src2  (a null src / src2 reads 0, a null aux is true)
+enum { BK_ADD, BK_ADD_NZ, BK_SET, BK_SET_IMM, BK_FLAG_GT, BK_SEL, BK_ADD_SEL };
+struct BookOp {
+  uint32_t* dst;
+  const uint32_t* src;
+  const uint32_t* src2;
+  const uint32_t* aux;
+  uint32_t imm, bit;
+  int kind;
+};
+constexpr int kMaxBookOps = 12;
+struct BookOps {
+  BookOp op[kMaxBookOps];
+  int n = 0;
+};
+void launch_book(const BookOps& b, hipStream_t s);
+// p[0 .. n) = v by a kernel (graph-capturable, unlike hipMemsetAsync)
+void launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s, uint32_t n = 1);
 // host[0 .. n) = c[0 .. n) (host: device view of mapped fine-grained host memory), then
 // *seq_word = seq once those stores are visible to the host
 void launch_publish(const uint32_t* c, int n, uint32_t* host, uint32_t* seq_word, uint32_t seq,
@@ -129,22 +153,25 @@ void launch_apply_grid(const uint32_t* list, uint32_t n, const float* logit, con
                        uint8_t* st, float* occ, uint32_t* conflicts, uint8_t* eval_level,
                        int level_id, Lat lvl, int stride, Lat fin, int check_conflict,
                        hipStream_t s, uint32_t frame_nodes = 0, const FrameOcc* fo = nullptr,
-                       float* eval_logit = nullptr);
+                       float* eval_logit = nullptr, const uint32_t* n_dev = nullptr);
 // eval_level[list[m]] = level_id and eval_logit[list[m]] = logit[m] for m < n (list holds
 // indices of the lattice the two maps cover)
 void launch_trace_scatter(const uint32_t* list, uint32_t n, const float* logit, int level_id,
-                          uint8_t* eval_level, float* eval_logit, hipStream_t s);
+                          uint8_t* eval_level, float* eval_logit, hipStream_t s,
+                          const uint32_t* n_dev = nullptr);
 void launch_fill_i32(int32_t* p, int32_t v, size_t n, hipStream_t s);
 // frame_nodes > 0: list entries index a multi-frame state array of frames of that size.
 void launch_expand(const uint32_t* list, uint32_t n, uint8_t* st, Lat f, hipStream_t s,
-                   uint32_t frame_nodes = 0);
+                   uint32_t frame_nodes = 0, const uint32_t* n_dev = nullptr);
 void launch_cells(uint8_t* st, Lat f, uint8_t* labels, hipStream_t s);
 void launch_count_bits(const uint8_t* st, size_t n, uint8_t bit, uint32_t* out, hipStream_t s);
 
 // ------------------------------------------------------------------ evaluation kernels
+// List kernels below take an optional device-side count n_dev: the list then holds
+// min(n, *n_dev) entries (n is its capacity) and the grid strides over them.
 void launch_eval_analytic(const PointSrc& src, const uint32_t* list, uint32_t n, int kind,
                           const Ellipsoids& ell, const float plane[4], float* logit,
-                          uint8_t* lab, hipStream_t s);
+                          uint8_t* lab, hipStream_t s, const uint32_t* n_dev = nullptr);
 // Bilinear gather of C channels (Eq. 1's sampler) for points m in [0, n); writes
 // feat (n x C, in format feat_fmt: FMT_F32 / FMT_BF16 / FMT_F16) and ext (n x 4: z',
 // occ, clipped, 0).  n_dev (nullable): device-side point count <= n; the grid covers
@@ -154,32 +181,34 @@ void launch_gather(const PointSrc& src, const uint32_t* list, uint32_t n, const 
                    const uint32_t* n_dev = nullptr, uint32_t* ovf = nullptr);
 void launch_head(const float* h, int K, const float* W, const float* b, int n_out, int out_act,
                  uint32_t n, const float* ext, float* logit, uint8_t* lab, float* rgb_out,
-                 const uint32_t* rgb_index, hipStream_t s);
+                 const uint32_t* rgb_index, hipStream_t s, const uint32_t* n_dev = nullptr);
 // Positions m < n with |logit[m]| < g (any order) into glist (map[m] with a map).
 // *gcount is a running counter that holds `start` before the launch: the positions go to
 // glist[0 ..) and the count is *gcount - start afterwards (no reset between launches).
 void launch_guard_select(const float* logit, uint32_t n, float g, uint32_t* glist,
                          uint32_t* gcount, hipStream_t s, const uint32_t* map = nullptr,
-                         uint32_t start = 0);
+                         uint32_t start = 0, const uint32_t* n_dev = nullptr);
 
 // out[i] = src[pos[i]]
 void launch_gather_u32(const uint32_t* src, const uint32_t* pos, uint32_t n, uint32_t* out,
-                       hipStream_t s);
+                       hipStream_t s, const uint32_t* n_dev = nullptr);
 void launch_convert(const float* in, uint32_t n, int fmt, void* out, hipStream_t s);
 // logit[pos[i]] = tl[i], lab[pos[i]] = tb[i]
 void launch_scatter_results(const uint32_t* pos, uint32_t n, const float* tl, const uint8_t* tb,
-                            float* logit, uint8_t* lab, hipStream_t s);
+                            float* logit, uint8_t* lab, hipStream_t s,
+                            const uint32_t* n_dev = nullptr);
 size_t guard64_ws_bytes(const MLPDesc& d, uint32_t chunk);
 // pack: write the float64 weight copies into ws (once per call; later calls reuse them).
 void run_guard64(const PointSrc& src, const uint32_t* list, const uint32_t* glist, uint32_t gn,
                  const MLPDesc& d, const float* F, int H, int W, int C, float* logit, uint8_t* lab,
-                 void* ws, uint32_t chunk, bool pack, hipStream_t s);
+                 void* ws, uint32_t chunk, bool pack, hipStream_t s,
+                 const uint32_t* gn_dev = nullptr);
 
 // ------------------------------------------------------------------ render kernels
 void launch_ray_count(const uint8_t* stc, Lat c, int W, int H, int D, uint32_t* cnt,
                       uint32_t* kstar, uint32_t* shadow_total, hipStream_t s);
 void launch_scan_u32(const uint32_t* in, uint32_t n, uint32_t* out_excl, uint32_t* scratch,
-                     uint32_t* total, hipStream_t s);
+                     uint32_t* total, hipStream_t s, const uint32_t* n_dev = nullptr);
 size_t scan_scratch_words(size_t n);
 void launch_ray_list(const uint8_t* stc, Lat c, int W, int H, int D, const uint32_t* kstar,
                      const uint32_t* off, uint32_t* list, hipStream_t s);
@@ -234,15 +263,16 @@ struct GemmArgs {
 // ------------------------------------------------------------------ per-column hoisting
 // flags[i] = point i starts a new (x, y) column (list sorted or not: runs of one column)
 void launch_col_flags(const uint32_t* list, uint32_t n, uint32_t nz, uint32_t* flags,
-                      hipStream_t s);
+                      hipStream_t s, const uint32_t* n_dev = nullptr);
 // cid[i] = index of point i's column run; col_node[cid] = a node of that column
 void launch_col_ids(const uint32_t* list, const uint32_t* flags, const uint32_t* excl, uint32_t n,
-                    uint32_t* cid, uint32_t* col_node, hipStream_t s);
+                    uint32_t* cid, uint32_t* col_node, hipStream_t s,
+                    const uint32_t* n_dev = nullptr);
 // layer 0 with hoisting: h[i][o] = act(P[cid[i]][o] + wz[o] * z_i), z from the node index;
 // h in format h_fmt (ovf as for launch_gather)
 void launch_hoist_layer0(const float* P, int ldp, const uint32_t* cid, const uint32_t* list,
                          uint32_t n, int nz, const float* wz, int N, int act, void* h, int h_fmt,
-                         hipStream_t s, uint32_t* ovf = nullptr);
+                         hipStream_t s, uint32_t* ovf = nullptr, const uint32_t* n_dev = nullptr);
 
 // float32 -> OCP FP8 E4M3FN code (bias 7, 3 mantissa bits, no infinities), round to
 // nearest even, saturating at +-448; NaN -> 0x7f.
@@ -268,6 +298,9 @@ __host__ __device__ inline uint8_t f32_to_e4m3(float x) {
 // with the kernel's own start and end
 int launch_gemm(const GemmArgs& a, int precision, int tile_m, hipStream_t s,
                 hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// The same GEMM over a device-side row count (a.M_dev; a.M = capacity), as a persistent
+// launch whose size does not depend on the count.  FP32, BF16, FP16 and split-FP16.
+int launch_gemm_persist(const GemmArgs& a, int precision, hipStream_t s);
 // FP8 operand copy: amax_bits <- max |W| (float bits), dst = e4m3(W * 448 / amax).
 void launch_pack_fp8(const float* W, int N, int ldw, int K, uint32_t* amax_bits, uint8_t* dst,
                      hipStream_t s);

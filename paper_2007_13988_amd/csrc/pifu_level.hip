@@ -14,6 +14,41 @@ __global__ void k_fill_u8(uint8_t* __restrict__ p, uint8_t v, size_t n) {
   if (i < n) p[i] = v;
 }
 
+__global__ void k_set_words(uint32_t* __restrict__ p, uint32_t v, uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Fills n words with a kernel (not hipMemsetAsync: the calls that may be captured into a
+// graph clear their counters this way).
+void launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s, uint32_t n) {
+  if (n) hipLaunchKernelGGL(k_set_words, dim3((n + 255) / 256), dim3(256), 0, s, p, v, n);
+}
+
+// Bookkeeping of the device-driven calls: a few counter updates in order, one thread.
+__global__ void k_book(BookOps b) {
+  for (int i = 0; i < b.n; ++i) {
+    const BookOp& o = b.op[i];
+    const uint32_t a = o.src ? *o.src : 0u;
+    const uint32_t c = o.src2 ? *o.src2 : 0u;
+    const bool flag = o.aux ? *o.aux != 0u : true;
+    switch (o.kind) {
+      case BK_ADD: *o.dst += a; break;
+      case BK_ADD_NZ: *o.dst += a != 0u; break;
+      case BK_SET: *o.dst = a; break;
+      case BK_SET_IMM: *o.dst = o.imm; break;
+      case BK_FLAG_GT: if (a > o.imm) *o.dst |= o.bit; break;
+      case BK_SEL: *o.dst = flag ? a : 0u; break;
+      case BK_ADD_SEL: *o.dst += flag ? a : c; break;
+      default: break;
+    }
+  }
+}
+
+void launch_book(const BookOps& b, hipStream_t s) {
+  if (b.n) hipLaunchKernelGGL(k_book, dim3(1), dim3(1), 0, s, b);
+}
+
 void launch_fill_u8(uint8_t* p, uint8_t v, size_t n, hipStream_t s) {
   if (n) hipLaunchKernelGGL(k_fill_u8, dim3(grid1d(n, 256)), dim3(256), 0, s, p, v, n);
 }
@@ -313,9 +348,10 @@ k_compact_count(const uint8_t* __restrict__ st, size_t n, uint8_t mask, uint8_t 
 // Exclusive scan of n words by one workgroup of 1024 threads; writes the total.
 __global__ void __launch_bounds__(1024)
 k_scan_small(const uint32_t* __restrict__ in, uint32_t n, uint32_t* __restrict__ out,
-             uint32_t* __restrict__ total) {
+             uint32_t* __restrict__ total, const uint32_t* __restrict__ n_dev = nullptr) {
   __shared__ uint32_t wsum[16];
-  const uint32_t per = (n + 1023) / 1024;
+  const uint32_t per = (n + 1023) / 1024;   // the capacity sets the split, the count the end
+  if (n_dev) n = min(n, *n_dev);
   const uint32_t beg = threadIdx.x * per;
   uint32_t loc = 0;
   for (uint32_t i = 0; i < per; ++i)
@@ -388,7 +424,7 @@ void launch_compact(const uint8_t* st, size_t n, uint8_t mask, uint8_t val, uint
                     uint32_t index_base) {
   uint32_t nb = (uint32_t)((n + COMPACT_TILE - 1) / COMPACT_TILE);
   if (nb == 0) {
-    (void)hipMemsetAsync(total, 0, 4, s);
+    launch_set_u32(total, 0, s);
     return;
   }
   uint32_t* boff = bcount + nb;
@@ -396,7 +432,7 @@ void launch_compact(const uint8_t* st, size_t n, uint8_t mask, uint8_t val, uint
   // one workgroup scans up to a few thousand tile counts quickly; longer inputs (many
   // frames of a batch) take the multi-workgroup scan
   if (nb <= 8192)
-    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, bcount, nb, boff, total);
+    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, bcount, nb, boff, total, nullptr);
   else
     launch_scan_u32(bcount, nb, boff, bcount + 2 * (size_t)nb, total, s);
   hipLaunchKernelGGL(k_compact_write, dim3(nb), dim3(COMPACT_BLOCK), 0, s, st, n, mask, val, boff,
@@ -405,8 +441,10 @@ void launch_compact(const uint8_t* st, size_t n, uint8_t mask, uint8_t val, uint
 
 // ------------------------------------------------------------------ generic scan (render)
 __global__ void __launch_bounds__(1024)
-k_scan_tiles(const uint32_t* __restrict__ in, uint32_t n, uint32_t* __restrict__ tsum) {
+k_scan_tiles(const uint32_t* __restrict__ in, uint32_t n, uint32_t* __restrict__ tsum,
+             const uint32_t* __restrict__ n_dev) {
   __shared__ uint32_t wsum[16];
+  if (n_dev) n = min(n, *n_dev);
   uint32_t i = blockIdx.x * 1024 + threadIdx.x;
   uint32_t v = i < n ? in[i] : 0;
   uint32_t inc = wave_incl_scan(v);
@@ -421,8 +459,9 @@ k_scan_tiles(const uint32_t* __restrict__ in, uint32_t n, uint32_t* __restrict__
 
 __global__ void __launch_bounds__(1024)
 k_scan_apply(const uint32_t* __restrict__ in, uint32_t n, const uint32_t* __restrict__ toff,
-             uint32_t* __restrict__ out) {
+             uint32_t* __restrict__ out, const uint32_t* __restrict__ n_dev) {
   __shared__ uint32_t wsum[16];
+  if (n_dev) n = min(n, *n_dev);
   uint32_t i = blockIdx.x * 1024 + threadIdx.x;
   uint32_t v = i < n ? in[i] : 0;
   uint32_t inc = wave_incl_scan(v);
@@ -436,36 +475,42 @@ k_scan_apply(const uint32_t* __restrict__ in, uint32_t n, const uint32_t* __rest
 size_t scan_scratch_words(size_t n) { return (n + 1023) / 1024 * 2 + 64; }
 
 void launch_scan_u32(const uint32_t* in, uint32_t n, uint32_t* out_excl, uint32_t* scratch,
-                     uint32_t* total, hipStream_t s) {
+                     uint32_t* total, hipStream_t s, const uint32_t* n_dev) {
   uint32_t nt = (n + 1023) / 1024;
   if (nt == 0) {
-    (void)hipMemsetAsync(total, 0, 4, s);
+    launch_set_u32(total, 0, s);
     return;
   }
   if (n <= 8192) {   // up to 8 words per thread: one workgroup, one launch
-    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, in, n, out_excl, total);
+    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, in, n, out_excl, total, n_dev);
     return;
   }
-  hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(1024), 0, s, in, n, scratch);
-  hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, scratch, nt, scratch + nt, total);
-  hipLaunchKernelGGL(k_scan_apply, dim3(nt), dim3(1024), 0, s, in, n, scratch + nt, out_excl);
+  hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(1024), 0, s, in, n, scratch, n_dev);
+  hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, scratch, nt, scratch + nt, total,
+                     nullptr);
+  hipLaunchKernelGGL(k_scan_apply, dim3(nt), dim3(1024), 0, s, in, n, scratch + nt, out_excl,
+                     n_dev);
 }
 
 // ------------------------------------------------------------------ evaluation results
 // Writes the network's label and value into the level state; flags conflicts
 // ([logit > 0] != [interp > 1/2]) among the nodes evaluated at this level.
 __global__ void k_apply_grid(const uint32_t* __restrict__ list, uint32_t n,
+                             const uint32_t* __restrict__ n_dev,
                              const float* __restrict__ logit, const uint8_t* __restrict__ lab,
                              uint8_t* __restrict__ st, float* __restrict__ occ,
                              uint32_t* __restrict__ conflicts, uint8_t* __restrict__ eval_level,
                              float* __restrict__ eval_logit, int level_id, Lat lvl, int stride,
                              Lat fin, int check_conflict, uint32_t frame_nodes, FrameOcc fo) {
-  uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t ne = n_dev ? min(n, *n_dev) : n;
+  // the block's base index is uniform, so every lane of a wave runs the same iterations
+  for (uint32_t b0 = blockIdx.x * blockDim.x; b0 < ne; b0 += gridDim.x * blockDim.x) {
+  const uint32_t m = b0 + threadIdx.x;
   bool conf = false;
   if (frame_nodes) {
     // multi-frame: one conflict counter per frame (no evaluation-level map)
     uint32_t frame = 0;
-    if (m < n) {
+    if (m < ne) {
       const uint32_t node = list[m];
       const uint8_t s = st[node];
       const uint8_t l = lab[m] ? ST_LABEL : 0;
@@ -480,11 +525,11 @@ __global__ void k_apply_grid(const uint32_t* __restrict__ list, uint32_t n,
       }
       st[node] = ns;
     }
-    if (!conflicts) return;
+    if (!conflicts) continue;
     // the list is sorted, so a wave's conflicts nearly always share one frame: one atomic
     // per wave then, one per conflict where a wave straddles frames
     const unsigned long long bal = __ballot(conf);
-    if (!bal) return;
+    if (!bal) continue;
     const int first = __ffsll((long long)bal) - 1;
     const uint32_t f0 = __shfl(frame, first, 64);
     if (__all(!conf || frame == f0)) {
@@ -492,9 +537,9 @@ __global__ void k_apply_grid(const uint32_t* __restrict__ list, uint32_t n,
     } else if (conf) {
       atomicAdd(conflicts + frame, 1u);
     }
-    return;
+    continue;
   }
-  if (m < n) {
+  if (m < ne) {
     const uint32_t node = list[m];
     const uint8_t s = st[node];
     const uint8_t l = lab[m] ? ST_LABEL : 0;
@@ -522,29 +567,35 @@ __global__ void k_apply_grid(const uint32_t* __restrict__ list, uint32_t n,
     unsigned long long bal = __ballot(conf);
     if ((threadIdx.x & 63) == 0 && bal) atomicAdd(conflicts, (uint32_t)__popcll(bal));
   }
+  }
 }
 
 void launch_apply_grid(const uint32_t* list, uint32_t n, const float* logit, const uint8_t* lab,
                        uint8_t* st, float* occ, uint32_t* conflicts, uint8_t* eval_level,
                        int level_id, Lat lvl, int stride, Lat fin, int check_conflict,
-                       hipStream_t s, uint32_t frame_nodes, const FrameOcc* fo, float* eval_logit) {
+                       hipStream_t s, uint32_t frame_nodes, const FrameOcc* fo, float* eval_logit,
+                       const uint32_t* n_dev) {
   if (!n) return;
   FrameOcc t{};
   if (fo) t = *fo;
-  hipLaunchKernelGGL(k_apply_grid, dim3(grid1d(n, 256)), dim3(256), 0, s, list, n, logit, lab, st,
-                     occ, conflicts, eval_level, eval_logit, level_id, lvl, stride, fin,
-                     check_conflict, frame_nodes, t);
+  unsigned g = grid1d(n, 256);
+  if (n_dev && g > kStrideBlocks) g = kStrideBlocks;
+  hipLaunchKernelGGL(k_apply_grid, dim3(g), dim3(256), 0, s, list, n, n_dev, logit, lab, st, occ,
+                     conflicts, eval_level, eval_logit, level_id, lvl, stride, fin, check_conflict,
+                     frame_nodes, t);
 }
 
 // Conflict expansion: every not-yet-evaluated node of the 26-neighbourhood of a
 // conflict node of the last wave is selected.  Concurrent read-modify-writes of one
 // byte only ever add ST_PEND, so they agree.
-__global__ void k_expand(const uint32_t* __restrict__ list, uint32_t n, uint8_t* __restrict__ st,
-                         Lat f, uint32_t frame_nodes) {
-  uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= n) return;
+__global__ void k_expand(const uint32_t* __restrict__ list, uint32_t n,
+                         const uint32_t* __restrict__ n_dev, uint8_t* __restrict__ st0, Lat f,
+                         uint32_t frame_nodes) {
+  const uint32_t ne = n_dev ? min(n, *n_dev) : n;
+  for (uint32_t m = blockIdx.x * blockDim.x + threadIdx.x; m < ne; m += gridDim.x * blockDim.x) {
+  uint8_t* st = st0;
   uint32_t node = list[m];
-  if (!(st[node] & ST_CONF)) return;
+  if (!(st[node] & ST_CONF)) continue;
   if (frame_nodes) {   // neighbours stay inside the node's frame
     const uint32_t local = node % frame_nodes;
     st += (size_t)(node - local);
@@ -570,12 +621,15 @@ __global__ void k_expand(const uint32_t* __restrict__ list, uint32_t n, uint8_t*
       }
     }
   }
+  }
 }
 
 void launch_expand(const uint32_t* list, uint32_t n, uint8_t* st, Lat f, hipStream_t s,
-                   uint32_t frame_nodes) {
+                   uint32_t frame_nodes, const uint32_t* n_dev) {
   if (!n) return;
-  hipLaunchKernelGGL(k_expand, dim3(grid1d(n, 256)), dim3(256), 0, s, list, n, st, f, frame_nodes);
+  unsigned g = grid1d(n, 256);
+  if (n_dev && g > kStrideBlocks) g = kStrideBlocks;
+  hipLaunchKernelGGL(k_expand, dim3(g), dim3(256), 0, s, list, n, n_dev, st, f, frame_nodes);
 }
 
 // bounds[f] = first position of the sorted list whose entry is >= f * frame_nodes.

@@ -111,7 +111,9 @@ EXPORTS = ["pifu_create", "pifu_destroy", "pifu_status_string",
            "pifu_profile_enable", "pifu_profile_read", "pifu_mlp_train_workspace_size",
            "pifu_mlp_grad", "pifu_rmsprop_step", "pifu_occupancy_grid_batched_workspace_size",
            "pifu_occupancy_grid_batched", "pifu_autotune_mlp", "pifu_autotune_clear",
-           "pifu_convert_f32", "pifu_grid_and_render", "pifu_render_view_traced", "pifu_fp8_calibrate"]
+           "pifu_convert_f32", "pifu_grid_and_render", "pifu_render_view_traced", "pifu_fp8_calibrate",
+           "pifu_occupancy_grid_async_workspace_size", "pifu_occupancy_grid_async",
+           "pifu_render_view_async_workspace_size", "pifu_render_view_async"]
 
 _lib = None
 
@@ -149,6 +151,18 @@ def load_library():
                                             C.POINTER(PifuRenderTrace)]
     lib.pifu_fp8_calibrate.argtypes = [P, C.POINTER(PifuField), P, u32, C.POINTER(C.c_float), P,
                                        sz, P]
+    lib.pifu_occupancy_grid_async_workspace_size.argtypes = [C.POINTER(PifuField),
+                                                             C.POINTER(PifuGridOpts), u32,
+                                                             C.POINTER(sz)]
+    lib.pifu_occupancy_grid_async.argtypes = [P, C.POINTER(PifuField), C.POINTER(PifuGridOpts), u32,
+                                              P, P, P, P, u32, P, P, P, P, sz, P]
+    lib.pifu_render_view_async_workspace_size.argtypes = [C.POINTER(PifuField),
+                                                          C.POINTER(PifuField),
+                                                          C.POINTER(PifuRenderOpts), u32,
+                                                          C.POINTER(sz)]
+    lib.pifu_render_view_async.argtypes = [P, C.POINTER(PifuField), C.POINTER(PifuField),
+                                           C.POINTER(C.c_float), C.POINTER(PifuRenderOpts), u32,
+                                           C.POINTER(C.c_float), P, P, P, P, P, P, sz, P]
     lib.pifu_eval_points_workspace_size.argtypes = [C.POINTER(PifuField), i32, u32, C.POINTER(sz)]
     lib.pifu_eval_points.argtypes = [P, C.POINTER(PifuField), i32, C.c_float, C.c_float, P, u32, P,
                                      P, P, sz, P]
@@ -520,6 +534,93 @@ def fp8_calibrate(field: DeviceField, pts, stream=None) -> List[float]:
     _check(lib.pifu_fp8_calibrate(context(), C.byref(field.struct), _ptr(p4), n, out, _ptr(ws),
                                   sz.value, _stream(stream)), "pifu_fp8_calibrate")
     return [float(out[l]) for l in range(nh)]
+
+
+STATS_WORDS = C.sizeof(PifuLevelStats) // 4
+STATUS = {1: "list over max_points", 2: "waves left", 4: "guard over", 8: "cells over"}
+
+
+def stats_from_device(t: torch.Tensor) -> List[Dict[str, int]]:
+    """Device stats records (int32 words) -> list of dicts."""
+    a = t.view(-1, STATS_WORDS).cpu()
+    out = []
+    for row in a:
+        rec = PifuLevelStats.from_buffer_copy(bytes(row.numpy().tobytes()))
+        out.append(rec.as_dict())
+    return out
+
+
+class AsyncGrid:
+    """Outputs, device-side counts and workspace of pifu_occupancy_grid_async.  run()
+    only enqueues (graph-capturable); read n_cells / stats / status after the stream."""
+
+    def __init__(self, field: DeviceField, opts: PifuGridOpts, max_points: int = 0,
+                 eval_level: bool = False, cells_cap: Optional[int] = None, device="cuda"):
+        lib = load_library()
+        n = (1 << opts.log2_final) + 1
+        self.field, self.opts, self.max_points = field, opts, max_points
+        self.occ = torch.empty((n, n, n), dtype=torch.float32, device=device)
+        self.labels = torch.empty((n, n, n), dtype=torch.uint8, device=device)
+        self.eval_level = torch.empty((n, n, n), dtype=torch.uint8, device=device) if eval_level else None
+        cap = cells_cap if cells_cap is not None else min((n - 1) ** 3, 1 << 26)
+        self.cells = torch.empty(max(cap, 1), dtype=torch.int32, device=device)
+        self.cells_cap = cap
+        n_levels = 1 if opts.dense else opts.log2_final - opts.log2_coarse + 1
+        self.words = torch.zeros(2 + n_levels * STATS_WORDS, dtype=torch.int32, device=device)
+        sz = C.c_size_t()
+        _check(lib.pifu_occupancy_grid_async_workspace_size(C.byref(field.struct), C.byref(opts),
+                                                            max_points, C.byref(sz)),
+               "pifu_occupancy_grid_async_workspace_size")
+        self.ws = torch.empty(sz.value, dtype=torch.uint8, device=device)
+
+    def run(self, stream=None):
+        p = self.words.data_ptr()
+        st = load_library().pifu_occupancy_grid_async(
+            context(), C.byref(self.field.struct), C.byref(self.opts), self.max_points,
+            _ptr(self.occ), _ptr(self.labels), _ptr(self.eval_level), _ptr(self.cells),
+            self.cells_cap, p, p + 8, p + 4, _ptr(self.ws), self.ws.numel(), _stream(stream))
+        _check(st, "pifu_occupancy_grid_async")
+
+    def result(self):
+        nc = int(self.words[0].item())
+        return dict(occ=self.occ, labels=self.labels, eval_level=self.eval_level,
+                    cells=self.cells[:min(nc, self.cells_cap)], n_cells=nc,
+                    stats=stats_from_device(self.words[2:]), status=int(self.words[1].item()))
+
+
+class AsyncRender:
+    """Outputs, device-side counts and workspace of pifu_render_view_async."""
+
+    def __init__(self, occ_field: DeviceField, color_field: DeviceField, view, bg,
+                 opts: PifuRenderOpts, max_points: int = 0, device="cuda"):
+        lib = load_library()
+        W = 1 << opts.log2_w
+        self.occ_field, self.color_field, self.opts, self.max_points = occ_field, color_field, opts, max_points
+        self.view = (C.c_float * 12)(*[float(x) for x in np.asarray(view, np.float32).reshape(-1)])
+        self.bg = (C.c_float * 3)(*[float(x) for x in bg])
+        self.rgb = torch.empty((W, W, 3), dtype=torch.float32, device=device)
+        self.depth = torch.empty((W, W), dtype=torch.float32, device=device)
+        self.hit = torch.empty((W, W), dtype=torch.uint8, device=device)
+        n_levels = opts.log2_w - opts.log2_coarse_w + 1
+        self.words = torch.zeros(2 + n_levels * STATS_WORDS, dtype=torch.int32, device=device)
+        sz = C.c_size_t()
+        _check(lib.pifu_render_view_async_workspace_size(C.byref(occ_field.struct),
+                                                         C.byref(color_field.struct), C.byref(opts),
+                                                         max_points, C.byref(sz)),
+               "pifu_render_view_async_workspace_size")
+        self.ws = torch.empty(sz.value, dtype=torch.uint8, device=device)
+
+    def run(self, stream=None):
+        p = self.words.data_ptr()
+        st = load_library().pifu_render_view_async(
+            context(), C.byref(self.occ_field.struct), C.byref(self.color_field.struct), self.view,
+            C.byref(self.opts), self.max_points, self.bg, _ptr(self.rgb), _ptr(self.depth),
+            _ptr(self.hit), p + 8, p + 4, _ptr(self.ws), self.ws.numel(), _stream(stream))
+        _check(st, "pifu_render_view_async")
+
+    def result(self):
+        return dict(rgb=self.rgb, depth=self.depth, hit=self.hit,
+                    stats=stats_from_device(self.words[2:]), status=int(self.words[1].item()))
 
 
 class BatchedGrid:

@@ -8,9 +8,7 @@ The FP64 oracle cannot evaluate all ~1.2 M points of a full frame in test time, 
   * level logic: the oracle's localization is replayed with the GPU's point labels as
     its "network"; it must request exactly the nodes the GPU evaluated at each level and
     reproduce the labels and surface cells bit for bit;
-  * render: sampled hit pixels -- the colour network at the GPU's hit point matches the
-    oracle's colour network, and the surface point lies between two nodes of the ray
-    whose oracle labels differ or at the near plane.
+The render at the same size is replayed exactly in test_gpu_render_exact.py.
 """
 import numpy as np
 import pytest
@@ -74,45 +72,3 @@ def test_level_logic_replay_at_full_size(frame):
     for rec, g in zip(res.levels, out["stats"]):
         for k in ("nodes", "b0", "dilated", "evaluated", "waves", "conflicts"):
             assert g[k] == rec.stats[k], (rec.level, k)
-
-
-def test_render_full_size_sampled_hits(pifu, frame):
-    cfeat, cspec = synth.color_features(), synth.color_mlp()
-    cg = pifu.DeviceField.mlp_field(cfeat, cspec)
-    view = synth.yaw_view(90.0)
-    r = pifu.render_view(frame["fg"], cg, view, 9, 8, 6)
-    hit = r["hit"].cpu().numpy()
-    depth = r["depth"].cpu().numpy()
-    rgb = r["rgb"].cpu().numpy()
-    assert hit.sum() > 0
-    assert np.all(np.isnan(depth[hit == 0])) and np.all(rgb[hit == 0] == 0.0)
-    vs, us = np.nonzero(hit)
-    rng = np.random.default_rng(6)
-    sel = rng.choice(len(us), min(500, len(us)), replace=False)
-    u, v = us[sel], vs[sel]
-    z = depth[v, u].astype(np.float64)
-    assert np.all((z >= -1.0) & (z <= 1.0))
-    x = -1.0 + 2.0 * u / 512
-    y = -1.0 + 2.0 * v / 512
-    # node k1 (first node labelled inside, from the observer) from the hit depth:
-    # z = z_{k1+1} - t (z_{k1+1} - z_{k1}) with t in [0, 1)
-    kz = (z + 1.0) * 128.0
-    near = kz >= 256.0 - 1e-4
-    integral = np.abs(kz - np.rint(kz)) < 1e-4
-    k1 = np.where(near, 256, np.where(integral, np.rint(kz) - 1, np.floor(kz))).astype(np.int64)
-    fo = O.Field("mlp", feat=frame["feat"], mlp=frame["spec"])
-    node = lambda k: np.stack([x, y, -1.0 + 2.0 * k / 256], axis=1)
-    lg1 = O.view_logit(fo, view, node(k1))
-    lg0 = O.view_logit(fo, view, node(np.minimum(k1 + 1, 256)))
-    bracket = (lg1 > 0) & (near | (lg0 <= 0))
-    assert bracket.mean() >= 0.98, bracket.mean()
-    # colour network at the GPU's hit point; the occupancy input is the node's p, or 1
-    # where the hierarchy culled node k1
-    Pp, _ = O.apply_view(view, np.stack([x, y, z], axis=1))
-    f = O.bilinear_sample(cfeat, Pp[:, 0], Pp[:, 1])
-    errs = []
-    for occ in (O.sigmoid(lg1), np.ones_like(lg1)):
-        ref = np.tanh(O.mlp_preact(cspec, f, np.stack([Pp[:, 2], occ], axis=1)))
-        errs.append(np.max(np.abs(rgb[v, u] - ref), axis=1))
-    err = np.minimum(errs[0], errs[1])
-    assert np.mean(err <= 1e-4) >= 0.99, np.mean(err <= 1e-4)
