@@ -323,6 +323,103 @@ def localize(evaluate: Callable[[np.ndarray], np.ndarray], log2_cells: Tuple[int
     return LocalizeResult(dims, val, label, logit, evaluated, res_levels)
 
 
+# ------------------------------------------------------------------ octree baselines
+
+def _cells_of_nodes(flag: np.ndarray, fdims) -> np.ndarray:
+    """Fine-lattice nodes that lie in (inside or on the boundary of) a flagged coarse cell.
+
+    Coarse cell (a, b, c) spans fine nodes 2a..2a+2 along each axis; ``flag`` has one
+    entry per coarse cell."""
+    out = np.zeros(fdims, bool)
+    for a, b, c in np.argwhere(flag):
+        out[2 * a:2 * a + 3, 2 * b:2 * b + 3, 2 * c:2 * c + 3] = True
+    return out
+
+
+def _corner_stack(v: np.ndarray) -> List[np.ndarray]:
+    """The 8 corner values of every cell of a node array (cells (n-1)^3)."""
+    return [v[di:v.shape[0] - 1 + di, dj:v.shape[1] - 1 + dj, dk:v.shape[2] - 1 + dk]
+            for di in (0, 1) for dj in (0, 1) for dk in (0, 1)]
+
+
+def octree_localize(evaluate: Callable[[np.ndarray], np.ndarray], log2_cells: Tuple[int, int, int],
+                    n_refine: int, mode: str, thr: float = 0.0) -> LocalizeResult:
+    """The two octree subdivisions the paper compares its localization with (Sec. 3.2,
+    "Octree-based Robust Surface Localization", and the Fig. 3 comparison).
+
+    From the densely evaluated coarsest level, each level subdivides the coarse cells
+    selected by a rule and evaluates every node of those cells that was not evaluated
+    before; there is no dilation and no conflict search.
+      * mode "binarized": a cell is subdivided when the binarized occupancy [p > 0.5] of
+        its 8 corners is not all equal (the interface between inside and outside nodes).
+        Nodes of other cells take the trilinear interpolation of the binarized corner
+        labels (0 or 1 there).
+      * mode "threshold": a cell is subdivided when the maximum absolute deviation of
+        its 8 corner occupancy values from their mean exceeds thr.  Nodes of other cells
+        take the trilinear interpolation of the corner occupancy values; their label is
+        [value > 0.5].
+    Values are float64 occupancies p = sigmoid(logit).
+    """
+    assert mode in ("binarized", "threshold")
+    T = n_refine
+    dims_at = lambda t: tuple((1 << (L - (T - t))) + 1 for L in log2_cells)
+    level_id = lambda t: log2_cells[0] - (T - t)
+    dims = dims_at(0)
+    idx, lg = _eval_mask(evaluate, dims, np.ones(dims, bool))
+    logit = lg.reshape(dims)
+    label = (logit > 0).astype(np.uint8)
+    val = sigmoid(logit)
+    evaluated = np.ones(dims, bool)
+    levels = [LevelRecord(level_id(0), dims, idx, dict(nodes=int(np.prod(dims)),
+                                                       evaluated=int(idx.size), subdivided=0))]
+    for t in range(1, T + 1):
+        fdims = dims_at(t)
+        if mode == "binarized":
+            corners = _corner_stack(label.astype(bool))
+            anyv = np.zeros_like(corners[0])
+            allv = np.ones_like(corners[0])
+            for c in corners:
+                anyv |= c
+                allv &= c
+            flag = anyv & ~allv
+            interp = upsample_x2(label.astype(np.float64))
+        else:
+            corners = _corner_stack(val)
+            mean = sum(corners) / 8.0
+            dev = np.zeros_like(mean)
+            for c in corners:
+                dev = np.maximum(dev, np.abs(c - mean))
+            flag = dev > thr
+            interp = upsample_x2(val)
+        f_eval = np.zeros(fdims, bool)
+        f_eval[::2, ::2, ::2] = evaluated
+        f_logit = np.full(fdims, np.nan)
+        f_logit[::2, ::2, ::2] = logit
+        f_val = interp.copy()
+        f_val[::2, ::2, ::2] = val
+        f_label = (interp > 0.5).astype(np.uint8)
+        f_label[::2, ::2, ::2] = label
+        todo = _cells_of_nodes(flag, fdims) & ~f_eval
+        idx, lg = _eval_mask(evaluate, fdims, todo)
+        f_logit.reshape(-1)[idx] = lg
+        f_label.reshape(-1)[idx] = (lg > 0).astype(np.uint8)
+        f_val.reshape(-1)[idx] = sigmoid(lg)
+        f_eval.reshape(-1)[idx] = True
+        logit, label, val, evaluated = f_logit, f_label, f_val, f_eval
+        levels.append(LevelRecord(level_id(t), fdims, idx, dict(
+            nodes=int(np.prod(fdims)), evaluated=int(idx.size), subdivided=int(flag.sum()))))
+    return LocalizeResult(dims_at(T), val, label, logit, evaluated, levels)
+
+
+def octree_grid(fld: Field, log2_final: int, log2_coarse: int, mode: str,
+                thr: float = 0.0) -> Dict[str, object]:
+    """Octree-subdivision occupancy grid of the input view (see octree_localize)."""
+    res = octree_localize(lambda P: field_logit(fld, P), (log2_final,) * 3,
+                          log2_final - log2_coarse, mode, thr)
+    return dict(occ=res.val, labels=res.label, logit=res.logit, cells=surface_cells(res.label),
+                eval_level=eval_level_map(res), levels=res.levels, result=res)
+
+
 def surface_cells(label: np.ndarray) -> np.ndarray:
     """Sorted linear indices (i*Ry + j)*Rz + k of cells whose 8 corner labels differ."""
     L = label.astype(bool)
