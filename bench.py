@@ -31,6 +31,11 @@ import os
 import sys
 import time
 
+
+def log(msg):
+    """Progress on stderr (the JSON line is the only stdout output)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -122,7 +127,9 @@ def cpu_baseline(frame, budget_s):
         idx = np.rint((P + 1.0) * 128.0).astype(np.int64)
         return np.where(lab[idx[:, 0], idx[:, 1], idx[:, 2]] == 1, 1.0, -1.0)
 
+    log(f"cpu baseline: config 1 {t_cfg1 * 1e3:.1f} ms")
     t_loc = med(lambda: O.localize(look, (8, 8, 8), 3), 1)
+    log(f"cpu baseline: grid level logic {t_loc:.2f} s")
     rl, rv = frame["render_logit"], frame["render_level"]
 
     def look_r(P):
@@ -153,6 +160,7 @@ def cpu_baseline(frame, budget_s):
         np.tanh(O.mlp_preact(col, f, np.stack([P[:, 2], np.full(n, 0.5)], 1)))
         return (time.perf_counter() - t0) / n
 
+    log(f"cpu baseline: render level logic {t_ren:.2f} s")
     per_pt, done = mlp_rate(budget_s)
     per_hit = col_rate()
     with threadpool_limits(1):
@@ -358,6 +366,7 @@ def main():
         setup = {"surrogate_loaded_from": args.load_surrogate, "surrogate_deltas": deltas}
     elif want_sur:
         from paper_2007_13988_amd.surrogate import choose_delta, distill
+        log("distilling the surrogate")
         t0 = time.perf_counter()
         # the surrogate is distilled on the performance's earlier frames (t = -1 .. -n) and
         # each form's fallback band chosen on two older held-out frames in that form; the
@@ -407,6 +416,7 @@ def main():
 
     results = {}
     for form in forms:
+        log(f"form {form}")
         fld, gout, rout = make(form)
         for _ in range(args.warmup):
             P.grid_and_render_into(fld, gout, col_field, view, bg, rout, stream, stream2)
@@ -436,6 +446,7 @@ def main():
         # the timed steps run uninstrumented: a HIP event pair around a launch costs about
         # 9 us of stream time, ~3.7 ms over the ~370 MLP launches of a frame
         elapsed = timed_steps()
+        log(f"form {form}: {elapsed / args.steps * 1e3:.3f} ms/frame")
         # per-launch durations: the same steps again with HIP events around every launch
         # of the GEMM, gather and head families, on the stream they are launched on
         prof, instr = None, None
@@ -576,8 +587,10 @@ def main():
     out["levels_occupancy"] = main_r["gst"]
     out["levels_render"] = main_r["rst"]
     if not args.no_baselines:
+        log("baselines")
         out["baselines"] = baselines(P, synth, main_r["ms_occ"], args)
     if args.batched:
+        log("batched")
         out["batched"] = batched_bench(P, synth, max(1, min(args.steps, 3)))
     if not args.no_cpu:
         # the plain FP32 frame's labels and recorded render logits for the oracle's
@@ -591,6 +604,7 @@ def main():
                  "hits": r["stats"][-1]["hits"]}
         del g, r
         torch.cuda.empty_cache()
+        log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(frame, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

@@ -66,12 +66,35 @@ def test_async_grid_with_surrogate_equals_blocking(pifu):
     fld = pifu.DeviceField.mlp_field(feat, synth.pifu_mlp(), synth.surrogate_mlp())
     kw = dict(precision="fp16", band_delta=0.0075, surrogate_max_log2=6, surrogate_delta=0.3)
     blocking = pifu.occupancy_grid(fld, 8, 5, **kw)
+    most = max(s["waves"] for s in blocking["stats"])
+    print(f"[async surrogate] blocking call's most waves on a level: {most}", flush=True)
+    # the default ladder (12 waves) either suffices or says it did not
     ag = pifu.AsyncGrid(fld, pifu.grid_opts(8, 5, **kw))
+    ag.run()
+    torch.cuda.synchronize()
+    r = ag.result()
+    assert bool(r["status"] & 2) == (most > 12), (r["status"], most)
+    if most <= 12:
+        _same_grid(r, blocking)
+    # a ladder as long as the longest level's wave loop: the same results as the blocking
+    # call (a cap that the blocking call never reaches changes nothing there)
+    cap = max(most, 1)
+    capped = pifu.occupancy_grid(fld, 8, 5, max_waves=cap, **kw)
+    _same_grid_blocking(capped, blocking)
+    ag = pifu.AsyncGrid(fld, pifu.grid_opts(8, 5, max_waves=cap, **kw))
     ag.run()
     torch.cuda.synchronize()
     r = ag.result()
     assert sum(s["surrogate_fallback"] for s in r["stats"]) > 0
     _same_grid(r, blocking)
+
+
+def _same_grid_blocking(a, b):
+    assert torch.equal(a["labels"], b["labels"]) and torch.equal(a["occ"], b["occ"])
+    assert a["n_cells"] == b["n_cells"] and torch.equal(a["cells"], b["cells"])
+    for sa, sb in zip(a["stats"], b["stats"]):
+        for k in STAT_KEYS:
+            assert sa[k] == sb[k], (sb["level"], k, sa[k], sb[k])
 
 
 def pifu_color_field():
