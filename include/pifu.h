@@ -42,6 +42,8 @@ extern "C" {
 #define PIFU_ERR_WORKSPACE_TOO_SMALL (-2)
 #define PIFU_ERR_UNSUPPORTED (-3)        /* device is not gfx950, or unsupported shape */
 #define PIFU_ERR_HIP (-4)                /* a HIP runtime call or launch failed */
+#define PIFU_ERR_SCRATCH_TOO_SMALL (-5)  /* the options need more workspace than the fixed
+                                            scratch of pifu_occupancy_grid_async_noalloc */
 
 /* ---------------------------------------------------------------- enums */
 #define PIFU_FIELD_MLP 0          /* Eq. 1: MLP over bilinearly sampled features */
@@ -410,6 +412,29 @@ int32_t pifu_render_view_async(pifu_ctx* ctx, const pifu_field* occ_field,
                                float* rgb, float* depth, uint8_t* hit, pifu_level_stats* stats_dev,
                                uint32_t* status_dev, void* workspace, size_t workspace_bytes,
                                pifu_stream stream);
+
+/*
+ * pifu_occupancy_grid_async without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  The workspace is a fixed scratch array of
+ * PIFU_NOALLOC_SCRATCH_MIB MiB in the library's device memory, one per GPU, held until
+ * the process ends; its address is looked up once per device by pifu_create.  The call
+ * allocates nothing.  Arguments, outputs, results and device-side status are those of
+ * pifu_occupancy_grid_async.  Options whose workspace
+ * (pifu_occupancy_grid_async_workspace_size) exceeds the scratch return
+ * PIFU_ERR_SCRATCH_TOO_SMALL before anything is enqueued; a smaller max_points lowers
+ * the need.  Every call on one GPU shares that GPU's array and finds the previous
+ * call's contents in it (the call clears what it needs cleared): calls that overlap on
+ * one GPU -- on two streams, two threads, or two handles -- race and must not be made.
+ */
+#define PIFU_NOALLOC_SCRATCH_MIB 128
+size_t pifu_noalloc_scratch_bytes(void);
+int32_t pifu_occupancy_grid_async_noalloc(pifu_ctx* ctx, const pifu_field* field,
+                                          const pifu_grid_opts* opts, uint32_t max_points,
+                                          float* occ, uint8_t* labels, uint8_t* eval_level,
+                                          uint32_t* cells, uint32_t cells_cap,
+                                          uint32_t* n_cells_dev, pifu_level_stats* stats_dev,
+                                          uint32_t* status_dev, pifu_stream stream);
 
 /* ---------------------------------------------------------------- point evaluation */
 

@@ -1174,6 +1174,12 @@ pifu_ctx* ctx_new(int dev) {
   return c;
 }
 
+}  // namespace
+
+int pifu::ctx_device(const pifu_ctx* c) { return c ? c->device : -1; }
+
+namespace {
+
 void ctx_free(pifu_ctx* c) {
   if (!c) return;
   if (c->host_counters) (void)hipHostFree(c->host_counters);
@@ -1206,6 +1212,7 @@ int32_t pifu_create(pifu_ctx** out) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return PIFU_ERR_HIP;
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return PIFU_ERR_UNSUPPORTED;
+  if (int r = pifu::noalloc_setup(dev)) return r;
   pifu_ctx* c = ctx_new(dev);
   if (!c) return PIFU_ERR_HIP;
   c->peer = ctx_new(dev);
@@ -1230,6 +1237,8 @@ const char* pifu_status_string(int32_t s) {
     case PIFU_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
     case PIFU_ERR_UNSUPPORTED: return "unsupported";
     case PIFU_ERR_HIP: return "HIP runtime error";
+    case PIFU_ERR_SCRATCH_TOO_SMALL:
+      return "the options need more workspace than the no-allocation entry point's fixed scratch";
     default: return "unknown status";
   }
 }

@@ -327,6 +327,13 @@ void launch_pack_many(const PackJobs& jobs, hipStream_t s);
 }  // namespace pifu
 
 namespace pifu {
+// ------------------------------------------------------------------ handle helpers
+// The device a handle is bound to.
+int ctx_device(const pifu_ctx* c);
+// Looks up this device's copy of the no-allocation scratch array (the device must be
+// current); called by pifu_create.
+int noalloc_setup(int device);
+
 // ------------------------------------------------------------------ training kernels
 uint32_t bce_partials(uint32_t n);
 void launch_bce_grad(const float* s, const float4* pts, uint32_t n, float* g, float* loss_part,

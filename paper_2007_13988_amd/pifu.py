@@ -23,7 +23,7 @@ FIELD_MLP, FIELD_ELLIPSOIDS, FIELD_PLANE = 0, 1, 2
 ACT = {"relu": 1, "lrelu": 2, "sigmoid": 3, "tanh": 4}
 PREC = {"fp32": 0, "bf16": 1, "fp8": 2, "fp16": 3}
 STATUS = {0: "ok", -1: "invalid argument", -2: "workspace too small", -3: "unsupported",
-          -4: "HIP runtime error"}
+          -4: "HIP runtime error", -5: "scratch too small (no-allocation entry point)"}
 
 
 class PifuMLP(C.Structure):
@@ -113,7 +113,8 @@ EXPORTS = ["pifu_create", "pifu_destroy", "pifu_status_string",
            "pifu_occupancy_grid_batched", "pifu_autotune_mlp", "pifu_autotune_clear",
            "pifu_convert_f32", "pifu_grid_and_render", "pifu_render_view_traced", "pifu_fp8_calibrate",
            "pifu_occupancy_grid_async_workspace_size", "pifu_occupancy_grid_async",
-           "pifu_render_view_async_workspace_size", "pifu_render_view_async"]
+           "pifu_render_view_async_workspace_size", "pifu_render_view_async",
+           "pifu_noalloc_scratch_bytes", "pifu_occupancy_grid_async_noalloc"]
 
 _lib = None
 
@@ -156,6 +157,10 @@ def load_library():
                                                              C.POINTER(sz)]
     lib.pifu_occupancy_grid_async.argtypes = [P, C.POINTER(PifuField), C.POINTER(PifuGridOpts), u32,
                                               P, P, P, P, u32, P, P, P, P, sz, P]
+    lib.pifu_noalloc_scratch_bytes.argtypes = []
+    lib.pifu_occupancy_grid_async_noalloc.argtypes = [P, C.POINTER(PifuField),
+                                                      C.POINTER(PifuGridOpts), u32, P, P, P, P,
+                                                      u32, P, P, P, P]
     lib.pifu_render_view_async_workspace_size.argtypes = [C.POINTER(PifuField),
                                                           C.POINTER(PifuField),
                                                           C.POINTER(PifuRenderOpts), u32,
@@ -180,8 +185,9 @@ def load_library():
     lib.pifu_profile_enable.argtypes = [P, i32]
     lib.pifu_profile_read.argtypes = [P, C.POINTER(PifuKernelProfile)]
     for name in EXPORTS:
-        if name not in ("pifu_destroy", "pifu_status_string"):
+        if name not in ("pifu_destroy", "pifu_status_string", "pifu_noalloc_scratch_bytes"):
             getattr(lib, name).restype = i32
+    lib.pifu_noalloc_scratch_bytes.restype = sz
     _lib = lib
     return lib
 
@@ -555,7 +561,9 @@ class AsyncGrid:
     only enqueues (graph-capturable); read n_cells / stats / status after the stream."""
 
     def __init__(self, field: DeviceField, opts: PifuGridOpts, max_points: int = 0,
-                 eval_level: bool = False, cells_cap: Optional[int] = None, device="cuda"):
+                 eval_level: bool = False, cells_cap: Optional[int] = None, device="cuda",
+                 workspace: bool = True):
+        """workspace=False: no workspace buffer; only run_noalloc() can be used."""
         lib = load_library()
         n = (1 << opts.log2_final) + 1
         self.field, self.opts, self.max_points = field, opts, max_points
@@ -571,9 +579,21 @@ class AsyncGrid:
         _check(lib.pifu_occupancy_grid_async_workspace_size(C.byref(field.struct), C.byref(opts),
                                                             max_points, C.byref(sz)),
                "pifu_occupancy_grid_async_workspace_size")
-        self.ws = torch.empty(sz.value, dtype=torch.uint8, device=device)
+        self.ws_bytes = sz.value
+        self.ws = torch.empty(sz.value, dtype=torch.uint8, device=device) if workspace else None
+
+    def run_noalloc(self, stream=None):
+        """pifu_occupancy_grid_async_noalloc: the same call on the library's fixed scratch."""
+        p = self.words.data_ptr()
+        st = load_library().pifu_occupancy_grid_async_noalloc(
+            context(), C.byref(self.field.struct), C.byref(self.opts), self.max_points,
+            _ptr(self.occ), _ptr(self.labels), _ptr(self.eval_level), _ptr(self.cells),
+            self.cells_cap, p, p + 8, p + 4, _stream(stream))
+        _check(st, "pifu_occupancy_grid_async_noalloc")
 
     def run(self, stream=None):
+        if self.ws is None:
+            raise PifuError("this AsyncGrid has no workspace: use run_noalloc()")
         p = self.words.data_ptr()
         st = load_library().pifu_occupancy_grid_async(
             context(), C.byref(self.field.struct), C.byref(self.opts), self.max_points,
