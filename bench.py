@@ -322,6 +322,56 @@ def baselines(P, synth, ms_grid_fp32, args):
     return res
 
 
+OCTREE_THRESHOLDS = (0.05, 0.08, 0.12, 0.2, 0.3, 0.4)   # the thresholds of Fig. 3
+
+
+def octree_tradeoff(P, synth):
+    """The Fig. 3 comparison on synthetic fields: accuracy retained against the dense
+    (brute-force) grid -- IoU of the occupied nodes and the fraction of dense surface
+    cells found -- against the acceleration factor (dense nodes / evaluated nodes), for
+    the method's localization, the binarized octree and the threshold octree at the
+    paper's thresholds.  All FP32 (FP64 guard), 256^3 cells from 32^3."""
+    import torch
+
+    def score(labels, cells, dense_labels, dense_cells, evaluated):
+        a = labels.bool()
+        b = dense_labels.bool()
+        inter = int((a & b).sum().item())
+        union = int((a | b).sum().item())
+        dc = dense_cells.to(torch.int64)
+        found = int(torch.isin(dc, cells.to(torch.int64)).sum().item())
+        return {"iou": round(inter / max(union, 1), 6),
+                "surface_cells_found": round(found / max(dc.numel(), 1), 6),
+                "evaluated": int(evaluated),
+                "acceleration": round(257 ** 3 / max(evaluated, 1), 2)}
+
+    fields = {
+        "pifu_depth_slab_mlp": P.DeviceField.mlp_field(synth.pifu_sequence(102, 0), synth.pifu_mlp()),
+        "pifu_he_init_mlp": P.DeviceField.mlp_field(
+            synth.pifu_sequence(102, 0),
+            synth.he_mlp(256, 1, [1024, 512, 256, 128, 1], [False, True, True, True, False], 202)),
+        "ellipsoids_8": P.DeviceField.ellipsoids(synth.ellipsoids(8, 302), 8.0),
+    }
+    res = {}
+    for name, fld in fields.items():
+        d = P.occupancy_grid(fld, 8, 8, dense=True)
+        row = {}
+        h = P.occupancy_grid(fld, 8, 5)
+        row["method"] = score(h["labels"], h["cells"], d["labels"], d["cells"],
+                              sum(x["evaluated"] for x in h["stats"]))
+        for mode, thrs in (("binarized", (0.0,)), ("threshold", OCTREE_THRESHOLDS)):
+            for thr in thrs:
+                o = P.octree_grid(fld, 8, 5, mode, thr)
+                key = "octree_binarized" if mode == "binarized" else f"octree_threshold_{thr}"
+                row[key] = score(o["labels"], o["cells"], d["labels"], d["cells"],
+                                 sum(x["evaluated"] for x in o["stats"]))
+                del o
+        res[name] = row
+        del d, h
+        torch.cuda.empty_cache()
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -589,6 +639,8 @@ def main():
     if not args.no_baselines:
         log("baselines")
         out["baselines"] = baselines(P, synth, main_r["ms_occ"], args)
+        log("octree trade-off")
+        out["octree_tradeoff"] = octree_tradeoff(P, synth)
     if args.batched:
         log("batched")
         out["batched"] = batched_bench(P, synth, max(1, min(args.steps, 3)))

@@ -223,6 +223,37 @@ int32_t pifu_occupancy_grid(pifu_ctx* ctx, const pifu_field* field, const pifu_g
                             pifu_level_stats* stats, void* workspace, size_t workspace_bytes,
                             pifu_stream stream);
 
+/* ---------------------------------------------------------------- octree baselines */
+
+#define PIFU_OCTREE_BINARIZED 0   /* subdivide cells whose corner labels [p > 0.5] differ */
+#define PIFU_OCTREE_THRESHOLD 1   /* subdivide cells whose corner occupancies deviate from their
+                                     mean by more than a threshold */
+
+/*
+ * The octree subdivisions that Sec. 3.2 ("Octree-based Robust Surface Localization")
+ * compares its localization with (the trade-off of Fig. 3), on the input-view grid:
+ * the coarsest level is evaluated densely; each finer level subdivides the coarse cells
+ * selected by `mode` and evaluates every node of them not evaluated before (no dilation,
+ * no conflict search).  Other nodes take the trilinear interpolation of the coarse
+ * values -- of the corner labels for PIFU_OCTREE_BINARIZED (so 0 or 1), of the corner
+ * occupancies for PIFU_OCTREE_THRESHOLD, with label [value > 0.5].
+ * PIFU_OCTREE_THRESHOLD subdivides a cell when max_i |p_i - mean(p)| > threshold over
+ * its 8 corner occupancy values p_i; the decision reads the stored float32 occupancies
+ * and takes mean and deviations in float64 (corner sum over (di, dj, dk), dk fastest),
+ * and interpolation is separable in float64 (x, then y, then z; 0.5 (lo + hi) per step).
+ * threshold is ignored for PIFU_OCTREE_BINARIZED.
+ * opts, outputs, workspace (pifu_occupancy_grid_workspace_size) and errors as for
+ * pifu_occupancy_grid; opts->dense must be 0; the surrogate and max_waves are not used.
+ * stats (host, nullable, one record per level): nodes, b0 = cells subdivided from the
+ * coarser level, dilated = evaluated = nodes evaluated at the level, and the
+ * evaluation counters.  Blocks until done.
+ */
+int32_t pifu_octree_grid(pifu_ctx* ctx, const pifu_field* field, const pifu_grid_opts* opts,
+                         int32_t mode, double threshold, float* occ, uint8_t* labels,
+                         uint8_t* eval_level, uint32_t* cells, uint32_t cells_cap,
+                         uint32_t* n_cells, pifu_level_stats* stats, void* workspace,
+                         size_t workspace_bytes, pifu_stream stream);
+
 /* ---------------------------------------------------------------- several frames */
 
 /* Outputs of one frame of pifu_occupancy_grid_batched (device buffers as in

@@ -342,6 +342,40 @@ def _corner_stack(v: np.ndarray) -> List[np.ndarray]:
             for di in (0, 1) for dj in (0, 1) for dk in (0, 1)]
 
 
+def octree_step(val: np.ndarray, label: np.ndarray, evaluated: np.ndarray, mode: str,
+                thr: float = 0.0):
+    """One level of the octree subdivision (see octree_localize): from a level's node
+    values, labels and evaluated flags, the cells it subdivides, the finer level's
+    interpolated values and labels (before any evaluation) and the finer nodes to
+    evaluate.  Returns (flag per coarse cell, f_val, f_label, f_eval, todo)."""
+    fdims = tuple(2 * n - 1 for n in val.shape)
+    if mode == "binarized":
+        corners = _corner_stack(label.astype(bool))
+        anyv = np.zeros_like(corners[0])
+        allv = np.ones_like(corners[0])
+        for c in corners:
+            anyv |= c
+            allv &= c
+        flag = anyv & ~allv
+        interp = upsample_x2(label.astype(np.float64))
+    else:
+        corners = _corner_stack(val)
+        mean = sum(corners) / 8.0
+        dev = np.zeros_like(mean)
+        for c in corners:
+            dev = np.maximum(dev, np.abs(c - mean))
+        flag = dev > thr
+        interp = upsample_x2(val)
+    f_eval = np.zeros(fdims, bool)
+    f_eval[::2, ::2, ::2] = evaluated
+    f_val = interp.copy()
+    f_val[::2, ::2, ::2] = val
+    f_label = (interp > 0.5).astype(np.uint8)
+    f_label[::2, ::2, ::2] = label
+    todo = _cells_of_nodes(flag, fdims) & ~f_eval
+    return flag, f_val, f_label, f_eval, todo
+
+
 def octree_localize(evaluate: Callable[[np.ndarray], np.ndarray], log2_cells: Tuple[int, int, int],
                     n_refine: int, mode: str, thr: float = 0.0) -> LocalizeResult:
     """The two octree subdivisions the paper compares its localization with (Sec. 3.2,
@@ -374,32 +408,9 @@ def octree_localize(evaluate: Callable[[np.ndarray], np.ndarray], log2_cells: Tu
                                                        evaluated=int(idx.size), subdivided=0))]
     for t in range(1, T + 1):
         fdims = dims_at(t)
-        if mode == "binarized":
-            corners = _corner_stack(label.astype(bool))
-            anyv = np.zeros_like(corners[0])
-            allv = np.ones_like(corners[0])
-            for c in corners:
-                anyv |= c
-                allv &= c
-            flag = anyv & ~allv
-            interp = upsample_x2(label.astype(np.float64))
-        else:
-            corners = _corner_stack(val)
-            mean = sum(corners) / 8.0
-            dev = np.zeros_like(mean)
-            for c in corners:
-                dev = np.maximum(dev, np.abs(c - mean))
-            flag = dev > thr
-            interp = upsample_x2(val)
-        f_eval = np.zeros(fdims, bool)
-        f_eval[::2, ::2, ::2] = evaluated
+        flag, f_val, f_label, f_eval, todo = octree_step(val, label, evaluated, mode, thr)
         f_logit = np.full(fdims, np.nan)
         f_logit[::2, ::2, ::2] = logit
-        f_val = interp.copy()
-        f_val[::2, ::2, ::2] = val
-        f_label = (interp > 0.5).astype(np.uint8)
-        f_label[::2, ::2, ::2] = label
-        todo = _cells_of_nodes(flag, fdims) & ~f_eval
         idx, lg = _eval_mask(evaluate, fdims, todo)
         f_logit.reshape(-1)[idx] = lg
         f_label.reshape(-1)[idx] = (lg > 0).astype(np.uint8)

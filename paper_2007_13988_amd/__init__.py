@@ -6,4 +6,5 @@ from .pifu import (FIELD_ELLIPSOIDS, FIELD_MLP, FIELD_PLANE, AsyncGrid, AsyncRen
                    DeviceField, DeviceMLP, GridOutputs, RenderOutputs, autotune, autotune_clear,
                    convert, eval_points, fp8_calibrate, grid_opts, load_library, occupancy_grid,
                    occupancy_grid_into, profile_enable, profile_read, render_opts, render_view,
-                   render_view_into, render_view_traced, grid_and_render_into)
+                   render_view_into, render_view_traced, grid_and_render_into, octree_grid,
+                   octree_grid_into)

@@ -989,6 +989,55 @@ int localize(EvalCtx& e, const FieldPrep& fp, const EvalWs& ew, const double* vi
   return PIFU_OK;
 }
 
+// Octree subdivision (the baselines of Sec. 3.2 / Fig. 3): levels 0..T of the input-view
+// grid.  Level 0 is evaluated densely; level t evaluates every node of the level-(t-1)
+// cells that `mode` subdivides and that was not evaluated before.  The cell flags live in
+// w.lab until the level's evaluation rewrites it.
+int octree_levels(EvalCtx& e, const FieldPrep& fp, const EvalWs& ew, int T, LevelBuf* lv,
+                  const LocalizeWs& w, uint8_t* eval_level, Lat eval_lat, int mode, double thr,
+                  pifu_level_stats* stats) {
+  PointSrc src;
+  std::memset(&src, 0, sizeof(src));
+  src.mode = 0;
+  for (int t = 0; t <= T; ++t) {
+    LevelBuf& L = lv[t];
+    pifu_level_stats st;
+    std::memset(&st, 0, sizeof(st));
+    st.level = L.level_id;
+    st.nodes = (uint32_t)L.lat.n();
+    src.nx = L.lat.nx;
+    src.ny = L.lat.ny;
+    src.nz = L.lat.nz;
+    const int stride = (eval_lat.nx - 1) / (L.lat.nx - 1);
+    const uint32_t n_nodes = (uint32_t)L.lat.n();
+    HIP_TRY(hipMemsetAsync(e.counters, 0, sizeof(uint32_t) * C_OVF, e.s));   // keeps C_OVF
+    e.sel_base = 0;
+    uint32_t n = n_nodes;
+    if (t == 0) {
+      launch_fill_u8(L.st, 0, n_nodes, e.s);
+      launch_iota(w.list, n_nodes, e.s);
+    } else {
+      LevelBuf& Cc = lv[t - 1];
+      launch_oct_flags(Cc.st, Cc.occ, Cc.lat, mode, thr, w.lab, e.counters + C_B0, e.s);
+      launch_oct_transition(Cc.st, Cc.occ, Cc.lat, w.lab, L.st, L.occ, L.lat, mode, e.s);
+      int r = compact_count(e, L.st, n_nodes, ST_PEND, ST_PEND, w.cscratch, w.list, n_nodes, 0,
+                            L.lat, &n);
+      if (r) return r;
+      st.b0 = e.ctx->host_counters[C_B0];
+    }
+    int r = eval_occupancy(e, fp, src, w.list, n, ew, w.logit, w.lab, &st);
+    if (r) return r;
+    launch_apply_grid(w.list, n, w.logit, w.lab, L.st, L.occ, nullptr, eval_level, L.level_id,
+                      L.lat, stride, eval_lat, 0, e.s);
+    r = check_launch();
+    if (r) return r;
+    st.dilated = n;
+    st.evaluated = n;
+    if (stats) stats[t] = st;
+  }
+  return PIFU_OK;
+}
+
 // ------------------------------------------------------------------ occupancy grid layout
 struct GridWs {
   LevelBuf lv[11];
@@ -1289,6 +1338,53 @@ int32_t pifu_occupancy_grid(pifu_ctx* ctx, const pifu_field* field, const pifu_g
   if (eval_level) launch_fill_u8(eval_level, 255, fin.n(), s);
   r = localize(e, g.fp, g.ew, nullptr, g.log2, g.T, g.T, g.lv, g.w, eval_level, fin,
                opts->max_waves, opts->surrogate_max_log2, stats);
+  if (!r) {
+    launch_cells(g.lv[g.T].st, fin, labels, s);
+    uint32_t nc = 0;
+    r = compact_count(e, g.lv[g.T].st, fin.n(), ST_CELL, ST_CELL, g.w.cscratch, cells, cells_cap,
+                      1, fin, &nc);
+    *n_cells = nc;
+  }
+  if (!r) r = hipStreamSynchronize(s) == hipSuccess ? PIFU_OK : PIFU_ERR_HIP;
+  prof_resolve(ctx);
+  delete gp;
+  return r;
+}
+
+int32_t pifu_octree_grid(pifu_ctx* ctx, const pifu_field* field, const pifu_grid_opts* opts,
+                         int32_t mode, double threshold, float* occ, uint8_t* labels,
+                         uint8_t* eval_level, uint32_t* cells, uint32_t cells_cap,
+                         uint32_t* n_cells, pifu_level_stats* stats, void* workspace,
+                         size_t workspace_bytes, pifu_stream stream) {
+  if (!ctx || !occ || !labels || !n_cells || !workspace) return PIFU_ERR_INVALID_ARGUMENT;
+  if (cells_cap && !cells) return PIFU_ERR_INVALID_ARGUMENT;
+  if (!aligned(workspace, kAlign)) return PIFU_ERR_INVALID_ARGUMENT;
+  if (mode != PIFU_OCTREE_BINARIZED && mode != PIFU_OCTREE_THRESHOLD)
+    return PIFU_ERR_INVALID_ARGUMENT;
+  if (mode == PIFU_OCTREE_THRESHOLD && !(threshold >= 0.0)) return PIFU_ERR_INVALID_ARGUMENT;
+  int r = validate_grid_opts(field, opts);
+  if (r) return r;
+  if (opts->dense) return PIFU_ERR_INVALID_ARGUMENT;
+  GridWs* gp = new (std::nothrow) GridWs;
+  if (!gp) return PIFU_ERR_HIP;
+  GridWs& g = *gp;
+  plan_grid(field, opts, nullptr, nullptr, g);
+  if (workspace_bytes < g.bytes) {
+    delete gp;
+    return PIFU_ERR_WORKSPACE_TOO_SMALL;
+  }
+  plan_grid(field, opts, workspace, occ, g);
+  hipStream_t s = as_stream(stream);
+  EvalCtx e{ctx, s, g.counters, opts->precision, opts->guard_logit};
+  e.band = logit_band(opts->band_delta);
+  e.tile_m = opts->tile_m;
+  if (int pr = pack_field(g.fp, ctx, s, g.counters)) {
+    delete gp;
+    return pr;
+  }
+  const Lat fin = g.lv[g.T].lat;
+  if (eval_level) launch_fill_u8(eval_level, 255, fin.n(), s);
+  r = octree_levels(e, g.fp, g.ew, g.T, g.lv, g.w, eval_level, fin, mode, threshold, stats);
   if (!r) {
     launch_cells(g.lv[g.T].st, fin, labels, s);
     uint32_t nc = 0;

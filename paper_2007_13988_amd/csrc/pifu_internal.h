@@ -165,6 +165,13 @@ void launch_expand(const uint32_t* list, uint32_t n, uint8_t* st, Lat f, hipStre
                    uint32_t frame_nodes = 0, const uint32_t* n_dev = nullptr);
 void launch_cells(uint8_t* st, Lat f, uint8_t* labels, hipStream_t s);
 void launch_count_bits(const uint8_t* st, size_t n, uint8_t bit, uint32_t* out, hipStream_t s);
+// Octree-subdivision baselines: per coarse cell of lattice c, flags[cell] = subdivide
+// (mode PIFU_OCTREE_*, threshold thr), *count += subdivided cells; then the fine level's
+// state and values with ST_PEND on every node of a subdivided cell not evaluated before.
+void launch_oct_flags(const uint8_t* cst, const float* cocc, Lat c, int mode, double thr,
+                      uint8_t* flags, uint32_t* count, hipStream_t s);
+void launch_oct_transition(const uint8_t* cst, const float* cocc, Lat c, const uint8_t* flags,
+                           uint8_t* fst, float* focc, Lat f, int mode, hipStream_t s);
 
 // ------------------------------------------------------------------ evaluation kernels
 // List kernels below take an optional device-side count n_dev: the list then holds

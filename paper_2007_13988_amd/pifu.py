@@ -114,7 +114,7 @@ EXPORTS = ["pifu_create", "pifu_destroy", "pifu_status_string",
            "pifu_convert_f32", "pifu_grid_and_render", "pifu_render_view_traced", "pifu_fp8_calibrate",
            "pifu_occupancy_grid_async_workspace_size", "pifu_occupancy_grid_async",
            "pifu_render_view_async_workspace_size", "pifu_render_view_async",
-           "pifu_noalloc_scratch_bytes", "pifu_occupancy_grid_async_noalloc"]
+           "pifu_noalloc_scratch_bytes", "pifu_occupancy_grid_async_noalloc", "pifu_octree_grid"]
 
 _lib = None
 
@@ -157,6 +157,9 @@ def load_library():
                                                              C.POINTER(sz)]
     lib.pifu_occupancy_grid_async.argtypes = [P, C.POINTER(PifuField), C.POINTER(PifuGridOpts), u32,
                                               P, P, P, P, u32, P, P, P, P, sz, P]
+    lib.pifu_octree_grid.argtypes = [P, C.POINTER(PifuField), C.POINTER(PifuGridOpts), i32,
+                                     C.c_double, P, P, P, P, u32, C.POINTER(u32),
+                                     C.POINTER(PifuLevelStats), P, sz, P]
     lib.pifu_noalloc_scratch_bytes.argtypes = []
     lib.pifu_occupancy_grid_async_noalloc.argtypes = [P, C.POINTER(PifuField),
                                                       C.POINTER(PifuGridOpts), u32, P, P, P, P,
@@ -399,6 +402,34 @@ def occupancy_grid(field: DeviceField, log2_final: int, log2_coarse: int, *, den
                      max_waves=max_waves, **kw)
     out = GridOutputs(field, opts, cells_cap, eval_level)
     occupancy_grid_into(field, out, stream)
+    nc = out.n_cells.value
+    return dict(occ=out.occ, labels=out.labels, eval_level=out.eval_level,
+                cells=out.cells[:min(nc, out.cells_cap)], n_cells=nc,
+                stats=[s.as_dict() for s in out.stats])
+
+
+OCTREE = {"binarized": 0, "threshold": 1}
+
+
+def octree_grid_into(field: DeviceField, out: GridOutputs, mode: str, threshold: float = 0.0,
+                     stream=None) -> None:
+    """pifu_octree_grid into preallocated outputs (the workspace of the occupancy grid)."""
+    lib = load_library()
+    st = lib.pifu_octree_grid(context(), C.byref(field.struct), C.byref(out.opts), OCTREE[mode],
+                              float(threshold), _ptr(out.occ), _ptr(out.labels),
+                              _ptr(out.eval_level), _ptr(out.cells), out.cells_cap,
+                              C.byref(out.n_cells), out.stats, _ptr(out.ws), out.ws_bytes,
+                              _stream(stream))
+    _check(st, "pifu_octree_grid")
+
+
+def octree_grid(field: DeviceField, log2_final: int, log2_coarse: int, mode: str,
+                threshold: float = 0.0, *, precision="fp32", guard_logit=1e-3, band_delta=0.02,
+                cells_cap=None, eval_level=False, stream=None, **kw) -> Dict[str, object]:
+    """Octree-subdivision baseline grid (see pifu_octree_grid in include/pifu.h)."""
+    opts = grid_opts(log2_final, log2_coarse, False, precision, band_delta, guard_logit, **kw)
+    out = GridOutputs(field, opts, cells_cap, eval_level)
+    octree_grid_into(field, out, mode, threshold, stream)
     nc = out.n_cells.value
     return dict(occ=out.occ, labels=out.labels, eval_level=out.eval_level,
                 cells=out.cells[:min(nc, out.cells_cap)], n_cells=nc,
