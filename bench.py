@@ -67,6 +67,9 @@ def parse():
                     help="skip the second, event-instrumented pass (no roofline)")
     ap.add_argument("--no-serial", action="store_true",
                     help="skip the last pass that runs grid and render one after the other")
+    ap.add_argument("--serial-only", action="store_true",
+                    help="time only the serial pass (grid, then render, on one stream) and its "
+                         "event pass: a profile of the kernels on their own")
     ap.add_argument("--train-frames", type=int, default=6)
     ap.add_argument("--train-samples", type=int, default=1747627)   # 6 x 1.75 M = 10.5 M
     ap.add_argument("--train-steps", type=int, default=4000)
@@ -77,6 +80,8 @@ def parse():
                          "(keeps training kernels out of a profiled run)")
     ap.add_argument("--batched", action="store_true",
                     help="also time 16-frame batched occupancy grids against one call per frame")
+    ap.add_argument("--no-graph-batch", action="store_true",
+                    help="skip the 16-frame batches captured into one HIP graph")
     ap.add_argument("--no-baselines", action="store_true",
                     help="skip the dense 257^3, ellipsoid and He-init field timings")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -264,6 +269,60 @@ def batched_bench(P, synth, steps):
                      "occupied_fraction_min_max": [round(min(occ), 4), round(max(occ), 4)],
                      "evaluated_points_min_max": [min(pts), max(pts)]}
         del bg, outs
+        torch.cuda.empty_cache()
+    return res
+
+
+def graph_batch_bench(P, synth, reps=3):
+    """The batching workload in one captured HIP graph (pifu_occupancy_grid_batched_async:
+    one set of launches per level and wave over every frame's combined list, no host
+    read-back): 16 PIFu-MLP frames of different feature maps at 256^3 from 32^3 (FP32),
+    and 16 ellipsoid-union frames (2-40% occupied) alternating 256^3 / 512^3 from 32^3.
+    Graph replays are timed against the blocking batched call on the same frames; every
+    frame's labels and cells are checked equal to the blocking call's."""
+    import torch
+    from paper_2007_13988_amd.pifu import BatchedGrid
+
+    def timed(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / n * 1e3
+
+    res = {}
+    teacher = P.DeviceMLP(synth.pifu_mlp())
+    mlp_frames = [P.DeviceField(P.FIELD_MLP, feat=synth.pifu_sequence(500 + i, 0), mlp=teacher)
+                  for i in range(16)]
+    scales = [0.5 + 0.08 * i for i in range(16)]
+    ell_frames = [P.DeviceField.ellipsoids(synth.ellipsoids(8, 500 + i, sc))
+                  for i, sc in enumerate(scales)]
+    for name, frames, finals, cap in (("mlp_16x256_fp32", mlp_frames, [8] * 16, 8 << 20),
+                                      ("ellipsoids_16x256_512", ell_frames,
+                                       [8 if i % 2 == 0 else 9 for i in range(16)], 32 << 20)):
+        opts = [P.grid_opts(L, 5) for L in finals]
+        ab = P.AsyncBatchedGrid(frames, opts, max_points=cap)
+        ab.run()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            ab.run(torch.cuda.current_stream())
+        ms_graph = timed(g.replay, reps) / len(frames)
+        status = int(ab.status[0].item())
+        bg = BatchedGrid(frames, opts)
+        ms_blocking = timed(bg.run, reps) / len(frames)
+        same = all(torch.equal(ab.labels[i], bg.labels[i]) and
+                   ab.result(i)["n_cells"] == bg.result(i)["n_cells"] and
+                   torch.equal(ab.result(i)["cells"], bg.result(i)["cells"])
+                   for i in range(len(frames)))
+        res[name] = {"frames": len(frames), "ms_per_frame_graph": round(ms_graph, 3),
+                     "ms_per_frame_blocking_batched": round(ms_blocking, 3),
+                     "graph_speedup": round(ms_blocking / ms_graph, 3), "status": status,
+                     "identical_to_blocking": bool(same), "max_points": cap,
+                     "workspace_gib": round(ab.ws.numel() / 2 ** 30, 2)}
+        del ab, bg, g
         torch.cuda.empty_cache()
     return res
 
@@ -495,21 +554,24 @@ def main():
 
         # the timed steps run uninstrumented: a HIP event pair around a launch costs about
         # 9 us of stream time, ~3.7 ms over the ~370 MLP launches of a frame
-        elapsed = timed_steps()
+        prof, instr = None, None
+        if args.serial_only:
+            elapsed, _ = serial_steps()
+        else:
+            elapsed = timed_steps()
         log(f"form {form}: {elapsed / args.steps * 1e3:.3f} ms/frame")
         # per-launch durations: the same steps again with HIP events around every launch
         # of the GEMM, gather and head families, on the stream they are launched on
-        prof, instr = None, None
-        if not args.no_profile:
+        if not args.no_profile and not args.serial_only:
             P.profile_enable(True)
             instr = timed_steps()
             prof = P.profile_read()
             P.profile_enable(False)
-        ser, t_occ = serial_steps() if not args.no_serial else (None, None)
+        ser, t_occ = serial_steps() if not args.no_serial or args.serial_only else (None, None)
         # the kernels on their own: the serial calls again with events (one stream, nothing
         # running beside them)
         prof_iso, instr_iso = None, None
-        if not args.no_profile and not args.no_serial:
+        if not args.no_profile and (not args.no_serial or args.serial_only):
             P.profile_enable(True)
             instr_iso, _ = serial_steps()
             prof_iso = P.profile_read()
@@ -644,6 +706,9 @@ def main():
     if args.batched:
         log("batched")
         out["batched"] = batched_bench(P, synth, max(1, min(args.steps, 3)))
+    if not args.no_graph_batch:
+        log("graph-captured batch")
+        out["graph_batch"] = graph_batch_bench(P, synth)
     if not args.no_cpu:
         # the plain FP32 frame's labels and recorded render logits for the oracle's
         # level-logic replay

@@ -150,7 +150,8 @@ typedef struct pifu_level_stats {
  *   size use field->surrogate when present (points with |p_s - 0.5| <
  *   surrogate_delta go to the full MLP); -1 disables.  tile_m: MLP point tile
  *   (0 = chosen per launch: autotuned, else by size; 32 (FP32 only, else 64), 64,
- *   128 or 256).  Every tile gives bit-identical results.  max_waves: cap on
+ *   96 (FP32: 128 points x 64 outputs, else 128), 128 or 256).  Every tile gives
+ *   bit-identical results.  max_waves: cap on
  *   conflict waves per level
  *   (0 = none).
  */
@@ -467,6 +468,75 @@ int32_t pifu_occupancy_grid_async_noalloc(pifu_ctx* ctx, const pifu_field* field
                                           uint32_t* n_cells_dev, pifu_level_stats* stats_dev,
                                           uint32_t* status_dev, pifu_stream stream);
 
+/* Outputs of one frame of pifu_occupancy_grid_batched_async (device buffers as in
+ * pifu_occupancy_grid_async). */
+typedef struct pifu_grid_out_dev {
+  float* occ;
+  uint8_t* labels;
+  uint32_t* cells;
+  uint32_t cells_cap;
+  uint32_t* n_cells_dev;          /* device uint32: the frame's true surface-cell count */
+  pifu_level_stats* stats_dev;    /* device, log2_final - log2_coarse + 1 records */
+} pifu_grid_out_dev;
+
+/*
+ * Device-driven pifu_occupancy_grid_batched (frames are processed independently in the
+ * paper, Sec. 3, so their levels run in lockstep): every level and conflict wave is one
+ * set of launches over all frames' combined work list -- one pass of the network's
+ * persistent GEMMs, the precision band and the FP64 guard over every frame's points --
+ * with all counts in device memory and nothing read back, so the whole call can be
+ * captured into one HIP graph and replayed.  Frames, options and restrictions as in
+ * pifu_occupancy_grid_batched (n <= 16; one network; frames may differ in log2_final);
+ * the conflict loop runs the wave ladder of pifu_occupancy_grid_async (opts->max_waves,
+ * else 12 waves with PIFU_STATUS_WAVES_LEFT).  max_points bounds the combined points of
+ * one pass (0: min(largest combined level, 2^21)); the workspace holds that many points'
+ * activations.  Per-frame statistics are tallied on the device.  *status_dev receives the
+ * PIFU_STATUS_* bits of all frames.  Results equal pifu_occupancy_grid_batched's and n
+ * pifu_occupancy_grid calls'.  Unsupported: PIFU_PREC_FP8, PIFU_FIELD_PLANE, and the
+ * surrogate on any level.
+ */
+int32_t pifu_occupancy_grid_batched_async_workspace_size(int32_t n, const pifu_field* const* fields,
+                                                         const pifu_grid_opts* const* opts,
+                                                         uint32_t max_points, size_t* bytes);
+int32_t pifu_occupancy_grid_batched_async(pifu_ctx* ctx, int32_t n, const pifu_field* const* fields,
+                                          const pifu_grid_opts* const* opts, uint32_t max_points,
+                                          const pifu_grid_out_dev* outs, uint32_t* status_dev,
+                                          void* workspace, size_t workspace_bytes,
+                                          pifu_stream stream);
+
+/* ---------------------------------------------------------------- mesh hand-off */
+
+/*
+ * Marching Cubes over the surface cells of an occupancy grid -- the mesh extraction of
+ * the PIFu baseline (Sec. 1; Sec. 3.2, "Inference for Human Reconstruction") -- with
+ * vertex colours (the texture paragraph of Sec. 3.1).
+ * Inputs (device): occ and labels over the (2^log2_final + 1)^3 nodes (z fastest), as
+ * written by pifu_occupancy_grid; cells, the sorted surface-cell list (n_cells entries).
+ * Vertices: one per lattice edge whose end labels differ, at the 0.5 crossing of the
+ * linear interpolation of the two end occupancies (t clipped to [0, 1]), sorted by edge
+ * id 3 * node + axis; verts (device float32 vert_cap x 3, NDC).  Triangles: per cell in
+ * list order, from a 256-case table derived from the contour on the cube faces (an
+ * ambiguous face keeps its inside corners apart, so neighbouring cells agree and the
+ * mesh is closed); normals (right-hand rule) point from label 1 to label 0; tris
+ * (device uint32 tri_cap x 3, vertex indices).  *n_verts and *n_tris (host) receive the
+ * true counts; only the first vert_cap / tri_cap are written (a triangle whose vertex
+ * lies past vert_cap is then meaningless).
+ * colors (device float32 vert_cap x 3, nullable; requires color_field): a vertex seen by
+ * the input camera (orthographic, at z = +1: no label-1 node above the edge's k in the
+ * columns of its two nodes) takes the input pixel -- bilinear over image (device HWC
+ * float32, img_h x img_w x 3, texels outside 0; nullable: then every vertex uses the
+ * network); the others take Eq. 2's colour network (PIFU_FIELD_MLP, n_extra 2, 3
+ * outputs) at [Phi(g_T, P_xy); P_z; 0.5], in FP32.  Workspace: pifu_mesh_workspace_size.
+ * Blocks until done.
+ */
+int32_t pifu_mesh_workspace_size(int32_t log2_final, uint32_t n_cells, uint32_t vert_cap,
+                                 const pifu_field* color_field, size_t* bytes);
+int32_t pifu_mesh(pifu_ctx* ctx, int32_t log2_final, const float* occ, const uint8_t* labels,
+                  const uint32_t* cells, uint32_t n_cells, const pifu_field* color_field,
+                  const float* image, int32_t img_h, int32_t img_w, float* verts, float* colors,
+                  uint32_t vert_cap, uint32_t* n_verts, uint32_t* tris, uint32_t tri_cap,
+                  uint32_t* n_tris, void* workspace, size_t workspace_bytes, pifu_stream stream);
+
 /* ---------------------------------------------------------------- point evaluation */
 
 int32_t pifu_eval_points_workspace_size(const pifu_field* field, int32_t precision, uint32_t n,
@@ -515,6 +585,40 @@ int32_t pifu_mlp_train_workspace_size(const pifu_field* field, uint32_t max_batc
 int32_t pifu_mlp_grad(pifu_ctx* ctx, const pifu_field* field, const float* pts, uint32_t n,
                       float* const* dW, float* const* db, float* loss, void* workspace,
                       size_t workspace_bytes, pifu_stream stream);
+
+/* pifu_mlp_grad that also writes every point's loss softplus(s_m) - t_m s_m to
+ * point_loss (device float32 n, nullable) -- the per-point BCE that point-OHEM reads. */
+int32_t pifu_mlp_grad_ex(pifu_ctx* ctx, const pifu_field* field, const float* pts, uint32_t n,
+                         float* const* dW, float* const* db, float* loss, float* point_loss,
+                         void* workspace, size_t workspace_bytes, pifu_stream stream);
+
+/*
+ * Point-OHEM sampling (Sec. 3.3, Eq. 6 right): draws `batch` training points with
+ * replacement, with probability proportional to their stored inverse probabilities
+ * weights[0 .. n) (device float32, >= 0, not all 0; n <= 2^27).  Each weight w is taken
+ * as the integer floor(w * 2^16) and the prefix sums are exact 64-bit integers; draw b
+ * uses r = output number counter * batch + b of SplitMix64 (Steele, Lea and Flood 2014)
+ * started from state seed, the target t = floor(r * S / 2^64) with S the weights' total,
+ * and picks the first point whose inclusive prefix sum exceeds t.  idx (device uint32,
+ * batch) receives the drawn indices; batch_pts (device float32 batch x 4, 16-byte
+ * aligned, nullable) receives pool[idx] (pool: device n x 4, the training points).
+ * Workspace: pifu_ohem_sample_workspace_size.  Asynchronous on stream.
+ */
+int32_t pifu_ohem_sample_workspace_size(uint32_t n, size_t* bytes);
+int32_t pifu_ohem_sample(pifu_ctx* ctx, const float* weights, uint32_t n, const float* pool,
+                         uint32_t batch, uint64_t seed, uint64_t counter, uint32_t* idx,
+                         float* batch_pts, void* workspace, size_t workspace_bytes,
+                         pifu_stream stream);
+
+/*
+ * The stored inverse probabilities of the drawn points from their losses (Eq. 6 right):
+ * weights[idx[b]] = min(1 / (exp(-point_loss[b] / alpha) + beta), 2^20) for b < batch
+ * (device pointers; alpha > 0, beta >= 0).  The cap keeps the inverse probability finite.
+ * Asynchronous on stream.
+ */
+int32_t pifu_ohem_update(pifu_ctx* ctx, const float* point_loss, const uint32_t* idx,
+                         uint32_t batch, float alpha, float beta, float* weights,
+                         pifu_stream stream);
 
 /*
  * One RMSProp step on every parameter of net (the optimizer the paper trains the

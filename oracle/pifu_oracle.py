@@ -28,6 +28,12 @@ Readings of the paper where it is silent or ambiguous (kept identical on the GPU
     view transform have logit -inf.
   * the surface point is the 0.5 crossing of the linear interpolation of the
     two nodes' occupancy values along z.
+  * the octree baselines compared in Sec. 3.2 / Fig. 3 subdivide the closed 3x3x3 node
+    blocks of the selected coarse cells, with no dilation and no conflict search.
+  * point-OHEM (Sec. 3.3, Eq. 6 right) caps the inverse probability at 2^20 and draws
+    with integer-quantised weights and the SplitMix64 generator.
+  * the mesh hand-off (Marching Cubes) derives its 256-case table from the contour on the
+    cube faces; conventions are listed with the mesh functions below.
 
 Parity: every function here is pinned by the ``-m "not gpu"`` tests in
 ``tests/test_oracle_*.py`` (closed forms, library routines, invariants, brute
@@ -610,6 +616,258 @@ def rmsprop_step(w: np.ndarray, g: np.ndarray, v: np.ndarray, lr: float = 1e-3,
     v = alpha * v + (1.0 - alpha) * g * g
     w = w - lr * g / (np.sqrt(v) + eps)
     return w, v
+
+
+# ------------------------------------------------------------------ mesh hand-off
+# Marching Cubes over the surface cells (the PIFu baseline's mesh extraction, Sec. 1 and
+# Sec. 3.2 "Inference for Human Reconstruction"), with the triangulation of each of the
+# 256 corner cases derived here from the contour on the cube's faces.
+#
+# Conventions (readings; the paper only names the algorithm):
+#   * corner c of a cell has offsets (dx, dy, dz) = (c >> 2 & 1, c >> 1 & 1, c & 1);
+#     local edge e = 4 * axis + 2 * u + v, where (u, v) are the cell offsets of the edge's
+#     lower corner along the two other axes in increasing axis order;
+#   * a face whose four corners alternate inside/outside (ambiguous) keeps its inside
+#     corners apart: each inside corner is cut off by its own segment.  The choice depends
+#     on the face alone, so two cells sharing a face cut it alike and the mesh is closed;
+#   * each face segment is directed so that, seen from outside the cube, the inside
+#     corners lie on its left; the segments of a case join into closed loops, each listed
+#     from its smallest local edge; a loop is cut into the fan (v0, v_i+1, v_i) from the
+#     first position v0 (in loop order) whose fan has no triangle lying in one face of the
+#     cube, so every triangle's normal (right-hand rule) points from inside (label 1) to
+#     outside;
+#   * loops are emitted by increasing smallest edge; cells in the order of the cell list;
+#   * one vertex per lattice edge whose end labels differ, at the 0.5 crossing of the
+#     linear interpolation of the two end occupancies (t clipped to [0, 1], t = 1/2 when
+#     they are equal); vertices are ordered by global edge id 3 * node + axis.
+
+
+def _mc_edge_corners(e: int) -> Tuple[int, int]:
+    axis, u, v = e // 4, (e >> 1) & 1, e & 1
+    others = [a for a in range(3) if a != axis]
+    lo = [0, 0, 0]
+    lo[others[0]], lo[others[1]] = u, v
+    hi = list(lo)
+    hi[axis] = 1
+    enc = lambda q: 4 * q[0] + 2 * q[1] + q[2]
+    return enc(lo), enc(hi)
+
+
+def _mc_corner_pos(c: int) -> np.ndarray:
+    return np.array([(c >> 2) & 1, (c >> 1) & 1, c & 1], np.float64)
+
+
+def mc_case_triangles(case: int) -> List[Tuple[int, int, int]]:
+    """Triangles (local edge triples) of one corner case (bit c set: corner c inside)."""
+    inside = [(case >> c) & 1 for c in range(8)]
+    edges = [_mc_edge_corners(e) for e in range(12)]
+    mid = [(_mc_corner_pos(a) + _mc_corner_pos(b)) / 2 for a, b in edges]
+    nxt = {}
+    for axis in range(3):
+        for side in (0, 1):
+            normal = np.zeros(3)
+            normal[axis] = 1.0 if side else -1.0
+            corners = [c for c in range(8) if ((c >> (2 - axis)) & 1) == side]
+            fedges = [e for e in range(12) if e // 4 != axis and
+                      all(((c >> (2 - axis)) & 1) == side for c in edges[e])]
+            cross = [e for e in fedges if inside[edges[e][0]] != inside[edges[e][1]]]
+            ins = [c for c in corners if inside[c]]
+            if not cross:
+                continue
+            if len(cross) == 2:
+                segs = [(cross[0], cross[1], ins[0])]
+            else:   # ambiguous face: cut off each inside corner
+                segs = []
+                for c in ins:
+                    a, b = [e for e in cross if c in edges[e]]
+                    segs.append((a, b, c))
+            for a, b, q in segs:
+                d = mid[b] - mid[a]
+                if np.dot(np.cross(normal, d), _mc_corner_pos(q) - mid[a]) < 0:
+                    a, b = b, a
+                assert a not in nxt
+                nxt[a] = b
+    tris = []
+    seen = set()
+    for start in sorted(nxt):
+        if start in seen:
+            continue
+        loop = [start]
+        seen.add(start)
+        e = nxt[start]
+        while e != start:
+            loop.append(e)
+            seen.add(e)
+            e = nxt[e]
+        # fan origin: the first loop position (from the smallest edge, in loop order)
+        # whose fan has no triangle lying in one face of the cube (such a triangle would
+        # overlap the neighbouring cell's cut of that face); every case has one
+        def fan(st):
+            L = loop[st:] + loop[:st]
+            return [(L[0], L[i + 1], L[i]) for i in range(1, len(L) - 1)]
+        for st in range(len(loop)):
+            cand = fan(st)
+            if not any(_mc_common_face(t) for t in cand):
+                tris.extend(cand)
+                break
+        else:
+            raise AssertionError("no fan origin for case %d" % case)
+    return tris
+
+
+def _mc_common_face(tri) -> bool:
+    """The three edges of a triangle lie in one face of the cube."""
+    common = None
+    for e in tri:
+        a, b = _mc_edge_corners(e)
+        fs = {(ax, sd) for ax in range(3) for sd in (0, 1)
+              if ((a >> (2 - ax)) & 1) == sd and ((b >> (2 - ax)) & 1) == sd}
+        common = fs if common is None else common & fs
+    return bool(common)
+
+
+def mc_table() -> List[List[Tuple[int, int, int]]]:
+    return [mc_case_triangles(c) for c in range(256)]
+
+
+def mesh_from_grid(occ: np.ndarray, labels: np.ndarray) -> Dict[str, np.ndarray]:
+    """Vertices (NDC, float64), their global edge ids and the triangles (vertex index
+    triples) of the labelled grid, cell by cell in sorted cell order."""
+    n = labels.shape[0]
+    R = n - 1
+    lab = labels.astype(bool)
+    occ = np.asarray(occ, np.float64)
+    ids, pos = [], []
+    for axis in range(3):
+        lo = [slice(0, n)] * 3
+        hi = [slice(0, n)] * 3
+        lo[axis] = slice(0, n - 1)
+        hi[axis] = slice(1, n)
+        crossed = lab[tuple(lo)] != lab[tuple(hi)]
+        for i, j, k in np.argwhere(crossed):
+            a = np.array([i, j, k])
+            b = a.copy()
+            b[axis] += 1
+            pa, pb = occ[tuple(a)], occ[tuple(b)]
+            t = 0.5 if pb == pa else min(max((0.5 - pa) / (pb - pa), 0.0), 1.0)
+            Pa = -1.0 + 2.0 * a / R
+            Pb = -1.0 + 2.0 * b / R
+            ids.append(((i * n + j) * n + k) * 3 + axis)
+            pos.append(Pa + t * (Pb - Pa))
+    order = np.argsort(np.array(ids, np.int64), kind="stable")
+    ids = np.array(ids, np.int64)[order]
+    verts = np.array(pos, np.float64).reshape(-1, 3)[order]
+    table = mc_table()
+    tris = []
+    for cell in surface_cells(labels):
+        i, j, k = int(cell // (R * R)), int((cell // R) % R), int(cell % R)
+        case = 0
+        for c in range(8):
+            if lab[i + ((c >> 2) & 1), j + ((c >> 1) & 1), k + (c & 1)]:
+                case |= 1 << c
+        for tri in table[case]:
+            vs = []
+            for e in tri:
+                axis, u, v = e // 4, (e >> 1) & 1, e & 1
+                off = [0, 0, 0]
+                others = [a for a in range(3) if a != axis]
+                off[others[0]], off[others[1]] = u, v
+                gid = (((i + off[0]) * n + (j + off[1])) * n + (k + off[2])) * 3 + axis
+                vs.append(int(np.searchsorted(ids, gid)))
+            tris.append(vs)
+    return dict(edge_ids=ids, verts=verts, tris=np.array(tris, np.int64).reshape(-1, 3))
+
+
+def front_depth_index(labels: np.ndarray) -> np.ndarray:
+    """Per input-view column (i, j): the largest k with label 1 (the occupied node nearest
+    the camera at z = +1), -1 where the column is empty."""
+    n = labels.shape[2]
+    ks = np.where(labels.astype(bool), np.arange(n)[None, None, :], -1)
+    return ks.max(axis=2)
+
+
+def mesh_vertex_visible(edge_ids: np.ndarray, labels: np.ndarray) -> np.ndarray:
+    """A vertex on the edge from node (i, j, k) along an axis is visible from the input
+    camera (orthographic, at z = +1) when no occupied node lies in front of it in the
+    columns of the edge's two nodes: every column's front node index is <= k."""
+    n = labels.shape[0]
+    kf = front_depth_index(labels)
+    out = np.zeros(edge_ids.size, bool)
+    for m, g in enumerate(edge_ids):
+        axis = int(g % 3)
+        node = int(g // 3)
+        i, j, k = node // (n * n), (node // n) % n, node % n
+        cols = [(i, j)]
+        if axis == 0:
+            cols.append((i + 1, j))
+        elif axis == 1:
+            cols.append((i, j + 1))
+        out[m] = all(kf[c] <= k for c in cols)
+    return out
+
+
+def mesh_colors(verts: np.ndarray, visible: np.ndarray, image: np.ndarray,
+                color_fld: Field) -> np.ndarray:
+    """Vertex colours: the input pixel (bilinear, HWC image in [-1, 1]) for visible
+    vertices (the texture paragraph of Sec. 3.1); Eq. 2's colour network at
+    [Phi(g_T, P_xy); P_z; 0.5] for the others (the vertex lies on the 0.5 level set)."""
+    out = np.empty((verts.shape[0], 3))
+    if np.any(visible):
+        out[visible] = bilinear_sample(image, verts[visible, 0], verts[visible, 1])
+    hid = ~visible
+    if np.any(hid):
+        P = verts[hid]
+        f = bilinear_sample(color_fld.feat, P[:, 0], P[:, 1])
+        extras = np.stack([P[:, 2], np.full(P.shape[0], 0.5)], 1)
+        out[hid] = np.tanh(mlp_preact(color_fld.mlp, f, extras))
+    return out
+
+
+# ------------------------------------------------------------------ point-OHEM (Sec. 3.3)
+# Readings: the inverse probability is capped at OHEM_W_MAX (the paper only asks that it
+# stay finite); weights enter the sampler as fixed-point integers floor(w * 2^16), so the
+# prefix sums are exact; draws come from the counter-based SplitMix64 generator.
+OHEM_W_MAX = 2.0 ** 20
+OHEM_Q_SCALE = 2 ** 16
+_M64 = (1 << 64) - 1
+_GOLDEN_GAMMA = 0x9E3779B97F4A7C15
+
+
+def ohem_point_weight(loss: np.ndarray, alpha: float = 0.7, beta: float = 0.0) -> np.ndarray:
+    """Eq. 6 (right): inverse sampling probability of a point from its BCE loss,
+    P_pt^-1 = 1 / (exp(-L / alpha) + beta), capped at OHEM_W_MAX."""
+    with np.errstate(divide="ignore"):
+        w = 1.0 / (np.exp(-np.asarray(loss, np.float64) / alpha) + beta)
+    return np.minimum(w, OHEM_W_MAX)
+
+
+def splitmix64(seed: int, counter: int) -> int:
+    """Output number `counter` (0-based) of SplitMix64 (Steele, Lea and Flood 2014)
+    started from state `seed`: the state advanced counter + 1 times by the golden gamma,
+    then the published finaliser (xor-shift 30, multiply, xor-shift 27, multiply,
+    xor-shift 31)."""
+    z = (seed + (counter + 1) * _GOLDEN_GAMMA) & _M64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+    return z ^ (z >> 31)
+
+
+def ohem_sample(weights: np.ndarray, batch: int, seed: int, counter: int) -> np.ndarray:
+    """Indices of one training batch drawn with replacement with probability proportional
+    to the stored inverse probabilities (their normalisation, Sec. 3.3).  Weights are
+    taken as float32 and quantised to q_m = floor(w_m 2^16); draw b uses
+    r_b = splitmix64(seed, counter * batch + b), the target t_b = floor(r_b S / 2^64)
+    with S = sum q, and picks the first m whose inclusive prefix sum exceeds t_b."""
+    w32 = np.asarray(weights, np.float32).astype(np.float64)
+    q = np.floor(w32 * OHEM_Q_SCALE).astype(np.uint64)
+    S = np.cumsum(q, dtype=np.uint64)
+    total = int(S[-1])
+    out = np.empty(batch, np.int64)
+    for b in range(batch):
+        r = splitmix64(seed, counter * batch + b)
+        t = (r * total) >> 64
+        out[b] = int(np.searchsorted(S, np.uint64(t), side="right"))
+    return out
 
 
 # ------------------------------------------------------------------ number formats

@@ -81,12 +81,16 @@ __device__ inline void bilinear_setup(double x, double y, int H, int W, int& u0,
 
 // ------------------------------------------------------------------ analytic fields
 __global__ void k_eval_analytic(PointSrc src, const uint32_t* __restrict__ list, uint32_t n,
-                                const uint32_t* __restrict__ n_dev, int kind, Ellipsoids ell,
-                                float4 plane, float* __restrict__ logit, uint8_t* __restrict__ lab) {
+                                const uint32_t* __restrict__ n_dev, int kind, Ellipsoids ell0,
+                                float4 plane, float* __restrict__ logit, uint8_t* __restrict__ lab,
+                                const Ellipsoids* __restrict__ ell_tab) {
   const uint32_t ne = eff_count(n, n_dev);
   for (uint32_t m = blockIdx.x * blockDim.x + threadIdx.x; m < ne; m += gridDim.x * blockDim.x) {
   double P[3];
-  bool in = src_point(src, list, m, P, nullptr);
+  int frame = 0;
+  bool in = src_point(src, list, m, P, nullptr, &frame);
+  // multi-frame lists: each frame's shapes from the table
+  const Ellipsoids& ell = ell_tab ? ell_tab[frame] : ell0;
   double lg;
   if (!in) {
     lg = -INFINITY;
@@ -114,11 +118,22 @@ __global__ void k_eval_analytic(PointSrc src, const uint32_t* __restrict__ list,
 
 void launch_eval_analytic(const PointSrc& src, const uint32_t* list, uint32_t n, int kind,
                           const Ellipsoids& ell, const float plane[4], float* logit, uint8_t* lab,
-                          hipStream_t s, const uint32_t* n_dev) {
+                          hipStream_t s, const uint32_t* n_dev, const Ellipsoids* ell_tab) {
   if (!n) return;
   float4 pl = make_float4(plane[0], plane[1], plane[2], plane[3]);
   hipLaunchKernelGGL(k_eval_analytic, dim3(list_grid(n, 128, n_dev)), dim3(128), 0, s, src, list,
-                     n, n_dev, kind, ell, pl, logit, lab);
+                     n, n_dev, kind, ell, pl, logit, lab, ell_tab);
+}
+
+__global__ void k_store_ellipsoids(Ellipsoids e, Ellipsoids* __restrict__ dst) {
+  const int n = (int)(sizeof(Ellipsoids) / 4);
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(&e);
+  uint32_t* d = reinterpret_cast<uint32_t*>(dst);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) d[i] = src[i];
+}
+
+void launch_store_ellipsoids(Ellipsoids* dst, const Ellipsoids& e, hipStream_t s) {
+  hipLaunchKernelGGL(k_store_ellipsoids, dim3(1), dim3(256), 0, s, e, dst);
 }
 
 // ------------------------------------------------------------------ bilinear gather

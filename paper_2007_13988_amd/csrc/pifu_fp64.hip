@@ -12,8 +12,14 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 static inline unsigned grid1d(size_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
-__device__ inline bool src_point64(const PointSrc& s, uint32_t idx, double P[3], double* occ) {
+__device__ inline bool src_point64(const PointSrc& s, uint32_t idx, double P[3], double* occ,
+                                   int* frame = nullptr) {
   idx -= s.base_sub;
+  if (s.frame_nodes) {   // an index into frames of frame_nodes nodes stored back to back
+    const uint32_t f = idx / s.frame_nodes;
+    idx -= f * s.frame_nodes;
+    if (frame) *frame = (int)f;
+  }
   if (s.mode == 1) {
     const float4 q = s.pts[idx];
     P[0] = q.x;
@@ -68,7 +74,9 @@ k_gather64(PointSrc src, const uint32_t* __restrict__ nodes, uint32_t n,
   const uint32_t waves = (gridDim.x * blockDim.x) >> 6;
   for (uint32_t m = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; m < n; m += waves) {
   double P[3], occ;
-  const bool in = src_point64(src, nodes[m], P, &occ);
+  int frame = 0;
+  const bool in = src_point64(src, nodes[m], P, &occ, &frame);
+  const float* __restrict__ Fm = src.frame_nodes ? src.feat_tab[frame] : F;
   double u = __dmul_rn(__dmul_rn(__dadd_rn(P[0], 1.0), 0.5), (double)(W - 1));
   double v = __dmul_rn(__dmul_rn(__dadd_rn(P[1], 1.0), 0.5), (double)(H - 1));
   const double fu0 = floor(u), fv0 = floor(v);
@@ -82,7 +90,7 @@ k_gather64(PointSrc src, const uint32_t* __restrict__ nodes, uint32_t n,
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       if (tu[t] < 0 || tu[t] > W - 1 || tv[t] < 0 || tv[t] > H - 1) continue;
-      acc += w[t] * (double)F[((size_t)tv[t] * W + tu[t]) * C + c];
+      acc += w[t] * (double)Fm[((size_t)tv[t] * W + tu[t]) * C + c];
     }
     feat[(size_t)m * C + c] = acc;
   }

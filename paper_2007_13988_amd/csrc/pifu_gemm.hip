@@ -288,6 +288,9 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_f32(GemmArgs a) {
 #pragma unroll
         for (int j = 0; j < TJ; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i].w, bv[j].w, acc[i][j], 0, 0, 0);
+      // scheduling hint: interleave the LDS reads of the next group with these MFMAs
+      // (instruction order only; every accumulator sums k in the same order)
+      __builtin_amdgcn_iglp_opt(0);
     }
     if (kt + 1 < nk) sstore(buf ^ 1);
     __syncthreads();
@@ -1015,7 +1018,7 @@ int launch_gemm(const GemmArgs& a, int precision, int tile_m, hipStream_t s, hip
   if (a.M <= 0) return 0;
   const bool bn128 = (a.N % 128) == 0;
   if (!bn128 && (a.N % 64) != 0) return -1;
-  int bm = tile_m == 64 ? 64 : (tile_m == 256 ? 256 : (tile_m == 32 ? 32 : 128));
+  int bm = tile_m == 64 ? 64 : (tile_m == 256 ? 256 : (tile_m == 32 ? 32 : (tile_m == 96 ? 96 : 128)));
   if (precision == PIFU_PREC_FP32) {
     if ((a.K1 % 32) || (a.K2 % 32)) return -1;
     if (bm == 32) {
@@ -1024,14 +1027,21 @@ int launch_gemm(const GemmArgs& a, int precision, int tile_m, hipStream_t s, hip
                          dim3(128), 0, s, a);
       return 0;
     }
-    if (bn128) {
-      if (bm == 64) PIFU_F32(64, 128, 1, 4, 2);
-      else if (bm == 128) PIFU_F32(128, 128, 2, 2, 2);
-      else PIFU_F32(256, 128, 2, 2, 1);
+    // 256: 256 x 128 (or 256 x 64) over eight waves; 128: 128 x 128 (or 128 x 64);
+    // 96: 128 x 64; 64: 64 x 64.  Every shape walks k in the same order.
+    if (bm == 256) {
+      if (bn128)
+        PIFU_GO((k_gemm_f32<256, 128, 4, 2, 1, 512>), dim3(row_tiles(a.M, 256), a.N / 128),
+                dim3(512), 0, s, a);
+      else
+        PIFU_GO((k_gemm_f32<256, 64, 4, 2, 1, 512>), dim3(row_tiles(a.M, 256), a.N / 64),
+                dim3(512), 0, s, a);
+    } else if (bm == 128 && bn128) {
+      PIFU_F32(128, 128, 2, 2, 2);
+    } else if (bm == 128 || bm == 96) {
+      PIFU_F32(128, 64, 2, 2, 2);
     } else {
-      if (bm == 64) PIFU_F32(64, 64, 2, 2, 2);
-      else if (bm == 128) PIFU_F32(128, 64, 4, 1, 2);
-      else PIFU_F32(256, 64, 4, 1, 1);
+      PIFU_F32(64, 64, 2, 2, 2);
     }
     return 0;
   }
@@ -1053,6 +1063,7 @@ int launch_gemm(const GemmArgs& a, int precision, int tile_m, hipStream_t s, hip
     return 0;
   }
   if (bm == 32) bm = 64;   // the 32-point tile exists for FP32 only
+  if (bm == 96) bm = 128;  // so does the 128 x 64 choice
   if (precision == PIFU_PREC_BF16 || precision == PIFU_PREC_FP16) {
     if ((a.K1 % 64) || (a.K2 % 64)) return -1;
     if (precision == PIFU_PREC_FP16) launch_h16<true>(a, bm, s, ev0, ev1);

@@ -429,6 +429,8 @@ int hoist_np(const FieldPrep& fp) {
   return std::max(fp.mlp.NP, fp.has_sur ? fp.sur.NP : 0);
 }
 
+struct FrameCount;
+
 struct EvalCtx {
   pifu_ctx* ctx;
   hipStream_t s;
@@ -449,6 +451,9 @@ struct EvalCtx {
   // level being evaluated
   uint32_t* aw = nullptr;
   pifu_level_stats* st_dev = nullptr;
+  // multi-frame device-driven calls: per-frame attribution of the evaluation counters
+  // (null: every count goes to st_dev)
+  const FrameCount* fc = nullptr;
 };
 
 int batch_bucket(uint32_t m) { return m <= 8192 ? 0 : (m <= 32768 ? 1 : 2); }
@@ -470,13 +475,28 @@ int default_tile(int prec, int N, int K, uint32_t m) {
   return 64;
 }
 
+// FP32 tile without an autotuned entry (measured on gfx950 over the MLP's layer shapes):
+// launches of 48k+ points take 256 x 128 tiles over eight waves (one workgroup per CU,
+// 0.68-0.78 of the FP32 MFMA peak); launches that still give 512+ workgroups of
+// 128 x 64 take those (two per CU; their last round stays full at mid sizes, e.g. 24k
+// points x 512 outputs: 0.74 against 0.58 for 128 x 128); then 64 x 64; launches too
+// small to fill the chip with 64 x 64 tiles take 32 x 64.  (The tile code 96 names the
+// 128 x 64 shape.)
+int fp32_tile(int N, uint32_t m) {
+  auto tiles = [&](int bm, int bn) { return ((m + bm - 1) / bm) * (uint64_t)(N / bn); };
+  if (N % 64 != 0) return 128;
+  if (m >= 49152) return 256;
+  if (tiles(128, 64) >= 512) return 96;
+  if (tiles(64, 64) >= 256) return 64;
+  return 32;
+}
+
 int pick_tile(const EvalCtx& e, int prec, int N, int K, uint32_t m) {
   if (e.tile_m) return e.tile_m;
-  // FP32 launches too small to fill the chip with 64-point tiles take 32 x 64 tiles:
-  // more workgroups, each with half the serial work
-  if (prec == PIFU_PREC_FP32 && N % 64 == 0 &&
-      ((m + 63) / 64) * (uint64_t)(N % 128 == 0 ? N / 128 : N / 64) < 256)
-    return 32;
+  if (prec == PIFU_PREC_FP32) {
+    auto it = e.ctx->tile_cache.find(tile_key(prec, N, K, m));
+    return it == e.ctx->tile_cache.end() ? fp32_tile(N, m) : it->second;
+  }
   auto it = e.ctx->tile_cache.find(tile_key(prec, N, K, m));
   return it == e.ctx->tile_cache.end() ? default_tile(prec, N, K, m) : it->second;
 }
@@ -1262,6 +1282,7 @@ int32_t pifu_create(pifu_ctx** out) {
   if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return PIFU_ERR_HIP;
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return PIFU_ERR_UNSUPPORTED;
   if (int r = pifu::noalloc_setup(dev)) return r;
+  if (int r = pifu::mesh_table_upload()) return r;
   pifu_ctx* c = ctx_new(dev);
   if (!c) return PIFU_ERR_HIP;
   c->peer = ctx_new(dev);
@@ -1928,6 +1949,13 @@ int32_t pifu_mlp_train_workspace_size(const pifu_field* field, uint32_t max_batc
 int32_t pifu_mlp_grad(pifu_ctx* ctx, const pifu_field* field, const float* pts, uint32_t n,
                       float* const* dW, float* const* db, float* loss, void* workspace,
                       size_t workspace_bytes, pifu_stream stream) {
+  return pifu_mlp_grad_ex(ctx, field, pts, n, dW, db, loss, nullptr, workspace, workspace_bytes,
+                          stream);
+}
+
+int32_t pifu_mlp_grad_ex(pifu_ctx* ctx, const pifu_field* field, const float* pts, uint32_t n,
+                         float* const* dW, float* const* db, float* loss, float* point_loss,
+                         void* workspace, size_t workspace_bytes, pifu_stream stream) {
   if (!ctx || !pts || !dW || !db || !workspace || n == 0) return PIFU_ERR_INVALID_ARGUMENT;
   if (!aligned(pts, 16) || !aligned(workspace, kAlign)) return PIFU_ERR_INVALID_ARGUMENT;
   int r = validate_train_field(field);
@@ -1985,7 +2013,7 @@ int32_t pifu_mlp_grad(pifu_ctx* ctx, const pifu_field* field, const float* pts, 
   launch_head(t.H[L - 1], d.widths[L - 1], d.W[L], d.b[L], 1, d.out_act, n, t.ext, t.s, t.lab,
               nullptr, nullptr, s);
   // loss and dloss/dlogit
-  launch_bce_grad(t.s, src.pts, n, t.g, t.loss_part, loss, s);
+  launch_bce_grad(t.s, src.pts, n, t.g, t.loss_part, loss, s, point_loss);
   // backward
   const float* G = t.g;
   int Ng = 1;
@@ -2009,6 +2037,35 @@ int32_t pifu_mlp_grad(pifu_ctx* ctx, const pifu_field* field, const float* pts, 
   }
   r = check_launch();
   return r;
+}
+
+int32_t pifu_ohem_sample_workspace_size(uint32_t n, size_t* bytes) {
+  if (!bytes || n == 0 || n > (1u << 27)) return PIFU_ERR_INVALID_ARGUMENT;
+  *bytes = ohem_workspace_bytes(n);
+  return PIFU_OK;
+}
+
+int32_t pifu_ohem_sample(pifu_ctx* ctx, const float* weights, uint32_t n, const float* pool,
+                         uint32_t batch, uint64_t seed, uint64_t counter, uint32_t* idx,
+                         float* batch_pts, void* workspace, size_t workspace_bytes,
+                         pifu_stream stream) {
+  if (!ctx || !weights || !idx || !workspace || batch == 0 || n == 0 || n > (1u << 27))
+    return PIFU_ERR_INVALID_ARGUMENT;
+  if (batch_pts && (!pool || !aligned(pool, 16) || !aligned(batch_pts, 16)))
+    return PIFU_ERR_INVALID_ARGUMENT;
+  if (workspace_bytes < ohem_workspace_bytes(n)) return PIFU_ERR_WORKSPACE_TOO_SMALL;
+  launch_ohem_sample(weights, n, reinterpret_cast<const float4*>(pool), batch, seed, counter, idx,
+                     reinterpret_cast<float4*>(batch_pts), workspace, as_stream(stream));
+  return check_launch();
+}
+
+int32_t pifu_ohem_update(pifu_ctx* ctx, const float* point_loss, const uint32_t* idx,
+                         uint32_t batch, float alpha, float beta, float* weights,
+                         pifu_stream stream) {
+  if (!ctx || !point_loss || !idx || !weights || batch == 0) return PIFU_ERR_INVALID_ARGUMENT;
+  if (!(alpha > 0.f) || !(beta >= 0.f)) return PIFU_ERR_INVALID_ARGUMENT;
+  launch_ohem_update(point_loss, idx, batch, alpha, beta, weights, as_stream(stream));
+  return check_launch();
 }
 
 int32_t pifu_rmsprop_step(pifu_ctx* ctx, const pifu_mlp* net, const float* const* dW,
@@ -2051,8 +2108,11 @@ struct BatchPlan {
   uint32_t* counters = nullptr;
   LocalizeWs w;
   uint32_t list_cap = 0;
+  size_t list_words = 0;   // words of w.list: >= list_cap and >= every level's candidate masks
   FieldPrep fps[kMaxFrames];
   EvalWs ew;
+  uint32_t* aw = nullptr;             // device-driven calls: count words
+  Ellipsoids* ell_tab = nullptr;      // device-driven calls: each frame position's shapes
   size_t bytes = 0;
 };
 
@@ -2083,8 +2143,10 @@ int validate_batch(int n, const pifu_field* const* fields, const pifu_grid_opts*
   return PIFU_OK;
 }
 
+// async_cap > 0: the layout of the device-driven call, whose evaluations hold up to
+// async_cap points of the combined list in one pass.
 void plan_batch(int n, const pifu_field* const* fields, const pifu_grid_opts* const* opts, void* base,
-                BatchPlan& b) {
+                BatchPlan& b, uint32_t async_cap = 0) {
   b.n = n;
   b.l0 = opts[0]->log2_coarse;
   b.Tmax = 0;
@@ -2109,8 +2171,12 @@ void plan_batch(int n, const pifu_field* const* fields, const pifu_grid_opts* co
     b.occ[r] = cv.take<float>(tot);
     max_n = std::max(max_n, tot);
   }
-  b.list_cap = (uint32_t)std::min<size_t>(max_n, kBatchListCap);
-  b.w.list = cv.take<uint32_t>(b.list_cap);
+  b.list_cap = (uint32_t)std::min<size_t>(max_n, async_cap ? async_cap : kBatchListCap);
+  // the list buffer also holds a level's candidate bit masks before its compaction
+  b.list_words = b.list_cap;
+  for (int r = 1; r <= b.Tmax; ++r)
+    b.list_words = std::max(b.list_words, 2 * b0_mask_words(b.lat[r]) * (size_t)b.active[r]);
+  b.w.list = cv.take<uint32_t>(b.list_words);
   b.w.cscratch = cv.take<uint32_t>(compact_scratch_words(max_n));
   b.w.logit = cv.take<float>(b.list_cap);
   b.w.lab = cv.take<uint8_t>(b.list_cap);
@@ -2129,9 +2195,23 @@ void plan_batch(int n, const pifu_field* const* fields, const pifu_grid_opts* co
   const int C = fields[0]->kind == PIFU_FIELD_MLP ? fields[0]->C : 0;
   int mh = b.fps[0].has_mlp ? b.fps[0].mlp.max_hidden : 0;
   if (b.fps[0].has_sur) mh = std::max(mh, b.fps[0].sur.max_hidden);
-  carve_eval(cv, b.list_cap, C, mh, b.ew);
-  carve_guard(cv, b.fps[0], b.list_cap, b.ew);
-  carve_hoist(cv, hoist_np(b.fps[0]), b.ew);
+  if (async_cap) {
+    b.aw = cv.take<uint32_t>(AW_COUNT_WORDS);
+    b.ell_tab = cv.take<Ellipsoids>(kMaxFrames);
+    if (b.fps[0].has_mlp) {
+      carve_eval(cv, b.list_cap, C, mh, b.ew, true);
+      carve_guard(cv, b.fps[0], b.list_cap, b.ew);
+      // an evaluation covers at most every x-y column of every active frame
+      size_t cols = 0;
+      for (int r = 0; r <= b.Tmax; ++r)
+        cols = std::max(cols, (size_t)b.active[r] * b.lat[r].nx * b.lat[r].ny);
+      carve_hoist(cv, hoist_np(b.fps[0]), b.ew, (uint32_t)std::min<size_t>(cols, UINT32_MAX));
+    }
+  } else {
+    carve_eval(cv, b.list_cap, C, mh, b.ew);
+    carve_guard(cv, b.fps[0], b.list_cap, b.ew);
+    carve_hoist(cv, hoist_np(b.fps[0]), b.ew);
+  }
   b.bytes = cv.off + kAlign;
 }
 
@@ -2324,7 +2404,7 @@ int32_t pifu_occupancy_grid_batched(pifu_ctx* ctx, int32_t n, const pifu_field* 
       }
     } else {
       launch_transition(b.st[r - 1], b.occ[r - 1], b.lat[r - 1], b.st[r], b.occ[r], L, s, A, &fo);
-      if (2 * b0_mask_words(L) * (size_t)A <= b.list_cap) {
+      if (2 * b0_mask_words(L) * (size_t)A <= b.list_words) {
         // the candidate list is consumed until compact_frames rewrites it
         launch_select_b0(b.st[r], L, A, reinterpret_cast<uint64_t*>(b.w.list), b.counters + C_B0_F,
                          1, s);
@@ -2412,6 +2492,7 @@ enum {
   AW_N0,         // a host-known count, stored for kernels that read counts from memory
   AW_NH,         // render hits
   AW_STATUS,     // status bits (kStatus*)
+  AW_NBSEL,      // multi-frame FP16 runs: band points counted (0 after an overflow)
   AW_COUNT = 16
 };
 // bits of the status word
@@ -2439,6 +2520,35 @@ struct Book {
 
 uint32_t* stat_word(pifu_level_stats* st, uint32_t pifu_level_stats::*f) {
   return reinterpret_cast<uint32_t*>(&(st->*f));
+}
+
+// Per-frame statistics of a multi-frame device-driven evaluation: list entries are
+// combined indices frame * frame_nodes + node; st[p] is frame position p's record of the
+// level being evaluated.
+struct FrameCount {
+  int frames = 0;
+  uint32_t frame_nodes = 0;
+  uint32_t* tally = nullptr;   // kMaxBatch device words, zero between uses
+  pifu_level_stats* st[kMaxBatch] = {};
+};
+
+// field of every frame's record op= (entries of the list, or of its positions pos, per
+// frame), for the first min(cap, *n_dev) entries.
+void count_frames(EvalCtx& e, const uint32_t* list, const uint32_t* pos, uint32_t cap,
+                  const uint32_t* n_dev, uint32_t pifu_level_stats::*field, int op = BK_ADD,
+                  uint32_t pifu_level_stats::*field2 = nullptr, int op2 = BK_ADD) {
+  const FrameCount& fc = *e.fc;
+  launch_frame_tally(list, pos, cap, n_dev, fc.frame_nodes, fc.tally, e.s);
+  FrameApply a{};
+  a.frames = fc.frames;
+  a.nops = field2 ? 2 : 1;
+  a.kind[0] = op;
+  a.kind[1] = op2;
+  for (int p = 0; p < fc.frames; ++p) {
+    a.dst[0][p] = stat_word(fc.st[p], field);
+    if (field2) a.dst[1][p] = stat_word(fc.st[p], field2);
+  }
+  launch_frame_apply(fc.tally, a, e.s);
 }
 
 // run_mlp over a list whose length lives on the device (at most cap <= ew.chunk
@@ -2570,17 +2680,28 @@ int post_full_dev(EvalCtx& e, const FieldPrep& fp, const PointSrc& src, const fl
     launch_scatter_results(ew.band_pos, cap, ew.band_logit, ew.band_lab, logit, lab, e.s, nb);
   }
   Book b(e.s);
-  uint32_t* band_stat = stat_word(e.st_dev, &pifu_level_stats::band_fp32);
+  uint32_t* band_stat = e.fc ? nullptr : stat_word(e.st_dev, &pifu_level_stats::band_fp32);
   if (f16) {
     // a value outside the binary16 range so far in this call: all points in FP32
     uint32_t* rr = e.aw + AW_RR;
     b.add(BK_SEL, rr, n_dev, 0, 0, e.counters + C_OVF);
-    b.add(BK_ADD_SEL, band_stat, n_dev, 0, 0, e.counters + C_OVF, band ? nb : nullptr);
-    b.flush();
+    if (e.fc) {
+      // per frame: every point after an overflow, else the band's points
+      uint32_t* nb_sel = e.aw + AW_NBSEL;
+      b.add(BK_SET_IMM, nb_sel, nullptr, 0);
+      b.add(BK_ADD_SEL, nb_sel, nullptr, 0, 0, e.counters + C_OVF, band ? nb : nullptr);
+      b.flush();
+      count_frames(e, list, nullptr, cap, rr, &pifu_level_stats::band_fp32);
+      if (band) count_frames(e, list, ew.band_pos, cap, nb_sel, &pifu_level_stats::band_fp32);
+    } else {
+      b.add(BK_ADD_SEL, band_stat, n_dev, 0, 0, e.counters + C_OVF, band ? nb : nullptr);
+      b.flush();
+    }
     r = run_mlp_dev(e, fp, fp.mlp, PIFU_PREC_FP32, src, list, cap, rr, ew, logit, lab, nullptr, F);
     if (r) return r;
   } else if (band) {
-    b.add(BK_ADD, band_stat, nb);
+    if (e.fc) count_frames(e, list, ew.band_pos, cap, nb, &pifu_level_stats::band_fp32);
+    else b.add(BK_ADD, band_stat, nb);
   }
   if (!(e.guard > 0.f)) return PIFU_OK;
   uint32_t* gn = e.aw + AW_GN;
@@ -2588,7 +2709,9 @@ int post_full_dev(EvalCtx& e, const FieldPrep& fp, const PointSrc& src, const fl
   run_guard64(src, list, ew.glist, std::min(cap, ew.chunk64), fp.mlp.d, F, f->H, f->W, f->C, logit,
               lab, ew.g64, ew.chunk64, !e.g64_packed, e.s, gn);
   e.g64_packed = true;
-  b.add(BK_ADD, stat_word(e.st_dev, &pifu_level_stats::guard_fp64), gn);
+  if (e.fc) count_frames(e, list, ew.glist, std::min(cap, ew.chunk64), gn,
+                         &pifu_level_stats::guard_fp64);
+  else b.add(BK_ADD, stat_word(e.st_dev, &pifu_level_stats::guard_fp64), gn);
   b.add(BK_FLAG_GT, e.aw + AW_STATUS, gn, ew.chunk64, kStatusGuardOver);
   return check_launch();
 }
@@ -2598,7 +2721,9 @@ int eval_full_dev(EvalCtx& e, const FieldPrep& fp, const PointSrc& src, const ui
                   uint8_t* lab) {
   int r = run_mlp_dev(e, fp, fp.mlp, e.precision, src, list, cap, n_dev, ew, logit, lab, nullptr);
   if (r) return r;
-  {
+  if (e.fc) {
+    count_frames(e, list, nullptr, cap, n_dev, &pifu_level_stats::mlp_points);
+  } else {
     Book b(e.s);
     b.add(BK_ADD, stat_word(e.st_dev, &pifu_level_stats::mlp_points), n_dev);
   }
@@ -2709,8 +2834,9 @@ int localize_dev(EvalCtx& e, const FieldPrep& fp, const EvalWs& ew, const double
       }
       if (rung == budget && bounded) break;
       launch_expand(w.list, ecap, L.st, L.lat, e.s, 0, n_dev);
+      // an empty wave selects nothing: the compaction is gated on its count
       launch_compact(L.st, n_nodes, ST_PEND, ST_PEND, w.cscratch, n_dev, w.list, n_nodes, 0, L.lat,
-                     e.s);
+                     e.s, 0, n_dev);
       Book b(e.s);
       if (rung < budget) {
         b.add(BK_ADD_NZ, stat_word(sd, &pifu_level_stats::waves), n_dev);
@@ -2942,6 +3068,392 @@ int32_t pifu_render_view_async(pifu_ctx* ctx, const pifu_field* occ_field,
   }
   if (!r) r = check_launch();
   delete gp;
+  return r;
+}
+
+}  // extern "C"
+
+// ================================================================== device-driven batch
+// Several frames' levels in lockstep, as pifu_occupancy_grid_batched, with every count in
+// device memory and a fixed ladder of conflict waves per level (as
+// pifu_occupancy_grid_async): one set of launches per level and wave covers every
+// frame's work list, nothing is read back, and the whole call can be captured into one
+// HIP graph.  Per-frame statistics are tallied from the combined lists on the device.
+namespace {
+
+constexpr int C_TALLY = 72;   // kMaxBatch counter words for per-frame tallies
+constexpr uint32_t kDefaultBatchCap = 1u << 21;
+
+// Evaluates min(cap, *n_dev) entries of the combined list (indices p * frame_nodes +
+// node): one pass of the network over every frame (the gathers pick each frame's feature
+// map), the precision band and the FP64 guard over the combined list; analytic frames
+// read their shapes from the device table.
+int eval_frames_dev(EvalCtx& e, BatchPlan& b, const PointSrc& sall, uint32_t cap,
+                    const uint32_t* n_dev) {
+  const FieldPrep& fp0 = b.fps[0];
+  if (!fp0.has_mlp) {
+    launch_eval_analytic(sall, b.w.list, cap, fp0.f->kind, fp0.ell, fp0.f->plane, b.w.logit,
+                         b.w.lab, e.s, n_dev, b.ell_tab);
+    return check_launch();
+  }
+  return eval_full_dev(e, fp0, sall, b.w.list, cap, n_dev, b.ew, b.w.logit, b.w.lab);
+}
+
+int validate_batch_async(int n, const pifu_field* const* fields, const pifu_grid_opts* const* opts) {
+  int r = validate_batch(n, fields, opts);
+  if (r) return r;
+  const pifu_grid_opts& o = *opts[0];
+  if (o.precision == PIFU_PREC_FP8) return PIFU_ERR_UNSUPPORTED;
+  if (fields[0]->kind == PIFU_FIELD_PLANE) return PIFU_ERR_UNSUPPORTED;
+  if (fields[0]->kind == PIFU_FIELD_MLP && fields[0]->surrogate &&
+      o.surrogate_max_log2 >= o.log2_coarse)
+    return PIFU_ERR_UNSUPPORTED;
+  return PIFU_OK;
+}
+
+// The combined capacity of one evaluation pass.
+uint32_t batch_async_cap(int n, const pifu_field* const* fields, const pifu_grid_opts* const* opts,
+                         uint32_t max_points, size_t* max_n_out) {
+  BatchPlan* bp = new (std::nothrow) BatchPlan;
+  if (!bp) return 0;
+  plan_batch(n, fields, opts, nullptr, *bp, 1);
+  size_t max_n = 0;
+  for (int r = 0; r <= bp->Tmax; ++r) max_n = std::max(max_n, bp->lat[r].n() * bp->active[r]);
+  delete bp;
+  if (max_n_out) *max_n_out = max_n;
+  const size_t want = max_points ? max_points : std::min<size_t>(max_n, kDefaultBatchCap);
+  return (uint32_t)std::min<size_t>(want, max_n);
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t pifu_occupancy_grid_batched_async_workspace_size(int32_t n, const pifu_field* const* fields,
+                                                         const pifu_grid_opts* const* opts,
+                                                         uint32_t max_points, size_t* bytes) {
+  if (!bytes) return PIFU_ERR_INVALID_ARGUMENT;
+  int r = validate_batch_async(n, fields, opts);
+  if (r) return r;
+  const uint32_t cap = batch_async_cap(n, fields, opts, max_points, nullptr);
+  if (!cap) return PIFU_ERR_HIP;
+  BatchPlan* bp = new (std::nothrow) BatchPlan;
+  if (!bp) return PIFU_ERR_HIP;
+  plan_batch(n, fields, opts, nullptr, *bp, cap);
+  *bytes = bp->bytes;
+  delete bp;
+  return PIFU_OK;
+}
+
+int32_t pifu_occupancy_grid_batched_async(pifu_ctx* ctx, int32_t n, const pifu_field* const* fields,
+                                          const pifu_grid_opts* const* opts, uint32_t max_points,
+                                          const pifu_grid_out_dev* outs, uint32_t* status_dev,
+                                          void* workspace, size_t workspace_bytes,
+                                          pifu_stream stream) {
+  if (!ctx || !outs || !status_dev || !workspace || !aligned(workspace, kAlign) ||
+      !aligned(status_dev, 4))
+    return PIFU_ERR_INVALID_ARGUMENT;
+  int rc = validate_batch_async(n, fields, opts);
+  if (rc) return rc;
+  for (int f = 0; f < n; ++f) {
+    const pifu_grid_out_dev& o = outs[f];
+    if (!o.occ || !o.labels || !o.n_cells_dev || !o.stats_dev || (o.cells_cap && !o.cells) ||
+        !aligned(o.n_cells_dev, 4) || !aligned(o.stats_dev, 4))
+      return PIFU_ERR_INVALID_ARGUMENT;
+  }
+  const uint32_t cap = batch_async_cap(n, fields, opts, max_points, nullptr);
+  if (!cap) return PIFU_ERR_HIP;
+  BatchPlan* bp = new (std::nothrow) BatchPlan;
+  if (!bp) return PIFU_ERR_HIP;
+  BatchPlan& b = *bp;
+  plan_batch(n, fields, opts, nullptr, b, cap);
+  if (workspace_bytes < b.bytes) {
+    delete bp;
+    return PIFU_ERR_WORKSPACE_TOO_SMALL;
+  }
+  plan_batch(n, fields, opts, workspace, b, cap);
+  // the first level evaluates every node of every frame in one pass
+  if ((size_t)b.lat[0].n() * b.active[0] > cap) {
+    delete bp;
+    return PIFU_ERR_WORKSPACE_TOO_SMALL;
+  }
+  hipStream_t s = as_stream(stream);
+  const pifu_grid_opts& o = *opts[0];
+  EvalCtx e{ctx, s, b.counters, o.precision, o.guard_logit};
+  e.band = logit_band(o.band_delta);
+  e.aw = b.aw;
+  FrameCount fc;
+  fc.tally = b.counters + C_TALLY;
+  e.fc = &fc;
+  launch_set_u32(b.aw, 0, s, AW_COUNT_WORDS);
+  launch_set_u32(b.counters, 0, s, kCounters + 2 * kMaxFrames + 64);
+  for (int f = 0; f < n; ++f)
+    launch_set_u32(reinterpret_cast<uint32_t*>(outs[f].stats_dev), 0, s,
+                   (uint32_t)((b.T[f] + 1) * sizeof(pifu_level_stats) / 4));
+  rc = pack_field(b.fps[0], ctx, s, b.counters);
+  if (rc) {
+    delete bp;
+    return rc;
+  }
+  for (int f = 1; f < n; ++f) {   // frames share the packed network
+    b.fps[f].mlp = b.fps[0].mlp;
+    b.fps[f].sur = b.fps[0].sur;
+  }
+  if (!b.fps[0].has_mlp)
+    for (int p = 0; p < n; ++p) launch_store_ellipsoids(b.ell_tab + p, b.fps[b.order[p]].ell, s);
+  const bool bounded = o.max_waves > 0;
+  const int budget = bounded ? o.max_waves : kDefaultWaveBudget;
+  uint32_t* n_dev = b.counters + C_TOTAL;
+  for (int r = 0; r <= b.Tmax && !rc; ++r) {
+    const Lat L = b.lat[r];
+    const int A = b.active[r];
+    const uint32_t nl = (uint32_t)L.n();
+    const uint32_t tot = nl * (uint32_t)A;
+    const int level_id = b.l0 + r;
+    fc.frames = A;
+    fc.frame_nodes = nl;
+    for (int p = 0; p < A; ++p) fc.st[p] = outs[b.order[p]].stats_dev + r;
+    launch_set_u32(b.counters, 0, s, C_OVF);   // keeps C_OVF
+    launch_set_u32(b.counters + C_SEG, 0, s, C_TALLY + kMaxFrames - C_SEG);
+    {
+      Book bk(s);
+      for (int p = 0; p < A; ++p) {
+        bk.add(BK_SET_IMM, reinterpret_cast<uint32_t*>(&fc.st[p]->level), nullptr,
+               (uint32_t)level_id);
+        bk.add(BK_SET_IMM, stat_word(fc.st[p], &pifu_level_stats::nodes), nullptr, nl);
+      }
+    }
+    FrameOcc fo{};
+    for (int p = 0; p < A; ++p)
+      if (b.T[b.order[p]] == r) fo.p[p] = outs[b.order[p]].occ;
+    PointSrc sall;
+    std::memset(&sall, 0, sizeof(sall));
+    sall.mode = 0;
+    sall.nx = L.nx;
+    sall.ny = L.ny;
+    sall.nz = L.nz;
+    sall.frame_nodes = nl;
+    for (int p = 0; p < A; ++p) sall.feat_tab[p] = b.fps[b.order[p]].f->feat;
+    if (r == 0) {
+      launch_fill_u8(b.st[0], 0, tot, s);
+      launch_iota(b.w.list, tot, s);
+      {
+        Book bk(s);
+        bk.add(BK_SET_IMM, b.aw + AW_N0, nullptr, tot);
+      }
+      rc = eval_frames_dev(e, b, sall, tot, b.aw + AW_N0);
+      if (rc) break;
+      launch_apply_grid(b.w.list, tot, b.w.logit, b.w.lab, b.st[0], b.occ[0], nullptr, nullptr,
+                        level_id, L, 1, L, 0, s, nl, &fo, nullptr, b.aw + AW_N0);
+      Book bk(s);
+      for (int p = 0; p < A; ++p) {
+        bk.add(BK_SET_IMM, stat_word(fc.st[p], &pifu_level_stats::dilated), nullptr, nl);
+        bk.add(BK_SET_IMM, stat_word(fc.st[p], &pifu_level_stats::evaluated), nullptr, nl);
+      }
+    } else {
+      launch_transition(b.st[r - 1], b.occ[r - 1], b.lat[r - 1], b.st[r], b.occ[r], L, s, A, &fo);
+      if (2 * b0_mask_words(L) * (size_t)A <= b.list_words) {
+        launch_select_b0(b.st[r], L, A, reinterpret_cast<uint64_t*>(b.w.list), b.counters + C_B0_F,
+                         1, s);
+      } else {
+        for (int p = 0; p < A; ++p)
+          launch_count_bits(b.st[r] + (size_t)p * nl, nl, ST_B0, b.counters + C_B0_F + p, s);
+        launch_select(b.st[r], L, s, A);
+      }
+      const uint32_t ecap = std::min(tot, cap);
+      launch_compact(b.st[r], tot, ST_PEND, ST_PEND, b.w.cscratch, n_dev, b.w.list, b.list_cap, 0,
+                     L, s);
+      count_frames(e, b.w.list, nullptr, ecap, n_dev, &pifu_level_stats::dilated, BK_SET);
+      {
+        Book bk(s);
+        bk.add(BK_FLAG_GT, b.aw + AW_STATUS, n_dev, cap, kStatusListOver);
+      }
+      for (int rung = 0; rung <= budget; ++rung) {
+        rc = eval_frames_dev(e, b, sall, ecap, n_dev);
+        if (rc) break;
+        launch_apply_grid(b.w.list, ecap, b.w.logit, b.w.lab, b.st[r], b.occ[r],
+                          b.counters + C_CONF_F, nullptr, level_id, L, 1, L, 1, s, nl, &fo, nullptr,
+                          n_dev);
+        count_frames(e, b.w.list, nullptr, ecap, n_dev, &pifu_level_stats::evaluated, BK_ADD,
+                     rung > 0 ? &pifu_level_stats::waves : nullptr, BK_ADD_NZ);
+        if (rung == budget && bounded) break;
+        launch_expand(b.w.list, ecap, b.st[r], L, s, nl, n_dev);
+        launch_compact(b.st[r], tot, ST_PEND, ST_PEND, b.w.cscratch, n_dev, b.w.list, b.list_cap,
+                       0, L, s, 0, n_dev);
+        Book bk(s);
+        if (rung < budget) bk.add(BK_FLAG_GT, b.aw + AW_STATUS, n_dev, cap, kStatusListOver);
+        else bk.add(BK_FLAG_GT, b.aw + AW_STATUS, n_dev, 0, kStatusWavesLeft);
+      }
+      if (rc) break;
+      Book bk(s);
+      for (int p = 0; p < A; ++p) {
+        bk.add(BK_SET, stat_word(fc.st[p], &pifu_level_stats::conflicts), b.counters + C_CONF_F + p);
+        bk.add(BK_SET, stat_word(fc.st[p], &pifu_level_stats::b0), b.counters + C_B0_F + p);
+      }
+    }
+    // frames whose final level this is: labels, cells and their count out
+    for (int p = 0; p < A; ++p) {
+      const int f = b.order[p];
+      if (b.T[f] != r) continue;
+      uint8_t* sf = b.st[r] + (size_t)p * nl;
+      launch_cells(sf, L, outs[f].labels, s);
+      launch_compact(sf, nl, ST_CELL, ST_CELL, b.w.cscratch, n_dev, outs[f].cells, outs[f].cells_cap,
+                     1, L, s);
+      Book bk(s);
+      bk.add(BK_SET, outs[f].n_cells_dev, n_dev);
+      bk.add(BK_FLAG_GT, b.aw + AW_STATUS, n_dev, outs[f].cells_cap, kStatusCellsOver);
+    }
+    if (!rc) rc = check_launch();
+  }
+  if (!rc) {
+    Book bk(s);
+    bk.add(BK_SET, status_dev, b.aw + AW_STATUS);
+  }
+  if (!rc) rc = check_launch();
+  delete bp;
+  return rc;
+}
+
+}  // extern "C"
+
+// ================================================================== mesh hand-off
+namespace {
+
+struct MeshWs {
+  uint32_t* counters = nullptr;
+  uint8_t* flags = nullptr;      // 3 per node: the lattice edge from the node crosses
+  uint32_t* ids = nullptr;       // crossed edge ids, sorted (one vertex each)
+  uint32_t* cscratch = nullptr;
+  int32_t* kf = nullptr;         // front node per input-view column
+  uint32_t *tcnt = nullptr, *toff = nullptr, *tscan = nullptr;
+  uint8_t* hidden = nullptr;     // per vertex: not visible from the input camera
+  uint32_t* hlist = nullptr;     // vertices coloured by the network
+  float4* pts = nullptr;         // per vertex (x, y, z, 0.5): the colour network's input
+  FieldPrep cp;
+  EvalWs ew;
+  size_t bytes = 0;
+};
+
+void plan_mesh(int L, uint32_t n_cells, uint32_t vert_cap, const pifu_field* col, void* base,
+               MeshWs& m) {
+  const size_t nn = ((size_t)1 << L) + 1, N = nn * nn * nn;
+  Carver cv(base);
+  m.counters = cv.take<uint32_t>(kCounters);
+  m.flags = cv.take<uint8_t>(3 * N + 16);
+  m.ids = cv.take<uint32_t>(std::max<uint32_t>(vert_cap, 1));
+  m.cscratch = cv.take<uint32_t>(std::max(compact_scratch_words(3 * N),
+                                          std::max(compact_scratch_words(vert_cap),
+                                                   scan_scratch_words(n_cells))));
+  m.kf = cv.take<int32_t>(nn * nn);
+  m.tcnt = cv.take<uint32_t>(std::max<uint32_t>(n_cells, 1));
+  m.toff = cv.take<uint32_t>(std::max<uint32_t>(n_cells, 1));
+  m.tscan = cv.take<uint32_t>(scan_scratch_words(std::max<uint32_t>(n_cells, 1)));
+  m.hidden = cv.take<uint8_t>((size_t)vert_cap + 16);
+  m.hlist = cv.take<uint32_t>(std::max<uint32_t>(vert_cap, 1));
+  m.pts = cv.take<float4>(std::max<uint32_t>(vert_cap, 1));
+  if (col) {
+    carve_field(cv, col, PIFU_PREC_FP32, m.cp);
+    carve_eval(cv, std::max<uint32_t>(vert_cap, 1), col->C, m.cp.mlp.max_hidden, m.ew);
+  }
+  m.bytes = cv.off + kAlign;
+}
+
+int validate_mesh(int L, uint32_t n_cells, const uint32_t* cells, const pifu_field* col,
+                  const float* image, int img_h, int img_w) {
+  if (L < 1 || L > 9) return PIFU_ERR_INVALID_ARGUMENT;
+  if (n_cells && !cells) return PIFU_ERR_INVALID_ARGUMENT;
+  if ((uint64_t)n_cells > ((uint64_t)1 << (3 * L))) return PIFU_ERR_INVALID_ARGUMENT;
+  if (col) {
+    if (col->kind != PIFU_FIELD_MLP) return PIFU_ERR_INVALID_ARGUMENT;
+    if (int r = validate_field(col, 2, 3)) return r;
+  }
+  if (image && (img_h < 2 || img_w < 2)) return PIFU_ERR_INVALID_ARGUMENT;
+  return PIFU_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t pifu_mesh_workspace_size(int32_t log2_final, uint32_t n_cells, uint32_t vert_cap,
+                                 const pifu_field* color_field, size_t* bytes) {
+  if (!bytes) return PIFU_ERR_INVALID_ARGUMENT;
+  static const uint32_t kNoCells = 0;   // the cell pointer is not needed for the size
+  if (int r = validate_mesh(log2_final, n_cells, &kNoCells, color_field, nullptr, 0, 0)) return r;
+  MeshWs m;
+  plan_mesh(log2_final, n_cells, vert_cap, color_field, nullptr, m);
+  *bytes = m.bytes;
+  return PIFU_OK;
+}
+
+int32_t pifu_mesh(pifu_ctx* ctx, int32_t log2_final, const float* occ, const uint8_t* labels,
+                  const uint32_t* cells, uint32_t n_cells, const pifu_field* color_field,
+                  const float* image, int32_t img_h, int32_t img_w, float* verts, float* colors,
+                  uint32_t vert_cap, uint32_t* n_verts, uint32_t* tris, uint32_t tri_cap,
+                  uint32_t* n_tris, void* workspace, size_t workspace_bytes, pifu_stream stream) {
+  if (!ctx || !occ || !labels || !n_verts || !n_tris || !workspace || !aligned(workspace, kAlign))
+    return PIFU_ERR_INVALID_ARGUMENT;
+  if ((vert_cap && !verts) || (tri_cap && !tris)) return PIFU_ERR_INVALID_ARGUMENT;
+  if (colors && !color_field) return PIFU_ERR_INVALID_ARGUMENT;
+  if (int r = validate_mesh(log2_final, n_cells, cells, color_field, image, img_h, img_w)) return r;
+  MeshWs m;
+  plan_mesh(log2_final, n_cells, vert_cap, colors ? color_field : nullptr, nullptr, m);
+  if (workspace_bytes < m.bytes) return PIFU_ERR_WORKSPACE_TOO_SMALL;
+  plan_mesh(log2_final, n_cells, vert_cap, colors ? color_field : nullptr, workspace, m);
+  hipStream_t s = as_stream(stream);
+  const int nn = (1 << log2_final) + 1;
+  const size_t N = (size_t)nn * nn * nn;
+  EvalCtx e{ctx, s, m.counters, PIFU_PREC_FP32, 0.f};
+  HIP_TRY(hipMemsetAsync(m.counters, 0, sizeof(uint32_t) * kCounters, s));
+  // vertices: the crossed lattice edges, in edge-id order
+  launch_mesh_edge_flags(labels, nn, m.flags, s);
+  uint32_t nv_all = 0;
+  Lat flat{1, 1, (int)std::min<size_t>(3 * N, INT32_MAX)};
+  int r = compact_count(e, m.flags, 3 * N, 1, 1, m.cscratch, m.ids, vert_cap, 0, flat, &nv_all);
+  if (r) return r;
+  const uint32_t nv = std::min(nv_all, vert_cap);
+  launch_mesh_front(labels, nn, m.kf, s);
+  launch_mesh_verts(m.ids, nv, occ, nn, m.kf, verts, colors ? m.hidden : nullptr,
+                    colors ? m.pts : nullptr, s);
+  // triangles: per-cell counts, offsets, then each cell's triangles
+  uint32_t nt_all = 0;
+  if (n_cells) {
+    launch_mesh_tri_count(cells, n_cells, labels, nn, m.tcnt, s);
+    launch_scan_u32(m.tcnt, n_cells, m.toff, m.tscan, m.counters + C_GUARD, s);
+    r = read_counters(e, C_GUARD + 1);
+    if (r) return r;
+    nt_all = ctx->host_counters[C_GUARD];
+    launch_mesh_tri_write(cells, n_cells, labels, nn, m.toff, m.ids, nv, tris, tri_cap, s);
+  }
+  // colours: the input pixel where visible, the colour network elsewhere
+  if (colors && nv) {
+    if (image) {
+      launch_mesh_pixel_colors(verts, m.hidden, nv, image, img_h, img_w, colors, s);
+    } else {
+      launch_fill_u8(m.hidden, 1, nv, s);
+    }
+    uint32_t nh = 0;
+    Lat vl{1, 1, (int)nv};
+    r = compact_count(e, m.hidden, nv, 1, 1, m.cscratch, m.hlist, nv, 0, vl, &nh);
+    if (r) return r;
+    if (nh) {
+      r = pack_field(m.cp, ctx, s, m.counters);
+      if (r) return r;
+      PointSrc ps;
+      std::memset(&ps, 0, sizeof(ps));
+      ps.mode = 1;
+      ps.pts = m.pts;
+      EvalCtx ec{ctx, s, m.counters, PIFU_PREC_FP32, 0.f};
+      r = run_mlp(ec, m.cp, m.cp.mlp, PIFU_PREC_FP32, ps, m.hlist, nh, m.ew, nullptr, nullptr,
+                  colors);
+      if (r) return r;
+    }
+  }
+  r = check_launch();
+  if (!r) r = hipStreamSynchronize(s) == hipSuccess ? PIFU_OK : PIFU_ERR_HIP;
+  *n_verts = nv_all;
+  *n_tris = nt_all;
+  prof_resolve(ctx);
   return r;
 }
 

@@ -145,9 +145,11 @@ void launch_segment_bounds(const uint32_t* list, uint32_t n, uint32_t frame_node
 // Stable compaction of the nodes whose state byte satisfies (st & mask) == val.
 // mode 0 writes node indices (plus index_base), mode 1 cell indices (i*(nx-1)+j)*(nz... of
 // lattice f).  st must be 16-byte aligned.
+// gate (device, nullable): when *gate is 0 at the start, nothing is selected and the
+// passes exit at once (total = 0); the gate may be the total word itself.
 void launch_compact(const uint8_t* st, size_t n, uint8_t mask, uint8_t val, uint32_t* bcount,
                     uint32_t* total, uint32_t* out, uint32_t cap, int mode, Lat f, hipStream_t s,
-                    uint32_t index_base = 0);
+                    uint32_t index_base = 0, const uint32_t* gate = nullptr);
 size_t compact_scratch_words(size_t n);
 void launch_apply_grid(const uint32_t* list, uint32_t n, const float* logit, const uint8_t* lab,
                        uint8_t* st, float* occ, uint32_t* conflicts, uint8_t* eval_level,
@@ -164,6 +166,20 @@ void launch_fill_i32(int32_t* p, int32_t v, size_t n, hipStream_t s);
 void launch_expand(const uint32_t* list, uint32_t n, uint8_t* st, Lat f, hipStream_t s,
                    uint32_t frame_nodes = 0, const uint32_t* n_dev = nullptr);
 void launch_cells(uint8_t* st, Lat f, uint8_t* labels, hipStream_t s);
+// Per-frame counts of a list over frames of frame_nodes nodes (tally[f] +=; pos: the
+// list positions to count, null for the first min(n, *n_dev) entries), then the stats
+// updates that read them (FrameApply; BK_ADD, BK_ADD_NZ or BK_SET per op), which also
+// clear the tally.
+void launch_frame_tally(const uint32_t* list, const uint32_t* pos, uint32_t n,
+                        const uint32_t* n_dev, uint32_t frame_nodes, uint32_t* tally,
+                        hipStream_t s);
+constexpr int kMaxFrameOps = 4;
+struct FrameApply {
+  int frames, nops;
+  int kind[kMaxFrameOps];
+  uint32_t* dst[kMaxFrameOps][kMaxBatch];
+};
+void launch_frame_apply(uint32_t* tally, const FrameApply& a, hipStream_t s);
 void launch_count_bits(const uint8_t* st, size_t n, uint8_t bit, uint32_t* out, hipStream_t s);
 // Octree-subdivision baselines: per coarse cell of lattice c, flags[cell] = subdivide
 // (mode PIFU_OCTREE_*, threshold thr), *count += subdivided cells; then the fine level's
@@ -176,9 +192,13 @@ void launch_oct_transition(const uint8_t* cst, const float* cocc, Lat c, const u
 // ------------------------------------------------------------------ evaluation kernels
 // List kernels below take an optional device-side count n_dev: the list then holds
 // min(n, *n_dev) entries (n is its capacity) and the grid strides over them.
+// ell_tab (device, nullable): with a multi-frame source, frame f's shapes are ell_tab[f].
 void launch_eval_analytic(const PointSrc& src, const uint32_t* list, uint32_t n, int kind,
                           const Ellipsoids& ell, const float plane[4], float* logit,
-                          uint8_t* lab, hipStream_t s, const uint32_t* n_dev = nullptr);
+                          uint8_t* lab, hipStream_t s, const uint32_t* n_dev = nullptr,
+                          const Ellipsoids* ell_tab = nullptr);
+// *dst = e, by a kernel (graph-capturable)
+void launch_store_ellipsoids(Ellipsoids* dst, const Ellipsoids& e, hipStream_t s);
 // Bilinear gather of C channels (Eq. 1's sampler) for points m in [0, n); writes
 // feat (n x C, in format feat_fmt: FMT_F32 / FMT_BF16 / FMT_F16) and ext (n x 4: z',
 // occ, clipped, 0).  n_dev (nullable): device-side point count <= n; the grid covers
@@ -215,7 +235,8 @@ void run_guard64(const PointSrc& src, const uint32_t* list, const uint32_t* glis
 void launch_ray_count(const uint8_t* stc, Lat c, int W, int H, int D, uint32_t* cnt,
                       uint32_t* kstar, uint32_t* shadow_total, hipStream_t s);
 void launch_scan_u32(const uint32_t* in, uint32_t n, uint32_t* out_excl, uint32_t* scratch,
-                     uint32_t* total, hipStream_t s, const uint32_t* n_dev = nullptr);
+                     uint32_t* total, hipStream_t s, const uint32_t* n_dev = nullptr,
+                     const uint32_t* gate = nullptr);
 size_t scan_scratch_words(size_t n);
 void launch_ray_list(const uint8_t* stc, Lat c, int W, int H, int D, const uint32_t* kstar,
                      const uint32_t* off, uint32_t* list, hipStream_t s);
@@ -334,6 +355,22 @@ void launch_pack_many(const PackJobs& jobs, hipStream_t s);
 }  // namespace pifu
 
 namespace pifu {
+// ------------------------------------------------------------------ mesh hand-off
+// Builds the Marching Cubes triangle table and copies it to the device's constant memory
+// (the current device); called by pifu_create.
+int mesh_table_upload();
+void launch_mesh_edge_flags(const uint8_t* labels, int nn, uint8_t* flags, hipStream_t s);
+void launch_mesh_front(const uint8_t* labels, int nn, int32_t* kf, hipStream_t s);
+void launch_mesh_verts(const uint32_t* ids, uint32_t nv, const float* occ, int nn, const int32_t* kf,
+                       float* verts, uint8_t* hidden, float4* pts, hipStream_t s);
+void launch_mesh_tri_count(const uint32_t* cells, uint32_t nc, const uint8_t* labels, int nn,
+                           uint32_t* cnt, hipStream_t s);
+void launch_mesh_tri_write(const uint32_t* cells, uint32_t nc, const uint8_t* labels, int nn,
+                           const uint32_t* off, const uint32_t* ids, uint32_t nv, uint32_t* tris,
+                           uint32_t tri_cap, hipStream_t s);
+void launch_mesh_pixel_colors(const float* verts, const uint8_t* hidden, uint32_t nv,
+                              const float* img, int H, int W, float* colors, hipStream_t s);
+
 // ------------------------------------------------------------------ handle helpers
 // The device a handle is bound to.
 int ctx_device(const pifu_ctx* c);
@@ -344,7 +381,15 @@ int noalloc_setup(int device);
 // ------------------------------------------------------------------ training kernels
 uint32_t bce_partials(uint32_t n);
 void launch_bce_grad(const float* s, const float4* pts, uint32_t n, float* g, float* loss_part,
-                     float* loss, hipStream_t st);
+                     float* loss, hipStream_t st, float* point_loss = nullptr);
+// point-OHEM: weighted draws (quantised weights, exact 64-bit prefix sums, SplitMix64)
+// and the weight update from per-point losses
+size_t ohem_workspace_bytes(uint32_t n);
+void launch_ohem_sample(const float* w, uint32_t n, const float4* pool, uint32_t batch,
+                        uint64_t seed, uint64_t counter, uint32_t* idx, float4* out, void* ws,
+                        hipStream_t s);
+void launch_ohem_update(const float* L, const uint32_t* idx, uint32_t batch, float alpha,
+                        float beta, float* w, hipStream_t s);
 void launch_weight_grad(const float* G, int N, const float* A1, int K1, int lda1, const float* A2,
                         int K2, int lda2, const float* ext, int n_ext, uint32_t M, float* part,
                         float* dW, float* db, hipStream_t st);

@@ -331,8 +331,9 @@ __device__ inline uint32_t wave_incl_scan(uint32_t v) {
 
 __global__ void __launch_bounds__(COMPACT_BLOCK)
 k_compact_count(const uint8_t* __restrict__ st, size_t n, uint8_t mask, uint8_t val,
-                uint32_t* __restrict__ bcount) {
+                uint32_t* __restrict__ bcount, const uint32_t* __restrict__ gate) {
   __shared__ uint32_t wsum[COMPACT_BLOCK / 64];
+  if (gate && *gate == 0) return;   // nothing can be selected: the scan writes total 0
   size_t base = (size_t)blockIdx.x * COMPACT_TILE + (size_t)threadIdx.x * COMPACT_PER_THREAD;
   uint32_t c = __popc(pred_mask16(st, base, n, mask, val));
   uint32_t inc = wave_incl_scan(c);
@@ -348,8 +349,13 @@ k_compact_count(const uint8_t* __restrict__ st, size_t n, uint8_t mask, uint8_t 
 // Exclusive scan of n words by one workgroup of 1024 threads; writes the total.
 __global__ void __launch_bounds__(1024)
 k_scan_small(const uint32_t* __restrict__ in, uint32_t n, uint32_t* __restrict__ out,
-             uint32_t* __restrict__ total, const uint32_t* __restrict__ n_dev = nullptr) {
+             uint32_t* __restrict__ total, const uint32_t* __restrict__ n_dev = nullptr,
+             const uint32_t* __restrict__ gate = nullptr) {
   __shared__ uint32_t wsum[16];
+  if (gate && *gate == 0) {   // gated compaction: nothing selected
+    if (threadIdx.x == 0 && total) *total = 0;
+    return;
+  }
   const uint32_t per = (n + 1023) / 1024;   // the capacity sets the split, the count the end
   if (n_dev) n = min(n, *n_dev);
   const uint32_t beg = threadIdx.x * per;
@@ -381,8 +387,9 @@ k_scan_small(const uint32_t* __restrict__ in, uint32_t n, uint32_t* __restrict__
 __global__ void __launch_bounds__(COMPACT_BLOCK)
 k_compact_write(const uint8_t* __restrict__ st, size_t n, uint8_t mask, uint8_t val,
                 const uint32_t* __restrict__ boff, uint32_t* __restrict__ out, uint32_t cap,
-                int mode, Lat f, uint32_t index_base) {
+                int mode, Lat f, uint32_t index_base, const uint32_t* __restrict__ total) {
   __shared__ uint32_t wsum[COMPACT_BLOCK / 64];
+  if (total && *total == 0) return;   // gated compaction with nothing selected
   size_t base = (size_t)blockIdx.x * COMPACT_TILE + (size_t)threadIdx.x * COMPACT_PER_THREAD;
   uint32_t m = pred_mask16(st, base, n, mask, val);
   uint32_t c = __popc(m);
@@ -421,29 +428,32 @@ size_t compact_scratch_words(size_t n) {
 
 void launch_compact(const uint8_t* st, size_t n, uint8_t mask, uint8_t val, uint32_t* bcount,
                     uint32_t* total, uint32_t* out, uint32_t cap, int mode, Lat f, hipStream_t s,
-                    uint32_t index_base) {
+                    uint32_t index_base, const uint32_t* gate) {
   uint32_t nb = (uint32_t)((n + COMPACT_TILE - 1) / COMPACT_TILE);
   if (nb == 0) {
     launch_set_u32(total, 0, s);
     return;
   }
   uint32_t* boff = bcount + nb;
-  hipLaunchKernelGGL(k_compact_count, dim3(nb), dim3(COMPACT_BLOCK), 0, s, st, n, mask, val, bcount);
+  hipLaunchKernelGGL(k_compact_count, dim3(nb), dim3(COMPACT_BLOCK), 0, s, st, n, mask, val, bcount,
+                     gate);
   // one workgroup scans up to a few thousand tile counts quickly; longer inputs (many
   // frames of a batch) take the multi-workgroup scan
   if (nb <= 8192)
-    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, bcount, nb, boff, total, nullptr);
+    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, bcount, nb, boff, total, nullptr,
+                       gate);
   else
-    launch_scan_u32(bcount, nb, boff, bcount + 2 * (size_t)nb, total, s);
+    launch_scan_u32(bcount, nb, boff, bcount + 2 * (size_t)nb, total, s, nullptr, gate);
   hipLaunchKernelGGL(k_compact_write, dim3(nb), dim3(COMPACT_BLOCK), 0, s, st, n, mask, val, boff,
-                     out, cap, mode, f, index_base);
+                     out, cap, mode, f, index_base, gate ? total : nullptr);
 }
 
 // ------------------------------------------------------------------ generic scan (render)
 __global__ void __launch_bounds__(1024)
 k_scan_tiles(const uint32_t* __restrict__ in, uint32_t n, uint32_t* __restrict__ tsum,
-             const uint32_t* __restrict__ n_dev) {
+             const uint32_t* __restrict__ n_dev, const uint32_t* __restrict__ gate) {
   __shared__ uint32_t wsum[16];
+  if (gate && *gate == 0) return;
   if (n_dev) n = min(n, *n_dev);
   uint32_t i = blockIdx.x * 1024 + threadIdx.x;
   uint32_t v = i < n ? in[i] : 0;
@@ -459,8 +469,11 @@ k_scan_tiles(const uint32_t* __restrict__ in, uint32_t n, uint32_t* __restrict__
 
 __global__ void __launch_bounds__(1024)
 k_scan_apply(const uint32_t* __restrict__ in, uint32_t n, const uint32_t* __restrict__ toff,
-             uint32_t* __restrict__ out, const uint32_t* __restrict__ n_dev) {
+             uint32_t* __restrict__ out, const uint32_t* __restrict__ n_dev,
+             const uint32_t* __restrict__ gate) {
   __shared__ uint32_t wsum[16];
+  // gated: the gate word may be the total the middle pass rewrote; 0 means no output
+  if (gate && *gate == 0) return;
   if (n_dev) n = min(n, *n_dev);
   uint32_t i = blockIdx.x * 1024 + threadIdx.x;
   uint32_t v = i < n ? in[i] : 0;
@@ -475,21 +488,22 @@ k_scan_apply(const uint32_t* __restrict__ in, uint32_t n, const uint32_t* __rest
 size_t scan_scratch_words(size_t n) { return (n + 1023) / 1024 * 2 + 64; }
 
 void launch_scan_u32(const uint32_t* in, uint32_t n, uint32_t* out_excl, uint32_t* scratch,
-                     uint32_t* total, hipStream_t s, const uint32_t* n_dev) {
+                     uint32_t* total, hipStream_t s, const uint32_t* n_dev, const uint32_t* gate) {
   uint32_t nt = (n + 1023) / 1024;
   if (nt == 0) {
     launch_set_u32(total, 0, s);
     return;
   }
   if (n <= 8192) {   // up to 8 words per thread: one workgroup, one launch
-    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, in, n, out_excl, total, n_dev);
+    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, in, n, out_excl, total, n_dev,
+                       gate);
     return;
   }
-  hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(1024), 0, s, in, n, scratch, n_dev);
+  hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(1024), 0, s, in, n, scratch, n_dev, gate);
   hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, scratch, nt, scratch + nt, total,
-                     nullptr);
+                     nullptr, gate);
   hipLaunchKernelGGL(k_scan_apply, dim3(nt), dim3(1024), 0, s, in, n, scratch + nt, out_excl,
-                     n_dev);
+                     n_dev, gate);
 }
 
 // ------------------------------------------------------------------ evaluation results
@@ -650,6 +664,59 @@ __global__ void k_segment_bounds(const uint32_t* __restrict__ list, uint32_t n,
 void launch_segment_bounds(const uint32_t* list, uint32_t n, uint32_t frame_nodes, int frames,
                            uint32_t* bounds, hipStream_t s) {
   hipLaunchKernelGGL(k_segment_bounds, dim3(1), dim3(64), 0, s, list, n, frame_nodes, frames, bounds);
+}
+
+// ------------------------------------------------------------------ per-frame tallies
+// tally[f] += entries m < min(n, *n_dev) whose node (list[pos[m]], or list[m] without
+// pos) lies in frame f = node / frame_nodes: a block histogram in LDS, then one atomic
+// per frame and block.
+__global__ void __launch_bounds__(256)
+k_frame_tally(const uint32_t* __restrict__ list, const uint32_t* __restrict__ pos, uint32_t n,
+              const uint32_t* __restrict__ n_dev, uint32_t frame_nodes, uint32_t* __restrict__ tally) {
+  __shared__ uint32_t h[kMaxBatch];
+  if (threadIdx.x < kMaxBatch) h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t ne = n_dev ? min(n, *n_dev) : n;
+  for (uint32_t m = blockIdx.x * blockDim.x + threadIdx.x; m < ne; m += gridDim.x * blockDim.x) {
+    const uint32_t node = list[pos ? pos[m] : m];
+    const uint32_t f = node / frame_nodes;
+    if (f < kMaxBatch) atomicAdd(&h[f], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < kMaxBatch && h[threadIdx.x]) atomicAdd(tally + threadIdx.x, h[threadIdx.x]);
+}
+
+void launch_frame_tally(const uint32_t* list, const uint32_t* pos, uint32_t n,
+                        const uint32_t* n_dev, uint32_t frame_nodes, uint32_t* tally,
+                        hipStream_t s) {
+  if (!n) return;
+  unsigned g = (unsigned)((n + 255) / 256);
+  if (g > kStrideBlocks) g = kStrideBlocks;
+  hipLaunchKernelGGL(k_frame_tally, dim3(g), dim3(256), 0, s, list, pos, n, n_dev, frame_nodes,
+                     tally);
+}
+
+// For frame p < a.frames and op q < a.nops: *a.dst[q][p] += tally[p] (ADD), += (tally[p]
+// != 0) (ADD_NZ) or = tally[p] (SET); then tally[0 .. kMaxBatch) = 0.  One block.
+__global__ void k_frame_apply(uint32_t* __restrict__ tally, FrameApply a) {
+  const int p = threadIdx.x;
+  uint32_t v = 0;
+  if (p < kMaxBatch) v = tally[p];
+  __syncthreads();
+  if (p < a.frames) {
+    for (int q = 0; q < a.nops; ++q) {
+      uint32_t* d = a.dst[q][p];
+      if (!d) continue;
+      if (a.kind[q] == BK_ADD) *d += v;
+      else if (a.kind[q] == BK_ADD_NZ) *d += v != 0;
+      else *d = v;
+    }
+  }
+  if (p < kMaxBatch) tally[p] = 0;
+}
+
+void launch_frame_apply(uint32_t* tally, const FrameApply& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_frame_apply, dim3(1), dim3(64), 0, s, tally, a);
 }
 
 // Final level: export the 0/1 labels and flag mixed cells (8 corner labels differ).

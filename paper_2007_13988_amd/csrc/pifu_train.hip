@@ -12,7 +12,7 @@ static inline unsigned grid1d(size_t n, int block) { return (unsigned)((n + bloc
 // g[m] = (sigmoid(s) - t) / n ; per-block partial sums of softplus(s) - t s.
 __global__ void __launch_bounds__(256)
 k_bce_grad(const float* __restrict__ s, const float4* __restrict__ pts, uint32_t n,
-           float* __restrict__ g, float* __restrict__ loss_part) {
+           float* __restrict__ g, float* __restrict__ loss_part, float* __restrict__ point_loss) {
   __shared__ float red[256];
   const uint32_t m = blockIdx.x * 256 + threadIdx.x;
   float l = 0.f;
@@ -22,6 +22,7 @@ k_bce_grad(const float* __restrict__ s, const float4* __restrict__ pts, uint32_t
     const float p = 1.f / (1.f + expf(-x));
     g[m] = (p - t) / (float)n;
     l = fmaxf(x, 0.f) - t * x + log1pf(expf(-fabsf(x)));
+    if (point_loss) point_loss[m] = l;
   }
   red[threadIdx.x] = l;
   __syncthreads();
@@ -196,10 +197,10 @@ __global__ void k_rmsprop(float* __restrict__ w, const float* __restrict__ g, fl
 uint32_t bce_partials(uint32_t n) { return (n + 255) / 256; }
 
 void launch_bce_grad(const float* s, const float4* pts, uint32_t n, float* g, float* loss_part,
-                     float* loss, hipStream_t st) {
+                     float* loss, hipStream_t st, float* point_loss) {
   if (!n) return;
   const uint32_t nb = bce_partials(n);
-  hipLaunchKernelGGL(k_bce_grad, dim3(nb), dim3(256), 0, st, s, pts, n, g, loss_part);
+  hipLaunchKernelGGL(k_bce_grad, dim3(nb), dim3(256), 0, st, s, pts, n, g, loss_part, point_loss);
   if (loss) hipLaunchKernelGGL(k_sum_ordered, dim3(1), dim3(64), 0, st, loss_part, nb, 1.f / n, loss);
 }
 

@@ -72,6 +72,11 @@ class PifuGridOut(C.Structure):
                 ("stats", C.POINTER(PifuLevelStats))]
 
 
+class PifuGridOutDev(C.Structure):
+    _fields_ = [("occ", C.c_void_p), ("labels", C.c_void_p), ("cells", C.c_void_p),
+                ("cells_cap", C.c_uint32), ("n_cells_dev", C.c_void_p), ("stats_dev", C.c_void_p)]
+
+
 class PifuGridCall(C.Structure):
     _fields_ = [("field", C.POINTER(PifuField)), ("opts", C.POINTER(PifuGridOpts)),
                 ("occ", C.c_void_p), ("labels", C.c_void_p), ("eval_level", C.c_void_p),
@@ -114,7 +119,10 @@ EXPORTS = ["pifu_create", "pifu_destroy", "pifu_status_string",
            "pifu_convert_f32", "pifu_grid_and_render", "pifu_render_view_traced", "pifu_fp8_calibrate",
            "pifu_occupancy_grid_async_workspace_size", "pifu_occupancy_grid_async",
            "pifu_render_view_async_workspace_size", "pifu_render_view_async",
-           "pifu_noalloc_scratch_bytes", "pifu_occupancy_grid_async_noalloc", "pifu_octree_grid"]
+           "pifu_noalloc_scratch_bytes", "pifu_occupancy_grid_async_noalloc", "pifu_octree_grid",
+           "pifu_occupancy_grid_batched_async_workspace_size", "pifu_occupancy_grid_batched_async",
+           "pifu_mlp_grad_ex", "pifu_ohem_sample_workspace_size", "pifu_ohem_sample",
+           "pifu_ohem_update", "pifu_mesh_workspace_size", "pifu_mesh"]
 
 _lib = None
 
@@ -160,6 +168,20 @@ def load_library():
     lib.pifu_octree_grid.argtypes = [P, C.POINTER(PifuField), C.POINTER(PifuGridOpts), i32,
                                      C.c_double, P, P, P, P, u32, C.POINTER(u32),
                                      C.POINTER(PifuLevelStats), P, sz, P]
+    lib.pifu_occupancy_grid_batched_async_workspace_size.argtypes = [i32, C.POINTER(C.c_void_p),
+                                                                     C.POINTER(C.c_void_p), u32,
+                                                                     C.POINTER(sz)]
+    lib.pifu_occupancy_grid_batched_async.argtypes = [P, i32, C.POINTER(C.c_void_p),
+                                                      C.POINTER(C.c_void_p), u32,
+                                                      C.POINTER(PifuGridOutDev), P, P, sz, P]
+    lib.pifu_mlp_grad_ex.argtypes = [P, C.POINTER(PifuField), P, u32, C.POINTER(C.c_void_p),
+                                     C.POINTER(C.c_void_p), P, P, P, sz, P]
+    lib.pifu_ohem_sample_workspace_size.argtypes = [u32, C.POINTER(sz)]
+    lib.pifu_ohem_sample.argtypes = [P, P, u32, P, u32, C.c_uint64, C.c_uint64, P, P, P, sz, P]
+    lib.pifu_ohem_update.argtypes = [P, P, P, u32, C.c_float, C.c_float, P, P]
+    lib.pifu_mesh_workspace_size.argtypes = [i32, u32, u32, C.POINTER(PifuField), C.POINTER(sz)]
+    lib.pifu_mesh.argtypes = [P, i32, P, P, P, u32, C.POINTER(PifuField), P, i32, i32, P, P, u32,
+                              C.POINTER(u32), P, u32, C.POINTER(u32), P, sz, P]
     lib.pifu_noalloc_scratch_bytes.argtypes = []
     lib.pifu_occupancy_grid_async_noalloc.argtypes = [P, C.POINTER(PifuField),
                                                       C.POINTER(PifuGridOpts), u32, P, P, P, P,
@@ -719,3 +741,125 @@ class BatchedGrid:
         return dict(occ=self.occ[i], labels=self.labels[i],
                     cells=self.cells[i][:min(nc, self.outs[i].cells_cap)], n_cells=nc,
                     stats=[s.as_dict() for s in self.stats[i]])
+
+
+class AsyncBatchedGrid:
+    """Outputs, device-side counts and workspace of pifu_occupancy_grid_batched_async.
+    run() only enqueues (graph-capturable); read results after the stream."""
+
+    def __init__(self, fields: Sequence[DeviceField], opts: Sequence[PifuGridOpts],
+                 max_points: int = 0, device="cuda"):
+        lib = load_library()
+        self.fields = list(fields)
+        self.opts = list(opts)
+        self.max_points = max_points
+        n = len(fields)
+        self._f = (C.c_void_p * n)(*[C.addressof(f.struct) for f in self.fields])
+        self._o = (C.c_void_p * n)(*[C.addressof(o) for o in self.opts])
+        sz = C.c_size_t()
+        _check(lib.pifu_occupancy_grid_batched_async_workspace_size(n, self._f, self._o,
+                                                                    max_points, C.byref(sz)),
+               "pifu_occupancy_grid_batched_async_workspace_size")
+        self.ws = torch.empty(sz.value, dtype=torch.uint8, device=device)
+        self.outs = (PifuGridOutDev * n)()
+        self.status = torch.zeros(1, dtype=torch.int32, device=device)
+        self.occ, self.labels, self.cells, self.words = [], [], [], []
+        for i, o in enumerate(self.opts):
+            m = (1 << o.log2_final) + 1
+            occ = torch.empty((m, m, m), dtype=torch.float32, device=device)
+            lab = torch.empty((m, m, m), dtype=torch.uint8, device=device)
+            cap = min((m - 1) ** 3, 1 << 26)
+            cells = torch.empty(cap, dtype=torch.int32, device=device)
+            nlev = o.log2_final - o.log2_coarse + 1
+            words = torch.zeros(1 + nlev * STATS_WORDS, dtype=torch.int32, device=device)
+            self.occ.append(occ)
+            self.labels.append(lab)
+            self.cells.append(cells)
+            self.words.append(words)
+            self.outs[i].occ = occ.data_ptr()
+            self.outs[i].labels = lab.data_ptr()
+            self.outs[i].cells = cells.data_ptr()
+            self.outs[i].cells_cap = cap
+            self.outs[i].n_cells_dev = words.data_ptr()
+            self.outs[i].stats_dev = words.data_ptr() + 4
+
+    def run(self, stream=None):
+        st = load_library().pifu_occupancy_grid_batched_async(
+            context(), len(self.fields), self._f, self._o, self.max_points, self.outs,
+            self.status.data_ptr(), self.ws.data_ptr(), self.ws.numel(), _stream(stream))
+        _check(st, "pifu_occupancy_grid_batched_async")
+
+    def result(self, i):
+        nc = int(self.words[i][0].item())
+        return dict(occ=self.occ[i], labels=self.labels[i],
+                    cells=self.cells[i][:min(nc, self.outs[i].cells_cap)], n_cells=nc,
+                    stats=stats_from_device(self.words[i][1:]),
+                    status=int(self.status[0].item()))
+
+
+class OhemSampler:
+    """Point-OHEM (Sec. 3.3, Eq. 6 right) over a pool of training points: stored inverse
+    probabilities (initially 1), weighted draws (pifu_ohem_sample) and the update from
+    per-point losses (pifu_ohem_update)."""
+
+    def __init__(self, pool: torch.Tensor, batch: int, seed: int = 0, alpha: float = 0.7,
+                 beta: float = 0.0):
+        lib = load_library()
+        assert pool.dtype == torch.float32 and pool.shape[1] == 4 and pool.is_contiguous()
+        self.pool, self.batch, self.seed = pool, batch, seed
+        self.alpha, self.beta = alpha, beta
+        n = pool.shape[0]
+        self.weights = torch.ones(n, dtype=torch.float32, device=pool.device)
+        self.idx = torch.empty(batch, dtype=torch.int32, device=pool.device)
+        self.pts = torch.empty((batch, 4), dtype=torch.float32, device=pool.device)
+        sz = C.c_size_t()
+        _check(lib.pifu_ohem_sample_workspace_size(n, C.byref(sz)), "pifu_ohem_sample_workspace_size")
+        self.ws = torch.empty(sz.value, dtype=torch.uint8, device=pool.device)
+        self.counter = 0
+
+    def draw(self, stream=None) -> torch.Tensor:
+        st = load_library().pifu_ohem_sample(
+            context(), self.weights.data_ptr(), self.pool.shape[0], self.pool.data_ptr(),
+            self.batch, self.seed, self.counter, self.idx.data_ptr(), self.pts.data_ptr(),
+            self.ws.data_ptr(), self.ws.numel(), _stream(stream))
+        _check(st, "pifu_ohem_sample")
+        self.counter += 1
+        return self.pts
+
+    def update(self, point_loss: torch.Tensor, stream=None) -> None:
+        st = load_library().pifu_ohem_update(context(), point_loss.data_ptr(), self.idx.data_ptr(),
+                                             self.batch, self.alpha, self.beta,
+                                             self.weights.data_ptr(), _stream(stream))
+        _check(st, "pifu_ohem_update")
+
+
+def mesh(occ: torch.Tensor, labels: torch.Tensor, cells: torch.Tensor,
+         color_field: Optional[DeviceField] = None, image: Optional[torch.Tensor] = None,
+         vert_cap: Optional[int] = None, tri_cap: Optional[int] = None,
+         stream=None) -> Dict[str, object]:
+    """Marching Cubes over the surface cells (pifu_mesh): vertices, triangles and, with a
+    colour field, vertex colours (the input pixel where visible when an image is given)."""
+    lib = load_library()
+    n = occ.shape[0]
+    L = (n - 1).bit_length() - 1
+    nc = int(cells.numel())
+    vcap = vert_cap if vert_cap is not None else max(4 * nc, 16)
+    tcap = tri_cap if tri_cap is not None else max(5 * nc, 16)
+    fs = C.byref(color_field.struct) if color_field is not None else None
+    sz = C.c_size_t()
+    _check(lib.pifu_mesh_workspace_size(L, nc, vcap, fs, C.byref(sz)), "pifu_mesh_workspace_size")
+    ws = torch.empty(sz.value, dtype=torch.uint8, device=occ.device)
+    verts = torch.empty((vcap, 3), dtype=torch.float32, device=occ.device)
+    colors = torch.empty((vcap, 3), dtype=torch.float32, device=occ.device) if color_field is not None else None
+    tris = torch.empty((tcap, 3), dtype=torch.int32, device=occ.device)
+    nv, nt = C.c_uint32(), C.c_uint32()
+    img = image.contiguous() if image is not None else None
+    st = lib.pifu_mesh(context(), L, occ.data_ptr(), labels.data_ptr(),
+                       cells.data_ptr() if nc else None, nc, fs, _ptr(img),
+                       img.shape[0] if img is not None else 0, img.shape[1] if img is not None else 0,
+                       verts.data_ptr(), _ptr(colors), vcap, C.byref(nv), tris.data_ptr(), tcap,
+                       C.byref(nt), ws.data_ptr(), ws.numel(), _stream(stream))
+    _check(st, "pifu_mesh")
+    v, t = nv.value, nt.value
+    return dict(verts=verts[:min(v, vcap)], colors=colors[:min(v, vcap)] if colors is not None else None,
+                tris=tris[:min(t, tcap)], n_verts=v, n_tris=t)

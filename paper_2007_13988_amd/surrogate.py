@@ -32,13 +32,13 @@ def full_mlp_points(stats: Sequence[Dict[str, int]]) -> int:
 
 def distill(teacher_spec, student_spec, feats_train: Sequence[np.ndarray], samples_per_frame: int,
             steps: int = 4000, batch: int = 65536, seed: int = 0, lr: float = 3e-3,
-            lr_final: float = 1e-4):
+            lr_final: float = 1e-4, ohem: bool = False):
     """Trains student_spec (in place on the GPU) against teacher_spec; returns the
-    DeviceMLP of the student and the logged losses."""
+    DeviceMLP of the student and the logged losses.  ohem: point-OHEM sampling."""
     data = make_distill_data(teacher_spec, feats_train, samples_per_frame, seed)
     net = P.DeviceMLP(student_spec)
     tr, losses = train_surrogate(net, data, steps=steps, batch=batch, lr=lr, lr_final=lr_final,
-                                 seed=seed, log_every=max(1, steps // 50))
+                                 seed=seed, log_every=max(1, steps // 50), ohem=ohem)
     del data
     return net, losses
 

@@ -41,8 +41,10 @@ class MLPTrainer:
     def _field(self, feat: torch.Tensor) -> P.DeviceField:
         return P.DeviceField(P.FIELD_MLP, feat=feat, mlp=self.net)
 
-    def grad(self, feat: torch.Tensor, pts4: torch.Tensor, stream=None) -> torch.Tensor:
-        """pts4: device float32 (n, 4) = (x, y, z, teacher p).  Fills self.dW/self.db."""
+    def grad(self, feat: torch.Tensor, pts4: torch.Tensor, stream=None,
+             point_loss: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """pts4: device float32 (n, 4) = (x, y, z, teacher p).  Fills self.dW/self.db (and
+        point_loss, device float32 (n,), with every point's BCE when given)."""
         lib = P.load_library()
         fld = self._field(feat)
         n = pts4.shape[0]
@@ -52,11 +54,19 @@ class MLPTrainer:
             P._check(lib.pifu_mlp_train_workspace_size(C.byref(fld.struct), self.max_batch,
                                                        C.byref(sz)), "train_workspace_size")
             self.ws = torch.empty(sz.value, dtype=torch.uint8, device="cuda")
-        st = lib.pifu_mlp_grad(P.context(), C.byref(fld.struct), pts4.data_ptr(), n, self._dW,
-                               self._db, self.loss.data_ptr(), self.ws.data_ptr(),
-                               self.ws.numel(), P._stream(stream))
-        P._check(st, "pifu_mlp_grad")
+        st = lib.pifu_mlp_grad_ex(P.context(), C.byref(fld.struct), pts4.data_ptr(), n, self._dW,
+                                  self._db, self.loss.data_ptr(),
+                                  point_loss.data_ptr() if point_loss is not None else None,
+                                  self.ws.data_ptr(), self.ws.numel(), P._stream(stream))
+        P._check(st, "pifu_mlp_grad_ex")
         return self.loss
+
+    def point_loss(self, feat: torch.Tensor, pts4: torch.Tensor, stream=None) -> torch.Tensor:
+        """Every point's soft-target BCE under the current weights (gradients are filled
+        as a side effect)."""
+        out = torch.empty(pts4.shape[0], dtype=torch.float32, device="cuda")
+        self.grad(feat, pts4, stream, point_loss=out)
+        return out
 
     def step(self, stream=None) -> None:
         lib = P.load_library()
@@ -150,21 +160,36 @@ def make_distill_data(teacher_spec, feats_np: Sequence[np.ndarray], per_frame: i
 
 
 def train_surrogate(net: P.DeviceMLP, data: DistillData, steps: int = 4000, batch: int = 65536,
-                    lr: float = 3e-3, lr_final: float = 1e-4, seed: int = 0, log_every: int = 0):
+                    lr: float = 3e-3, lr_final: float = 1e-4, seed: int = 0, log_every: int = 0,
+                    ohem: bool = False, ohem_alpha: float = 0.7, ohem_beta: float = 0.0):
     """RMSProp on the soft-target BCE.  Step s draws a batch (with replacement) from
-    frame s mod n_frames; the learning rate follows a cosine from lr to lr_final."""
+    frame s mod n_frames; the learning rate follows a cosine from lr to lr_final.
+    ohem: point-OHEM (Sec. 3.3, Eq. 6 right) -- each frame's points are drawn with
+    probability proportional to 1 / (exp(-L / alpha) + beta) of their last loss L (1
+    before a point is first drawn), in libpifu's kernels; else uniformly."""
     import math
+    from .pifu import OhemSampler
     tr = MLPTrainer(net, batch, lr=lr)
     g = torch.Generator(device="cuda")
     g.manual_seed(seed)
     losses = []
     nf = len(data.samples)
+    samplers = [OhemSampler(smp, min(batch, smp.shape[0]), seed=seed * 1000 + f,
+                            alpha=ohem_alpha, beta=ohem_beta)
+                for f, smp in enumerate(data.samples)] if ohem else None
+    pl = torch.empty(batch, dtype=torch.float32, device="cuda") if ohem else None
     for step in range(steps):
         tr.lr = lr_final + 0.5 * (lr - lr_final) * (1.0 + math.cos(math.pi * step / max(steps, 1)))
         f = step % nf
         smp = data.samples[f]
-        sel = torch.randint(0, smp.shape[0], (min(batch, smp.shape[0]),), generator=g, device="cuda")
-        loss = tr.grad(data.feats[f], smp[sel].contiguous())
+        if ohem:
+            pts = samplers[f].draw()
+            loss = tr.grad(data.feats[f], pts, point_loss=pl)
+            samplers[f].update(pl)
+        else:
+            sel = torch.randint(0, smp.shape[0], (min(batch, smp.shape[0]),), generator=g,
+                                device="cuda")
+            loss = tr.grad(data.feats[f], smp[sel].contiguous())
         tr.step()
         if log_every and (step + 1) % log_every == 0:
             losses.append(float(loss.item()))

@@ -267,3 +267,53 @@ def precision_points(n: int, seed: int = 403) -> np.ndarray:
 def jitter_points(base: np.ndarray, spacing: float, seed: int) -> np.ndarray:
     g = rng(seed)
     return base + g.uniform(-0.5 * spacing, 0.5 * spacing, base.shape)
+
+
+@dataclass
+class CBNSpec:
+    """Weights of the conditional-batch-norm lifting network with soft one-hot depth
+    (appendix, "Depth Representation" and "Pixel-aligned 3D Lifting"): a first layer from
+    the n_z-channel depth code to `width`, n_blocks blocks of [linear layer (the first one
+    is the depth layer), conditional batch norm whose scale and shift are linear maps of
+    the pixel-aligned feature, ReLU], and a linear head.  Everything float32."""
+    feat_dim: int
+    n_z: int
+    width: int
+    n_blocks: int
+    Wp: np.ndarray              # [width][n_z]
+    bp: np.ndarray
+    W: List[np.ndarray]         # blocks 1 .. n_blocks-1: [width][width]
+    b: List[np.ndarray]
+    Wg: List[np.ndarray]        # per block [width][feat_dim]: scale gamma(c)
+    bg: List[np.ndarray]
+    Wb: List[np.ndarray]        # per block [width][feat_dim]: shift beta(c)
+    bb: List[np.ndarray]
+    mean: List[np.ndarray]      # per block running mean [width]
+    var: List[np.ndarray]       # per block running variance [width]
+    Wo: np.ndarray              # [1][width]
+    bo: np.ndarray              # [1]
+    eps: float = 1e-5
+
+
+def cbn_net(feat_dim: int = 256, n_z: int = 64, width: int = 128, n_blocks: int = 5,
+            seed: int = 212) -> CBNSpec:
+    """He-initialised linear layers; gamma(c) = 1 + a small linear map of c, beta(c) a
+    linear map of c; running statistics near (0, 1); a zero-mean head."""
+    g = rng(seed)
+    f32 = np.float32
+
+    def lin(o, i, std):
+        return (g.standard_normal((o, i)) * std).astype(f32)
+
+    W = [lin(width, width, np.sqrt(2.0 / width)) for _ in range(n_blocks - 1)]
+    return CBNSpec(
+        feat_dim, n_z, width, n_blocks,
+        Wp=lin(width, n_z, np.sqrt(2.0)), bp=np.zeros(width, f32),
+        W=W, b=[np.zeros(width, f32) for _ in W],
+        Wg=[lin(width, feat_dim, 0.1 / np.sqrt(feat_dim)) for _ in range(n_blocks)],
+        bg=[np.ones(width, f32) for _ in range(n_blocks)],
+        Wb=[lin(width, feat_dim, 1.0 / np.sqrt(feat_dim)) for _ in range(n_blocks)],
+        bb=[np.zeros(width, f32) for _ in range(n_blocks)],
+        mean=[(g.standard_normal(width) * 0.1).astype(f32) for _ in range(n_blocks)],
+        var=[g.uniform(0.5, 1.5, width).astype(f32) for _ in range(n_blocks)],
+        Wo=lin(1, width, np.sqrt(1.0 / width)), bo=np.zeros(1, f32))

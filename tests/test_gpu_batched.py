@@ -58,7 +58,7 @@ def test_tile_choice_never_changes_results(pifu, prec):
     spec = synth.pifu_mlp()
     fld = pifu.DeviceField.mlp_field(feat, spec)
     ref = pifu.occupancy_grid(fld, 6, 4, precision=prec, tile_m=128)
-    for t in (32, 64, 256):
+    for t in (32, 64, 96, 256):
         o = pifu.occupancy_grid(fld, 6, 4, precision=prec, tile_m=t)
         assert torch.equal(o["labels"], ref["labels"]) and torch.equal(o["occ"], ref["occ"]), t
     chosen = PP.autotune(fld, prec, batch_sizes=(4096, 16384))
