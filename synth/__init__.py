@@ -296,9 +296,10 @@ class CBNSpec:
 
 
 def cbn_net(feat_dim: int = 256, n_z: int = 64, width: int = 128, n_blocks: int = 5,
-            seed: int = 212) -> CBNSpec:
+            seed: int = 212, out_bias: float = -2.5) -> CBNSpec:
     """He-initialised linear layers; gamma(c) = 1 + a small linear map of c, beta(c) a
-    linear map of c; running statistics near (0, 1); a zero-mean head."""
+    linear map of c; running statistics near (0, 1); a random head whose constant bias
+    (a fixed input, -2.5 by default) puts the surface inside the volume."""
     g = rng(seed)
     f32 = np.float32
 
@@ -316,4 +317,4 @@ def cbn_net(feat_dim: int = 256, n_z: int = 64, width: int = 128, n_blocks: int 
         bb=[np.zeros(width, f32) for _ in range(n_blocks)],
         mean=[(g.standard_normal(width) * 0.1).astype(f32) for _ in range(n_blocks)],
         var=[g.uniform(0.5, 1.5, width).astype(f32) for _ in range(n_blocks)],
-        Wo=lin(1, width, np.sqrt(1.0 / width)), bo=np.zeros(1, f32))
+        Wo=lin(1, width, np.sqrt(1.0 / width)), bo=np.full(1, out_bias, f32))
