@@ -80,6 +80,8 @@ def parse():
                          "(keeps training kernels out of a profiled run)")
     ap.add_argument("--batched", action="store_true",
                     help="also time 16-frame batched occupancy grids against one call per frame")
+    ap.add_argument("--no-ohem", action="store_true",
+                    help="skip the point-OHEM against uniform distillation comparison")
     ap.add_argument("--no-graph-batch", action="store_true",
                     help="skip the 16-frame batches captured into one HIP graph")
     ap.add_argument("--no-baselines", action="store_true",
@@ -273,6 +275,47 @@ def batched_bench(P, synth, steps):
     return res
 
 
+def ohem_distillation(P, synth, args):
+    """Point-OHEM (Sec. 3.3, Eq. 6 right) against uniform sampling in the surrogate's
+    distillation: the same frames, samples, steps and schedule; reported on a held-out
+    frame's samples (the coarse-level nodes the pipeline evaluates, plus uniform points):
+    mean BCE, mean BCE of the hardest 10%, and the surrogate+BF16 grid's full-network
+    fallback points and surface-cell disagreement with FP32 at delta_s = 0.3."""
+    import torch
+    from paper_2007_13988_amd.surrogate import cell_disagreement, distill
+    from paper_2007_13988_amd.train import MLPTrainer, make_distill_data
+
+    teacher = synth.pifu_mlp()
+    frames = [synth.pifu_sequence(102, -t) for t in range(1, args.train_frames + 1)]
+    held_F = synth.pifu_sequence(102, -(args.train_frames + 1))
+    held = make_distill_data(teacher, [held_F], 262144, seed=99)
+    ref = P.occupancy_grid(P.DeviceField.mlp_field(held_F, teacher), 8, 5)["cells"].clone()
+    out = {}
+    for name, ohem in (("uniform", False), ("point_ohem", True)):
+        t0 = time.perf_counter()
+        net, losses = distill(teacher, synth.surrogate_mlp(), frames,
+                              samples_per_frame=args.train_samples, steps=args.train_steps,
+                              seed=0, ohem=ohem)
+        t_train = time.perf_counter() - t0
+        tr = MLPTrainer(net, held.samples[0].shape[0])
+        pl = tr.point_loss(held.feats[0], held.samples[0])
+        hard = torch.topk(pl, pl.numel() // 10).values
+        fld = P.DeviceField(P.FIELD_MLP, feat=held_F, mlp=P.DeviceMLP(teacher), surrogate=net)
+        g = P.occupancy_grid(fld, 8, 5, precision="bf16", band_delta=0.02, surrogate_max_log2=5,
+                             surrogate_delta=0.3)
+        out[name] = {"train_s": round(t_train, 2),
+                     "held_out_bce": round(float(pl.mean().item()), 5),
+                     "held_out_bce_hardest_10pct": round(float(hard.mean().item()), 5),
+                     "surrogate_fallback_points": sum(x["surrogate_fallback"] for x in g["stats"]),
+                     "full_mlp_points": sum(x["mlp_points"] for x in g["stats"]),
+                     "cell_disagreement_vs_fp32": cell_disagreement(g["cells"], ref)}
+        del net, tr, fld, g
+        torch.cuda.empty_cache()
+    out["note"] = ("alpha_p = 0.7, beta_p = 0; weights start at 1; draws with replacement "
+                   "proportional to the stored inverse probabilities (pifu_ohem_sample)")
+    return out
+
+
 def graph_batch_bench(P, synth, reps=3):
     """The batching workload in one captured HIP graph (pifu_occupancy_grid_batched_async:
     one set of launches per level and wave over every frame's combined list, no host
@@ -377,6 +420,61 @@ def baselines(P, synth, ms_grid_fp32, args):
         "note": "He-init weights without the depth-slab units: a surface extruded through "
                 "the whole depth (poor stand-in for a body), same arithmetic per point"}
     del gh, rh
+    torch.cuda.empty_cache()
+    return res
+
+
+def cbn_and_mesh(P, synth, feat, t_net, col_field, reps=5):
+    """The appendix's CBN + SoftZ network on the benchmarked grid (256^3 from 32^3, FP32,
+    same 256-channel features), and the mesh hand-off (Marching Cubes with vertex colours)
+    of the plain FP32 frame's grid."""
+    import numpy as np
+    import torch
+
+    def timed(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / n * 1e3
+
+    res = {}
+    spec = synth.cbn_net()
+    cf = P.DeviceField.cbn_field(feat, spec)
+    out = P.GridOutputs(cf, P.grid_opts(8, 5))
+    ms = timed(lambda: P.occupancy_grid_into(cf, out), reps)
+    pts = sum(s.mlp_points for s in out.stats)
+    w, c, nz, nb = spec.width, spec.feat_dim, spec.n_z, spec.n_blocks
+    flop_pt = 2 * nz * w + 2 * w * w * (nb - 1) + nb * 2 * (2 * c * w) + 2 * w
+    res["cbn_grid_256_from_32_fp32"] = {
+        "ms": round(ms, 3), "mlp_points": pts,
+        "evaluated_points": sum(s.evaluated for s in out.stats),
+        "surface_cells": int(out.n_cells.value),
+        "flop_per_point_unhoisted": flop_pt,
+        "gflop_per_4096_calls": round(flop_pt * 4096 / 1e9, 3),
+        "algorithmic_tflop_per_s": round(pts * flop_pt / (ms * 1e-3) / 1e12, 2),
+        "network": f"SoftZ n_z={nz} -> {nb} CBN blocks of width {w} conditioned on {c} "
+                   "channels -> 1, gamma/beta hoisted per (x, y) column",
+        "note": "algorithmic rate counts every point's unhoisted FLOPs (Tab. 2's formulation)"}
+    del out
+    fld = P.DeviceField(P.FIELD_MLP, feat=feat, mlp=t_net)
+    g = P.occupancy_grid(fld, 8, 5)
+    img = torch.from_numpy(np.tanh(synth.feature_map(512, 512, 3, 8.0, 9)).astype(np.float32)).cuda()
+    m = {}
+
+    def run_mesh():
+        m.update(P.mesh(g["occ"], g["labels"], g["cells"], col_field, img))
+
+    ms_c = timed(run_mesh, reps)
+    ms_g = timed(lambda: P.mesh(g["occ"], g["labels"], g["cells"]), reps)
+    res["mesh_256_fp32_frame"] = {
+        "ms_with_colors": round(ms_c, 3), "ms_geometry_only": round(ms_g, 3),
+        "surface_cells": g["n_cells"], "vertices": m["n_verts"], "triangles": m["n_tris"],
+        "note": "blocking pifu_mesh on the FP32 frame's grid; colours from a 512x512 "
+                "synthetic input image where visible, else the colour MLP at occupancy 0.5"}
+    del g, m
     torch.cuda.empty_cache()
     return res
 
@@ -703,12 +801,17 @@ def main():
         out["baselines"] = baselines(P, synth, main_r["ms_occ"], args)
         log("octree trade-off")
         out["octree_tradeoff"] = octree_tradeoff(P, synth)
+        log("CBN network and mesh hand-off")
+        out["cbn_and_mesh"] = cbn_and_mesh(P, synth, feat, t_net, col_field)
     if args.batched:
         log("batched")
         out["batched"] = batched_bench(P, synth, max(1, min(args.steps, 3)))
     if not args.no_graph_batch:
         log("graph-captured batch")
         out["graph_batch"] = graph_batch_bench(P, synth)
+    if not args.no_ohem:
+        log("point-OHEM distillation")
+        out["ohem_distillation"] = ohem_distillation(P, synth, args)
     if not args.no_cpu:
         # the plain FP32 frame's labels and recorded render logits for the oracle's
         # level-logic replay

@@ -49,6 +49,8 @@ extern "C" {
 #define PIFU_FIELD_MLP 0          /* Eq. 1: MLP over bilinearly sampled features */
 #define PIFU_FIELD_ELLIPSOIDS 1   /* analytic stand-in: k (1 - min_i |M_i (P - c_i)|^2) */
 #define PIFU_FIELD_PLANE 2        /* analytic stand-in: a x + b y + c z + d */
+#define PIFU_FIELD_CBN 3          /* the appendix's lifting network: soft one-hot depth code and
+                                     conditional batch norm on the sampled feature (pifu_cbn) */
 
 #define PIFU_ACT_RELU 1
 #define PIFU_ACT_LRELU 2          /* LeakyReLU, negative slope 0.01 */
@@ -94,6 +96,39 @@ typedef struct pifu_mlp {
 } pifu_mlp;
 
 /*
+ * The conditional-batch-norm lifting network with soft one-hot depth (appendix, "Depth
+ * Representation" and "Pixel-aligned 3D Lifting"; Tab. 2, HRNet-CBN-SoftZ).  With
+ * c = Phi(P_xy) the sampled feature (feat_dim channels) and Z the soft one-hot code of
+ * P_z (n_z channels: with s = (n_z - 1)(P_z + 1)/2, Z[floor s] = 1 + floor s - s,
+ * Z[floor s + 1] = s - floor s; the code is defined for -1 <= P_z <= 1 and a depth
+ * outside is clamped to that interval):
+ *   h_0 = Wp Z + bp;  for block i = 0 .. n_blocks-1 (h_i = W[i-1] a_{i-1} + b[i-1] for
+ *   i >= 1):  a_i = relu(gamma_i(c) (h_i - mean[i]) / sqrt(var[i] + eps) + beta_i(c)),
+ *   gamma_i(c) = Wg[i] c + bg[i], beta_i(c) = Wb[i] c + bb[i];  logit = Wo a_last + bo.
+ * (Batch norm with its running statistics.)  Device float32 arrays, row-major
+ * [out][in], 16-byte aligned: Wp [width][n_z], W[i] [width][width], Wg[i] and Wb[i]
+ * [width][feat_dim], Wo [1][width]; vectors of width (bo: 1).  Supported: width % 64 == 0
+ * and <= 512, feat_dim % 32 == 0 and <= 512, 2 <= n_z <= 256, 1 <= n_blocks <= 8.
+ */
+#define PIFU_CBN_MAX_BLOCKS 8
+typedef struct pifu_cbn {
+  int32_t feat_dim, n_z, width, n_blocks;
+  float eps;
+  const float* Wp;
+  const float* bp;
+  const float* W[PIFU_CBN_MAX_BLOCKS];
+  const float* b[PIFU_CBN_MAX_BLOCKS];
+  const float* Wg[PIFU_CBN_MAX_BLOCKS];
+  const float* bg[PIFU_CBN_MAX_BLOCKS];
+  const float* Wb[PIFU_CBN_MAX_BLOCKS];
+  const float* bb[PIFU_CBN_MAX_BLOCKS];
+  const float* mean[PIFU_CBN_MAX_BLOCKS];
+  const float* var[PIFU_CBN_MAX_BLOCKS];
+  const float* Wo;
+  const float* bo;
+} pifu_cbn;
+
+/*
  * An occupancy (or colour) field.  For PIFU_FIELD_MLP: feat (device, HWC float32,
  * H x W x C with C == mlp->feat_dim) and mlp (host struct) are required;
  * surrogate (host struct, nullable) is a cheaper MLP over the same features used
@@ -113,6 +148,9 @@ typedef struct pifu_field {
   float sharpness;
   const float* ell;
   float plane[4];
+  const pifu_cbn* cbn;      /* PIFU_FIELD_CBN (host struct): the network; feat as for MLP fields.
+                               Supported by pifu_occupancy_grid, pifu_octree_grid and
+                               pifu_eval_points in PIFU_PREC_FP32 */
 } pifu_field;
 
 /* Per-level counters (Sec. 3.2 steps), written to host memory by the calls. */

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpifu.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["pifu_level.hip", "pifu_octree.hip", "pifu_eval.hip", "pifu_gemm.hip", "pifu_fp64.hip", "pifu_train.hip", "pifu_ohem.hip", "pifu_mesh.hip",
+SOURCES = ["pifu_level.hip", "pifu_octree.hip", "pifu_eval.hip", "pifu_gemm.hip", "pifu_fp64.hip", "pifu_train.hip", "pifu_ohem.hip", "pifu_mesh.hip", "pifu_cbn.hip",
            "pifu_host.hip", "pifu_noalloc.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-shared", "-std=c++17",

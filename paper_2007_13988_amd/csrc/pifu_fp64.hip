@@ -316,4 +316,106 @@ void run_guard64(const PointSrc& src, const uint32_t* list, const uint32_t* glis
   }
 }
 
+// ------------------------------------------------------------------ CBN network guard
+// One workgroup per guarded point evaluates the conditional-batch-norm network in float64
+// (the FP32 path's arithmetic, in double): gamma / beta of every block from the point's
+// float64 feature, the soft one-hot layer, the blocks and the head.
+constexpr int kCbnThreads = 256;
+
+__global__ void __launch_bounds__(kCbnThreads)
+k_cbn64(CbnDesc d, const double* __restrict__ feat, const double* __restrict__ ext, uint32_t gn,
+        const uint32_t* __restrict__ glist, float* __restrict__ logit, uint8_t* __restrict__ lab) {
+  extern __shared__ double sh[];
+  double* f = sh;                                  // C
+  double* gb = f + d.C;                            // 2 nb width
+  double* h = gb + 2 * (size_t)d.nb * d.width;     // width
+  double* a = h + d.width;                         // width
+  __shared__ double red[kCbnThreads];
+  const uint32_t m = blockIdx.x;
+  if (m >= gn) return;
+  const int tid = threadIdx.x;
+  for (int k = tid; k < d.C; k += kCbnThreads) f[k] = feat[(size_t)m * d.C + k];
+  __syncthreads();
+  const int rows = 2 * d.nb * d.width;
+  for (int r = tid; r < rows; r += kCbnThreads) {
+    const int blk = (r / d.width) % d.nb, c = r % d.width;
+    const bool is_g = r < d.nb * d.width;
+    const float* W = (is_g ? d.Wg[blk] : d.Wb[blk]) + (size_t)c * d.C;
+    double acc = 0.0;
+    for (int k = 0; k < d.C; ++k) acc += (double)W[k] * f[k];
+    gb[r] = acc + (double)(is_g ? d.bg[blk][c] : d.bb[blk][c]);
+  }
+  const double z = fmin(fmax(ext[4 * (size_t)m], -1.0), 1.0);   // the code's interval
+  const double s = (double)(d.n_z - 1) * 0.5 * (z + 1.0);
+  double fj = floor(s);
+  int j = (int)fj;
+  if (j > d.n_z - 1) {
+    j = d.n_z - 1;
+    fj = (double)j;
+  }
+  const double frac = s - fj;
+  for (int c = tid; c < d.width; c += kCbnThreads) {
+    const float* wr = d.Wp + (size_t)c * d.n_z;
+    double v = (1.0 - frac) * (double)wr[j] + (double)d.bp[c];
+    if (j + 1 < d.n_z) v += frac * (double)wr[j + 1];
+    h[c] = v;
+  }
+  __syncthreads();
+  for (int blk = 0; blk < d.nb; ++blk) {
+    if (blk > 0) {
+      for (int c = tid; c < d.width; c += kCbnThreads) {
+        const float* wr = d.W[blk - 1] + (size_t)c * d.width;
+        double acc = 0.0;
+        for (int k = 0; k < d.width; ++k) acc += (double)wr[k] * a[k];
+        h[c] = acc + (double)d.b[blk - 1][c];
+      }
+      __syncthreads();
+    }
+    for (int c = tid; c < d.width; c += kCbnThreads) {
+      const double hn = (h[c] - (double)d.mean[blk][c]) / sqrt((double)d.var[blk][c] + (double)d.eps);
+      const double v = gb[(size_t)blk * d.width + c] * hn + gb[((size_t)d.nb + blk) * d.width + c];
+      a[c] = v > 0.0 ? v : 0.0;
+    }
+    __syncthreads();
+  }
+  double part = 0.0;
+  for (int k = tid; k < d.width; k += kCbnThreads) part += (double)d.Wo[k] * a[k];
+  red[tid] = part;
+  __syncthreads();
+  for (int w = kCbnThreads / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double lg = red[0] + (double)d.bo[0];
+    const uint32_t pos = glist[m];
+    logit[pos] = (float)lg;
+    lab[pos] = lg > 0.0;
+  }
+}
+
+size_t guard_cbn64_ws_bytes(const CbnDesc& d, uint32_t chunk) {
+  return ((size_t)chunk * (d.C + 4) + 64) * sizeof(double) + (size_t)chunk * 4 + 4096;
+}
+
+void run_guard_cbn64(const PointSrc& src, const uint32_t* list, const uint32_t* glist, uint32_t gn,
+                     const CbnDesc& d, const float* F, int H, int W, float* logit, uint8_t* lab,
+                     void* ws, uint32_t chunk, hipStream_t s) {
+  if (!gn) return;
+  double* feat = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(ws) + 255) & ~uintptr_t(255));
+  double* ext = feat + (size_t)chunk * d.C;
+  uint32_t* gnode = reinterpret_cast<uint32_t*>(ext + (size_t)chunk * 4);
+  const size_t shmem = ((size_t)d.C + 2 * (size_t)d.nb * d.width + 2 * (size_t)d.width) * sizeof(double);
+  for (uint32_t c0 = 0; c0 < gn; c0 += chunk) {
+    const uint32_t m = gn - c0 < chunk ? gn - c0 : chunk;
+    hipLaunchKernelGGL(k_guard_nodes, dim3(std::min(grid1d(m, 256), kStrideBlocks)), dim3(256), 0,
+                       s, list, glist + c0, m, nullptr, gnode);
+    const uint32_t pw = std::min(m, 2048u);
+    hipLaunchKernelGGL(k_gather64, dim3(grid1d((size_t)pw * 64, 256)), dim3(256), 0, s, src, gnode,
+                       m, nullptr, F, H, W, d.C, feat, ext);
+    hipLaunchKernelGGL(k_cbn64, dim3(m), dim3(kCbnThreads), shmem, s, d, feat, ext, m, glist + c0,
+                       logit, lab);
+  }
+}
+
 }  // namespace pifu

@@ -89,6 +89,12 @@ __device__ inline void store_block(const GemmArgs& a, const f32x16& acc, int row
     uint32_t ix[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) ix[r] = a.rowadd_idx[rr[r]];
+    if (OUT == FMT_F32 && a.rowmul) {   // conditional batch norm: scale, then shift
+      const float mu = a.cbn_mu[col], rs = a.cbn_rstd[col];
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        v[r] = (v[r] - mu) * rs * a.rowmul[(size_t)ix[r] * a.rowadd_ld + a.rowmul_off + col];
+    }
 #pragma unroll
     for (int r = 0; r < 16; ++r) v[r] += a.rowadd[(size_t)ix[r] * a.rowadd_ld + a.rowadd_off + col];
   }

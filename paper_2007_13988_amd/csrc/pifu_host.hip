@@ -163,6 +163,8 @@ int validate_mlp(const pifu_mlp* m, int C, int n_extra_expected, int n_out_expec
   return PIFU_OK;
 }
 
+int validate_cbn(const pifu_field* f);
+
 int validate_field(const pifu_field* f, int n_extra, int n_out) {
   if (!f) return PIFU_ERR_INVALID_ARGUMENT;
   if (f->kind == PIFU_FIELD_MLP) {
@@ -177,6 +179,11 @@ int validate_field(const pifu_field* f, int n_extra, int n_out) {
     return PIFU_OK;
   }
   if (n_out != 1) return PIFU_ERR_INVALID_ARGUMENT;
+  if (f->kind == PIFU_FIELD_CBN) {
+    if (n_extra != 1) return PIFU_ERR_INVALID_ARGUMENT;
+    if (!f->feat || f->H < 2 || f->W < 2 || !aligned(f->feat, 16)) return PIFU_ERR_INVALID_ARGUMENT;
+    return validate_cbn(f);
+  }
   if (f->kind == PIFU_FIELD_ELLIPSOIDS) {
     if (!f->ell || f->n_ell < 1 || f->n_ell > PIFU_MAX_ELLIPSOIDS) return PIFU_ERR_INVALID_ARGUMENT;
     return PIFU_OK;
@@ -344,13 +351,76 @@ struct FieldPrep {
   MlpPrep mlp, sur;
   bool has_mlp = false, has_sur = false;
   Ellipsoids ell;
+  // PIFU_FIELD_CBN: the network, its stacked conditional maps [gamma_i; beta_i] (NPc rows)
+  // and biases, and the batch-norm constants
+  bool has_cbn = false;
+  CbnDesc cd;
+  int NPc = 0;
+  float *Wgb = nullptr, *bgb = nullptr, *mu = nullptr, *rstd = nullptr;
 };
+
+CbnDesc cbn_desc(const pifu_field* f) {
+  CbnDesc d;
+  std::memset(&d, 0, sizeof(d));
+  const pifu_cbn* n = f->cbn;
+  d.C = n->feat_dim;
+  d.n_z = n->n_z;
+  d.width = n->width;
+  d.nb = n->n_blocks;
+  d.eps = n->eps;
+  d.Wp = n->Wp;
+  d.bp = n->bp;
+  for (int i = 0; i < PIFU_CBN_MAX_BLOCKS; ++i) {
+    d.W[i] = n->W[i];
+    d.b[i] = n->b[i];
+    d.Wg[i] = n->Wg[i];
+    d.bg[i] = n->bg[i];
+    d.Wb[i] = n->Wb[i];
+    d.bb[i] = n->bb[i];
+    d.mean[i] = n->mean[i];
+    d.var[i] = n->var[i];
+  }
+  d.Wo = n->Wo;
+  d.bo = n->bo;
+  return d;
+}
+
+int validate_cbn(const pifu_field* f) {
+  const pifu_cbn* n = f->cbn;
+  if (!n) return PIFU_ERR_INVALID_ARGUMENT;
+  if (n->feat_dim != f->C || f->C % 32 != 0 || f->C > 512) return PIFU_ERR_INVALID_ARGUMENT;
+  if (n->width <= 0 || n->width % 64 != 0 || n->width > 512) return PIFU_ERR_INVALID_ARGUMENT;
+  if (n->n_z < 2 || n->n_z > 256 || n->n_blocks < 1 || n->n_blocks > PIFU_CBN_MAX_BLOCKS)
+    return PIFU_ERR_INVALID_ARGUMENT;
+  if (!(n->eps > 0.f)) return PIFU_ERR_INVALID_ARGUMENT;
+  // the float64 guard keeps one point's feature, maps and activations in LDS
+  if (((size_t)f->C + 2 * (size_t)n->n_blocks * n->width + 2 * (size_t)n->width) * 8 > 60 * 1024)
+    return PIFU_ERR_UNSUPPORTED;
+  if (!n->Wp || !n->bp || !n->Wo || !n->bo || !aligned(n->Wp, 16) || !aligned(n->Wo, 16))
+    return PIFU_ERR_INVALID_ARGUMENT;
+  for (int i = 0; i < n->n_blocks; ++i) {
+    if (!n->Wg[i] || !n->bg[i] || !n->Wb[i] || !n->bb[i] || !n->mean[i] || !n->var[i])
+      return PIFU_ERR_INVALID_ARGUMENT;
+    if (i > 0 && (!n->W[i - 1] || !n->b[i - 1] || !aligned(n->W[i - 1], 16)))
+      return PIFU_ERR_INVALID_ARGUMENT;
+  }
+  return PIFU_OK;
+}
 
 void carve_field(Carver& cv, const pifu_field* f, int precision, FieldPrep& fp) {
   fp.f = f;
   fp.has_mlp = f->kind == PIFU_FIELD_MLP;
   fp.has_sur = fp.has_mlp && f->surrogate != nullptr;
+  fp.has_cbn = f->kind == PIFU_FIELD_CBN;
   std::memset(&fp.ell, 0, sizeof(fp.ell));
+  if (fp.has_cbn) {
+    fp.cd = cbn_desc(f);
+    fp.NPc = 2 * fp.cd.nb * fp.cd.width;
+    fp.Wgb = cv.take<float>((size_t)fp.NPc * fp.cd.C);
+    fp.bgb = cv.take<float>(fp.NPc);
+    fp.mu = cv.take<float>((size_t)fp.cd.nb * fp.cd.width);
+    fp.rstd = cv.take<float>((size_t)fp.cd.nb * fp.cd.width);
+  }
   if (fp.has_mlp) {
     carve_mlp(cv, f->mlp, precision, fp.mlp);
     if (fp.has_sur) carve_mlp(cv, f->surrogate, PIFU_PREC_BF16, fp.sur);
@@ -374,10 +444,19 @@ int pack_field(FieldPrep& fp, pifu_ctx* ctx, hipStream_t s, uint32_t* counters,
   }
   if (fp.has_mlp) r = pack_mlp(fp.mlp, ctx, s, ovf);
   if (!r && fp.has_sur) r = pack_mlp(fp.sur, ctx, s, nullptr);
+  if (!r && fp.has_cbn) {
+    launch_cbn_pack(fp.cd, fp.Wgb, fp.bgb, fp.mu, fp.rstd, s);
+    r = check_launch();
+  }
   return r;
 }
 
 void carve_guard(Carver& cv, const FieldPrep& fp, uint32_t max_points, EvalWs& ew) {
+  if (fp.has_cbn) {
+    ew.chunk64 = std::max<uint32_t>(64, std::min<uint32_t>(16384, max_points));
+    ew.g64 = cv.take<char>(guard_cbn64_ws_bytes(fp.cd, ew.chunk64));
+    return;
+  }
   if (!fp.has_mlp) return;
   ew.chunk64 = std::max<uint32_t>(64, std::min<uint32_t>(16384, max_points));
   ew.g64 = cv.take<char>(guard64_ws_bytes(fp.mlp.d, ew.chunk64));
@@ -424,7 +503,14 @@ void carve_hoist(Carver& cv, int NP, EvalWs& ew, uint32_t col_cap = 0) {
   ew.Pcol = cv.take<float>((size_t)ew.col_rows * NP);
 }
 
+// Feature channels and widest hidden layer of a network field (0 for analytic fields).
+int net_channels(const FieldPrep& fp) { return fp.has_mlp || fp.has_cbn ? fp.f->C : 0; }
+int net_hidden(const FieldPrep& fp) {
+  return fp.has_mlp ? fp.mlp.max_hidden : (fp.has_cbn ? fp.cd.width : 0);
+}
+
 int hoist_np(const FieldPrep& fp) {
+  if (fp.has_cbn) return fp.NPc;
   if (!fp.has_mlp) return 0;
   return std::max(fp.mlp.NP, fp.has_sur ? fp.sur.NP : 0);
 }
@@ -863,10 +949,113 @@ int eval_full(EvalCtx& e, const FieldPrep& fp, const PointSrc& src, const uint32
 // Evaluates the occupancy field at n points; fills logit and label per point.  With
 // use_surrogate, the surrogate network (BF16) runs first and the points whose
 // surrogate occupancy lies within the fallback band of 0.5 go to the full network.
+// The conditional-batch-norm network (PIFU_FIELD_CBN) on n points, FP32, then the FP64
+// guard.  Input-view lattice points share their column's gamma / beta rows (computed once
+// per column); other points take one row each.
+int eval_cbn(EvalCtx& e, const FieldPrep& fp, const PointSrc& src, const uint32_t* list,
+             uint32_t n, const EvalWs& ew, float* logit, uint8_t* lab, pifu_level_stats* st) {
+  const pifu_field* f = fp.f;
+  const CbnDesc& d = fp.cd;
+  const int C = f->C;
+  if (!ew.Pcol || ew.col_rows < ew.chunk) return PIFU_ERR_WORKSPACE_TOO_SMALL;
+  const bool columns = src.mode == 0 && !src.has_view && !src.frame_nodes;
+  for (uint32_t c0 = 0; c0 < n; c0 += ew.chunk) {
+    const uint32_t m = std::min(ew.chunk, n - c0);
+    const uint32_t* lst = list + c0;
+    const uint32_t* rows_dev = nullptr;   // rows of the conditional GEMM (device count)
+    const uint32_t* rows_src = lst;       // the point whose feature each row samples
+    if (columns) {
+      launch_col_flags(lst, m, (uint32_t)src.nz, ew.cflags, e.s);
+      launch_scan_u32(ew.cflags, m, ew.cexcl, ew.cscan, e.counters + C_TOTAL, e.s);
+      launch_col_ids(lst, ew.cflags, ew.cexcl, m, ew.cid, ew.cnode, e.s);
+      rows_dev = e.counters + C_TOTAL;
+      rows_src = ew.cnode;
+    } else {
+      launch_iota(ew.cid, m, e.s);
+    }
+    {
+      ProfScope ps(e.ctx, e.s, PIFU_KERN_GATHER, 0.0, 0.0, rows_dev ? rows_dev : nullptr,
+                   0.0, 20.0 * C + 20.0);
+      launch_gather(src, rows_src, m, f->feat, f->H, f->W, C, ew.feat, FMT_F32, ew.ext, e.s,
+                    rows_dev, nullptr);
+    }
+    GemmArgs g;
+    std::memset(&g, 0, sizeof(g));
+    g.A1 = ew.feat;
+    g.K1 = g.lda1 = C;
+    g.W = fp.Wgb;
+    g.ldw = C;
+    g.bias = fp.bgb;
+    g.C = ew.Pcol;
+    g.ldc = g.N = fp.NPc;
+    g.M = (int)m;
+    g.M_dev = rows_dev;
+    g.scale = 1.f;
+    {
+      ProfScope ps(e.ctx, e.s, PIFU_KERN_GEMM_F32, rows_dev ? 0.0 : 2.0 * m * g.N * C,
+                   rows_dev ? (double)g.N * C * 4.0 : 0.0, rows_dev, 2.0 * g.N * C,
+                   C * 4.0 + g.N * 4.0, true);
+      if (launch_gemm(g, PIFU_PREC_FP32, pick_tile(e, PIFU_PREC_FP32, g.N, C, m), e.s, ps.start(),
+                      ps.stop()))
+        return PIFU_ERR_UNSUPPORTED;
+    }
+    launch_cbn_first(src, lst, m, d, ew.Pcol, ew.cid, fp.mu, fp.rstd,
+                     reinterpret_cast<float*>(ew.hA), e.s);
+    const void* prev = ew.hA;
+    void* out = ew.hB;
+    for (int i = 1; i < d.nb; ++i) {
+      std::memset(&g, 0, sizeof(g));
+      g.A1 = prev;
+      g.K1 = g.lda1 = d.width;
+      g.W = d.W[i - 1];
+      g.ldw = d.width;
+      g.bias = d.b[i - 1];
+      g.rowadd = ew.Pcol;
+      g.rowadd_idx = ew.cid;
+      g.rowadd_ld = fp.NPc;
+      g.rowadd_off = (d.nb + i) * d.width;   // beta_i
+      g.rowmul = ew.Pcol;
+      g.rowmul_off = i * d.width;            // gamma_i
+      g.cbn_mu = fp.mu + (size_t)i * d.width;
+      g.cbn_rstd = fp.rstd + (size_t)i * d.width;
+      g.C = out;
+      g.ldc = g.N = d.width;
+      g.M = (int)m;
+      g.act = PIFU_ACT_RELU;
+      g.scale = 1.f;
+      {
+        ProfScope ps(e.ctx, e.s, PIFU_KERN_GEMM_F32, 2.0 * m * g.N * g.K1,
+                     4.0 * ((double)m * (g.K1 + 3.0 * g.N) + (double)g.N * g.K1), nullptr, 0.0, 0.0,
+                     true);
+        if (launch_gemm(g, PIFU_PREC_FP32, pick_tile(e, PIFU_PREC_FP32, g.N, g.K1, m), e.s,
+                        ps.start(), ps.stop()))
+          return PIFU_ERR_UNSUPPORTED;
+      }
+      prev = out;
+      out = (out == ew.hA) ? ew.hB : ew.hA;
+    }
+    ProfScope ps(e.ctx, e.s, PIFU_KERN_HEAD, 2.0 * m * d.width, 0.0);
+    launch_head(reinterpret_cast<const float*>(prev), d.width, d.Wo, d.bo, 1, PIFU_ACT_SIGMOID, m,
+                nullptr, logit + c0, lab + c0, nullptr, nullptr, e.s);
+  }
+  int r = check_launch();
+  if (r) return r;
+  if (st) st->mlp_points += n;
+  if (!(e.guard > 0.f)) return PIFU_OK;
+  uint32_t gn = 0;
+  r = select_near(e, logit, n, e.guard, ew.glist, &gn);
+  if (r) return r;
+  run_guard_cbn64(src, list, ew.glist, gn, d, f->feat, f->H, f->W, logit, lab, ew.g64, ew.chunk64,
+                  e.s);
+  if (st) st->guard_fp64 += gn;
+  return check_launch();
+}
+
 int eval_occupancy(EvalCtx& e, const FieldPrep& fp, const PointSrc& src, const uint32_t* list,
                    uint32_t n, const EvalWs& ew, float* logit, uint8_t* lab, pifu_level_stats* st,
                    bool use_surrogate = false) {
   if (!n) return PIFU_OK;
+  if (fp.has_cbn) return eval_cbn(e, fp, src, list, n, ew, logit, lab, st);
   if (!fp.has_mlp) {
     launch_eval_analytic(src, list, n, fp.f->kind, fp.ell, fp.f->plane, logit, lab, e.s);
     return check_launch();
@@ -1095,8 +1284,8 @@ int plan_grid(const pifu_field* field, const pifu_grid_opts* o, void* base, floa
   g.w.logit = cv.take<float>(max_n);
   g.w.lab = cv.take<uint8_t>(max_n);
   carve_field(cv, field, o->precision, g.fp);
-  const int C = field->kind == PIFU_FIELD_MLP ? field->C : 0;
-  const int mh = g.fp.has_mlp ? g.fp.mlp.max_hidden : 0;
+  const int C = net_channels(g.fp);
+  const int mh = net_hidden(g.fp);
   if (async_cap) {
     g.aw = cv.take<uint32_t>(AW_COUNT_WORDS);
     const uint32_t cap = (uint32_t)std::min<size_t>(async_cap, max_n);
@@ -1122,7 +1311,11 @@ int validate_grid_opts(const pifu_field* field, const pifu_grid_opts* o) {
     return PIFU_ERR_INVALID_ARGUMENT;
   int r = validate_precision(o->precision);
   if (r) return r;
-  return validate_field(field, 1, 1);
+  r = validate_field(field, 1, 1);
+  if (r) return r;
+  // the lifting network runs in FP32 (with the FP64 guard), without a surrogate
+  if (field->kind == PIFU_FIELD_CBN && o->precision != PIFU_PREC_FP32) return PIFU_ERR_UNSUPPORTED;
+  return PIFU_OK;
 }
 
 // ------------------------------------------------------------------ render layout
@@ -1153,6 +1346,7 @@ int validate_render_opts(const pifu_field* occ, const pifu_field* col, const pif
   if (r) return r;
   r = validate_field(occ, 1, 1);
   if (r) return r;
+  if (occ->kind == PIFU_FIELD_CBN) return PIFU_ERR_UNSUPPORTED;
   if (!col || col->kind != PIFU_FIELD_MLP) return PIFU_ERR_INVALID_ARGUMENT;
   return validate_field(col, 2, 3);
 }
@@ -1630,15 +1824,16 @@ int32_t pifu_eval_points_workspace_size(const pifu_field* field, int32_t precisi
   if (r) return r;
   r = validate_field(field, 1, 1);
   if (r) return r;
+  if (field->kind == PIFU_FIELD_CBN && precision != PIFU_PREC_FP32) return PIFU_ERR_UNSUPPORTED;
   Carver cv(nullptr);
   cv.take<uint32_t>(kCounters);
   cv.take<uint32_t>(std::max<uint32_t>(n, 1));
   FieldPrep fp;
   carve_field(cv, field, precision, fp);
   EvalWs ew;
-  carve_eval(cv, std::max<uint32_t>(n, 1), field->kind == PIFU_FIELD_MLP ? field->C : 0,
-             fp.has_mlp ? fp.mlp.max_hidden : 0, ew);
+  carve_eval(cv, std::max<uint32_t>(n, 1), net_channels(fp), net_hidden(fp), ew);
   carve_guard(cv, fp, std::max<uint32_t>(n, 1), ew);
+  if (fp.has_cbn) carve_hoist(cv, hoist_np(fp), ew);
   *bytes = cv.off + kAlign;
   return PIFU_OK;
 }
@@ -1660,9 +1855,9 @@ int32_t pifu_eval_points(pifu_ctx* ctx, const pifu_field* field, int32_t precisi
   FieldPrep fp;
   carve_field(cv, field, precision, fp);
   EvalWs ew;
-  carve_eval(cv, n, field->kind == PIFU_FIELD_MLP ? field->C : 0,
-             fp.has_mlp ? fp.mlp.max_hidden : 0, ew);
+  carve_eval(cv, n, net_channels(fp), net_hidden(fp), ew);
   carve_guard(cv, fp, n, ew);
+  if (fp.has_cbn) carve_hoist(cv, hoist_np(fp), ew);
   hipStream_t s = as_stream(stream);
   uint8_t* lab = labels;
   if (!lab) lab = reinterpret_cast<uint8_t*>(ew.glist);   // scratch when labels are not wanted
@@ -1675,7 +1870,7 @@ int32_t pifu_eval_points(pifu_ctx* ctx, const pifu_field* field, int32_t precisi
   std::memset(&src, 0, sizeof(src));
   src.mode = 1;
   src.pts = reinterpret_cast<const float4*>(pts);
-  if (!labels && fp.has_mlp && guard_logit > 0.f) return PIFU_ERR_INVALID_ARGUMENT;
+  if (!labels && (fp.has_mlp || fp.has_cbn) && guard_logit > 0.f) return PIFU_ERR_INVALID_ARGUMENT;
   r = eval_occupancy(e, fp, src, iota, n, ew, logit, lab, nullptr);
   if (!r) r = check_launch();
   if (!r) r = hipStreamSynchronize(s) == hipSuccess ? PIFU_OK : PIFU_ERR_HIP;
@@ -2131,6 +2326,7 @@ int validate_batch(int n, const pifu_field* const* fields, const pifu_grid_opts*
     const pifu_field* A = fields[0];
     const pifu_field* B = fields[f];
     if (A->kind != B->kind) return PIFU_ERR_INVALID_ARGUMENT;
+    if (A->kind == PIFU_FIELD_CBN) return PIFU_ERR_UNSUPPORTED;
     if (A->kind == PIFU_FIELD_MLP) {
       // frames share one network; only the feature maps differ
       if (B->H != A->H || B->W != A->W || B->C != A->C) return PIFU_ERR_INVALID_ARGUMENT;
@@ -2870,7 +3066,7 @@ int32_t pifu_occupancy_grid_async_workspace_size(const pifu_field* field,
   if (!bytes) return PIFU_ERR_INVALID_ARGUMENT;
   int r = validate_grid_opts(field, opts);
   if (r) return r;
-  if (opts->precision == PIFU_PREC_FP8) return PIFU_ERR_UNSUPPORTED;
+  if (opts->precision == PIFU_PREC_FP8 || field->kind == PIFU_FIELD_CBN) return PIFU_ERR_UNSUPPORTED;
   GridWs* g = new (std::nothrow) GridWs;
   if (!g) return PIFU_ERR_HIP;
   plan_grid(field, opts, nullptr, nullptr, *g, 1);

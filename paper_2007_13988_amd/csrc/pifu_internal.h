@@ -286,7 +286,46 @@ struct GemmArgs {
   uint32_t* ovf;
   // PREC_F32X3: the lo copy of W (W holds the hi copy)
   const void* Wlo;
+  // conditional batch norm (FP32 only): v = (v - cbn_mu[col]) * cbn_rstd[col] *
+  // rowmul[rowadd_idx[row] * rowadd_ld + rowmul_off + col], before the rowadd term
+  const float* rowmul;
+  int rowmul_off;
+  const float* cbn_mu;
+  const float* cbn_rstd;
 };
+
+// The conditional-batch-norm lifting network (pifu_cbn) as kernels read it.
+struct CbnDesc {
+  int C, n_z, width, nb;
+  float eps;
+  const float* Wp;
+  const float* bp;
+  const float* W[PIFU_CBN_MAX_BLOCKS];
+  const float* b[PIFU_CBN_MAX_BLOCKS];
+  const float* Wg[PIFU_CBN_MAX_BLOCKS];
+  const float* bg[PIFU_CBN_MAX_BLOCKS];
+  const float* Wb[PIFU_CBN_MAX_BLOCKS];
+  const float* bb[PIFU_CBN_MAX_BLOCKS];
+  const float* mean[PIFU_CBN_MAX_BLOCKS];
+  const float* var[PIFU_CBN_MAX_BLOCKS];
+  const float* Wo;
+  const float* bo;
+};
+// Packs [Wg_0 .. Wg_nb-1; Wb_0 .. Wb_nb-1] (2 nb width x C) and their biases, and the
+// batch-norm constants mu[i][c], rstd[i][c] = 1 / sqrt(var[i][c] + eps).
+void launch_cbn_pack(const CbnDesc& d, float* Wgb, float* bgb, float* mu, float* rstd,
+                     hipStream_t s);
+// First block for points m < n: the soft one-hot depth layer, then conditional batch norm
+// with gamma_0 / beta_0 from the hoisted rows P[cid[m]] (ld 2 nb width), and ReLU; a is
+// n x width.
+void launch_cbn_first(const PointSrc& src, const uint32_t* list, uint32_t n, const CbnDesc& d,
+                      const float* P, const uint32_t* cid, const float* mu, const float* rstd,
+                      float* a, hipStream_t s);
+// FP64 re-evaluation of the guarded points (positions glist into list): logit and label.
+size_t guard_cbn64_ws_bytes(const CbnDesc& d, uint32_t chunk);
+void run_guard_cbn64(const PointSrc& src, const uint32_t* list, const uint32_t* glist, uint32_t gn,
+                     const CbnDesc& d, const float* F, int H, int W, float* logit, uint8_t* lab,
+                     void* ws, uint32_t chunk, hipStream_t s);
 
 // ------------------------------------------------------------------ per-column hoisting
 // flags[i] = point i starts a new (x, y) column (list sorted or not: runs of one column)

@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libpifu.so")
 INCLUDE = os.path.join(os.path.dirname(_HERE), "include", "pifu.h")
 
 MAX_LAYERS = 8
-FIELD_MLP, FIELD_ELLIPSOIDS, FIELD_PLANE = 0, 1, 2
+CBN_MAX_BLOCKS = 8
+FIELD_MLP, FIELD_ELLIPSOIDS, FIELD_PLANE, FIELD_CBN = 0, 1, 2, 3
 ACT = {"relu": 1, "lrelu": 2, "sigmoid": 3, "tanh": 4}
 PREC = {"fp32": 0, "bf16": 1, "fp8": 2, "fp16": 3}
 STATUS = {0: "ok", -1: "invalid argument", -2: "workspace too small", -3: "unsupported",
@@ -34,11 +35,20 @@ class PifuMLP(C.Structure):
                 ("fp8_amax", C.c_float * MAX_LAYERS)]
 
 
+class PifuCBN(C.Structure):
+    _fields_ = [("feat_dim", C.c_int32), ("n_z", C.c_int32), ("width", C.c_int32),
+                ("n_blocks", C.c_int32), ("eps", C.c_float), ("Wp", C.c_void_p), ("bp", C.c_void_p)] + \
+               [(k, C.c_void_p * CBN_MAX_BLOCKS) for k in ("W", "b", "Wg", "bg", "Wb", "bb", "mean",
+                                                          "var")] + \
+               [("Wo", C.c_void_p), ("bo", C.c_void_p)]
+
+
 class PifuField(C.Structure):
     _fields_ = [("kind", C.c_int32), ("H", C.c_int32), ("W", C.c_int32), ("C", C.c_int32),
                 ("feat", C.c_void_p), ("mlp", C.POINTER(PifuMLP)),
                 ("surrogate", C.POINTER(PifuMLP)), ("n_ell", C.c_int32),
-                ("sharpness", C.c_float), ("ell", C.c_void_p), ("plane", C.c_float * 4)]
+                ("sharpness", C.c_float), ("ell", C.c_void_p), ("plane", C.c_float * 4),
+                ("cbn", C.POINTER(PifuCBN))]
 
 
 class PifuLevelStats(C.Structure):
@@ -319,6 +329,26 @@ class DeviceMLP:
         self.struct = s
 
 
+class DeviceCBN:
+    """The conditional-batch-norm lifting network (synth.CBNSpec) on the GPU."""
+
+    def __init__(self, spec, device="cuda"):
+        t = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32)).to(device)
+        self.spec = spec
+        self.Wp, self.bp, self.Wo, self.bo = t(spec.Wp), t(spec.bp), t(spec.Wo), t(spec.bo)
+        lists = {k: [t(a) for a in getattr(spec, k)] for k in ("W", "b", "Wg", "bg", "Wb", "bb",
+                                                               "mean", "var")}
+        self.lists = lists
+        s = PifuCBN()
+        s.feat_dim, s.n_z, s.width, s.n_blocks = spec.feat_dim, spec.n_z, spec.width, spec.n_blocks
+        s.eps = spec.eps
+        s.Wp, s.bp, s.Wo, s.bo = (x.data_ptr() for x in (self.Wp, self.bp, self.Wo, self.bo))
+        for k, arr in lists.items():
+            for i, a in enumerate(arr):
+                getattr(s, k)[i] = a.data_ptr()
+        self.struct = s
+
+
 class DeviceField:
     """An occupancy/colour field for the C ABI (MLP over a feature map, or analytic)."""
 
@@ -339,6 +369,14 @@ class DeviceField:
             if surrogate is not None:
                 s.surrogate = C.pointer(surrogate.struct)
             self.surrogate = surrogate
+        elif kind == FIELD_CBN:
+            ft = torch.as_tensor(np.ascontiguousarray(feat, np.float32)).to(device) \
+                if not isinstance(feat, torch.Tensor) else feat.contiguous()
+            self.feat = ft
+            s.H, s.W, s.C = ft.shape
+            s.feat = ft.data_ptr()
+            self.cbn = mlp
+            s.cbn = C.pointer(mlp.struct)
         elif kind == FIELD_ELLIPSOIDS:
             e = np.ascontiguousarray(ell, np.float32).reshape(-1, 12)
             self._ell = e
@@ -355,6 +393,10 @@ class DeviceField:
         sur = DeviceMLP(surrogate_spec, device) if surrogate_spec is not None else None
         return DeviceField(FIELD_MLP, feat=feat, mlp=DeviceMLP(spec, device), surrogate=sur,
                            device=device)
+
+    @staticmethod
+    def cbn_field(feat, spec, device="cuda"):
+        return DeviceField(FIELD_CBN, feat=feat, mlp=DeviceCBN(spec, device), device=device)
 
     @staticmethod
     def ellipsoids(ell, sharpness=8.0):
@@ -596,7 +638,7 @@ def fp8_calibrate(field: DeviceField, pts, stream=None) -> List[float]:
 
 
 STATS_WORDS = C.sizeof(PifuLevelStats) // 4
-STATUS = {1: "list over max_points", 2: "waves left", 4: "guard over", 8: "cells over"}
+ASYNC_STATUS = {1: "list over max_points", 2: "waves left", 4: "guard over", 8: "cells over"}
 
 
 def stats_from_device(t: torch.Tensor) -> List[Dict[str, int]]:

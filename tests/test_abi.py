@@ -199,3 +199,34 @@ def test_grid_and_render_validates_both_calls_first(P):
     assert lib.pifu_grid_and_render(fake, C.byref(g), C.byref(r)) == -2
     g, r = calls(rws_bytes=rws.value - 1)
     assert lib.pifu_grid_and_render(fake, C.byref(g), C.byref(r)) == -2
+
+
+def test_cbn_field_validation_and_scope(P):
+    """The CBN field's host-side checks (host stand-ins for the device arrays: the queries
+    validate before anything touches memory): supported sizes pass, others are refused,
+    and the calls outside its scope answer UNSUPPORTED."""
+    lib = P.load_library()
+    spec = synth.cbn_net(feat_dim=64, n_z=16, width=64, n_blocks=3, seed=1)
+    feat = synth.feature_map(8, 8, 64, 2.0, 1)
+    f = P.DeviceField.cbn_field(feat, spec, device="cpu")
+    assert _ws(P, f, P.grid_opts(5, 3))[0] == 0
+    for prec in ("bf16", "fp16", "fp8"):
+        assert _ws(P, f, P.grid_opts(5, 3, precision=prec))[0] == -3, prec
+    n = C.c_size_t()
+    assert lib.pifu_occupancy_grid_async_workspace_size(C.byref(f.struct),
+                                                        C.byref(P.grid_opts(5, 3)), 0,
+                                                        C.byref(n)) == -3
+    assert lib.pifu_eval_points_workspace_size(C.byref(f.struct), 0, 100, C.byref(n)) == 0
+    assert lib.pifu_eval_points_workspace_size(C.byref(f.struct), 1, 100, C.byref(n)) == -3
+    # sizes outside the supported set
+    for field, bad in (("width", 96), ("n_z", 1), ("n_blocks", 9), ("n_blocks", 0),
+                       ("feat_dim", 48)):
+        old = getattr(f.cbn.struct, field)
+        setattr(f.cbn.struct, field, bad)
+        assert _ws(P, f, P.grid_opts(5, 3))[0] == -1, (field, bad)
+        setattr(f.cbn.struct, field, old)
+    f.cbn.struct.eps = 0.0
+    assert _ws(P, f, P.grid_opts(5, 3))[0] == -1
+    f.cbn.struct.eps = spec.eps
+    f.cbn.struct.Wg[2] = None
+    assert _ws(P, f, P.grid_opts(5, 3))[0] == -1
