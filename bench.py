@@ -193,15 +193,20 @@ def cpu_baseline(frame, budget_s):
                        f"{threads} BLAS threads on a host with nproc {_nproc()}")}
 
 
+# The sources that decide the MLP GEMM launches of a frame: the kernels, their argument
+# layout, and the host code that chooses the point lists, tiles and chunks.  A recorded
+# HBM traffic figure holds only while these are unchanged.
+TRAFFIC_SOURCES = ("pifu_gemm.hip", "pifu_internal.h", "pifu_host.hip")
+
+
 def sources_sha256():
-    """SHA-256 over the library's kernel and host sources (name + bytes, sorted)."""
-    import glob
+    """SHA-256 over TRAFFIC_SOURCES (name + bytes, in that order)."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2007_13988_amd", "csrc")
-    for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h"))):
-        h.update(os.path.basename(f).encode())
-        with open(f, "rb") as fh:
+    for name in TRAFFIC_SOURCES:
+        h.update(name.encode())
+        with open(os.path.join(csrc, name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
@@ -626,7 +631,11 @@ def main():
         log(f"form {form}")
         fld, gout, rout = make(form)
         for _ in range(args.warmup):
-            P.grid_and_render_into(fld, gout, col_field, view, bg, rout, stream, stream2)
+            if args.serial_only:
+                P.occupancy_grid_into(fld, gout, stream)
+                P.render_view_into(fld, col_field, view, bg, rout, stream)
+            else:
+                P.grid_and_render_into(fld, gout, col_field, view, bg, rout, stream, stream2)
         torch.cuda.synchronize()
 
         def timed_steps():
