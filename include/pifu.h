@@ -584,13 +584,14 @@ int32_t pifu_eval_points_workspace_size(const pifu_field* field, int32_t precisi
  * Evaluates a field at n input-view NDC points (Eq. 1) with the same kernels the
  * grid path uses.  pts: device float32 n x 4 (x, y, z, unused).  logit: device
  * float32 n.  labels (device uint8 n, nullable) receives the label decided with
- * the guard band.  precision / band_delta / guard_logit as in pifu_grid_opts.
- * Blocks until done.
+ * the guard band.  occ (device float32 n, nullable) receives the occupancy value
+ * p = 1 / (1 + exp(-logit)) in float32, as the grid computes it.  precision /
+ * band_delta / guard_logit as in pifu_grid_opts.  Blocks until done.
  */
 int32_t pifu_eval_points(pifu_ctx* ctx, const pifu_field* field, int32_t precision,
                          float band_delta, float guard_logit, const float* pts, uint32_t n,
-                         float* logit, uint8_t* labels, void* workspace, size_t workspace_bytes,
-                         pifu_stream stream);
+                         float* logit, uint8_t* labels, float* occ, void* workspace,
+                         size_t workspace_bytes, pifu_stream stream);
 
 /*
  * Static FP8 activation scales (the per-layer scale of the precision ladder): runs

@@ -356,32 +356,38 @@ __device__ inline void stage_ray_bits(const uint8_t* __restrict__ stc, Lat c, in
 // The ray of pixel column (u, v): its coarse columns (LDS word offsets) and the AND / OR
 // of their label masks.
 struct Ray {
+  // the up to four coarse columns around the pixel column: (ua, va), (ua, vb), (ub, va),
+  // (ub, vb); use[i] says whether column i is a distinct one (every loop below has a
+  // fixed trip count, so these arrays and A / O stay in registers)
   int off[4];
+  bool use[4];
   int ncol, nw, nzc;
   uint64_t A[kRayMaxWords], O[kRayMaxWords];
 
   __device__ inline void init(const uint64_t* bits, int nz, int u, int v, int cu0, int cv0) {
     nzc = nz;
     nw = ray_words(nz);
-    ncol = 0;
     const int ua = u >> 1, ub = (u + 1) >> 1, va = v >> 1, vb = (v + 1) >> 1;
-    for (int i = 0; i < 2; ++i) {
-      const int cu = i ? ub : ua;
-      if (i && ub == ua) continue;
-      for (int j = 0; j < 2; ++j) {
-        const int cv = j ? vb : va;
-        if (j && vb == va) continue;
-        off[ncol++] = ((cu - cu0) * kRayCoarse + (cv - cv0)) * nw;
-      }
-    }
+    off[0] = ((ua - cu0) * kRayCoarse + (va - cv0)) * nw;
+    off[1] = ((ua - cu0) * kRayCoarse + (vb - cv0)) * nw;
+    off[2] = ((ub - cu0) * kRayCoarse + (va - cv0)) * nw;
+    off[3] = ((ub - cu0) * kRayCoarse + (vb - cv0)) * nw;
+    use[0] = true;
+    use[1] = vb != va;
+    use[2] = ub != ua;
+    use[3] = ub != ua && vb != va;
+    ncol = 1 + (int)use[1] + (int)use[2] + (int)use[3];
+#pragma unroll
     for (int q = 0; q < kRayMaxWords; ++q) {
       uint64_t a = ~0ull, o = 0ull;
       if (q < nw) {
-        for (int i = 0; i < ncol; ++i) {
-          const uint64_t m = bits[off[i] + q];
-          a &= m;
-          o |= m;
-        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (use[i]) {
+            const uint64_t m = bits[off[i] + q];
+            a &= m;
+            o |= m;
+          }
       } else {
         a = 0ull;
       }
@@ -389,7 +395,8 @@ struct Ray {
       O[q] = o;
     }
   }
-  // bit m of word q of the mask shifted down by one node (m + 1 -> m)
+  // bit m of word q of the mask shifted down by one node (m + 1 -> m); q is a constant
+  // after unrolling
   __device__ static inline uint64_t next(const uint64_t* X, int q) {
     return (X[q] >> 1) | (q + 1 < kRayMaxWords ? X[q + 1] << 63 : 0ull);
   }
@@ -406,11 +413,13 @@ struct Ray {
   // k* = the node nearest the observer (largest k) that is full, -1 if none
   __device__ inline int kstar() const {
     int ke = -1, ko = -1;
-    for (int q = nw - 1; q >= 0 && ke < 0; --q)
-      if (A[q]) ke = 2 * (64 * q + 63 - __clzll(A[q]));
-    for (int q = nw - 1; q >= 0 && ko < 0; --q) {
+#pragma unroll
+    for (int q = kRayMaxWords - 1; q >= 0; --q)
+      if (q < nw && ke < 0 && A[q]) ke = 2 * (64 * q + 63 - __clzll(A[q]));
+#pragma unroll
+    for (int q = kRayMaxWords - 1; q >= 0; --q) {
       const uint64_t aa = A[q] & next(A, q) & odd_valid(q);
-      if (aa) ko = 2 * (64 * q + 63 - __clzll(aa)) + 1;
+      if (q < nw && ko < 0 && aa) ko = 2 * (64 * q + 63 - __clzll(aa)) + 1;
     }
     return ke > ko ? ke : ko;
   }
@@ -425,7 +434,9 @@ struct Ray {
   __device__ inline void at(const uint64_t* bits, int k, int& sum, int& cnt) const {
     auto S = [&](int kc) {
       int s = 0;
-      for (int i = 0; i < ncol; ++i) s += (int)((bits[off[i] + (kc >> 6)] >> (kc & 63)) & 1ull);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (use[i]) s += (int)((bits[off[i] + (kc >> 6)] >> (kc & 63)) & 1ull);
       return s;
     };
     if (k & 1) {
@@ -455,8 +466,9 @@ __global__ void __launch_bounds__(256) k_ray_count(const uint8_t* __restrict__ s
     r.init(bits, c.nz, u, v, u0 >> 1, v0 >> 1);
     const int ks = r.kstar();
     uint32_t n = 0;
-    for (int q = 0; q < r.nw; ++q)
-      n += (uint32_t)(__popcll(r.even_cand(ks, q)) + __popcll(r.odd_cand(ks, q)));
+#pragma unroll
+    for (int q = 0; q < kRayMaxWords; ++q)
+      if (q < r.nw) n += (uint32_t)(__popcll(r.even_cand(ks, q)) + __popcll(r.odd_cand(ks, q)));
     const uint32_t col = (uint32_t)u * H + v;
     cnt[col] = n;
     kstar[col] = (uint32_t)ks;
@@ -492,8 +504,17 @@ __global__ void __launch_bounds__(256) k_ray_list(const uint8_t* __restrict__ st
   const int ks = (int)kstar[col];
   uint32_t pos = off[col];
   const size_t base = ((size_t)u * (H + 1) + v) * (size_t)(D + 1);
-  for (int q = 0; q < r.nw; ++q) {
-    const uint64_t ev = r.even_cand(ks, q), od = r.odd_cand(ks, q);
+  // the candidate words first (fixed trip count: the Ray stays in registers), then the
+  // bit walk over them
+  uint64_t evw[kRayMaxWords], odw[kRayMaxWords];
+#pragma unroll
+  for (int q = 0; q < kRayMaxWords; ++q) {
+    evw[q] = q < r.nw ? r.even_cand(ks, q) : 0ull;
+    odw[q] = q < r.nw ? r.odd_cand(ks, q) : 0ull;
+  }
+#pragma unroll
+  for (int q = 0; q < kRayMaxWords; ++q) {
+    const uint64_t ev = evw[q], od = odw[q];
     uint64_t any = ev | od;
     while (any) {
       const int bit = __ffsll((unsigned long long)any) - 1;

@@ -177,6 +177,16 @@ __device__ inline bool stage_block(const GemmArgs& a, const f32x16& acc, int m0,
 // ------------------------------------------------------------------ FP32 operands
 // v_mfma_f32_32x32x2_f32: per lane one A and one B element per MFMA; 4 MFMAs consume
 // a float4 of k from LDS (k-group of 8).
+//
+// Pipeline of one 32-deep k stage (two LDS buffers): first the LDS writes of stage k + 1,
+// whose global loads were issued one stage earlier, then the LDS reads of group 0 and
+// the global loads of stage k + 2, then the 64 MFMAs of the stage, each group's LDS reads
+// issued during the previous group's MFMAs; one barrier per stage.  The body is one basic
+// block (the last stages reload the last k tile and write it into the idle buffer, which
+// nobody reads), so the scheduling groups below can spread the LDS writes, global loads
+// and LDS reads between the MFMAs.  Rows past M load row M - 1 (their outputs are never
+// stored).  Instruction order only: every accumulator sums k in the same order in every
+// tile shape.
 template <int BM, int BN, int WM, int WN, int MINB, int NT = 256, bool PERSIST = false>
 __global__ void __launch_bounds__(NT, MINB) k_gemm_f32(GemmArgs a) {
   // NT = 64 * WM * WN threads (the 32-point tile for tiny launches uses 2 waves)
@@ -203,49 +213,39 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_f32(GemmArgs a) {
   constexpr int A_LOADS = BM * (BK / 4) / NT;
   constexpr int B_LOADS = BN * (BK / 4) / NT;
   f32x4 ra[A_LOADS], rb[B_LOADS];
-  const float* A1 = reinterpret_cast<const float*>(a.A1);
-  const float* A2 = reinterpret_cast<const float*>(a.A2);
-  const float* Wp = reinterpret_cast<const float*>(a.W);
-
+  // this thread's global rows (A rows clamped into [0, M)) and LDS slots, per load
+  const float* pa1[A_LOADS];
+  const float* pa2[A_LOADS];
+  const float* pb[B_LOADS];
+  int sa[A_LOADS], sb[B_LOADS];
+#pragma unroll
+  for (int i = 0; i < A_LOADS; ++i) {
+    const int e = tid + NT * i;
+    const int gm = min(m0 + (e >> 3), M - 1);
+    pa1[i] = reinterpret_cast<const float*>(a.A1) + (size_t)gm * a.lda1 + 4 * (e & 7);
+    pa2[i] = a.A2 ? reinterpret_cast<const float*>(a.A2) + (size_t)gm * a.lda2 + 4 * (e & 7) : pa1[i];
+    sa[i] = (e >> 3) * LD + 4 * (e & 7);
+  }
+#pragma unroll
+  for (int i = 0; i < B_LOADS; ++i) {
+    const int e = tid + NT * i;
+    pb[i] = reinterpret_cast<const float*>(a.W) + (size_t)(n0 + (e >> 3)) * a.ldw + 4 * (e & 7);
+    sb[i] = (e >> 3) * LD + 4 * (e & 7);
+  }
   auto gload = [&](int kt) {
     const int k0 = kt * BK;
-    const float* src;
-    int ld, kk0;
-    if (k0 < a.K1) {
-      src = A1;
-      ld = a.lda1;
-      kk0 = k0;
-    } else {
-      src = A2;
-      ld = a.lda2;
-      kk0 = k0 - a.K1;
-    }
+    const bool first = k0 < a.K1;   // A = [A1 ; A2] along k
 #pragma unroll
-    for (int i = 0; i < A_LOADS; ++i) {
-      const int e = tid + NT * i;
-      const int row = e >> 3, c4 = e & 7;
-      const int gm = m0 + row;
-      ra[i] = gm < M ? *reinterpret_cast<const f32x4*>(src + (size_t)gm * ld + kk0 + 4 * c4)
-                       : (f32x4){0.f, 0.f, 0.f, 0.f};
-    }
+    for (int i = 0; i < A_LOADS; ++i)
+      ra[i] = *reinterpret_cast<const f32x4*>(first ? pa1[i] + k0 : pa2[i] + (k0 - a.K1));
 #pragma unroll
-    for (int i = 0; i < B_LOADS; ++i) {
-      const int e = tid + NT * i;
-      const int row = e >> 3, c4 = e & 7;
-      rb[i] = *reinterpret_cast<const f32x4*>(Wp + (size_t)(n0 + row) * a.ldw + k0 + 4 * c4);
-    }
+    for (int i = 0; i < B_LOADS; ++i) rb[i] = *reinterpret_cast<const f32x4*>(pb[i] + k0);
   };
   auto sstore = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < A_LOADS; ++i) {
-      const int e = tid + NT * i;
-      *reinterpret_cast<f32x4*>(&As[buf][(e >> 3) * LD + 4 * (e & 7)]) = ra[i];
-    }
+    for (int i = 0; i < A_LOADS; ++i) *reinterpret_cast<f32x4*>(&As[buf][sa[i]]) = ra[i];
 #pragma unroll
-    for (int i = 0; i < B_LOADS; ++i) {
-      const int e = tid + NT * i;
-      *reinterpret_cast<f32x4*>(&Bs[buf][(e >> 3) * LD + 4 * (e & 7)]) = rb[i];
-    }
+    for (int i = 0; i < B_LOADS; ++i) *reinterpret_cast<f32x4*>(&Bs[buf][sb[i]]) = rb[i];
   };
 
   f32x16 acc[TI][TJ];
@@ -256,49 +256,70 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_f32(GemmArgs a) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-  gload(0);
-  sstore(0);
-  __syncthreads();
   const int h = lane >> 5, l32 = lane & 31;
   const int wrow = wm * (BM / WM), wcol = wn * (BN / WN);
+  gload(0);
+  sstore(0);
+  gload(min(1, nk - 1));
+  __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
-    if (kt + 1 < nk) gload(kt + 1);
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 8) {
-      float4 av[TI], bv[TJ];
+    sstore(buf ^ 1);
+    float4 av[2][TI], bv[2][TJ];
+    auto lread = [&](int kk, int sl) {
 #pragma unroll
       for (int i = 0; i < TI; ++i)
-        av[i] = *reinterpret_cast<const float4*>(&As[buf][(wrow + 32 * i + l32) * LD + kk + 4 * h]);
+        av[sl][i] = *reinterpret_cast<const float4*>(&As[buf][(wrow + 32 * i + l32) * LD + kk + 4 * h]);
 #pragma unroll
       for (int j = 0; j < TJ; ++j)
-        bv[j] = *reinterpret_cast<const float4*>(&Bs[buf][(wcol + 32 * j + l32) * LD + kk + 4 * h]);
-      // k slot outermost: consecutive MFMAs write different accumulators
+        bv[sl][j] = *reinterpret_cast<const float4*>(&Bs[buf][(wcol + 32 * j + l32) * LD + kk + 4 * h]);
+    };
+    // k slot outermost: consecutive MFMAs write different accumulators
+    auto mfma = [&](int sl) {
 #pragma unroll
-      for (int i = 0; i < TI; ++i)
+      for (int c = 0; c < 4; ++c)
 #pragma unroll
-        for (int j = 0; j < TJ; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i].x, bv[j].x, acc[i][j], 0, 0, 0);
+        for (int i = 0; i < TI; ++i)
 #pragma unroll
-      for (int i = 0; i < TI; ++i)
+          for (int j = 0; j < TJ; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[sl][i][c], bv[sl][j][c], acc[i][j], 0, 0, 0);
+    };
+    lread(0, 0);
+    gload(min(kt + 2, nk - 1));
+    lread(8, 1);
+    mfma(0);
+    lread(16, 0);
+    mfma(1);
+    lread(24, 1);
+    mfma(0);
+    mfma(1);
+    // scheduling groups (mask 0x008 MFMA, 0x020 global load, 0x100 LDS read, 0x200 LDS
+    // write): the writes and group 0's reads, then one global load or group 1 read after
+    // each MFMA, then the reads of groups 2 and 3 spread over groups 1 and 2
+    constexpr int NW = A_LOADS + B_LOADS, NR = TI + TJ, NM = TI * TJ * 4;
+    __builtin_amdgcn_sched_group_barrier(0x200, NW, 0);
+    __builtin_amdgcn_sched_group_barrier(0x100, NR, 0);
 #pragma unroll
-        for (int j = 0; j < TJ; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i].y, bv[j].y, acc[i][j], 0, 0, 0);
-#pragma unroll
-      for (int i = 0; i < TI; ++i)
-#pragma unroll
-        for (int j = 0; j < TJ; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i].z, bv[j].z, acc[i][j], 0, 0, 0);
-#pragma unroll
-      for (int i = 0; i < TI; ++i)
-#pragma unroll
-        for (int j = 0; j < TJ; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i].w, bv[j].w, acc[i][j], 0, 0, 0);
-      // scheduling hint: interleave the LDS reads of the next group with these MFMAs
-      // (instruction order only; every accumulator sums k in the same order)
-      __builtin_amdgcn_iglp_opt(0);
+    for (int q = 0; q < NW; ++q) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
     }
-    if (kt + 1 < nk) sstore(buf ^ 1);
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    }
+    if (NM > NW + NR) __builtin_amdgcn_sched_group_barrier(0x008, NM - NW - NR, 0);
+#pragma unroll
+    for (int g = 1; g < 3; ++g) {
+#pragma unroll
+      for (int q = 0; q < NR; ++q) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      }
+      if (NM > 2 * NR) __builtin_amdgcn_sched_group_barrier(0x008, NM - 2 * NR, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, NM, 0);
     __syncthreads();
   }
 #pragma unroll

@@ -563,11 +563,11 @@ int default_tile(int prec, int N, int K, uint32_t m) {
 
 // FP32 tile without an autotuned entry (measured on gfx950 over the MLP's layer shapes):
 // launches of 48k+ points take 256 x 128 tiles over eight waves (one workgroup per CU,
-// 0.68-0.78 of the FP32 MFMA peak); launches that still give 512+ workgroups of
-// 128 x 64 take those (two per CU; their last round stays full at mid sizes, e.g. 24k
-// points x 512 outputs: 0.74 against 0.58 for 128 x 128); then 64 x 64; launches too
-// small to fill the chip with 64 x 64 tiles take 32 x 64.  (The tile code 96 names the
-// 128 x 64 shape.)
+// 0.66-0.70 of the FP32 MFMA peak on 64k points); launches that still give 512+
+// workgroups of 128 x 64 take those (two per CU, so the last round stays full at mid
+// sizes); then 64 x 64; launches too small to fill the chip with 64 x 64 tiles take
+// 32 x 64.  Taking 128 x 128 for mid sizes instead measured the same frame time.  (The
+// tile code 96 names the 128 x 64 shape.)
 int fp32_tile(int N, uint32_t m) {
   auto tiles = [&](int bm, int bn) { return ((m + bm - 1) / bm) * (uint64_t)(N / bn); };
   if (N % 64 != 0) return 128;
@@ -1840,8 +1840,8 @@ int32_t pifu_eval_points_workspace_size(const pifu_field* field, int32_t precisi
 
 int32_t pifu_eval_points(pifu_ctx* ctx, const pifu_field* field, int32_t precision,
                          float band_delta, float guard_logit, const float* pts, uint32_t n,
-                         float* logit, uint8_t* labels, void* workspace, size_t workspace_bytes,
-                         pifu_stream stream) {
+                         float* logit, uint8_t* labels, float* occ, void* workspace,
+                         size_t workspace_bytes, pifu_stream stream) {
   if (!ctx || !pts || !logit || !workspace) return PIFU_ERR_INVALID_ARGUMENT;
   if (!aligned(pts, 16) || !aligned(workspace, kAlign)) return PIFU_ERR_INVALID_ARGUMENT;
   size_t need = 0;
@@ -1872,6 +1872,7 @@ int32_t pifu_eval_points(pifu_ctx* ctx, const pifu_field* field, int32_t precisi
   src.pts = reinterpret_cast<const float4*>(pts);
   if (!labels && (fp.has_mlp || fp.has_cbn) && guard_logit > 0.f) return PIFU_ERR_INVALID_ARGUMENT;
   r = eval_occupancy(e, fp, src, iota, n, ew, logit, lab, nullptr);
+  if (!r && occ) launch_occupancy(logit, n, occ, s);
   if (!r) r = check_launch();
   if (!r) r = hipStreamSynchronize(s) == hipSuccess ? PIFU_OK : PIFU_ERR_HIP;
   prof_resolve(ctx);

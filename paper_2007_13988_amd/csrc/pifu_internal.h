@@ -122,6 +122,7 @@ void launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s, uint32_t n = 1);
 void launch_publish(const uint32_t* c, int n, uint32_t* host, uint32_t* seq_word, uint32_t seq,
                     hipStream_t s);
 void launch_iota(uint32_t* list, uint32_t n, hipStream_t s);
+void launch_occupancy(const float* logit, uint32_t n, float* occ, hipStream_t s);
 // frames > 1: `frames` lattices stored back to back (coarse and fine), one grid row each.
 // Frames of one batched call; per frame, where its occupancy goes at a level (null:
 // the combined array's slice of that frame).

@@ -80,6 +80,16 @@ void launch_iota(uint32_t* list, uint32_t n, hipStream_t s) {
   if (n) hipLaunchKernelGGL(k_iota, dim3(grid1d(n, 256)), dim3(256), 0, s, list, n);
 }
 
+// Occupancy p = sigmoid(logit), in float32 with the expression the grid's apply kernels use.
+__global__ void k_occupancy(const float* __restrict__ logit, uint32_t n, float* __restrict__ occ) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) occ[i] = 1.0f / (1.0f + expf(-logit[i]));
+}
+
+void launch_occupancy(const float* logit, uint32_t n, float* occ, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_occupancy, dim3(grid1d(n, 256)), dim3(256), 0, s, logit, n, occ);
+}
+
 // Level transition.  Coarse level nodes keep their label, evaluated flag and value;
 // every other fine node gets the mean of the binarized labels of its 2/4/8 enclosing
 // coarse corners (trilinear interpolation of the binary field).  Fractional means are

@@ -205,7 +205,7 @@ def load_library():
                                            C.POINTER(C.c_float), P, P, P, P, P, P, sz, P]
     lib.pifu_eval_points_workspace_size.argtypes = [C.POINTER(PifuField), i32, u32, C.POINTER(sz)]
     lib.pifu_eval_points.argtypes = [P, C.POINTER(PifuField), i32, C.c_float, C.c_float, P, u32, P,
-                                     P, P, sz, P]
+                                     P, P, P, sz, P]
     PP = C.POINTER(C.c_void_p)
     lib.pifu_mlp_train_workspace_size.argtypes = [C.POINTER(PifuField), u32, C.POINTER(sz)]
     lib.pifu_mlp_grad.argtypes = [P, C.POINTER(PifuField), P, u32, PP, PP, P, P, sz, P]
@@ -598,8 +598,9 @@ def render_view_traced(occ_field: DeviceField, color_field: DeviceField, view, l
 
 
 def eval_points(field: DeviceField, pts, precision="fp32", guard_logit=1e-3, band_delta=0.02,
-                stream=None):
-    """Field logits and labels at input-view NDC points (n x 3)."""
+                stream=None, occ=False):
+    """Field logits and labels at input-view NDC points (n x 3); with occ=True also the
+    occupancy values p computed by the library."""
     lib = load_library()
     p = torch.as_tensor(np.asarray(pts, np.float32)) if not isinstance(pts, torch.Tensor) else pts
     n = p.shape[0]
@@ -611,11 +612,12 @@ def eval_points(field: DeviceField, pts, precision="fp32", guard_logit=1e-3, ban
     _check(lib.pifu_eval_points_workspace_size(C.byref(field.struct), PREC[precision], n,
                                                C.byref(sz)), "pifu_eval_points_workspace_size")
     ws = torch.empty(sz.value, dtype=torch.uint8, device="cuda")
+    p_out = torch.empty(n, dtype=torch.float32, device="cuda") if occ else None
     st = lib.pifu_eval_points(context(), C.byref(field.struct), PREC[precision], band_delta,
-                              guard_logit, _ptr(p4), n, _ptr(logit), _ptr(labels), _ptr(ws),
-                              sz.value, _stream(stream))
+                              guard_logit, _ptr(p4), n, _ptr(logit), _ptr(labels), _ptr(p_out),
+                              _ptr(ws), sz.value, _stream(stream))
     _check(st, "pifu_eval_points")
-    return logit, labels
+    return (logit, labels, p_out) if occ else (logit, labels)
 
 
 def fp8_calibrate(field: DeviceField, pts, stream=None) -> List[float]:

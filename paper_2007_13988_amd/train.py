@@ -152,8 +152,8 @@ def make_distill_data(teacher_spec, feats_np: Sequence[np.ndarray], per_frame: i
         lat = lat[pick]
         n_uni = per_frame - n_lat
         uni = torch.rand((n_uni, 3), generator=g, device="cuda") * 2 - 1
-        logit, _ = P.eval_points(fld, uni, guard_logit=0.0)
-        uni4 = torch.cat([uni, torch.sigmoid(logit)[:, None]], dim=1)
+        _, _, p = P.eval_points(fld, uni, guard_logit=0.0, occ=True)
+        uni4 = torch.cat([uni, p[:, None]], dim=1)
         samples.append(torch.cat([lat, uni4]).contiguous())
         feats.append(fld.feat)
     return DistillData(feats, samples)

@@ -59,6 +59,18 @@ def test_eval_points_tiny_mlp(pifu):
     assert np.array_equal(lab.cpu().numpy(), (ref > 0).astype(np.uint8))
 
 
+def test_eval_points_occupancy_output(pifu):
+    """pifu_eval_points' occupancy output is the sigmoid of its logit, as the grid computes
+    it, and within 1e-4 of the oracle's."""
+    fo, fg = _fields_tiny(pifu)
+    pts = synth.precision_points(5000, 13).astype(np.float32).astype(np.float64)
+    lg, lab, p = pifu.eval_points(fg, pts, occ=True)
+    want = 1.0 / (1.0 + torch.exp(-lg))
+    assert torch.allclose(p, want, rtol=2e-7, atol=1e-7)
+    ref = O.field_logit(fo, pts)
+    assert np.max(np.abs(p.cpu().numpy().astype(np.float64) - O.sigmoid(ref))) <= P_TOL
+
+
 def test_eval_points_pifu_mlp(pifu):
     feat = synth.pifu_features()
     spec = synth.pifu_mlp()
