@@ -429,10 +429,11 @@ def baselines(P, synth, ms_grid_fp32, args):
     return res
 
 
-def cbn_and_mesh(P, synth, feat, t_net, col_field, reps=5):
+def cbn_and_mesh(P, synth, feat, t_net, col_field, ms_grid_mlp, reps=5):
     """The appendix's CBN + SoftZ network on the benchmarked grid (256^3 from 32^3, FP32,
-    same 256-channel features), and the mesh hand-off (Marching Cubes with vertex colours)
-    of the plain FP32 frame's grid."""
+    same 256-channel features, carrying the same depth slab as the benchmark's MLP), and
+    the mesh hand-off (Marching Cubes with vertex colours) of the plain FP32 frame's
+    grid."""
     import numpy as np
     import torch
 
@@ -446,7 +447,7 @@ def cbn_and_mesh(P, synth, feat, t_net, col_field, reps=5):
         return (time.perf_counter() - t0) / n * 1e3
 
     res = {}
-    spec = synth.cbn_net()
+    spec = synth.pifu_cbn()
     cf = P.DeviceField.cbn_field(feat, spec)
     out = P.GridOutputs(cf, P.grid_opts(8, 5))
     ms = timed(lambda: P.occupancy_grid_into(cf, out), reps)
@@ -460,6 +461,8 @@ def cbn_and_mesh(P, synth, feat, t_net, col_field, reps=5):
         "flop_per_point_unhoisted": flop_pt,
         "gflop_per_4096_calls": round(flop_pt * 4096 / 1e9, 3),
         "algorithmic_tflop_per_s": round(pts * flop_pt / (ms * 1e-3) / 1e12, 2),
+        "mlp_grid_ms_same_frame": round(ms_grid_mlp, 3) if ms_grid_mlp else None,
+        "ms_vs_mlp_grid": round(ms / ms_grid_mlp, 3) if ms_grid_mlp else None,
         "network": f"SoftZ n_z={nz} -> {nb} CBN blocks of width {w} conditioned on {c} "
                    "channels -> 1, gamma/beta hoisted per (x, y) column",
         "note": "algorithmic rate counts every point's unhoisted FLOPs (Tab. 2's formulation)"}
@@ -811,7 +814,7 @@ def main():
         log("octree trade-off")
         out["octree_tradeoff"] = octree_tradeoff(P, synth)
         log("CBN network and mesh hand-off")
-        out["cbn_and_mesh"] = cbn_and_mesh(P, synth, feat, t_net, col_field)
+        out["cbn_and_mesh"] = cbn_and_mesh(P, synth, feat, t_net, col_field, main_r["ms_occ"])
     if args.batched:
         log("batched")
         out["batched"] = batched_bench(P, synth, max(1, min(args.steps, 3)))

@@ -318,3 +318,81 @@ def cbn_net(feat_dim: int = 256, n_z: int = 64, width: int = 128, n_blocks: int 
         mean=[(g.standard_normal(width) * 0.1).astype(f32) for _ in range(n_blocks)],
         var=[g.uniform(0.5, 1.5, width).astype(f32) for _ in range(n_blocks)],
         Wo=lin(1, width, np.sqrt(1.0 / width)), bo=np.full(1, out_bias, f32))
+
+
+def depth_slab_cbn(spec: CBNSpec, seed: int, kappa: float = 16.0, mu_scale: float = 0.3,
+                   tau0: float = -0.05, tau_scale: float = 0.25, eps: float = 0.1) -> CBNSpec:
+    """The depth-slab field of depth_slab_mlp built into a CBN network: units 0-3 of every
+    block carry u0 = relu(z - mu(c)), u1 = relu(mu(c) - z), t+ = relu(tau(c)),
+    t- = relu(-tau(c)) with mu(c) = mu_scale * a.c and tau(c) = tau0 + tau_scale * b.c.
+    The depth layer writes z on units 0 and 1 (the soft one-hot code interpolates the bin
+    positions linearly, so Wp[:, j] = -1 + 2 j / (n_z - 1) reproduces P_z exactly) and 0 on
+    units 2 and 3; block 0's batch norm is the identity on them (mean 0, variance
+    1 - eps_bn) and its conditional scale and shift give the four units (gamma = +1 / -1 /
+    0 / 0, beta = -mu / +mu / tau / -tau); later blocks pass them through.  The head reads
+    kappa * (t+ - t- - u0 - u1 + eps * r) with r the random head over the other units.
+    The same seed as depth_slab_mlp gives the same directions a, b, hence the same slab.
+    The other units keep their random weights, so the arithmetic per point is unchanged."""
+    assert spec.width >= 4
+    g = rng(seed)
+    C = spec.feat_dim
+    a = g.standard_normal(C)
+    a /= np.linalg.norm(a)
+    b = g.standard_normal(C)
+    b /= np.linalg.norm(b)
+    f32 = np.float32
+    zpos = -1.0 + 2.0 * np.arange(spec.n_z) / (spec.n_z - 1)
+    Wp = spec.Wp.astype(np.float64)
+    bp = spec.bp.astype(np.float64)
+    Wp[:4, :] = 0.0
+    Wp[0, :] = zpos
+    Wp[1, :] = zpos
+    bp[:4] = 0.0
+    W = [w.astype(np.float64) for w in spec.W]
+    B = [x.astype(np.float64) for x in spec.b]
+    for l in range(len(W)):
+        W[l][:4, :] = 0.0
+        for k in range(4):
+            W[l][k, k] = 1.0
+        B[l][:4] = 0.0
+    Wg = [w.astype(np.float64) for w in spec.Wg]
+    bg = [x.astype(np.float64) for x in spec.bg]
+    Wb = [w.astype(np.float64) for w in spec.Wb]
+    bb = [x.astype(np.float64) for x in spec.bb]
+    mean = [m.astype(np.float64) for m in spec.mean]
+    var = [v.astype(np.float64) for v in spec.var]
+    for i in range(spec.n_blocks):
+        Wg[i][:4, :] = 0.0
+        Wb[i][:4, :] = 0.0
+        mean[i][:4] = 0.0
+        var[i][:4] = 1.0 - spec.eps
+        if i == 0:
+            bg[i][:4] = [1.0, -1.0, 0.0, 0.0]
+            Wb[i][0, :] = -mu_scale * a
+            Wb[i][1, :] = mu_scale * a
+            Wb[i][2, :] = tau_scale * b
+            Wb[i][3, :] = -tau_scale * b
+            bb[i][:4] = [0.0, 0.0, tau0, -tau0]
+        else:
+            bg[i][:4] = 1.0
+            bb[i][:4] = 0.0
+    Wo = spec.Wo.astype(np.float64)
+    Wo[:, 4:] *= eps
+    Wo[:, :4] = np.array([-1.0, -1.0, 1.0, -1.0])
+    Wo *= kappa
+    bo = spec.bo.astype(np.float64) * kappa * eps
+    c = lambda x: np.ascontiguousarray(x.astype(f32))
+    return CBNSpec(spec.feat_dim, spec.n_z, spec.width, spec.n_blocks, Wp=c(Wp), bp=c(bp),
+                   W=[c(w) for w in W], b=[c(x) for x in B], Wg=[c(w) for w in Wg],
+                   bg=[c(x) for x in bg], Wb=[c(w) for w in Wb], bb=[c(x) for x in bb],
+                   mean=[c(m) for m in mean], var=[c(v) for v in var], Wo=c(Wo), bo=c(bo),
+                   eps=spec.eps)
+
+
+def pifu_cbn(seed: int = 212):
+    """The appendix's CBN + SoftZ network at the paper's size (SoftZ n_z = 64, five CBN
+    blocks of width 128 on 256 feature channels) carrying the benchmark's depth-slab field
+    (the slab of pifu_mlp(): same directions).  The other units are batch-normalised, so
+    their head term is larger than the He-init MLP's; eps = 0.02 gives a slab of about the
+    same occupancy and surface area."""
+    return depth_slab_cbn(cbn_net(seed=seed, out_bias=0.0), 203, eps=0.02)

@@ -34,9 +34,10 @@ def _tiny(P, n_blocks=3, seed=7):
     return O.Field("cbn", feat=feat, mlp=spec), P.DeviceField.cbn_field(feat, spec)
 
 
-def _paper(P):
+def _paper(P, slab=False):
+    """The paper-size network: random weights, or carrying the benchmark's depth slab."""
     feat = synth.pifu_features()
-    spec = synth.cbn_net()
+    spec = synth.pifu_cbn() if slab else synth.cbn_net()
     return O.Field("cbn", feat=feat, mlp=spec), P.DeviceField.cbn_field(feat, spec)
 
 
@@ -107,8 +108,9 @@ def test_grid_tiny_cbn(pifu, L, l0):
     _grid_parity(g, ref)
 
 
-def test_grid_paper_size_cbn_64(pifu):
-    fo, fg = _paper(pifu)
+@pytest.mark.parametrize("slab", [False, True])
+def test_grid_paper_size_cbn_64(pifu, slab):
+    fo, fg = _paper(pifu, slab)
     g = pifu.occupancy_grid(fg, 6, 4, eval_level=True)
     ref = O.occupancy_grid(fo, 6, 4)
     _grid_parity(g, ref)
@@ -131,9 +133,10 @@ def test_octree_binarized_cbn(pifu):
     assert g["n_cells"] == o["cells"].size
 
 
-def test_sampled_nodes_at_benchmark_size(pifu):
+@pytest.mark.parametrize("slab", [False, True])
+def test_sampled_nodes_at_benchmark_size(pifu, slab):
     """256^3 cells from 32^3 on the 256-channel features: sampled evaluated nodes."""
-    fo, fg = _paper(pifu)
+    fo, fg = _paper(pifu, slab)
     out = pifu.occupancy_grid(fg, 8, 5, eval_level=True)
     lab = out["labels"].cpu().numpy()
     occ = out["occ"].cpu().numpy()

@@ -86,3 +86,29 @@ def test_field_has_a_surface():
     lg = O.field_logit(fld, P)
     frac = float(np.mean(lg > 0))
     assert 0.05 < frac < 0.95, frac
+
+
+def test_network_carrying_a_closed_form_field():
+    """A CBN network built to carry the depth-slab field (synth.depth_slab_cbn with the
+    random head term switched off) gives kappa * (tau(c) - |z - mu(c)|) exactly up to
+    float32 weights: units 0-3 pass the batch norms unchanged (mean 0, variance 1 - eps)
+    and the conditional shifts supply mu and tau.  A dropped term, a wrong sign or a
+    transposed map changes the logit by O(1)."""
+    import math
+    spec = synth.depth_slab_cbn(synth.cbn_net(feat_dim=32, n_z=16, width=64, n_blocks=3,
+                                              seed=4, out_bias=0.0), 9, eps=0.0)
+    rng = np.random.default_rng(2)
+    f = rng.standard_normal((300, 32))
+    z = rng.uniform(-1, 1, 300)
+    g = synth.rng(9)
+    a = g.standard_normal(32)
+    a /= np.linalg.norm(a)
+    b = g.standard_normal(32)
+    b /= np.linalg.norm(b)
+    mu = f @ (0.3 * a).astype(np.float32).astype(np.float64)
+    tau = f @ (0.25 * b).astype(np.float32).astype(np.float64) + np.float64(np.float32(-0.05))
+    want = 16.0 * (tau - np.abs(z - mu))
+    bn = 1.0 / math.sqrt(float(np.float32(1.0 - spec.eps)) + spec.eps)   # ~1 + 5e-9
+    got = O.cbn_logit(spec, f, z)
+    # the bin positions -1 + 2 j / 15 are float32 weights: z is reproduced to ~6e-8
+    assert np.max(np.abs(got - want * bn)) <= 2e-6
