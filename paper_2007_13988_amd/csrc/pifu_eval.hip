@@ -777,6 +777,93 @@ void launch_hoist_layer0(const float* P, int ldp, const uint32_t* cid, const uin
                        cid, list, n, n_dev, nz, wz, N, act, h, h_fmt, ovf);
 }
 
+// ------------------------------------------------------------------ per-texel hoisting
+// Every layer that reads the sampled feature f is linear in f before its activation, and
+// f is the bilinear blend of four texels, so W_f f = sum_t w_t (W_f F[texel_t]): the
+// products W_f F of all texels are computed once per call (a GEMM over the feature map)
+// and each point blends four rows of them.  This holds for any point, in any view.
+__global__ void k_taps(PointSrc src, const uint32_t* __restrict__ list, uint32_t n,
+                       const uint32_t* __restrict__ n_dev, int H, int W, int4* __restrict__ tidx,
+                       float4* __restrict__ tw, float* __restrict__ ext) {
+  const uint32_t ne = eff_count(n, n_dev);
+  for (uint32_t m = blockIdx.x * blockDim.x + threadIdx.x; m < ne; m += gridDim.x * blockDim.x) {
+    double P[3];
+    float occ = 0.f;
+    const bool in = src_point(src, list, m, P, &occ);
+    int u0, v0;
+    double w[4];
+    bilinear_setup(P[0], P[1], H, W, u0, v0, w);
+    const int tu[4] = {u0, u0 + 1, u0, u0 + 1};
+    const int tv[4] = {v0, v0, v0 + 1, v0 + 1};
+    int id[4];
+    float wf[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const bool ok = tu[t] >= 0 && tu[t] <= W - 1 && tv[t] >= 0 && tv[t] <= H - 1;
+      id[t] = ok ? tv[t] * W + tu[t] : 0;
+      wf[t] = ok ? (float)w[t] : 0.f;
+    }
+    tidx[m] = make_int4(id[0], id[1], id[2], id[3]);
+    tw[m] = make_float4(wf[0], wf[1], wf[2], wf[3]);
+    *reinterpret_cast<float4*>(ext + 4 * (size_t)m) = make_float4((float)P[2], occ, in ? 0.f : 1.f, 0.f);
+  }
+}
+
+void launch_taps(const PointSrc& src, const uint32_t* list, uint32_t n, int H, int W, int4* tidx,
+                 float4* tw, float* ext, hipStream_t s, const uint32_t* n_dev) {
+  if (n)
+    hipLaunchKernelGGL(k_taps, dim3(list_grid(n, 256, n_dev)), dim3(256), 0, s, src, list, n,
+                       n_dev, H, W, tidx, tw, ext);
+}
+
+__global__ void k_taps_layer0(const float* __restrict__ T, int ldt, const int4* __restrict__ tidx,
+                              const float4* __restrict__ tw, const float* __restrict__ ext,
+                              uint32_t n, const uint32_t* __restrict__ n_dev,
+                              const float* __restrict__ bias, const float* __restrict__ wz, int N,
+                              int act, float* __restrict__ h) {
+  // four consecutive outputs per thread (N % 4 == 0, ldt % 4 == 0)
+  const uint32_t n4 = (uint32_t)N >> 2;
+  const uint32_t ne = eff_count(n, n_dev);
+  for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < ne * n4;
+       e += gridDim.x * blockDim.x) {
+    const uint32_t i = e / n4;
+    const uint32_t o = (e - i * n4) << 2;
+    const int4 id = tidx[i];
+    const float4 w = tw[i];
+    const float z = ext[4 * (size_t)i];
+    const int ids[4] = {id.x, id.y, id.z, id.w};
+    const float ws[4] = {w.x, w.y, w.z, w.w};
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const float4 p = *reinterpret_cast<const float4*>(T + (size_t)ids[t] * ldt + o);
+      acc.x = fmaf(ws[t], p.x, acc.x);
+      acc.y = fmaf(ws[t], p.y, acc.y);
+      acc.z = fmaf(ws[t], p.z, acc.z);
+      acc.w = fmaf(ws[t], p.w, acc.w);
+    }
+    const float4 b = *reinterpret_cast<const float4*>(bias + o);
+    const float4 wzv = *reinterpret_cast<const float4*>(wz + o);
+    float v[4] = {fmaf(z, wzv.x, acc.x + b.x), fmaf(z, wzv.y, acc.y + b.y),
+                  fmaf(z, wzv.z, acc.z + b.z), fmaf(z, wzv.w, acc.w + b.w)};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (act == PIFU_ACT_RELU) v[q] = v[q] > 0.f ? v[q] : 0.f;
+      else if (act == PIFU_ACT_LRELU) v[q] = v[q] > 0.f ? v[q] : 0.01f * v[q];
+    }
+    *reinterpret_cast<float4*>(h + (size_t)i * N + o) = make_float4(v[0], v[1], v[2], v[3]);
+  }
+}
+
+void launch_taps_layer0(const float* T, int ldt, const int4* tidx, const float4* tw,
+                        const float* ext, uint32_t n, const float* bias, const float* wz, int N,
+                        int act, float* h, hipStream_t s, const uint32_t* n_dev) {
+  const size_t tot = (size_t)n * (N >> 2);
+  if (tot)
+    hipLaunchKernelGGL(k_taps_layer0, dim3(list_grid(tot, 256, n_dev)), dim3(256), 0, s, T, ldt,
+                       tidx, tw, ext, n, n_dev, bias, wz, N, act, h);
+}
+
 // The library's number-format conversions applied to an array (for checking them).
 __global__ void k_convert(const float* __restrict__ in, uint32_t n, int fmt, void* __restrict__ out) {
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;

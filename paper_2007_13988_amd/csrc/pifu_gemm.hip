@@ -70,7 +70,7 @@ __device__ inline float act_apply(float v, int act) {
 // Epilogue: 32x32 accumulator block -> C in format OUT (FMT_*).  Output layout of a
 // 32x32 MFMA block: lane l, register r holds row 8*(r/4) + 4*(l/32) + (r%4), column l%32.
 // FMT_F16: a value outside the binary16 range sets *a.ovf.
-template <int OUT>
+template <int OUT, bool TAPS = false>
 __device__ inline void store_block(const GemmArgs& a, const f32x16& acc, int row0, int col0,
                                    int lane, int M) {
   const int col = col0 + (lane & 31);
@@ -85,7 +85,27 @@ __device__ inline void store_block(const GemmArgs& a, const f32x16& acc, int row
   float v[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) v[r] = acc[r] * a.scale + bias;
-  if (a.rowadd) {
+  if constexpr (TAPS) {
+    // per-texel hoisting: blend the four texel rows of each point
+    // (four rows at a time: the scheduling barrier keeps the loads of only four rows in
+    // flight, so the blend needs few registers beside the accumulators)
+    const float* rb = a.rowadd + a.rowadd_off + col;
+    const size_t ld = (size_t)a.rowadd_ld;
+#pragma unroll
+    for (int r0 = 0; r0 < 16; r0 += 4) {
+#pragma unroll
+      for (int r = r0; r < r0 + 4; ++r) {
+        const int4 ti = a.tap_idx[rr[r]];
+        const float4 tw = a.tap_w[rr[r]];
+        float t = tw.x * rb[(size_t)ti.x * ld];
+        t = fmaf(tw.y, rb[(size_t)ti.y * ld], t);
+        t = fmaf(tw.z, rb[(size_t)ti.z * ld], t);
+        t = fmaf(tw.w, rb[(size_t)ti.w * ld], t);
+        v[r] += t;
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  } else if (a.rowadd) {
     uint32_t ix[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) ix[r] = a.rowadd_idx[rr[r]];
@@ -187,8 +207,10 @@ __device__ inline bool stage_block(const GemmArgs& a, const f32x16& acc, int m0,
 // and LDS reads between the MFMAs.  Rows past M load row M - 1 (their outputs are never
 // stored).  Instruction order only: every accumulator sums k in the same order in every
 // tile shape.
-template <int BM, int BN, int WM, int WN, int MINB, int NT = 256, bool PERSIST = false>
+template <int BM, int BN, int WM, int WN, int MINB, int NT = 256, bool PERSIST = false,
+          bool TAPS = false>
 __global__ void __launch_bounds__(NT, MINB) k_gemm_f32(GemmArgs a) {
+  // TAPS: the epilogue blends four texel rows per point (per-texel hoisting)
   // NT = 64 * WM * WN threads (the 32-point tile for tiny launches uses 2 waves)
   constexpr int BK = 32;
   constexpr int LD = BK + 4;
@@ -326,7 +348,7 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_f32(GemmArgs a) {
   for (int i = 0; i < TI; ++i)
 #pragma unroll
     for (int j = 0; j < TJ; ++j)
-      store_block<FMT_F32>(a, acc[i][j], m0 + wrow + 32 * i, n0 + wcol + 32 * j, lane, M);
+      store_block<FMT_F32, TAPS>(a, acc[i][j], m0 + wrow + 32 * i, n0 + wcol + 32 * j, lane, M);
   if (PERSIST) __syncthreads();   // LDS is reused by the next tile
   }
 }
@@ -945,12 +967,6 @@ void launch_pack_fp8(const float* W, int N, int ldw, int K, uint32_t* amax_bits,
       hipLaunchKernelGGL(K, G, B, SH, ST, __VA_ARGS__);                                          \
   } while (0)
 
-// Tile shapes per point tile BM (the autotuned parameter) and output tile BN:
-//   BM 64: waves 1x4 (BN 128) / 2x2 (BN 64); BM 128: 2x2 / 4x1; BM 256: 2x2 / 4x1.
-// Every variant walks k in the same order, so results do not depend on BM.
-#define PIFU_F32(BM_, BN_, WM_, WN_, MB_) \
-  PIFU_GO((k_gemm_f32<BM_, BN_, WM_, WN_, MB_>), dim3(row_tiles(a.M, BM_), a.N / BN_), \
-                     dim3(256), 0, s, a)
 #define PIFU_H16(BM_, BN_, WM_, WN_, MB_, F16_)                                                  \
   do {                                                                                           \
     if (a.c_bf16)                                                                                \
@@ -960,6 +976,34 @@ void launch_pack_fp8(const float* W, int N, int ldw, int K, uint32_t* amax_bits,
       PIFU_GO((k_gemm_h16<BM_, BN_, WM_, WN_, MB_, false, F16_>),                     \
                          dim3(row_tiles(a.M, BM_), a.N / BN_), dim3(256), 0, s, a);             \
   } while (0)
+
+// FP32 tiles: 256: 256 x 128 (or 256 x 64) over eight waves; 128: 128 x 128 (or 128 x 64);
+// 96: 128 x 64; 64: 64 x 64; 32: 32 x 64 tiles of two 32 x 32 waves (tiny launches spread
+// over more CUs).  Every shape walks k in the same order.
+template <bool TAPS>
+void launch_f32(const GemmArgs& a, int bm, bool bn128, hipStream_t s, hipEvent_t ev0,
+                hipEvent_t ev1) {
+  if (bm == 32) {
+    PIFU_GO((k_gemm_f32<32, 64, 1, 2, 2, 128, false, TAPS>), dim3(row_tiles(a.M, 32), a.N / 64),
+            dim3(128), 0, s, a);
+  } else if (bm == 256) {
+    if (bn128)
+      PIFU_GO((k_gemm_f32<256, 128, 4, 2, 1, 512, false, TAPS>), dim3(row_tiles(a.M, 256), a.N / 128),
+              dim3(512), 0, s, a);
+    else
+      PIFU_GO((k_gemm_f32<256, 64, 4, 2, 1, 512, false, TAPS>), dim3(row_tiles(a.M, 256), a.N / 64),
+              dim3(512), 0, s, a);
+  } else if (bm == 128 && bn128) {
+    PIFU_GO((k_gemm_f32<128, 128, 2, 2, 2, 256, false, TAPS>), dim3(row_tiles(a.M, 128), a.N / 128),
+            dim3(256), 0, s, a);
+  } else if (bm == 128 || bm == 96) {
+    PIFU_GO((k_gemm_f32<128, 64, 2, 2, 2, 256, false, TAPS>), dim3(row_tiles(a.M, 128), a.N / 64),
+            dim3(256), 0, s, a);
+  } else {
+    PIFU_GO((k_gemm_f32<64, 64, 2, 2, 2, 256, false, TAPS>), dim3(row_tiles(a.M, 64), a.N / 64),
+            dim3(256), 0, s, a);
+  }
+}
 
 template <bool F16>
 void launch_h16(const GemmArgs& a, int bm, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
@@ -1003,8 +1047,12 @@ int launch_gemm_persist(const GemmArgs& a, int precision, hipStream_t s) {
   };
   if (precision == PIFU_PREC_FP32) {
     if ((a.K1 % 32) || (a.K2 % 32)) return -1;
-    if (bn128)
+    if (bn128 && a.tap_idx)
+      hipLaunchKernelGGL((k_gemm_f32<128, 128, 2, 2, 2, 256, true, true>), grid(128, 128), dim3(256), 0, s, a);
+    else if (bn128)
       hipLaunchKernelGGL((k_gemm_f32<128, 128, 2, 2, 2, 256, true>), grid(128, 128), dim3(256), 0, s, a);
+    else if (a.tap_idx)
+      hipLaunchKernelGGL((k_gemm_f32<128, 64, 4, 1, 2, 256, true, true>), grid(128, 64), dim3(256), 0, s, a);
     else
       hipLaunchKernelGGL((k_gemm_f32<128, 64, 4, 1, 2, 256, true>), grid(128, 64), dim3(256), 0, s, a);
     return 0;
@@ -1048,28 +1096,8 @@ int launch_gemm(const GemmArgs& a, int precision, int tile_m, hipStream_t s, hip
   int bm = tile_m == 64 ? 64 : (tile_m == 256 ? 256 : (tile_m == 32 ? 32 : (tile_m == 96 ? 96 : 128)));
   if (precision == PIFU_PREC_FP32) {
     if ((a.K1 % 32) || (a.K2 % 32)) return -1;
-    if (bm == 32) {
-      // tiny launches: 32 x 64 tiles of two 32 x 32 waves spread the work over more CUs
-      PIFU_GO((k_gemm_f32<32, 64, 1, 2, 2, 128>), dim3(row_tiles(a.M, 32), a.N / 64),
-                         dim3(128), 0, s, a);
-      return 0;
-    }
-    // 256: 256 x 128 (or 256 x 64) over eight waves; 128: 128 x 128 (or 128 x 64);
-    // 96: 128 x 64; 64: 64 x 64.  Every shape walks k in the same order.
-    if (bm == 256) {
-      if (bn128)
-        PIFU_GO((k_gemm_f32<256, 128, 4, 2, 1, 512>), dim3(row_tiles(a.M, 256), a.N / 128),
-                dim3(512), 0, s, a);
-      else
-        PIFU_GO((k_gemm_f32<256, 64, 4, 2, 1, 512>), dim3(row_tiles(a.M, 256), a.N / 64),
-                dim3(512), 0, s, a);
-    } else if (bm == 128 && bn128) {
-      PIFU_F32(128, 128, 2, 2, 2);
-    } else if (bm == 128 || bm == 96) {
-      PIFU_F32(128, 64, 2, 2, 2);
-    } else {
-      PIFU_F32(64, 64, 2, 2, 2);
-    }
+    if (a.tap_idx) launch_f32<true>(a, bm, bn128, s, ev0, ev1);
+    else launch_f32<false>(a, bm, bn128, s, ev0, ev1);
     return 0;
   }
   if (precision == PREC_F32X3) {

@@ -344,6 +344,12 @@ struct EvalWs {
   uint32_t *cflags = nullptr, *cexcl = nullptr, *cid = nullptr, *cnode = nullptr, *cscan = nullptr;
   float* Pcol = nullptr;     // col_rows x NP
   uint32_t col_rows = 0;
+  // per-texel hoisting (points in any view, FP32 runs of the network ttex_mlp): the
+  // feature terms of every texel (H W x NP, no biases) and each point's four taps
+  float* Ttex = nullptr;
+  const MlpPrep* ttex_mlp = nullptr;
+  int4* tidx = nullptr;
+  float4* tw = nullptr;
 };
 
 struct FieldPrep {
@@ -503,6 +509,18 @@ void carve_hoist(Carver& cv, int NP, EvalWs& ew, uint32_t col_cap = 0) {
   ew.Pcol = cv.take<float>((size_t)ew.col_rows * NP);
 }
 
+// Buffers of per-texel hoisting for the occupancy network of an MLP field (whose layer 0
+// reads [f; z]): the texel table and the taps of one chunk.
+void carve_texel(Carver& cv, const FieldPrep& fp, EvalWs& ew) {
+  if (!fp.has_mlp) return;
+  const MlpPrep& mp = fp.mlp;
+  if (mp.NP <= 0 || mp.NP % 4 || mp.d.widths[0] % 4 || mp.hoist_off[0] != 0) return;
+  ew.Ttex = cv.take<float>((size_t)fp.f->H * fp.f->W * mp.NP);
+  ew.tidx = cv.take<int4>(ew.chunk);
+  ew.tw = cv.take<float4>(ew.chunk);
+  ew.ttex_mlp = &fp.mlp;
+}
+
 // Feature channels and widest hidden layer of a network field (0 for analytic fields).
 int net_channels(const FieldPrep& fp) { return fp.has_mlp || fp.has_cbn ? fp.f->C : 0; }
 int net_hidden(const FieldPrep& fp) {
@@ -634,7 +652,7 @@ double gemm_bytes(const GemmArgs& g, int prec) {
   const double ew = f32a ? 4.0 : prec == PIFU_PREC_FP8 ? 1.0 : 2.0;   // X3: hi + lo copies
   const double K = (double)g.K1 + g.K2, M = g.M, N = g.N;
   double b = M * K * ea + N * K * ew + M * N * (g.c_bf16 ? 2.0 : 4.0);
-  if (g.rowadd) b += M * N * 4.0;
+  if (g.rowadd) b += g.tap_idx ? M * (N * 16.0 + 32.0) : M * N * 4.0;   // taps: four rows
   if (g.n_ext) b += M * 16.0;
   return b;
 }
@@ -654,6 +672,31 @@ const void* layer_weights(const MlpPrep& mp, int prec, int l) {
   return prec == PIFU_PREC_FP8    ? (const void*)mp.Wp8[l]
          : prec == PIFU_PREC_FP32 ? (const void*)mp.Wp32[l]
                                   : (const void*)mp.Wp16[l];
+}
+
+// The texel table of per-texel hoisting: the feature terms of every layer that reads f,
+// for every texel of the feature map (one FP32 GEMM [H W x C] x [C x NP], no biases).
+// Run once per call, after the network is packed.
+int fill_texel(EvalCtx& e, const FieldPrep& fp, const EvalWs& ew) {
+  if (!ew.Ttex) return PIFU_OK;
+  const MlpPrep& mp = *ew.ttex_mlp;
+  const pifu_field* f = fp.f;
+  GemmArgs g;
+  std::memset(&g, 0, sizeof(g));
+  g.A1 = f->feat;
+  g.K1 = g.lda1 = f->C;
+  g.W = mp.Wf32;
+  g.ldw = f->C;
+  g.C = ew.Ttex;
+  g.ldc = g.N = mp.NP;
+  g.M = f->H * f->W;
+  g.scale = 1.f;
+  ProfScope ps(e.ctx, e.s, PIFU_KERN_GEMM_F32, 2.0 * g.M * g.N * g.K1,
+               gemm_bytes(g, PIFU_PREC_FP32), nullptr, 0.0, 0.0, true);
+  if (launch_gemm(g, PIFU_PREC_FP32, pick_tile(e, PIFU_PREC_FP32, g.N, g.K1, (uint32_t)g.M), e.s,
+                  ps.start(), ps.stop()))
+    return PIFU_ERR_UNSUPPORTED;
+  return PIFU_OK;
 }
 
 // Runs an MLP over n points (chunked): gather -> hidden GEMMs -> head.  prec selects
@@ -767,6 +810,62 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
                 rgb ? lst : nullptr, e.s);
   }
   if (hoist) return check_launch();
+  // other points of one frame in an FP32 run of the network the texel table was built for:
+  // blend four texel rows per point instead of gathering the feature
+  const bool texel = ew.Ttex && &mp == ew.ttex_mlp && prec == PIFU_PREC_FP32 && nseg == 1 &&
+                     !src.frame_nodes && segs[0].F == f->feat && !e.amax;
+  for (uint32_t c0 = 0; c0 < n && texel; c0 += ew.chunk) {
+    const uint32_t m = std::min(ew.chunk, n - c0);
+    const uint32_t* lst = list + c0;
+    {
+      ProfScope ps(e.ctx, e.s, PIFU_KERN_GATHER, 0.0, (double)m * 52.0);
+      PointSrc sq = src;
+      sq.base_sub = segs[0].base_sub;
+      launch_taps(sq, lst, m, f->H, f->W, ew.tidx, ew.tw, ew.ext, e.s);
+    }
+    launch_taps_layer0(ew.Ttex, mp.NP, ew.tidx, ew.tw, ew.ext, m, mp.bf, mp.wz, d.widths[0],
+                       d.hidden_act, reinterpret_cast<float*>(ew.hA), e.s);
+    const void* prev = ew.hA;
+    void* out = ew.hB;
+    for (int l = 1; l + 1 < d.n_layers; ++l) {
+      GemmArgs g;
+      std::memset(&g, 0, sizeof(g));
+      g.A1 = prev;
+      g.K1 = g.lda1 = d.widths[l - 1];
+      g.W = mp.Wp32[l];
+      g.ldw = mp.Kp[l];
+      g.Wf = d.W[l];
+      g.ldwf = d.in_w[l];
+      g.bias = d.b[l];
+      if (mp.hoist_off[l] >= 0) {
+        g.rowadd = ew.Ttex;
+        g.rowadd_ld = mp.NP;
+        g.rowadd_off = mp.hoist_off[l];
+        g.tap_idx = ew.tidx;
+        g.tap_w = ew.tw;
+      }
+      g.C = out;
+      g.ldc = g.N = d.widths[l];
+      g.M = (int)m;
+      g.act = d.hidden_act;
+      g.scale = 1.f;
+      {
+        ProfScope ps(e.ctx, e.s, PIFU_KERN_GEMM_F32, 2.0 * m * g.N * g.K1,
+                     gemm_bytes(g, PIFU_PREC_FP32), nullptr, 0.0, 0.0, true);
+        if (launch_gemm(g, PIFU_PREC_FP32, pick_tile(e, PIFU_PREC_FP32, g.N, g.K1, m), e.s,
+                        ps.start(), ps.stop()))
+          return PIFU_ERR_UNSUPPORTED;
+      }
+      prev = out;
+      out = (out == ew.hA) ? ew.hB : ew.hA;
+    }
+    const int L = d.n_layers - 1;
+    ProfScope ps(e.ctx, e.s, PIFU_KERN_HEAD, 2.0 * m * d.widths[L - 1] * d.widths[L], 0.0);
+    launch_head(reinterpret_cast<const float*>(prev), d.widths[L - 1], d.W[L], d.b[L], d.widths[L],
+                d.out_act, m, ew.ext, logit ? logit + c0 : nullptr, lab ? lab + c0 : nullptr, rgb,
+                rgb ? lst : nullptr, e.s);
+  }
+  if (texel) return check_launch();
   for (uint32_t c0 = 0; c0 < n; c0 += ew.chunk) {
     const uint32_t m = std::min(ew.chunk, n - c0);
     const uint32_t* lst = list + c0;
@@ -1402,6 +1501,7 @@ int plan_render(const pifu_field* occ, const pifu_field* col, const pifu_render_
     carve_eval(cv, (uint32_t)max_n, C, mh, g.ew);
     carve_guard(cv, g.fp, (uint32_t)max_n, g.ew);
   }
+  if (o->precision != PIFU_PREC_FP8) carve_texel(cv, g.fp, g.ew);
   g.bytes = cv.off + kAlign;
   return PIFU_OK;
 }
@@ -1661,6 +1761,10 @@ int32_t render_impl(pifu_ctx* ctx, const pifu_field* occ_field, const pifu_field
   // one clear of the overflow flag per call: by the occupancy network's pack when FP16
   if (int pr = pack_field(g.cp, ctx, s, g.counters,
                           !(g.fp.has_mlp && g.fp.mlp.prec == PIFU_PREC_FP16))) {
+    delete gp;
+    return pr;
+  }
+  if (int pr = fill_texel(e, g.fp, g.ew)) {
     delete gp;
     return pr;
   }
@@ -2769,6 +2873,9 @@ int run_mlp_dev(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, co
   uint32_t* ovf = prec == PIFU_PREC_FP16 || x3 ? e.counters + C_OVF : nullptr;
   const bool hoist = src.mode == 0 && !src.has_view && mp.NP > 0 && mp.NP % 4 == 0 &&
                      d.widths[0] % 4 == 0 && ew.Pcol != nullptr;
+  // per-texel hoisting, as in run_mlp
+  const bool texel = !hoist && ew.Ttex && &mp == ew.ttex_mlp && prec == PIFU_PREC_FP32 &&
+                     !src.frame_nodes && F == f->feat;
   const void* prev = nullptr;
   void* out = ew.hA;
   int l0 = 0;
@@ -2799,6 +2906,13 @@ int run_mlp_dev(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, co
     prev = ew.hA;
     out = ew.hB;
     l0 = 1;
+  } else if (texel) {
+    launch_taps(src, list, cap, f->H, f->W, ew.tidx, ew.tw, ew.ext, e.s, n_dev);
+    launch_taps_layer0(ew.Ttex, mp.NP, ew.tidx, ew.tw, ew.ext, cap, mp.bf, mp.wz, d.widths[0],
+                       d.hidden_act, reinterpret_cast<float*>(ew.hA), e.s, n_dev);
+    prev = ew.hA;
+    out = ew.hB;
+    l0 = 1;
   } else {
     launch_gather(src, list, cap, F, f->H, f->W, C, ew.feat, hf, ew.ext, e.s, n_dev, ovf);
   }
@@ -2818,6 +2932,13 @@ int run_mlp_dev(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, co
         g.rowadd_idx = ew.cid;
         g.rowadd_ld = mp.NP;
         g.rowadd_off = mp.hoist_off[l];
+      } else if (texel && mp.hoist_off[l] >= 0) {
+        g.bias = d.b[l];
+        g.rowadd = ew.Ttex;
+        g.rowadd_ld = mp.NP;
+        g.rowadd_off = mp.hoist_off[l];
+        g.tap_idx = ew.tidx;
+        g.tap_w = ew.tw;
       } else {
         g.bias = d.b[l];
         if (d.skip[l]) {
@@ -3186,6 +3307,7 @@ int32_t pifu_render_view_async(pifu_ctx* ctx, const pifu_field* occ_field,
   r = pack_field(g.fp, ctx, s, g.counters);
   if (!r)
     r = pack_field(g.cp, ctx, s, g.counters, !(g.fp.has_mlp && g.fp.mlp.prec == PIFU_PREC_FP16));
+  if (!r) r = fill_texel(e, g.fp, g.ew);
   double vd[12];
   for (int i = 0; i < 12; ++i) vd[i] = view[i];
   const Lat finL = level_lattice(g.log2, T, T);

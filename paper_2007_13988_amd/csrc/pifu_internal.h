@@ -293,6 +293,11 @@ struct GemmArgs {
   int rowmul_off;
   const float* cbn_mu;
   const float* cbn_rstd;
+  // per-texel hoisting (FP32 output only): with rowadd, each row's term is the bilinear
+  // blend sum_t tap_w[row].t * rowadd[tap_idx[row].t * rowadd_ld + rowadd_off + col] of
+  // four texel rows (rowadd_idx unused); bias is added as usual
+  const int4* tap_idx;
+  const float4* tap_w;
 };
 
 // The conditional-batch-norm lifting network (pifu_cbn) as kernels read it.
@@ -341,6 +346,15 @@ void launch_col_ids(const uint32_t* list, const uint32_t* flags, const uint32_t*
 void launch_hoist_layer0(const float* P, int ldp, const uint32_t* cid, const uint32_t* list,
                          uint32_t n, int nz, const float* wz, int N, int act, void* h, int h_fmt,
                          hipStream_t s, uint32_t* ovf = nullptr, const uint32_t* n_dev = nullptr);
+// Per-texel hoisting: the four bilinear taps (texel index, weight; texels outside the map
+// get weight 0) of each point and its extras as launch_gather writes them.
+void launch_taps(const PointSrc& src, const uint32_t* list, uint32_t n, int H, int W, int4* tidx,
+                 float4* tw, float* ext, hipStream_t s, const uint32_t* n_dev = nullptr);
+// Layer 0 from the texel table T (ldt per texel): h = act(sum_t w_t T[idx_t] + bias + wz z),
+// N outputs (N % 4 == 0), float32 out.
+void launch_taps_layer0(const float* T, int ldt, const int4* tidx, const float4* tw,
+                        const float* ext, uint32_t n, const float* bias, const float* wz, int N,
+                        int act, float* h, hipStream_t s, const uint32_t* n_dev = nullptr);
 
 // float32 -> OCP FP8 E4M3FN code (bias 7, 3 mantissa bits, no infinities), round to
 // nearest even, saturating at +-448; NaN -> 0x7f.
