@@ -1501,7 +1501,11 @@ int plan_render(const pifu_field* occ, const pifu_field* col, const pifu_render_
     carve_eval(cv, (uint32_t)max_n, C, mh, g.ew);
     carve_guard(cv, g.fp, (uint32_t)max_n, g.ew);
   }
-  if (o->precision != PIFU_PREC_FP8) carve_texel(cv, g.fp, g.ew);
+  // the texel table serves FP32 runs of the network: the plain FP32 render and the FP32
+  // band of a BF16 render (an FP16 render's band runs on split-FP16 products and does not
+  // read it; FP8 renders keep the plain path throughout)
+  if (o->precision == PIFU_PREC_FP32 || o->precision == PIFU_PREC_BF16)
+    carve_texel(cv, g.fp, g.ew);
   g.bytes = cv.off + kAlign;
   return PIFU_OK;
 }

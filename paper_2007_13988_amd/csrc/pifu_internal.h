@@ -298,6 +298,10 @@ struct GemmArgs {
   // four texel rows (rowadd_idx unused); bias is added as usual
   const int4* tap_idx;
   const float4* tap_w;
+  // FP32 kernels, set by the launch code (callers leave it 0): every array the epilogue
+  // reads or writes four columns at a time is 16-byte aligned, so the tile is finished
+  // through LDS with 16-byte accesses (else block by block, 4 bytes per lane)
+  int ep_vec;
 };
 
 // The conditional-batch-norm lifting network (pifu_cbn) as kernels read it.
