@@ -567,13 +567,19 @@ uint64_t tile_key(int prec, int N, int K, uint32_t m) {
 }
 
 // Point tile without an autotuned entry: the largest tile that still gives the launch
-// at least 256 workgroups (one per CU).  BF16's 256-point tiles pay off on long
-// contractions (K >= 512) or wide layers (N a multiple of 256, >= 512).
+// at least 256 workgroups (one per CU).  16-bit 256-point tiles pay off on long
+// contractions (K >= 512) or wide layers (N a multiple of 256, >= 512), but not on
+// short contractions into at most 1024 outputs (layer 0 over the feature, K = 256: its
+// four k stages leave each tile bound by load and store latency, which many 64 x 64
+// tiles overlap best; BF16, 65k / 20k points: 127 / 42 us against 144 / 71 us with
+// 256 x 256 tiles) or on 128-wide layers (128 x 128 tiles: 23 against 29 us at 65k).
 int default_tile(int prec, int N, int K, uint32_t m) {
   auto blocks = [&](int bm, int bn) { return ((m + bm - 1) / bm) * (uint64_t)((N + bn - 1) / bn); };
   const int bn128 = N % 128 == 0 ? 128 : 64;
   const bool h16 = prec == PIFU_PREC_BF16 || prec == PIFU_PREC_FP16;
-  if (h16 && (K >= 512 || (N % 256 == 0 && N >= 512)) && blocks(256, N % 256 == 0 ? 256 : bn128) >= 256)
+  if (h16 && K <= 256 && N <= 1024) return 64;
+  if (h16 && N > 128 && (K >= 512 || (N % 256 == 0 && N >= 512)) &&
+      blocks(256, N % 256 == 0 ? 256 : bn128) >= 256)
     return 256;
   if (blocks(128, bn128) >= 256) return 128;
   return 64;
