@@ -587,18 +587,18 @@ int default_tile(int prec, int N, int K, uint32_t m) {
 
 // FP32 tile without an autotuned entry (measured on gfx950 over the MLP's layer shapes):
 // launches of 48k+ points take 256 x 128 tiles over eight waves (one workgroup per CU,
-// 0.66-0.70 of the FP32 MFMA peak on 64k points); launches that still give 512+
-// workgroups of 128 x 64 take those (two per CU, so the last round stays full at mid
-// sizes); then 64 x 64; launches too small to fill the chip with 64 x 64 tiles take
-// 32 x 64.  Taking 128 x 128 for mid sizes instead measured the same frame time.  (The
-// tile code 96 names the 128 x 64 shape.)
+// 0.63-0.72 of the FP32 MFMA peak on 64k points); wide layers from 20k points, and the
+// 1024+-wide column and texel GEMMs, take 128 x 64 tiles while they give 512+
+// workgroups (two per CU); everything else takes 64 x 64 tiles, which beat 32 x 64 ones
+// even where they leave CUs idle (layer 1 at 2k points: 28 against 43 us; the 128-wide
+// last layer at 5k: 10 against 14 us) and 128 x 64 ones up to ~16k points (layer 1 at
+// 9k: 109 against 131 us).  (The tile code 96 names the 128 x 64 shape.)
 int fp32_tile(int N, uint32_t m) {
   auto tiles = [&](int bm, int bn) { return ((m + bm - 1) / bm) * (uint64_t)(N / bn); };
   if (N % 64 != 0) return 128;
   if (m >= 49152) return 256;
-  if (tiles(128, 64) >= 512) return 96;
-  if (tiles(64, 64) >= 256) return 64;
-  return 32;
+  if (tiles(128, 64) >= 512 && (N >= 1024 || (N > 128 && m >= 20480))) return 96;
+  return 64;
 }
 
 int pick_tile(const EvalCtx& e, int prec, int N, int K, uint32_t m) {
