@@ -298,8 +298,12 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_f32(GemmArgs a) {
   // (row-major, LDT floats per row: the two row groups of a 32 x 32 block's store land
   // 32 banks apart) after it
   constexpr int LDT = BN + 8;
-  constexpr int SM_OP = 2 * (BM + BN) * LD, SM_EP = BM * LDT;
-  __shared__ __attribute__((aligned(16))) float smem[SM_OP > SM_EP ? SM_OP : SM_EP];
+  constexpr int SM_OP = 2 * (BM + BN) * LD;
+  // the output tile is staged EPR rows at a time, as many as the operand stages' LDS holds
+  // (the 256 x 128 tile in two halves), so the epilogue adds no LDS to the workgroup
+  constexpr int EPR = BM * LDT <= SM_OP ? BM : BM / 2;
+  static_assert(EPR * LDT <= SM_OP && EPR % (BM / WM) == 0, "output staging");
+  __shared__ __attribute__((aligned(16))) float smem[SM_OP];
   float (*const As)[BM * LD] = reinterpret_cast<float (*)[BM * LD]>(smem);              // As[stage]
   float (*const Bs)[BN * LD] = reinterpret_cast<float (*)[BN * LD]>(smem + 2 * BM * LD);  // Bs[stage]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -434,15 +438,23 @@ __global__ void __launch_bounds__(NT, MINB) k_gemm_f32(GemmArgs a) {
     // tile in LDS, then finish it four columns per lane (persistent tiles keep the block
     // epilogue: their tap variant has no registers to spare for both)
 #pragma unroll
-    for (int i = 0; i < TI; ++i)
+    for (int q = 0; q < BM / EPR; ++q) {
+      // rows [q EPR, (q + 1) EPR) of the tile: whole wave rows, so a wave stages in one
+      // round only
+      if (q > 0) __syncthreads();   // the previous round's rows have been read
+      if (wrow / EPR == q) {
 #pragma unroll
-      for (int j = 0; j < TJ; ++j) {
-        float* t = smem + (wrow + 32 * i + 4 * h) * LDT + wcol + 32 * j + l32;
+        for (int i = 0; i < TI; ++i)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) t[(8 * (r >> 2) + (r & 3)) * LDT] = acc[i][j][r];
+          for (int j = 0; j < TJ; ++j) {
+            float* t = smem + (wrow - q * EPR + 32 * i + 4 * h) * LDT + wcol + 32 * j + l32;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) t[(8 * (r >> 2) + (r & 3)) * LDT] = acc[i][j][r];
+          }
       }
-    __syncthreads();
-    finish_tile<BM, BN, NT, TAPS>(a, smem, LDT, m0, n0, M, tid);
+      __syncthreads();
+      finish_tile<EPR, BN, NT, TAPS>(a, smem, LDT, m0 + q * EPR, n0, M, tid);
+    }
   } else {
 #pragma unroll
     for (int i = 0; i < TI; ++i)
