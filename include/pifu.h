@@ -211,7 +211,10 @@ typedef struct pifu_grid_opts {
  * and y and 2^log2_d cells in z; the coarsest level has 2^log2_coarse_w cells in
  * x and y (and 2^(log2_d - log2_w + log2_coarse_w) in z).  The image is W x H with
  * W = H = 2^log2_w; pixel (row v, column u) is node column (u, v).  Other fields
- * as in pifu_grid_opts.
+ * as in pifu_grid_opts; precision applies to the occupancy network, and the colour
+ * network runs in FP32, or (BF16 and FP16 renders) with FP32-accurate products of
+ * binary16 hi / lo operand splits, re-run in FP32 if an operand leaves the binary16
+ * range.
  */
 typedef struct pifu_render_opts {
   int32_t log2_w;

@@ -1487,9 +1487,11 @@ int plan_render(const pifu_field* occ, const pifu_field* col, const pifu_render_
   g.hitlist = cv.take<uint32_t>(ncol);
   g.hitpts = cv.take<float4>(ncol);
   carve_field(cv, occ, o->precision, g.fp);
-  // FP16 runs colour the hits with FP32-accurate split-FP16 products (binary16 hi / lo
-  // copies of the colour network); other runs in FP32
-  carve_field(cv, col, o->precision == PIFU_PREC_FP16 ? PIFU_PREC_FP16 : PIFU_PREC_FP32, g.cp);
+  // 16-bit runs colour the hits with FP32-accurate split-FP16 products (binary16 hi / lo
+  // copies of the colour network; a value outside the binary16 range re-runs them in
+  // FP32); FP32 and FP8 runs in FP32
+  const bool col16 = o->precision == PIFU_PREC_FP16 || o->precision == PIFU_PREC_BF16;
+  carve_field(cv, col, col16 ? PIFU_PREC_FP16 : PIFU_PREC_FP32, g.cp);
   int C = 0, mh = 0;
   if (g.fp.has_mlp) {
     C = occ->C;
@@ -3376,8 +3378,8 @@ int32_t pifu_render_view_async(pifu_ctx* ctx, const pifu_field* occ_field,
     EvalCtx ec{ctx, s, g.counters, PIFU_PREC_FP32, 0.f};
     ec.aw = g.aw;
     ec.st_dev = sd;
-    // FP16 renders colour with split-FP16 products; a value of this call outside the
-    // binary16 range (the occupancy passes' or these products') re-runs them in FP32
+    // 16-bit renders colour with split-FP16 products; a value of this call outside the
+    // binary16 range (an FP16 occupancy pass's or these products') re-runs them in FP32
     const bool x3 = g.cp.mlp.prec == PIFU_PREC_FP16;
     r = run_mlp_dev(ec, g.cp, g.cp.mlp, x3 ? PREC_F32X3 : PIFU_PREC_FP32, ps, g.hitlist,
                     (uint32_t)(W * H), nh, g.ew, nullptr, nullptr, rgb);

@@ -210,9 +210,10 @@ def test_render_tiny(pifu, yaw):
 
 
 @pytest.mark.parametrize("yaw", [0.0, 90.0])
-def test_render_fp16_colour_is_fp32_accurate(pifu, yaw):
-    """FP16 runs colour the hits with FP32-accurate split-FP16 products.  On an analytic
-    occupancy field the hits, depths and occupancy inputs do not depend on the MLP
+@pytest.mark.parametrize("prec,band", [("fp16", 0.0075), ("bf16", 0.02)])
+def test_render_16bit_colour_is_fp32_accurate(pifu, yaw, prec, band):
+    """BF16 and FP16 runs colour the hits with FP32-accurate split-FP16 products.  On an
+    analytic occupancy field the hits, depths and occupancy inputs do not depend on the MLP
     precision, so the colours are compared as they are: against the FP32 run and the
     oracle."""
     ell = synth.ellipsoids(8, 302)
@@ -225,7 +226,7 @@ def test_render_fp16_colour_is_fp32_accurate(pifu, yaw):
     bg = (0.2, 0.4, 0.6)
     ref = O.render_view(fo, co, view, 6, 5, 4, bg)
     g32 = pifu.render_view(fg, cg, view, 6, 5, 4, bg)
-    g16 = pifu.render_view(fg, cg, view, 6, 5, 4, bg, precision="fp16", band_delta=0.0075)
+    g16 = pifu.render_view(fg, cg, view, 6, 5, 4, bg, precision=prec, band_delta=band)
     assert torch.equal(g16["hit"], g32["hit"])
     assert np.array_equal(g16["hit"].cpu().numpy(), ref["hit"])
     assert torch.equal(torch.isnan(g16["depth"]), torch.isnan(g32["depth"]))
@@ -233,5 +234,5 @@ def test_render_fp16_colour_is_fp32_accurate(pifu, yaw):
     assert torch.equal(g16["depth"][h], g32["depth"][h])
     d16 = np.abs(g16["rgb"].cpu().numpy() - g32["rgb"].cpu().numpy()).max()
     dref = np.abs(g16["rgb"].cpu().numpy() - ref["rgb"]).max()
-    print(f"yaw {yaw}: {int(h.sum())} hits; |rgb16 - rgb32| max {d16:.2e}, vs oracle {dref:.2e}")
+    print(f"{prec} yaw {yaw}: {int(h.sum())} hits; |rgb16 - rgb32| max {d16:.2e}, vs oracle {dref:.2e}")
     assert d16 <= 2e-5 and dref <= 1e-4
