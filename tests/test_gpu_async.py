@@ -102,7 +102,7 @@ def pifu_color_field():
     return P.DeviceField.mlp_field(synth.color_features(), synth.color_mlp())
 
 
-@pytest.mark.parametrize("prec,band", [("fp32", 0.0), ("fp16", 0.0075)])
+@pytest.mark.parametrize("prec,band", [("fp32", 0.0), ("fp16", 0.0075), ("bf16", 0.02)])
 def test_async_render_equals_blocking(pifu, prec, band):
     fld, _ = _fields(pifu, "pifu")
     col = pifu_color_field()
