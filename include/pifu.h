@@ -178,11 +178,14 @@ typedef struct pifu_level_stats {
  *   2^log2_coarse.  dense != 0 evaluates every final node instead (the
  *   brute-force baseline) and ignores log2_coarse.
  *   precision: PIFU_PREC_*.  band_delta: for BF16/FP16/FP8, points with
- *   |p - 0.5| < band_delta are re-run in FP32 (FP16 runs: FP32-accurate products of
- *   binary16 hi / lo operand splits, three FP16 MFMAs per step).  FP16 runs check every converted
- *   operand (feature, weight, hidden activation) against the binary16 range; once
- *   one falls outside it, every evaluation of the call from then on (including the
- *   one that overflowed) is re-run in FP32 and counted in band_fp32.  guard_logit: points whose FP32
+ *   |p - 0.5| < band_delta are re-run with FP32 accuracy (FP8 runs: FP32 MFMA; BF16 and
+ *   FP16 runs: FP32-accurate products of binary16 hi / lo operand splits, three FP16
+ *   MFMAs per step).  FP16 runs check every converted operand (feature, weight, hidden
+ *   activation) against the binary16 range; once one falls outside it, every evaluation
+ *   of the call from then on (including the one that overflowed) is re-run in FP32 and
+ *   counted in band_fp32.  BF16 runs check the split operands (binary16 weight copies,
+ *   the band's features and activations) and, once one falls outside the range, re-run
+ *   that band and every later band of the call in FP32.  guard_logit: points whose FP32
  *   logit has |logit| < guard_logit are re-run in FP64 so that labels are decided
  *   exactly (0 disables).  surrogate_max_log2: levels with at most this log2
  *   size use field->surrogate when present (points with |p_s - 0.5| <
@@ -710,7 +713,8 @@ int32_t pifu_convert_f32(pifu_ctx* ctx, const float* in, uint32_t n, int32_t pre
 #define PIFU_KERN_HEAD 4          /* last MLP layer + output rule */
 #define PIFU_KERN_GEMM_F16 5      /* MLP hidden layer, FP16 MFMA */
 #define PIFU_KERN_GEMM_F16X3 6    /* FP32-accurate hidden layer from three FP16 MFMA products
-                                     (the FP32 band of an FP16 run) */
+                                     (the FP32-accurate band of a BF16 or FP16
+                                     run, the colour MLP of their renders) */
 #define PIFU_KERN_COUNT 8
 
 /* Accumulated over the launches of one kernel family since the last enable. flops

@@ -114,9 +114,11 @@ constexpr int kHostWords = 256;   // pinned read-back buffer (>= every device co
 constexpr uint32_t kDefaultChunk = 65536;
 
 // Device-side counters (words of the counters array).
-// C_OVF: FP16 runs set it when a value leaves the binary16 range.  It is cleared once
-// per call (before the weights are packed) and kept by the per-level counter clears,
-// so that an overflow sends every later evaluation of the call to FP32 as well.
+// C_OVF: set when a value converted to binary16 leaves its range (FP16 runs: any such
+// value; BF16 runs: the binary16 weight copies and the split-FP16 band's operands).  It
+// is cleared once per call (before the weights are packed) and kept by the per-level
+// counter clears, so that an overflow sends every later evaluation of the call (FP16) or
+// every later band (BF16) to FP32 as well.
 enum { C_TOTAL = 0, C_CONFLICTS = 1, C_B0 = 2, C_GUARD = 3, C_SHADOW = 4, C_OVF = 15 };
 
 struct Carver {
@@ -203,7 +205,10 @@ struct MlpPrep {
   MLPDesc d;
   float* Wp32[PIFU_MAX_LAYERS];      // FP32 operand copies [N][Kp]
   uint16_t* Wp16[PIFU_MAX_LAYERS];   // 16-bit operand copies (BF16 or FP16 runs, that format)
-  uint16_t* Wlo16[PIFU_MAX_LAYERS];  // FP16 runs: scaled binary16 residuals (FP16 x 3 band)
+  // split-FP16 band operands (FP16 and BF16 runs): binary16 hi copies (an FP16 run's are
+  // Wp16) and scaled binary16 residuals
+  uint16_t* Wh16[PIFU_MAX_LAYERS] = {};
+  uint16_t* Wlo16[PIFU_MAX_LAYERS] = {};
   uint8_t* Wp8[PIFU_MAX_LAYERS];     // FP8 e4m3 operand copies (FP8 runs), scaled by 1/w_scale
   uint32_t* amax;                    // device: per-layer max |W| (float bits), FP8 runs
   float w_scale[PIFU_MAX_LAYERS];    // FP8 weight scale amax/448 (host, after pack)
@@ -216,7 +221,8 @@ struct MlpPrep {
   int hoist_off[PIFU_MAX_LAYERS];    // offset of layer l in the stacked outputs, -1 if none
   float* Wf32 = nullptr;             // [NP][C]
   uint16_t* Wf16 = nullptr;          // [NP][C] (BF16 or FP16 runs)
-  uint16_t* Wflo16 = nullptr;        // [NP][C] residuals (FP16 runs)
+  uint16_t* Wfh16 = nullptr;         // [NP][C] binary16 hi copies (BF16 runs)
+  uint16_t* Wflo16 = nullptr;        // [NP][C] residuals (FP16 and BF16 runs)
   float* bf = nullptr;               // [NP] biases of those layers
   float* wz = nullptr;               // [widths[0]] layer 0's weights of z, contiguous
 };
@@ -238,10 +244,11 @@ void describe_mlp(const pifu_mlp* m, MLPDesc& d) {
   }
 }
 
-// Carves the packed operand copies of the hidden layers: one in the run precision
-// and, for BF16/FP16/FP8 runs, an FP32 copy for the threshold-band re-evaluation.
+// Carves the packed operand copies of the hidden layers: one in the run precision, an
+// FP32 copy, and for BF16/FP16 runs the binary16 hi / lo copies of the split-FP16 band.
 void carve_mlp(Carver& cv, const pifu_mlp* m, int precision, MlpPrep& p) {
   describe_mlp(m, p.d);
+  const bool split = precision == PIFU_PREC_FP16 || precision == PIFU_PREC_BF16;
   p.max_hidden = 0;
   p.prec = precision;
   p.amax = precision == PIFU_PREC_FP8 ? cv.take<uint32_t>(PIFU_MAX_LAYERS) : nullptr;
@@ -251,7 +258,8 @@ void carve_mlp(Carver& cv, const pifu_mlp* m, int precision, MlpPrep& p) {
     p.Wp32[l] = cv.take<float>(n);
     p.Wp16[l] = precision == PIFU_PREC_BF16 || precision == PIFU_PREC_FP16 ? cv.take<uint16_t>(n)
                                                                            : nullptr;
-    p.Wlo16[l] = precision == PIFU_PREC_FP16 ? cv.take<uint16_t>(n) : nullptr;
+    p.Wh16[l] = precision == PIFU_PREC_BF16 ? cv.take<uint16_t>(n) : nullptr;
+    p.Wlo16[l] = split ? cv.take<uint16_t>(n) : nullptr;
     p.Wp8[l] = precision == PIFU_PREC_FP8 ? cv.take<uint8_t>(n) : nullptr;
     p.max_hidden = std::max(p.max_hidden, m->widths[l]);
     const float amax_a = m->fp8_amax[l] > 0.f ? m->fp8_amax[l] : 16.f;
@@ -271,7 +279,8 @@ void carve_mlp(Carver& cv, const pifu_mlp* m, int precision, MlpPrep& p) {
     p.Wf32 = cv.take<float>(n);
     p.Wf16 = precision == PIFU_PREC_BF16 || precision == PIFU_PREC_FP16 ? cv.take<uint16_t>(n)
                                                                         : nullptr;
-    p.Wflo16 = precision == PIFU_PREC_FP16 ? cv.take<uint16_t>(n) : nullptr;
+    p.Wfh16 = precision == PIFU_PREC_BF16 ? cv.take<uint16_t>(n) : nullptr;
+    p.Wflo16 = split ? cv.take<uint16_t>(n) : nullptr;
     p.bf = cv.take<float>(p.NP);
     p.wz = cv.take<float>(m->widths[0]);
   }
@@ -290,7 +299,10 @@ int pack_mlp(MlpPrep& p, pifu_ctx* ctx, hipStream_t s, uint32_t* ovf) {
   };
   for (int l = 0; l + 1 < p.d.n_layers; ++l) {
     add(p.d.W[l], p.d.widths[l], p.d.in_w[l], p.Kp[l], p.Wp32[l], FMT_F32, nullptr);
-    if (p.Wp16[l]) add(p.d.W[l], p.d.widths[l], p.d.in_w[l], p.Kp[l], p.Wp16[l], f16, ovf);
+    if (p.Wp16[l])
+      add(p.d.W[l], p.d.widths[l], p.d.in_w[l], p.Kp[l], p.Wp16[l], f16,
+          f16 == FMT_F16 ? ovf : nullptr);
+    if (p.Wh16[l]) add(p.d.W[l], p.d.widths[l], p.d.in_w[l], p.Kp[l], p.Wh16[l], FMT_F16, ovf);
     if (p.Wlo16[l]) add(p.d.W[l], p.d.widths[l], p.d.in_w[l], p.Kp[l], p.Wlo16[l], FMT_F16LO, nullptr);
     if (p.Wp8[l])
       launch_pack_fp8(p.d.W[l], p.d.widths[l], p.d.in_w[l], p.Kp[l], p.amax + l, p.Wp8[l], s);
@@ -299,7 +311,11 @@ int pack_mlp(MlpPrep& p, pifu_ctx* ctx, hipStream_t s, uint32_t* ovf) {
       const int fcol = l == 0 ? 0 : p.d.widths[l - 1];   // where f starts in layer l's input
       const size_t off = (size_t)p.hoist_off[l];
       add(p.d.W[l] + fcol, p.d.widths[l], p.d.in_w[l], C, p.Wf32 + off * C, FMT_F32, nullptr);
-      if (p.Wf16) add(p.d.W[l] + fcol, p.d.widths[l], p.d.in_w[l], C, p.Wf16 + off * C, f16, ovf);
+      if (p.Wf16)
+        add(p.d.W[l] + fcol, p.d.widths[l], p.d.in_w[l], C, p.Wf16 + off * C, f16,
+            f16 == FMT_F16 ? ovf : nullptr);
+      if (p.Wfh16)
+        add(p.d.W[l] + fcol, p.d.widths[l], p.d.in_w[l], C, p.Wfh16 + off * C, FMT_F16, ovf);
       if (p.Wflo16)
         add(p.d.W[l] + fcol, p.d.widths[l], p.d.in_w[l], C, p.Wflo16 + off * C, FMT_F16LO, nullptr);
       // the layer's biases, as a one-row copy
@@ -437,14 +453,20 @@ void carve_field(Carver& cv, const pifu_field* f, int precision, FieldPrep& fp) 
   }
 }
 
-// Packs the operand copies of the field's networks.  The binary16 copies of an FP16
-// network report values outside the binary16 range into the call's overflow flag
+// The field's occupancy network holds split-FP16 operand copies (FP16 and BF16 runs):
+// its precision band runs on split-FP16 products.
+bool split_band(const FieldPrep& fp) {
+  return fp.has_mlp && (fp.mlp.prec == PIFU_PREC_FP16 || fp.mlp.prec == PIFU_PREC_BF16);
+}
+
+// Packs the operand copies of the field's networks.  The binary16 copies of an FP16 or
+// BF16 network report values outside the binary16 range into the call's overflow flag
 // (counters[C_OVF]), which `clear` resets first (once per call).
 int pack_field(FieldPrep& fp, pifu_ctx* ctx, hipStream_t s, uint32_t* counters,
                bool clear = true) {
   int r = PIFU_OK;
   uint32_t* ovf = nullptr;
-  if (fp.has_mlp && fp.mlp.prec == PIFU_PREC_FP16) {
+  if (split_band(fp)) {
     ovf = counters + C_OVF;
     if (clear) launch_set_u32(ovf, 0, s);   // a kernel: the call may be captured
   }
@@ -675,6 +697,8 @@ int gemm_kind(int prec) {
 // Operand copy of hidden layer l for a run precision (16-bit copies hold the format the
 // network was prepared for).
 const void* layer_weights(const MlpPrep& mp, int prec, int l) {
+  if (prec == PREC_F32X3)   // the binary16 hi copy
+    return mp.prec == PIFU_PREC_FP16 ? (const void*)mp.Wp16[l] : (const void*)mp.Wh16[l];
   return prec == PIFU_PREC_FP8    ? (const void*)mp.Wp8[l]
          : prec == PIFU_PREC_FP32 ? (const void*)mp.Wp32[l]
                                   : (const void*)mp.Wp16[l];
@@ -720,7 +744,7 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
   // a 16-bit run needs the operand copies of its own format; X3 the FP16 hi / lo copies
   if ((prec == PIFU_PREC_BF16 || prec == PIFU_PREC_FP16) && mp.prec != prec)
     return PIFU_ERR_UNSUPPORTED;
-  if (x3 && mp.prec != PIFU_PREC_FP16) return PIFU_ERR_UNSUPPORTED;
+  if (x3 && !mp.Wlo16[0]) return PIFU_ERR_UNSUPPORTED;
   // FP16 conversions and split-FP16 operands report values outside the binary16 range
   uint32_t* ovf = prec == PIFU_PREC_FP16 || x3 ? e.counters + C_OVF : nullptr;
   Seg one{0, n, f->feat, src.base_sub};
@@ -754,7 +778,8 @@ int run_mlp(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, const 
     std::memset(&g, 0, sizeof(g));
     g.A1 = ew.feat;
     g.K1 = g.lda1 = C;
-    g.W = b16 || x3 ? (const void*)mp.Wf16 : (const void*)mp.Wf32;
+    g.W = x3 ? (mp.prec == PIFU_PREC_FP16 ? (const void*)mp.Wf16 : (const void*)mp.Wfh16)
+          : b16 ? (const void*)mp.Wf16 : (const void*)mp.Wf32;
     g.Wlo = x3 ? (const void*)mp.Wflo16 : nullptr;
     g.ovf = ovf;
     g.ldw = C;
@@ -966,10 +991,12 @@ int select_near(EvalCtx& e, const float* logit, uint32_t n, float bound, uint32_
   return PIFU_OK;
 }
 
-// After the run-precision pass: the FP32 band (BF16/FP16/FP8 runs), then the FP64 guard.
-// F is the feature map of the points' frame.  An FP16 run whose call has seen a value
+// After the run-precision pass: the FP32-accurate band (BF16/FP16/FP8 runs), then the FP64
+// guard.  F is the feature map of the points' frame.  FP16 and BF16 runs re-run their band
+// on split-FP16 products, FP8 runs on FP32 MFMA.  An FP16 run whose call has seen a value
 // outside the binary16 range is re-run whole in FP32 instead of the band; so is one whose
-// split-FP16 band reports such a value (read back with the guard's count).
+// split-FP16 band reports such a value (read back with the guard's count).  A BF16 run's
+// own pass does not depend on that range: there only the band's points go to FP32.
 int post_full(EvalCtx& e, const FieldPrep& fp, const PointSrc& src, const float* F,
               const uint32_t* list, uint32_t n, const EvalWs& ew, float* logit, uint8_t* lab,
               pifu_level_stats* st) {
@@ -979,12 +1006,23 @@ int post_full(EvalCtx& e, const FieldPrep& fp, const PointSrc& src, const float*
   uint32_t nb_run = 0;   // points re-run by the band
   bool over = false;     // FP16 overflow: all n points re-run in FP32
   const bool f16 = e.precision == PIFU_PREC_FP16;
+  bool bx3 = false;      // a BF16 run's band on split-FP16 products
   auto rerun_fp32 = [&]() {
     int q = run_mlp(e, fp, fp.mlp, PIFU_PREC_FP32, src, list, n, ew, logit, lab, nullptr, &one, 1);
     if (!q && st) st->band_fp32 += n - nb_run;
     nb_run = 0;
     return q;
   };
+  auto rerun_band_fp32 = [&]() {
+    const Seg bseg{0, nb_run, F, src.base_sub};
+    int q = run_mlp(e, fp, fp.mlp, PIFU_PREC_FP32, src, ew.band_nodes, nb_run, ew, ew.band_logit,
+                    ew.band_lab, nullptr, &bseg, 1);
+    if (!q) launch_scatter_results(ew.band_pos, nb_run, ew.band_logit, ew.band_lab, logit, lab, e.s);
+    return q;
+  };
+  // after split-FP16 products: a value outside the binary16 range sends an FP16 run's
+  // points, or a BF16 run's band, to FP32
+  auto overflow_rerun = [&]() { return f16 ? rerun_fp32() : rerun_band_fp32(); };
   if (e.precision != PIFU_PREC_FP32 && e.band > 0.f) {
     uint32_t nb = 0;
     r = select_near(e, logit, n, e.band, ew.band_pos, &nb);
@@ -995,8 +1033,11 @@ int post_full(EvalCtx& e, const FieldPrep& fp, const PointSrc& src, const float*
       launch_gather_u32(list, ew.band_pos, nb, ew.band_nodes, e.s);
       const Seg bseg{0, nb, F, src.base_sub};
       // an FP16 run's band: FP32-accurate split-FP16 products (operands inside the
-      // binary16 range, which the FP16 pass checked; the band reports its own)
-      const int bprec = f16 ? PREC_F32X3 : PIFU_PREC_FP32;
+      // binary16 range, which the FP16 pass checked; the band reports its own); a BF16
+      // run's too, unless a value of this call already left that range (its binary16
+      // weight copies report theirs when packed)
+      bx3 = e.precision == PIFU_PREC_BF16 && split_band(fp) && e.ctx->host_counters[C_OVF] == 0;
+      const int bprec = f16 || bx3 ? PREC_F32X3 : PIFU_PREC_FP32;
       r = run_mlp(e, fp, fp.mlp, bprec, src, ew.band_nodes, nb, ew, ew.band_logit, ew.band_lab,
                   nullptr, &bseg, 1);
       if (r) return r;
@@ -1013,9 +1054,9 @@ int post_full(EvalCtx& e, const FieldPrep& fp, const PointSrc& src, const float*
     if (r) return r;
   }
   if (!(e.guard > 0.f)) {
-    if (f16 && nb_run) {   // no guard read-back to carry the band's overflow report
+    if ((f16 || bx3) && nb_run) {   // no guard read-back to carry the band's overflow report
       r = read_counters(e, C_OVF + 1);
-      if (!r && e.ctx->host_counters[C_OVF]) r = rerun_fp32();
+      if (!r && e.ctx->host_counters[C_OVF]) r = overflow_rerun();
     }
     return r;
   }
@@ -1024,9 +1065,10 @@ int post_full(EvalCtx& e, const FieldPrep& fp, const PointSrc& src, const float*
     // every point with |logit| < guard lies inside the band and now holds its FP32
     // result: the guard picks from the band's results only
     if (nb_run) r = select_near(e, ew.band_logit, nb_run, e.guard, ew.glist, &gn, ew.band_pos);
-    if (!r && f16 && nb_run && e.ctx->host_counters[C_OVF]) {
-      r = rerun_fp32();
-      if (!r) r = select_near(e, logit, n, e.guard, ew.glist, &gn);
+    if (!r && (f16 || bx3) && nb_run && e.ctx->host_counters[C_OVF]) {
+      r = overflow_rerun();
+      if (!r && f16) r = select_near(e, logit, n, e.guard, ew.glist, &gn);
+      else if (!r) r = select_near(e, ew.band_logit, nb_run, e.guard, ew.glist, &gn, ew.band_pos);
     }
   } else {
     r = select_near(e, logit, n, e.guard, ew.glist, &gn);
@@ -1509,11 +1551,9 @@ int plan_render(const pifu_field* occ, const pifu_field* col, const pifu_render_
     carve_eval(cv, (uint32_t)max_n, C, mh, g.ew);
     carve_guard(cv, g.fp, (uint32_t)max_n, g.ew);
   }
-  // the texel table serves FP32 runs of the network: the plain FP32 render and the FP32
-  // band of a BF16 render (an FP16 render's band runs on split-FP16 products and does not
-  // read it; FP8 renders keep the plain path throughout)
-  if (o->precision == PIFU_PREC_FP32 || o->precision == PIFU_PREC_BF16)
-    carve_texel(cv, g.fp, g.ew);
+  // the texel table serves the plain FP32 render (the bands of BF16 and FP16 renders run on
+  // split-FP16 products and do not read it; FP8 renders keep the plain path throughout)
+  if (o->precision == PIFU_PREC_FP32) carve_texel(cv, g.fp, g.ew);
   g.bytes = cv.off + kAlign;
   return PIFU_OK;
 }
@@ -1770,9 +1810,9 @@ int32_t render_impl(pifu_ctx* ctx, const pifu_field* occ_field, const pifu_field
     delete gp;
     return pr;
   }
-  // one clear of the overflow flag per call: by the occupancy network's pack when FP16
-  if (int pr = pack_field(g.cp, ctx, s, g.counters,
-                          !(g.fp.has_mlp && g.fp.mlp.prec == PIFU_PREC_FP16))) {
+  // one clear of the overflow flag per call: by the occupancy network's pack when it has
+  // binary16 copies (FP16, BF16)
+  if (int pr = pack_field(g.cp, ctx, s, g.counters, !split_band(g.fp))) {
     delete gp;
     return pr;
   }
@@ -2801,7 +2841,7 @@ enum {
   AW_NB,         // points of the precision band
   AW_NS,         // surrogate points sent to the full network
   AW_GN,         // points of the FP64 guard
-  AW_RR,         // points re-run in FP32 after an FP16 range overflow (0 or all)
+  AW_RR,         // points re-run in FP32 after a binary16 range overflow (0, or all / the band)
   AW_N0,         // a host-known count, stored for kernels that read counts from memory
   AW_NH,         // render hits
   AW_STATUS,     // status bits (kStatus*)
@@ -2879,7 +2919,7 @@ int run_mlp_dev(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, co
   const int hf = x3 ? FMT_F32 : h16_fmt(prec);
   if ((prec == PIFU_PREC_BF16 || prec == PIFU_PREC_FP16) && mp.prec != prec)
     return PIFU_ERR_UNSUPPORTED;
-  if (x3 && mp.prec != PIFU_PREC_FP16) return PIFU_ERR_UNSUPPORTED;
+  if (x3 && !mp.Wlo16[0]) return PIFU_ERR_UNSUPPORTED;
   if (prec == PIFU_PREC_FP8) return PIFU_ERR_UNSUPPORTED;
   if (!F) F = f->feat;
   uint32_t* ovf = prec == PIFU_PREC_FP16 || x3 ? e.counters + C_OVF : nullptr;
@@ -2902,7 +2942,8 @@ int run_mlp_dev(EvalCtx& e, const FieldPrep& fp, const MlpPrep& mp, int prec, co
     std::memset(&g, 0, sizeof(g));
     g.A1 = ew.feat;
     g.K1 = g.lda1 = C;
-    g.W = b16 || x3 ? (const void*)mp.Wf16 : (const void*)mp.Wf32;
+    g.W = x3 ? (mp.prec == PIFU_PREC_FP16 ? (const void*)mp.Wf16 : (const void*)mp.Wfh16)
+          : b16 ? (const void*)mp.Wf16 : (const void*)mp.Wf32;
     g.Wlo = x3 ? (const void*)mp.Wflo16 : nullptr;
     g.ovf = ovf;
     g.ldw = C;
@@ -2992,7 +3033,7 @@ void select_dev(EvalCtx& e, const float* logit, uint32_t cap, const uint32_t* n_
 }
 
 // post_full for a device-side count: the precision band (with the FP32 re-run of an FP16
-// call whose values left the binary16 range), then the FP64 guard.
+// call whose values left the binary16 range, or of a BF16 call's band), then the FP64 guard.
 int post_full_dev(EvalCtx& e, const FieldPrep& fp, const PointSrc& src, const float* F,
                   const uint32_t* list, uint32_t cap, const uint32_t* n_dev, const EvalWs& ew,
                   float* logit, uint8_t* lab) {
@@ -3000,14 +3041,27 @@ int post_full_dev(EvalCtx& e, const FieldPrep& fp, const PointSrc& src, const fl
   int r = PIFU_OK;
   const bool f16 = e.precision == PIFU_PREC_FP16;
   const bool band = e.precision != PIFU_PREC_FP32 && e.band > 0.f;
+  const bool bx3 = band && e.precision == PIFU_PREC_BF16 && split_band(fp);
   uint32_t* nb = e.aw + AW_NB;
   if (band) {
     select_dev(e, logit, cap, n_dev, e.band, ew.band_pos, nb);
     launch_gather_u32(list, ew.band_pos, cap, ew.band_nodes, e.s, nb);
-    r = run_mlp_dev(e, fp, fp.mlp, f16 ? PREC_F32X3 : PIFU_PREC_FP32, src, ew.band_nodes, cap, nb,
-                    ew, ew.band_logit, ew.band_lab, nullptr, F);
+    r = run_mlp_dev(e, fp, fp.mlp, f16 || bx3 ? PREC_F32X3 : PIFU_PREC_FP32, src, ew.band_nodes,
+                    cap, nb, ew, ew.band_logit, ew.band_lab, nullptr, F);
     if (r) return r;
     launch_scatter_results(ew.band_pos, cap, ew.band_logit, ew.band_lab, logit, lab, e.s, nb);
+  }
+  if (bx3) {
+    // a BF16 call with a value outside the binary16 range so far: the band's points in FP32
+    uint32_t* rr = e.aw + AW_RR;
+    {
+      Book b(e.s);
+      b.add(BK_SEL, rr, nb, 0, 0, e.counters + C_OVF);
+    }
+    r = run_mlp_dev(e, fp, fp.mlp, PIFU_PREC_FP32, src, ew.band_nodes, cap, rr, ew, ew.band_logit,
+                    ew.band_lab, nullptr, F);
+    if (r) return r;
+    launch_scatter_results(ew.band_pos, cap, ew.band_logit, ew.band_lab, logit, lab, e.s, rr);
   }
   Book b(e.s);
   uint32_t* band_stat = e.fc ? nullptr : stat_word(e.st_dev, &pifu_level_stats::band_fp32);
@@ -3318,7 +3372,7 @@ int32_t pifu_render_view_async(pifu_ctx* ctx, const pifu_field* occ_field,
                  (uint32_t)((T + 1) * sizeof(pifu_level_stats) / 4));
   r = pack_field(g.fp, ctx, s, g.counters);
   if (!r)
-    r = pack_field(g.cp, ctx, s, g.counters, !(g.fp.has_mlp && g.fp.mlp.prec == PIFU_PREC_FP16));
+    r = pack_field(g.cp, ctx, s, g.counters, !split_band(g.fp));
   if (!r) r = fill_texel(e, g.fp, g.ew);
   double vd[12];
   for (int i = 0; i < 12; ++i) vd[i] = view[i];

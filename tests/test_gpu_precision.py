@@ -194,6 +194,50 @@ def test_fp16_overflow_reruns_in_fp32(pifu, case):
     assert sum(s["band_fp32"] for s in g["stats"]) < 0.5 * sum(s["mlp_points"] for s in g["stats"])
 
 
+@pytest.mark.parametrize("case", ["activation", "feature"])
+def test_bf16_band_overflow_reruns_band_in_fp32(pifu, case):
+    """A BF16 run re-evaluates its band on split-FP16 products.  A split operand outside the
+    binary16 range (a hidden activation or a sampled feature, which BF16 itself holds) sends
+    the band's points to FP32: points well inside the band then hold the FP32 run's logits
+    bit for bit, where the unscaled network's band holds split-FP16 results.  Labels equal
+    the FP32 run's, and the device-driven grid equals the blocking one."""
+    spec = synth.he_mlp(64, 1, [128, 64, 1], [False, True, False], 207)
+    feat = synth.tiny_features()
+    if case == "activation":
+        big, big_feat = _scaled(spec, 2.0 ** 17), feat
+    else:
+        big, big_feat = _scaled(spec, 1.0, 2.0 ** 17), (feat * 2.0 ** 17).astype(np.float32)
+    f32 = pifu.DeviceField.mlp_field(feat, spec)
+    fbig = pifu.DeviceField.mlp_field(big_feat, big)
+    fo = O.Field("mlp", feat=feat, mlp=spec)
+    pts = _sample_points(fo, 50000, 409)
+    delta = 0.05
+    kw = dict(precision="bf16", band_delta=delta, guard_logit=1e-3)
+    l32, b32 = pifu.eval_points(f32, pts, precision="fp32", guard_logit=1e-3)
+    lbig, bbig = pifu.eval_points(fbig, pts, **kw)
+    lx3, bx3 = pifu.eval_points(f32, pts, **kw)
+    assert torch.equal(bbig, b32) and torch.equal(bx3, b32)
+    l32, lbig, lx3 = (t.cpu().numpy() for t in (l32, lbig, lx3))
+    # BF16's logit error on this network stays far below a quarter of the band
+    sure = (np.abs(l32) < 0.25 * np.log((0.5 + delta) / (0.5 - delta))) & (np.abs(l32) > 1e-3)
+    print(f"{case}: {int(sure.sum())} points well inside the band", flush=True)
+    assert sure.sum() > 100
+    assert np.array_equal(lbig[sure], l32[sure])
+    assert np.abs(lx3[sure] - l32[sure]).max() < 1e-4 and not np.array_equal(lx3[sure], l32[sure])
+    g32 = pifu.occupancy_grid(f32, 6, 4, precision="fp32")
+    gopt = dict(precision="bf16", band_delta=delta)
+    gb = pifu.occupancy_grid(fbig, 6, 4, **gopt)
+    assert torch.equal(gb["labels"], g32["labels"])
+    ag = pifu.AsyncGrid(fbig, pifu.grid_opts(6, 4, **gopt))
+    ag.run()
+    torch.cuda.synchronize()
+    r = ag.result()
+    assert r["status"] == 0, r["status"]
+    assert torch.equal(r["labels"], gb["labels"]) and torch.equal(r["occ"], gb["occ"])
+    for sa, sb in zip(r["stats"], gb["stats"]):
+        assert sa["band_fp32"] == sb["band_fp32"]
+
+
 @pytest.mark.parametrize("net", ["tiny", "pifu"])
 def test_fp16_band_products_are_fp32_accurate(pifu, net):
     """An FP16 run re-evaluates its band with FP32-accurate products of binary16 hi / lo
