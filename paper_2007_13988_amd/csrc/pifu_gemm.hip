@@ -1230,9 +1230,11 @@ int launch_gemm(const GemmArgs& a_in, int precision, int tile_m, hipStream_t s, 
     return 0;
   }
   if (precision == PREC_F32X3) {
-    // one shape for every launch: 64 x 64 tiles of four 32 x 32 waves keep four waves per
-    // SIMD (a 128 x 128 tile holds both accumulator sets in 369 registers, one wave per
-    // SIMD, and ran 1.3-1.7x slower at every band size measured)
+    // one shape for every launch: 64 x 64 tiles of four 32 x 32 waves, at most 128
+    // registers (four workgroups per CU) so that four waves fit per SIMD (with 140
+    // registers and three waves the band launches ran 6-9% longer; a 128 x 128 tile holds
+    // both accumulator sets in 369 registers, one wave per SIMD, and ran 1.3-1.7x slower
+    // at every band size measured; 128 x 64 tiles ran as fast as 64 x 64)
     if ((a.K1 % 32) || (a.K2 % 32)) return -1;
     // a launch that fits one round at two workgroups per CU and has a deep contraction
     // takes 64-deep k stages (half the stages of its latency chain; e.g. layer 1 at 1k /
@@ -1243,7 +1245,7 @@ int launch_gemm(const GemmArgs& a_in, int precision, int tile_m, hipStream_t s, 
         (size_t)rows * (a.N / 64) <= 512)
       PIFU_GO((k_gemm_x3<64, 64, 2, 2, 2, 256, 64>), dim3(rows, a.N / 64), dim3(256), 0, s, a);
     else
-      PIFU_GO((k_gemm_x3<64, 64, 2, 2, 2>), dim3(rows, a.N / 64), dim3(256), 0, s, a);
+      PIFU_GO((k_gemm_x3<64, 64, 2, 2, 4>), dim3(rows, a.N / 64), dim3(256), 0, s, a);
     return 0;
   }
   if (bm == 32) bm = 64;   // the 32-point tile exists for FP32 only
