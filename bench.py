@@ -12,8 +12,9 @@ one pifu_grid_and_render call that runs its two parts concurrently on two stream
 `value` is the plain method in FP32 (the paper's arithmetic; FP32 MFMA, FP64 guard at
 |logit| < 1e-3).  Further forms on the same frame are reported beside it:
   * surrogate_bf16: the distilled (256+z)->128->64->1 network (BF16) on each call's
-    densely evaluated coarsest level, the full network in BF16 with an FP32 re-run of
-    the points with |p-0.5| < 0.02 -- the surrogate+BF16 form set against FP32;
+    densely evaluated coarsest level, the full network in BF16 with an FP32-accurate
+    re-run (split-FP16 products) of the points with |p-0.5| < 0.02 -- the surrogate+BF16
+    form set against FP32;
   * surrogate_bf16_32to128: the same with the surrogate on every level up to 128^3;
   * fp16 / surrogate_fp16: the full network in FP16 MFMA, band 0.0075 re-run with
     FP32-accurate split-FP16 products.
@@ -41,7 +42,7 @@ sys.path.insert(0, ROOT)
 
 # fp16x3: FP32-equivalent FLOP/s of the split-FP16 band (three FP16 MFMA products per step)
 PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0, "fp8": 5000.0, "fp16x3": 2500.0 / 3}
-# run precision and FP32 band of each form; the band is the logit error of the
+# run precision and FP32-accurate band of each form; the band is the logit error of the
 # precision over near-surface points with a margin (FP16: 0.0117 max, band 0.030 in
 # logit; BF16: 0.082 max, band 0.080)
 # (run precision, band delta, surrogate levels: None = no surrogate, -1 = each call's
